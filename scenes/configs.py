@@ -1,0 +1,132 @@
+"""The benchmark workloads as seeded synthetic scenes.
+
+Each generator uses numpy's PCG64 with a fixed default seed and returns a
+`Scene`.  Geometry constants that the workload descriptions leave open
+(sphere placement, cloth height, torus radii, ...) are fixed here once.
+"""
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from .meshes import icosphere, grid_cloth, torus, edges_of_faces, merge_meshes
+
+
+@dataclass
+class Scene:
+    name: str
+    V0: np.ndarray          # (nv, 3) float64, positions at t=0
+    V1: np.ndarray          # (nv, 3) float64, positions at t=1
+    E: np.ndarray           # (ne, 2) int32, e[0] < e[1]
+    F: np.ndarray           # (nf, 3) int32
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def nv(self):
+        return int(self.V0.shape[0])
+
+    @property
+    def ne(self):
+        return int(self.E.shape[0])
+
+    @property
+    def nf(self):
+        return int(self.F.shape[0])
+
+    @property
+    def nb(self):
+        return self.nv + self.ne + self.nf
+
+
+def _scene(name, V0, V1, F, **meta):
+    V0 = np.ascontiguousarray(V0, dtype=np.float64)
+    V1 = np.ascontiguousarray(V1, dtype=np.float64)
+    F = np.ascontiguousarray(F, dtype=np.int32)
+    E = np.ascontiguousarray(edges_of_faces(F), dtype=np.int32)
+    return Scene(name, V0, V1, E, F, dict(meta))
+
+
+def two_spheres(seed=1, subdivisions=3, jitter=1e-3, gap=0.05, displacement=0.1):
+    """Two unit icospheres approaching each other along x.
+
+    Centres at (-(1+gap/2), 0, 0) and (+(1+gap/2), 0, 0); every vertex gets
+    the same N(0, jitter^2) offset at t=0 and t=1; each sphere moves
+    `displacement` toward the other, so first contact is near t = gap/(2*displacement).
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    c = 1.0 + gap / 2.0
+    parts = []
+    for sgn in (-1.0, 1.0):
+        V, F = icosphere(subdivisions, 1.0, (sgn * c, 0.0, 0.0))
+        V = V + rng.normal(0.0, jitter, size=V.shape)
+        V1 = V.copy()
+        V1[:, 0] -= sgn * displacement
+        parts.append((V, V1, F))
+    V0, V1, F = merge_meshes(parts)
+    return _scene("two_spheres", V0, V1, F, seed=seed, subdivisions=subdivisions)
+
+
+def cloth_on_sphere(seed=2, n=256, side=3.0, sphere_subdivisions=5, noise=0.3, drop=0.5):
+    """n x n cloth falling onto a static unit icosphere at the origin.
+
+    The cloth lies flat in the plane y = 1 + 0.25*e (e = mean cloth edge
+    length) at t=0; at t=1 every cloth vertex has moved by
+    N(0, (noise*e)^2) per coordinate plus (0, -drop*e, 0).  The union of the
+    two meshes yields cloth self pairs and cloth-sphere pairs.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    Vc, Fc = grid_cloth(n, side, 0.0, axis_normal=1)
+    Ec = edges_of_faces(Fc)
+    elen = np.linalg.norm(Vc[Ec[:, 0]] - Vc[Ec[:, 1]], axis=1)
+    ebar = float(elen.mean())
+    Vc[:, 1] = 1.0 + 0.25 * ebar
+    Vc1 = Vc + rng.normal(0.0, noise * ebar, size=Vc.shape)
+    Vc1[:, 1] -= drop * ebar
+    Vs, Fs = icosphere(sphere_subdivisions, 1.0)
+    V0, V1, F = merge_meshes([(Vc, Vc1, Fc), (Vs, Vs.copy(), Fs)])
+    return _scene("cloth_on_sphere", V0, V1, F, seed=seed, n=n, mean_edge=ebar)
+
+
+def perturbed_torus(seed=3, n_major=1000, n_minor=500, R=1.0, r=0.4, rest_noise=0.1, noise=0.5):
+    """Closed torus surface with Gaussian vertex perturbations.
+
+    t=0 positions are the torus plus N(0, (rest_noise*e)^2), t=1 positions add
+    N(0, (noise*e)^2) per coordinate (e = mean edge length of the clean torus).
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    V, F = torus(n_major, n_minor, R, r)
+    E = edges_of_faces(F)
+    ebar = float(np.linalg.norm(V[E[:, 0]] - V[E[:, 1]], axis=1).mean())
+    V0 = V + rng.normal(0.0, rest_noise * ebar, size=V.shape)
+    V1 = V0 + rng.normal(0.0, noise * ebar, size=V.shape)
+    return _scene("perturbed_torus", V0, V1, F, seed=seed, mean_edge=ebar)
+
+
+def tiny_random_scene(seed, n_tris=6, extent=1.0, motion=0.6, dyadic_bits=None):
+    """A few disconnected triangles with random linear motion, for exhaustive checks.
+
+    With `dyadic_bits=b` every coordinate is a multiple of 2^-b, so exact
+    rational arithmetic on the inputs is cheap.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    V0 = rng.uniform(-extent, extent, size=(3 * n_tris, 3))
+    V1 = V0 + rng.uniform(-motion, motion, size=V0.shape)
+    if dyadic_bits is not None:
+        q = float(2 ** dyadic_bits)
+        V0 = np.round(V0 * q) / q
+        V1 = np.round(V1 * q) / q
+    F = np.arange(3 * n_tris, dtype=np.int32).reshape(n_tris, 3)
+    return _scene("tiny_random", V0, V1, F, seed=seed)
+
+
+CONFIG_NAMES = {1: "two_spheres", 2: "cloth_on_sphere", 3: "perturbed_torus"}
+
+
+def make_config(k, **kw):
+    """Scene for workload k (1: two spheres, 2: cloth on sphere, 3: perturbed torus)."""
+    if k == 1:
+        return two_spheres(**kw)
+    if k == 2:
+        return cloth_on_sphere(**kw)
+    if k == 3:
+        return perturbed_torus(**kw)
+    raise ValueError(f"no scene generator for workload {k}")
