@@ -1,0 +1,146 @@
+/*
+ * ccd.h -- C ABI of the MI355X (gfx950) conservative continuous collision
+ * detection library: broad phase (sort and sweep over trajectory boxes) and
+ * narrow phase (inclusion-based root finding over (t, u, v)) of Belgrod et
+ * al., "Time of Impact Dataset for Continuous Collision Detection and a
+ * Scalable Conservative Algorithm" (arXiv 2112.06300), Sec. 4.
+ *
+ * Problem statement (Sec. 2 and Alg. 1): vertices move linearly from V0
+ * (t = 0) to V1 (t = 1); the library reports the vertex-face and edge-edge
+ * primitive pairs that may touch (broad phase) and, per pair, whether they
+ * may collide and a conservative time of impact, plus the earliest one over
+ * all pairs (narrow phase; +infinity when nothing collides).
+ *
+ * Conventions for every entry point
+ *   - All array arguments are DEVICE pointers on the context's GPU unless
+ *     stated otherwise; counts and scalars passed by pointer are HOST memory
+ *     unless stated otherwise.  The caller owns every input and output buffer.
+ *   - Coordinates are float64, row-major n x 3.  Topology and pairs are int32,
+ *     row-major.  Sizes are int64.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Work is enqueued
+ *     on it; calls that return counts or status synchronize that stream.
+ *   - Every call returns a ccd_status and never aborts or throws across the
+ *     ABI; ccd_last_error() gives a message for the last failing call on the
+ *     calling thread.
+ *   - A context must not be used from two threads at once.
+ */
+#ifndef CCD_H
+#define CCD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CCD_OK = 0,
+    CCD_ERR_INVALID_ARG = -1, /* null pointer with nonzero count, index out of range, delta <= 0, max_iter < 1 */
+    CCD_ERR_CAPACITY = -2,    /* an output buffer is too small; required sizes are reported */
+    CCD_ERR_DEVICE = -3,      /* a HIP runtime call failed */
+    CCD_ERR_OOM = -4,         /* the library could not allocate its scratch memory */
+    CCD_ERR_NONFINITE = -5    /* a coordinate is NaN, infinite, or larger than 2^960 in magnitude */
+} ccd_status;
+
+typedef struct ccd_context ccd_context;
+
+/* Create a context on HIP device `device`.  The context owns a growable pool
+ * of device scratch memory (released by ccd_destroy) and nothing else. */
+ccd_status ccd_create(int device, ccd_context **out);
+void ccd_destroy(ccd_context *ctx);
+
+/* Message describing the last error on this thread ("" if none). */
+const char *ccd_last_error(void);
+
+/* Library version string. */
+const char *ccd_version(void);
+
+/*
+ * Broad phase (Sec. 4.1 box construction, Sec. 4.2 / Alg. 2 sweep).
+ *
+ * Builds, for every vertex, edge and face, the box of its trajectory over
+ * t in [0,1] (min and max over its vertices at t=0 and t=1) rounded outward to
+ * float32 (lo = largest float <= the double value, hi = smallest float >=),
+ * sorts the boxes along the axis where box centres vary most, and sweeps the
+ * sorted order.  Boxes overlap when their closed intervals overlap on all
+ * three axes.  Outputs exactly
+ *   vf: every (v, f) with vertex v not a corner of face f and overlapping boxes;
+ *   ee: every (e, g), e < g, of edges without a shared endpoint and with
+ *       overlapping boxes.
+ * Sec. 4.5: the sweep only compares floats, so this set equals the set an
+ * all-pairs comparison of the same boxes finds.  Pair order is unspecified.
+ *
+ *   V0, V1   nv x 3 float64 positions at t=0 and t=1
+ *   E        ne x 2 int32 vertex ids (each undirected edge once)
+ *   F        nf x 3 int32 vertex ids
+ *   vf       vf_cap x 2 int32 output;  *n_vf (host) receives the pair count
+ *   ee       ee_cap x 2 int32 output;  *n_ee (host) receives the pair count
+ *
+ * Errors: CCD_ERR_CAPACITY when n_vf > vf_cap or n_ee > ee_cap -- the counts
+ * still hold the required sizes, output contents are unspecified; the caller
+ * reallocates and calls again.  CCD_ERR_INVALID_ARG for a vertex id outside
+ * [0, nv); CCD_ERR_NONFINITE for a bad coordinate.  Synchronizes `stream`.
+ */
+ccd_status ccd_broad(ccd_context *ctx, const double *V0, const double *V1, int64_t nv,
+                     const int32_t *E, int64_t ne, const int32_t *F, int64_t nf,
+                     int32_t *vf, int64_t vf_cap, int64_t *n_vf,
+                     int32_t *ee, int64_t ee_cap, int64_t *n_ee, void *stream);
+
+/*
+ * Narrow phase (Sec. 4.3 / Alg. 3), one conservative answer per pair.
+ *
+ * For each pair, searches (t, u, v) in [0,1]^3 for a root of
+ *   vertex-face:  F(t,u,v) = p(t) - a(t) - u (b(t) - a(t)) - v (c(t) - a(t))
+ *   edge-edge:    F(t,u,v) = a0(t) + u (a1(t) - a0(t)) - b0(t) - v (b1(t) - b0(t))
+ * with x(t) = x0 + t (x1 - x0), by breadth-first bisection of dyadic
+ * intervals.  An interval is discarded when the box of F over its corners
+ * misses the tolerance box C_eps (a forward bound on the float64 rounding of
+ * the evaluation, so no true root is lost), reported as a root when that box
+ * is narrower than `delta` or inside C_eps, and split otherwise.  Each pair
+ * keeps its own earliest reported time t*, and intervals starting at or after
+ * it are pruned at the end of each level.
+ *
+ *   V0, V1, nv, E, ne, F, nf   the scene (as for ccd_broad)
+ *   vf       n_vf x 2 int32 (vertex, face) pairs
+ *   ee       n_ee x 2 int32 (edge, edge) pairs
+ *   delta    root-finding tolerance in distance units (> 0)
+ *   max_iter cap on the intervals enqueued per pair (>= 1): once exceeded the
+ *            pair reports a hit at the earliest time still in its frontier
+ *   hit      (n_vf + n_ee) uint8 output, VF pairs first: 1 = may collide
+ *   toi      (n_vf + n_ee) float64 output: time of impact, +inf without hit;
+ *            an exact dyadic value, never above the earliest true contact
+ *   toi_min  1 float64 DEVICE output: minimum of toi (+inf if no hit)
+ *   n_enq    optional (may be NULL) (n_vf + n_ee) int64 output: intervals
+ *            enqueued per pair -- the solver's per-pair cost log
+ *
+ * Results do not depend on pair order or on how the GPU schedules intervals.
+ * Errors: CCD_ERR_INVALID_ARG (index out of range, delta <= 0, max_iter < 1),
+ * CCD_ERR_NONFINITE, CCD_ERR_OOM.  Synchronizes `stream`.
+ */
+ccd_status ccd_narrow(ccd_context *ctx, const double *V0, const double *V1, int64_t nv,
+                      const int32_t *E, int64_t ne, const int32_t *F, int64_t nf,
+                      const int32_t *vf, int64_t n_vf, const int32_t *ee, int64_t n_ee,
+                      double delta, int64_t max_iter,
+                      uint8_t *hit, double *toi, double *toi_min, int64_t *n_enq, void *stream);
+
+/*
+ * Phase timings of the last ccd_broad / ccd_narrow call on this context, in
+ * milliseconds (GPU events on the call's stream), and work counters.
+ */
+typedef struct {
+    double broad_ms;        /* whole ccd_broad call, first kernel to last */
+    double narrow_ms;       /* whole ccd_narrow call, first kernel to last */
+    double narrow_light_ms; /* lane-per-pair stage */
+    double narrow_heavy_ms; /* workgroup-per-pair stage for pairs with wide frontiers */
+    int64_t sort_axis;      /* axis the last broad phase swept along */
+    int64_t heavy_pairs;    /* pairs the last narrow phase passed to the wide stage */
+    int64_t heavy_reruns;   /* pairs re-run with a larger frontier buffer */
+} ccd_stats;
+
+ccd_status ccd_get_stats(ccd_context *ctx, ccd_stats *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CCD_H */

@@ -1,0 +1,198 @@
+"""Python binding of the MI355X (gfx950) conservative CCD library.
+
+Argument marshalling only: every step of the broad and narrow phases runs in
+the HIP kernels of libccd.so, reached through its C ABI (include/ccd.h).
+PyTorch supplies device memory and the current HIP stream.  There is no CPU
+fallback: importing works without the library, but every call raises if
+libccd.so is missing or no GPU is present.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libccd.so")
+
+CCD_OK = 0
+CCD_ERR_INVALID_ARG = -1
+CCD_ERR_CAPACITY = -2
+CCD_ERR_DEVICE = -3
+CCD_ERR_OOM = -4
+CCD_ERR_NONFINITE = -5
+
+_STATUS_NAMES = {
+    CCD_ERR_INVALID_ARG: "CCD_ERR_INVALID_ARG",
+    CCD_ERR_CAPACITY: "CCD_ERR_CAPACITY",
+    CCD_ERR_DEVICE: "CCD_ERR_DEVICE",
+    CCD_ERR_OOM: "CCD_ERR_OOM",
+    CCD_ERR_NONFINITE: "CCD_ERR_NONFINITE",
+}
+
+# Every symbol include/ccd.h declares.
+EXPORTED = ["ccd_create", "ccd_destroy", "ccd_last_error", "ccd_version", "ccd_broad", "ccd_narrow",
+            "ccd_get_stats"]
+
+
+class CCDError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("broad_ms", ctypes.c_double), ("narrow_ms", ctypes.c_double),
+                ("narrow_light_ms", ctypes.c_double), ("narrow_heavy_ms", ctypes.c_double),
+                ("sort_axis", ctypes.c_int64), ("heavy_pairs", ctypes.c_int64),
+                ("heavy_reruns", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Load libccd.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with paper_2112_06300_amd/build.py "
+                           "(the CCD path has no CPU fallback)")
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    i64 = ctypes.c_int64
+    lib.ccd_create.argtypes = [ctypes.c_int, ctypes.POINTER(P)]
+    lib.ccd_create.restype = ctypes.c_int
+    lib.ccd_destroy.argtypes = [P]
+    lib.ccd_destroy.restype = None
+    lib.ccd_last_error.argtypes = []
+    lib.ccd_last_error.restype = ctypes.c_char_p
+    lib.ccd_version.argtypes = []
+    lib.ccd_version.restype = ctypes.c_char_p
+    lib.ccd_broad.argtypes = [P, P, P, i64, P, i64, P, i64, P, i64, ctypes.POINTER(i64), P, i64,
+                              ctypes.POINTER(i64), P]
+    lib.ccd_broad.restype = ctypes.c_int
+    lib.ccd_narrow.argtypes = [P, P, P, i64, P, i64, P, i64, P, i64, P, i64, ctypes.c_double, i64,
+                               P, P, P, P, P]
+    lib.ccd_narrow.restype = ctypes.c_int
+    lib.ccd_get_stats.argtypes = [P, ctypes.POINTER(Stats)]
+    lib.ccd_get_stats.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(status):
+    if status != CCD_OK:
+        raise CCDError(status, load_library().ccd_last_error().decode())
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else ctypes.c_void_p(0)
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev(t, dtype, cols):
+    import torch
+    t = torch.as_tensor(t)
+    if t.dtype != dtype or not t.is_cuda or not t.is_contiguous():
+        t = t.to(device="cuda", dtype=dtype).contiguous()
+    return t.reshape(-1, cols)
+
+
+class Context:
+    """A library context on one GPU: owns the device scratch pool."""
+
+    def __init__(self, device=0):
+        lib = load_library()
+        h = ctypes.c_void_p()
+        _check(lib.ccd_create(int(device), ctypes.byref(h)))
+        self._h = h
+        self.device = int(device)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().ccd_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def stats(self):
+        st = Stats()
+        _check(load_library().ccd_get_stats(self._h, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in Stats._fields_}
+
+    def broad(self, V0, V1, E, F, vf_cap=None, ee_cap=None, stream=None):
+        """Candidate pairs (vf (n,2) int32, ee (m,2) int32) as CUDA tensors; order unspecified."""
+        import torch
+        lib = load_library()
+        V0 = _dev(V0, torch.float64, 3)
+        V1 = _dev(V1, torch.float64, 3)
+        E = _dev(E, torch.int32, 2)
+        F = _dev(F, torch.int32, 3)
+        nb = V0.shape[0] + E.shape[0] + F.shape[0]
+        vf_cap = int(vf_cap if vf_cap is not None else max(1024, 4 * nb))
+        ee_cap = int(ee_cap if ee_cap is not None else max(1024, 4 * nb))
+        for _ in range(2):
+            vf = torch.empty((vf_cap, 2), dtype=torch.int32, device=V0.device)
+            ee = torch.empty((ee_cap, 2), dtype=torch.int32, device=V0.device)
+            n_vf = ctypes.c_int64()
+            n_ee = ctypes.c_int64()
+            st = lib.ccd_broad(self._h, _ptr(V0), _ptr(V1), V0.shape[0], _ptr(E), E.shape[0], _ptr(F), F.shape[0],
+                               _ptr(vf), vf_cap, ctypes.byref(n_vf), _ptr(ee), ee_cap, ctypes.byref(n_ee),
+                               _stream(stream))
+            if st == CCD_ERR_CAPACITY:
+                vf_cap = max(vf_cap, n_vf.value)
+                ee_cap = max(ee_cap, n_ee.value)
+                continue
+            _check(st)
+            return vf[:n_vf.value], ee[:n_ee.value]
+        raise CCDError(CCD_ERR_CAPACITY, "broad phase output did not fit after resizing")
+
+    def broad_into(self, V0, V1, E, F, vf, ee, stream=None):
+        """Broad phase into preallocated outputs; returns (n_vf, n_ee) or raises CCDError."""
+        lib = load_library()
+        n_vf = ctypes.c_int64()
+        n_ee = ctypes.c_int64()
+        st = lib.ccd_broad(self._h, _ptr(V0), _ptr(V1), V0.shape[0], _ptr(E), E.shape[0], _ptr(F), F.shape[0],
+                           _ptr(vf), vf.shape[0], ctypes.byref(n_vf), _ptr(ee), ee.shape[0], ctypes.byref(n_ee),
+                           _stream(stream))
+        _check(st)
+        return n_vf.value, n_ee.value
+
+    def narrow(self, V0, V1, E, F, vf, ee, delta=1e-6, max_iter=10**6, with_costs=False, out=None, stream=None):
+        """Per-pair (hit uint8, toi float64, toi_min (1,) float64, n_enq int64 or None), VF pairs first."""
+        import torch
+        lib = load_library()
+        V0 = _dev(V0, torch.float64, 3)
+        V1 = _dev(V1, torch.float64, 3)
+        E = _dev(E, torch.int32, 2)
+        F = _dev(F, torch.int32, 3)
+        vf = _dev(vf, torch.int32, 2)
+        ee = _dev(ee, torch.int32, 2)
+        n = vf.shape[0] + ee.shape[0]
+        if out is None:
+            hit = torch.empty(n, dtype=torch.uint8, device=V0.device)
+            toi = torch.empty(n, dtype=torch.float64, device=V0.device)
+            tmin = torch.empty(1, dtype=torch.float64, device=V0.device)
+            nenq = torch.empty(n, dtype=torch.int64, device=V0.device) if with_costs else None
+        else:
+            hit, toi, tmin, nenq = out
+        _check(lib.ccd_narrow(self._h, _ptr(V0), _ptr(V1), V0.shape[0], _ptr(E), E.shape[0], _ptr(F), F.shape[0],
+                              _ptr(vf), vf.shape[0], _ptr(ee), ee.shape[0], float(delta), int(max_iter),
+                              _ptr(hit), _ptr(toi), _ptr(tmin), _ptr(nenq), _stream(stream)))
+        return hit, toi, tmin, nenq
+
+
+def version():
+    return load_library().ccd_version().decode()

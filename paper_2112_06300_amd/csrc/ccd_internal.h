@@ -1,0 +1,132 @@
+// ccd_internal.h -- device helpers and launcher declarations shared by the
+// gfx950 kernels of the CCD library (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ccd {
+
+// ---------------------------------------------------------------------------
+// Conservative float32 rounding of trajectory box bounds (Sec. 4.1): lo is the
+// largest float <= x, hi the smallest float >= x.  Round to nearest, then step
+// one float outward when the rounding went the wrong way.  The result has no
+// negative zero, so that float order and the order of the uint32 sort keys
+// below agree exactly.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float step_down(float f)
+{
+    uint32_t b = __float_as_uint(f);
+    if ((b & 0x7fffffffu) == 0u) return __uint_as_float(0x80000001u);  // +-0 -> -min subnormal
+    return __uint_as_float((b & 0x80000000u) ? b + 1u : b - 1u);
+}
+
+__device__ __forceinline__ float step_up(float f)
+{
+    uint32_t b = __float_as_uint(f);
+    if ((b & 0x7fffffffu) == 0u) return __uint_as_float(0x00000001u);  // +-0 -> +min subnormal
+    return __uint_as_float((b & 0x80000000u) ? b - 1u : b + 1u);
+}
+
+__device__ __forceinline__ float round_down_f32(double x)
+{
+    float f = (float)x;
+    if ((double)f > x) f = step_down(f);
+    return f + 0.0f;  // -0 -> +0
+}
+
+__device__ __forceinline__ float round_up_f32(double x)
+{
+    float f = (float)x;
+    if ((double)f < x) f = step_up(f);
+    return f + 0.0f;
+}
+
+// Order-preserving map float -> uint32 (no NaN, no -0 in the inputs).
+__device__ __forceinline__ uint32_t sort_key(float f)
+{
+    uint32_t b = __float_as_uint(f);
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+
+// Largest allowed coordinate magnitude: keeps every intermediate of the
+// narrow-phase evaluation finite.
+constexpr double kMaxCoord = 0x1p960;
+
+// Error flags raised by kernels (bitwise OR into a device word).
+enum : uint32_t {
+    FLAG_BAD_INDEX = 1u,
+    FLAG_NONFINITE = 2u,
+    FLAG_HEAVY_OVERFLOW = 4u,
+};
+
+// ---------------------------------------------------------------------------
+// Broad-phase workspace: all device pointers, owned by the context pool.
+// ---------------------------------------------------------------------------
+struct BroadBuffers {
+    // boxes in primitive order, segments [V | E | F], SoA
+    float *lo[3], *hi[3];
+    // sort keys / payload (double-buffered)
+    uint32_t *keyA, *keyB, *valA, *valB;
+    uint32_t *hist;       // 768 * nblocks
+    double *stats;        // 6 accumulators: sum c_a, sum c_a^2
+    int32_t *axis;        // chosen sweep axis
+    // sorted sweep records, segments [V | E | F]
+    uint32_t *khi;        // key of hi on the sweep axis
+    float *lob, *hib, *loc, *hic;  // the two other axes
+    int32_t *pid;         // primitive id
+    int32_t *vtx;         // up to 3 vertex ids per record (stride 3)
+    unsigned long long *counts;    // [0] = n_vf, [1] = n_ee
+    uint32_t *flags;
+};
+
+int64_t sort_blocks(int64_t nb);
+
+void launch_broad(const double *V0, const double *V1, int64_t nv, const int32_t *E, int64_t ne,
+                  const int32_t *F, int64_t nf, int32_t *vf, int64_t vf_cap, int32_t *ee,
+                  int64_t ee_cap, const BroadBuffers &B, int64_t nblocks_sort, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Narrow-phase workspace.
+// ---------------------------------------------------------------------------
+constexpr int kLightK = 8;          // survivors kept per pair per level in the light stage
+constexpr int kLightMaxLevel = 21;  // light-stage numerators are packed in 21 bits each
+constexpr int kMaxLevel = 52;       // finest dyadic level per dimension
+constexpr int kSpillNodes = 2 * kLightK;
+
+struct HeavyEntry {
+    int32_t pair;
+    int32_t nnodes;
+    int32_t lvl[3];
+    int32_t pad;
+    double tstar;
+    long long n_enq;
+};
+
+struct NarrowBuffers {
+    HeavyEntry *heavy;             // capacity n_pairs
+    unsigned long long *spill;     // n_pairs * kSpillNodes packed nodes
+    unsigned int *counters;        // [0] heavy count, [1] heavy next, [2] overflow count, [3] rerun next
+    int32_t *overflow_list[2];     // heavy slots to re-run with larger buffers (alternating)
+    unsigned long long *scratch;   // heavy frontier buffers
+    uint32_t *flags;
+    double *toi_min;
+};
+
+void launch_narrow_light(const double *V0, const double *V1, int64_t nv, const int32_t *E, int64_t ne,
+                         const int32_t *F, int64_t nf, const int32_t *vf, int64_t n_vf,
+                         const int32_t *ee, int64_t n_ee, double delta, long long max_iter,
+                         uint8_t *hit, double *toi, long long *n_enq, const NarrowBuffers &B,
+                         hipStream_t s);
+
+// Wide stage: `nslots` workgroups, each with a frontier buffer of `cap` nodes
+// (two buffers of 3 x cap uint64).  Round 0 works on every handed-over pair;
+// round r > 0 re-runs the pairs that overflowed their buffer in round r - 1.
+void launch_narrow_heavy(const double *V0, const double *V1, const int32_t *E, const int32_t *F,
+                         const int32_t *vf, const int32_t *ee, int64_t n_vf, double delta,
+                         long long max_iter, uint8_t *hit, double *toi, long long *n_enq,
+                         const NarrowBuffers &B, int nslots, int64_t cap, int round, hipStream_t s);
+
+void launch_toi_min(const double *toi, int64_t n, double *out, hipStream_t s);
+
+}  // namespace ccd
