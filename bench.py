@@ -1,0 +1,218 @@
+"""Benchmark: candidate pairs per second through broad + narrow phase on one MI355X.
+
+Workload: 256 x 256 cloth (130,050 triangles) falling onto a static 10,242-vertex
+icosphere, union mesh with self and cross pairs, float64 narrow phase,
+delta = 1e-6, max_iter = 1e6.  One step = ccd_broad on device-resident
+V0/V1/E/F followed by ccd_narrow on its candidate pairs (per-pair hit/TOI and
+the global minimum).  Inputs are seeded synthetic meshes built by `scenes`.
+
+Prints one JSON line.  See the design doc for the roofline definitions.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, GB/s
+FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector (FMA = 2 flops)
+DELTA = 1e-6
+MAX_ITER = 10 ** 6
+FLOPS_PER_AXIS = {0: 46, 1: 44}   # canonical evaluation sequence, per axis: VF 20 fma + 6 add, EE 16 fma + 12 add
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_cloth_on_sphere.json")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cloth-n", type=int, default=256)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of known size (for HBM counter scaling)")
+    return ap.parse_args()
+
+
+def source_hash(files):
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def copy_calibration():
+    import torch
+    n = 1 << 28  # 2 GiB of float64 read + 2 GiB written
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "launches": 3}))
+
+
+def cpu_baseline(scene, gpu_pairs):
+    """The oracle (brute-force broad phase + sequential narrow solver) on the host cores."""
+    import numpy as np
+    import oracle
+    nthreads = oracle.default_threads()
+    t0 = time.perf_counter()
+    vf, ee = oracle.broad(scene.V0, scene.V1, scene.E, scene.F, nthreads=nthreads)
+    t1 = time.perf_counter()
+    hit, toi, n_enq, n_eval, n_axis, tmin = oracle.narrow_with_work(scene.V0, scene.V1, scene.E, scene.F, vf, ee,
+                                                                    DELTA, MAX_ITER, nthreads=nthreads)
+    t2 = time.perf_counter()
+    pairs = len(vf) + len(ee)
+    kinds = np.concatenate([np.zeros(len(vf), np.int64), np.ones(len(ee), np.int64)])
+    flops = int(np.sum(n_axis * np.where(kinds == 0, FLOPS_PER_AXIS[0], FLOPS_PER_AXIS[1])))
+    return {
+        "value": pairs / (t2 - t0),
+        "unit": "pairs/s",
+        "cores": nthreads,
+        "kind": "oracle",
+        "sample": f"the full workload once: brute-force broad phase ({t1 - t0:.2f} s) + narrow phase on its "
+                  f"{pairs} pairs ({t2 - t1:.2f} s), {nthreads} threads",
+        "pairs_match_gpu": bool(pairs == gpu_pairs),
+    }, flops, int(n_eval.sum())
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the narrow and broad phases of this "
+              "library run on a single MI355X; multi-GPU sharding is described in DESIGN.md but not built.",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if args.copy_calibration:
+        copy_calibration()
+        return
+    import numpy as np
+    import scenes
+    import paper_2112_06300_amd as ccd
+
+    scene = scenes.cloth_on_sphere(n=args.cloth_n)
+    dev = lambda x, dt: torch.as_tensor(np.ascontiguousarray(x)).to("cuda", dt)
+    V0, V1 = dev(scene.V0, torch.float64), dev(scene.V1, torch.float64)
+    E, F = dev(scene.E, torch.int32), dev(scene.F, torch.int32)
+    ctx = ccd.Context(0)
+
+    # size the pair buffers once (outside the timed region)
+    vf0, ee0 = ctx.broad(V0, V1, E, F)
+    cap_vf, cap_ee = vf0.shape[0] + 1024, ee0.shape[0] + 1024
+    vf = torch.empty((cap_vf, 2), dtype=torch.int32, device="cuda")
+    ee = torch.empty((cap_ee, 2), dtype=torch.int32, device="cuda")
+    n_pairs_max = cap_vf + cap_ee
+    hit = torch.empty(n_pairs_max, dtype=torch.uint8, device="cuda")
+    toi = torch.empty(n_pairs_max, dtype=torch.float64, device="cuda")
+    tmin = torch.empty(1, dtype=torch.float64, device="cuda")
+
+    def step():
+        n_vf, n_ee = ctx.broad_into(V0, V1, E, F, vf, ee)
+        st_b = ctx.stats()
+        n = n_vf + n_ee
+        ctx.narrow(V0, V1, E, F, vf[:n_vf], ee[:n_ee], DELTA, MAX_ITER,
+                   out=(hit[:n], toi[:n], tmin, None))
+        st_n = ctx.stats()
+        return n_vf, n_ee, st_b, st_n
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    stage = {k: 0.0 for k in ("broad_ms", "box_ms", "sort_ms", "gather_ms", "sweep_ms", "narrow_ms",
+                              "narrow_light_ms", "narrow_heavy_ms")}
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        n_vf, n_ee, st_b, st_n = step()
+        for k in ("broad_ms", "box_ms", "sort_ms", "gather_ms", "sweep_ms"):
+            stage[k] += st_b[k]
+        for k in ("narrow_ms", "narrow_light_ms", "narrow_heavy_ms"):
+            stage[k] += st_n[k]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    K = args.steps
+    ms_per_step = (t1 - t0) * 1000.0 / K
+    stage = {k: v / K for k, v in stage.items()}
+    pairs = n_vf + n_ee
+    value = pairs / (ms_per_step / 1000.0)
+    heavy_pairs = st_n["heavy_pairs"]
+
+    nv, ne, nf = scene.nv, scene.ne, scene.nf
+    nb = nv + ne + nf
+    # broad phase algorithmic bytes: inputs, box write, one key+id permutation, sorted record read,
+    # ids for the pair filter, pair write
+    broad_bytes = (48 * nv + 8 * ne + 12 * nf) + 24 * nb + 16 * nb + 28 * nb + (4 * nv + 8 * ne + 12 * nf) + 8 * pairs
+    broad_gbs = broad_bytes / (stage["broad_ms"] * 1e-3) / 1e9
+
+    cpu = None
+    flops = None
+    n_eval = None
+    if not args.no_cpu_baseline:
+        cpu, flops, n_eval = cpu_baseline(scene, pairs)
+
+    narrow_tflops = flops / (stage["narrow_ms"] * 1e-3) / 1e12 if flops else None
+    light_tflops = flops / ((stage["narrow_light_ms"] + stage["narrow_heavy_ms"]) * 1e-3) / 1e12 if flops else None
+
+    # the dominant kernel of the step
+    kernels = {"sweep_kernel": stage["sweep_ms"], "light_kernel": stage["narrow_light_ms"],
+               "heavy_kernel": stage["narrow_heavy_ms"], "radix sort": stage["sort_ms"]}
+    dominant = max(kernels, key=kernels.get)
+    traffic = None
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+        if rec.get("kernel") == dominant and rec.get("source_hash") == source_hash(rec["sources"]):
+            traffic = rec["bytes_per_launch"]
+    except (OSError, ValueError, KeyError):
+        pass
+    if dominant == "sweep_kernel":
+        # bytes the sweep must move: sorted records read once (key lo/hi 8, other axes 16, id 4, vertex ids
+        # 4/8/12) and the pairs written
+        alg = 28 * nb + (4 * nv + 8 * ne + 12 * nf) + 8 * pairs
+        achieved = alg / (stage["sweep_ms"] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": dominant}
+    else:
+        ms = stage["narrow_light_ms"] if dominant == "light_kernel" else stage["narrow_heavy_ms"]
+        achieved = (flops / (stage["narrow_light_ms"] + stage["narrow_heavy_ms"]) * 1e-9 / 1e-3
+                    if flops else None)
+        roof = {"bound": "fp64", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": (achieved / FP64_PEAK_TFLOPS if achieved else None), "traffic": traffic,
+                "kernel": dominant}
+
+    out = {
+        "metric": "candidate pairs/sec (broad+narrow, FP64, delta=1e-6), plain schedule",
+        "value": value,
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"cloth_on_sphere: {args.cloth_n}x{args.cloth_n} cloth + 10,242-vertex icosphere "
+                               f"(nv={nv}, ne={ne}, nf={nf}, boxes={nb})",
+                   "pairs": pairs, "vf_pairs": n_vf, "ee_pairs": n_ee, "delta": DELTA, "max_iter": MAX_ITER,
+                   "schedule": "plain"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "stages_ms": stage,
+        "broad_hbm": {"alg_bytes": broad_bytes, "achieved_gbs": broad_gbs, "frac": broad_gbs / HBM_PEAK_GBS},
+        "narrow_fp64": {"alg_flops": flops, "canonical_evals": n_eval, "achieved_tflops": narrow_tflops,
+                        "frac": (narrow_tflops / FP64_PEAK_TFLOPS if narrow_tflops else None),
+                        "kernels_tflops": light_tflops, "heavy_pairs": heavy_pairs},
+    }
+    ctx.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

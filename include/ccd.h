@@ -129,9 +129,13 @@ ccd_status ccd_narrow(ccd_context *ctx, const double *V0, const double *V1, int6
  */
 typedef struct {
     double broad_ms;        /* whole ccd_broad call, first kernel to last */
+    double box_ms;          /* trajectory boxes and centre statistics */
+    double sort_ms;         /* sort keys and the four radix passes */
+    double gather_ms;       /* sorted sweep records */
+    double sweep_ms;        /* the sweep that emits the pairs */
     double narrow_ms;       /* whole ccd_narrow call, first kernel to last */
     double narrow_light_ms; /* lane-per-pair stage */
-    double narrow_heavy_ms; /* workgroup-per-pair stage for pairs with wide frontiers */
+    double narrow_heavy_ms; /* workgroup-per-pair stage for pairs with wide frontiers (first round) */
     int64_t sort_axis;      /* axis the last broad phase swept along */
     int64_t heavy_pairs;    /* pairs the last narrow phase passed to the wide stage */
     int64_t heavy_reruns;   /* pairs re-run with a larger frontier buffer */

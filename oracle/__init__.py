@@ -53,7 +53,7 @@ def _load():
     lib.oracle_eps.argtypes = [ctypes.c_int, P, P]
     lib.oracle_levels_needed.argtypes = [ctypes.c_int, P, ctypes.c_double, P]
     lib.oracle_narrow.argtypes = [P, P, P, P, P, i64, P, i64, ctypes.c_double, i64, ctypes.c_int,
-                                  P, P, P, P, P]
+                                  P, P, P, P, P, P]
     _lib = lib
     return lib
 
@@ -145,8 +145,11 @@ def levels_needed(kind, q24, delta):
     return out
 
 
-def narrow(V0, V1, E, F, vf, ee, delta=1e-6, max_iter=10**6, nthreads=None):
-    """Per-pair (hit uint8, toi float64, n_enq int64, n_eval int64) and the global minimum TOI."""
+def narrow_with_work(V0, V1, E, F, vf, ee, delta=1e-6, max_iter=10**6, nthreads=None):
+    """Per-pair (hit, toi, n_enq, n_eval, n_axis) and the global minimum TOI.
+
+    n_axis counts the per-axis inclusion boxes the solver computed (its
+    arithmetic work)."""
     lib = _load()
     V0, V1 = _c(V0, np.float64), _c(V1, np.float64)
     E, F = _c(E, np.int32).reshape(-1, 2), _c(F, np.int32).reshape(-1, 3)
@@ -157,11 +160,18 @@ def narrow(V0, V1, E, F, vf, ee, delta=1e-6, max_iter=10**6, nthreads=None):
     toi = np.zeros(n, np.float64)
     n_enq = np.zeros(n, np.int64)
     n_eval = np.zeros(n, np.int64)
+    n_axis = np.zeros(n, np.int64)
     tmin = np.zeros(1, np.float64)
     lib.oracle_narrow(_ptr(V0), _ptr(V1), _ptr(E), _ptr(F), _ptr(vf), len(vf), _ptr(ee), len(ee),
                       float(delta), int(max_iter), nthreads or default_threads(),
-                      _ptr(hit), _ptr(toi), _ptr(n_enq), _ptr(n_eval), _ptr(tmin))
-    return hit, toi, n_enq, n_eval, float(tmin[0])
+                      _ptr(hit), _ptr(toi), _ptr(n_enq), _ptr(n_eval), _ptr(n_axis), _ptr(tmin))
+    return hit, toi, n_enq, n_eval, n_axis, float(tmin[0])
+
+
+def narrow(V0, V1, E, F, vf, ee, delta=1e-6, max_iter=10**6, nthreads=None):
+    """Per-pair (hit uint8, toi float64, n_enq int64, n_eval int64) and the global minimum TOI."""
+    hit, toi, n_enq, n_eval, _, tmin = narrow_with_work(V0, V1, E, F, vf, ee, delta, max_iter, nthreads)
+    return hit, toi, n_enq, n_eval, tmin
 
 
 def all_pairs(E, F, nv):

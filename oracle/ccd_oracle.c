@@ -343,7 +343,7 @@ enum { NODE_DISCARD = 0, NODE_ACCEPT = 1, NODE_SPLIT = 2 };
  * otherwise split.  A vertex-face interval entirely beyond u + v = 1 holds no
  * triangle point and is discarded; an interval at the finest level in all
  * three dimensions cannot be split and is reported. */
-static int process_node(const query *q, const uint64_t n[3], const int l[3], double delta)
+static int process_node(const query *q, const uint64_t n[3], const int l[3], double delta, int64_t *n_axis)
 {
     double lo_[3], hi_[3];
     for (int k = 0; k < 3; k++) {
@@ -356,6 +356,7 @@ static int process_node(const query *q, const uint64_t n[3], const int l[3], dou
     int inside = 1;
     for (int a = 0; a < 3; a++) {
         double bmin = INFINITY, bmax = -INFINITY;
+        (*n_axis)++;
         for (int it = 0; it < 2; it++)
             for (int iu = 0; iu < 2; iu++)
                 for (int iv = 0; iv < 2; iv++) {
@@ -402,7 +403,8 @@ typedef struct { uint64_t n[3]; } node;
  * frontier is not empty the query stops and reports a hit at the earliest
  * t-lower-bound still in the frontier, which is conservative. */
 static void solve_query(const query *q, double delta, int64_t max_iter,
-                        uint8_t *hit, double *toi, int64_t *n_enq_out, int64_t *n_eval_out)
+                        uint8_t *hit, double *toi, int64_t *n_enq_out, int64_t *n_eval_out,
+                        int64_t *n_axis_out)
 {
     int64_t capF = 64, nF = 1;
     node *Fr = (node *)malloc((size_t)capF * sizeof(node));
@@ -411,13 +413,13 @@ static void solve_query(const query *q, double delta, int64_t max_iter,
     memset(&Fr[0], 0, sizeof(node));
     int l[3] = {0, 0, 0};
     double tstar = INFINITY;
-    int64_t n_enq = 0, n_eval = 0;
+    int64_t n_enq = 0, n_eval = 0, n_axis = 0;
     int capped = 0;
     while (nF > 0) {
         int64_t nS = 0;
         for (int64_t i = 0; i < nF; i++) {
             n_eval++;
-            int r = process_node(q, Fr[i].n, l, delta);
+            int r = process_node(q, Fr[i].n, l, delta, &n_axis);
             if (r == NODE_ACCEPT) {
                 double t = ldexp((double)Fr[i].n[0], -l[0]);
                 if (t < tstar) tstar = t;
@@ -459,6 +461,7 @@ static void solve_query(const query *q, double delta, int64_t max_iter,
     *toi = t;
     if (n_enq_out) *n_enq_out = n_enq;
     if (n_eval_out) *n_eval_out = n_eval;
+    if (n_axis_out) *n_axis_out = n_axis;
     free(Fr);
     free(S);
 }
@@ -469,7 +472,7 @@ void oracle_query(int kind, const double *q24, double delta, int64_t max_iter,
 {
     query q;
     make_query(&q, kind, q24, delta);
-    solve_query(&q, delta, max_iter, hit, toi, n_enq, n_eval);
+    solve_query(&q, delta, max_iter, hit, toi, n_enq, n_eval, NULL);
 }
 
 /* Internals exposed for the pins: F at one point, the tolerance box, the
@@ -513,7 +516,7 @@ typedef struct {
     int64_t max_iter;
     uint8_t *hit;
     double *toi;
-    int64_t *n_enq, *n_eval;
+    int64_t *n_enq, *n_eval, *n_axis;
     int64_t next;
     pthread_mutex_t mu;
 } narrow_job;
@@ -547,10 +550,11 @@ static void *narrow_worker(void *arg)
             gather(j->V0, j->V1, ids, q24);
             query q;
             make_query(&q, kind, q24, j->delta);
-            int64_t ne_ = 0, nv_ = 0;
-            solve_query(&q, j->delta, j->max_iter, &j->hit[i], &j->toi[i], &ne_, &nv_);
+            int64_t ne_ = 0, nv_ = 0, na_ = 0;
+            solve_query(&q, j->delta, j->max_iter, &j->hit[i], &j->toi[i], &ne_, &nv_, &na_);
             if (j->n_enq) j->n_enq[i] = ne_;
             if (j->n_eval) j->n_eval[i] = nv_;
+            if (j->n_axis) j->n_axis[i] = na_;
         }
     }
     return NULL;
@@ -559,17 +563,20 @@ static void *narrow_worker(void *arg)
 /* Per-pair hit / time of impact for n_vf vertex-face pairs (v, f) followed by
  * n_ee edge-edge pairs (e, g); outputs are indexed VF first.  toi is +inf when
  * there is no hit; *toi_min is the minimum over all pairs (+inf if none).
- * n_enq / n_eval (may be NULL) receive the per-pair count of enqueued and of
- * evaluated intervals, the cost log of the solver. */
+ * n_enq / n_eval / n_axis (may be NULL) receive the per-pair count of enqueued
+ * intervals, of evaluated intervals, and of per-axis inclusion boxes computed
+ * (an interval discarded on its first axis computes one): the cost log of the
+ * solver and the basis of its arithmetic count. */
 void oracle_narrow(const double *V0, const double *V1, const int32_t *E, const int32_t *F,
                    const int32_t *vf, int64_t n_vf, const int32_t *ee, int64_t n_ee,
                    double delta, int64_t max_iter, int nthreads,
-                   uint8_t *hit, double *toi, int64_t *n_enq, int64_t *n_eval, double *toi_min)
+                   uint8_t *hit, double *toi, int64_t *n_enq, int64_t *n_eval, int64_t *n_axis,
+                   double *toi_min)
 {
     narrow_job j;
     j.V0 = V0; j.V1 = V1; j.E = E; j.F = F; j.vf = vf; j.ee = ee;
     j.n_vf = n_vf; j.n_ee = n_ee; j.delta = delta; j.max_iter = max_iter;
-    j.hit = hit; j.toi = toi; j.n_enq = n_enq; j.n_eval = n_eval; j.next = 0;
+    j.hit = hit; j.toi = toi; j.n_enq = n_enq; j.n_eval = n_eval; j.n_axis = n_axis; j.next = 0;
     pthread_mutex_init(&j.mu, NULL);
     if (nthreads < 1) nthreads = 1;
     if (nthreads > 256) nthreads = 256;

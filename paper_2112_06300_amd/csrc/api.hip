@@ -68,7 +68,7 @@ struct ccd_context {
     int device = 0;
     Pool broad, narrow, scratch;
     void *host = nullptr;  // pinned host staging for counters and flags
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t ev[8] = {};
     ccd_stats stats{};
 };
 
@@ -160,8 +160,8 @@ ccd_status ccd_broad(ccd_context *c, const double *V0, const double *V1, int64_t
     const int64_t nb = nv + ne + nf;
     const int64_t nbl = sort_blocks(nb);
     const size_t n = (size_t)std::max<int64_t>(nb, 1);
-    const size_t need = aligned_total({6 * n * 4, 4 * n * 4, (size_t)768 * nbl * 4, 6 * 8, 4, n * 4, 4 * n * 4,
-                                       n * 4, 3 * n * 4, 2 * 8, 4});
+    const size_t need = aligned_total({6 * n * 4, 4 * n * 4, (size_t)768 * nbl * 4, 768 * 4, 768 * 4, 6 * 8, 4,
+                                       n * 4, 4 * n * 4, n * 4, 3 * n * 4, 2 * 8, 4});
     ccd_status st = ensure(c->broad, need);
     if (st != CCD_OK) return st;
     Carver cv(c->broad.base);
@@ -171,6 +171,8 @@ ccd_status ccd_broad(ccd_context *c, const double *V0, const double *V1, int64_t
     B.keyA = cv.take<uint32_t>(n); B.keyB = cv.take<uint32_t>(n);
     B.valA = cv.take<uint32_t>(n); B.valB = cv.take<uint32_t>(n);
     B.hist = cv.take<uint32_t>((size_t)768 * nbl);
+    B.bin_tot = cv.take<uint32_t>(768);
+    B.bin_base = cv.take<uint32_t>(768);
     B.stats = cv.take<double>(6);
     B.axis = cv.take<int32_t>(1);
     B.khi = cv.take<uint32_t>(n);
@@ -181,7 +183,13 @@ ccd_status ccd_broad(ccd_context *c, const double *V0, const double *V1, int64_t
     B.flags = cv.take<uint32_t>(1);
 
     HIP_TRY(hipEventRecord(c->ev[0], s));
-    launch_broad(V0, V1, nv, E, ne, F, nf, vf, vf_cap, ee, ee_cap, B, nbl, s);
+    launch_broad_boxes(V0, V1, nv, E, ne, F, nf, B, s);
+    HIP_TRY(hipEventRecord(c->ev[2], s));
+    launch_broad_sort(nv, ne, nf, B, nbl, s);
+    HIP_TRY(hipEventRecord(c->ev[3], s));
+    launch_broad_gather(E, F, nv, ne, nf, B, s);
+    HIP_TRY(hipEventRecord(c->ev[4], s));
+    launch_broad_sweep(nv, ne, nf, vf, vf_cap, ee, ee_cap, B, s);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(c->ev[1], s));
     unsigned long long *h = (unsigned long long *)c->host;
@@ -189,9 +197,17 @@ ccd_status ccd_broad(ccd_context *c, const double *V0, const double *V1, int64_t
     HIP_TRY(hipMemcpyAsync(h + 2, B.flags, 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(h + 3, B.axis, 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    float ms = 0.f;
+    float ms = 0.f, m_box = 0.f, m_sort = 0.f, m_gather = 0.f, m_sweep = 0.f;
     HIP_TRY(hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
+    HIP_TRY(hipEventElapsedTime(&m_box, c->ev[0], c->ev[2]));
+    HIP_TRY(hipEventElapsedTime(&m_sort, c->ev[2], c->ev[3]));
+    HIP_TRY(hipEventElapsedTime(&m_gather, c->ev[3], c->ev[4]));
+    HIP_TRY(hipEventElapsedTime(&m_sweep, c->ev[4], c->ev[1]));
     c->stats.broad_ms = ms;
+    c->stats.box_ms = m_box;
+    c->stats.sort_ms = m_sort;
+    c->stats.gather_ms = m_gather;
+    c->stats.sweep_ms = m_sweep;
     const uint32_t flags = (uint32_t)(h[2] & 0xffffffffu);
     c->stats.sort_axis = nb ? (int64_t)(int32_t)(h[3] & 0xffffffffu) : 0;
     *n_vf = (int64_t)h[0];
@@ -249,6 +265,7 @@ ccd_status ccd_narrow(ccd_context *c, const double *V0, const double *V1, int64_
     HIP_TRY(hipEventRecord(c->ev[2], s));
     launch_narrow_heavy(V0, V1, E, F, vf, ee, n_vf, delta, (long long)max_iter, hit, toi, nenq, B, nslots, cap, 0, s);
     HIP_TRY(hipGetLastError());
+    HIP_TRY(hipEventRecord(c->ev[3], s));
     launch_toi_min(toi, n, toi_min, s);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(c->ev[1], s));
@@ -256,12 +273,13 @@ ccd_status ccd_narrow(ccd_context *c, const double *V0, const double *V1, int64_
     HIP_TRY(hipMemcpyAsync(h, B.counters, 16 * 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(h + 16, B.flags, 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    float ms = 0.f, ms_light = 0.f;
+    float ms = 0.f, ms_light = 0.f, ms_heavy = 0.f;
     HIP_TRY(hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
     HIP_TRY(hipEventElapsedTime(&ms_light, c->ev[0], c->ev[2]));
+    HIP_TRY(hipEventElapsedTime(&ms_heavy, c->ev[2], c->ev[3]));
     c->stats.narrow_ms = ms;
     c->stats.narrow_light_ms = ms_light;
-    c->stats.narrow_heavy_ms = ms - ms_light;
+    c->stats.narrow_heavy_ms = ms_heavy;
     c->stats.heavy_pairs = h[0];
     c->stats.heavy_reruns = 0;
     uint32_t flags = h[16];

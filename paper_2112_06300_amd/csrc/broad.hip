@@ -27,7 +27,7 @@ constexpr int kSortThreads = 256;
 constexpr int kSortRounds = 16;
 constexpr int kSortTile = kSortThreads * kSortRounds;  // 4096 keys per block
 constexpr int kBins = 3 * 256;                        // segment x digit
-constexpr int kSweepBlock = 256;
+constexpr int kTile = 64;
 
 __global__ void zero_kernel(double *stats, unsigned long long *counts, uint32_t *flags)
 {
@@ -158,30 +158,49 @@ __global__ __launch_bounds__(kSortThreads) void hist_kernel(const uint32_t *__re
     for (int b = threadIdx.x; b < kBins; b += kSortThreads) hist[(int64_t)b * nblocks + blockIdx.x] = h[b];
 }
 
-// Exclusive scan of hist (bin-major, so each (bin, block) gets the global
-// output offset of its first key).  One workgroup; each thread scans a chunk.
-__global__ __launch_bounds__(1024) void scan_kernel(uint32_t *hist, int64_t total)
+// Offsets for the scatter: hist is bin-major ([bin][block]).  One wave per
+// bin turns its row into an exclusive prefix over blocks and records the
+// bin total; a second kernel scans the 768 totals into per-bin bases.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int lane)
+{
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t w = __shfl_up(v, o);
+        if (lane >= o) v += w;
+    }
+    return v;
+}
+
+__global__ __launch_bounds__(256) void bin_scan_kernel(uint32_t *hist, int64_t nblocks, uint32_t *tot)
+{
+    const int lane = threadIdx.x & 63;
+    const int bin = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (bin >= kBins) return;
+    uint32_t *row = hist + (int64_t)bin * nblocks;
+    uint32_t carry = 0u;
+    for (int64_t b0 = 0; b0 < nblocks; b0 += 64) {
+        const int64_t k = b0 + lane;
+        const uint32_t x = k < nblocks ? row[k] : 0u;
+        const uint32_t inc = wave_incl_scan(x, lane);
+        if (k < nblocks) row[k] = carry + inc - x;
+        carry += __shfl(inc, 63);
+    }
+    if (lane == 0) tot[bin] = carry;
+}
+
+__global__ __launch_bounds__(1024) void bin_base_kernel(const uint32_t *tot, uint32_t *base)
 {
     __shared__ uint32_t part[1024];
     const int t = threadIdx.x;
-    const int64_t chunk = (total + 1023) / 1024;
-    const int64_t b = t * chunk, e = b + chunk < total ? b + chunk : total;
-    uint32_t s = 0;
-    for (int64_t i = b; i < e; i++) s += hist[i];
-    part[t] = s;
+    const uint32_t x = t < kBins ? tot[t] : 0u;
+    part[t] = x;
     __syncthreads();
     for (int o = 1; o < 1024; o <<= 1) {
-        uint32_t v = t >= o ? part[t - o] : 0u;
+        const uint32_t v = t >= o ? part[t - o] : 0u;
         __syncthreads();
         part[t] += v;
         __syncthreads();
     }
-    uint32_t run = part[t] - s;  // exclusive prefix of this chunk
-    for (int64_t i = b; i < e; i++) {
-        const uint32_t x = hist[i];
-        hist[i] = run;
-        run += x;
-    }
+    if (t < kBins) base[t] = part[t] - x;
 }
 
 // Stable scatter: keys of the tile are ranked in their original order.  Each
@@ -190,10 +209,12 @@ __global__ __launch_bounds__(1024) void scan_kernel(uint32_t *hist, int64_t tota
 // offsets in order.
 __global__ __launch_bounds__(kSortThreads) void scatter_kernel(
     const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint32_t *kout, uint32_t *vout,
-    int64_t n, int64_t n0, int64_t n1, int shift, const uint32_t *__restrict__ hist, int64_t nblocks)
+    int64_t n, int64_t n0, int64_t n1, int shift, const uint32_t *__restrict__ hist, int64_t nblocks,
+    const uint32_t *__restrict__ bin_base)
 {
     __shared__ uint32_t off[kBins];
-    for (int b = threadIdx.x; b < kBins; b += kSortThreads) off[b] = hist[(int64_t)b * nblocks + blockIdx.x];
+    for (int b = threadIdx.x; b < kBins; b += kSortThreads)
+        off[b] = bin_base[b] + hist[(int64_t)b * nblocks + blockIdx.x];
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const unsigned long long lt = (1ull << lane) - 1ull;
@@ -268,85 +289,182 @@ __global__ void gather_kernel(const uint32_t *__restrict__ vals, int64_t nv, int
     }
 }
 
-// Append (a, b) for every lane with want set; one atomic per wave.
-__device__ __forceinline__ void emit_pairs(bool want, int32_t a, int32_t b, int32_t *out, int64_t cap,
-                                           unsigned long long *counter)
+// Sweep, one wave per tile of 64 consecutive sorted query records.  The
+// wave streams the candidate records (faces for a vertex tile, later edges
+// for an edge tile, vertices for a face tile) through LDS 64 at a time; every
+// lane tests its query against all 64, reading each candidate as an LDS
+// broadcast.  A lane's own window is enforced by comparisons (lower key,
+// upper key), so the tile scans the union of its lanes' windows and stops
+// once a chunk starts beyond every lane's upper key.
+//   vertex v -> face f:  key_lo(v) <= key_lo(f) <= key_hi(v)
+//   edge i   -> edge j:  i < j (sorted position), key_lo(j) <= key_hi(i)
+//   face f   -> vertex v: key_lo(f) <  key_lo(v) <= key_hi(f)
+// so each overlapping vertex-face pair is found from exactly one side.
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v)
 {
-    const unsigned long long mask = __ballot(want);
-    if (mask == 0ull) return;
-    const int lane = __lane_id();
-    const int leader = __ffsll((long long)mask) - 1;
+    for (int o = 32; o > 0; o >>= 1) { const uint32_t w = __shfl_xor(v, o); v = w < v ? w : v; }
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v)
+{
+    for (int o = 32; o > 0; o >>= 1) { const uint32_t w = __shfl_xor(v, o); v = w > v ? w : v; }
+    return v;
+}
+
+// Output staging: a tile keeps its pairs in LDS and reserves global space
+// with one atomic per flush, so waves do not contend on the pair counters.
+constexpr int kOutCap = 512;
+
+__device__ __forceinline__ void flush_pairs(int32_t (*buf)[2], int fill, int32_t *out, int64_t cap,
+                                            unsigned long long *counter, int lane)
+{
     unsigned long long base = 0ull;
-    if (lane == leader) base = atomicAdd(counter, (unsigned long long)__popcll(mask));
-    base = __shfl(base, leader);
-    if (want) {
-        const unsigned long long idx = base + (unsigned long long)__popcll(mask & ((1ull << lane) - 1ull));
+    if (lane == 0) base = atomicAdd(counter, (unsigned long long)fill);
+    base = __shfl(base, 0);
+    for (int k = lane; k < fill; k += kTile) {
+        const unsigned long long idx = base + (unsigned long long)k;
         if ((int64_t)idx < cap) {
-            out[2 * idx] = a;
-            out[2 * idx + 1] = b;
+            out[2 * idx] = buf[k][0];
+            out[2 * idx + 1] = buf[k][1];
         }
     }
 }
 
-__global__ __launch_bounds__(kSweepBlock) void sweep_kernel(
+__global__ __launch_bounds__(kTile) void sweep_kernel(
     const uint32_t *__restrict__ klo, const uint32_t *__restrict__ khi, const float *__restrict__ lob,
     const float *__restrict__ hib, const float *__restrict__ loc, const float *__restrict__ hic,
     const int32_t *__restrict__ pid, const int32_t *__restrict__ vtx, int64_t nv, int64_t ne, int64_t nf,
-    int32_t *vf, int64_t vf_cap, int32_t *ee, int64_t ee_cap, unsigned long long *counts)
+    int64_t tiles_v, int64_t tiles_e, int32_t *vf, int64_t vf_cap, int32_t *ee, int64_t ee_cap,
+    unsigned long long *counts)
 {
-    const int64_t nb = nv + ne + nf;
-    const int64_t i = (int64_t)blockIdx.x * kSweepBlock + threadIdx.x;
-    if (i >= nb) return;
-    const uint32_t kh = khi[i];
-    const float lb = lob[i], hb = hib[i], lc = loc[i], hc = hic[i];
-    const int32_t me = pid[i];
-    const int64_t f0 = nv + ne;  // first face record
-    if (i < nv) {
-        // vertex: faces with lower bound >= mine (first such via binary search)
-        const uint32_t kl = klo[i];
-        int64_t a = f0, b = nb;
-        while (a < b) {
-            const int64_t m = (a + b) >> 1;
-            if (klo[m] < kl) a = m + 1; else b = m;
-        }
-        for (int64_t j = a; j < nb; j++) {
-            if (klo[j] > kh) break;
-            bool want = lob[j] <= hb && lb <= hib[j] && loc[j] <= hc && lc <= hic[j];
-            if (want) {
-                const int32_t *fv = vtx + 3 * j;
-                want = fv[0] != me && fv[1] != me && fv[2] != me;
-            }
-            emit_pairs(want, me, pid[j], vf, vf_cap, &counts[0]);
-        }
-    } else if (i < f0) {
-        // edge: later edges in sorted order
-        const int32_t e0 = vtx[3 * i], e1 = vtx[3 * i + 1];
-        for (int64_t j = i + 1; j < f0; j++) {
-            if (klo[j] > kh) break;
-            bool want = lob[j] <= hb && lb <= hib[j] && loc[j] <= hc && lc <= hic[j];
-            if (want) {
-                const int32_t g0 = vtx[3 * j], g1 = vtx[3 * j + 1];
-                want = e0 != g0 && e0 != g1 && e1 != g0 && e1 != g1;
-            }
-            const int32_t o = pid[j];
-            emit_pairs(want, me < o ? me : o, me < o ? o : me, ee, ee_cap, &counts[1]);
-        }
+    __shared__ uint32_t s_klo[kTile];
+    __shared__ float4 s_box[kTile];
+    __shared__ int32_t s_pid[kTile];
+    __shared__ int32_t s_vtx[3][kTile];
+    __shared__ int32_t s_out[kOutCap][2];
+    const int lane = threadIdx.x;
+    const int64_t nb = nv + ne + nf, f0 = nv + ne;
+    const int64_t t = blockIdx.x;
+    int role;  // 0: vertex tile, 1: edge tile, 2: face tile
+    int64_t qbase, qend, cbeg, cend;
+    if (t < tiles_v) {
+        role = 0; qbase = t * kTile; qend = nv; cbeg = f0; cend = nb;
+    } else if (t < tiles_v + tiles_e) {
+        role = 1; qbase = nv + (t - tiles_v) * kTile; qend = f0; cbeg = nv; cend = f0;
     } else {
-        // face: vertices with lower bound > mine
-        const uint32_t kl = klo[i];
-        const int32_t v0 = vtx[3 * i], v1 = vtx[3 * i + 1], v2 = vtx[3 * i + 2];
-        int64_t a = 0, b = nv;
+        role = 2; qbase = f0 + (t - tiles_v - tiles_e) * kTile; qend = nb; cbeg = 0; cend = nv;
+    }
+    int32_t *out = role == 1 ? ee : vf;
+    const int64_t out_cap = role == 1 ? ee_cap : vf_cap;
+    unsigned long long *counter = role == 1 ? &counts[1] : &counts[0];
+    const int64_t i = qbase + lane;
+    const bool valid = i < qend;
+    uint32_t kl = 0xffffffffu, kh = 0u;
+    float lb = 0.f, hb = 0.f, lc = 0.f, hc = 0.f;
+    int32_t me = -1, w0 = -1, w1 = -1, w2 = -1;
+    if (valid) {
+        kl = klo[i]; kh = khi[i];
+        lb = lob[i]; hb = hib[i]; lc = loc[i]; hc = hic[i];
+        me = pid[i];
+        w0 = vtx[3 * i]; w1 = vtx[3 * i + 1]; w2 = vtx[3 * i + 2];
+    }
+    const uint32_t kmin = wave_min_u32(kl), kmax = wave_max_u32(kh);
+    int64_t js;
+    if (role == 1) {
+        js = qbase;
+    } else {
+        int64_t a = cbeg, b = cend;
         while (a < b) {
             const int64_t m = (a + b) >> 1;
-            if (klo[m] <= kl) a = m + 1; else b = m;
+            const uint32_t km = klo[m];
+            if (role == 0 ? km < kmin : km <= kmin) a = m + 1; else b = m;
         }
-        for (int64_t j = a; j < nv; j++) {
-            if (klo[j] > kh) break;
-            bool want = lob[j] <= hb && lb <= hib[j] && loc[j] <= hc && lc <= hic[j];
-            const int32_t v = pid[j];
-            want = want && v != v0 && v != v1 && v != v2;
-            emit_pairs(want, v, me, vf, vf_cap, &counts[0]);
+        js = a;
+    }
+    int fill = 0;  // pairs staged in s_out (wave-uniform)
+    for (int64_t cb = js; cb < cend; cb += kTile) {
+        const int64_t j = cb + lane;
+        uint32_t jk = 0xffffffffu;
+        if (j < cend) {
+            jk = klo[j];
+            s_box[lane] = make_float4(lob[j], hib[j], loc[j], hic[j]);
+            s_pid[lane] = pid[j];
+            s_vtx[0][lane] = vtx[3 * j]; s_vtx[1][lane] = vtx[3 * j + 1]; s_vtx[2][lane] = vtx[3 * j + 2];
         }
+        s_klo[lane] = jk;
+        const uint32_t first = __shfl(jk, 0);
+        if (first > kmax) break;  // uniform: this and every later chunk lies beyond all windows
+        __syncthreads();
+        // box tests: bit k of hits = overlap with candidate k of the chunk
+        unsigned long long hits = 0ull;
+#pragma unroll 16
+        for (int k = 0; k < kTile; k++) {
+            const uint32_t kj = s_klo[k];
+            const float4 bx = s_box[k];
+            bool ok = kj <= kh && bx.x <= hb && lb <= bx.y && bx.z <= hc && lc <= bx.w;
+            if (role == 0) ok = ok && kj >= kl;
+            else if (role == 1) ok = ok && cb + k > i;
+            else ok = ok && kj > kl;
+            hits |= (unsigned long long)ok << k;
+        }
+        // candidate rules on the (few) overlapping boxes
+        unsigned long long keep = 0ull;
+        for (unsigned long long m = hits; m; m &= m - 1ull) {
+            const int k = __ffsll((long long)m) - 1;
+            const int32_t g0 = s_vtx[0][k], g1 = s_vtx[1][k], g2 = s_vtx[2][k], o = s_pid[k];
+            bool ok;
+            if (role == 0) ok = g0 != me && g1 != me && g2 != me;
+            else if (role == 1) ok = w0 != g0 && w0 != g1 && w1 != g0 && w1 != g1;
+            else ok = o != w0 && o != w1 && o != w2;
+            if (ok) keep |= 1ull << k;
+        }
+        const uint32_t cnt = (uint32_t)__popcll(keep);
+        const uint32_t incl = wave_incl_scan(cnt, lane);
+        const int total = (int)__shfl(incl, 63);
+        if (total > 0) {
+            if (fill + total > kOutCap) {
+                flush_pairs(s_out, fill, out, out_cap, counter, lane);
+                fill = 0;
+                __syncthreads();
+            }
+            if (total <= kOutCap) {
+                int pos = fill + (int)(incl - cnt);
+                for (unsigned long long m = keep; m; m &= m - 1ull) {
+                    const int k = __ffsll((long long)m) - 1;
+                    const int32_t o = s_pid[k];
+                    int32_t a, b;
+                    if (role == 0) { a = me; b = o; }
+                    else if (role == 1) { a = me < o ? me : o; b = me < o ? o : me; }
+                    else { a = o; b = me; }
+                    s_out[pos][0] = a;
+                    s_out[pos][1] = b;
+                    pos++;
+                }
+                fill += total;
+            } else {
+                // more pairs than the staging buffer holds: write this chunk directly
+                unsigned long long base = 0ull;
+                if (lane == 0) base = atomicAdd(counter, (unsigned long long)total);
+                base = __shfl(base, 0);
+                unsigned long long idx = base + (incl - cnt);
+                for (unsigned long long m = keep; m; m &= m - 1ull) {
+                    const int k = __ffsll((long long)m) - 1;
+                    const int32_t o = s_pid[k];
+                    int32_t a, b;
+                    if (role == 0) { a = me; b = o; }
+                    else if (role == 1) { a = me < o ? me : o; b = me < o ? o : me; }
+                    else { a = o; b = me; }
+                    if ((int64_t)idx < out_cap) { out[2 * idx] = a; out[2 * idx + 1] = b; }
+                    idx++;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (fill > 0) {
+        __syncthreads();
+        flush_pairs(s_out, fill, out, out_cap, counter, lane);
     }
 }
 
@@ -354,9 +472,8 @@ inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 
 
 }  // namespace
 
-void launch_broad(const double *V0, const double *V1, int64_t nv, const int32_t *E, int64_t ne,
-                  const int32_t *F, int64_t nf, int32_t *vf, int64_t vf_cap, int32_t *ee, int64_t ee_cap,
-                  const BroadBuffers &B, int64_t nblocks_sort, hipStream_t s)
+void launch_broad_boxes(const double *V0, const double *V1, int64_t nv, const int32_t *E, int64_t ne,
+                        const int32_t *F, int64_t nf, const BroadBuffers &B, hipStream_t s)
 {
     const int64_t nb = nv + ne + nf;
     zero_kernel<<<1, 64, 0, s>>>(B.stats, B.counts, B.flags);
@@ -364,6 +481,13 @@ void launch_broad(const double *V0, const double *V1, int64_t nv, const int32_t 
     box_kernel<<<grid_for(nb, kBoxBlock), kBoxBlock, 0, s>>>(V0, V1, nv, E, ne, F, nf, B.lo[0], B.lo[1],
                                                             B.lo[2], B.hi[0], B.hi[1], B.hi[2], B.stats,
                                                             B.flags);
+}
+
+void launch_broad_sort(int64_t nv, int64_t ne, int64_t nf, const BroadBuffers &B, int64_t nblocks_sort,
+                       hipStream_t s)
+{
+    const int64_t nb = nv + ne + nf;
+    if (nb == 0) return;
     key_kernel<<<grid_for(nb, 256), 256, 0, s>>>(B.lo[0], B.lo[1], B.lo[2], nb, B.stats, B.axis, B.keyA,
                                                  B.valA);
     uint32_t *kin = B.keyA, *vin = B.valA, *kout = B.keyB, *vout = B.valB;
@@ -371,19 +495,36 @@ void launch_broad(const double *V0, const double *V1, int64_t nv, const int32_t 
         const int shift = 8 * pass;
         hist_kernel<<<(unsigned)nblocks_sort, kSortThreads, 0, s>>>(kin, nb, nv, nv + ne, shift, B.hist,
                                                                    nblocks_sort);
-        scan_kernel<<<1, 1024, 0, s>>>(B.hist, (int64_t)kBins * nblocks_sort);
+        bin_scan_kernel<<<kBins / 4, 256, 0, s>>>(B.hist, nblocks_sort, B.bin_tot);
+        bin_base_kernel<<<1, 1024, 0, s>>>(B.bin_tot, B.bin_base);
         scatter_kernel<<<(unsigned)nblocks_sort, kSortThreads, 0, s>>>(kin, vin, kout, vout, nb, nv, nv + ne,
-                                                                      shift, B.hist, nblocks_sort);
+                                                                      shift, B.hist, nblocks_sort, B.bin_base);
         uint32_t *tk = kin, *tv = vin;
         kin = kout; vin = vout; kout = tk; vout = tv;
     }
     // four passes: the sorted keys and values are back in keyA / valA
+}
+
+void launch_broad_gather(const int32_t *E, const int32_t *F, int64_t nv, int64_t ne, int64_t nf,
+                         const BroadBuffers &B, hipStream_t s)
+{
+    const int64_t nb = nv + ne + nf;
+    if (nb == 0) return;
     gather_kernel<<<grid_for(nb, 256), 256, 0, s>>>(B.valA, nv, ne, nf, E, F, B.lo[0], B.lo[1], B.lo[2],
                                                    B.hi[0], B.hi[1], B.hi[2], B.axis, B.khi, B.lob, B.hib,
                                                    B.loc, B.hic, B.pid, B.vtx);
-    sweep_kernel<<<grid_for(nb, kSweepBlock), kSweepBlock, 0, s>>>(B.keyA, B.khi, B.lob, B.hib, B.loc, B.hic,
-                                                                  B.pid, B.vtx, nv, ne, nf, vf, vf_cap, ee,
-                                                                  ee_cap, B.counts);
+}
+
+void launch_broad_sweep(int64_t nv, int64_t ne, int64_t nf, int32_t *vf, int64_t vf_cap, int32_t *ee,
+                        int64_t ee_cap, const BroadBuffers &B, hipStream_t s)
+{
+    const int64_t nb = nv + ne + nf;
+    if (nb == 0) return;
+    const int64_t tv = (nv + kTile - 1) / kTile, te = (ne + kTile - 1) / kTile, tf = (nf + kTile - 1) / kTile;
+    if (tv + te + tf == 0) return;
+    sweep_kernel<<<(unsigned)(tv + te + tf), kTile, 0, s>>>(B.keyA, B.khi, B.lob, B.hib, B.loc, B.hic, B.pid,
+                                                          B.vtx, nv, ne, nf, tv, te, vf, vf_cap, ee, ee_cap,
+                                                          B.counts);
 }
 
 int64_t sort_blocks(int64_t nb) { return nb > 0 ? (nb + kSortTile - 1) / kSortTile : 1; }

@@ -69,6 +69,7 @@ struct BroadBuffers {
     // sort keys / payload (double-buffered)
     uint32_t *keyA, *keyB, *valA, *valB;
     uint32_t *hist;       // 768 * nblocks
+    uint32_t *bin_tot, *bin_base;  // 768 each
     double *stats;        // 6 accumulators: sum c_a, sum c_a^2
     int32_t *axis;        // chosen sweep axis
     // sorted sweep records, segments [V | E | F]
@@ -82,9 +83,17 @@ struct BroadBuffers {
 
 int64_t sort_blocks(int64_t nb);
 
-void launch_broad(const double *V0, const double *V1, int64_t nv, const int32_t *E, int64_t ne,
-                  const int32_t *F, int64_t nf, int32_t *vf, int64_t vf_cap, int32_t *ee,
-                  int64_t ee_cap, const BroadBuffers &B, int64_t nblocks_sort, hipStream_t s);
+// Broad phase in four stages (the host records timing events between them):
+// boxes + centre statistics, sort (keys + 4 radix passes), gather of the
+// sorted sweep records, sweep.
+void launch_broad_boxes(const double *V0, const double *V1, int64_t nv, const int32_t *E, int64_t ne,
+                        const int32_t *F, int64_t nf, const BroadBuffers &B, hipStream_t s);
+void launch_broad_sort(int64_t nv, int64_t ne, int64_t nf, const BroadBuffers &B, int64_t nblocks_sort,
+                       hipStream_t s);
+void launch_broad_gather(const int32_t *E, const int32_t *F, int64_t nv, int64_t ne, int64_t nf,
+                         const BroadBuffers &B, hipStream_t s);
+void launch_broad_sweep(int64_t nv, int64_t ne, int64_t nf, int32_t *vf, int64_t vf_cap, int32_t *ee,
+                        int64_t ee_cap, const BroadBuffers &B, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Narrow-phase workspace.
@@ -106,7 +115,7 @@ struct HeavyEntry {
 struct NarrowBuffers {
     HeavyEntry *heavy;             // capacity n_pairs
     unsigned long long *spill;     // n_pairs * kSpillNodes packed nodes
-    unsigned int *counters;        // [0] heavy count, [1] heavy next, [2] overflow count, [3] rerun next
+    unsigned int *counters;        // [0] handed-over pairs, [1] work index, [2]/[3] overflow counts, [4] re-run index
     int32_t *overflow_list[2];     // heavy slots to re-run with larger buffers (alternating)
     unsigned long long *scratch;   // heavy frontier buffers
     uint32_t *flags;

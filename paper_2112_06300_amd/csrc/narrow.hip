@@ -92,7 +92,8 @@ __device__ __forceinline__ bool load_query(Query &q, bool vf, const int32_t ids[
 }
 
 // Inclusion box of F over the interval's 8 corners and the decision of
-// Alg. 3 (discard / report / split).  The corner values follow one fixed
+// Alg. 3 (discard / report / split).  Inputs are finite, so min / max are
+// exact; the sign of a zero bound never changes a decision.  The corner values follow one fixed
 // float64 sequence: x(t) = fma(t, x1 - x0, x0);
 //   VF: g = fma(-u, b - a, p - a), F = fma(-v, c - a, g)
 //   EE: A = fma(u, a1 - a0, a0), B = fma(v, b1 - b0, b0), F = A - B.
@@ -120,8 +121,8 @@ __device__ __forceinline__ int process(const Query &q, bool vf, double t0, doubl
 #pragma unroll
                     for (int iv = 0; iv < 2; iv++) {
                         const double f = fma(-(iv ? v1 : v0), ec, g);
-                        bmin = f < bmin ? f : bmin;
-                        bmax = f > bmax ? f : bmax;
+                        bmin = fmin(bmin, f);
+                        bmax = fmax(bmax, f);
                     }
                 }
             } else {
@@ -129,10 +130,8 @@ __device__ __forceinline__ int process(const Query &q, bool vf, double t0, doubl
                 const double A0 = fma(u0, ea, P0), A1 = fma(u1, ea, P0);
                 const double B0 = fma(v0, eb, P2), B1 = fma(v1, eb, P2);
                 const double f00 = A0 - B0, f01 = A0 - B1, f10 = A1 - B0, f11 = A1 - B1;
-                bmin = f00 < bmin ? f00 : bmin; bmax = f00 > bmax ? f00 : bmax;
-                bmin = f01 < bmin ? f01 : bmin; bmax = f01 > bmax ? f01 : bmax;
-                bmin = f10 < bmin ? f10 : bmin; bmax = f10 > bmax ? f10 : bmax;
-                bmin = f11 < bmin ? f11 : bmin; bmax = f11 > bmax ? f11 : bmax;
+                bmin = fmin(fmin(bmin, f00), fmin(f01, fmin(f10, f11)));
+                bmax = fmax(fmax(bmax, f00), fmax(f01, fmax(f10, f11)));
             }
         }
         if (bmin > q.eps[a] || bmax < -q.eps[a]) return DISCARD;
