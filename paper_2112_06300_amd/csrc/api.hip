@@ -70,6 +70,8 @@ struct ccd_context {
     void *host = nullptr;  // pinned host staging for counters and flags
     hipEvent_t ev[8] = {};
     ccd_stats stats{};
+    int cus = 256;            // compute units of the device
+    int pool_blocks = 1024;   // resident 64-lane workgroups of the pool stage
 };
 
 namespace {
@@ -110,6 +112,14 @@ ccd_status ccd_create(int device, ccd_context **out)
     HIP_TRY(hipSetDevice(device));
     ccd_context *c = new ccd_context();
     c->device = device;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0) {
+        c->cus = cus;
+    }
+    {
+        const int per_cu = pool_blocks_per_cu();
+        c->pool_blocks = per_cu * c->cus;
+    }
     if (hipHostMalloc(&c->host, 4096, hipHostMallocDefault) != hipSuccess) {
         delete c;
         return fail(CCD_ERR_OOM, "could not allocate pinned host staging");
@@ -237,13 +247,19 @@ ccd_status ccd_narrow(ccd_context *c, const double *V0, const double *V1, int64_
     HIP_TRY(hipSetDevice(c->device));
     hipStream_t s = (hipStream_t)stream;
     const size_t m = (size_t)std::max<int64_t>(n, 1);
-    const size_t need = aligned_total({m * sizeof(HeavyEntry), m * kSpillNodes * 8, 16 * 4, m * 4, m * 4, 4});
+    const int64_t hnode_cap = 4 * (int64_t)m + 65536;
+    const size_t need = aligned_total({m * 16, m * 24, m * 4, m * sizeof(HeavyEntry), (size_t)hnode_cap * 8, 16 * 4,
+                                       m * 4, m * 4, 4});
     ccd_status st = ensure(c->narrow, need);
     if (st != CCD_OK) return st;
     Carver cv(c->narrow.base);
     NarrowBuffers B;
+    B.ids4 = cv.take<int4>(m);
+    B.eps = cv.take<double>(3 * m);
+    B.m = cv.take<uint32_t>(m);
     B.heavy = cv.take<HeavyEntry>(m);
-    B.spill = cv.take<unsigned long long>(m * kSpillNodes);
+    B.hnodes = cv.take<unsigned long long>((size_t)hnode_cap);
+    B.hnode_cap = hnode_cap;
     B.counters = cv.take<unsigned int>(16);
     B.overflow_list[0] = cv.take<int32_t>(m);
     B.overflow_list[1] = cv.take<int32_t>(m);
@@ -260,10 +276,10 @@ ccd_status ccd_narrow(ccd_context *c, const double *V0, const double *V1, int64_
     long long *nenq = (long long *)n_enq;
     HIP_TRY(hipEventRecord(c->ev[0], s));
     launch_narrow_light(V0, V1, nv, E, ne, F, nf, vf, n_vf, ee, n_ee, delta, (long long)max_iter, hit, toi, nenq,
-                        B, s);
+                        B, c->pool_blocks, s);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(c->ev[2], s));
-    launch_narrow_heavy(V0, V1, E, F, vf, ee, n_vf, delta, (long long)max_iter, hit, toi, nenq, B, nslots, cap, 0, s);
+    launch_narrow_heavy(V0, V1, n_vf, delta, (long long)max_iter, hit, toi, nenq, B, nslots, cap, 0, s);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(c->ev[3], s));
     launch_toi_min(toi, n, toi_min, s);
@@ -303,8 +319,7 @@ ccd_status ccd_narrow(ccd_context *c, const double *V0, const double *V1, int64_
         if (st != CCD_OK) return st;
         B.scratch = (unsigned long long *)c->scratch.base;
         HIP_TRY(hipEventRecord(c->ev[0], s));
-        launch_narrow_heavy(V0, V1, E, F, vf, ee, n_vf, delta, (long long)max_iter, hit, toi, nenq, B, nslots, cap,
-                            round, s);
+        launch_narrow_heavy(V0, V1, n_vf, delta, (long long)max_iter, hit, toi, nenq, B, nslots, cap, round, s);
         HIP_TRY(hipGetLastError());
         launch_toi_min(toi, n, toi_min, s);
         HIP_TRY(hipGetLastError());

@@ -98,11 +98,10 @@ void launch_broad_sweep(int64_t nv, int64_t ne, int64_t nf, int32_t *vf, int64_t
 // ---------------------------------------------------------------------------
 // Narrow-phase workspace.
 // ---------------------------------------------------------------------------
-constexpr int kLightK = 8;          // survivors kept per pair per level in the light stage
-constexpr int kLightMaxLevel = 21;  // light-stage numerators are packed in 21 bits each
+constexpr int kLightMaxLevel = 21;  // the wave pool packs numerators in 21 bits each
 constexpr int kMaxLevel = 52;       // finest dyadic level per dimension
-constexpr int kSpillNodes = 2 * kLightK;
 
+// A pair handed to the wide stage: survivors at levels lvl, still to be split.
 struct HeavyEntry {
     int32_t pair;
     int32_t nnodes;
@@ -110,31 +109,39 @@ struct HeavyEntry {
     int32_t pad;
     double tstar;
     long long n_enq;
+    long long node_off;  // first survivor in the node buffer; -1: restart from the root
 };
 
 struct NarrowBuffers {
+    int4 *ids4;                    // the 4 vertex ids of every pair (x < 0: invalid pair)
+    double *eps;                   // C_eps half-widths, 3 per pair
+    uint32_t *m;                   // split levels m_t | m_u << 8 | m_v << 16 per pair
     HeavyEntry *heavy;             // capacity n_pairs
-    unsigned long long *spill;     // n_pairs * kSpillNodes packed nodes
-    unsigned int *counters;        // [0] handed-over pairs, [1] work index, [2]/[3] overflow counts, [4] re-run index
+    unsigned long long *hnodes;    // survivors of handed-over pairs (21-bit packed)
+    int64_t hnode_cap;
+    unsigned int *counters;        // [0] handed-over pairs, [1] work index, [2]/[3] overflow counts,
+                                   // [4] re-run index, [8..9] pair claim counter, [10..11] node counter
     int32_t *overflow_list[2];     // heavy slots to re-run with larger buffers (alternating)
     unsigned long long *scratch;   // heavy frontier buffers
     uint32_t *flags;
     double *toi_min;
 };
 
+// Resident 64-lane pool workgroups per CU.
+int pool_blocks_per_cu();
+
 void launch_narrow_light(const double *V0, const double *V1, int64_t nv, const int32_t *E, int64_t ne,
                          const int32_t *F, int64_t nf, const int32_t *vf, int64_t n_vf,
                          const int32_t *ee, int64_t n_ee, double delta, long long max_iter,
                          uint8_t *hit, double *toi, long long *n_enq, const NarrowBuffers &B,
-                         hipStream_t s);
+                         int pool_blocks, hipStream_t s);
 
 // Wide stage: `nslots` workgroups, each with a frontier buffer of `cap` nodes
 // (two buffers of 3 x cap uint64).  Round 0 works on every handed-over pair;
 // round r > 0 re-runs the pairs that overflowed their buffer in round r - 1.
-void launch_narrow_heavy(const double *V0, const double *V1, const int32_t *E, const int32_t *F,
-                         const int32_t *vf, const int32_t *ee, int64_t n_vf, double delta,
-                         long long max_iter, uint8_t *hit, double *toi, long long *n_enq,
-                         const NarrowBuffers &B, int nslots, int64_t cap, int round, hipStream_t s);
+void launch_narrow_heavy(const double *V0, const double *V1, int64_t n_vf, double delta, long long max_iter,
+                         uint8_t *hit, double *toi, long long *n_enq, const NarrowBuffers &B, int nslots,
+                         int64_t cap, int round, hipStream_t s);
 
 void launch_toi_min(const double *toi, int64_t n, double *out, hipStream_t s);
 

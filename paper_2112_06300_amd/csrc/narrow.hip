@@ -8,23 +8,29 @@
 // is counted (n_enq) and evaluated.  t* is kept per pair, so every pair's
 // answer is independent of every other pair and of evaluation order.
 //
-// Two stages share that procedure:
-//   light: one lane per pair, the pair's constants in VGPRs, survivors in a
-//          per-lane LDS ring (at most kLightK per level, numerators packed 21
-//          bits each).  Most pairs finish here.
-//   wide:  a pair whose frontier outgrows the ring, or that needs levels above
-//          21, is handed over (state + survivors) to a workgroup that runs its
-//          levels with all 256 lanes, frontier in HBM scratch.
+// Stages:
+//   prep:  per pair, the 4 vertex ids (checked), C_eps and the split levels.
+//   pool:  each wave keeps 64 pairs in flight (constants in LDS).  A round is
+//          a bookkeeping phase -- every owner lane consumes its pair's results,
+//          counts and caps, and pushes the next level's intervals into a
+//          shared LDS queue through a wave prefix sum -- followed by a
+//          converged evaluation phase in which every lane evaluates one queued
+//          interval of any pair.  The float64 work never diverges and the
+//          bookkeeping is paid once per level, not once per interval.
+//   wide:  pairs whose level does not fit the wave's queue, or that need
+//          levels above 21, continue in a workgroup of their own with the
+//          frontier in HBM scratch.
 #include "ccd_internal.h"
 
 namespace ccd {
 
 namespace {
 
-constexpr int kLightBlock = 256;
 constexpr int kHeavyBlock = 256;
+constexpr int kPoolSlots = 64;   // pairs in flight per wave (one owner lane each)
+constexpr int kQCap = 512;       // intervals per round per wave
+constexpr int kClaim = 256;      // pairs a wave claims from the global list at once
 constexpr int DISCARD = 0, ACCEPT = 1, SPLIT = 2;
-constexpr unsigned long long kInfBits = 0x7ff0000000000000ull;
 
 struct Query {
     double x0[4][3];  // points at t = 0 (VF: p, a, b, c; EE: a0, a1, b0, b1)
@@ -44,57 +50,75 @@ __device__ __forceinline__ int need_levels(double L, double delta)
     return m < 0 ? 0 : (m > 127 ? 127 : m);
 }
 
-// Load the 8 points, check them, and derive C_eps and the split levels.
-// C_eps: forward error bound of the evaluation below, 36 u M (vertex-face) or
-// 28 u M (edge-edge) per axis with u = 2^-53 and M the largest coordinate
-// magnitude of the 8 inputs on that axis, plus 2^-1060 for underflow.
-__device__ __forceinline__ bool load_query(Query &q, bool vf, const int32_t ids[4],
-                                           const double *__restrict__ V0, const double *__restrict__ V1,
-                                           double delta)
+// The 8 query points: raw[3 k + a] at t = 0 and raw[12 + 3 k + a] at t = 1.
+__device__ __forceinline__ void load_raw(const int4 ids, const double *__restrict__ V0,
+                                         const double *__restrict__ V1, double raw[24])
 {
-    double x1[4][3];
-    bool ok = true;
+    const int id[4] = {ids.x, ids.y, ids.z, ids.w};
+#pragma unroll
     for (int k = 0; k < 4; k++)
+#pragma unroll
         for (int a = 0; a < 3; a++) {
-            q.x0[k][a] = V0[3 * (int64_t)ids[k] + a];
-            x1[k][a] = V1[3 * (int64_t)ids[k] + a];
-            ok = ok && fabs(q.x0[k][a]) <= kMaxCoord && fabs(x1[k][a]) <= kMaxCoord;
+            raw[3 * k + a] = V0[3 * (int64_t)id[k] + a];
+            raw[12 + 3 * k + a] = V1[3 * (int64_t)id[k] + a];
         }
+}
+
+// C_eps and the split levels of one pair.  C_eps is the forward error bound of
+// the evaluation sequence in process(): 36 u M (vertex-face) or 28 u M
+// (edge-edge) per axis, u = 2^-53, M the largest coordinate magnitude of the
+// 8 inputs on that axis, plus 2^-1060 for underflow.  m_k is the number of
+// halvings after which dimension k (bounded derivative L_k) contributes at most
+// delta / 3 to the width of F.  Returns false for a coordinate that is not
+// finite or exceeds 2^960.
+__device__ __forceinline__ bool pair_constants(bool vf, const double raw[24], double delta, double eps[3],
+                                               uint32_t &mpack)
+{
+    bool ok = true;
     const double c = vf ? 36.0 : 28.0;
     double Lt = 0.0, Lu = 0.0, Lv = 0.0;
+#pragma unroll
     for (int a = 0; a < 3; a++) {
         double M = 0.0;
+        double dd[4];
+#pragma unroll
         for (int k = 0; k < 4; k++) {
-            q.d[k][a] = x1[k][a] - q.x0[k][a];
-            const double s0 = fabs(q.x0[k][a]), s1 = fabs(x1[k][a]);
+            const double x0 = raw[3 * k + a], x1 = raw[12 + 3 * k + a];
+            ok = ok && fabs(x0) <= kMaxCoord && fabs(x1) <= kMaxCoord;
+            dd[k] = x1 - x0;
+            const double s0 = fabs(x0), s1 = fabs(x1);
             M = s0 > M ? s0 : M;
             M = s1 > M ? s1 : M;
         }
-        q.eps[a] = ldexp(c * M, -53) + 0x1p-1060;
+        eps[a] = ldexp(c * M, -53) + 0x1p-1060;
         double lt, lu, lv;
         if (vf) {
-            lt = ((fabs(q.d[0][a]) + fabs(q.d[1][a])) + fabs(q.d[2][a])) + fabs(q.d[3][a]);
-            lu = fmax(fabs(q.x0[2][a] - q.x0[1][a]), fabs(x1[2][a] - x1[1][a]));
-            lv = fmax(fabs(q.x0[3][a] - q.x0[1][a]), fabs(x1[3][a] - x1[1][a]));
+            // dF/dt = dp - da - u (db - da) - v (dc - da); dF/du = -(b - a); dF/dv = -(c - a)
+            lt = ((fabs(dd[0]) + fabs(dd[1])) + fabs(dd[2])) + fabs(dd[3]);
+            lu = fmax(fabs(raw[6 + a] - raw[3 + a]), fabs(raw[18 + a] - raw[15 + a]));
+            lv = fmax(fabs(raw[9 + a] - raw[3 + a]), fabs(raw[21 + a] - raw[15 + a]));
         } else {
-            lt = fmax(fabs(q.d[0][a]), fabs(q.d[1][a])) + fmax(fabs(q.d[2][a]), fabs(q.d[3][a]));
-            lu = fmax(fabs(q.x0[1][a] - q.x0[0][a]), fabs(x1[1][a] - x1[0][a]));
-            lv = fmax(fabs(q.x0[3][a] - q.x0[2][a]), fabs(x1[3][a] - x1[2][a]));
+            // dF/dt = da0 + u (da1 - da0) - db0 - v (db1 - db0); dF/du = a1 - a0; dF/dv = -(b1 - b0)
+            lt = fmax(fabs(dd[0]), fabs(dd[1])) + fmax(fabs(dd[2]), fabs(dd[3]));
+            lu = fmax(fabs(raw[3 + a] - raw[0 + a]), fabs(raw[15 + a] - raw[12 + a]));
+            lv = fmax(fabs(raw[9 + a] - raw[6 + a]), fabs(raw[21 + a] - raw[18 + a]));
         }
         Lt = lt > Lt ? lt : Lt;
         Lu = lu > Lu ? lu : Lu;
         Lv = lv > Lv ? lv : Lv;
     }
-    q.m[0] = need_levels(Lt, delta);
-    q.m[1] = need_levels(Lu, delta);
-    q.m[2] = need_levels(Lv, delta);
+    mpack = (uint32_t)need_levels(Lt, delta) | ((uint32_t)need_levels(Lu, delta) << 8) |
+            ((uint32_t)need_levels(Lv, delta) << 16);
     return ok;
 }
 
+// 2^-l for 0 <= l <= 52, built from the exponent bits.
+__device__ __forceinline__ double pow2neg(int l) { return __longlong_as_double((long long)(1023 - l) << 52); }
+
 // Inclusion box of F over the interval's 8 corners and the decision of
 // Alg. 3 (discard / report / split).  Inputs are finite, so min / max are
-// exact; the sign of a zero bound never changes a decision.  The corner values follow one fixed
-// float64 sequence: x(t) = fma(t, x1 - x0, x0);
+// exact; the sign of a zero bound never changes a decision.  The corner
+// values follow one fixed float64 sequence: x(t) = fma(t, x1 - x0, x0);
 //   VF: g = fma(-u, b - a, p - a), F = fma(-v, c - a, g)
 //   EE: A = fma(u, a1 - a0, a0), B = fma(v, b1 - b0, b0), F = A - B.
 __device__ __forceinline__ int process(const Query &q, bool vf, double t0, double t1, double u0, double u1,
@@ -157,131 +181,371 @@ __device__ __forceinline__ int split_dim(const int m[3], const int l[3])
     return best;
 }
 
-__device__ __forceinline__ bool pair_ids(int64_t p, int64_t n_vf, const int32_t *__restrict__ vf,
-                                         const int32_t *__restrict__ ee, const int32_t *__restrict__ E,
-                                         int64_t ne, const int32_t *__restrict__ F, int64_t nf, int64_t nv,
-                                         int32_t ids[4])
+__device__ __forceinline__ void unpack_m(uint32_t mp, int m[3])
 {
+    m[0] = (int)(mp & 255u);
+    m[1] = (int)((mp >> 8) & 255u);
+    m[2] = (int)((mp >> 16) & 255u);
+}
+
+// ---------------------------------------------------------------------------
+// prep: vertex ids, C_eps and split levels of every pair.  ids.x = -1 marks a
+// pair with an index out of range, ids.x = -2 one with a bad coordinate.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void prep_kernel(const double *__restrict__ V0, const double *__restrict__ V1,
+                                                  int64_t nv, const int32_t *__restrict__ vf, int64_t n_vf,
+                                                  const int32_t *__restrict__ ee, int64_t n_ee,
+                                                  const int32_t *__restrict__ E, int64_t ne,
+                                                  const int32_t *__restrict__ F, int64_t nf, double delta,
+                                                  int4 *ids4, double *peps, uint32_t *pm, uint32_t *flags)
+{
+    const int64_t n = n_vf + n_ee;
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= n) return;
+    int32_t id[4] = {-1, -1, -1, -1};
+    bool ok;
     if (p < n_vf) {
         const int32_t v = vf[2 * p], f = vf[2 * p + 1];
-        if (v < 0 || v >= nv || f < 0 || f >= nf) return false;
-        ids[0] = v; ids[1] = F[3 * (int64_t)f]; ids[2] = F[3 * (int64_t)f + 1]; ids[3] = F[3 * (int64_t)f + 2];
+        ok = v >= 0 && v < nv && f >= 0 && f < nf;
+        if (ok) { id[0] = v; id[1] = F[3 * (int64_t)f]; id[2] = F[3 * (int64_t)f + 1]; id[3] = F[3 * (int64_t)f + 2]; }
     } else {
-        const int64_t q = p - n_vf;
-        const int32_t e = ee[2 * q], g = ee[2 * q + 1];
-        if (e < 0 || e >= ne || g < 0 || g >= ne) return false;
-        ids[0] = E[2 * (int64_t)e]; ids[1] = E[2 * (int64_t)e + 1];
-        ids[2] = E[2 * (int64_t)g]; ids[3] = E[2 * (int64_t)g + 1];
-    }
-    for (int k = 0; k < 4; k++)
-        if (ids[k] < 0 || ids[k] >= nv) return false;
-    return true;
-}
-
-__device__ __forceinline__ unsigned long long pack21(uint32_t nt, uint32_t nu, uint32_t nv_)
-{
-    return (unsigned long long)nt | ((unsigned long long)nu << 21) | ((unsigned long long)nv_ << 42);
-}
-
-__global__ __launch_bounds__(kLightBlock) void light_kernel(
-    const double *__restrict__ V0, const double *__restrict__ V1, int64_t nv, const int32_t *__restrict__ E,
-    int64_t ne, const int32_t *__restrict__ F, int64_t nf, const int32_t *__restrict__ vfp, int64_t n_vf,
-    const int32_t *__restrict__ eep, int64_t n_ee, double delta, long long max_iter, uint8_t *hit,
-    double *toi, long long *n_enq_out, HeavyEntry *heavy, unsigned long long *spill, unsigned int *counters,
-    uint32_t *flags)
-{
-    __shared__ unsigned long long ring[2][2 * kLightK][kLightBlock];
-    const int tid = threadIdx.x;
-    const int64_t p = (int64_t)blockIdx.x * kLightBlock + tid;
-    if (p >= n_vf + n_ee) return;
-    const bool vf = p < n_vf;
-    int32_t ids[4];
-    if (!pair_ids(p, n_vf, vfp, eep, E, ne, F, nf, nv, ids)) {
-        atomicOr(flags, FLAG_BAD_INDEX);
-        hit[p] = 0; toi[p] = __builtin_huge_val();
-        if (n_enq_out) n_enq_out[p] = 0;
-        return;
-    }
-    Query q;
-    if (!load_query(q, vf, ids, V0, V1, delta)) {
-        atomicOr(flags, FLAG_NONFINITE);
-        hit[p] = 0; toi[p] = __builtin_huge_val();
-        if (n_enq_out) n_enq_out[p] = 0;
-        return;
-    }
-    int l[3] = {0, 0, 0};
-    double tstar = __builtin_huge_val();
-    long long nenq = 0;
-    int nS = 0, cur = 0;
-    bool capped = false;
-    double tcap = 0.0;
-    {
-        const int r = process(q, vf, 0.0, 1.0, 0.0, 1.0, 0.0, 1.0, false, delta);
-        if (r == ACCEPT) tstar = 0.0;
-        if (r == SPLIT) { ring[0][0][tid] = 0ull; nS = 1; }
-    }
-    while (nS > 0) {
-        const int k = split_dim(q.m, l);
-        if (l[k] + 1 > kLightMaxLevel) {
-            // hand over the survivors of this level, still to be split
-            const unsigned slot = atomicAdd(&counters[0], 1u);
-            HeavyEntry h;
-            h.pair = (int32_t)p; h.nnodes = nS; h.lvl[0] = l[0]; h.lvl[1] = l[1]; h.lvl[2] = l[2];
-            h.pad = 0; h.tstar = tstar; h.n_enq = nenq;
-            heavy[slot] = h;
-            for (int i = 0; i < nS; i++) spill[(int64_t)slot * kSpillNodes + i] = ring[cur][i][tid];
-            return;
+        const int64_t qq = p - n_vf;
+        const int32_t e = ee[2 * qq], g = ee[2 * qq + 1];
+        ok = e >= 0 && e < ne && g >= 0 && g < ne;
+        if (ok) {
+            id[0] = E[2 * (int64_t)e]; id[1] = E[2 * (int64_t)e + 1];
+            id[2] = E[2 * (int64_t)g]; id[3] = E[2 * (int64_t)g + 1];
         }
-        l[k]++;
-        const int sh = 21 * k;
-        const double tsnap = tstar;
-        const double tscale = ldexp(1.0, -l[0]), uscale = ldexp(1.0, -l[1]), vscale = ldexp(1.0, -l[2]);
-        const bool finest = false;  // light levels never reach the finest level
+    }
+    for (int k = 0; k < 4; k++) ok = ok && id[k] >= 0 && id[k] < nv;
+    if (!ok) {
+        atomicOr(flags, FLAG_BAD_INDEX);
+        ids4[p] = make_int4(-1, 0, 0, 0);
+        return;
+    }
+    const int4 ids = make_int4(id[0], id[1], id[2], id[3]);
+    double raw[24], eps[3];
+    load_raw(ids, V0, V1, raw);
+    uint32_t mp = 0u;
+    if (!pair_constants(p < n_vf, raw, delta, eps, mp)) {
+        atomicOr(flags, FLAG_NONFINITE);
+        ids4[p] = make_int4(-2, 0, 0, 0);
+        return;
+    }
+    ids4[p] = ids;
+    peps[3 * p] = eps[0];
+    peps[3 * p + 1] = eps[1];
+    peps[3 * p + 2] = eps[2];
+    pm[p] = mp;
+}
+
+__device__ __forceinline__ int wave_excl_scan(int v, int lane, int &total)
+{
+    int x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int w = __shfl_up(x, o);
+        if (lane >= o) x += w;
+    }
+    total = __shfl(x, 63);
+    return x - v;
+}
+
+struct PoolLds {
+    double x0[12][kPoolSlots];   // query points at t = 0 of each slot's pair
+    double d[12][kPoolSlots];    // displacements
+    double eps[3][kPoolSlots];
+    uint32_t lv[kPoolSlots];     // levels l_t | l_u << 8 | l_v << 16 | vertex-face << 24
+    unsigned long long node[2][kQCap];  // interval numerators, 21 bits each (t | u << 21 | v << 42)
+    uint8_t slot[2][kQCap];
+    uint8_t res[kQCap];
+    // per-slot accumulators of one bookkeeping pass
+    unsigned long long tstar[kPoolSlots];  // t* bits (non-negative doubles order like uint64)
+    unsigned long long tmin[kPoolSlots];   // earliest kept child
+    unsigned long long hoff[kPoolSlots];   // first node of a hand-over in the node buffer
+    int nsurv[kPoolSlots], cnt[kPoolSlots], k[kPoolSlots], off[kPoolSlots], pos[kPoolSlots];
+};
+
+constexpr unsigned long long kInfBits = 0x7ff0000000000000ull;
+constexpr int kNoExpand = -1, kHandNodes = -2;
+
+__device__ __forceinline__ double node_tlo(unsigned long long nd, double tscale)
+{
+    return (double)(uint32_t)(nd & 0x1fffffull) * tscale;
+}
+
+__device__ __forceinline__ unsigned long long child_of(unsigned long long nd, int k, int c)
+{
+    const int sh = 21 * k;
+    const unsigned long long nk = (nd >> sh) & 0x1fffffull;
+    return (nd & ~(0x1fffffull << sh)) | ((2ull * nk + (unsigned long long)c) << sh);
+}
+
+__global__ __launch_bounds__(kPoolSlots) void pool_kernel(
+    const double *__restrict__ V0, const double *__restrict__ V1, const int4 *__restrict__ ids4,
+    const double *__restrict__ peps, const uint32_t *__restrict__ pm, int64_t n_vf, int64_t n_pairs,
+    double delta, long long max_iter, uint8_t *hit, double *toi, long long *n_enq_out, HeavyEntry *heavy,
+    unsigned long long *hnodes, int64_t hnode_cap, unsigned int *counters)
+{
+    __shared__ PoolLds S;
+    const int lane = threadIdx.x;
+    const unsigned long long lt_mask = (1ull << lane) - 1ull;
+    // wave-uniform chunk of unclaimed pairs
+    long long ch_cur = 0, ch_end = 0;
+    bool exhausted = false;
+    // prefetched next pair (np >= 0) and its data
+    long long np = -1;
+    bool np_ok = false;
+    double raw[24], neps[3];
+    uint32_t nm = 0u;
+    // the pair this lane owns (slot = lane)
+    bool active = false;
+    long long p = -1;
+    bool vf = false;
+    int m[3] = {0, 0, 0}, l[3] = {0, 0, 0};
+    double tstar = 0.0;
+    long long nenq = 0;
+    int cur = 0;  // queue holding last round's evaluated entries
+    int nq = 0;   // its length
+
+    for (;;) {
+        // ---- claim and prefetch the next pair of every lane without one (uniform control flow)
+        bool need = np < 0 && !exhausted;
+        unsigned long long want = __ballot(need);
+        while (want) {
+            if (ch_cur >= ch_end) {
+                unsigned long long b = 0ull;
+                if (lane == 0) b = atomicAdd((unsigned long long *)&counters[8], (unsigned long long)kClaim);
+                b = __shfl(b, 0);
+                ch_cur = (long long)b;
+                ch_end = ch_cur + kClaim < n_pairs ? ch_cur + kClaim : n_pairs;
+                if (ch_cur >= n_pairs) { exhausted = true; break; }
+            }
+            const long long avail = ch_end - ch_cur;
+            const long long rank = __popcll(want & lt_mask);
+            if (need && rank < avail) {
+                np = ch_cur + rank;
+                need = false;
+                const int4 id = ids4[np];
+                np_ok = id.x >= 0;
+                if (np_ok) {
+                    load_raw(id, V0, V1, raw);
+                    neps[0] = peps[3 * np]; neps[1] = peps[3 * np + 1]; neps[2] = peps[3 * np + 2];
+                    nm = pm[np];
+                }
+            }
+            const long long taken = __popcll(want) < avail ? __popcll(want) : avail;
+            ch_cur += taken;
+            want = __ballot(need);
+        }
         const int nxt = cur ^ 1;
-        int nN = 0;
-        long long cnt = 0;
-        double tmin = __builtin_huge_val();
-        for (int i = 0; i < nS; i++) {
-            const unsigned long long par = ring[cur][i][tid];
-            const unsigned long long nk = (par >> sh) & 0x1fffffull;
-            const unsigned long long base = par & ~(0x1fffffull << sh);
-#pragma unroll
-            for (int c = 0; c < 2; c++) {
-                const unsigned long long ch = base | ((2ull * nk + (unsigned long long)c) << sh);
-                const uint32_t nt = (uint32_t)(ch & 0x1fffffull);
-                const uint32_t nu = (uint32_t)((ch >> 21) & 0x1fffffull);
-                const uint32_t nvv = (uint32_t)((ch >> 42) & 0x1fffffull);
-                const double t0 = (double)nt * tscale;
-                if (!(t0 < tsnap)) continue;
-                cnt++;
-                tmin = t0 < tmin ? t0 : tmin;
-                if (!(t0 < tstar)) continue;  // pruned by a root found earlier in this level
-                const double t1 = (double)(nt + 1u) * tscale;
-                const double u0 = (double)nu * uscale, u1 = (double)(nu + 1u) * uscale;
-                const double v0 = (double)nvv * vscale, v1 = (double)(nvv + 1u) * vscale;
-                const int r = process(q, vf, t0, t1, u0, u1, v0, v1, finest, delta);
-                if (r == ACCEPT) tstar = t0;
-                else if (r == SPLIT) ring[nxt][nN++][tid] = ch;
+
+        // ---- A: reset this slot's accumulators
+        S.tstar[lane] = (unsigned long long)__double_as_longlong(tstar);
+        S.tmin[lane] = kInfBits;
+        S.nsurv[lane] = 0;
+        S.cnt[lane] = 0;
+        S.pos[lane] = 0;
+        S.k[lane] = kNoExpand;
+        __syncthreads();
+        // ---- B (all lanes over all entries): reported roots lower t*, split entries are survivors
+        for (int b0 = 0; b0 < nq; b0 += kPoolSlots) {
+            const int e = b0 + lane;
+            if (e < nq) {
+                const int r = S.res[e];
+                const int s = S.slot[cur][e];
+                if (r == ACCEPT) {
+                    const double tl = node_tlo(S.node[cur][e], pow2neg((int)(S.lv[s] & 255u)));
+                    atomicMin(&S.tstar[s], (unsigned long long)__double_as_longlong(tl));
+                } else if (r == SPLIT) {
+                    atomicAdd(&S.nsurv[s], 1);
+                }
             }
         }
-        nenq += cnt;
-        if (cnt == 0) { nS = 0; break; }
-        if (nenq > max_iter) { capped = true; tcap = tmin; nS = 0; break; }
-        if (nN > kLightK) {
-            const unsigned slot = atomicAdd(&counters[0], 1u);
-            HeavyEntry h;
-            h.pair = (int32_t)p; h.nnodes = nN; h.lvl[0] = l[0]; h.lvl[1] = l[1]; h.lvl[2] = l[2];
-            h.pad = 0; h.tstar = tstar; h.n_enq = nenq;
-            heavy[slot] = h;
-            for (int i = 0; i < nN; i++) spill[(int64_t)slot * kSpillNodes + i] = ring[nxt][i][tid];
-            return;
+        __syncthreads();
+        // ---- C (owner lanes): finished, handed over for depth, or expanding along k
+        int outcome = 0;  // 1 finished, 2 capped, 3 hand over, 4 push the next level
+        int k = -1, nsurv = 0;
+        if (active) {
+            tstar = __longlong_as_double((long long)S.tstar[lane]);
+            nsurv = S.nsurv[lane];
+            if (nsurv == 0) {
+                outcome = 1;
+            } else {
+                k = split_dim(m, l);
+                if (l[k] + 1 > kLightMaxLevel) outcome = 3;
+                else S.k[lane] = k;
+            }
         }
+        __syncthreads();
+        // ---- D (all lanes over all entries): count the children that start before t*
+        for (int b0 = 0; b0 < nq; b0 += kPoolSlots) {
+            const int e = b0 + lane;
+            if (e < nq && S.res[e] == SPLIT) {
+                const int s = S.slot[cur][e];
+                const int ks = S.k[s];
+                if (ks >= 0) {
+                    const double tsn = pow2neg((int)(S.lv[s] & 255u) + (ks == 0 ? 1 : 0));
+                    const double ts = __longlong_as_double((long long)S.tstar[s]);
+                    const unsigned long long nd = S.node[cur][e];
+#pragma unroll
+                    for (int c = 0; c < 2; c++) {
+                        const double tl = node_tlo(child_of(nd, ks, c), tsn);
+                        if (tl < ts) {
+                            atomicAdd(&S.cnt[s], 1);
+                            atomicMin(&S.tmin[s], (unsigned long long)__double_as_longlong(tl));
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        // ---- E (owner lanes): count, cap, queue offsets; a level that does not fit is handed over
+        int push = 0;
+        const double tmin = __longlong_as_double((long long)S.tmin[lane]);
+        if (outcome == 0 && active) {
+            const int cnt = S.cnt[lane];
+            if (cnt == 0) outcome = 1;
+            else if (nenq + cnt > max_iter) { outcome = 2; nenq += cnt; }
+            else { outcome = 4; push = cnt; }
+        }
+        int total = 0;
+        int off = wave_excl_scan(outcome == 4 ? push : 0, lane, total);
+        if (total > kQCap) {
+            if (outcome == 4 && off + push > kQCap) outcome = 3;
+            off = wave_excl_scan(outcome == 4 ? push : 0, lane, total);
+        }
+        if (outcome == 1 || outcome == 2) {
+            hit[p] = (uint8_t)(outcome == 2 || tstar < __builtin_huge_val());
+            toi[p] = outcome == 2 ? tmin : tstar;
+            if (n_enq_out) n_enq_out[p] = nenq;
+            active = false;
+            S.k[lane] = kNoExpand;
+        } else if (outcome == 3) {
+            // survivors (levels l, still to be split), t* and count go to the wide stage
+            const unsigned hs = atomicAdd(&counters[0], 1u);
+            const unsigned long long ho = atomicAdd((unsigned long long *)&counters[10], (unsigned long long)nsurv);
+            HeavyEntry h;
+            h.pair = (int32_t)p;
+            h.pad = 0;
+            if ((int64_t)(ho + nsurv) <= hnode_cap) {
+                h.nnodes = nsurv;
+                h.lvl[0] = l[0]; h.lvl[1] = l[1]; h.lvl[2] = l[2];
+                h.tstar = tstar;
+                h.n_enq = nenq;
+                h.node_off = (long long)ho;
+                S.hoff[lane] = ho;
+                S.k[lane] = kHandNodes;
+            } else {
+                h.nnodes = 1;  // node buffer full: the wide stage restarts the pair from its root
+                h.lvl[0] = h.lvl[1] = h.lvl[2] = 0;
+                h.tstar = __builtin_huge_val();
+                h.n_enq = 0;
+                h.node_off = -1;
+                S.k[lane] = kNoExpand;
+            }
+            heavy[hs] = h;
+            active = false;
+        } else if (outcome == 4) {
+            S.off[lane] = off;
+        }
+        __syncthreads();
+        // ---- F (all lanes over all entries): write kept children, or copy hand-over survivors
+        for (int b0 = 0; b0 < nq; b0 += kPoolSlots) {
+            const int e = b0 + lane;
+            if (e < nq && S.res[e] == SPLIT) {
+                const int s = S.slot[cur][e];
+                const int ks = S.k[s];
+                const unsigned long long nd = S.node[cur][e];
+                if (ks >= 0) {
+                    const double tsn = pow2neg((int)(S.lv[s] & 255u) + (ks == 0 ? 1 : 0));
+                    const double ts = __longlong_as_double((long long)S.tstar[s]);
+#pragma unroll
+                    for (int c = 0; c < 2; c++) {
+                        const unsigned long long ch = child_of(nd, ks, c);
+                        if (node_tlo(ch, tsn) < ts) {
+                            const int q = S.off[s] + atomicAdd(&S.pos[s], 1);
+                            S.node[nxt][q] = ch;
+                            S.slot[nxt][q] = (uint8_t)s;
+                        }
+                    }
+                } else if (ks == kHandNodes) {
+                    hnodes[S.hoff[s] + (unsigned long long)atomicAdd(&S.pos[s], 1)] = nd;
+                }
+            }
+        }
+        __syncthreads();
+        // ---- G (owner lanes): new levels; free slots take their prefetched pair as a new root
+        if (outcome == 4) {
+            l[k]++;
+            nenq += push;
+            S.lv[lane] = (uint32_t)l[0] | ((uint32_t)l[1] << 8) | ((uint32_t)l[2] << 16) | ((uint32_t)vf << 24);
+        }
+        if (!active && np >= 0 && !np_ok) {
+            // a pair with a bad index or coordinate: reported as no collision (the call returns an error)
+            hit[np] = 0;
+            toi[np] = __builtin_huge_val();
+            if (n_enq_out) n_enq_out[np] = 0;
+            np = -1;
+        }
+        const bool new_root = !active && np >= 0;
+        int rtotal = 0;
+        const int roff = wave_excl_scan(new_root ? 1 : 0, lane, rtotal);
+        const bool root_fits = new_root && total + roff < kQCap;
+        if (root_fits) {
+            p = np;
+            np = -1;
+            vf = p < n_vf;
+#pragma unroll
+            for (int kk = 0; kk < 12; kk++) {
+                S.x0[kk][lane] = raw[kk];
+                S.d[kk][lane] = raw[12 + kk] - raw[kk];
+            }
+            S.eps[0][lane] = neps[0]; S.eps[1][lane] = neps[1]; S.eps[2][lane] = neps[2];
+            unpack_m(nm, m);
+            l[0] = l[1] = l[2] = 0;
+            tstar = __builtin_huge_val();
+            nenq = 0;
+            S.node[nxt][total + roff] = 0ull;
+            S.slot[nxt][total + roff] = (uint8_t)lane;
+            S.lv[lane] = (uint32_t)vf << 24;
+            active = true;
+        }
+        const int T = total + __popcll(__ballot(root_fits));
+        if (T == 0 && !__ballot(np >= 0)) break;  // nothing queued and no pair left for this wave
+        __syncthreads();
+        // ---- evaluation phase: one queued interval per lane, any slot
+        for (int b0 = 0; b0 < T; b0 += kPoolSlots) {
+            const int e = b0 + lane;
+            if (e < T) {
+                const int s = S.slot[nxt][e];
+                const unsigned long long nd = S.node[nxt][e];
+                const uint32_t lvp = S.lv[s];
+                const bool evf = (lvp >> 24) & 1u;
+                const double tscale = pow2neg((int)(lvp & 255u));
+                const double uscale = pow2neg((int)((lvp >> 8) & 255u));
+                const double vscale = pow2neg((int)((lvp >> 16) & 255u));
+                const uint32_t nt = (uint32_t)(nd & 0x1fffffull);
+                const uint32_t nu = (uint32_t)((nd >> 21) & 0x1fffffull);
+                const uint32_t nw = (uint32_t)((nd >> 42) & 0x1fffffull);
+                Query q;
+#pragma unroll
+                for (int kk = 0; kk < 4; kk++)
+#pragma unroll
+                    for (int a = 0; a < 3; a++) {
+                        q.x0[kk][a] = S.x0[3 * kk + a][s];
+                        q.d[kk][a] = S.d[3 * kk + a][s];
+                    }
+                q.eps[0] = S.eps[0][s]; q.eps[1] = S.eps[1][s]; q.eps[2] = S.eps[2][s];
+                const int r = process(q, evf, (double)nt * tscale, (double)(nt + 1u) * tscale, (double)nu * uscale,
+                                      (double)(nu + 1u) * uscale, (double)nw * vscale, (double)(nw + 1u) * vscale,
+                                      false, delta);
+                S.res[e] = (uint8_t)r;
+            }
+        }
+        __syncthreads();
         cur = nxt;
-        nS = nN;
+        nq = T;
     }
-    hit[p] = (uint8_t)((tstar < __builtin_huge_val()) || capped);
-    toi[p] = capped ? tcap : tstar;
-    if (n_enq_out) n_enq_out[p] = nenq;
 }
 
 __device__ __forceinline__ double wave_min(double v)
@@ -299,15 +563,16 @@ __device__ __forceinline__ long long wave_sum_ll(long long v)
     return v;
 }
 
-// Wide stage: one workgroup per handed-over pair.  `list` (optional) maps work
-// indices to heavy slots; `list_count` holds the number of work items.
+// Wide stage: one workgroup per handed-over pair, frontier in HBM scratch.
+// `list` (optional) maps work indices to heavy slots; `list_count` holds the
+// number of work items.
 __global__ __launch_bounds__(kHeavyBlock) void heavy_kernel(
-    const double *__restrict__ V0, const double *__restrict__ V1, const int32_t *__restrict__ E,
-    const int32_t *__restrict__ F, const int32_t *__restrict__ vfp, const int32_t *__restrict__ eep,
-    int64_t n_vf, double delta, long long max_iter, uint8_t *hit, double *toi, long long *n_enq_out,
-    const HeavyEntry *__restrict__ heavy, const unsigned long long *__restrict__ spill,
-    const int32_t *list, const unsigned int *list_count, unsigned int *next, int32_t *ovf_list,
-    unsigned int *ovf_count, unsigned long long *scratch, int64_t cap, uint32_t *flags)
+    const double *__restrict__ V0, const double *__restrict__ V1, const int4 *__restrict__ ids4,
+    const double *__restrict__ peps, const uint32_t *__restrict__ pm, int64_t n_vf, double delta,
+    long long max_iter, uint8_t *hit, double *toi, long long *n_enq_out, const HeavyEntry *__restrict__ heavy,
+    const unsigned long long *__restrict__ hnodes, const int32_t *list, const unsigned int *list_count,
+    unsigned int *next, int32_t *ovf_list, unsigned int *ovf_count, unsigned long long *scratch, int64_t cap,
+    uint32_t *flags)
 {
     __shared__ int s_idx;
     __shared__ unsigned long long s_tstar;  // live t* as bits (non-negative doubles order like uint64)
@@ -329,39 +594,48 @@ __global__ __launch_bounds__(kHeavyBlock) void heavy_kernel(
         const HeavyEntry h = heavy[slot];
         const int64_t p = h.pair;
         const bool vf = p < n_vf;
-        int32_t ids[4];
-        if (vf) {
-            const int32_t f = vfp[2 * p + 1];
-            ids[0] = vfp[2 * p]; ids[1] = F[3 * (int64_t)f]; ids[2] = F[3 * (int64_t)f + 1];
-            ids[3] = F[3 * (int64_t)f + 2];
-        } else {
-            const int64_t qq = p - n_vf;
-            const int32_t e = eep[2 * qq], g = eep[2 * qq + 1];
-            ids[0] = E[2 * (int64_t)e]; ids[1] = E[2 * (int64_t)e + 1];
-            ids[2] = E[2 * (int64_t)g]; ids[3] = E[2 * (int64_t)g + 1];
-        }
+        double raw[24];
+        load_raw(ids4[p], V0, V1, raw);
         Query q;
-        load_query(q, vf, ids, V0, V1, delta);  // inputs were checked by the light stage
+#pragma unroll
+        for (int kk = 0; kk < 4; kk++)
+#pragma unroll
+            for (int a = 0; a < 3; a++) {
+                q.x0[kk][a] = raw[3 * kk + a];
+                q.d[kk][a] = raw[12 + 3 * kk + a] - raw[3 * kk + a];
+            }
+        q.eps[0] = peps[3 * p]; q.eps[1] = peps[3 * p + 1]; q.eps[2] = peps[3 * p + 2];
+        unpack_m(pm[p], q.m);
         int l[3] = {h.lvl[0], h.lvl[1], h.lvl[2]};
         long long nenq = h.n_enq;
         int64_t nS = h.nnodes;
         unsigned long long *cur = A, *nxt = Bb;
-        if (tid < nS) {
-            const unsigned long long pk = spill[(int64_t)slot * kSpillNodes + tid];
-            cur[tid] = pk & 0x1fffffull;
-            cur[cap + tid] = (pk >> 21) & 0x1fffffull;
-            cur[2 * cap + tid] = (pk >> 42) & 0x1fffffull;
-        }
-        if (tid == 0) { s_tstar = __double_as_longlong(h.tstar); s_overflow = 0u; }
-        __syncthreads();
-        double tcap = 0.0;
         int state = 0;
+        double tcap = 0.0;
+        double tstart = h.tstar;
+        if (h.node_off < 0) {
+            // restart from the root
+            const int r = process(q, vf, 0.0, 1.0, 0.0, 1.0, 0.0, 1.0, false, delta);
+            if (r == ACCEPT) { state = 1; tstart = 0.0; }
+            else if (r == DISCARD) state = 1;
+            if (tid == 0) { cur[0] = 0ull; cur[cap] = 0ull; cur[2 * cap] = 0ull; }
+            nS = 1;
+        } else {
+            for (int64_t i = tid; i < nS; i += kHeavyBlock) {
+                const unsigned long long pk = hnodes[h.node_off + i];
+                cur[i] = pk & 0x1fffffull;
+                cur[cap + i] = (pk >> 21) & 0x1fffffull;
+                cur[2 * cap + i] = (pk >> 42) & 0x1fffffull;
+            }
+        }
+        if (tid == 0) { s_tstar = (unsigned long long)__double_as_longlong(tstart); s_overflow = 0u; }
+        __syncthreads();
         while (state == 0) {
             const int k = split_dim(q.m, l);
             if (k < 0) break;  // unreachable: intervals at the finest level are always reported
             l[k]++;
             const double tsnap = __longlong_as_double((long long)s_tstar);
-            const double tscale = ldexp(1.0, -l[0]), uscale = ldexp(1.0, -l[1]), vscale = ldexp(1.0, -l[2]);
+            const double tscale = pow2neg(l[0]), uscale = pow2neg(l[1]), vscale = pow2neg(l[2]);
             const bool finest = l[0] == kMaxLevel && l[1] == kMaxLevel && l[2] == kMaxLevel;
             if (tid == 0) s_nN = 0u;
             __syncthreads();
@@ -485,21 +759,30 @@ __global__ void counters_zero_kernel(unsigned int *c, int n, uint32_t *flags)
 
 }  // namespace
 
+int pool_blocks_per_cu()
+{
+    int b = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, pool_kernel, kPoolSlots, 0) != hipSuccess || b < 1) b = 4;
+    return b;
+}
+
 void launch_narrow_light(const double *V0, const double *V1, int64_t nv, const int32_t *E, int64_t ne,
                          const int32_t *F, int64_t nf, const int32_t *vf, int64_t n_vf, const int32_t *ee,
                          int64_t n_ee, double delta, long long max_iter, uint8_t *hit, double *toi,
-                         long long *n_enq, const NarrowBuffers &B, hipStream_t s)
+                         long long *n_enq, const NarrowBuffers &B, int pool_blocks, hipStream_t s)
 {
-    counters_zero_kernel<<<1, 64, 0, s>>>(B.counters, 8, B.flags);
+    counters_zero_kernel<<<1, 64, 0, s>>>(B.counters, 16, B.flags);
     const int64_t n = n_vf + n_ee;
     if (n == 0) return;
-    light_kernel<<<(unsigned)((n + kLightBlock - 1) / kLightBlock), kLightBlock, 0, s>>>(
-        V0, V1, nv, E, ne, F, nf, vf, n_vf, ee, n_ee, delta, max_iter, hit, toi, n_enq, B.heavy, B.spill,
-        B.counters, B.flags);
+    prep_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(V0, V1, nv, vf, n_vf, ee, n_ee, E, ne, F, nf, delta,
+                                                           B.ids4, B.eps, B.m, B.flags);
+    int64_t blocks = (n + kPoolSlots - 1) / kPoolSlots;
+    if (blocks > pool_blocks) blocks = pool_blocks;
+    pool_kernel<<<(unsigned)blocks, kPoolSlots, 0, s>>>(V0, V1, B.ids4, B.eps, B.m, n_vf, n, delta, max_iter, hit,
+                                                       toi, n_enq, B.heavy, B.hnodes, B.hnode_cap, B.counters);
 }
 
-void launch_narrow_heavy(const double *V0, const double *V1, const int32_t *E, const int32_t *F,
-                         const int32_t *vf, const int32_t *ee, int64_t n_vf, double delta, long long max_iter,
+void launch_narrow_heavy(const double *V0, const double *V1, int64_t n_vf, double delta, long long max_iter,
                          uint8_t *hit, double *toi, long long *n_enq, const NarrowBuffers &B, int nslots,
                          int64_t cap, int round, hipStream_t s)
 {
@@ -516,8 +799,8 @@ void launch_narrow_heavy(const double *V0, const double *V1, const int32_t *E, c
         next = &B.counters[4];
         rerun_reset_kernel<<<1, 1, 0, s>>>(B.counters, round);
     }
-    heavy_kernel<<<(unsigned)nslots, kHeavyBlock, 0, s>>>(V0, V1, E, F, vf, ee, n_vf, delta, max_iter, hit, toi,
-                                                          n_enq, B.heavy, B.spill, list, count, next, ovf,
+    heavy_kernel<<<(unsigned)nslots, kHeavyBlock, 0, s>>>(V0, V1, B.ids4, B.eps, B.m, n_vf, delta, max_iter, hit,
+                                                          toi, n_enq, B.heavy, B.hnodes, list, count, next, ovf,
                                                           ovf_count, B.scratch, cap, B.flags);
 }
 
