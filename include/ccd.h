@@ -3,9 +3,9 @@
  * detection library: broad phase (sort and sweep over trajectory boxes) and
  * narrow phase (inclusion-based root finding over (t, u, v)) of Belgrod et
  * al., "Time of Impact Dataset for Continuous Collision Detection and a
- * Scalable Conservative Algorithm" (arXiv 2112.06300), Sec. 4.
+ * Scalable Conservative Algorithm" (arXiv 2112.06300), Sec. 5.
  *
- * Problem statement (Sec. 2 and Alg. 1): vertices move linearly from V0
+ * Problem statement (Sec. 3 and Alg. 1): vertices move linearly from V0
  * (t = 0) to V1 (t = 1); the library reports the vertex-face and edge-edge
  * primitive pairs that may touch (broad phase) and, per pair, whether they
  * may collide and a conservative time of impact, plus the earliest one over
@@ -56,7 +56,7 @@ const char *ccd_last_error(void);
 const char *ccd_version(void);
 
 /*
- * Broad phase (Sec. 4.1 box construction, Sec. 4.2 / Alg. 2 sweep).
+ * Broad phase (Sec. 5.1 box construction, Sec. 5.2 / Alg. 2 sweep).
  *
  * Builds, for every vertex, edge and face, the box of its trajectory over
  * t in [0,1] (min and max over its vertices at t=0 and t=1) rounded outward to
@@ -67,7 +67,7 @@ const char *ccd_version(void);
  *   vf: every (v, f) with vertex v not a corner of face f and overlapping boxes;
  *   ee: every (e, g), e < g, of edges without a shared endpoint and with
  *       overlapping boxes.
- * Sec. 4.5: the sweep only compares floats, so this set equals the set an
+ * Sec. 5.5: the sweep only compares floats, so this set equals the set an
  * all-pairs comparison of the same boxes finds.  Pair order is unspecified.
  *
  *   V0, V1   nv x 3 float64 positions at t=0 and t=1
@@ -87,7 +87,7 @@ ccd_status ccd_broad(ccd_context *ctx, const double *V0, const double *V1, int64
                      int32_t *ee, int64_t ee_cap, int64_t *n_ee, void *stream);
 
 /*
- * Narrow phase (Sec. 4.3 / Alg. 3), one conservative answer per pair.
+ * Narrow phase (Sec. 5.3 / Alg. 3), one conservative answer per pair.
  *
  * For each pair, searches (t, u, v) in [0,1]^3 for a root of
  *   vertex-face:  F(t,u,v) = p(t) - a(t) - u (b(t) - a(t)) - v (c(t) - a(t))
@@ -134,8 +134,9 @@ typedef struct {
     double gather_ms;       /* sorted sweep records */
     double sweep_ms;        /* the sweep that emits the pairs */
     double narrow_ms;       /* whole ccd_narrow call, first kernel to last */
-    double narrow_light_ms; /* lane-per-pair stage */
-    double narrow_heavy_ms; /* workgroup-per-pair stage for pairs with wide frontiers (first round) */
+    double narrow_prep_ms;  /* per-pair ids, tolerance box and split levels */
+    double narrow_pool_ms;  /* wave-pool search (64 pairs in flight per wave) */
+    double narrow_heavy_ms; /* workgroup-per-pair search of handed-over pairs (first round) */
     int64_t sort_axis;      /* axis the last broad phase swept along */
     int64_t heavy_pairs;    /* pairs the last narrow phase passed to the wide stage */
     int64_t heavy_reruns;   /* pairs re-run with a larger frontier buffer */

@@ -9,9 +9,9 @@
  * it and shares no code, header, table or helper with it.
  *
  * What it computes (each function names the passage it follows):
- *   - oracle_boxes:   conservative single-precision trajectory boxes (Sec. 4.1).
+ *   - oracle_boxes:   conservative single-precision trajectory boxes (Sec. 5.1).
  *   - oracle_broad:   every vertex-face and edge-edge pair whose boxes overlap,
- *                     by brute force over all pairs.  Sec. 4.5 states that the
+ *                     by brute force over all pairs.  Sec. 5.5 states that the
  *                     sweep's comparisons are exact, so the sweep returns
  *                     exactly this set; brute force is its definition.
  *   - oracle_narrow:  the inclusion-based root finder of Alg. 3, run one pair
@@ -39,7 +39,7 @@
 #define ORACLE_MAX_LEVEL 52
 
 /* ------------------------------------------------------------------------ */
-/* Sec. 4.1: round a double outward to single precision.                     */
+/* Sec. 5.1: round a double outward to single precision.                     */
 /* rd32(x) is the largest float <= x, ru32(x) the smallest float >= x.       */
 /* ------------------------------------------------------------------------ */
 float oracle_rd32(double x)
@@ -101,7 +101,7 @@ static int overlap(const float *loA, const float *hiA, const float *loB, const f
 
 /* ------------------------------------------------------------------------ */
 /* Brute-force broad phase over all vertex-face and edge-edge pairs.         */
-/* Candidate rules (Sec. 3): a vertex is never paired with a face that uses  */
+/* Candidate rules (Sec. 4): a vertex is never paired with a face that uses  */
 /* it, and two edges that share an endpoint are never paired.                */
 /* ------------------------------------------------------------------------ */
 typedef struct {

@@ -41,7 +41,8 @@ class CCDError(RuntimeError):
 class Stats(ctypes.Structure):
     _fields_ = [("broad_ms", ctypes.c_double), ("box_ms", ctypes.c_double), ("sort_ms", ctypes.c_double),
                 ("gather_ms", ctypes.c_double), ("sweep_ms", ctypes.c_double), ("narrow_ms", ctypes.c_double),
-                ("narrow_light_ms", ctypes.c_double), ("narrow_heavy_ms", ctypes.c_double),
+                ("narrow_prep_ms", ctypes.c_double), ("narrow_pool_ms", ctypes.c_double),
+                ("narrow_heavy_ms", ctypes.c_double),
                 ("sort_axis", ctypes.c_int64), ("heavy_pairs", ctypes.c_int64),
                 ("heavy_reruns", ctypes.c_int64)]
 

@@ -275,8 +275,9 @@ ccd_status ccd_narrow(ccd_context *c, const double *V0, const double *V1, int64_
 
     long long *nenq = (long long *)n_enq;
     HIP_TRY(hipEventRecord(c->ev[0], s));
-    launch_narrow_light(V0, V1, nv, E, ne, F, nf, vf, n_vf, ee, n_ee, delta, (long long)max_iter, hit, toi, nenq,
-                        B, c->pool_blocks, s);
+    launch_narrow_prep(V0, V1, nv, E, ne, F, nf, vf, n_vf, ee, n_ee, delta, B, s);
+    HIP_TRY(hipEventRecord(c->ev[4], s));
+    launch_narrow_pool(V0, V1, n_vf, n_ee, delta, (long long)max_iter, hit, toi, nenq, B, c->pool_blocks, s);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(c->ev[2], s));
     launch_narrow_heavy(V0, V1, n_vf, delta, (long long)max_iter, hit, toi, nenq, B, nslots, cap, 0, s);
@@ -289,12 +290,14 @@ ccd_status ccd_narrow(ccd_context *c, const double *V0, const double *V1, int64_
     HIP_TRY(hipMemcpyAsync(h, B.counters, 16 * 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(h + 16, B.flags, 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    float ms = 0.f, ms_light = 0.f, ms_heavy = 0.f;
+    float ms = 0.f, ms_prep = 0.f, ms_pool = 0.f, ms_heavy = 0.f;
     HIP_TRY(hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
-    HIP_TRY(hipEventElapsedTime(&ms_light, c->ev[0], c->ev[2]));
+    HIP_TRY(hipEventElapsedTime(&ms_prep, c->ev[0], c->ev[4]));
+    HIP_TRY(hipEventElapsedTime(&ms_pool, c->ev[4], c->ev[2]));
     HIP_TRY(hipEventElapsedTime(&ms_heavy, c->ev[2], c->ev[3]));
     c->stats.narrow_ms = ms;
-    c->stats.narrow_light_ms = ms_light;
+    c->stats.narrow_prep_ms = ms_prep;
+    c->stats.narrow_pool_ms = ms_pool;
     c->stats.narrow_heavy_ms = ms_heavy;
     c->stats.heavy_pairs = h[0];
     c->stats.heavy_reruns = 0;

@@ -1,5 +1,5 @@
 // broad.hip -- broad phase on gfx950: trajectory boxes, sweep-axis choice,
-// LSD radix sort and the sort-and-sweep pair emission (Sec. 4.1, 4.2, Alg. 2).
+// LSD radix sort and the sort-and-sweep pair emission (Sec. 5.1, 5.2, Alg. 2).
 //
 // Layout in HBM.  Boxes are built once in primitive order as structure of
 // arrays (lo_x, lo_y, lo_z, hi_x, hi_y, hi_z, float32), segments

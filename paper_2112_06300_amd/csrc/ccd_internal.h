@@ -8,7 +8,7 @@
 namespace ccd {
 
 // ---------------------------------------------------------------------------
-// Conservative float32 rounding of trajectory box bounds (Sec. 4.1): lo is the
+// Conservative float32 rounding of trajectory box bounds (Sec. 5.1): lo is the
 // largest float <= x, hi the smallest float >= x.  Round to nearest, then step
 // one float outward when the rounding went the wrong way.  The result has no
 // negative zero, so that float order and the order of the uint32 sort keys
@@ -130,11 +130,15 @@ struct NarrowBuffers {
 // Resident 64-lane pool workgroups per CU.
 int pool_blocks_per_cu();
 
-void launch_narrow_light(const double *V0, const double *V1, int64_t nv, const int32_t *E, int64_t ne,
-                         const int32_t *F, int64_t nf, const int32_t *vf, int64_t n_vf,
-                         const int32_t *ee, int64_t n_ee, double delta, long long max_iter,
-                         uint8_t *hit, double *toi, long long *n_enq, const NarrowBuffers &B,
-                         int pool_blocks, hipStream_t s);
+// prep: counters, per-pair ids, C_eps and split levels.
+void launch_narrow_prep(const double *V0, const double *V1, int64_t nv, const int32_t *E, int64_t ne,
+                        const int32_t *F, int64_t nf, const int32_t *vf, int64_t n_vf, const int32_t *ee,
+                        int64_t n_ee, double delta, const NarrowBuffers &B, hipStream_t s);
+
+// pool: the wave-pool search of every pair (hands wide / deep pairs over).
+void launch_narrow_pool(const double *V0, const double *V1, int64_t n_vf, int64_t n_ee, double delta,
+                        long long max_iter, uint8_t *hit, double *toi, long long *n_enq, const NarrowBuffers &B,
+                        int pool_blocks, hipStream_t s);
 
 // Wide stage: `nslots` workgroups, each with a frontier buffer of `cap` nodes
 // (two buffers of 3 x cap uint64).  Round 0 works on every handed-over pair;

@@ -1,5 +1,5 @@
 // narrow.hip -- narrow phase on gfx950: inclusion-based root finding over
-// (t, u, v) with breadth-first bisection (Sec. 4.3, Alg. 3).
+// (t, u, v) with breadth-first bisection (Sec. 5.3, Alg. 3).
 //
 // Per pair the search is level-synchronous: all intervals of one level share
 // the same dyadic levels (l_t, l_u, l_v), so an interval is three integer
@@ -766,16 +766,23 @@ int pool_blocks_per_cu()
     return b;
 }
 
-void launch_narrow_light(const double *V0, const double *V1, int64_t nv, const int32_t *E, int64_t ne,
-                         const int32_t *F, int64_t nf, const int32_t *vf, int64_t n_vf, const int32_t *ee,
-                         int64_t n_ee, double delta, long long max_iter, uint8_t *hit, double *toi,
-                         long long *n_enq, const NarrowBuffers &B, int pool_blocks, hipStream_t s)
+void launch_narrow_prep(const double *V0, const double *V1, int64_t nv, const int32_t *E, int64_t ne,
+                        const int32_t *F, int64_t nf, const int32_t *vf, int64_t n_vf, const int32_t *ee,
+                        int64_t n_ee, double delta, const NarrowBuffers &B, hipStream_t s)
 {
     counters_zero_kernel<<<1, 64, 0, s>>>(B.counters, 16, B.flags);
     const int64_t n = n_vf + n_ee;
     if (n == 0) return;
     prep_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(V0, V1, nv, vf, n_vf, ee, n_ee, E, ne, F, nf, delta,
                                                            B.ids4, B.eps, B.m, B.flags);
+}
+
+void launch_narrow_pool(const double *V0, const double *V1, int64_t n_vf, int64_t n_ee, double delta,
+                        long long max_iter, uint8_t *hit, double *toi, long long *n_enq, const NarrowBuffers &B,
+                        int pool_blocks, hipStream_t s)
+{
+    const int64_t n = n_vf + n_ee;
+    if (n == 0) return;
     int64_t blocks = (n + kPoolSlots - 1) / kPoolSlots;
     if (blocks > pool_blocks) blocks = pool_blocks;
     pool_kernel<<<(unsigned)blocks, kPoolSlots, 0, s>>>(V0, V1, B.ids4, B.eps, B.m, n_vf, n, delta, max_iter, hit,

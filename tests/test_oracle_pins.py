@@ -22,7 +22,7 @@ GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 
 # --------------------------------------------------------------------------- #
-# Box rounding (Sec. 4.1): lo = largest float <= x, hi = smallest float >= x.  #
+# Box rounding (Sec. 5.1): lo = largest float <= x, hi = smallest float >= x.  #
 # --------------------------------------------------------------------------- #
 def _special_doubles(rng, n):
     parts = [
