@@ -124,6 +124,66 @@ ccd_status ccd_narrow(ccd_context *ctx, const double *V0, const double *V1, int6
                       uint8_t *hit, double *toi, double *toi_min, int64_t *n_enq, void *stream);
 
 /*
+ * Learned schedule (not part of the paper's method): a small MLP predicts each
+ * pair's search cost, log2(1 + intervals enqueued), from CCD_NUM_FEATURES
+ * geometric features; the narrow phase then takes pairs in decreasing
+ * predicted cost, which balances the load across the GPU.  The schedule only
+ * changes the order in which pairs are searched: hit, toi, toi_min and n_enq
+ * are identical to the plain schedule's.
+ *
+ * Model parameters are CCD_MODEL_PARAMS float32 values, contiguous:
+ *   W1[16][64], b1[64], W2[64][64], b2[64], W3[64], b3
+ * and the feature normalization is 2 * CCD_NUM_FEATURES float32 values:
+ * mean[16] then 1 / std[16].  The network is evaluated with bf16 weights and
+ * activations on the matrix cores and float32 accumulation:
+ *   y = W3 . relu(W2^T relu(W1^T x + b1) + b2) + b3.
+ */
+#define CCD_NUM_FEATURES 16
+#define CCD_MODEL_PARAMS 5313
+
+enum { CCD_SCHED_PLAIN = 0, CCD_SCHED_LEARNED = 1, CCD_SCHED_ORDER = 2 };
+
+typedef struct {
+    int kind;              /* CCD_SCHED_PLAIN, CCD_SCHED_LEARNED or CCD_SCHED_ORDER */
+    const float *params;   /* LEARNED: device, CCD_MODEL_PARAMS floats */
+    const float *norm;     /* LEARNED: device, 2 * CCD_NUM_FEATURES floats */
+    const int32_t *order;  /* ORDER: device permutation of [0, n_vf + n_ee): search order */
+} ccd_schedule;
+
+/* ccd_narrow with a schedule (NULL = plain: pairs in index order).  Same
+ * arguments, outputs and errors as ccd_narrow; the LEARNED time includes the
+ * features, the network and the ordering. */
+ccd_status ccd_narrow_sched(ccd_context *ctx, const double *V0, const double *V1, int64_t nv,
+                            const int32_t *E, int64_t ne, const int32_t *F, int64_t nf,
+                            const int32_t *vf, int64_t n_vf, const int32_t *ee, int64_t n_ee,
+                            double delta, int64_t max_iter,
+                            uint8_t *hit, double *toi, double *toi_min, int64_t *n_enq,
+                            const ccd_schedule *sched, void *stream);
+
+/* Scheduling features of every pair: feat is a DEVICE (n_vf + n_ee) x
+ * CCD_NUM_FEATURES float32 array, VF pairs first (zeros for a pair with an
+ * index out of range, which also makes the call fail with INVALID_ARG). */
+ccd_status ccd_features(ccd_context *ctx, const double *V0, const double *V1, int64_t nv,
+                        const int32_t *E, int64_t ne, const int32_t *F, int64_t nf,
+                        const int32_t *vf, int64_t n_vf, const int32_t *ee, int64_t n_ee,
+                        double delta, float *feat, void *stream);
+
+/* Predicted cost of n pairs (DEVICE arrays: feat n x 16, out n). */
+ccd_status ccd_mlp_predict(ccd_context *ctx, const float *params, const float *norm, const float *feat,
+                           int64_t n, float *out, void *stream);
+
+/* Gradient of the mean squared error of the predictions against label (DEVICE
+ * arrays) with respect to params: grad (DEVICE, CCD_MODEL_PARAMS) is
+ * overwritten; *loss_sse (DEVICE, 1 float) receives the sum of squared errors. */
+ccd_status ccd_mlp_grad(ccd_context *ctx, const float *params, const float *norm, const float *feat,
+                        const float *label, int64_t n, float *grad, float *loss_sse, void *stream);
+
+/* One Adam step on params (DEVICE) with moment buffers m, v (DEVICE,
+ * CCD_MODEL_PARAMS each, zero before the first step); step counts from 1. */
+ccd_status ccd_adam_step(ccd_context *ctx, float *params, const float *grad, float *m, float *v,
+                         int64_t step, float lr, float beta1, float beta2, float eps, void *stream);
+
+/*
  * Phase timings of the last ccd_broad / ccd_narrow call on this context, in
  * milliseconds (GPU events on the call's stream), and work counters.
  */
@@ -135,6 +195,7 @@ typedef struct {
     double sweep_ms;        /* the sweep that emits the pairs */
     double narrow_ms;       /* whole ccd_narrow call, first kernel to last */
     double narrow_prep_ms;  /* per-pair ids, tolerance box and split levels */
+    double narrow_sched_ms; /* learned schedule: features, network and ordering (0 when plain) */
     double narrow_pool_ms;  /* wave-pool search (64 pairs in flight per wave) */
     double narrow_heavy_ms; /* workgroup-per-pair search of handed-over pairs (first round) */
     int64_t sort_axis;      /* axis the last broad phase swept along */

@@ -29,7 +29,13 @@ _STATUS_NAMES = {
 
 # Every symbol include/ccd.h declares.
 EXPORTED = ["ccd_create", "ccd_destroy", "ccd_last_error", "ccd_version", "ccd_broad", "ccd_narrow",
+            "ccd_narrow_sched", "ccd_features", "ccd_mlp_predict", "ccd_mlp_grad", "ccd_adam_step",
             "ccd_get_stats"]
+
+NUM_FEATURES = 16
+HIDDEN = 64
+MODEL_PARAMS = NUM_FEATURES * HIDDEN + HIDDEN + HIDDEN * HIDDEN + HIDDEN + HIDDEN + 1
+SCHED_PLAIN, SCHED_LEARNED, SCHED_ORDER = 0, 1, 2
 
 
 class CCDError(RuntimeError):
@@ -41,10 +47,16 @@ class CCDError(RuntimeError):
 class Stats(ctypes.Structure):
     _fields_ = [("broad_ms", ctypes.c_double), ("box_ms", ctypes.c_double), ("sort_ms", ctypes.c_double),
                 ("gather_ms", ctypes.c_double), ("sweep_ms", ctypes.c_double), ("narrow_ms", ctypes.c_double),
-                ("narrow_prep_ms", ctypes.c_double), ("narrow_pool_ms", ctypes.c_double),
+                ("narrow_prep_ms", ctypes.c_double), ("narrow_sched_ms", ctypes.c_double),
+                ("narrow_pool_ms", ctypes.c_double),
                 ("narrow_heavy_ms", ctypes.c_double),
                 ("sort_axis", ctypes.c_int64), ("heavy_pairs", ctypes.c_int64),
                 ("heavy_reruns", ctypes.c_int64)]
+
+
+class Schedule(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("params", ctypes.c_void_p), ("norm", ctypes.c_void_p),
+                ("order", ctypes.c_void_p)]
 
 
 _lib = None
@@ -75,6 +87,18 @@ def load_library(path=LIB_PATH):
     lib.ccd_narrow.argtypes = [P, P, P, i64, P, i64, P, i64, P, i64, P, i64, ctypes.c_double, i64,
                                P, P, P, P, P]
     lib.ccd_narrow.restype = ctypes.c_int
+    lib.ccd_narrow_sched.argtypes = [P, P, P, i64, P, i64, P, i64, P, i64, P, i64, ctypes.c_double, i64,
+                                     P, P, P, P, ctypes.POINTER(Schedule), P]
+    lib.ccd_narrow_sched.restype = ctypes.c_int
+    lib.ccd_features.argtypes = [P, P, P, i64, P, i64, P, i64, P, i64, P, i64, ctypes.c_double, P, P]
+    lib.ccd_features.restype = ctypes.c_int
+    lib.ccd_mlp_predict.argtypes = [P, P, P, P, i64, P, P]
+    lib.ccd_mlp_predict.restype = ctypes.c_int
+    lib.ccd_mlp_grad.argtypes = [P, P, P, P, P, i64, P, P, P]
+    lib.ccd_mlp_grad.restype = ctypes.c_int
+    f32 = ctypes.c_float
+    lib.ccd_adam_step.argtypes = [P, P, P, P, P, i64, f32, f32, f32, f32, P]
+    lib.ccd_adam_step.restype = ctypes.c_int
     lib.ccd_get_stats.argtypes = [P, ctypes.POINTER(Stats)]
     lib.ccd_get_stats.restype = ctypes.c_int
     _lib = lib
@@ -172,8 +196,12 @@ class Context:
         _check(st)
         return n_vf.value, n_ee.value
 
-    def narrow(self, V0, V1, E, F, vf, ee, delta=1e-6, max_iter=10**6, with_costs=False, out=None, stream=None):
-        """Per-pair (hit uint8, toi float64, toi_min (1,) float64, n_enq int64 or None), VF pairs first."""
+    def narrow(self, V0, V1, E, F, vf, ee, delta=1e-6, max_iter=10**6, with_costs=False, out=None, stream=None,
+               schedule=None):
+        """Per-pair (hit uint8, toi float64, toi_min (1,) float64, n_enq int64 or None), VF pairs first.
+
+        schedule: None (plain: pairs in index order), ("learned", params, norm) or ("order", perm) --
+        the order in which pairs are searched; the results are the same for every schedule."""
         import torch
         lib = load_library()
         V0 = _dev(V0, torch.float64, 3)
@@ -190,10 +218,105 @@ class Context:
             nenq = torch.empty(n, dtype=torch.int64, device=V0.device) if with_costs else None
         else:
             hit, toi, tmin, nenq = out
-        _check(lib.ccd_narrow(self._h, _ptr(V0), _ptr(V1), V0.shape[0], _ptr(E), E.shape[0], _ptr(F), F.shape[0],
-                              _ptr(vf), vf.shape[0], _ptr(ee), ee.shape[0], float(delta), int(max_iter),
-                              _ptr(hit), _ptr(toi), _ptr(tmin), _ptr(nenq), _stream(stream)))
+        if schedule is None:
+            _check(lib.ccd_narrow(self._h, _ptr(V0), _ptr(V1), V0.shape[0], _ptr(E), E.shape[0], _ptr(F),
+                                  F.shape[0], _ptr(vf), vf.shape[0], _ptr(ee), ee.shape[0], float(delta),
+                                  int(max_iter), _ptr(hit), _ptr(toi), _ptr(tmin), _ptr(nenq), _stream(stream)))
+            return hit, toi, tmin, nenq
+        sch, keep = _schedule(schedule)
+        _check(lib.ccd_narrow_sched(self._h, _ptr(V0), _ptr(V1), V0.shape[0], _ptr(E), E.shape[0], _ptr(F),
+                                    F.shape[0], _ptr(vf), vf.shape[0], _ptr(ee), ee.shape[0], float(delta),
+                                    int(max_iter), _ptr(hit), _ptr(toi), _ptr(tmin), _ptr(nenq),
+                                    ctypes.byref(sch), _stream(stream)))
+        del keep
         return hit, toi, tmin, nenq
+
+    def features(self, V0, V1, E, F, vf, ee, delta=1e-6, stream=None):
+        """Scheduling features, (n_vf + n_ee) x 16 float32 on the device, VF pairs first."""
+        import torch
+        lib = load_library()
+        V0 = _dev(V0, torch.float64, 3)
+        V1 = _dev(V1, torch.float64, 3)
+        E = _dev(E, torch.int32, 2)
+        F = _dev(F, torch.int32, 3)
+        vf = _dev(vf, torch.int32, 2)
+        ee = _dev(ee, torch.int32, 2)
+        n = vf.shape[0] + ee.shape[0]
+        feat = torch.empty((n, NUM_FEATURES), dtype=torch.float32, device=V0.device)
+        _check(lib.ccd_features(self._h, _ptr(V0), _ptr(V1), V0.shape[0], _ptr(E), E.shape[0], _ptr(F), F.shape[0],
+                                _ptr(vf), vf.shape[0], _ptr(ee), ee.shape[0], float(delta), _ptr(feat),
+                                _stream(stream)))
+        return feat
+
+    def mlp_predict(self, params, norm, feat, out=None, stream=None):
+        """Predicted log2(1 + n_enq) of every row of feat (float32 on the device)."""
+        import torch
+        lib = load_library()
+        params, norm, feat = _f32(params, MODEL_PARAMS), _f32(norm, 2 * NUM_FEATURES), _dev(feat, torch.float32,
+                                                                                          NUM_FEATURES)
+        n = feat.shape[0]
+        if out is None:
+            out = torch.empty(n, dtype=torch.float32, device=feat.device)
+        _check(lib.ccd_mlp_predict(self._h, _ptr(params), _ptr(norm), _ptr(feat), n, _ptr(out), _stream(stream)))
+        return out
+
+    def mlp_grad(self, params, norm, feat, label, grad=None, loss=None, stream=None):
+        """(gradient of the mean squared error w.r.t. params, sum of squared errors (1,)), on the device."""
+        import torch
+        lib = load_library()
+        params, norm = _f32(params, MODEL_PARAMS), _f32(norm, 2 * NUM_FEATURES)
+        feat = _dev(feat, torch.float32, NUM_FEATURES)
+        label = _dev(label, torch.float32, 1).reshape(-1)
+        n = feat.shape[0]
+        if label.shape[0] != n:
+            raise ValueError("label and feat have different lengths")
+        if grad is None:
+            grad = torch.empty(MODEL_PARAMS, dtype=torch.float32, device=feat.device)
+        if loss is None:
+            loss = torch.empty(1, dtype=torch.float32, device=feat.device)
+        _check(lib.ccd_mlp_grad(self._h, _ptr(params), _ptr(norm), _ptr(feat), _ptr(label), n, _ptr(grad),
+                                _ptr(loss), _stream(stream)))
+        return grad, loss
+
+    def adam_step(self, params, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        """One in-place Adam step on params (device float32, MODEL_PARAMS values)."""
+        for t in (params, grad, m, v):
+            _require_f32(t, MODEL_PARAMS)
+        _check(load_library().ccd_adam_step(self._h, _ptr(params), _ptr(grad), _ptr(m), _ptr(v), int(step),
+                                            float(lr), float(beta1), float(beta2), float(eps), _stream(stream)))
+
+
+def _f32(t, size):
+    import torch
+    t = torch.as_tensor(t)
+    if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+        t = t.to(device="cuda", dtype=torch.float32).contiguous()
+    t = t.reshape(-1)
+    if t.numel() != size:
+        raise ValueError(f"expected {size} float32 values, got {t.numel()}")
+    return t
+
+
+def _require_f32(t, size):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.dtype == torch.float32 and t.is_cuda and t.is_contiguous()
+            and t.numel() == size):
+        raise ValueError(f"expected a contiguous CUDA float32 tensor of {size} values")
+
+
+def _schedule(schedule):
+    """ctypes Schedule for ("learned", params, norm) or ("order", perm); also the tensors it points into."""
+    import torch
+    kind = schedule[0]
+    if kind == "plain":
+        return Schedule(SCHED_PLAIN, None, None, None), ()
+    if kind == "learned":
+        params, norm = _f32(schedule[1], MODEL_PARAMS), _f32(schedule[2], 2 * NUM_FEATURES)
+        return Schedule(SCHED_LEARNED, params.data_ptr(), norm.data_ptr(), None), (params, norm)
+    if kind == "order":
+        perm = _dev(schedule[1], torch.int32, 1).reshape(-1)
+        return Schedule(SCHED_ORDER, None, None, perm.data_ptr() if perm.numel() else None), (perm,)
+    raise ValueError(f"unknown schedule {kind!r}")
 
 
 def version():

@@ -10,7 +10,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["broad.hip", "narrow.hip", "api.hip"]
+SOURCES = ["broad.hip", "narrow.hip", "learned.hip", "api.hip"]
 LIB = os.path.join(HERE, "libccd.so")
 
 FLAGS = [

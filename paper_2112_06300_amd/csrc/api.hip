@@ -66,7 +66,7 @@ size_t aligned_total(std::initializer_list<size_t> sizes)
 
 struct ccd_context {
     int device = 0;
-    Pool broad, narrow, scratch;
+    Pool broad, narrow, scratch, sched;
     void *host = nullptr;  // pinned host staging for counters and flags
     hipEvent_t ev[8] = {};
     ccd_stats stats{};
@@ -139,7 +139,7 @@ void ccd_destroy(ccd_context *c)
 {
     if (!c) return;
     hipSetDevice(c->device);
-    for (Pool *p : {&c->broad, &c->narrow, &c->scratch})
+    for (Pool *p : {&c->broad, &c->narrow, &c->scratch, &c->sched})
         if (p->base) hipFree(p->base);
     for (auto &e : c->ev)
         if (e) hipEventDestroy(e);
@@ -231,21 +231,23 @@ ccd_status ccd_broad(ccd_context *c, const double *V0, const double *V1, int64_t
     return CCD_OK;
 }
 
-ccd_status ccd_narrow(ccd_context *c, const double *V0, const double *V1, int64_t nv, const int32_t *E, int64_t ne,
-                      const int32_t *F, int64_t nf, const int32_t *vf, int64_t n_vf, const int32_t *ee,
-                      int64_t n_ee, double delta, int64_t max_iter, uint8_t *hit, double *toi, double *toi_min,
-                      int64_t *n_enq, void *stream)
+}  // extern "C"
+
+namespace {
+
+// Validates the common narrow-phase arguments and carves the narrow workspace.
+ccd_status narrow_setup(ccd_context *c, const double *V0, const double *V1, int64_t nv, const int32_t *E, int64_t ne,
+                        const int32_t *F, int64_t nf, const int32_t *vf, int64_t n_vf, const int32_t *ee,
+                        int64_t n_ee, double delta, NarrowBuffers &B)
 {
-    if (!c || !toi_min) return fail(CCD_ERR_INVALID_ARG, "NULL context or toi_min");
+    if (!c) return fail(CCD_ERR_INVALID_ARG, "NULL context");
     if (nv < 0 || ne < 0 || nf < 0 || n_vf < 0 || n_ee < 0) return fail(CCD_ERR_INVALID_ARG, "negative size");
     if (!(delta > 0.0) || !std::isfinite(delta)) return fail(CCD_ERR_INVALID_ARG, "delta must be finite and > 0");
-    if (max_iter < 1) return fail(CCD_ERR_INVALID_ARG, "max_iter must be >= 1");
     const int64_t n = n_vf + n_ee;
     if (n > INT32_MAX) return fail(CCD_ERR_INVALID_ARG, "too many pairs for one call");
-    if ((nv && (!V0 || !V1)) || (ne && !E) || (nf && !F) || (n_vf && !vf) || (n_ee && !ee) || (n && (!hit || !toi)))
+    if ((nv && (!V0 || !V1)) || (ne && !E) || (nf && !F) || (n_vf && !vf) || (n_ee && !ee))
         return fail(CCD_ERR_INVALID_ARG, "NULL pointer with nonzero size");
     HIP_TRY(hipSetDevice(c->device));
-    hipStream_t s = (hipStream_t)stream;
     const size_t m = (size_t)std::max<int64_t>(n, 1);
     const int64_t hnode_cap = 4 * (int64_t)m + 65536;
     const size_t need = aligned_total({m * 16, m * 24, m * 4, m * sizeof(HeavyEntry), (size_t)hnode_cap * 8, 16 * 4,
@@ -253,7 +255,6 @@ ccd_status ccd_narrow(ccd_context *c, const double *V0, const double *V1, int64_
     ccd_status st = ensure(c->narrow, need);
     if (st != CCD_OK) return st;
     Carver cv(c->narrow.base);
-    NarrowBuffers B;
     B.ids4 = cv.take<int4>(m);
     B.eps = cv.take<double>(3 * m);
     B.m = cv.take<uint32_t>(m);
@@ -264,7 +265,72 @@ ccd_status ccd_narrow(ccd_context *c, const double *V0, const double *V1, int64_
     B.overflow_list[0] = cv.take<int32_t>(m);
     B.overflow_list[1] = cv.take<int32_t>(m);
     B.flags = cv.take<uint32_t>(1);
+    B.toi_min = nullptr;
+    B.scratch = nullptr;
+    return CCD_OK;
+}
+
+// Scheduling workspace: features, predicted cost, order, a permutation bitmap
+// and the counting-sort bins.
+struct SchedBuffers {
+    float *feat, *cost;
+    int32_t *order;
+    uint32_t *bits, *bins, *flag;
+};
+
+ccd_status sched_setup(ccd_context *c, int64_t n, SchedBuffers &S)
+{
+    const size_t m = (size_t)std::max<int64_t>(n, 1);
+    const size_t words = (m + 31) / 32;
+    ccd_status st = ensure(c->sched, aligned_total({m * kNumFeatures * 4, m * 4, m * 4, words * 4, 3 * 256 * 4, 4}));
+    if (st != CCD_OK) return st;
+    Carver cv(c->sched.base);
+    S.feat = cv.take<float>(m * kNumFeatures);
+    S.cost = cv.take<float>(m);
+    S.order = cv.take<int32_t>(m);
+    S.bits = cv.take<uint32_t>(words);
+    S.bins = cv.take<uint32_t>(3 * 256);
+    S.flag = cv.take<uint32_t>(1);
+    return CCD_OK;
+}
+
+ccd_status narrow_impl(ccd_context *c, const double *V0, const double *V1, int64_t nv, const int32_t *E, int64_t ne,
+                       const int32_t *F, int64_t nf, const int32_t *vf, int64_t n_vf, const int32_t *ee,
+                       int64_t n_ee, double delta, int64_t max_iter, uint8_t *hit, double *toi, double *toi_min,
+                       int64_t *n_enq, const ccd_schedule *sched, void *stream)
+{
+    if (!c || !toi_min) return fail(CCD_ERR_INVALID_ARG, "NULL context or toi_min");
+    if (max_iter < 1) return fail(CCD_ERR_INVALID_ARG, "max_iter must be >= 1");
+    const int64_t n = n_vf + n_ee;
+    if (n > 0 && (!hit || !toi)) return fail(CCD_ERR_INVALID_ARG, "NULL pointer with nonzero size");
+    const int kind = sched ? sched->kind : CCD_SCHED_PLAIN;
+    if (kind != CCD_SCHED_PLAIN && kind != CCD_SCHED_LEARNED && kind != CCD_SCHED_ORDER)
+        return fail(CCD_ERR_INVALID_ARG, "unknown schedule kind %d", kind);
+    if (kind == CCD_SCHED_LEARNED && (!sched->params || !sched->norm))
+        return fail(CCD_ERR_INVALID_ARG, "learned schedule without parameters or normalization");
+    if (kind == CCD_SCHED_ORDER && n > 0 && !sched->order)
+        return fail(CCD_ERR_INVALID_ARG, "order schedule without an order");
+    NarrowBuffers B;
+    ccd_status st = narrow_setup(c, V0, V1, nv, E, ne, F, nf, vf, n_vf, ee, n_ee, delta, B);
+    if (st != CCD_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
     B.toi_min = toi_min;
+    SchedBuffers S{};
+    if (kind != CCD_SCHED_PLAIN) {
+        st = sched_setup(c, n, S);
+        if (st != CCD_OK) return st;
+    }
+    const int32_t *order = nullptr;
+    if (kind == CCD_SCHED_ORDER && n > 0) {
+        // a caller's order must be a permutation: checked before any pair is searched
+        unsigned int *h = (unsigned int *)c->host;
+        launch_check_permutation(sched->order, n, S.bits, S.flag, s);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(h, S.flag, 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (h[0]) return fail(CCD_ERR_INVALID_ARG, "order is not a permutation of [0, %lld)", (long long)n);
+        order = sched->order;
+    }
 
     // wide-stage frontier buffers: start with 1024 workgroups x 8192 nodes
     int nslots = 1024;
@@ -277,7 +343,14 @@ ccd_status ccd_narrow(ccd_context *c, const double *V0, const double *V1, int64_
     HIP_TRY(hipEventRecord(c->ev[0], s));
     launch_narrow_prep(V0, V1, nv, E, ne, F, nf, vf, n_vf, ee, n_ee, delta, B, s);
     HIP_TRY(hipEventRecord(c->ev[4], s));
-    launch_narrow_pool(V0, V1, n_vf, n_ee, delta, (long long)max_iter, hit, toi, nenq, B, c->pool_blocks, s);
+    if (kind == CCD_SCHED_LEARNED) {
+        launch_narrow_features(V0, V1, n_vf, n_ee, delta, B, S.feat, s);
+        launch_mlp_predict(sched->params, sched->norm, S.feat, n, S.cost, s);
+        launch_cost_order(S.cost, n, S.order, S.bins, s);
+        order = S.order;
+    }
+    HIP_TRY(hipEventRecord(c->ev[5], s));
+    launch_narrow_pool(V0, V1, n_vf, n_ee, delta, (long long)max_iter, hit, toi, nenq, B, c->pool_blocks, order, s);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(c->ev[2], s));
     launch_narrow_heavy(V0, V1, n_vf, delta, (long long)max_iter, hit, toi, nenq, B, nslots, cap, 0, s);
@@ -290,13 +363,15 @@ ccd_status ccd_narrow(ccd_context *c, const double *V0, const double *V1, int64_
     HIP_TRY(hipMemcpyAsync(h, B.counters, 16 * 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(h + 16, B.flags, 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    float ms = 0.f, ms_prep = 0.f, ms_pool = 0.f, ms_heavy = 0.f;
+    float ms = 0.f, ms_prep = 0.f, ms_sched = 0.f, ms_pool = 0.f, ms_heavy = 0.f;
     HIP_TRY(hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
     HIP_TRY(hipEventElapsedTime(&ms_prep, c->ev[0], c->ev[4]));
-    HIP_TRY(hipEventElapsedTime(&ms_pool, c->ev[4], c->ev[2]));
+    HIP_TRY(hipEventElapsedTime(&ms_sched, c->ev[4], c->ev[5]));
+    HIP_TRY(hipEventElapsedTime(&ms_pool, c->ev[5], c->ev[2]));
     HIP_TRY(hipEventElapsedTime(&ms_heavy, c->ev[2], c->ev[3]));
     c->stats.narrow_ms = ms;
     c->stats.narrow_prep_ms = ms_prep;
+    c->stats.narrow_sched_ms = kind == CCD_SCHED_LEARNED ? ms_sched : 0.0;
     c->stats.narrow_pool_ms = ms_pool;
     c->stats.narrow_heavy_ms = ms_heavy;
     c->stats.heavy_pairs = h[0];
@@ -334,6 +409,101 @@ ccd_status ccd_narrow(ccd_context *c, const double *V0, const double *V1, int64_
         c->stats.narrow_heavy_ms += ms;
         overflowed = h[2 + (round & 1)];
     }
+    g_err.clear();
+    return CCD_OK;
+}
+
+// Device arrays of the learned model must not alias in ways the kernels do not
+// expect; sizes are the only thing checked here.
+ccd_status check_mlp_args(ccd_context *c, const float *params, const float *norm, const float *feat, int64_t n)
+{
+    if (!c) return fail(CCD_ERR_INVALID_ARG, "NULL context");
+    if (n < 0) return fail(CCD_ERR_INVALID_ARG, "negative size");
+    if (n > INT32_MAX) return fail(CCD_ERR_INVALID_ARG, "too many rows for one call");
+    if (!params || !norm || (n && !feat)) return fail(CCD_ERR_INVALID_ARG, "NULL pointer");
+    HIP_TRY(hipSetDevice(c->device));
+    return CCD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ccd_status ccd_narrow(ccd_context *c, const double *V0, const double *V1, int64_t nv, const int32_t *E, int64_t ne,
+                      const int32_t *F, int64_t nf, const int32_t *vf, int64_t n_vf, const int32_t *ee,
+                      int64_t n_ee, double delta, int64_t max_iter, uint8_t *hit, double *toi, double *toi_min,
+                      int64_t *n_enq, void *stream)
+{
+    return narrow_impl(c, V0, V1, nv, E, ne, F, nf, vf, n_vf, ee, n_ee, delta, max_iter, hit, toi, toi_min, n_enq,
+                       nullptr, stream);
+}
+
+ccd_status ccd_narrow_sched(ccd_context *c, const double *V0, const double *V1, int64_t nv, const int32_t *E,
+                            int64_t ne, const int32_t *F, int64_t nf, const int32_t *vf, int64_t n_vf,
+                            const int32_t *ee, int64_t n_ee, double delta, int64_t max_iter, uint8_t *hit,
+                            double *toi, double *toi_min, int64_t *n_enq, const ccd_schedule *sched, void *stream)
+{
+    return narrow_impl(c, V0, V1, nv, E, ne, F, nf, vf, n_vf, ee, n_ee, delta, max_iter, hit, toi, toi_min, n_enq,
+                       sched, stream);
+}
+
+ccd_status ccd_features(ccd_context *c, const double *V0, const double *V1, int64_t nv, const int32_t *E, int64_t ne,
+                        const int32_t *F, int64_t nf, const int32_t *vf, int64_t n_vf, const int32_t *ee,
+                        int64_t n_ee, double delta, float *feat, void *stream)
+{
+    NarrowBuffers B;
+    ccd_status st = narrow_setup(c, V0, V1, nv, E, ne, F, nf, vf, n_vf, ee, n_ee, delta, B);
+    if (st != CCD_OK) return st;
+    const int64_t n = n_vf + n_ee;
+    if (n > 0 && !feat) return fail(CCD_ERR_INVALID_ARG, "NULL feat with nonzero size");
+    hipStream_t s = (hipStream_t)stream;
+    launch_narrow_prep(V0, V1, nv, E, ne, F, nf, vf, n_vf, ee, n_ee, delta, B, s);
+    launch_narrow_features(V0, V1, n_vf, n_ee, delta, B, feat, s);
+    HIP_TRY(hipGetLastError());
+    unsigned int *h = (unsigned int *)c->host;
+    HIP_TRY(hipMemcpyAsync(h, B.flags, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (h[0] & FLAG_BAD_INDEX) return fail(CCD_ERR_INVALID_ARG, "pair, edge or face index out of range");
+    if (h[0] & FLAG_NONFINITE) return fail(CCD_ERR_NONFINITE, "non-finite or too large (> 2^960) coordinate");
+    g_err.clear();
+    return CCD_OK;
+}
+
+ccd_status ccd_mlp_predict(ccd_context *c, const float *params, const float *norm, const float *feat, int64_t n,
+                           float *out, void *stream)
+{
+    ccd_status st = check_mlp_args(c, params, norm, feat, n);
+    if (st != CCD_OK) return st;
+    if (n && !out) return fail(CCD_ERR_INVALID_ARG, "NULL out");
+    launch_mlp_predict(params, norm, feat, n, out, (hipStream_t)stream);
+    HIP_TRY(hipGetLastError());
+    g_err.clear();
+    return CCD_OK;
+}
+
+ccd_status ccd_mlp_grad(ccd_context *c, const float *params, const float *norm, const float *feat, const float *label,
+                        int64_t n, float *grad, float *loss_sse, void *stream)
+{
+    ccd_status st = check_mlp_args(c, params, norm, feat, n);
+    if (st != CCD_OK) return st;
+    if (!grad || !loss_sse || (n && !label)) return fail(CCD_ERR_INVALID_ARG, "NULL pointer");
+    launch_mlp_grad(params, norm, feat, label, n, grad, loss_sse, (hipStream_t)stream);
+    HIP_TRY(hipGetLastError());
+    g_err.clear();
+    return CCD_OK;
+}
+
+ccd_status ccd_adam_step(ccd_context *c, float *params, const float *grad, float *m, float *v, int64_t step, float lr,
+                         float beta1, float beta2, float eps, void *stream)
+{
+    if (!c) return fail(CCD_ERR_INVALID_ARG, "NULL context");
+    if (!params || !grad || !m || !v) return fail(CCD_ERR_INVALID_ARG, "NULL pointer");
+    if (step < 1) return fail(CCD_ERR_INVALID_ARG, "step counts from 1");
+    if (!(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f) || !std::isfinite(lr))
+        return fail(CCD_ERR_INVALID_ARG, "invalid Adam hyper-parameters");
+    HIP_TRY(hipSetDevice(c->device));
+    launch_adam(params, grad, m, v, step, lr, beta1, beta2, eps, (hipStream_t)stream);
+    HIP_TRY(hipGetLastError());
     g_err.clear();
     return CCD_OK;
 }

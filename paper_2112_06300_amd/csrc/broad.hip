@@ -331,11 +331,53 @@ __device__ __forceinline__ void flush_pairs(int32_t (*buf)[2], int fill, int32_t
     }
 }
 
+// First index j in [a, b) with key[j] >= x (strict = false) or key[j] > x
+// (strict = true); keys sorted ascending.  The wave probes 64 evenly spaced
+// keys per step, so a search costs about log_64(b - a) dependent loads.
+__device__ __forceinline__ int64_t wave_lower_bound(const uint32_t *__restrict__ key, int64_t a, int64_t b,
+                                                    uint32_t x, bool strict, int lane)
+{
+    while (b - a > 64) {
+        const int64_t step = (b - a + 63) / 64;
+        const int64_t j = a + (int64_t)lane * step;
+        bool before = false;  // key[j] lies before the answer
+        if (j < b) {
+            const uint32_t kj = key[j];
+            before = strict ? kj <= x : kj < x;
+        }
+        const int nb = __popcll(__ballot(before));  // probes before the answer (a prefix)
+        if (nb == 0) return a;  // key[a] itself is not before the answer
+        const int64_t na = a + (int64_t)(nb - 1) * step + 1;
+        const int64_t nbb = a + (int64_t)nb * step;
+        a = na;
+        b = nbb < b ? nbb : b;
+    }
+    const int64_t j = a + lane;
+    bool before = false;
+    if (j < b) {
+        const uint32_t kj = key[j];
+        before = strict ? kj <= x : kj < x;
+    }
+    return a + __popcll(__ballot(before));
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs.  Tiles are dealt to
+// the XCDs in groups of kTileGroup consecutive tiles, so that the overlapping
+// sweep windows of a group are read through one L2 while the work stays
+// spread over all XCDs.
+constexpr int64_t kTileGroup = 16;
+
+__device__ __forceinline__ int64_t xcd_tile(int64_t b)
+{
+    const int64_t x = b % 8, i = b / 8;
+    return ((i / kTileGroup) * 8 + x) * kTileGroup + (i % kTileGroup);
+}
+
 __global__ __launch_bounds__(kTile) void sweep_kernel(
     const uint32_t *__restrict__ klo, const uint32_t *__restrict__ khi, const float *__restrict__ lob,
     const float *__restrict__ hib, const float *__restrict__ loc, const float *__restrict__ hic,
     const int32_t *__restrict__ pid, const int32_t *__restrict__ vtx, int64_t nv, int64_t ne, int64_t nf,
-    int64_t tiles_v, int64_t tiles_e, int32_t *vf, int64_t vf_cap, int32_t *ee, int64_t ee_cap,
+    int64_t tiles_v, int64_t tiles_e, int64_t ntiles, int32_t *vf, int64_t vf_cap, int32_t *ee, int64_t ee_cap,
     unsigned long long *counts)
 {
     __shared__ uint32_t s_klo[kTile];
@@ -345,7 +387,8 @@ __global__ __launch_bounds__(kTile) void sweep_kernel(
     __shared__ int32_t s_out[kOutCap][2];
     const int lane = threadIdx.x;
     const int64_t nb = nv + ne + nf, f0 = nv + ne;
-    const int64_t t = blockIdx.x;
+    const int64_t t = xcd_tile(blockIdx.x);
+    if (t >= ntiles) return;
     int role;  // 0: vertex tile, 1: edge tile, 2: face tile
     int64_t qbase, qend, cbeg, cend;
     if (t < tiles_v) {
@@ -370,32 +413,35 @@ __global__ __launch_bounds__(kTile) void sweep_kernel(
         w0 = vtx[3 * i]; w1 = vtx[3 * i + 1]; w2 = vtx[3 * i + 2];
     }
     const uint32_t kmin = wave_min_u32(kl), kmax = wave_max_u32(kh);
-    int64_t js;
-    if (role == 1) {
-        js = qbase;
-    } else {
-        int64_t a = cbeg, b = cend;
-        while (a < b) {
-            const int64_t m = (a + b) >> 1;
-            const uint32_t km = klo[m];
-            if (role == 0 ? km < kmin : km <= kmin) a = m + 1; else b = m;
-        }
-        js = a;
-    }
+    const int64_t js = role == 1 ? qbase : wave_lower_bound(klo, cbeg, cend, kmin, role == 2, lane);
     int fill = 0;  // pairs staged in s_out (wave-uniform)
-    for (int64_t cb = js; cb < cend; cb += kTile) {
-        const int64_t j = cb + lane;
-        uint32_t jk = 0xffffffffu;
+    // candidate chunk in registers, loaded one chunk ahead of its use
+    uint32_t jk = 0xffffffffu;
+    float4 jb = make_float4(0.f, 0.f, 0.f, 0.f);
+    int32_t jp = 0, jv0 = 0, jv1 = 0, jv2 = 0;
+    {
+        const int64_t j = js + lane;
         if (j < cend) {
-            jk = klo[j];
-            s_box[lane] = make_float4(lob[j], hib[j], loc[j], hic[j]);
-            s_pid[lane] = pid[j];
-            s_vtx[0][lane] = vtx[3 * j]; s_vtx[1][lane] = vtx[3 * j + 1]; s_vtx[2][lane] = vtx[3 * j + 2];
+            jk = klo[j]; jb = make_float4(lob[j], hib[j], loc[j], hic[j]);
+            jp = pid[j]; jv0 = vtx[3 * j]; jv1 = vtx[3 * j + 1]; jv2 = vtx[3 * j + 2];
         }
-        s_klo[lane] = jk;
+    }
+    for (int64_t cb = js; cb < cend; cb += kTile) {
         const uint32_t first = __shfl(jk, 0);
         if (first > kmax) break;  // uniform: this and every later chunk lies beyond all windows
+        s_klo[lane] = jk;
+        s_box[lane] = jb;
+        s_pid[lane] = jp;
+        s_vtx[0][lane] = jv0; s_vtx[1][lane] = jv1; s_vtx[2][lane] = jv2;
         __syncthreads();
+        {
+            const int64_t j = cb + kTile + lane;
+            jk = 0xffffffffu;
+            if (j < cend) {
+                jk = klo[j]; jb = make_float4(lob[j], hib[j], loc[j], hic[j]);
+                jp = pid[j]; jv0 = vtx[3 * j]; jv1 = vtx[3 * j + 1]; jv2 = vtx[3 * j + 2];
+            }
+        }
         // box tests: bit k of hits = overlap with candidate k of the chunk
         unsigned long long hits = 0ull;
 #pragma unroll 16
@@ -521,10 +567,11 @@ void launch_broad_sweep(int64_t nv, int64_t ne, int64_t nf, int32_t *vf, int64_t
     const int64_t nb = nv + ne + nf;
     if (nb == 0) return;
     const int64_t tv = (nv + kTile - 1) / kTile, te = (ne + kTile - 1) / kTile, tf = (nf + kTile - 1) / kTile;
-    if (tv + te + tf == 0) return;
-    sweep_kernel<<<(unsigned)(tv + te + tf), kTile, 0, s>>>(B.keyA, B.khi, B.lob, B.hib, B.loc, B.hic, B.pid,
-                                                          B.vtx, nv, ne, nf, tv, te, vf, vf_cap, ee, ee_cap,
-                                                          B.counts);
+    const int64_t nt = tv + te + tf;
+    if (nt == 0) return;
+    const int64_t grid = (nt + 8 * kTileGroup - 1) / (8 * kTileGroup) * (8 * kTileGroup);
+    sweep_kernel<<<(unsigned)grid, kTile, 0, s>>>(B.keyA, B.khi, B.lob, B.hib, B.loc, B.hic, B.pid, B.vtx, nv, ne,
+                                                 nf, tv, te, nt, vf, vf_cap, ee, ee_cap, B.counts);
 }
 
 int64_t sort_blocks(int64_t nb) { return nb > 0 ? (nb + kSortTile - 1) / kSortTile : 1; }

@@ -135,10 +135,39 @@ void launch_narrow_prep(const double *V0, const double *V1, int64_t nv, const in
                         const int32_t *F, int64_t nf, const int32_t *vf, int64_t n_vf, const int32_t *ee,
                         int64_t n_ee, double delta, const NarrowBuffers &B, hipStream_t s);
 
+// Scheduling features of every pair (after prep): n x kNumFeatures floats.
+constexpr int kNumFeatures = 16;
+void launch_narrow_features(const double *V0, const double *V1, int64_t n_vf, int64_t n_ee, double delta,
+                            const NarrowBuffers &B, float *feat, hipStream_t s);
+
 // pool: the wave-pool search of every pair (hands wide / deep pairs over).
+// Pairs are taken in index order, or in `order` (a permutation) when given.
 void launch_narrow_pool(const double *V0, const double *V1, int64_t n_vf, int64_t n_ee, double delta,
                         long long max_iter, uint8_t *hit, double *toi, long long *n_enq, const NarrowBuffers &B,
-                        int pool_blocks, hipStream_t s);
+                        int pool_blocks, const int32_t *order, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Learned schedule: MLP kNumFeatures -> 64 -> 64 -> 1 on bf16 MFMA.
+// Parameters (float32, contiguous): W1[16][64], b1[64], W2[64][64], b2[64],
+// W3[64], b3.  norm: feature mean[16] then 1 / std[16].
+// ---------------------------------------------------------------------------
+constexpr int kHidden = 64;
+constexpr int kModelParams = kNumFeatures * kHidden + kHidden + kHidden * kHidden + kHidden + kHidden + 1;
+
+void launch_mlp_predict(const float *params, const float *norm, const float *feat, int64_t n, float *out,
+                        hipStream_t s);
+// grad (kModelParams floats) and loss (1 float, sum of squared errors) are
+// accumulated; the launcher clears them first.  The loss is the mean squared
+// error over the n pairs.
+void launch_mlp_grad(const float *params, const float *norm, const float *feat, const float *label, int64_t n,
+                     float *grad, float *loss, hipStream_t s);
+void launch_adam(float *params, const float *grad, float *m, float *v, int64_t step, float lr, float beta1,
+                 float beta2, float eps, hipStream_t s);
+// order = pairs sorted by predicted cost, most expensive first (bins of 1/4 in
+// log2 cost); scratch holds 3 x 256 uint32.
+void launch_cost_order(const float *cost, int64_t n, int32_t *order, uint32_t *scratch, hipStream_t s);
+// *flag = 0 iff order is a permutation of [0, n); bits holds ceil(n / 32) words.
+void launch_check_permutation(const int32_t *order, int64_t n, uint32_t *bits, uint32_t *flag, hipStream_t s);
 
 // Wide stage: `nslots` workgroups, each with a frontier buffer of `cap` nodes
 // (two buffers of 3 x cap uint64).  Round 0 works on every handed-over pair;

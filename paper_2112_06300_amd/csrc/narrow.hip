@@ -29,7 +29,7 @@ namespace {
 constexpr int kHeavyBlock = 256;
 constexpr int kPoolSlots = 64;   // pairs in flight per wave (one owner lane each)
 constexpr int kQCap = 512;       // intervals per round per wave
-constexpr int kClaim = 256;      // pairs a wave claims from the global list at once
+constexpr int kClaim = 64;       // pairs a wave claims from the global list at once
 constexpr int DISCARD = 0, ACCEPT = 1, SPLIT = 2;
 
 struct Query {
@@ -239,6 +239,102 @@ __global__ __launch_bounds__(256) void prep_kernel(const double *__restrict__ V0
     pm[p] = mp;
 }
 
+// F on axis a at one point (t, u, v) with the canonical sequence of process().
+__device__ __forceinline__ double eval_point(const double raw[24], bool vf, int a, double t, double u, double v)
+{
+    double P[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) P[k] = fma(t, raw[12 + 3 * k + a] - raw[3 * k + a], raw[3 * k + a]);
+    if (vf) return fma(-v, P[3] - P[1], fma(-u, P[2] - P[1], P[0] - P[1]));
+    return fma(u, P[1] - P[0], P[0]) - fma(v, P[3] - P[2], P[2]);
+}
+
+__device__ __forceinline__ float log_ratio(double x, double delta) { return (float)log2(1.0 + fabs(x) / delta); }
+
+// Scheduling features of every pair (16 floats; pair order as in prep).  They
+// describe how hard the pair's search will be -- derivative bounds, the
+// root-level inclusion box against C_eps, F at the parameter-space centre at
+// t = 0, 1/2, 1 -- and never influence a result.  A pair with a bad index gets
+// zeros.
+__global__ __launch_bounds__(256) void feature_kernel(const double *__restrict__ V0, const double *__restrict__ V1,
+                                                     const int4 *__restrict__ ids4, const double *__restrict__ peps,
+                                                     const uint32_t *__restrict__ pm, int64_t n_vf, int64_t n,
+                                                     double delta, float *feat)
+{
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= n) return;
+    float f[kNumFeatures];
+    for (int i = 0; i < kNumFeatures; i++) f[i] = 0.f;
+    const int4 id = ids4[p];
+    if (id.x >= 0) {
+        const bool vf = p < n_vf;
+        double raw[24];
+        load_raw(id, V0, V1, raw);
+        const uint32_t mp = pm[p];
+        f[0] = vf ? 0.f : 1.f;
+        f[1] = (float)(mp & 255u);
+        f[2] = (float)((mp >> 8) & 255u);
+        f[3] = (float)((mp >> 16) & 255u);
+        double Lt = 0.0, Lu = 0.0, Lv = 0.0;
+        double gap = -__builtin_huge_val(), wmin = __builtin_huge_val(), wmax = 0.0;
+        int straddle = 0;
+        for (int a = 0; a < 3; a++) {
+            double dd[4];
+            for (int k = 0; k < 4; k++) dd[k] = raw[12 + 3 * k + a] - raw[3 * k + a];
+            double lt, lu, lv;
+            if (vf) {
+                lt = ((fabs(dd[0]) + fabs(dd[1])) + fabs(dd[2])) + fabs(dd[3]);
+                lu = fmax(fabs(raw[6 + a] - raw[3 + a]), fabs(raw[18 + a] - raw[15 + a]));
+                lv = fmax(fabs(raw[9 + a] - raw[3 + a]), fabs(raw[21 + a] - raw[15 + a]));
+            } else {
+                lt = fmax(fabs(dd[0]), fabs(dd[1])) + fmax(fabs(dd[2]), fabs(dd[3]));
+                lu = fmax(fabs(raw[3 + a] - raw[0 + a]), fabs(raw[15 + a] - raw[12 + a]));
+                lv = fmax(fabs(raw[9 + a] - raw[6 + a]), fabs(raw[21 + a] - raw[18 + a]));
+            }
+            Lt = fmax(Lt, lt);
+            Lu = fmax(Lu, lu);
+            Lv = fmax(Lv, lv);
+            double bmin = __builtin_huge_val(), bmax = -__builtin_huge_val();
+            for (int c = 0; c < 8; c++) {
+                const double fv = eval_point(raw, vf, a, (double)(c & 1), (double)((c >> 1) & 1), (double)(c >> 2));
+                bmin = fmin(bmin, fv);
+                bmax = fmax(bmax, fv);
+            }
+            const double e = peps[3 * p + a];
+            gap = fmax(gap, fmax(bmin - e, -e - bmax));
+            wmin = fmin(wmin, bmax - bmin);
+            wmax = fmax(wmax, bmax - bmin);
+            straddle += (bmin <= e && bmax >= -e) ? 1 : 0;
+        }
+        f[4] = log_ratio(Lt, delta);
+        f[5] = log_ratio(Lu, delta);
+        f[6] = log_ratio(Lv, delta);
+        f[7] = (gap > 0.0 ? 1.f : -1.f) * log_ratio(gap, delta);
+        f[8] = log_ratio(wmin, delta);
+        f[9] = log_ratio(wmax, delta);
+        f[10] = (float)straddle;
+        const double uc = vf ? 1.0 / 3.0 : 0.5, vc = uc;
+        double F0[3], F1[3], Fm[3];
+        for (int a = 0; a < 3; a++) {
+            F0[a] = eval_point(raw, vf, a, 0.0, uc, vc);
+            F1[a] = eval_point(raw, vf, a, 1.0, uc, vc);
+            Fm[a] = eval_point(raw, vf, a, 0.5, uc, vc);
+        }
+        const double n0 = sqrt(F0[0] * F0[0] + F0[1] * F0[1] + F0[2] * F0[2]);
+        const double n1 = sqrt(F1[0] * F1[0] + F1[1] * F1[1] + F1[2] * F1[2]);
+        const double nm = sqrt(Fm[0] * Fm[0] + Fm[1] * Fm[1] + Fm[2] * Fm[2]);
+        f[11] = log_ratio(n0, delta);
+        f[12] = log_ratio(n1, delta);
+        f[13] = log_ratio(nm, delta);
+        int flips = 0;
+        for (int a = 0; a < 3; a++) flips += ((F0[a] > 0.0) != (F1[a] > 0.0)) ? 1 : 0;
+        f[14] = (float)flips;
+        const double dot = F0[0] * F1[0] + F0[1] * F1[1] + F0[2] * F1[2];
+        f[15] = (float)(n0 > 0.0 && n1 > 0.0 ? dot / (n0 * n1) : 0.0);
+    }
+    for (int i = 0; i < kNumFeatures; i++) feat[p * kNumFeatures + i] = f[i];
+}
+
 __device__ __forceinline__ int wave_excl_scan(int v, int lane, int &total)
 {
     int x = v;
@@ -255,10 +351,11 @@ struct PoolLds {
     double d[12][kPoolSlots];    // displacements
     double eps[3][kPoolSlots];
     uint32_t lv[kPoolSlots];     // levels l_t | l_u << 8 | l_v << 16 | vertex-face << 24
+    uint32_t mm[kPoolSlots];     // split levels m_t | m_u << 8 | m_v << 16
     unsigned long long node[2][kQCap];  // interval numerators, 21 bits each (t | u << 21 | v << 42)
     uint8_t slot[2][kQCap];
     uint8_t res[kQCap];
-    // per-slot accumulators of one bookkeeping pass
+    // per-slot accumulators
     unsigned long long tstar[kPoolSlots];  // t* bits (non-negative doubles order like uint64)
     unsigned long long tmin[kPoolSlots];   // earliest kept child
     unsigned long long hoff[kPoolSlots];   // first node of a hand-over in the node buffer
@@ -280,23 +377,43 @@ __device__ __forceinline__ unsigned long long child_of(unsigned long long nd, in
     return (nd & ~(0x1fffffull << sh)) | ((2ull * nk + (unsigned long long)c) << sh);
 }
 
+// Split dimension of a slot's next level from its packed levels and m.
+__device__ __forceinline__ int slot_split(uint32_t lvp, uint32_t mp, int &lk)
+{
+    int m[3], l[3];
+    unpack_m(mp, m);
+    l[0] = (int)(lvp & 255u); l[1] = (int)((lvp >> 8) & 255u); l[2] = (int)((lvp >> 16) & 255u);
+    const int k = split_dim(m, l);
+    lk = l[k];
+    return k;
+}
+
+// The pool.  A round:
+//   D (all lanes, last round's queue): count the kept children of every split
+//     interval into its slot (LDS atomics);
+//   E (owner lanes): finish, cap, hand over or expand each pair; queue offsets
+//     by wave prefix sums; free slots take their prefetched pair as a new root;
+//   F (all lanes): write the kept children (or hand-over survivors);
+//   EVAL (all lanes, this round's queue): evaluate, then fold the result into
+//     the slot (atomic min of t*, survivor count).
 __global__ __launch_bounds__(kPoolSlots) void pool_kernel(
     const double *__restrict__ V0, const double *__restrict__ V1, const int4 *__restrict__ ids4,
     const double *__restrict__ peps, const uint32_t *__restrict__ pm, int64_t n_vf, int64_t n_pairs,
     double delta, long long max_iter, uint8_t *hit, double *toi, long long *n_enq_out, HeavyEntry *heavy,
-    unsigned long long *hnodes, int64_t hnode_cap, unsigned int *counters)
+    unsigned long long *hnodes, int64_t hnode_cap, unsigned int *counters, const int32_t *__restrict__ order)
 {
     __shared__ PoolLds S;
     const int lane = threadIdx.x;
     const unsigned long long lt_mask = (1ull << lane) - 1ull;
-    // wave-uniform chunk of unclaimed pairs
-    long long ch_cur = 0, ch_end = 0;
+    // wave-uniform claim state: current chunk [ch_cur, ch_end) and the next chunk, claimed ahead
+    long long ch_cur = 0, ch_end = 0, nx_base = -1;
     bool exhausted = false;
-    // prefetched next pair (np >= 0) and its data
-    long long np = -1;
-    bool np_ok = false;
-    double raw[24], neps[3];
-    uint32_t nm = 0u;
+    // two-stage prefetch: stage A holds ids / eps / m, stage B the gathered points
+    long long pa = -1, pb = -1;
+    int4 ida = make_int4(-1, 0, 0, 0);
+    double epsa[3] = {0.0, 0.0, 0.0}, epsb[3] = {0.0, 0.0, 0.0}, raw[24];
+    uint32_t ma = 0u, mb = 0u;
+    bool okb = false;
     // the pair this lane owns (slot = lane)
     bool active = false;
     long long p = -1;
@@ -306,32 +423,47 @@ __global__ __launch_bounds__(kPoolSlots) void pool_kernel(
     long long nenq = 0;
     int cur = 0;  // queue holding last round's evaluated entries
     int nq = 0;   // its length
+    if (lane == 0) nx_base = (long long)atomicAdd((unsigned long long *)&counters[8], (unsigned long long)kClaim);
+    nx_base = __shfl(nx_base, 0);
+    S.tstar[lane] = kInfBits;
+    S.nsurv[lane] = 0;
+    S.cnt[lane] = 0;
+    S.tmin[lane] = kInfBits;
+    S.lv[lane] = 0u;
+    S.mm[lane] = 0u;
 
     for (;;) {
-        // ---- claim and prefetch the next pair of every lane without one (uniform control flow)
-        bool need = np < 0 && !exhausted;
+        // ---- prefetch pipeline (uniform control flow)
+        if (pb < 0 && pa >= 0) {
+            // stage B: gather the points of the pair whose ids arrived last round
+            pb = pa;
+            pa = -1;
+            okb = ida.x >= 0;
+            if (okb) load_raw(ida, V0, V1, raw);
+            epsb[0] = epsa[0]; epsb[1] = epsa[1]; epsb[2] = epsa[2];
+            mb = ma;
+        }
+        bool need = pa < 0 && !exhausted;
         unsigned long long want = __ballot(need);
         while (want) {
             if (ch_cur >= ch_end) {
+                if (nx_base >= n_pairs) { exhausted = true; break; }
+                ch_cur = nx_base;
+                ch_end = ch_cur + kClaim < n_pairs ? ch_cur + kClaim : n_pairs;
                 unsigned long long b = 0ull;
                 if (lane == 0) b = atomicAdd((unsigned long long *)&counters[8], (unsigned long long)kClaim);
-                b = __shfl(b, 0);
-                ch_cur = (long long)b;
-                ch_end = ch_cur + kClaim < n_pairs ? ch_cur + kClaim : n_pairs;
-                if (ch_cur >= n_pairs) { exhausted = true; break; }
+                nx_base = (long long)__shfl(b, 0);
             }
             const long long avail = ch_end - ch_cur;
             const long long rank = __popcll(want & lt_mask);
             if (need && rank < avail) {
-                np = ch_cur + rank;
+                // stage A: ids, C_eps and split levels of the claimed pair (in schedule order)
+                pa = ch_cur + rank;
+                if (order) pa = order[pa];
                 need = false;
-                const int4 id = ids4[np];
-                np_ok = id.x >= 0;
-                if (np_ok) {
-                    load_raw(id, V0, V1, raw);
-                    neps[0] = peps[3 * np]; neps[1] = peps[3 * np + 1]; neps[2] = peps[3 * np + 2];
-                    nm = pm[np];
-                }
+                ida = ids4[pa];
+                epsa[0] = peps[3 * pa]; epsa[1] = peps[3 * pa + 1]; epsa[2] = peps[3 * pa + 2];
+                ma = pm[pa];
             }
             const long long taken = __popcll(want) < avail ? __popcll(want) : avail;
             ch_cur += taken;
@@ -339,52 +471,16 @@ __global__ __launch_bounds__(kPoolSlots) void pool_kernel(
         }
         const int nxt = cur ^ 1;
 
-        // ---- A: reset this slot's accumulators
-        S.tstar[lane] = (unsigned long long)__double_as_longlong(tstar);
-        S.tmin[lane] = kInfBits;
-        S.nsurv[lane] = 0;
-        S.cnt[lane] = 0;
-        S.pos[lane] = 0;
-        S.k[lane] = kNoExpand;
-        __syncthreads();
-        // ---- B (all lanes over all entries): reported roots lower t*, split entries are survivors
-        for (int b0 = 0; b0 < nq; b0 += kPoolSlots) {
-            const int e = b0 + lane;
-            if (e < nq) {
-                const int r = S.res[e];
-                const int s = S.slot[cur][e];
-                if (r == ACCEPT) {
-                    const double tl = node_tlo(S.node[cur][e], pow2neg((int)(S.lv[s] & 255u)));
-                    atomicMin(&S.tstar[s], (unsigned long long)__double_as_longlong(tl));
-                } else if (r == SPLIT) {
-                    atomicAdd(&S.nsurv[s], 1);
-                }
-            }
-        }
-        __syncthreads();
-        // ---- C (owner lanes): finished, handed over for depth, or expanding along k
-        int outcome = 0;  // 1 finished, 2 capped, 3 hand over, 4 push the next level
-        int k = -1, nsurv = 0;
-        if (active) {
-            tstar = __longlong_as_double((long long)S.tstar[lane]);
-            nsurv = S.nsurv[lane];
-            if (nsurv == 0) {
-                outcome = 1;
-            } else {
-                k = split_dim(m, l);
-                if (l[k] + 1 > kLightMaxLevel) outcome = 3;
-                else S.k[lane] = k;
-            }
-        }
-        __syncthreads();
-        // ---- D (all lanes over all entries): count the children that start before t*
+        // ---- D (all lanes over last round's entries): count children that start before t*
         for (int b0 = 0; b0 < nq; b0 += kPoolSlots) {
             const int e = b0 + lane;
             if (e < nq && S.res[e] == SPLIT) {
                 const int s = S.slot[cur][e];
-                const int ks = S.k[s];
-                if (ks >= 0) {
-                    const double tsn = pow2neg((int)(S.lv[s] & 255u) + (ks == 0 ? 1 : 0));
+                const uint32_t lvp = S.lv[s];
+                int lk = 0;
+                const int ks = slot_split(lvp, S.mm[s], lk);
+                if (lk + 1 <= kLightMaxLevel) {
+                    const double tsn = pow2neg((int)(lvp & 255u) + (ks == 0 ? 1 : 0));
                     const double ts = __longlong_as_double((long long)S.tstar[s]);
                     const unsigned long long nd = S.node[cur][e];
 #pragma unroll
@@ -399,14 +495,27 @@ __global__ __launch_bounds__(kPoolSlots) void pool_kernel(
             }
         }
         __syncthreads();
-        // ---- E (owner lanes): count, cap, queue offsets; a level that does not fit is handed over
-        int push = 0;
-        const double tmin = __longlong_as_double((long long)S.tmin[lane]);
-        if (outcome == 0 && active) {
-            const int cnt = S.cnt[lane];
-            if (cnt == 0) outcome = 1;
-            else if (nenq + cnt > max_iter) { outcome = 2; nenq += cnt; }
-            else { outcome = 4; push = cnt; }
+        // ---- E (owner lanes): decide, queue offsets, outputs, hand-overs, new roots
+        int outcome = 0;  // 1 finished, 2 capped, 3 hand over, 4 push the next level
+        int k = -1, push = 0, nsurv = 0;
+        double tmin = __builtin_huge_val();
+        if (active) {
+            tstar = __longlong_as_double((long long)S.tstar[lane]);
+            nsurv = S.nsurv[lane];
+            tmin = __longlong_as_double((long long)S.tmin[lane]);
+            if (nsurv == 0) {
+                outcome = 1;
+            } else {
+                k = split_dim(m, l);
+                if (l[k] + 1 > kLightMaxLevel) {
+                    outcome = 3;
+                } else {
+                    const int cnt = S.cnt[lane];
+                    if (cnt == 0) outcome = 1;
+                    else if (nenq + cnt > max_iter) { outcome = 2; nenq += cnt; }
+                    else { outcome = 4; push = cnt; }
+                }
+            }
         }
         int total = 0;
         int off = wave_excl_scan(outcome == 4 ? push : 0, lane, total);
@@ -414,12 +523,13 @@ __global__ __launch_bounds__(kPoolSlots) void pool_kernel(
             if (outcome == 4 && off + push > kQCap) outcome = 3;
             off = wave_excl_scan(outcome == 4 ? push : 0, lane, total);
         }
+        S.k[lane] = kNoExpand;
+        S.pos[lane] = 0;
         if (outcome == 1 || outcome == 2) {
             hit[p] = (uint8_t)(outcome == 2 || tstar < __builtin_huge_val());
             toi[p] = outcome == 2 ? tmin : tstar;
             if (n_enq_out) n_enq_out[p] = nenq;
             active = false;
-            S.k[lane] = kNoExpand;
         } else if (outcome == 3) {
             // survivors (levels l, still to be split), t* and count go to the wide stage
             const unsigned hs = atomicAdd(&counters[0], 1u);
@@ -441,15 +551,55 @@ __global__ __launch_bounds__(kPoolSlots) void pool_kernel(
                 h.tstar = __builtin_huge_val();
                 h.n_enq = 0;
                 h.node_off = -1;
-                S.k[lane] = kNoExpand;
             }
             heavy[hs] = h;
             active = false;
         } else if (outcome == 4) {
+            l[k]++;
+            nenq += push;
+            S.k[lane] = k;
             S.off[lane] = off;
+            S.lv[lane] = (uint32_t)l[0] | ((uint32_t)l[1] << 8) | ((uint32_t)l[2] << 16) | ((uint32_t)vf << 24);
         }
+        if (!active && pb >= 0 && !okb) {
+            // a pair with a bad index or coordinate: reported as no collision (the call returns an error)
+            hit[pb] = 0;
+            toi[pb] = __builtin_huge_val();
+            if (n_enq_out) n_enq_out[pb] = 0;
+            pb = -1;
+        }
+        const bool new_root = !active && pb >= 0;
+        int rtotal = 0;
+        const int roff = wave_excl_scan(new_root ? 1 : 0, lane, rtotal);
+        const bool root_fits = new_root && total + roff < kQCap;
+        if (root_fits) {
+            p = pb;
+            pb = -1;
+            vf = p < n_vf;
+#pragma unroll
+            for (int kk = 0; kk < 12; kk++) {
+                S.x0[kk][lane] = raw[kk];
+                S.d[kk][lane] = raw[12 + kk] - raw[kk];
+            }
+            S.eps[0][lane] = epsb[0]; S.eps[1][lane] = epsb[1]; S.eps[2][lane] = epsb[2];
+            S.mm[lane] = mb;
+            unpack_m(mb, m);
+            l[0] = l[1] = l[2] = 0;
+            tstar = __builtin_huge_val();
+            nenq = 0;
+            S.node[nxt][total + roff] = 0ull;
+            S.slot[nxt][total + roff] = (uint8_t)lane;
+            S.lv[lane] = (uint32_t)vf << 24;
+            active = true;
+        }
+        // accumulators for the next EVAL and D
+        S.tstar[lane] = (unsigned long long)__double_as_longlong(active ? tstar : __builtin_huge_val());
+        S.nsurv[lane] = 0;
+        S.cnt[lane] = 0;
+        S.tmin[lane] = kInfBits;
+        const int T = total + __popcll(__ballot(root_fits));
         __syncthreads();
-        // ---- F (all lanes over all entries): write kept children, or copy hand-over survivors
+        // ---- F (all lanes over last round's entries): kept children, or hand-over survivors
         for (int b0 = 0; b0 < nq; b0 += kPoolSlots) {
             const int e = b0 + lane;
             if (e < nq && S.res[e] == SPLIT) {
@@ -457,7 +607,7 @@ __global__ __launch_bounds__(kPoolSlots) void pool_kernel(
                 const int ks = S.k[s];
                 const unsigned long long nd = S.node[cur][e];
                 if (ks >= 0) {
-                    const double tsn = pow2neg((int)(S.lv[s] & 255u) + (ks == 0 ? 1 : 0));
+                    const double tsn = pow2neg((int)(S.lv[s] & 255u));  // levels already advanced
                     const double ts = __longlong_as_double((long long)S.tstar[s]);
 #pragma unroll
                     for (int c = 0; c < 2; c++) {
@@ -474,46 +624,9 @@ __global__ __launch_bounds__(kPoolSlots) void pool_kernel(
             }
         }
         __syncthreads();
-        // ---- G (owner lanes): new levels; free slots take their prefetched pair as a new root
-        if (outcome == 4) {
-            l[k]++;
-            nenq += push;
-            S.lv[lane] = (uint32_t)l[0] | ((uint32_t)l[1] << 8) | ((uint32_t)l[2] << 16) | ((uint32_t)vf << 24);
-        }
-        if (!active && np >= 0 && !np_ok) {
-            // a pair with a bad index or coordinate: reported as no collision (the call returns an error)
-            hit[np] = 0;
-            toi[np] = __builtin_huge_val();
-            if (n_enq_out) n_enq_out[np] = 0;
-            np = -1;
-        }
-        const bool new_root = !active && np >= 0;
-        int rtotal = 0;
-        const int roff = wave_excl_scan(new_root ? 1 : 0, lane, rtotal);
-        const bool root_fits = new_root && total + roff < kQCap;
-        if (root_fits) {
-            p = np;
-            np = -1;
-            vf = p < n_vf;
-#pragma unroll
-            for (int kk = 0; kk < 12; kk++) {
-                S.x0[kk][lane] = raw[kk];
-                S.d[kk][lane] = raw[12 + kk] - raw[kk];
-            }
-            S.eps[0][lane] = neps[0]; S.eps[1][lane] = neps[1]; S.eps[2][lane] = neps[2];
-            unpack_m(nm, m);
-            l[0] = l[1] = l[2] = 0;
-            tstar = __builtin_huge_val();
-            nenq = 0;
-            S.node[nxt][total + roff] = 0ull;
-            S.slot[nxt][total + roff] = (uint8_t)lane;
-            S.lv[lane] = (uint32_t)vf << 24;
-            active = true;
-        }
-        const int T = total + __popcll(__ballot(root_fits));
-        if (T == 0 && !__ballot(np >= 0)) break;  // nothing queued and no pair left for this wave
-        __syncthreads();
-        // ---- evaluation phase: one queued interval per lane, any slot
+        // after F, so that the survivors of a pair handed over in this round are copied
+        if (T == 0 && !__ballot(pa >= 0 || pb >= 0)) break;  // nothing queued and no pair left for this wave
+        // ---- EVAL: one queued interval per lane, any slot; results folded into the slot
         for (int b0 = 0; b0 < T; b0 += kPoolSlots) {
             const int e = b0 + lane;
             if (e < T) {
@@ -536,10 +649,13 @@ __global__ __launch_bounds__(kPoolSlots) void pool_kernel(
                         q.d[kk][a] = S.d[3 * kk + a][s];
                     }
                 q.eps[0] = S.eps[0][s]; q.eps[1] = S.eps[1][s]; q.eps[2] = S.eps[2][s];
-                const int r = process(q, evf, (double)nt * tscale, (double)(nt + 1u) * tscale, (double)nu * uscale,
+                const double t0 = (double)nt * tscale;
+                const int r = process(q, evf, t0, (double)(nt + 1u) * tscale, (double)nu * uscale,
                                       (double)(nu + 1u) * uscale, (double)nw * vscale, (double)(nw + 1u) * vscale,
                                       false, delta);
                 S.res[e] = (uint8_t)r;
+                if (r == ACCEPT) atomicMin(&S.tstar[s], (unsigned long long)__double_as_longlong(t0));
+                else if (r == SPLIT) atomicAdd(&S.nsurv[s], 1);
             }
         }
         __syncthreads();
@@ -777,16 +893,24 @@ void launch_narrow_prep(const double *V0, const double *V1, int64_t nv, const in
                                                            B.ids4, B.eps, B.m, B.flags);
 }
 
+void launch_narrow_features(const double *V0, const double *V1, int64_t n_vf, int64_t n_ee, double delta,
+                            const NarrowBuffers &B, float *feat, hipStream_t s)
+{
+    const int64_t n = n_vf + n_ee;
+    if (n == 0) return;
+    feature_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(V0, V1, B.ids4, B.eps, B.m, n_vf, n, delta, feat);
+}
+
 void launch_narrow_pool(const double *V0, const double *V1, int64_t n_vf, int64_t n_ee, double delta,
                         long long max_iter, uint8_t *hit, double *toi, long long *n_enq, const NarrowBuffers &B,
-                        int pool_blocks, hipStream_t s)
+                        int pool_blocks, const int32_t *order, hipStream_t s)
 {
     const int64_t n = n_vf + n_ee;
     if (n == 0) return;
     int64_t blocks = (n + kPoolSlots - 1) / kPoolSlots;
     if (blocks > pool_blocks) blocks = pool_blocks;
     pool_kernel<<<(unsigned)blocks, kPoolSlots, 0, s>>>(V0, V1, B.ids4, B.eps, B.m, n_vf, n, delta, max_iter, hit,
-                                                       toi, n_enq, B.heavy, B.hnodes, B.hnode_cap, B.counters);
+                                                       toi, n_enq, B.heavy, B.hnodes, B.hnode_cap, B.counters, order);
 }
 
 void launch_narrow_heavy(const double *V0, const double *V1, int64_t n_vf, double delta, long long max_iter,
