@@ -6,7 +6,11 @@ delta = 1e-6, max_iter = 1e6.  One step = ccd_broad on device-resident
 V0/V1/E/F followed by ccd_narrow on its candidate pairs (per-pair hit/TOI and
 the global minimum).  Inputs are seeded synthetic meshes built by `scenes`.
 
-Prints one JSON line.  See the design doc for the roofline definitions.
+The step is timed twice: with the learned schedule (features, network and
+ordering inside the timed step) -- the reported value -- and with the plain
+schedule (pairs in broad-phase order), reported beside it.
+
+Prints one JSON line.
 """
 import argparse
 import hashlib
@@ -96,6 +100,7 @@ def main():
     import numpy as np
     import scenes
     import paper_2112_06300_amd as ccd
+    from paper_2112_06300_amd import sched
 
     scene = scenes.cloth_on_sphere(n=args.cloth_n)
     dev = lambda x, dt: torch.as_tensor(np.ascontiguousarray(x)).to("cuda", dt)
@@ -113,35 +118,46 @@ def main():
     toi = torch.empty(n_pairs_max, dtype=torch.float64, device="cuda")
     tmin = torch.empty(1, dtype=torch.float64, device="cuda")
 
-    def step():
+    params, norm, model_meta = sched.load_model()
+    learned = ("learned", torch.as_tensor(params).cuda(), torch.as_tensor(norm).cuda(), ccd.HEAVY_THRESHOLD,
+               ccd.MAX_HEAVY)
+
+    def step(schedule):
         n_vf, n_ee = ctx.broad_into(V0, V1, E, F, vf, ee)
         st_b = ctx.stats()
         n = n_vf + n_ee
-        ctx.narrow(V0, V1, E, F, vf[:n_vf], ee[:n_ee], DELTA, MAX_ITER,
-                   out=(hit[:n], toi[:n], tmin, None))
+        ctx.narrow(V0, V1, E, F, vf[:n_vf], ee[:n_ee], DELTA, MAX_ITER, out=(hit[:n], toi[:n], tmin, None),
+                   schedule=schedule)
         st_n = ctx.stats()
         return n_vf, n_ee, st_b, st_n
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    stage = {k: 0.0 for k in ("broad_ms", "box_ms", "sort_ms", "gather_ms", "sweep_ms", "narrow_ms",
-                              "narrow_prep_ms", "narrow_pool_ms", "narrow_heavy_ms")}
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        n_vf, n_ee, st_b, st_n = step()
-        for k in ("broad_ms", "box_ms", "sort_ms", "gather_ms", "sweep_ms"):
-            stage[k] += st_b[k]
-        for k in ("narrow_ms", "narrow_prep_ms", "narrow_pool_ms", "narrow_heavy_ms"):
-            stage[k] += st_n[k]
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    b_keys = ("broad_ms", "box_ms", "sort_ms", "gather_ms", "sweep_ms")
+    n_keys = ("narrow_ms", "narrow_prep_ms", "narrow_sched_ms", "narrow_pool_ms", "narrow_heavy_ms",
+              "heavy_pairs", "sched_heavy_pairs")
+
+    def timed(schedule):
+        for _ in range(args.warmup):
+            step(schedule)
+        torch.cuda.synchronize()
+        acc = {k: 0.0 for k in b_keys + n_keys}
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            n_vf, n_ee, st_b, st_n = step(schedule)
+            for k in b_keys:
+                acc[k] += st_b[k]
+            for k in n_keys:
+                acc[k] += st_n[k]
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        return n_vf, n_ee, (t1 - t0) * 1000.0 / args.steps, {k: v / args.steps for k, v in acc.items()}
+
+    n_vf, n_ee, ms_per_step, stage = timed(learned)
+    _, _, plain_ms, plain_stage = timed(None)
     K = args.steps
-    ms_per_step = (t1 - t0) * 1000.0 / K
-    stage = {k: v / K for k, v in stage.items()}
     pairs = n_vf + n_ee
     value = pairs / (ms_per_step / 1000.0)
-    heavy_pairs = st_n["heavy_pairs"]
+    plain_value = pairs / (plain_ms / 1000.0)
+    heavy_pairs = stage["heavy_pairs"]
 
     nv, ne, nf = scene.nv, scene.ne, scene.nf
     nb = nv + ne + nf
@@ -156,8 +172,9 @@ def main():
     if not args.no_cpu_baseline:
         cpu, flops, n_eval = cpu_baseline(scene, pairs)
 
-    search_ms = stage["narrow_pool_ms"] + stage["narrow_heavy_ms"]
+    search_ms = plain_stage["narrow_pool_ms"] + plain_stage["narrow_heavy_ms"]
     narrow_tflops = flops / (stage["narrow_ms"] * 1e-3) / 1e12 if flops else None
+    plain_narrow_tflops = flops / (plain_stage["narrow_ms"] * 1e-3) / 1e12 if flops else None
     search_tflops = flops / (search_ms * 1e-3) / 1e12 if flops else None
 
     # the dominant kernel of the step (GPU event times on the library's stream)
@@ -188,7 +205,7 @@ def main():
                 "kernel": "pool_kernel+heavy_kernel (interval search)", "alg_flops_per_launch": flops}
 
     out = {
-        "metric": "candidate pairs/sec (broad+narrow, FP64, delta=1e-6), plain schedule",
+        "metric": "candidate pairs/sec (broad+narrow, FP64, delta=1e-6), learned-sched vs plain",
         "value": value,
         "unit": "pairs/s",
         "n_gpus": 1,
@@ -203,14 +220,19 @@ def main():
         "config": {"workload": f"cloth_on_sphere: {args.cloth_n}x{args.cloth_n} cloth + 10,242-vertex icosphere "
                                f"(nv={nv}, ne={ne}, nf={nf}, boxes={nb})",
                    "pairs": pairs, "vf_pairs": n_vf, "ee_pairs": n_ee, "delta": DELTA, "max_iter": MAX_ITER,
-                   "schedule": "plain"},
+                   "schedule": "learned", "model": model_meta.get("train"),
+                   "heavy_threshold": ccd.HEAVY_THRESHOLD, "max_heavy": ccd.MAX_HEAVY},
+        "plain": {"value": plain_value, "ms_per_step": plain_ms, "stages_ms": plain_stage},
+        "learned_over_plain": value / plain_value,
         "roofline": roof,
         "cpu_baseline": cpu,
         "stages_ms": stage,
         "broad_hbm": {"alg_bytes": broad_bytes, "achieved_gbs": broad_gbs, "frac": broad_gbs / HBM_PEAK_GBS},
         "narrow_fp64": {"alg_flops": flops, "canonical_evals": n_eval, "achieved_tflops": narrow_tflops,
                         "frac": (narrow_tflops / FP64_PEAK_TFLOPS if narrow_tflops else None),
-                        "search_kernels_tflops": search_tflops, "heavy_pairs": heavy_pairs},
+                        "plain_achieved_tflops": plain_narrow_tflops,
+                        "plain_search_kernels_tflops": search_tflops, "heavy_pairs": heavy_pairs,
+                        "sched_heavy_pairs": stage["sched_heavy_pairs"]},
     }
     ctx.close()
     print(json.dumps(out))

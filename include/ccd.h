@@ -126,10 +126,14 @@ ccd_status ccd_narrow(ccd_context *ctx, const double *V0, const double *V1, int6
 /*
  * Learned schedule (not part of the paper's method): a small MLP predicts each
  * pair's search cost, log2(1 + intervals enqueued), from CCD_NUM_FEATURES
- * geometric features; the narrow phase then takes pairs in decreasing
- * predicted cost, which balances the load across the GPU.  The schedule only
- * changes the order in which pairs are searched: hit, toi, toi_min and n_enq
- * are identical to the plain schedule's.
+ * geometric features.  The pairs predicted costliest (at least
+ * heavy_threshold, at most max_heavy of them) start at once in the
+ * workgroup-per-pair wide stage, on a second stream beside the wave pool,
+ * instead of reaching it only after overflowing a pool queue; the pool takes
+ * the others ranked by predicted cost and dealt so that every 64-pair claim
+ * spans the cost range.  The schedule only changes where and in which order
+ * pairs are searched: hit, toi, toi_min and n_enq are identical to the plain
+ * schedule's.
  *
  * Model parameters are CCD_MODEL_PARAMS float32 values, contiguous:
  *   W1[16][64], b1[64], W2[64][64], b2[64], W3[64], b3
@@ -148,6 +152,8 @@ typedef struct {
     const float *params;   /* LEARNED: device, CCD_MODEL_PARAMS floats */
     const float *norm;     /* LEARNED: device, 2 * CCD_NUM_FEATURES floats */
     const int32_t *order;  /* ORDER: device permutation of [0, n_vf + n_ee): search order */
+    float heavy_threshold; /* LEARNED: predicted log2(1 + n_enq) from which a pair starts in the wide stage */
+    int32_t max_heavy;     /* LEARNED: at most this many such pairs (0: none), 0..4096 */
 } ccd_schedule;
 
 /* ccd_narrow with a schedule (NULL = plain: pairs in index order).  Same
@@ -201,9 +207,79 @@ typedef struct {
     int64_t sort_axis;      /* axis the last broad phase swept along */
     int64_t heavy_pairs;    /* pairs the last narrow phase passed to the wide stage */
     int64_t heavy_reruns;   /* pairs re-run with a larger frontier buffer */
+    int64_t sched_heavy_pairs; /* pairs the learned schedule started in the wide stage */
+    double batch_ms;        /* last ccd_batch_run pass (graph launch or eager kernels) */
 } ccd_stats;
 
 ccd_status ccd_get_stats(ccd_context *ctx, ccd_stats *out);
+
+/*
+ * Tuning of the kernels' launch shapes (the results never depend on it).
+ *   sweep_tile_group    sweep tiles dealt to one XCD slot together, so that
+ *                       their overlapping windows share one L2 (default 16)
+ *   pool_blocks_per_cu  resident narrow-phase pool workgroups per compute
+ *                       unit, 0 = as many as fit (default)
+ *   heavy_slots         workgroups of the wide stage (default 1024)
+ *   heavy_cap_log2      log2 of each wide-stage frontier buffer in intervals
+ *                       (default 13); a frontier that outgrows it is re-run
+ *                       with 8x larger buffers
+ * ccd_set_tuning(ctx, NULL) restores the defaults.  INVALID_ARG when a value
+ * is out of range (group 1..1024, blocks 0..64, slots 1..65536, cap 8..24).
+ */
+typedef struct {
+    int32_t sweep_tile_group;
+    int32_t pool_blocks_per_cu;
+    int32_t heavy_slots;
+    int32_t heavy_cap_log2;
+} ccd_tuning;
+
+ccd_status ccd_set_tuning(ccd_context *ctx, const ccd_tuning *tuning);
+ccd_status ccd_get_tuning(ccd_context *ctx, ccd_tuning *tuning);
+
+/*
+ * Batches (Sec. 4.4 runs scenes of uneven size through fixed device buffers):
+ * S scenes processed by one pass of the broad and narrow phases, pairs never
+ * crossing scenes.  The scenes are concatenated in CSR layout: scene s owns
+ * vertices [v_off[s], v_off[s+1]), edges [e_off[s], e_off[s+1]) and faces
+ * [f_off[s], f_off[s+1]) of the concatenated V0, V1, E, F, whose vertex ids
+ * are GLOBAL (already offset).  Offsets are HOST arrays of S + 1 values
+ * starting at 0, copied at creation; 1 <= S <= 65536.
+ *
+ * ccd_batch_create allocates every device buffer of the pass once (for the
+ * given pair capacities), so that runs allocate nothing but the wide stage's
+ * rare enlarged re-run buffers.  The batch borrows the context, which must
+ * outlive it.
+ *
+ * ccd_batch_run: candidate pairs into vf (vf_cap x 2) and ee (ee_cap x 2),
+ * per-pair hit / toi (vf_cap + ee_cap entries, VF pairs first: pair p is
+ * vf[p] for p < *n_vf, else ee[p - *n_vf]), optional n_enq (same length, or
+ * NULL), and toi_min[s] (S doubles, +inf for a scene without a hit).  All
+ * DEVICE pointers; *n_vf, *n_ee are host.  With use_graph != 0 the pass is
+ * captured once into a HIP graph and replayed (re-captured when a pointer,
+ * delta, max_iter or the tuning changes).  The pass runs on a stream of the
+ * batch ordered after `stream`, and `stream` waits for it.  CAPACITY: *n_vf /
+ * *n_ee hold the required counts and the outputs are unspecified; other errors
+ * as ccd_broad and ccd_narrow.  Calls on one batch must not overlap.
+ *
+ * ccd_batch_autotune: times batch passes over candidate tunings (coordinate
+ * descent over tile group, pool blocks per CU and wide-stage slots) and sets
+ * the best on the context.  With cache_path the choice is stored under a
+ * signature of the device and the workload's size, and a later call with the
+ * same signature takes it from the file without timing.  Outputs as
+ * ccd_batch_run (without n_enq).
+ */
+typedef struct ccd_batch ccd_batch;
+
+ccd_status ccd_batch_create(ccd_context *ctx, int64_t n_scenes, const int64_t *v_off, const int64_t *e_off,
+                            const int64_t *f_off, int64_t vf_cap, int64_t ee_cap, ccd_batch **out);
+void ccd_batch_destroy(ccd_batch *batch);
+ccd_status ccd_batch_run(ccd_batch *batch, const double *V0, const double *V1, const int32_t *E, const int32_t *F,
+                         double delta, int64_t max_iter, int32_t *vf, int32_t *ee, int64_t *n_vf, int64_t *n_ee,
+                         uint8_t *hit, double *toi, double *toi_min, int64_t *n_enq, int use_graph, void *stream);
+ccd_status ccd_batch_autotune(ccd_batch *batch, const double *V0, const double *V1, const int32_t *E,
+                              const int32_t *F, double delta, int64_t max_iter, int32_t *vf, int32_t *ee,
+                              uint8_t *hit, double *toi, double *toi_min, const char *cache_path,
+                              ccd_tuning *chosen, void *stream);
 
 #ifdef __cplusplus
 }

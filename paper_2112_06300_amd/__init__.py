@@ -30,7 +30,8 @@ _STATUS_NAMES = {
 # Every symbol include/ccd.h declares.
 EXPORTED = ["ccd_create", "ccd_destroy", "ccd_last_error", "ccd_version", "ccd_broad", "ccd_narrow",
             "ccd_narrow_sched", "ccd_features", "ccd_mlp_predict", "ccd_mlp_grad", "ccd_adam_step",
-            "ccd_get_stats"]
+            "ccd_get_stats", "ccd_set_tuning", "ccd_get_tuning", "ccd_batch_create", "ccd_batch_destroy",
+            "ccd_batch_run", "ccd_batch_autotune"]
 
 NUM_FEATURES = 16
 HIDDEN = 64
@@ -51,12 +52,24 @@ class Stats(ctypes.Structure):
                 ("narrow_pool_ms", ctypes.c_double),
                 ("narrow_heavy_ms", ctypes.c_double),
                 ("sort_axis", ctypes.c_int64), ("heavy_pairs", ctypes.c_int64),
-                ("heavy_reruns", ctypes.c_int64)]
+                ("heavy_reruns", ctypes.c_int64), ("sched_heavy_pairs", ctypes.c_int64),
+                ("batch_ms", ctypes.c_double)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("sweep_tile_group", ctypes.c_int32), ("pool_blocks_per_cu", ctypes.c_int32),
+                ("heavy_slots", ctypes.c_int32), ("heavy_cap_log2", ctypes.c_int32)]
 
 
 class Schedule(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("params", ctypes.c_void_p), ("norm", ctypes.c_void_p),
-                ("order", ctypes.c_void_p)]
+                ("order", ctypes.c_void_p), ("heavy_threshold", ctypes.c_float), ("max_heavy", ctypes.c_int32)]
+
+
+# Learned schedule defaults: predictions of log2(1 + n_enq) from which a pair starts in the wide stage, and
+# the most such pairs.
+HEAVY_THRESHOLD = 10.0
+MAX_HEAVY = 256
 
 
 _lib = None
@@ -99,6 +112,20 @@ def load_library(path=LIB_PATH):
     f32 = ctypes.c_float
     lib.ccd_adam_step.argtypes = [P, P, P, P, P, i64, f32, f32, f32, f32, P]
     lib.ccd_adam_step.restype = ctypes.c_int
+    lib.ccd_set_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
+    lib.ccd_set_tuning.restype = ctypes.c_int
+    lib.ccd_get_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
+    lib.ccd_get_tuning.restype = ctypes.c_int
+    lib.ccd_batch_create.argtypes = [P, i64, P, P, P, i64, i64, ctypes.POINTER(P)]
+    lib.ccd_batch_create.restype = ctypes.c_int
+    lib.ccd_batch_destroy.argtypes = [P]
+    lib.ccd_batch_destroy.restype = None
+    lib.ccd_batch_run.argtypes = [P, P, P, P, P, ctypes.c_double, i64, P, P, ctypes.POINTER(i64),
+                                  ctypes.POINTER(i64), P, P, P, P, ctypes.c_int, P]
+    lib.ccd_batch_run.restype = ctypes.c_int
+    lib.ccd_batch_autotune.argtypes = [P, P, P, P, P, ctypes.c_double, i64, P, P, P, P, P, ctypes.c_char_p,
+                                       ctypes.POINTER(Tuning), P]
+    lib.ccd_batch_autotune.restype = ctypes.c_int
     lib.ccd_get_stats.argtypes = [P, ctypes.POINTER(Stats)]
     lib.ccd_get_stats.restype = ctypes.c_int
     _lib = lib
@@ -153,6 +180,23 @@ class Context:
     def handle(self):
         return self._h
 
+    def set_tuning(self, tuning=None):
+        """Set launch-shape tuning from a dict (missing keys keep their current value); None restores defaults."""
+        lib = load_library()
+        if tuning is None:
+            _check(lib.ccd_set_tuning(self._h, None))
+            return
+        t = Tuning()
+        _check(lib.ccd_get_tuning(self._h, ctypes.byref(t)))
+        for k, v in dict(tuning).items():
+            setattr(t, k, int(v))
+        _check(lib.ccd_set_tuning(self._h, ctypes.byref(t)))
+
+    def get_tuning(self):
+        t = Tuning()
+        _check(load_library().ccd_get_tuning(self._h, ctypes.byref(t)))
+        return {k: getattr(t, k) for k, _ in Tuning._fields_}
+
     def stats(self):
         st = Stats()
         _check(load_library().ccd_get_stats(self._h, ctypes.byref(st)))
@@ -200,8 +244,9 @@ class Context:
                schedule=None):
         """Per-pair (hit uint8, toi float64, toi_min (1,) float64, n_enq int64 or None), VF pairs first.
 
-        schedule: None (plain: pairs in index order), ("learned", params, norm) or ("order", perm) --
-        the order in which pairs are searched; the results are the same for every schedule."""
+        schedule: None (plain: pairs in index order), ("learned", params, norm[, heavy_threshold, max_heavy])
+        or ("order", perm) -- where and in which order pairs are searched; the results are the same for every
+        schedule."""
         import torch
         lib = load_library()
         V0 = _dev(V0, torch.float64, 3)
@@ -286,6 +331,72 @@ class Context:
                                             float(lr), float(beta1), float(beta2), float(eps), _stream(stream)))
 
 
+class Batch:
+    """Several scenes in CSR layout through one broad + narrow pass (see ccd_batch_run).
+
+    v_off, e_off, f_off: S + 1 offsets each; V0/V1/E/F passed to run() are the concatenated scenes with
+    global vertex ids.  The batch owns its pair and result buffers (sized by vf_cap / ee_cap), so repeated
+    graph runs reuse one captured graph."""
+
+    def __init__(self, ctx, v_off, e_off, f_off, vf_cap, ee_cap):
+        import numpy as np
+        import torch
+        lib = load_library()
+        self.ctx = ctx
+        offs = [np.ascontiguousarray(np.asarray(o, dtype=np.int64)) for o in (v_off, e_off, f_off)]
+        self.n_scenes = len(offs[0]) - 1
+        if any(len(o) != self.n_scenes + 1 for o in offs):
+            raise ValueError("offset arrays must have the same length")
+        self.vf_cap, self.ee_cap = int(vf_cap), int(ee_cap)
+        h = ctypes.c_void_p()
+        _check(lib.ccd_batch_create(ctx.handle, self.n_scenes, offs[0].ctypes.data, offs[1].ctypes.data,
+                                    offs[2].ctypes.data, self.vf_cap, self.ee_cap, ctypes.byref(h)))
+        self._h = h
+        dev = torch.device("cuda", ctx.device)
+        cap = self.vf_cap + self.ee_cap
+        self.vf = torch.empty((self.vf_cap, 2), dtype=torch.int32, device=dev)
+        self.ee = torch.empty((self.ee_cap, 2), dtype=torch.int32, device=dev)
+        self.hit = torch.empty(cap, dtype=torch.uint8, device=dev)
+        self.toi = torch.empty(cap, dtype=torch.float64, device=dev)
+        self.n_enq = torch.empty(cap, dtype=torch.int64, device=dev)
+        self.toi_min = torch.empty(self.n_scenes, dtype=torch.float64, device=dev)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().ccd_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self, V0, V1, E, F, delta=1e-6, max_iter=10**6, use_graph=True, with_costs=False, stream=None):
+        """(vf, ee, hit, toi, toi_min, n_enq or None): views of the batch's buffers, valid until the next run."""
+        lib = load_library()
+        n_vf, n_ee = ctypes.c_int64(), ctypes.c_int64()
+        st = lib.ccd_batch_run(self._h, _ptr(V0), _ptr(V1), _ptr(E), _ptr(F), float(delta), int(max_iter),
+                               _ptr(self.vf), _ptr(self.ee), ctypes.byref(n_vf), ctypes.byref(n_ee), _ptr(self.hit),
+                               _ptr(self.toi), _ptr(self.toi_min), _ptr(self.n_enq) if with_costs else None,
+                               int(bool(use_graph)), _stream(stream))
+        self.n_vf, self.n_ee = n_vf.value, n_ee.value
+        _check(st)
+        n = self.n_vf + self.n_ee
+        return (self.vf[:self.n_vf], self.ee[:self.n_ee], self.hit[:n], self.toi[:n], self.toi_min,
+                self.n_enq[:n] if with_costs else None)
+
+    def autotune(self, V0, V1, E, F, delta=1e-6, max_iter=10**6, cache_path=None, stream=None):
+        """Time candidate tunings, set the best on the context and return it (dict)."""
+        lib = load_library()
+        t = Tuning()
+        _check(lib.ccd_batch_autotune(self._h, _ptr(V0), _ptr(V1), _ptr(E), _ptr(F), float(delta), int(max_iter),
+                                      _ptr(self.vf), _ptr(self.ee), _ptr(self.hit), _ptr(self.toi),
+                                      _ptr(self.toi_min), cache_path.encode() if cache_path else None,
+                                      ctypes.byref(t), _stream(stream)))
+        return {k: getattr(t, k) for k, _ in Tuning._fields_}
+
+
 def _f32(t, size):
     import torch
     t = torch.as_tensor(t)
@@ -309,13 +420,15 @@ def _schedule(schedule):
     import torch
     kind = schedule[0]
     if kind == "plain":
-        return Schedule(SCHED_PLAIN, None, None, None), ()
+        return Schedule(SCHED_PLAIN, None, None, None, 0.0, 0), ()
     if kind == "learned":
         params, norm = _f32(schedule[1], MODEL_PARAMS), _f32(schedule[2], 2 * NUM_FEATURES)
-        return Schedule(SCHED_LEARNED, params.data_ptr(), norm.data_ptr(), None), (params, norm)
+        thr = float(schedule[3]) if len(schedule) > 3 else HEAVY_THRESHOLD
+        mh = int(schedule[4]) if len(schedule) > 4 else MAX_HEAVY
+        return Schedule(SCHED_LEARNED, params.data_ptr(), norm.data_ptr(), None, thr, mh), (params, norm)
     if kind == "order":
         perm = _dev(schedule[1], torch.int32, 1).reshape(-1)
-        return Schedule(SCHED_ORDER, None, None, perm.data_ptr() if perm.numel() else None), (perm,)
+        return Schedule(SCHED_ORDER, None, None, perm.data_ptr() if perm.numel() else None, 0.0, 0), (perm,)
     raise ValueError(f"unknown schedule {kind!r}")
 
 

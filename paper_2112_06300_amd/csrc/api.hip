@@ -41,15 +41,17 @@ struct Pool {
     size_t bytes = 0;
 };
 
+// With a null base it only measures (the pointers it returns are offsets).
 struct Carver {
     char *p;
     size_t off = 0;
     explicit Carver(char *b) : p(b) {}
+    size_t bytes() const { return off + 256; }
     template <class T>
     T *take(size_t n)
     {
         off = (off + 255) & ~size_t(255);
-        T *r = reinterpret_cast<T *>(p + off);
+        T *r = reinterpret_cast<T *>(reinterpret_cast<uintptr_t>(p) + off);
         off += n * sizeof(T);
         return r;
     }
@@ -70,11 +72,31 @@ struct ccd_context {
     void *host = nullptr;  // pinned host staging for counters and flags
     hipEvent_t ev[8] = {};
     ccd_stats stats{};
-    int cus = 256;            // compute units of the device
-    int pool_blocks = 1024;   // resident 64-lane workgroups of the pool stage
+    int cus = 256;             // compute units of the device
+    int pool_per_cu_max = 4;   // resident 64-lane pool workgroups per CU
+    char arch[64] = "gfx950";
+    ccd_tuning tune{};
+    hipStream_t side = nullptr;  // second stream: the learned schedule's early wide stage
 };
 
 namespace {
+
+ccd_tuning default_tuning()
+{
+    ccd_tuning t;
+    t.sweep_tile_group = 16;
+    t.pool_blocks_per_cu = 0;
+    t.heavy_slots = 1024;
+    t.heavy_cap_log2 = 13;
+    return t;
+}
+
+int pool_blocks(const ccd_context *c)
+{
+    int per_cu = c->tune.pool_blocks_per_cu;
+    if (per_cu <= 0 || per_cu > c->pool_per_cu_max) per_cu = c->pool_per_cu_max;
+    return per_cu * c->cus;
+}
 
 ccd_status ensure(Pool &p, size_t need)
 {
@@ -94,13 +116,69 @@ ccd_status ensure(Pool &p, size_t need)
     return CCD_OK;
 }
 
+// Broad-phase workspace of nb boxes in S scenes.  Called once with a null
+// base to measure, then on the allocation.
+void broad_carve(Carver &cv, int64_t nb, int64_t S, int64_t nbl, BroadBuffers &B)
+{
+    const size_t n = (size_t)std::max<int64_t>(nb, 1);
+    const bool multi = S > 1;
+    B.nscenes = S;
+    B.off = nullptr;
+    B.bscene = multi ? cv.take<uint32_t>(n) : nullptr;
+    for (int a = 0; a < 3; a++) B.lo[a] = cv.take<float>(n);
+    for (int a = 0; a < 3; a++) B.hi[a] = cv.take<float>(n);
+    B.keyA = cv.take<uint32_t>(n); B.keyB = cv.take<uint32_t>(n);
+    B.valA = cv.take<uint32_t>(n); B.valB = cv.take<uint32_t>(n);
+    B.hist = cv.take<uint32_t>((size_t)768 * nbl);
+    B.bin_tot = cv.take<uint32_t>(768);
+    B.bin_base = cv.take<uint32_t>(768);
+    B.stats = cv.take<double>(6 * (size_t)S);
+    B.partial = cv.take<double>(8 * (size_t)box_blocks(nb));
+    B.partial_scene = cv.take<int32_t>((size_t)box_blocks(nb));
+    B.axis = cv.take<int32_t>((size_t)S);
+    B.khi = multi ? nullptr : cv.take<uint32_t>(n);
+    B.klo64 = multi ? cv.take<unsigned long long>(n) : nullptr;
+    B.khi64 = multi ? cv.take<unsigned long long>(n) : nullptr;
+    B.lob = cv.take<float>(n); B.hib = cv.take<float>(n); B.loc = cv.take<float>(n); B.hic = cv.take<float>(n);
+    B.pid = cv.take<int32_t>(n);
+    B.vtx = cv.take<int32_t>(3 * n);
+    B.counts = cv.take<unsigned long long>(2);
+    B.flags = cv.take<uint32_t>(1);
+}
+
+// Narrow-phase workspace of npairs pairs.
+void narrow_carve(Carver &cv, int64_t npairs, NarrowBuffers &B)
+{
+    const size_t m = (size_t)std::max<int64_t>(npairs, 1);
+    const int64_t hnode_cap = 4 * (int64_t)m + 65536;
+    B.ids4 = cv.take<int4>(m);
+    B.eps = cv.take<double>(3 * m);
+    B.m = cv.take<uint32_t>(m);
+    B.heavy = cv.take<HeavyEntry>(m);
+    B.hnodes = cv.take<unsigned long long>((size_t)hnode_cap);
+    B.hnode_cap = hnode_cap;
+    B.counters = cv.take<unsigned int>(16);
+    B.overflow_list[0] = cv.take<int32_t>(m);
+    B.overflow_list[1] = cv.take<int32_t>(m);
+    B.flags = cv.take<uint32_t>(1);
+    B.toi_min = nullptr;
+    B.scratch = nullptr;
+}
+
+bool valid_tuning(const ccd_tuning &t)
+{
+    return t.sweep_tile_group >= 1 && t.sweep_tile_group <= 1024 && t.pool_blocks_per_cu >= 0 &&
+           t.pool_blocks_per_cu <= 64 && t.heavy_slots >= 1 && t.heavy_slots <= 65536 && t.heavy_cap_log2 >= 8 &&
+           t.heavy_cap_log2 <= 24;
+}
+
 }  // namespace
 
 extern "C" {
 
 const char *ccd_last_error(void) { return g_err.c_str(); }
 
-const char *ccd_version(void) { return "mi355x-ccd 0.1 (gfx950)"; }
+const char *ccd_version(void) { return "mi355x-ccd 0.2 (gfx950)"; }
 
 ccd_status ccd_create(int device, ccd_context **out)
 {
@@ -112,17 +190,26 @@ ccd_status ccd_create(int device, ccd_context **out)
     HIP_TRY(hipSetDevice(device));
     ccd_context *c = new ccd_context();
     c->device = device;
+    c->tune = default_tuning();
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0) {
         c->cus = cus;
     }
-    {
-        const int per_cu = pool_blocks_per_cu();
-        c->pool_blocks = per_cu * c->cus;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+        std::snprintf(c->arch, sizeof c->arch, "%s", prop.gcnArchName);
+        for (char *q = c->arch; *q; q++)
+            if (*q == ':' || *q == ' ') { *q = 0; break; }
     }
+    c->pool_per_cu_max = pool_blocks_per_cu();
     if (hipHostMalloc(&c->host, 4096, hipHostMallocDefault) != hipSuccess) {
         delete c;
         return fail(CCD_ERR_OOM, "could not allocate pinned host staging");
+    }
+    if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess) {
+        c->side = nullptr;
+        ccd_destroy(c);
+        return fail(CCD_ERR_DEVICE, "could not create a stream");
     }
     for (auto &e : c->ev) {
         if (hipEventCreate(&e) != hipSuccess) {
@@ -144,7 +231,25 @@ void ccd_destroy(ccd_context *c)
     for (auto &e : c->ev)
         if (e) hipEventDestroy(e);
     if (c->host) hipHostFree(c->host);
+    if (c->side) hipStreamDestroy(c->side);
     delete c;
+}
+
+ccd_status ccd_set_tuning(ccd_context *c, const ccd_tuning *t)
+{
+    if (!c) return fail(CCD_ERR_INVALID_ARG, "NULL context");
+    const ccd_tuning v = t ? *t : default_tuning();
+    if (!valid_tuning(v)) return fail(CCD_ERR_INVALID_ARG, "tuning parameter out of range");
+    c->tune = v;
+    g_err.clear();
+    return CCD_OK;
+}
+
+ccd_status ccd_get_tuning(ccd_context *c, ccd_tuning *t)
+{
+    if (!c || !t) return fail(CCD_ERR_INVALID_ARG, "NULL argument");
+    *t = c->tune;
+    return CCD_OK;
 }
 
 ccd_status ccd_get_stats(ccd_context *c, ccd_stats *out)
@@ -169,28 +274,13 @@ ccd_status ccd_broad(ccd_context *c, const double *V0, const double *V1, int64_t
     hipStream_t s = (hipStream_t)stream;
     const int64_t nb = nv + ne + nf;
     const int64_t nbl = sort_blocks(nb);
-    const size_t n = (size_t)std::max<int64_t>(nb, 1);
-    const size_t need = aligned_total({6 * n * 4, 4 * n * 4, (size_t)768 * nbl * 4, 768 * 4, 768 * 4, 6 * 8, 4,
-                                       n * 4, 4 * n * 4, n * 4, 3 * n * 4, 2 * 8, 4});
-    ccd_status st = ensure(c->broad, need);
+    BroadBuffers B;
+    Carver measure(nullptr);
+    broad_carve(measure, nb, 1, nbl, B);
+    ccd_status st = ensure(c->broad, measure.bytes());
     if (st != CCD_OK) return st;
     Carver cv(c->broad.base);
-    BroadBuffers B;
-    for (int a = 0; a < 3; a++) B.lo[a] = cv.take<float>(n);
-    for (int a = 0; a < 3; a++) B.hi[a] = cv.take<float>(n);
-    B.keyA = cv.take<uint32_t>(n); B.keyB = cv.take<uint32_t>(n);
-    B.valA = cv.take<uint32_t>(n); B.valB = cv.take<uint32_t>(n);
-    B.hist = cv.take<uint32_t>((size_t)768 * nbl);
-    B.bin_tot = cv.take<uint32_t>(768);
-    B.bin_base = cv.take<uint32_t>(768);
-    B.stats = cv.take<double>(6);
-    B.axis = cv.take<int32_t>(1);
-    B.khi = cv.take<uint32_t>(n);
-    B.lob = cv.take<float>(n); B.hib = cv.take<float>(n); B.loc = cv.take<float>(n); B.hic = cv.take<float>(n);
-    B.pid = cv.take<int32_t>(n);
-    B.vtx = cv.take<int32_t>(3 * n);
-    B.counts = cv.take<unsigned long long>(2);
-    B.flags = cv.take<uint32_t>(1);
+    broad_carve(cv, nb, 1, nbl, B);
 
     HIP_TRY(hipEventRecord(c->ev[0], s));
     launch_broad_boxes(V0, V1, nv, E, ne, F, nf, B, s);
@@ -199,7 +289,7 @@ ccd_status ccd_broad(ccd_context *c, const double *V0, const double *V1, int64_t
     HIP_TRY(hipEventRecord(c->ev[3], s));
     launch_broad_gather(E, F, nv, ne, nf, B, s);
     HIP_TRY(hipEventRecord(c->ev[4], s));
-    launch_broad_sweep(nv, ne, nf, vf, vf_cap, ee, ee_cap, B, s);
+    launch_broad_sweep(nv, ne, nf, vf, vf_cap, ee, ee_cap, B, c->tune.sweep_tile_group, s);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(c->ev[1], s));
     unsigned long long *h = (unsigned long long *)c->host;
@@ -248,25 +338,12 @@ ccd_status narrow_setup(ccd_context *c, const double *V0, const double *V1, int6
     if ((nv && (!V0 || !V1)) || (ne && !E) || (nf && !F) || (n_vf && !vf) || (n_ee && !ee))
         return fail(CCD_ERR_INVALID_ARG, "NULL pointer with nonzero size");
     HIP_TRY(hipSetDevice(c->device));
-    const size_t m = (size_t)std::max<int64_t>(n, 1);
-    const int64_t hnode_cap = 4 * (int64_t)m + 65536;
-    const size_t need = aligned_total({m * 16, m * 24, m * 4, m * sizeof(HeavyEntry), (size_t)hnode_cap * 8, 16 * 4,
-                                       m * 4, m * 4, 4});
-    ccd_status st = ensure(c->narrow, need);
+    Carver measure(nullptr);
+    narrow_carve(measure, n, B);
+    ccd_status st = ensure(c->narrow, measure.bytes());
     if (st != CCD_OK) return st;
     Carver cv(c->narrow.base);
-    B.ids4 = cv.take<int4>(m);
-    B.eps = cv.take<double>(3 * m);
-    B.m = cv.take<uint32_t>(m);
-    B.heavy = cv.take<HeavyEntry>(m);
-    B.hnodes = cv.take<unsigned long long>((size_t)hnode_cap);
-    B.hnode_cap = hnode_cap;
-    B.counters = cv.take<unsigned int>(16);
-    B.overflow_list[0] = cv.take<int32_t>(m);
-    B.overflow_list[1] = cv.take<int32_t>(m);
-    B.flags = cv.take<uint32_t>(1);
-    B.toi_min = nullptr;
-    B.scratch = nullptr;
+    narrow_carve(cv, n, B);
     return CCD_OK;
 }
 
@@ -282,14 +359,15 @@ ccd_status sched_setup(ccd_context *c, int64_t n, SchedBuffers &S)
 {
     const size_t m = (size_t)std::max<int64_t>(n, 1);
     const size_t words = (m + 31) / 32;
-    ccd_status st = ensure(c->sched, aligned_total({m * kNumFeatures * 4, m * 4, m * 4, words * 4, 3 * 256 * 4, 4}));
+    ccd_status st = ensure(c->sched, aligned_total({m * kNumFeatures * 4, m * 4, m * 4, words * 4,
+                                                   (size_t)kSchedScratch * 4, 4}));
     if (st != CCD_OK) return st;
     Carver cv(c->sched.base);
     S.feat = cv.take<float>(m * kNumFeatures);
     S.cost = cv.take<float>(m);
     S.order = cv.take<int32_t>(m);
     S.bits = cv.take<uint32_t>(words);
-    S.bins = cv.take<uint32_t>(3 * 256);
+    S.bins = cv.take<uint32_t>(kSchedScratch);
     S.flag = cv.take<uint32_t>(1);
     return CCD_OK;
 }
@@ -308,6 +386,9 @@ ccd_status narrow_impl(ccd_context *c, const double *V0, const double *V1, int64
         return fail(CCD_ERR_INVALID_ARG, "unknown schedule kind %d", kind);
     if (kind == CCD_SCHED_LEARNED && (!sched->params || !sched->norm))
         return fail(CCD_ERR_INVALID_ARG, "learned schedule without parameters or normalization");
+    if (kind == CCD_SCHED_LEARNED &&
+        (sched->max_heavy < 0 || sched->max_heavy > 4096 || !std::isfinite(sched->heavy_threshold)))
+        return fail(CCD_ERR_INVALID_ARG, "learned schedule: max_heavy outside [0, 4096] or non-finite threshold");
     if (kind == CCD_SCHED_ORDER && n > 0 && !sched->order)
         return fail(CCD_ERR_INVALID_ARG, "order schedule without an order");
     NarrowBuffers B;
@@ -315,6 +396,7 @@ ccd_status narrow_impl(ccd_context *c, const double *V0, const double *V1, int64
     if (st != CCD_OK) return st;
     hipStream_t s = (hipStream_t)stream;
     B.toi_min = toi_min;
+    const PairCounts pc{n_vf, n_ee, nullptr};
     SchedBuffers S{};
     if (kind != CCD_SCHED_PLAIN) {
         st = sched_setup(c, n, S);
@@ -332,31 +414,49 @@ ccd_status narrow_impl(ccd_context *c, const double *V0, const double *V1, int64
         order = sched->order;
     }
 
-    // wide-stage frontier buffers: start with 1024 workgroups x 8192 nodes
-    int nslots = 1024;
-    int64_t cap = 8192;
-    st = ensure(c->scratch, (size_t)nslots * 6 * cap * 8);
+    // wide-stage frontier buffers (tuned: workgroups x nodes per buffer), and
+    // the early wide stage's of the learned schedule after them
+    int nslots = c->tune.heavy_slots;
+    int64_t cap = (int64_t)1 << c->tune.heavy_cap_log2;
+    const bool learned = kind == CCD_SCHED_LEARNED;
+    const int early_slots = learned ? std::max(0, std::min(sched->max_heavy, 4096)) : 0;
+    st = ensure(c->scratch, (size_t)(nslots + early_slots) * 6 * cap * 8);
     if (st != CCD_OK) return st;
     B.scratch = (unsigned long long *)c->scratch.base;
 
     long long *nenq = (long long *)n_enq;
+    const uint32_t *order_n = nullptr;
     HIP_TRY(hipEventRecord(c->ev[0], s));
-    launch_narrow_prep(V0, V1, nv, E, ne, F, nf, vf, n_vf, ee, n_ee, delta, B, s);
-    HIP_TRY(hipEventRecord(c->ev[4], s));
-    if (kind == CCD_SCHED_LEARNED) {
-        launch_narrow_features(V0, V1, n_vf, n_ee, delta, B, S.feat, s);
-        launch_mlp_predict(sched->params, sched->norm, S.feat, n, S.cost, s);
-        launch_cost_order(S.cost, n, S.order, S.bins, s);
+    if (learned) {
+        // prep, features, prediction and cost histogram in one pass; then the ordering
+        launch_narrow_prep_sched(V0, V1, nv, E, ne, F, nf, vf, ee, pc, delta, B, sched->params, sched->norm, S.cost,
+                                 S.bins, s);
+        HIP_TRY(hipEventRecord(c->ev[4], s));
+        launch_cost_schedule(S.cost, n, sched->heavy_threshold, early_slots, S.order, B.heavy, B.counters, S.bins,
+                             true, s);
         order = S.order;
+        order_n = S.bins + 2 * 256 + 1;
+    } else {
+        launch_narrow_prep(V0, V1, nv, E, ne, F, nf, vf, ee, pc, delta, B, s);
+        HIP_TRY(hipEventRecord(c->ev[4], s));
     }
     HIP_TRY(hipEventRecord(c->ev[5], s));
-    launch_narrow_pool(V0, V1, n_vf, n_ee, delta, (long long)max_iter, hit, toi, nenq, B, c->pool_blocks, order, s);
+    if (learned && early_slots > 0) {
+        // pairs predicted to outgrow the pool start in the wide stage now, beside the pool
+        HIP_TRY(hipStreamWaitEvent(c->side, c->ev[5], 0));
+        launch_narrow_heavy_early(V0, V1, pc, delta, (long long)max_iter, hit, toi, nenq, B,
+                                  B.scratch + (size_t)nslots * 6 * cap, early_slots, cap, c->side);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipEventRecord(c->ev[6], c->side));
+    }
+    launch_narrow_pool(V0, V1, pc, delta, (long long)max_iter, hit, toi, nenq, B, pool_blocks(c), order, order_n, s);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(c->ev[2], s));
-    launch_narrow_heavy(V0, V1, n_vf, delta, (long long)max_iter, hit, toi, nenq, B, nslots, cap, 0, s);
+    launch_narrow_heavy(V0, V1, pc, delta, (long long)max_iter, hit, toi, nenq, B, nslots, cap, 0, s);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(c->ev[3], s));
-    launch_toi_min(toi, n, toi_min, s);
+    if (learned && early_slots > 0) HIP_TRY(hipStreamWaitEvent(s, c->ev[6], 0));
+    launch_toi_min(toi, pc, toi_min, s);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(c->ev[1], s));
     unsigned int *h = (unsigned int *)c->host;
@@ -371,10 +471,12 @@ ccd_status narrow_impl(ccd_context *c, const double *V0, const double *V1, int64
     HIP_TRY(hipEventElapsedTime(&ms_heavy, c->ev[2], c->ev[3]));
     c->stats.narrow_ms = ms;
     c->stats.narrow_prep_ms = ms_prep;
+    // learned: the fused prep pass counts as schedule time beyond a plain prep
     c->stats.narrow_sched_ms = kind == CCD_SCHED_LEARNED ? ms_sched : 0.0;
     c->stats.narrow_pool_ms = ms_pool;
     c->stats.narrow_heavy_ms = ms_heavy;
-    c->stats.heavy_pairs = h[0];
+    c->stats.sched_heavy_pairs = learned ? h[12] : 0;
+    c->stats.heavy_pairs = h[0] - (learned ? h[12] : 0u);
     c->stats.heavy_reruns = 0;
     uint32_t flags = h[16];
     if (flags & FLAG_BAD_INDEX) return fail(CCD_ERR_INVALID_ARG, "pair, edge or face index out of range");
@@ -397,9 +499,9 @@ ccd_status narrow_impl(ccd_context *c, const double *V0, const double *V1, int64
         if (st != CCD_OK) return st;
         B.scratch = (unsigned long long *)c->scratch.base;
         HIP_TRY(hipEventRecord(c->ev[0], s));
-        launch_narrow_heavy(V0, V1, n_vf, delta, (long long)max_iter, hit, toi, nenq, B, nslots, cap, round, s);
+        launch_narrow_heavy(V0, V1, pc, delta, (long long)max_iter, hit, toi, nenq, B, nslots, cap, round, s);
         HIP_TRY(hipGetLastError());
-        launch_toi_min(toi, n, toi_min, s);
+        launch_toi_min(toi, pc, toi_min, s);
         HIP_TRY(hipGetLastError());
         HIP_TRY(hipEventRecord(c->ev[1], s));
         HIP_TRY(hipMemcpyAsync(h, B.counters, 16 * 4, hipMemcpyDeviceToHost, s));
@@ -457,8 +559,9 @@ ccd_status ccd_features(ccd_context *c, const double *V0, const double *V1, int6
     const int64_t n = n_vf + n_ee;
     if (n > 0 && !feat) return fail(CCD_ERR_INVALID_ARG, "NULL feat with nonzero size");
     hipStream_t s = (hipStream_t)stream;
-    launch_narrow_prep(V0, V1, nv, E, ne, F, nf, vf, n_vf, ee, n_ee, delta, B, s);
-    launch_narrow_features(V0, V1, n_vf, n_ee, delta, B, feat, s);
+    const PairCounts pc{n_vf, n_ee, nullptr};
+    launch_narrow_prep(V0, V1, nv, E, ne, F, nf, vf, ee, pc, delta, B, s);
+    launch_narrow_features(V0, V1, pc, delta, B, feat, s);
     HIP_TRY(hipGetLastError());
     unsigned int *h = (unsigned int *)c->host;
     HIP_TRY(hipMemcpyAsync(h, B.flags, 4, hipMemcpyDeviceToHost, s));
@@ -504,6 +607,412 @@ ccd_status ccd_adam_step(ccd_context *c, float *params, const float *grad, float
     HIP_TRY(hipSetDevice(c->device));
     launch_adam(params, grad, m, v, step, lr, beta1, beta2, eps, (hipStream_t)stream);
     HIP_TRY(hipGetLastError());
+    g_err.clear();
+    return CCD_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batches of scenes in CSR layout: one pass over all scenes, optionally as a
+// captured graph.
+// ---------------------------------------------------------------------------
+struct ccd_batch {
+    ccd_context *ctx = nullptr;
+    int64_t S = 0, nv = 0, ne = 0, nf = 0, vf_cap = 0, ee_cap = 0, nbl = 1;
+    Pool mem;                 // offsets, broad and narrow workspaces
+    Pool frontier;            // wide-stage frontier buffers
+    int64_t *off = nullptr;   // device: vertex, edge and face offsets, S + 1 each
+    BroadBuffers B{};
+    NarrowBuffers N{};
+    int heavy_slots = 0;
+    int64_t heavy_cap = 0;
+    hipStream_t cs = nullptr; // stream the batch runs (and is captured) on
+    hipEvent_t ev_in = nullptr, ev_out = nullptr, t0 = nullptr, t1 = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    struct Key {
+        const void *p[10];
+        double delta;
+        long long max_iter;
+        ccd_tuning tune;
+    } key{};
+    bool have_graph = false;
+};
+
+namespace {
+
+struct BatchArgs {
+    const double *V0, *V1;
+    const int32_t *E, *F;
+    double delta;
+    long long max_iter;
+    int32_t *vf, *ee;
+    uint8_t *hit;
+    double *toi, *toi_min;
+    long long *n_enq;
+};
+
+void drop_graph(ccd_batch *b)
+{
+    if (b->exec) hipGraphExecDestroy(b->exec);
+    if (b->graph) hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->have_graph = false;
+}
+
+// Frontier buffers of the wide stage, as the context's tuning asks.
+ccd_status batch_frontier(ccd_batch *b)
+{
+    const ccd_tuning &t = b->ctx->tune;
+    const int64_t cap = (int64_t)1 << t.heavy_cap_log2;
+    if (b->heavy_slots == t.heavy_slots && b->heavy_cap == cap) return CCD_OK;
+    drop_graph(b);
+    ccd_status st = ensure(b->frontier, (size_t)t.heavy_slots * 6 * (size_t)cap * 8);
+    if (st != CCD_OK) return st;
+    b->heavy_slots = t.heavy_slots;
+    b->heavy_cap = cap;
+    b->N.scratch = (unsigned long long *)b->frontier.base;
+    return CCD_OK;
+}
+
+// Every kernel of one batch pass, in stream order; no host synchronization and
+// no memset, so the sequence can be captured into a graph.
+void batch_enqueue(ccd_batch *b, const BatchArgs &a, hipStream_t s)
+{
+    const ccd_context *c = b->ctx;
+    launch_broad_boxes(a.V0, a.V1, b->nv, a.E, b->ne, a.F, b->nf, b->B, s);
+    launch_broad_sort(b->nv, b->ne, b->nf, b->B, b->nbl, s);
+    launch_broad_gather(a.E, a.F, b->nv, b->ne, b->nf, b->B, s);
+    launch_broad_sweep(b->nv, b->ne, b->nf, a.vf, b->vf_cap, a.ee, b->ee_cap, b->B, c->tune.sweep_tile_group, s);
+    const PairCounts pc{b->vf_cap, b->ee_cap, b->B.counts};
+    launch_narrow_prep(a.V0, a.V1, b->nv, a.E, b->ne, a.F, b->nf, a.vf, a.ee, pc, a.delta, b->N, s);
+    launch_narrow_pool(a.V0, a.V1, pc, a.delta, a.max_iter, a.hit, a.toi, a.n_enq, b->N, pool_blocks(c), nullptr,
+                       nullptr, s);
+    launch_narrow_heavy(a.V0, a.V1, pc, a.delta, a.max_iter, a.hit, a.toi, a.n_enq, b->N, b->heavy_slots,
+                        b->heavy_cap, 0, s);
+    launch_scene_min(a.toi, pc, a.vf, a.ee, b->off, b->off + (b->S + 1), b->S, a.toi_min, s);
+}
+
+ccd_batch::Key batch_key(const ccd_batch *b, const BatchArgs &a)
+{
+    ccd_batch::Key k{};
+    const void *p[10] = {a.V0, a.V1, a.E, a.F, a.vf, a.ee, a.hit, a.toi, a.toi_min, a.n_enq};
+    for (int i = 0; i < 10; i++) k.p[i] = p[i];
+    k.delta = a.delta;
+    k.max_iter = a.max_iter;
+    k.tune = b->ctx->tune;
+    return k;
+}
+
+bool same_key(const ccd_batch::Key &x, const ccd_batch::Key &y) { return std::memcmp(&x, &y, sizeof x) == 0; }
+
+// One batch pass on b->cs (graph or eager), then the host checks: counts,
+// flags and the rare wide-stage re-runs.
+ccd_status batch_pass(ccd_batch *b, const BatchArgs &a, bool use_graph, int64_t *n_vf, int64_t *n_ee, float *ms)
+{
+    ccd_context *c = b->ctx;
+    ccd_status st = batch_frontier(b);
+    if (st != CCD_OK) return st;
+    hipStream_t s = b->cs;
+    if (use_graph) {
+        const ccd_batch::Key k = batch_key(b, a);
+        if (!b->have_graph || !same_key(k, b->key)) {
+            drop_graph(b);
+            HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            batch_enqueue(b, a, s);
+            const hipError_t e = hipStreamEndCapture(s, &b->graph);
+            if (e != hipSuccess) {
+                b->graph = nullptr;
+                return fail(CCD_ERR_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
+            }
+            HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+            b->key = k;
+            b->have_graph = true;
+        }
+        HIP_TRY(hipEventRecord(b->t0, s));
+        HIP_TRY(hipGraphLaunch(b->exec, s));
+    } else {
+        HIP_TRY(hipEventRecord(b->t0, s));
+        batch_enqueue(b, a, s);
+    }
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipEventRecord(b->t1, s));
+    unsigned long long *h = (unsigned long long *)c->host;
+    HIP_TRY(hipMemcpyAsync(h, b->B.counts, 16, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(h + 2, b->B.flags, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(h + 3, b->N.flags, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(h + 4, b->N.counters, 16 * 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(hipEventElapsedTime(ms, b->t0, b->t1));
+    *n_vf = (int64_t)h[0];
+    *n_ee = (int64_t)h[1];
+    const uint32_t bflags = (uint32_t)h[2], nflags = (uint32_t)h[3];
+    const unsigned int *ctr = (const unsigned int *)(h + 4);
+    c->stats.heavy_pairs = ctr[0];
+    c->stats.heavy_reruns = 0;
+    if (bflags & FLAG_BAD_INDEX)
+        return fail(CCD_ERR_INVALID_ARG, "edge or face vertex id out of range, or outside its scene");
+    if ((bflags | nflags) & FLAG_NONFINITE)
+        return fail(CCD_ERR_NONFINITE, "non-finite or too large (> 2^960) coordinate");
+    if (nflags & FLAG_BAD_INDEX) return fail(CCD_ERR_INVALID_ARG, "pair index out of range");
+    if (*n_vf > b->vf_cap || *n_ee > b->ee_cap)
+        return fail(CCD_ERR_CAPACITY, "pair capacity too small: need %lld VF and %lld EE pairs", (long long)*n_vf,
+                    (long long)*n_ee);
+    // frontiers that outgrew their buffer: re-run those pairs eagerly with larger buffers
+    unsigned int overflowed = ctr[2];
+    if (overflowed > 0) {
+        const PairCounts pc{*n_vf, *n_ee, nullptr};
+        Pool big;
+        int64_t cap = b->heavy_cap;
+        int round = 0;
+        NarrowBuffers N = b->N;
+        while (overflowed > 0) {
+            round++;
+            c->stats.heavy_reruns += overflowed;
+            cap *= 8;
+            size_t free_b = 0, total_b = 0;
+            HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+            const size_t per_slot = (size_t)6 * cap * 8;
+            if (per_slot > free_b / 2 || round > 12) {
+                if (big.base) hipFree(big.base);
+                return fail(CCD_ERR_OOM, "interval frontier of %u pairs exceeds device memory", overflowed);
+            }
+            const int nslots = (int)std::min<size_t>({(size_t)1024, (free_b / 2) / per_slot, (size_t)overflowed});
+            st = ensure(big, (size_t)nslots * per_slot);
+            if (st != CCD_OK) return st;
+            N.scratch = (unsigned long long *)big.base;
+            launch_narrow_heavy(a.V0, a.V1, pc, a.delta, a.max_iter, a.hit, a.toi, a.n_enq, N, nslots, cap, round,
+                                s);
+            HIP_TRY(hipGetLastError());
+            unsigned int *hc = (unsigned int *)c->host;
+            HIP_TRY(hipMemcpyAsync(hc, N.counters, 16 * 4, hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            overflowed = hc[2 + (round & 1)];
+        }
+        if (big.base) hipFree(big.base);
+        launch_scene_min(a.toi, pc, a.vf, a.ee, b->off, b->off + (b->S + 1), b->S, a.toi_min, s);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    return CCD_OK;
+}
+
+ccd_status check_batch_args(ccd_batch *b, const BatchArgs &a, const int64_t *n_vf, const int64_t *n_ee)
+{
+    if (!b || !n_vf || !n_ee) return fail(CCD_ERR_INVALID_ARG, "NULL batch or count pointer");
+    if (!(a.delta > 0.0) || !std::isfinite(a.delta)) return fail(CCD_ERR_INVALID_ARG, "delta must be finite and > 0");
+    if (a.max_iter < 1) return fail(CCD_ERR_INVALID_ARG, "max_iter must be >= 1");
+    if ((b->nv && (!a.V0 || !a.V1)) || (b->ne && !a.E) || (b->nf && !a.F) || (b->vf_cap && !a.vf) ||
+        (b->ee_cap && !a.ee) || (b->vf_cap + b->ee_cap > 0 && (!a.hit || !a.toi)) || (b->S && !a.toi_min))
+        return fail(CCD_ERR_INVALID_ARG, "NULL pointer with nonzero size");
+    return CCD_OK;
+}
+
+// Autotuner cache: one line per workload signature, "signature: g p s c".
+bool cache_lookup(const char *path, const char *sig, ccd_tuning *t)
+{
+    if (!path) return false;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return false;
+    char line[512];
+    bool found = false;
+    const size_t n = std::strlen(sig);
+    while (std::fgets(line, sizeof line, f)) {
+        if (std::strncmp(line, sig, n) == 0 && line[n] == ':') {
+            ccd_tuning v;
+            if (std::sscanf(line + n + 1, "%d %d %d %d", &v.sweep_tile_group, &v.pool_blocks_per_cu, &v.heavy_slots,
+                            &v.heavy_cap_log2) == 4 &&
+                valid_tuning(v)) {
+                *t = v;
+                found = true;  // the last matching line wins
+            }
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+void cache_store(const char *path, const char *sig, const ccd_tuning &t)
+{
+    if (!path) return;
+    FILE *f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%s: %d %d %d %d\n", sig, t.sweep_tile_group, t.pool_blocks_per_cu, t.heavy_slots,
+                 t.heavy_cap_log2);
+    std::fclose(f);
+}
+
+int log2_bucket(int64_t x)
+{
+    int b = 0;
+    while (x > 1) { x >>= 1; b++; }
+    return b;
+}
+
+}  // namespace
+
+extern "C" {
+
+ccd_status ccd_batch_create(ccd_context *c, int64_t n_scenes, const int64_t *v_off, const int64_t *e_off,
+                            const int64_t *f_off, int64_t vf_cap, int64_t ee_cap, ccd_batch **out)
+{
+    if (!c || !out) return fail(CCD_ERR_INVALID_ARG, "NULL context or out");
+    *out = nullptr;
+    if (n_scenes < 1 || n_scenes > 65536) return fail(CCD_ERR_INVALID_ARG, "n_scenes must be in [1, 65536]");
+    if (!v_off || !e_off || !f_off) return fail(CCD_ERR_INVALID_ARG, "NULL offsets");
+    if (vf_cap < 0 || ee_cap < 0 || vf_cap + ee_cap > INT32_MAX) return fail(CCD_ERR_INVALID_ARG, "bad pair capacity");
+    const int64_t *offs[3] = {v_off, e_off, f_off};
+    for (int g = 0; g < 3; g++) {
+        if (offs[g][0] != 0) return fail(CCD_ERR_INVALID_ARG, "offsets must start at 0");
+        for (int64_t i = 0; i < n_scenes; i++)
+            if (offs[g][i + 1] < offs[g][i]) return fail(CCD_ERR_INVALID_ARG, "offsets must not decrease");
+    }
+    const int64_t nv = v_off[n_scenes], ne = e_off[n_scenes], nf = f_off[n_scenes];
+    if (nv > INT32_MAX || ne > INT32_MAX || nf > INT32_MAX || nv + ne + nf > (int64_t)UINT32_MAX)
+        return fail(CCD_ERR_INVALID_ARG, "batch too large for 32-bit ids");
+    HIP_TRY(hipSetDevice(c->device));
+    ccd_batch *b = new ccd_batch();
+    b->ctx = c;
+    b->S = n_scenes;
+    b->nv = nv; b->ne = ne; b->nf = nf;
+    b->vf_cap = vf_cap; b->ee_cap = ee_cap;
+    b->nbl = sort_blocks(nv + ne + nf);
+    Carver measure(nullptr);
+    int64_t *offp = measure.take<int64_t>(3 * (size_t)(n_scenes + 1));
+    (void)offp;
+    broad_carve(measure, nv + ne + nf, n_scenes, b->nbl, b->B);
+    narrow_carve(measure, vf_cap + ee_cap, b->N);
+    ccd_status st = ensure(b->mem, measure.bytes());
+    if (st != CCD_OK) {
+        delete b;
+        return st;
+    }
+    Carver cv(b->mem.base);
+    b->off = cv.take<int64_t>(3 * (size_t)(n_scenes + 1));
+    broad_carve(cv, nv + ne + nf, n_scenes, b->nbl, b->B);
+    narrow_carve(cv, vf_cap + ee_cap, b->N);
+    b->B.off = b->off;
+    if (hipStreamCreateWithFlags(&b->cs, hipStreamNonBlocking) != hipSuccess || hipEventCreate(&b->ev_in) != hipSuccess ||
+        hipEventCreate(&b->ev_out) != hipSuccess || hipEventCreate(&b->t0) != hipSuccess ||
+        hipEventCreate(&b->t1) != hipSuccess) {
+        ccd_batch_destroy(b);
+        return fail(CCD_ERR_DEVICE, "could not create the batch stream or events");
+    }
+    for (int g = 0; g < 3; g++) {
+        if (hipMemcpy(b->off + g * (n_scenes + 1), offs[g], (size_t)(n_scenes + 1) * 8, hipMemcpyHostToDevice) !=
+            hipSuccess) {
+            ccd_batch_destroy(b);
+            return fail(CCD_ERR_DEVICE, "could not upload the scene offsets");
+        }
+    }
+    *out = b;
+    g_err.clear();
+    return CCD_OK;
+}
+
+void ccd_batch_destroy(ccd_batch *b)
+{
+    if (!b) return;
+    hipSetDevice(b->ctx->device);
+    if (b->cs) hipStreamSynchronize(b->cs);
+    drop_graph(b);
+    for (Pool *p : {&b->mem, &b->frontier})
+        if (p->base) hipFree(p->base);
+    for (hipEvent_t e : {b->ev_in, b->ev_out, b->t0, b->t1})
+        if (e) hipEventDestroy(e);
+    if (b->cs) hipStreamDestroy(b->cs);
+    delete b;
+}
+
+ccd_status ccd_batch_run(ccd_batch *b, const double *V0, const double *V1, const int32_t *E, const int32_t *F,
+                         double delta, int64_t max_iter, int32_t *vf, int32_t *ee, int64_t *n_vf, int64_t *n_ee,
+                         uint8_t *hit, double *toi, double *toi_min, int64_t *n_enq, int use_graph, void *stream)
+{
+    const BatchArgs a{V0, V1, E, F, delta, (long long)max_iter, vf, ee, hit, toi, toi_min, (long long *)n_enq};
+    ccd_status st = check_batch_args(b, a, n_vf, n_ee);
+    if (st != CCD_OK) return st;
+    HIP_TRY(hipSetDevice(b->ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    // order the batch stream after the caller's stream, and the caller's after the batch
+    HIP_TRY(hipEventRecord(b->ev_in, s));
+    HIP_TRY(hipStreamWaitEvent(b->cs, b->ev_in, 0));
+    float ms = 0.f;
+    st = batch_pass(b, a, use_graph != 0, n_vf, n_ee, &ms);
+    HIP_TRY(hipEventRecord(b->ev_out, b->cs));
+    HIP_TRY(hipStreamWaitEvent(s, b->ev_out, 0));
+    b->ctx->stats.batch_ms = ms;
+    if (st == CCD_OK) g_err.clear();
+    return st;
+}
+
+ccd_status ccd_batch_autotune(ccd_batch *b, const double *V0, const double *V1, const int32_t *E, const int32_t *F,
+                              double delta, int64_t max_iter, int32_t *vf, int32_t *ee, uint8_t *hit, double *toi,
+                              double *toi_min, const char *cache_path, ccd_tuning *chosen, void *stream)
+{
+    int64_t n_vf = 0, n_ee = 0;
+    const BatchArgs a{V0, V1, E, F, delta, (long long)max_iter, vf, ee, hit, toi, toi_min, nullptr};
+    ccd_status st = check_batch_args(b, a, &n_vf, &n_ee);
+    if (st != CCD_OK) return st;
+    ccd_context *c = b->ctx;
+    HIP_TRY(hipSetDevice(c->device));
+    HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+    float ms = 0.f;
+    st = batch_pass(b, a, false, &n_vf, &n_ee, &ms);
+    if (st != CCD_OK) return st;
+    char sig[256];
+    std::snprintf(sig, sizeof sig, "%s cu%d S%lld nb%d pairs%d", c->arch, c->cus, (long long)b->S,
+                  log2_bucket(b->nv + b->ne + b->nf), log2_bucket(n_vf + n_ee));
+    ccd_tuning best = c->tune;
+    if (cache_lookup(cache_path, sig, &best)) {
+        c->tune = best;
+        if (chosen) *chosen = best;
+        g_err.clear();
+        return CCD_OK;
+    }
+    // coordinate descent: each parameter in turn over its candidates, the others held
+    auto measure = [&](const ccd_tuning &t, float *out) -> ccd_status {
+        c->tune = t;
+        float v[3];
+        for (int r = 0; r < 4; r++) {
+            float m = 0.f;
+            ccd_status s2 = batch_pass(b, a, false, &n_vf, &n_ee, &m);
+            if (s2 != CCD_OK) return s2;
+            if (r > 0) v[r - 1] = m;
+        }
+        std::sort(v, v + 3);
+        *out = v[1];
+        return CCD_OK;
+    };
+    float best_ms = 0.f;
+    st = measure(best, &best_ms);
+    if (st != CCD_OK) return st;
+    const int groups[] = {1, 4, 16, 64};
+    const int slots[] = {256, 512, 1024, 2048};
+    for (int param = 0; param < 3; param++) {
+        const int ncand = param == 0 ? 4 : (param == 1 ? c->pool_per_cu_max : 4);
+        for (int i = 0; i < ncand; i++) {
+            ccd_tuning t = best;
+            if (param == 0) t.sweep_tile_group = groups[i];
+            else if (param == 1) t.pool_blocks_per_cu = i + 1;
+            else t.heavy_slots = slots[i];
+            if (std::memcmp(&t, &best, sizeof t) == 0) continue;
+            float m = 0.f;
+            st = measure(t, &m);
+            if (st != CCD_OK) {
+                c->tune = best;
+                return st;
+            }
+            if (m < best_ms) {
+                best_ms = m;
+                best = t;
+            }
+        }
+    }
+    c->tune = best;
+    cache_store(cache_path, sig, best);
+    if (chosen) *chosen = best;
     g_err.clear();
     return CCD_OK;
 }

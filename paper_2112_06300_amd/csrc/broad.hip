@@ -29,10 +29,10 @@ constexpr int kSortTile = kSortThreads * kSortRounds;  // 4096 keys per block
 constexpr int kBins = 3 * 256;                        // segment x digit
 constexpr int kTile = 64;
 
-__global__ void zero_kernel(double *stats, unsigned long long *counts, uint32_t *flags)
+__global__ void zero_kernel(double *stats, int64_t nstats, unsigned long long *counts, uint32_t *flags)
 {
-    int t = threadIdx.x;
-    if (t < 6) stats[t] = 0.0;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < nstats) stats[t] = 0.0;
     if (t < 2) counts[t] = 0ull;
     if (t == 0) *flags = 0u;
 }
@@ -43,30 +43,53 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
+// Scene of entry i of one segment: the last s with off[s] <= i (off has S + 1
+// ascending entries, off[0] = 0).
+__device__ __forceinline__ int scene_in(const int64_t *__restrict__ off, int64_t S, int64_t i)
+{
+    int64_t lo = 0, hi = S;  // off[lo] <= i < off[hi]
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (off[mid] <= i) lo = mid; else hi = mid;
+    }
+    return (int)lo;
+}
+
+// Boxes, scene ids and per-scene centre statistics.  With S > 1 the
+// primitives are S scenes in CSR layout (off = vertex, edge and face offsets,
+// S + 1 each) and an edge or face must use vertices of its own scene.
 __global__ __launch_bounds__(kBoxBlock) void box_kernel(
     const double *__restrict__ V0, const double *__restrict__ V1, int64_t nv,
     const int32_t *__restrict__ E, int64_t ne, const int32_t *__restrict__ F, int64_t nf,
-    float *lo0, float *lo1, float *lo2, float *hi0, float *hi1, float *hi2,
-    double *stats, uint32_t *flags)
+    const int64_t *__restrict__ off, int64_t S, float *lo0, float *lo1, float *lo2, float *hi0, float *hi1,
+    float *hi2, uint32_t *bscene, double *stats, double *partial, int32_t *partial_scene, uint32_t *flags)
 {
     const int64_t nb = nv + ne + nf;
     const int64_t i = (int64_t)blockIdx.x * kBoxBlock + threadIdx.x;
     double c[3] = {0.0, 0.0, 0.0};
-    if (i < nb) {
+    int sc = 0;
+    const bool in = i < nb;
+    if (in) {
         int32_t ids[3];
         int k;
         if (i < nv) {
             ids[0] = (int32_t)i; k = 1;
+            if (S > 1) sc = scene_in(off, S, i);
         } else if (i < nv + ne) {
             const int64_t e = i - nv;
             ids[0] = E[2 * e]; ids[1] = E[2 * e + 1]; k = 2;
+            if (S > 1) sc = scene_in(off + (S + 1), S, e);
         } else {
             const int64_t f = i - nv - ne;
             ids[0] = F[3 * f]; ids[1] = F[3 * f + 1]; ids[2] = F[3 * f + 2]; k = 3;
+            if (S > 1) sc = scene_in(off + 2 * (S + 1), S, f);
         }
+        int64_t vlo = 0, vhi = nv;
+        if (S > 1) { vlo = off[sc]; vhi = off[sc + 1]; }
         bool ok = true;
-        for (int j = 0; j < k; j++) ok = ok && ids[j] >= 0 && (int64_t)ids[j] < nv;
+        for (int j = 0; j < k; j++) ok = ok && (int64_t)ids[j] >= vlo && (int64_t)ids[j] < vhi;
         float *lo[3] = {lo0, lo1, lo2}, *hi[3] = {hi0, hi1, hi2};
+        if (bscene) bscene[i] = (uint32_t)sc;
         if (!ok) {
             atomicOr(flags, FLAG_BAD_INDEX);
             for (int a = 0; a < 3; a++) { lo[a][i] = 0.0f; hi[a][i] = 0.0f; }
@@ -93,19 +116,35 @@ __global__ __launch_bounds__(kBoxBlock) void box_kernel(
             }
         }
     }
-    // centre statistics for the sweep-axis choice (Alg. 2: axis of largest variance)
+    // centre statistics of each scene for its sweep-axis choice (Alg. 2: axis of
+    // largest variance).  A block whose boxes all belong to one scene leaves its
+    // sums in `partial` (reduced by axis_kernel); the few blocks that straddle
+    // a scene boundary add each lane's values to the scene's totals directly.
     __shared__ double red[kBoxBlock / 64][6];
-    double v[6] = {c[0], c[1], c[2], c[0] * c[0], c[1] * c[1], c[2] * c[2]};
+    __shared__ int s_sc[kBoxBlock / 64];
+    const double v[6] = {c[0], c[1], c[2], c[0] * c[0], c[1] * c[1], c[2] * c[2]};
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int sc0 = __shfl(sc, 0);
+    const bool wave_uniform = __ballot(in && sc != sc0) == 0ull;
+    if (lane == 0) s_sc[wave] = wave_uniform ? sc0 : -1;
     for (int q = 0; q < 6; q++) {
-        double s = wave_sum(v[q]);
-        if (lane == 0) red[wave][q] = s;
+        const double t = wave_sum(v[q]);
+        if (lane == 0) red[wave][q] = t;
     }
     __syncthreads();
-    if (threadIdx.x < 6) {
-        double s = 0.0;
-        for (int w = 0; w < kBoxBlock / 64; w++) s += red[w][threadIdx.x];
-        atomicAdd(&stats[threadIdx.x], s);
+    bool block_uniform = true;
+    for (int w = 0; w < kBoxBlock / 64; w++) block_uniform = block_uniform && s_sc[w] == s_sc[0];
+    if (block_uniform) {
+        if (threadIdx.x < 6) {
+            double t = 0.0;
+            for (int w = 0; w < kBoxBlock / 64; w++) t += red[w][threadIdx.x];
+            partial[8 * (int64_t)blockIdx.x + threadIdx.x] = t;
+        }
+        if (threadIdx.x == 0) partial_scene[blockIdx.x] = s_sc[0];
+    } else {
+        if (threadIdx.x == 0) partial_scene[blockIdx.x] = -1;
+        if (in)
+            for (int q = 0; q < 6; q++) atomicAdd(&stats[6 * (int64_t)sc + q], v[q]);
     }
 }
 
@@ -121,14 +160,40 @@ __device__ __forceinline__ int choose_axis(const double *stats, double n)
     return best;
 }
 
+// Sweep axis of every scene: one wave per scene adds the partial sums of the
+// blocks that belong to it to the straddling blocks' totals.
+__global__ __launch_bounds__(64) void axis_kernel(double *stats, const double *__restrict__ partial,
+                                                  const int32_t *__restrict__ partial_scene, int64_t nblocks,
+                                                  const int64_t *__restrict__ off, int64_t S, int64_t nv, int64_t ne,
+                                                  int64_t nf, int32_t *axis)
+{
+    const int64_t s = blockIdx.x;
+    const int lane = threadIdx.x;
+    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int64_t b = lane; b < nblocks; b += 64)
+        if (partial_scene[b] == (int32_t)s)
+            for (int q = 0; q < 6; q++) acc[q] += partial[8 * b + q];
+    for (int q = 0; q < 6; q++) acc[q] = wave_sum(acc[q]);
+    if (lane == 0) {
+        double t[6];
+        for (int q = 0; q < 6; q++) t[q] = stats[6 * s + q] + acc[q];
+        int64_t n = nv + ne + nf;
+        if (S > 1) {
+            n = 0;
+            for (int g = 0; g < 3; g++) n += off[g * (S + 1) + s + 1] - off[g * (S + 1) + s];
+        }
+        axis[s] = n > 0 ? choose_axis(t, (double)n) : 0;
+    }
+}
+
 __global__ void key_kernel(const float *lo0, const float *lo1, const float *lo2, int64_t nb,
-                           const double *stats, int32_t *axis_out, uint32_t *keys, uint32_t *vals)
+                           const uint32_t *__restrict__ bscene, const int32_t *__restrict__ axis, uint32_t *keys,
+                           uint32_t *vals)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int axis = choose_axis(stats, (double)nb);
-    if (i == 0) *axis_out = axis;
     if (i < nb) {
-        const float *lo = axis == 0 ? lo0 : (axis == 1 ? lo1 : lo2);
+        const int a = axis[bscene ? bscene[i] : 0u];
+        const float *lo = a == 0 ? lo0 : (a == 1 ? lo1 : lo2);
         keys[i] = sort_key(lo[i]);
         vals[i] = (uint32_t)i;
     }
@@ -139,7 +204,18 @@ __device__ __forceinline__ int segment_of(int64_t i, int64_t n0, int64_t n1)
     return (i >= n0) + (i >= n1);
 }
 
-__global__ __launch_bounds__(kSortThreads) void hist_kernel(const uint32_t *__restrict__ keys, int64_t n,
+// Digit of entry i in a pass: byte `shift` of its key, or (scene passes) of
+// the scene id of the box it carries.
+__device__ __forceinline__ uint32_t digit_of(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ vals,
+                                             const uint32_t *__restrict__ bscene, int64_t i, int shift)
+{
+    const uint32_t x = bscene ? bscene[vals[i]] : keys[i];
+    return (x >> shift) & 255u;
+}
+
+__global__ __launch_bounds__(kSortThreads) void hist_kernel(const uint32_t *__restrict__ keys,
+                                                           const uint32_t *__restrict__ vals,
+                                                           const uint32_t *__restrict__ bscene, int64_t n,
                                                            int64_t n0, int64_t n1, int shift,
                                                            uint32_t *hist, int64_t nblocks)
 {
@@ -150,7 +226,7 @@ __global__ __launch_bounds__(kSortThreads) void hist_kernel(const uint32_t *__re
     for (int r = 0; r < kSortRounds; r++) {
         const int64_t i = base + (int64_t)r * kSortThreads + threadIdx.x;
         if (i < n) {
-            const int bin = segment_of(i, n0, n1) * 256 + ((keys[i] >> shift) & 255u);
+            const int bin = segment_of(i, n0, n1) * 256 + (int)digit_of(keys, vals, bscene, i, shift);
             atomicAdd(&h[bin], 1u);
         }
     }
@@ -208,9 +284,9 @@ __global__ __launch_bounds__(1024) void bin_base_kernel(const uint32_t *tot, uin
 // find each other with 10 ballots (bins < 1024); waves then take their
 // offsets in order.
 __global__ __launch_bounds__(kSortThreads) void scatter_kernel(
-    const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint32_t *kout, uint32_t *vout,
-    int64_t n, int64_t n0, int64_t n1, int shift, const uint32_t *__restrict__ hist, int64_t nblocks,
-    const uint32_t *__restrict__ bin_base)
+    const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, const uint32_t *__restrict__ bscene,
+    uint32_t *kout, uint32_t *vout, int64_t n, int64_t n0, int64_t n1, int shift,
+    const uint32_t *__restrict__ hist, int64_t nblocks, const uint32_t *__restrict__ bin_base)
 {
     __shared__ uint32_t off[kBins];
     for (int b = threadIdx.x; b < kBins; b += kSortThreads)
@@ -227,7 +303,7 @@ __global__ __launch_bounds__(kSortThreads) void scatter_kernel(
         if (valid) {
             k = kin[i];
             v = vin[i];
-            bin = segment_of(i, n0, n1) * 256 + (int)((k >> shift) & 255u);
+            bin = segment_of(i, n0, n1) * 256 + (int)((bscene ? bscene[v] : k) >> shift & 255u);
         }
         unsigned long long match = __ballot(valid);
         for (int bit = 0; bit < 10; bit++) {
@@ -253,21 +329,32 @@ __global__ __launch_bounds__(kSortThreads) void scatter_kernel(
     }
 }
 
-__global__ void gather_kernel(const uint32_t *__restrict__ vals, int64_t nv, int64_t ne, int64_t nf,
-                              const int32_t *__restrict__ E, const int32_t *__restrict__ F,
+// Sweep records in sorted order.  With several scenes the keys become
+// (scene << 32 | key) composites, so that one sorted segment holds the scenes
+// one after another and no window reaches into the next scene.
+__global__ void gather_kernel(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ vals, int64_t nv,
+                              int64_t ne, int64_t nf, const int32_t *__restrict__ E, const int32_t *__restrict__ F,
                               const float *lo0, const float *lo1, const float *lo2,
                               const float *hi0, const float *hi1, const float *hi2,
-                              const int32_t *axis_p, uint32_t *khi, float *lob, float *hib, float *loc,
-                              float *hic, int32_t *pid, int32_t *vtx)
+                              const uint32_t *__restrict__ bscene, const int32_t *__restrict__ axis_s, uint32_t *khi,
+                              unsigned long long *klo64, unsigned long long *khi64, float *lob, float *hib,
+                              float *loc, float *hic, int32_t *pid, int32_t *vtx)
 {
     const int64_t nb = nv + ne + nf;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nb) return;
-    const int axis = *axis_p;
+    const int64_t g = vals[i];
+    const uint32_t sc = bscene ? bscene[g] : 0u;
+    const int axis = axis_s[sc];
     const int ab = axis == 0 ? 1 : 0, ac = axis == 2 ? 1 : 2;
     const float *lo[3] = {lo0, lo1, lo2}, *hi[3] = {hi0, hi1, hi2};
-    const int64_t g = vals[i];
-    khi[i] = sort_key(hi[axis][g]);
+    const uint32_t kh = sort_key(hi[axis][g]);
+    if (khi64) {
+        khi64[i] = (unsigned long long)sc << 32 | kh;
+        klo64[i] = (unsigned long long)sc << 32 | keys[i];
+    } else {
+        khi[i] = kh;
+    }
     lob[i] = lo[ab][g];
     hib[i] = hi[ab][g];
     loc[i] = lo[ac][g];
@@ -289,26 +376,31 @@ __global__ void gather_kernel(const uint32_t *__restrict__ vals, int64_t nv, int
     }
 }
 
-// Sweep, one wave per tile of 64 consecutive sorted query records.  The
-// wave streams the candidate records (faces for a vertex tile, later edges
-// for an edge tile, vertices for a face tile) through LDS 64 at a time; every
-// lane tests its query against all 64, reading each candidate as an LDS
-// broadcast.  A lane's own window is enforced by comparisons (lower key,
-// upper key), so the tile scans the union of its lanes' windows and stops
-// once a chunk starts beyond every lane's upper key.
+// Sweep, one wave per tile of 64 consecutive sorted query records (one query
+// per lane).  The wave walks the union of its lanes' candidate windows in
+// sorted order -- faces for a vertex tile, later edges for an edge tile,
+// vertices for a face tile -- reading each candidate record with wave-uniform
+// (scalar) loads.  Every lane compares its query against the candidate; the
+// comparisons reduce to one lane mask per candidate, and only the rare
+// candidates that some lane overlaps take the branch that applies the pair
+// rules and stages the pairs.  A lane's own window is enforced by the
+// comparisons (lower key, upper key):
 //   vertex v -> face f:  key_lo(v) <= key_lo(f) <= key_hi(v)
 //   edge i   -> edge j:  i < j (sorted position), key_lo(j) <= key_hi(i)
 //   face f   -> vertex v: key_lo(f) <  key_lo(v) <= key_hi(f)
-// so each overlapping vertex-face pair is found from exactly one side.
-__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v)
+// so each overlapping vertex-face pair is found from exactly one side, and the
+// walk stops at the first candidate beyond every lane's upper key.
+template <typename K>
+__device__ __forceinline__ K wave_min_key(K v)
 {
-    for (int o = 32; o > 0; o >>= 1) { const uint32_t w = __shfl_xor(v, o); v = w < v ? w : v; }
+    for (int o = 32; o > 0; o >>= 1) { const K w = __shfl_xor(v, o); v = w < v ? w : v; }
     return v;
 }
 
-__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v)
+template <typename K>
+__device__ __forceinline__ K wave_max_key(K v)
 {
-    for (int o = 32; o > 0; o >>= 1) { const uint32_t w = __shfl_xor(v, o); v = w > v ? w : v; }
+    for (int o = 32; o > 0; o >>= 1) { const K w = __shfl_xor(v, o); v = w > v ? w : v; }
     return v;
 }
 
@@ -316,7 +408,7 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v)
 // with one atomic per flush, so waves do not contend on the pair counters.
 constexpr int kOutCap = 512;
 
-__device__ __forceinline__ void flush_pairs(int32_t (*buf)[2], int fill, int32_t *out, int64_t cap,
+__device__ __forceinline__ void flush_pairs(const int32_t (*buf)[2], int fill, int32_t *__restrict__ out, int64_t cap,
                                             unsigned long long *counter, int lane)
 {
     unsigned long long base = 0ull;
@@ -334,15 +426,16 @@ __device__ __forceinline__ void flush_pairs(int32_t (*buf)[2], int fill, int32_t
 // First index j in [a, b) with key[j] >= x (strict = false) or key[j] > x
 // (strict = true); keys sorted ascending.  The wave probes 64 evenly spaced
 // keys per step, so a search costs about log_64(b - a) dependent loads.
-__device__ __forceinline__ int64_t wave_lower_bound(const uint32_t *__restrict__ key, int64_t a, int64_t b,
-                                                    uint32_t x, bool strict, int lane)
+template <typename K>
+__device__ __forceinline__ int64_t wave_lower_bound(const K *__restrict__ key, int64_t a, int64_t b, K x,
+                                                    bool strict, int lane)
 {
     while (b - a > 64) {
         const int64_t step = (b - a + 63) / 64;
         const int64_t j = a + (int64_t)lane * step;
         bool before = false;  // key[j] lies before the answer
         if (j < b) {
-            const uint32_t kj = key[j];
+            const K kj = key[j];
             before = strict ? kj <= x : kj < x;
         }
         const int nb = __popcll(__ballot(before));  // probes before the answer (a prefix)
@@ -355,158 +448,141 @@ __device__ __forceinline__ int64_t wave_lower_bound(const uint32_t *__restrict__
     const int64_t j = a + lane;
     bool before = false;
     if (j < b) {
-        const uint32_t kj = key[j];
+        const K kj = key[j];
         before = strict ? kj <= x : kj < x;
     }
     return a + __popcll(__ballot(before));
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs.  Tiles are dealt to
-// the XCDs in groups of kTileGroup consecutive tiles, so that the overlapping
+// the XCDs in groups of `group` consecutive tiles, so that the overlapping
 // sweep windows of a group are read through one L2 while the work stays
 // spread over all XCDs.
-constexpr int64_t kTileGroup = 16;
-
-__device__ __forceinline__ int64_t xcd_tile(int64_t b)
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t group)
 {
     const int64_t x = b % 8, i = b / 8;
-    return ((i / kTileGroup) * 8 + x) * kTileGroup + (i % kTileGroup);
+    return ((i / group) * 8 + x) * group + (i % group);
 }
 
-__global__ __launch_bounds__(kTile) void sweep_kernel(
-    const uint32_t *__restrict__ klo, const uint32_t *__restrict__ khi, const float *__restrict__ lob,
-    const float *__restrict__ hib, const float *__restrict__ loc, const float *__restrict__ hic,
-    const int32_t *__restrict__ pid, const int32_t *__restrict__ vtx, int64_t nv, int64_t ne, int64_t nf,
-    int64_t tiles_v, int64_t tiles_e, int64_t ntiles, int32_t *vf, int64_t vf_cap, int32_t *ee, int64_t ee_cap,
-    unsigned long long *counts)
+struct SweepRecords {
+    const float *__restrict__ lob;
+    const float *__restrict__ hib;
+    const float *__restrict__ loc;
+    const float *__restrict__ hic;
+    const int32_t *__restrict__ pid;
+    const int32_t *__restrict__ vtx;
+};
+
+// Wave-uniform copy of a value every lane holds (it then lives in scalar
+// registers, and comparisons against it are uniform branches).
+__device__ __forceinline__ uint32_t uniform(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
+__device__ __forceinline__ unsigned long long uniform(unsigned long long v)
 {
-    __shared__ uint32_t s_klo[kTile];
-    __shared__ float4 s_box[kTile];
-    __shared__ int32_t s_pid[kTile];
-    __shared__ int32_t s_vtx[3][kTile];
-    __shared__ int32_t s_out[kOutCap][2];
-    const int lane = threadIdx.x;
-    const int64_t nb = nv + ne + nf, f0 = nv + ne;
-    const int64_t t = xcd_tile(blockIdx.x);
-    if (t >= ntiles) return;
-    int role;  // 0: vertex tile, 1: edge tile, 2: face tile
-    int64_t qbase, qend, cbeg, cend;
-    if (t < tiles_v) {
-        role = 0; qbase = t * kTile; qend = nv; cbeg = f0; cend = nb;
-    } else if (t < tiles_v + tiles_e) {
-        role = 1; qbase = nv + (t - tiles_v) * kTile; qend = f0; cbeg = nv; cend = f0;
-    } else {
-        role = 2; qbase = f0 + (t - tiles_v - tiles_e) * kTile; qend = nb; cbeg = 0; cend = nv;
+    const uint32_t lo = uniform((uint32_t)v), hi = uniform((uint32_t)(v >> 32));
+    return (unsigned long long)hi << 32 | lo;
+}
+
+// Candidates tested per block: their records are loaded together.
+template <typename K>
+struct SweepUnroll { static constexpr int value = 8; };
+template <>
+struct SweepUnroll<unsigned long long> { static constexpr int value = 4; };
+
+// Pair rules for candidate j on the lanes whose boxes overlap it (ok), then
+// the kept pairs are staged in LDS.
+template <typename K, int ROLE>
+__device__ __forceinline__ void sweep_emit(int64_t j, bool ok, const SweepRecords &R, int32_t me, int32_t w0,
+                                           int32_t w1, int32_t w2, int lane, unsigned long long lt, int &fill,
+                                           int32_t *__restrict__ out, int64_t out_cap, unsigned long long *counter,
+                                           int32_t (*s_out)[2])
+{
+    const int32_t o = R.pid[j], g0 = R.vtx[3 * j], g1 = R.vtx[3 * j + 1], g2 = R.vtx[3 * j + 2];
+    bool keep = ok;
+    if (ROLE == 0) keep &= (g0 != me) & (g1 != me) & (g2 != me);
+    else if (ROLE == 1) keep &= (w0 != g0) & (w0 != g1) & (w1 != g0) & (w1 != g1);
+    else keep &= (o != w0) & (o != w1) & (o != w2);
+    const unsigned long long km = __ballot(keep);
+    if (km == 0ull) return;
+    const int cnt = __popcll(km);
+    if (fill + cnt > kOutCap) {
+        __syncthreads();
+        flush_pairs(s_out, fill, out, out_cap, counter, lane);
+        fill = 0;
+        __syncthreads();
     }
-    int32_t *out = role == 1 ? ee : vf;
-    const int64_t out_cap = role == 1 ? ee_cap : vf_cap;
-    unsigned long long *counter = role == 1 ? &counts[1] : &counts[0];
+    if (keep) {
+        const int pos = fill + __popcll(km & lt);
+        int32_t a, b;
+        if (ROLE == 0) { a = me; b = o; }
+        else if (ROLE == 1) { a = me < o ? me : o; b = me < o ? o : me; }
+        else { a = o; b = me; }
+        s_out[pos][0] = a;
+        s_out[pos][1] = b;
+    }
+    fill += cnt;
+}
+
+// One tile of role ROLE (0 vertex, 1 edge, 2 face).
+template <typename K, int ROLE>
+__device__ __forceinline__ void sweep_tile(const K *__restrict__ klo, const K *__restrict__ khi,
+                                           const SweepRecords &R, int64_t qbase, int64_t qend, int64_t cbeg,
+                                           int64_t cend, int32_t *__restrict__ out, int64_t out_cap,
+                                           unsigned long long *counter, int32_t (*s_out)[2])
+{
+    constexpr int U = SweepUnroll<K>::value;
+    const int lane = threadIdx.x;
+    const unsigned long long lt = (1ull << lane) - 1ull;
     const int64_t i = qbase + lane;
     const bool valid = i < qend;
-    uint32_t kl = 0xffffffffu, kh = 0u;
+    // an invalid lane's window is empty: kh = 0 is below every key, kl = max above
+    K kl = ~(K)0, kh = 0;
     float lb = 0.f, hb = 0.f, lc = 0.f, hc = 0.f;
     int32_t me = -1, w0 = -1, w1 = -1, w2 = -1;
     if (valid) {
         kl = klo[i]; kh = khi[i];
-        lb = lob[i]; hb = hib[i]; lc = loc[i]; hc = hic[i];
-        me = pid[i];
-        w0 = vtx[3 * i]; w1 = vtx[3 * i + 1]; w2 = vtx[3 * i + 2];
+        lb = R.lob[i]; hb = R.hib[i]; lc = R.loc[i]; hc = R.hic[i];
+        me = R.pid[i];
+        w0 = R.vtx[3 * i]; w1 = R.vtx[3 * i + 1]; w2 = R.vtx[3 * i + 2];
     }
-    const uint32_t kmin = wave_min_u32(kl), kmax = wave_max_u32(kh);
-    const int64_t js = role == 1 ? qbase : wave_lower_bound(klo, cbeg, cend, kmin, role == 2, lane);
+    const K kmin = uniform(wave_min_key(kl)), kmax = uniform(wave_max_key(kh));
+    int64_t j = ROLE == 1 ? qbase + 1 : wave_lower_bound(klo, cbeg, cend, kmin, ROLE == 2, lane);
+    j = (int64_t)uniform((unsigned long long)j);
     int fill = 0;  // pairs staged in s_out (wave-uniform)
-    // candidate chunk in registers, loaded one chunk ahead of its use
-    uint32_t jk = 0xffffffffu;
-    float4 jb = make_float4(0.f, 0.f, 0.f, 0.f);
-    int32_t jp = 0, jv0 = 0, jv1 = 0, jv2 = 0;
-    {
-        const int64_t j = js + lane;
-        if (j < cend) {
-            jk = klo[j]; jb = make_float4(lob[j], hib[j], loc[j], hic[j]);
-            jp = pid[j]; jv0 = vtx[3 * j]; jv1 = vtx[3 * j + 1]; jv2 = vtx[3 * j + 2];
+    bool done = false;
+    for (; j + U <= cend; j += U) {
+        K kk[U];
+        float bl[U], bh[U], cl[U], ch[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            kk[u] = klo[j + u];
+            bl[u] = R.lob[j + u]; bh[u] = R.hib[j + u]; cl[u] = R.loc[j + u]; ch[u] = R.hic[j + u];
         }
+        if (kk[0] > kmax) { done = true; break; }  // this and every later candidate lies beyond all windows
+        bool ok[U];
+        unsigned long long any = 0ull;
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            bool t = (kk[u] <= kh) & (bl[u] <= hb) & (lb <= bh[u]) & (cl[u] <= hc) & (lc <= ch[u]);
+            if (ROLE == 0) t &= kk[u] >= kl;
+            else if (ROLE == 1) t &= j + u > i;
+            else t &= kk[u] > kl;
+            ok[u] = t;
+            any |= __ballot(t);
+        }
+        if (any == 0ull) continue;
+#pragma unroll
+        for (int u = 0; u < U; u++)
+            if (__ballot(ok[u])) sweep_emit<K, ROLE>(j + u, ok[u], R, me, w0, w1, w2, lane, lt, fill, out, out_cap,
+                                                     counter, s_out);
     }
-    for (int64_t cb = js; cb < cend; cb += kTile) {
-        const uint32_t first = __shfl(jk, 0);
-        if (first > kmax) break;  // uniform: this and every later chunk lies beyond all windows
-        s_klo[lane] = jk;
-        s_box[lane] = jb;
-        s_pid[lane] = jp;
-        s_vtx[0][lane] = jv0; s_vtx[1][lane] = jv1; s_vtx[2][lane] = jv2;
-        __syncthreads();
-        {
-            const int64_t j = cb + kTile + lane;
-            jk = 0xffffffffu;
-            if (j < cend) {
-                jk = klo[j]; jb = make_float4(lob[j], hib[j], loc[j], hic[j]);
-                jp = pid[j]; jv0 = vtx[3 * j]; jv1 = vtx[3 * j + 1]; jv2 = vtx[3 * j + 2];
-            }
-        }
-        // box tests: bit k of hits = overlap with candidate k of the chunk
-        unsigned long long hits = 0ull;
-#pragma unroll 16
-        for (int k = 0; k < kTile; k++) {
-            const uint32_t kj = s_klo[k];
-            const float4 bx = s_box[k];
-            bool ok = kj <= kh && bx.x <= hb && lb <= bx.y && bx.z <= hc && lc <= bx.w;
-            if (role == 0) ok = ok && kj >= kl;
-            else if (role == 1) ok = ok && cb + k > i;
-            else ok = ok && kj > kl;
-            hits |= (unsigned long long)ok << k;
-        }
-        // candidate rules on the (few) overlapping boxes
-        unsigned long long keep = 0ull;
-        for (unsigned long long m = hits; m; m &= m - 1ull) {
-            const int k = __ffsll((long long)m) - 1;
-            const int32_t g0 = s_vtx[0][k], g1 = s_vtx[1][k], g2 = s_vtx[2][k], o = s_pid[k];
-            bool ok;
-            if (role == 0) ok = g0 != me && g1 != me && g2 != me;
-            else if (role == 1) ok = w0 != g0 && w0 != g1 && w1 != g0 && w1 != g1;
-            else ok = o != w0 && o != w1 && o != w2;
-            if (ok) keep |= 1ull << k;
-        }
-        const uint32_t cnt = (uint32_t)__popcll(keep);
-        const uint32_t incl = wave_incl_scan(cnt, lane);
-        const int total = (int)__shfl(incl, 63);
-        if (total > 0) {
-            if (fill + total > kOutCap) {
-                flush_pairs(s_out, fill, out, out_cap, counter, lane);
-                fill = 0;
-                __syncthreads();
-            }
-            if (total <= kOutCap) {
-                int pos = fill + (int)(incl - cnt);
-                for (unsigned long long m = keep; m; m &= m - 1ull) {
-                    const int k = __ffsll((long long)m) - 1;
-                    const int32_t o = s_pid[k];
-                    int32_t a, b;
-                    if (role == 0) { a = me; b = o; }
-                    else if (role == 1) { a = me < o ? me : o; b = me < o ? o : me; }
-                    else { a = o; b = me; }
-                    s_out[pos][0] = a;
-                    s_out[pos][1] = b;
-                    pos++;
-                }
-                fill += total;
-            } else {
-                // more pairs than the staging buffer holds: write this chunk directly
-                unsigned long long base = 0ull;
-                if (lane == 0) base = atomicAdd(counter, (unsigned long long)total);
-                base = __shfl(base, 0);
-                unsigned long long idx = base + (incl - cnt);
-                for (unsigned long long m = keep; m; m &= m - 1ull) {
-                    const int k = __ffsll((long long)m) - 1;
-                    const int32_t o = s_pid[k];
-                    int32_t a, b;
-                    if (role == 0) { a = me; b = o; }
-                    else if (role == 1) { a = me < o ? me : o; b = me < o ? o : me; }
-                    else { a = o; b = me; }
-                    if ((int64_t)idx < out_cap) { out[2 * idx] = a; out[2 * idx + 1] = b; }
-                    idx++;
-                }
-            }
-        }
-        __syncthreads();
+    for (; !done && j < cend; j++) {
+        const K kj = klo[j];
+        if (kj > kmax) break;
+        bool t = (kj <= kh) & (R.lob[j] <= hb) & (lb <= R.hib[j]) & (R.loc[j] <= hc) & (lc <= R.hic[j]);
+        if (ROLE == 0) t &= kj >= kl;
+        else if (ROLE == 1) t &= j > i;
+        else t &= kj > kl;
+        if (__ballot(t)) sweep_emit<K, ROLE>(j, t, R, me, w0, w1, w2, lane, lt, fill, out, out_cap, counter, s_out);
     }
     if (fill > 0) {
         __syncthreads();
@@ -514,19 +590,47 @@ __global__ __launch_bounds__(kTile) void sweep_kernel(
     }
 }
 
+template <typename K>
+__global__ __launch_bounds__(kTile) void sweep_kernel(
+    const K *__restrict__ klo, const K *__restrict__ khi, const float *__restrict__ lob,
+    const float *__restrict__ hib, const float *__restrict__ loc, const float *__restrict__ hic,
+    const int32_t *__restrict__ pid, const int32_t *__restrict__ vtx, int64_t nv, int64_t ne, int64_t nf,
+    int64_t tiles_v, int64_t tiles_e, int64_t ntiles, int64_t group, int32_t *__restrict__ vf, int64_t vf_cap,
+    int32_t *__restrict__ ee, int64_t ee_cap, unsigned long long *counts)
+{
+    __shared__ int32_t s_out[kOutCap][2];
+    const int64_t nb = nv + ne + nf, f0 = nv + ne;
+    const int64_t t = xcd_tile(blockIdx.x, group);
+    if (t >= ntiles) return;
+    const SweepRecords R{lob, hib, loc, hic, pid, vtx};
+    if (t < tiles_v)
+        sweep_tile<K, 0>(klo, khi, R, t * kTile, nv, f0, nb, vf, vf_cap, &counts[0], s_out);
+    else if (t < tiles_v + tiles_e)
+        sweep_tile<K, 1>(klo, khi, R, nv + (t - tiles_v) * kTile, f0, nv, f0, ee, ee_cap, &counts[1], s_out);
+    else
+        sweep_tile<K, 2>(klo, khi, R, f0 + (t - tiles_v - tiles_e) * kTile, nb, 0, nv, vf, vf_cap, &counts[0],
+                         s_out);
+}
+
 inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
 
 }  // namespace
+
+int scene_passes(int64_t S) { return S <= 1 ? 0 : (S <= 256 ? 1 : 2); }
 
 void launch_broad_boxes(const double *V0, const double *V1, int64_t nv, const int32_t *E, int64_t ne,
                         const int32_t *F, int64_t nf, const BroadBuffers &B, hipStream_t s)
 {
     const int64_t nb = nv + ne + nf;
-    zero_kernel<<<1, 64, 0, s>>>(B.stats, B.counts, B.flags);
-    if (nb == 0) return;
-    box_kernel<<<grid_for(nb, kBoxBlock), kBoxBlock, 0, s>>>(V0, V1, nv, E, ne, F, nf, B.lo[0], B.lo[1],
-                                                            B.lo[2], B.hi[0], B.hi[1], B.hi[2], B.stats,
-                                                            B.flags);
+    const int64_t nstats = 6 * B.nscenes;
+    zero_kernel<<<grid_for(nstats > 64 ? nstats : 64, 256), 256, 0, s>>>(B.stats, nstats, B.counts, B.flags);
+    const int64_t nblk = box_blocks(nb);
+    if (nb > 0)
+        box_kernel<<<(unsigned)nblk, kBoxBlock, 0, s>>>(V0, V1, nv, E, ne, F, nf, B.off, B.nscenes, B.lo[0],
+                                                       B.lo[1], B.lo[2], B.hi[0], B.hi[1], B.hi[2], B.bscene, B.stats,
+                                                       B.partial, B.partial_scene, B.flags);
+    axis_kernel<<<(unsigned)B.nscenes, 64, 0, s>>>(B.stats, B.partial, B.partial_scene, nb > 0 ? nblk : 0, B.off,
+                                                  B.nscenes, nv, ne, nf, B.axis);
 }
 
 void launch_broad_sort(int64_t nv, int64_t ne, int64_t nf, const BroadBuffers &B, int64_t nblocks_sort,
@@ -534,21 +638,32 @@ void launch_broad_sort(int64_t nv, int64_t ne, int64_t nf, const BroadBuffers &B
 {
     const int64_t nb = nv + ne + nf;
     if (nb == 0) return;
-    key_kernel<<<grid_for(nb, 256), 256, 0, s>>>(B.lo[0], B.lo[1], B.lo[2], nb, B.stats, B.axis, B.keyA,
-                                                 B.valA);
+    key_kernel<<<grid_for(nb, 256), 256, 0, s>>>(B.lo[0], B.lo[1], B.lo[2], nb, B.bscene, B.axis, B.keyA, B.valA);
     uint32_t *kin = B.keyA, *vin = B.valA, *kout = B.keyB, *vout = B.valB;
-    for (int pass = 0; pass < 4; pass++) {
-        const int shift = 8 * pass;
-        hist_kernel<<<(unsigned)nblocks_sort, kSortThreads, 0, s>>>(kin, nb, nv, nv + ne, shift, B.hist,
+    const int passes = 4 + scene_passes(B.nscenes);
+    for (int pass = 0; pass < passes; pass++) {
+        // four passes over the key bytes, then (several scenes) the scene id bytes
+        const int shift = 8 * (pass < 4 ? pass : pass - 4);
+        const uint32_t *digits = pass < 4 ? nullptr : B.bscene;
+        hist_kernel<<<(unsigned)nblocks_sort, kSortThreads, 0, s>>>(kin, vin, digits, nb, nv, nv + ne, shift, B.hist,
                                                                    nblocks_sort);
         bin_scan_kernel<<<kBins / 4, 256, 0, s>>>(B.hist, nblocks_sort, B.bin_tot);
         bin_base_kernel<<<1, 1024, 0, s>>>(B.bin_tot, B.bin_base);
-        scatter_kernel<<<(unsigned)nblocks_sort, kSortThreads, 0, s>>>(kin, vin, kout, vout, nb, nv, nv + ne,
+        scatter_kernel<<<(unsigned)nblocks_sort, kSortThreads, 0, s>>>(kin, vin, digits, kout, vout, nb, nv, nv + ne,
                                                                       shift, B.hist, nblocks_sort, B.bin_base);
         uint32_t *tk = kin, *tv = vin;
         kin = kout; vin = vout; kout = tk; vout = tv;
     }
-    // four passes: the sorted keys and values are back in keyA / valA
+}
+
+// After an even number of passes the sorted keys and ids are back in keyA / valA.
+static inline const uint32_t *sorted_keys(const BroadBuffers &B)
+{
+    return (4 + scene_passes(B.nscenes)) % 2 == 0 ? B.keyA : B.keyB;
+}
+static inline const uint32_t *sorted_vals(const BroadBuffers &B)
+{
+    return (4 + scene_passes(B.nscenes)) % 2 == 0 ? B.valA : B.valB;
 }
 
 void launch_broad_gather(const int32_t *E, const int32_t *F, int64_t nv, int64_t ne, int64_t nf,
@@ -556,24 +671,35 @@ void launch_broad_gather(const int32_t *E, const int32_t *F, int64_t nv, int64_t
 {
     const int64_t nb = nv + ne + nf;
     if (nb == 0) return;
-    gather_kernel<<<grid_for(nb, 256), 256, 0, s>>>(B.valA, nv, ne, nf, E, F, B.lo[0], B.lo[1], B.lo[2],
-                                                   B.hi[0], B.hi[1], B.hi[2], B.axis, B.khi, B.lob, B.hib,
-                                                   B.loc, B.hic, B.pid, B.vtx);
+    const bool multi = B.nscenes > 1;
+    gather_kernel<<<grid_for(nb, 256), 256, 0, s>>>(sorted_keys(B), sorted_vals(B), nv, ne, nf, E, F, B.lo[0],
+                                                   B.lo[1], B.lo[2], B.hi[0], B.hi[1], B.hi[2], B.bscene, B.axis,
+                                                   B.khi, multi ? B.klo64 : nullptr, multi ? B.khi64 : nullptr,
+                                                   B.lob, B.hib, B.loc, B.hic, B.pid, B.vtx);
 }
 
 void launch_broad_sweep(int64_t nv, int64_t ne, int64_t nf, int32_t *vf, int64_t vf_cap, int32_t *ee,
-                        int64_t ee_cap, const BroadBuffers &B, hipStream_t s)
+                        int64_t ee_cap, const BroadBuffers &B, int64_t tile_group, hipStream_t s)
 {
     const int64_t nb = nv + ne + nf;
     if (nb == 0) return;
     const int64_t tv = (nv + kTile - 1) / kTile, te = (ne + kTile - 1) / kTile, tf = (nf + kTile - 1) / kTile;
     const int64_t nt = tv + te + tf;
     if (nt == 0) return;
-    const int64_t grid = (nt + 8 * kTileGroup - 1) / (8 * kTileGroup) * (8 * kTileGroup);
-    sweep_kernel<<<(unsigned)grid, kTile, 0, s>>>(B.keyA, B.khi, B.lob, B.hib, B.loc, B.hic, B.pid, B.vtx, nv, ne,
-                                                 nf, tv, te, nt, vf, vf_cap, ee, ee_cap, B.counts);
+    const int64_t g = tile_group < 1 ? 1 : tile_group;
+    const int64_t grid = (nt + 8 * g - 1) / (8 * g) * (8 * g);
+    if (B.nscenes > 1)
+        sweep_kernel<unsigned long long><<<(unsigned)grid, kTile, 0, s>>>(
+            B.klo64, B.khi64, B.lob, B.hib, B.loc, B.hic, B.pid, B.vtx, nv, ne, nf, tv, te, nt, g, vf, vf_cap, ee,
+            ee_cap, B.counts);
+    else
+        sweep_kernel<uint32_t><<<(unsigned)grid, kTile, 0, s>>>(sorted_keys(B), B.khi, B.lob, B.hib, B.loc, B.hic,
+                                                               B.pid, B.vtx, nv, ne, nf, tv, te, nt, g, vf, vf_cap,
+                                                               ee, ee_cap, B.counts);
 }
 
 int64_t sort_blocks(int64_t nb) { return nb > 0 ? (nb + kSortTile - 1) / kSortTile : 1; }
+
+int64_t box_blocks(int64_t nb) { return nb > 0 ? (nb + kBoxBlock - 1) / kBoxBlock : 1; }
 
 }  // namespace ccd

@@ -64,16 +64,25 @@ enum : uint32_t {
 // Broad-phase workspace: all device pointers, owned by the context pool.
 // ---------------------------------------------------------------------------
 struct BroadBuffers {
+    // scenes: S >= 1; with S > 1 `off` holds the device CSR offsets of the
+    // vertices, edges and faces (S + 1 each, in that order) and bscene the
+    // scene of every box
+    int64_t nscenes;
+    const int64_t *off;
+    uint32_t *bscene;
     // boxes in primitive order, segments [V | E | F], SoA
     float *lo[3], *hi[3];
     // sort keys / payload (double-buffered)
     uint32_t *keyA, *keyB, *valA, *valB;
     uint32_t *hist;       // 768 * nblocks
     uint32_t *bin_tot, *bin_base;  // 768 each
-    double *stats;        // 6 accumulators: sum c_a, sum c_a^2
-    int32_t *axis;        // chosen sweep axis
+    double *stats;        // 6 accumulators per scene: sum c_a, sum c_a^2 (boundary blocks)
+    double *partial;      // per box block: the 6 sums (stride 8) when the block is one scene
+    int32_t *partial_scene;  // per box block: its scene, or -1
+    int32_t *axis;        // sweep axis of every scene
     // sorted sweep records, segments [V | E | F]
-    uint32_t *khi;        // key of hi on the sweep axis
+    uint32_t *khi;        // key of hi on the sweep axis (one scene)
+    unsigned long long *klo64, *khi64;  // (scene, key) composites of lo and hi (several scenes)
     float *lob, *hib, *loc, *hic;  // the two other axes
     int32_t *pid;         // primitive id
     int32_t *vtx;         // up to 3 vertex ids per record (stride 3)
@@ -82,6 +91,7 @@ struct BroadBuffers {
 };
 
 int64_t sort_blocks(int64_t nb);
+int64_t box_blocks(int64_t nb);
 
 // Broad phase in four stages (the host records timing events between them):
 // boxes + centre statistics, sort (keys + 4 radix passes), gather of the
@@ -93,7 +103,34 @@ void launch_broad_sort(int64_t nv, int64_t ne, int64_t nf, const BroadBuffers &B
 void launch_broad_gather(const int32_t *E, const int32_t *F, int64_t nv, int64_t ne, int64_t nf,
                          const BroadBuffers &B, hipStream_t s);
 void launch_broad_sweep(int64_t nv, int64_t ne, int64_t nf, int32_t *vf, int64_t vf_cap, int32_t *ee,
-                        int64_t ee_cap, const BroadBuffers &B, hipStream_t s);
+                        int64_t ee_cap, const BroadBuffers &B, int64_t tile_group, hipStream_t s);
+// Radix passes over scene ids (0 for one scene).
+int scene_passes(int64_t S);
+
+// ---------------------------------------------------------------------------
+// Pair counts of a narrow-phase call.  Pairs are indexed VF first: p < n_vf
+// is vf[p], otherwise ee[p - n_vf].  With dev == null the counts are the host
+// values n_vf, n_ee; otherwise the kernels read them from device memory
+// (dev[0] VF, dev[1] EE, as the sweep leaves them), clamped to n_vf / n_ee,
+// which are then the capacities of the pair buffers.  This lets a captured
+// graph run the narrow phase on the broad phase's output without a host read.
+// ---------------------------------------------------------------------------
+struct PairCounts {
+    int64_t n_vf, n_ee;
+    const unsigned long long *dev;
+    int64_t capacity() const { return n_vf + n_ee; }
+    __device__ __forceinline__ void get(int64_t &vf, int64_t &all) const
+    {
+        if (dev) {
+            const int64_t a = (int64_t)dev[0], b = (int64_t)dev[1];
+            vf = a < n_vf ? a : n_vf;
+            all = vf + (b < n_ee ? b : n_ee);
+        } else {
+            vf = n_vf;
+            all = n_vf + n_ee;
+        }
+    }
+};
 
 // ---------------------------------------------------------------------------
 // Narrow-phase workspace.
@@ -132,26 +169,41 @@ int pool_blocks_per_cu();
 
 // prep: counters, per-pair ids, C_eps and split levels.
 void launch_narrow_prep(const double *V0, const double *V1, int64_t nv, const int32_t *E, int64_t ne,
-                        const int32_t *F, int64_t nf, const int32_t *vf, int64_t n_vf, const int32_t *ee,
-                        int64_t n_ee, double delta, const NarrowBuffers &B, hipStream_t s);
+                        const int32_t *F, int64_t nf, const int32_t *vf, const int32_t *ee, PairCounts pc,
+                        double delta, const NarrowBuffers &B, hipStream_t s);
 
 // Scheduling features of every pair (after prep): n x kNumFeatures floats.
 constexpr int kNumFeatures = 16;
-void launch_narrow_features(const double *V0, const double *V1, int64_t n_vf, int64_t n_ee, double delta,
-                            const NarrowBuffers &B, float *feat, hipStream_t s);
+constexpr int kHidden = 64;
+// The learned schedule's fused first pass: prep, features and the cost
+// model's prediction of every pair (cost[p]), and the histogram of predicted
+// cost bins (hist, 256 uint32, zeroed here).
+void launch_narrow_prep_sched(const double *V0, const double *V1, int64_t nv, const int32_t *E, int64_t ne,
+                              const int32_t *F, int64_t nf, const int32_t *vf, const int32_t *ee, PairCounts pc,
+                              double delta, const NarrowBuffers &B, const float *params, const float *norm,
+                              float *cost, uint32_t *hist, hipStream_t s);
+void launch_narrow_features(const double *V0, const double *V1, PairCounts pc, double delta, const NarrowBuffers &B,
+                            float *feat, hipStream_t s);
 
 // pool: the wave-pool search of every pair (hands wide / deep pairs over).
 // Pairs are taken in index order, or in `order` (a permutation) when given.
-void launch_narrow_pool(const double *V0, const double *V1, int64_t n_vf, int64_t n_ee, double delta,
-                        long long max_iter, uint8_t *hit, double *toi, long long *n_enq, const NarrowBuffers &B,
-                        int pool_blocks, const int32_t *order, hipStream_t s);
+// With order_n the pool searches order[0 .. *order_n) (the rest of the pairs
+// are the wide stage's).
+void launch_narrow_pool(const double *V0, const double *V1, PairCounts pc, double delta, long long max_iter,
+                        uint8_t *hit, double *toi, long long *n_enq, const NarrowBuffers &B, int pool_blocks,
+                        const int32_t *order, const uint32_t *order_n, hipStream_t s);
+// Wide stage over the learned schedule's early entries heavy[0 .. counters[12])
+// (work index counters[13]), with its own frontier buffers; it may run
+// concurrently with the pool on another stream.
+void launch_narrow_heavy_early(const double *V0, const double *V1, PairCounts pc, double delta, long long max_iter,
+                               uint8_t *hit, double *toi, long long *n_enq, const NarrowBuffers &B,
+                               unsigned long long *scratch, int nslots, int64_t cap, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Learned schedule: MLP kNumFeatures -> 64 -> 64 -> 1 on bf16 MFMA.
 // Parameters (float32, contiguous): W1[16][64], b1[64], W2[64][64], b2[64],
 // W3[64], b3.  norm: feature mean[16] then 1 / std[16].
 // ---------------------------------------------------------------------------
-constexpr int kHidden = 64;
 constexpr int kModelParams = kNumFeatures * kHidden + kHidden + kHidden * kHidden + kHidden + kHidden + 1;
 
 void launch_mlp_predict(const float *params, const float *norm, const float *feat, int64_t n, float *out,
@@ -163,19 +215,32 @@ void launch_mlp_grad(const float *params, const float *norm, const float *feat, 
                      float *grad, float *loss, hipStream_t s);
 void launch_adam(float *params, const float *grad, float *m, float *v, int64_t step, float lr, float beta1,
                  float beta2, float eps, hipStream_t s);
-// order = pairs sorted by predicted cost, most expensive first (bins of 1/4 in
-// log2 cost); scratch holds 3 x 256 uint32.
-void launch_cost_order(const float *cost, int64_t n, int32_t *order, uint32_t *scratch, hipStream_t s);
+// Learned schedule from predicted costs (log2(1 + n_enq)): the pairs ranked
+// first whose prediction is >= threshold (at most max_heavy) become wide-stage
+// entries heavy[0..H) starting from the root, and the wide stage's counters
+// [0], [1], [12] are set to H ([13] = 0); the other pairs fill order[0 ..
+// n - H), dealt by rank so that every 64 consecutive positions span the cost
+// range.  scratch: 3 x 256 + 4 uint32; scratch[2 * 256 + 1] = n - H (device).
+// hist_ready: scratch[0 .. 256) already holds the cost histogram (the fused
+// prep pass below computed it).
+void launch_cost_schedule(const float *cost, int64_t n, float threshold, int max_heavy, int32_t *order,
+                          HeavyEntry *heavy, unsigned int *counters, uint32_t *scratch, bool hist_ready,
+                          hipStream_t s);
+constexpr int kSchedScratch = 3 * 256 + 4;
 // *flag = 0 iff order is a permutation of [0, n); bits holds ceil(n / 32) words.
 void launch_check_permutation(const int32_t *order, int64_t n, uint32_t *bits, uint32_t *flag, hipStream_t s);
 
 // Wide stage: `nslots` workgroups, each with a frontier buffer of `cap` nodes
 // (two buffers of 3 x cap uint64).  Round 0 works on every handed-over pair;
 // round r > 0 re-runs the pairs that overflowed their buffer in round r - 1.
-void launch_narrow_heavy(const double *V0, const double *V1, int64_t n_vf, double delta, long long max_iter,
+void launch_narrow_heavy(const double *V0, const double *V1, PairCounts pc, double delta, long long max_iter,
                          uint8_t *hit, double *toi, long long *n_enq, const NarrowBuffers &B, int nslots,
                          int64_t cap, int round, hipStream_t s);
 
-void launch_toi_min(const double *toi, int64_t n, double *out, hipStream_t s);
+void launch_toi_min(const double *toi, PairCounts pc, double *out, hipStream_t s);
+// out[s] = earliest toi over the pairs of scene s (CSR vertex / edge offsets
+// on the device, S + 1 each); +inf for a scene without a hit.
+void launch_scene_min(const double *toi, PairCounts pc, const int32_t *vf, const int32_t *ee, const int64_t *v_off,
+                      const int64_t *e_off, int64_t S, double *out, hipStream_t s);
 
 }  // namespace ccd

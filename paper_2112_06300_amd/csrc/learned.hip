@@ -11,6 +11,7 @@
 // sit in LDS row-major as bf16; a transposed operand is read with swapped
 // strides.
 #include "ccd_internal.h"
+#include "mlp_tile.h"
 
 namespace ccd {
 
@@ -134,28 +135,29 @@ __device__ __forceinline__ void forward_tile(MlpLds &S, int w, int lane, f32x4 z
     }
 }
 
-__global__ __launch_bounds__(64 * kWaves) void mlp_predict_kernel(const float *__restrict__ prm,
-                                                                 const float *__restrict__ norm,
-                                                                 const float *__restrict__ feat, int64_t n,
-                                                                 float *out)
+// Prediction of every row of feat: one 16-row tile per wave at a time, the
+// weights in registers (mlp_tile.h).
+__global__ __launch_bounds__(256) void mlp_predict_kernel(const float *__restrict__ prm,
+                                                          const float *__restrict__ norm,
+                                                          const float *__restrict__ feat, int64_t n, float *out)
 {
-    __shared__ MlpLds S;
-    load_model(S, prm, norm);
+    __shared__ MlpConsts C;
+    mlp_load_consts(C, prm, norm);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    MlpWeights Wt;
+    mlp_load_weights(Wt, prm, lane);
+    __syncthreads();
+    const int r = lane & 15, g = (lane >> 4) * 4;
     const int64_t tiles = (n + 15) / 16;
-    for (int64_t t = (int64_t)blockIdx.x * kWaves + w; t < tiles; t += (int64_t)gridDim.x * kWaves) {
-        stage_features(S, w, feat, 16 * t, n, lane);
-        f32x4 z2[4];
-        float y[4];
-        forward_tile(S, w, lane, z2, y);
-        if ((lane & 15) == 0) {
-#pragma unroll
-            for (int j = 0; j < 4; j++) {
-                const int64_t p = 16 * t + (lane >> 4) * 4 + j;
-                if (p < n) out[p] = y[j];
-            }
+    for (int64_t t = (int64_t)blockIdx.x * 4 + w; t < tiles; t += (int64_t)gridDim.x * 4) {
+        const int64_t row = 16 * t + r;
+        float f[4] = {0.f, 0.f, 0.f, 0.f};
+        if (row < n) {
+            const float4 v = *reinterpret_cast<const float4 *>(feat + row * F + g);
+            f[0] = v.x; f[1] = v.y; f[2] = v.z; f[3] = v.w;
         }
-        __builtin_amdgcn_wave_barrier();
+        const float y = mlp_forward(Wt, C, mlp_input(C, f, lane), lane);
+        if (lane < 16 && row < n) out[row] = y;
     }
 }
 
@@ -297,13 +299,30 @@ __global__ void adam_kernel(float *prm, const float *__restrict__ grad, float *m
     prm[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
-// ---- ordering by predicted cost: counting sort into 256 bins, costliest first
+// ---- schedule from predicted costs.  Pairs are counted into 256 bins of
+// 1/4 in log2 cost, costliest first, which ranks them (ties in any order).
+// The first H ranks -- pairs predicted at or above the wide-stage threshold,
+// at most max_heavy -- become wide-stage entries that start from the root at
+// once; rank H + r of the other n_light = n - H pairs goes to position
+// (r * S) mod n_light of the pool's order, S the smallest integer >= 64
+// coprime with n_light.  A pool wave claims 64 consecutive positions, so each
+// claim holds about one pair of every cost stratum and the costliest pairs are
+// claimed first.
 constexpr int kCostBins = 256;
 
-__device__ __forceinline__ int cost_bin(float c)
+__device__ __forceinline__ int cost_bin(float c) { return sched_cost_bin(c); }
+
+// Valid lanes of the wave whose bin equals this lane's (8 ballots).
+__device__ __forceinline__ unsigned long long same_bin(int bin, bool valid)
 {
-    const int b = (int)(c * 4.f);
-    return kCostBins - 1 - (b < 0 ? 0 : (b > kCostBins - 1 ? kCostBins - 1 : b));
+    unsigned long long m = __ballot(valid);
+#pragma unroll
+    for (int bit = 0; bit < 8; bit++) {
+        const bool on = (bin >> bit) & 1;
+        const unsigned long long b = __ballot(valid && on);
+        m &= on ? b : ~b;
+    }
+    return m;
 }
 
 __global__ __launch_bounds__(256) void cost_hist_kernel(const float *__restrict__ cost, int64_t n, uint32_t *hist)
@@ -311,13 +330,29 @@ __global__ __launch_bounds__(256) void cost_hist_kernel(const float *__restrict_
     __shared__ uint32_t h[kCostBins];
     h[threadIdx.x] = 0u;
     __syncthreads();
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
-        atomicAdd(&h[cost_bin(cost[i])], 1u);
+    const int lane = threadIdx.x & 63;
+    for (int64_t b0 = (int64_t)blockIdx.x * 256; b0 < n; b0 += (int64_t)gridDim.x * 256) {
+        const int64_t i = b0 + threadIdx.x;
+        const bool valid = i < n;
+        const int bin = valid ? cost_bin(cost[i]) : 0;
+        const unsigned long long m = same_bin(bin, valid);
+        if (valid && (__ffsll((long long)m) - 1) == lane) atomicAdd(&h[bin], (uint32_t)__popcll(m));
+    }
     __syncthreads();
     if (h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
 }
 
-__global__ __launch_bounds__(256) void cost_scan_kernel(const uint32_t *hist, uint32_t *cursor)
+__device__ __forceinline__ uint32_t gcd_u32(uint32_t a, uint32_t b)
+{
+    while (b) { const uint32_t t = a % b; a = b; b = t; }
+    return a;
+}
+
+// Exclusive scan of the bins into cursors; H, n_light and S into info[0..2];
+// the wide stage's counters start at H (entries [0, H) are taken).
+__global__ __launch_bounds__(256) void cost_scan_kernel(const uint32_t *hist, uint32_t *cursor, uint32_t *info,
+                                                        int64_t n, float threshold, int max_heavy,
+                                                        unsigned int *counters)
 {
     __shared__ uint32_t s[kCostBins];
     const int t = threadIdx.x;
@@ -331,26 +366,75 @@ __global__ __launch_bounds__(256) void cost_scan_kernel(const uint32_t *hist, ui
         __syncthreads();
     }
     cursor[t] = s[t] - x;
+    if (t == 0) {
+        const int bt = cost_bin(threshold);  // bins 0..bt hold predictions >= the threshold
+        uint32_t H = s[bt];
+        if (H > (uint32_t)max_heavy) H = (uint32_t)max_heavy;
+        const uint32_t nl = (uint32_t)n - H;
+        uint32_t S = 1u;
+        if (nl > 1u) {
+            S = 64u;
+            while (gcd_u32(S, nl) != 1u) S++;
+        }
+        info[0] = H;
+        info[1] = nl;
+        info[2] = S;
+        counters[0] = H;   // pool hand-overs are appended after the early entries
+        counters[1] = H;   // the post-pool wide stage starts at the first hand-over
+        counters[12] = H;  // early wide-stage entries
+        counters[13] = 0u; // their work index
+    }
 }
 
-// Each block ranks its pairs within its bins in LDS and reserves one range per
-// bin; the order inside a bin is arbitrary (results do not depend on it).
 __global__ __launch_bounds__(256) void cost_scatter_kernel(const float *__restrict__ cost, int64_t n,
-                                                          uint32_t *cursor, int32_t *order)
+                                                           uint32_t *cursor, const uint32_t *__restrict__ info,
+                                                           int32_t *order, HeavyEntry *heavy)
 {
     __shared__ uint32_t h[kCostBins], base[kCostBins];
-    const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+    const int lane = threadIdx.x & 63;
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    const int64_t chunk = ((n + gridDim.x - 1) / gridDim.x + 255) / 256 * 256;
     const int64_t b0 = (int64_t)blockIdx.x * chunk, b1 = b0 + chunk < n ? b0 + chunk : n;
     h[threadIdx.x] = 0u;
     __syncthreads();
-    for (int64_t i = b0 + threadIdx.x; i < b1; i += 256) atomicAdd(&h[cost_bin(cost[i])], 1u);
+    for (int64_t r0 = b0; r0 < b1; r0 += 256) {
+        const int64_t i = r0 + threadIdx.x;
+        const bool valid = i < b1;
+        const int bin = valid ? cost_bin(cost[i]) : 0;
+        const unsigned long long m = same_bin(bin, valid);
+        if (valid && (__ffsll((long long)m) - 1) == lane) atomicAdd(&h[bin], (uint32_t)__popcll(m));
+    }
     __syncthreads();
     base[threadIdx.x] = h[threadIdx.x] ? atomicAdd(&cursor[threadIdx.x], h[threadIdx.x]) : 0u;
     h[threadIdx.x] = 0u;
     __syncthreads();
-    for (int64_t i = b0 + threadIdx.x; i < b1; i += 256) {
-        const int b = cost_bin(cost[i]);
-        order[base[b] + atomicAdd(&h[b], 1u)] = (int32_t)i;
+    const uint32_t H = info[0], nl = info[1], S = info[2];
+    for (int64_t r0 = b0; r0 < b1; r0 += 256) {
+        const int64_t i = r0 + threadIdx.x;
+        const bool valid = i < b1;
+        const int bin = valid ? cost_bin(cost[i]) : 0;
+        const unsigned long long m = same_bin(bin, valid);
+        const int leader = __ffsll((long long)m) - 1;
+        uint32_t first = 0u;
+        if (valid && leader == lane) first = atomicAdd(&h[bin], (uint32_t)__popcll(m));
+        first = __shfl(first, leader < 0 ? 0 : leader);
+        if (valid) {
+            const uint32_t pos = base[bin] + first + (uint32_t)__popcll(m & lt);
+            if (pos < H) {
+                HeavyEntry e;
+                e.pair = (int32_t)i;
+                e.nnodes = 1;  // from the root
+                e.lvl[0] = e.lvl[1] = e.lvl[2] = 0;
+                e.pad = 0;
+                e.tstar = __builtin_huge_val();
+                e.n_enq = 0;
+                e.node_off = -1;
+                heavy[pos] = e;
+            } else {
+                const uint64_t r = (uint64_t)(pos - H);
+                order[(r * S) % nl] = (int32_t)i;
+            }
+        }
     }
 }
 
@@ -390,9 +474,9 @@ void launch_mlp_predict(const float *params, const float *norm, const float *fea
 {
     if (n == 0) return;
     const int64_t tiles = (n + 15) / 16;
-    int64_t blocks = (tiles + kWaves - 1) / kWaves;
+    int64_t blocks = (tiles + 3) / 4;
     if (blocks > 2048) blocks = 2048;
-    mlp_predict_kernel<<<(unsigned)blocks, 64 * kWaves, 0, s>>>(params, norm, feat, n, out);
+    mlp_predict_kernel<<<(unsigned)blocks, 256, 0, s>>>(params, norm, feat, n, out);
 }
 
 void launch_mlp_grad(const float *params, const float *norm, const float *feat, const float *label, int64_t n,
@@ -415,15 +499,21 @@ void launch_adam(float *params, const float *grad, float *m, float *v, int64_t s
                                                            c1, c2);
 }
 
-void launch_cost_order(const float *cost, int64_t n, int32_t *order, uint32_t *scratch, hipStream_t s)
+void launch_cost_schedule(const float *cost, int64_t n, float threshold, int max_heavy, int32_t *order,
+                          HeavyEntry *heavy, unsigned int *counters, uint32_t *scratch, bool hist_ready, hipStream_t s)
 {
-    zero_u32_kernel<<<1, kCostBins, 0, s>>>(scratch, kCostBins);
-    if (n == 0) return;
-    int64_t blocks = (n + 4095) / 4096;
+    // scratch: histogram, cursors, info
+    int64_t blocks = (n + 1023) / 1024;
     if (blocks > 1024) blocks = 1024;
-    cost_hist_kernel<<<(unsigned)blocks, 256, 0, s>>>(cost, n, scratch);
-    cost_scan_kernel<<<1, kCostBins, 0, s>>>(scratch, scratch + kCostBins);
-    cost_scatter_kernel<<<(unsigned)blocks, 256, 0, s>>>(cost, n, scratch + kCostBins, order);
+    if (!hist_ready) {
+        zero_u32_kernel<<<1, kCostBins, 0, s>>>(scratch, kCostBins);
+        if (n > 0) cost_hist_kernel<<<(unsigned)blocks, 256, 0, s>>>(cost, n, scratch);
+    }
+    cost_scan_kernel<<<1, kCostBins, 0, s>>>(scratch, scratch + kCostBins, scratch + 2 * kCostBins, n, threshold,
+                                             max_heavy < 0 ? 0 : max_heavy, counters);
+    if (n > 0)
+        cost_scatter_kernel<<<(unsigned)blocks, 256, 0, s>>>(cost, n, scratch + kCostBins, scratch + 2 * kCostBins,
+                                                            order, heavy);
 }
 
 }  // namespace ccd

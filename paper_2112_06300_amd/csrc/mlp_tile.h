@@ -1,0 +1,130 @@
+// mlp_tile.h -- forward pass of the scheduling MLP (16 -> 64 -> 64 -> 1) for 16
+// pairs at a time on one wave, with the weights held in registers.
+//
+// v_mfma_f32_16x16x16_bf16 lane layout (lane l, r = l % 16, g = 4 (l / 16),
+// j = 0..3): A[r][g + j], B[g + j][r], D[g + j][r].  Both layers are computed
+// transposed -- H1^T = W1^T X^T and Z2^T = W2^T H1^T -- so that the first
+// layer's D fragment (rows g + j of H1^T, column r) is exactly the second
+// layer's B fragment, and no activation passes through LDS.  Weights and
+// activations are bf16, accumulation float32; biases, the last layer and the
+// normalization stay float32.
+#pragma once
+
+#include "ccd_internal.h"
+
+namespace ccd {
+
+typedef short mlp_bf16x4 __attribute__((ext_vector_type(4)));
+typedef float mlp_f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kMlpOffW1 = 0;
+constexpr int kMlpOffB1 = kMlpOffW1 + kNumFeatures * kHidden;
+constexpr int kMlpOffW2 = kMlpOffB1 + kHidden;
+constexpr int kMlpOffB2 = kMlpOffW2 + kHidden * kHidden;
+constexpr int kMlpOffW3 = kMlpOffB2 + kHidden;
+constexpr int kMlpOffB3 = kMlpOffW3 + kHidden;
+
+// float -> bf16, round to nearest even (finite inputs)
+__device__ __forceinline__ short mlp_bf16(float x)
+{
+    uint32_t u = __float_as_uint(x);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (short)(u >> 16);
+}
+
+// Weight fragments of one lane: a1[ob] = block ob of W1^T, a2[ob][kb] = block
+// (ob, kb) of W2^T.
+struct MlpWeights {
+    mlp_bf16x4 a1[4];
+    mlp_bf16x4 a2[4][4];
+};
+
+// Per-workgroup constants (LDS).
+struct MlpConsts {
+    float b1[kHidden], b2[kHidden], w3[kHidden];
+    float mean[kNumFeatures], istd[kNumFeatures];
+    float b3;
+};
+
+__device__ __forceinline__ void mlp_load_weights(MlpWeights &W, const float *__restrict__ prm, int lane)
+{
+    const int r = lane & 15, g = (lane >> 4) * 4;
+#pragma unroll
+    for (int ob = 0; ob < 4; ob++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) W.a1[ob][j] = mlp_bf16(prm[kMlpOffW1 + (g + j) * kHidden + 16 * ob + r]);
+#pragma unroll
+    for (int ob = 0; ob < 4; ob++)
+#pragma unroll
+        for (int kb = 0; kb < 4; kb++)
+#pragma unroll
+            for (int j = 0; j < 4; j++)
+                W.a2[ob][kb][j] = mlp_bf16(prm[kMlpOffW2 + (16 * kb + g + j) * kHidden + 16 * ob + r]);
+}
+
+// Block-wide: fills C (the caller synchronizes before use).
+__device__ __forceinline__ void mlp_load_consts(MlpConsts &C, const float *__restrict__ prm,
+                                                const float *__restrict__ norm)
+{
+    for (int i = threadIdx.x; i < kHidden; i += blockDim.x) {
+        C.b1[i] = prm[kMlpOffB1 + i];
+        C.b2[i] = prm[kMlpOffB2 + i];
+        C.w3[i] = prm[kMlpOffW3 + i];
+    }
+    for (int i = threadIdx.x; i < kNumFeatures; i += blockDim.x) {
+        C.mean[i] = norm[i];
+        C.istd[i] = norm[kNumFeatures + i];
+    }
+    if (threadIdx.x == 0) C.b3 = prm[kMlpOffB3];
+}
+
+// The layer-1 B fragment: features g .. g + 3 of the tile's row r, normalized
+// and rounded to bf16.
+__device__ __forceinline__ mlp_bf16x4 mlp_input(const MlpConsts &C, const float f[4], int lane)
+{
+    const int g = (lane >> 4) * 4;
+    mlp_bf16x4 x;
+#pragma unroll
+    for (int j = 0; j < 4; j++) x[j] = mlp_bf16((f[j] - C.mean[g + j]) * C.istd[g + j]);
+    return x;
+}
+
+// Prediction for the tile's row r = lane % 16 (every lane of a row holds it).
+__device__ __forceinline__ float mlp_forward(const MlpWeights &W, const MlpConsts &C, mlp_bf16x4 x, int lane)
+{
+    const int g = (lane >> 4) * 4;
+    mlp_bf16x4 h1[4];
+#pragma unroll
+    for (int ob = 0; ob < 4; ob++) {
+        mlp_f32x4 acc;
+#pragma unroll
+        for (int j = 0; j < 4; j++) acc[j] = C.b1[16 * ob + g + j];
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(W.a1[ob], x, acc, 0, 0, 0);
+#pragma unroll
+        for (int j = 0; j < 4; j++) h1[ob][j] = mlp_bf16(fmaxf(acc[j], 0.f));
+    }
+    float s = 0.f;
+#pragma unroll
+    for (int ob = 0; ob < 4; ob++) {
+        mlp_f32x4 acc;
+#pragma unroll
+        for (int j = 0; j < 4; j++) acc[j] = C.b2[16 * ob + g + j];
+#pragma unroll
+        for (int kb = 0; kb < 4; kb++) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(W.a2[ob][kb], h1[kb], acc, 0, 0, 0);
+#pragma unroll
+        for (int j = 0; j < 4; j++) s += fmaxf(acc[j], 0.f) * C.w3[16 * ob + g + j];
+    }
+    s += __shfl_xor(s, 16);
+    s += __shfl_xor(s, 32);
+    return s + C.b3;
+}
+
+// Bin of a predicted cost for the schedule's ordering: 256 bins of 1/4 in
+// log2 cost, costliest first.
+__device__ __forceinline__ int sched_cost_bin(float c)
+{
+    const int b = (int)(c * 4.f);
+    return 255 - (b < 0 ? 0 : (b > 255 ? 255 : b));
+}
+
+}  // namespace ccd

@@ -21,6 +21,7 @@
 //          levels above 21, continue in a workgroup of their own with the
 //          frontier in HBM scratch.
 #include "ccd_internal.h"
+#include "mlp_tile.h"
 
 namespace ccd {
 
@@ -192,16 +193,15 @@ __device__ __forceinline__ void unpack_m(uint32_t mp, int m[3])
 // prep: vertex ids, C_eps and split levels of every pair.  ids.x = -1 marks a
 // pair with an index out of range, ids.x = -2 one with a bad coordinate.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void prep_kernel(const double *__restrict__ V0, const double *__restrict__ V1,
-                                                  int64_t nv, const int32_t *__restrict__ vf, int64_t n_vf,
-                                                  const int32_t *__restrict__ ee, int64_t n_ee,
-                                                  const int32_t *__restrict__ E, int64_t ne,
-                                                  const int32_t *__restrict__ F, int64_t nf, double delta,
-                                                  int4 *ids4, double *peps, uint32_t *pm, uint32_t *flags)
+// Pair p: ids, C_eps and split levels written for the search.  Returns true
+// (and the pair's coordinates in raw) for a valid pair.
+__device__ __forceinline__ bool prep_pair(int64_t p, int64_t n_vf, const double *__restrict__ V0,
+                                          const double *__restrict__ V1, int64_t nv, const int32_t *__restrict__ vf,
+                                          const int32_t *__restrict__ ee, const int32_t *__restrict__ E, int64_t ne,
+                                          const int32_t *__restrict__ F, int64_t nf, double delta, int4 *ids4,
+                                          double *peps, uint32_t *pm, uint32_t *flags, double raw[24],
+                                          double eps[3], uint32_t &mp)
 {
-    const int64_t n = n_vf + n_ee;
-    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (p >= n) return;
     int32_t id[4] = {-1, -1, -1, -1};
     bool ok;
     if (p < n_vf) {
@@ -221,22 +221,42 @@ __global__ __launch_bounds__(256) void prep_kernel(const double *__restrict__ V0
     if (!ok) {
         atomicOr(flags, FLAG_BAD_INDEX);
         ids4[p] = make_int4(-1, 0, 0, 0);
-        return;
+        return false;
     }
     const int4 ids = make_int4(id[0], id[1], id[2], id[3]);
-    double raw[24], eps[3];
     load_raw(ids, V0, V1, raw);
-    uint32_t mp = 0u;
+    mp = 0u;
     if (!pair_constants(p < n_vf, raw, delta, eps, mp)) {
         atomicOr(flags, FLAG_NONFINITE);
         ids4[p] = make_int4(-2, 0, 0, 0);
-        return;
+        return false;
     }
     ids4[p] = ids;
     peps[3 * p] = eps[0];
     peps[3 * p + 1] = eps[1];
     peps[3 * p + 2] = eps[2];
     pm[p] = mp;
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// prep: vertex ids, C_eps and split levels of every pair.  ids.x = -1 marks a
+// pair with an index out of range, ids.x = -2 one with a bad coordinate.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void prep_kernel(const double *__restrict__ V0, const double *__restrict__ V1,
+                                                  int64_t nv, const int32_t *__restrict__ vf,
+                                                  const int32_t *__restrict__ ee, PairCounts pc,
+                                                  const int32_t *__restrict__ E, int64_t ne,
+                                                  const int32_t *__restrict__ F, int64_t nf, double delta,
+                                                  int4 *ids4, double *peps, uint32_t *pm, uint32_t *flags)
+{
+    int64_t n_vf, n;
+    pc.get(n_vf, n);
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= n) return;
+    double raw[24], eps[3];
+    uint32_t mp;
+    prep_pair(p, n_vf, V0, V1, nv, vf, ee, E, ne, F, nf, delta, ids4, peps, pm, flags, raw, eps, mp);
 }
 
 // F on axis a at one point (t, u, v) with the canonical sequence of process().
@@ -249,90 +269,150 @@ __device__ __forceinline__ double eval_point(const double raw[24], bool vf, int 
     return fma(u, P[1] - P[0], P[0]) - fma(v, P[3] - P[2], P[2]);
 }
 
-__device__ __forceinline__ float log_ratio(double x, double delta) { return (float)log2(1.0 + fabs(x) / delta); }
+// log2(1 + |x| / delta) in float32 (a feature, not a result)
+__device__ __forceinline__ float log_ratio(double x, double delta) { return log2f((float)(1.0 + fabs(x) / delta)); }
 
-// Scheduling features of every pair (16 floats; pair order as in prep).  They
-// describe how hard the pair's search will be -- derivative bounds, the
-// root-level inclusion box against C_eps, F at the parameter-space centre at
-// t = 0, 1/2, 1 -- and never influence a result.  A pair with a bad index gets
-// zeros.
+// Scheduling features of one pair (16 floats).  They describe how hard the
+// pair's search will be -- derivative bounds, the root-level inclusion box
+// against C_eps, F at the parameter-space centre at t = 0, 1/2, 1 -- and never
+// influence a result.
+__device__ __forceinline__ void pair_features(const double raw[24], bool vf, const double eps[3], uint32_t mp,
+                                              double delta, float f[kNumFeatures])
+{
+    f[0] = vf ? 0.f : 1.f;
+    f[1] = (float)(mp & 255u);
+    f[2] = (float)((mp >> 8) & 255u);
+    f[3] = (float)((mp >> 16) & 255u);
+    double Lt = 0.0, Lu = 0.0, Lv = 0.0;
+    double gap = -__builtin_huge_val(), wmin = __builtin_huge_val(), wmax = 0.0;
+    int straddle = 0;
+    for (int a = 0; a < 3; a++) {
+        double dd[4];
+        for (int k = 0; k < 4; k++) dd[k] = raw[12 + 3 * k + a] - raw[3 * k + a];
+        double lt, lu, lv;
+        if (vf) {
+            lt = ((fabs(dd[0]) + fabs(dd[1])) + fabs(dd[2])) + fabs(dd[3]);
+            lu = fmax(fabs(raw[6 + a] - raw[3 + a]), fabs(raw[18 + a] - raw[15 + a]));
+            lv = fmax(fabs(raw[9 + a] - raw[3 + a]), fabs(raw[21 + a] - raw[15 + a]));
+        } else {
+            lt = fmax(fabs(dd[0]), fabs(dd[1])) + fmax(fabs(dd[2]), fabs(dd[3]));
+            lu = fmax(fabs(raw[3 + a] - raw[0 + a]), fabs(raw[15 + a] - raw[12 + a]));
+            lv = fmax(fabs(raw[9 + a] - raw[6 + a]), fabs(raw[21 + a] - raw[18 + a]));
+        }
+        Lt = fmax(Lt, lt);
+        Lu = fmax(Lu, lu);
+        Lv = fmax(Lv, lv);
+        double bmin = __builtin_huge_val(), bmax = -__builtin_huge_val();
+        for (int c = 0; c < 8; c++) {
+            const double fv = eval_point(raw, vf, a, (double)(c & 1), (double)((c >> 1) & 1), (double)(c >> 2));
+            bmin = fmin(bmin, fv);
+            bmax = fmax(bmax, fv);
+        }
+        const double e = eps[a];
+        gap = fmax(gap, fmax(bmin - e, -e - bmax));
+        wmin = fmin(wmin, bmax - bmin);
+        wmax = fmax(wmax, bmax - bmin);
+        straddle += (bmin <= e && bmax >= -e) ? 1 : 0;
+    }
+    f[4] = log_ratio(Lt, delta);
+    f[5] = log_ratio(Lu, delta);
+    f[6] = log_ratio(Lv, delta);
+    f[7] = (gap > 0.0 ? 1.f : -1.f) * log_ratio(gap, delta);
+    f[8] = log_ratio(wmin, delta);
+    f[9] = log_ratio(wmax, delta);
+    f[10] = (float)straddle;
+    const double uc = vf ? 1.0 / 3.0 : 0.5, vc = uc;
+    double F0[3], F1[3], Fm[3];
+    for (int a = 0; a < 3; a++) {
+        F0[a] = eval_point(raw, vf, a, 0.0, uc, vc);
+        F1[a] = eval_point(raw, vf, a, 1.0, uc, vc);
+        Fm[a] = eval_point(raw, vf, a, 0.5, uc, vc);
+    }
+    const double n0 = sqrt(F0[0] * F0[0] + F0[1] * F0[1] + F0[2] * F0[2]);
+    const double n1 = sqrt(F1[0] * F1[0] + F1[1] * F1[1] + F1[2] * F1[2]);
+    const double nm = sqrt(Fm[0] * Fm[0] + Fm[1] * Fm[1] + Fm[2] * Fm[2]);
+    f[11] = log_ratio(n0, delta);
+    f[12] = log_ratio(n1, delta);
+    f[13] = log_ratio(nm, delta);
+    int flips = 0;
+    for (int a = 0; a < 3; a++) flips += ((F0[a] > 0.0) != (F1[a] > 0.0)) ? 1 : 0;
+    f[14] = (float)flips;
+    const double dot = F0[0] * F1[0] + F0[1] * F1[1] + F0[2] * F1[2];
+    f[15] = (float)(n0 > 0.0 && n1 > 0.0 ? dot / (n0 * n1) : 0.0);
+}
+
+// Features of every pair (pair order as in prep); a pair with a bad index gets zeros.
 __global__ __launch_bounds__(256) void feature_kernel(const double *__restrict__ V0, const double *__restrict__ V1,
                                                      const int4 *__restrict__ ids4, const double *__restrict__ peps,
-                                                     const uint32_t *__restrict__ pm, int64_t n_vf, int64_t n,
+                                                     const uint32_t *__restrict__ pm, PairCounts pc,
                                                      double delta, float *feat)
 {
+    int64_t n_vf, n;
+    pc.get(n_vf, n);
     const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (p >= n) return;
     float f[kNumFeatures];
     for (int i = 0; i < kNumFeatures; i++) f[i] = 0.f;
     const int4 id = ids4[p];
     if (id.x >= 0) {
-        const bool vf = p < n_vf;
         double raw[24];
         load_raw(id, V0, V1, raw);
-        const uint32_t mp = pm[p];
-        f[0] = vf ? 0.f : 1.f;
-        f[1] = (float)(mp & 255u);
-        f[2] = (float)((mp >> 8) & 255u);
-        f[3] = (float)((mp >> 16) & 255u);
-        double Lt = 0.0, Lu = 0.0, Lv = 0.0;
-        double gap = -__builtin_huge_val(), wmin = __builtin_huge_val(), wmax = 0.0;
-        int straddle = 0;
-        for (int a = 0; a < 3; a++) {
-            double dd[4];
-            for (int k = 0; k < 4; k++) dd[k] = raw[12 + 3 * k + a] - raw[3 * k + a];
-            double lt, lu, lv;
-            if (vf) {
-                lt = ((fabs(dd[0]) + fabs(dd[1])) + fabs(dd[2])) + fabs(dd[3]);
-                lu = fmax(fabs(raw[6 + a] - raw[3 + a]), fabs(raw[18 + a] - raw[15 + a]));
-                lv = fmax(fabs(raw[9 + a] - raw[3 + a]), fabs(raw[21 + a] - raw[15 + a]));
-            } else {
-                lt = fmax(fabs(dd[0]), fabs(dd[1])) + fmax(fabs(dd[2]), fabs(dd[3]));
-                lu = fmax(fabs(raw[3 + a] - raw[0 + a]), fabs(raw[15 + a] - raw[12 + a]));
-                lv = fmax(fabs(raw[9 + a] - raw[6 + a]), fabs(raw[21 + a] - raw[18 + a]));
-            }
-            Lt = fmax(Lt, lt);
-            Lu = fmax(Lu, lu);
-            Lv = fmax(Lv, lv);
-            double bmin = __builtin_huge_val(), bmax = -__builtin_huge_val();
-            for (int c = 0; c < 8; c++) {
-                const double fv = eval_point(raw, vf, a, (double)(c & 1), (double)((c >> 1) & 1), (double)(c >> 2));
-                bmin = fmin(bmin, fv);
-                bmax = fmax(bmax, fv);
-            }
-            const double e = peps[3 * p + a];
-            gap = fmax(gap, fmax(bmin - e, -e - bmax));
-            wmin = fmin(wmin, bmax - bmin);
-            wmax = fmax(wmax, bmax - bmin);
-            straddle += (bmin <= e && bmax >= -e) ? 1 : 0;
-        }
-        f[4] = log_ratio(Lt, delta);
-        f[5] = log_ratio(Lu, delta);
-        f[6] = log_ratio(Lv, delta);
-        f[7] = (gap > 0.0 ? 1.f : -1.f) * log_ratio(gap, delta);
-        f[8] = log_ratio(wmin, delta);
-        f[9] = log_ratio(wmax, delta);
-        f[10] = (float)straddle;
-        const double uc = vf ? 1.0 / 3.0 : 0.5, vc = uc;
-        double F0[3], F1[3], Fm[3];
-        for (int a = 0; a < 3; a++) {
-            F0[a] = eval_point(raw, vf, a, 0.0, uc, vc);
-            F1[a] = eval_point(raw, vf, a, 1.0, uc, vc);
-            Fm[a] = eval_point(raw, vf, a, 0.5, uc, vc);
-        }
-        const double n0 = sqrt(F0[0] * F0[0] + F0[1] * F0[1] + F0[2] * F0[2]);
-        const double n1 = sqrt(F1[0] * F1[0] + F1[1] * F1[1] + F1[2] * F1[2]);
-        const double nm = sqrt(Fm[0] * Fm[0] + Fm[1] * Fm[1] + Fm[2] * Fm[2]);
-        f[11] = log_ratio(n0, delta);
-        f[12] = log_ratio(n1, delta);
-        f[13] = log_ratio(nm, delta);
-        int flips = 0;
-        for (int a = 0; a < 3; a++) flips += ((F0[a] > 0.0) != (F1[a] > 0.0)) ? 1 : 0;
-        f[14] = (float)flips;
-        const double dot = F0[0] * F1[0] + F0[1] * F1[1] + F0[2] * F1[2];
-        f[15] = (float)(n0 > 0.0 && n1 > 0.0 ? dot / (n0 * n1) : 0.0);
+        const double eps[3] = {peps[3 * p], peps[3 * p + 1], peps[3 * p + 2]};
+        pair_features(raw, p < n_vf, eps, pm[p], delta, f);
     }
     for (int i = 0; i < kNumFeatures; i++) feat[p * kNumFeatures + i] = f[i];
+}
+
+// The learned schedule's first pass, fused: prep of every pair, its features
+// (kept in LDS), the cost model's prediction on the matrix cores (a wave runs
+// its 64 pairs as 4 tiles of 16), and the histogram of predicted-cost bins
+// (1/4 in log2 cost, costliest first) for the ordering.  Grid-stride over
+// chunks of 256 pairs.
+__global__ __launch_bounds__(256) void prep_sched_kernel(
+    const double *__restrict__ V0, const double *__restrict__ V1, int64_t nv, const int32_t *__restrict__ vf,
+    const int32_t *__restrict__ ee, PairCounts pc, const int32_t *__restrict__ E, int64_t ne,
+    const int32_t *__restrict__ F, int64_t nf, double delta, int4 *ids4, double *peps, uint32_t *pm,
+    uint32_t *flags, const float *__restrict__ prm, const float *__restrict__ norm, float *cost, uint32_t *hist)
+{
+    __shared__ MlpConsts C;
+    __shared__ float xs[4][64][kNumFeatures + 1];
+    __shared__ uint32_t h[256];
+    mlp_load_consts(C, prm, norm);
+    h[threadIdx.x] = 0u;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int r = lane & 15, g = (lane >> 4) * 4;
+    MlpWeights Wt;
+    mlp_load_weights(Wt, prm, lane);
+    __syncthreads();
+    int64_t n_vf, n;
+    pc.get(n_vf, n);
+    for (int64_t c0 = (int64_t)blockIdx.x * 256; c0 < n; c0 += (int64_t)gridDim.x * 256) {
+        const int64_t p = c0 + threadIdx.x;
+        float f[kNumFeatures];
+        for (int i = 0; i < kNumFeatures; i++) f[i] = 0.f;
+        if (p < n) {
+            double raw[24], eps[3];
+            uint32_t mp;
+            if (prep_pair(p, n_vf, V0, V1, nv, vf, ee, E, ne, F, nf, delta, ids4, peps, pm, flags, raw, eps, mp))
+                pair_features(raw, p < n_vf, eps, mp, delta, f);
+        }
+        for (int i = 0; i < kNumFeatures; i++) xs[w][lane][i] = f[i];
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+            const float fx[4] = {xs[w][16 * t + r][g], xs[w][16 * t + r][g + 1], xs[w][16 * t + r][g + 2],
+                                 xs[w][16 * t + r][g + 3]};
+            const float y = mlp_forward(Wt, C, mlp_input(C, fx, lane), lane);
+            const int64_t q = c0 + 64 * w + 16 * t + r;
+            const bool mine = lane < 16 && q < n;
+            if (mine) cost[q] = y;
+            if (mine) atomicAdd(&h[sched_cost_bin(y)], 1u);
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    if (h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
 }
 
 __device__ __forceinline__ int wave_excl_scan(int v, int lane, int &total)
@@ -398,11 +478,15 @@ __device__ __forceinline__ int slot_split(uint32_t lvp, uint32_t mp, int &lk)
 //     the slot (atomic min of t*, survivor count).
 __global__ __launch_bounds__(kPoolSlots) void pool_kernel(
     const double *__restrict__ V0, const double *__restrict__ V1, const int4 *__restrict__ ids4,
-    const double *__restrict__ peps, const uint32_t *__restrict__ pm, int64_t n_vf, int64_t n_pairs,
+    const double *__restrict__ peps, const uint32_t *__restrict__ pm, PairCounts pc,
     double delta, long long max_iter, uint8_t *hit, double *toi, long long *n_enq_out, HeavyEntry *heavy,
-    unsigned long long *hnodes, int64_t hnode_cap, unsigned int *counters, const int32_t *__restrict__ order)
+    unsigned long long *hnodes, int64_t hnode_cap, unsigned int *counters, const int32_t *__restrict__ order,
+    const uint32_t *__restrict__ order_n)
 {
     __shared__ PoolLds S;
+    int64_t n_vf, n_pairs;
+    pc.get(n_vf, n_pairs);
+    if (order_n) n_pairs = (int64_t)*order_n;
     const int lane = threadIdx.x;
     const unsigned long long lt_mask = (1ull << lane) - 1ull;
     // wave-uniform claim state: current chunk [ch_cur, ch_end) and the next chunk, claimed ahead
@@ -684,7 +768,7 @@ __device__ __forceinline__ long long wave_sum_ll(long long v)
 // number of work items.
 __global__ __launch_bounds__(kHeavyBlock) void heavy_kernel(
     const double *__restrict__ V0, const double *__restrict__ V1, const int4 *__restrict__ ids4,
-    const double *__restrict__ peps, const uint32_t *__restrict__ pm, int64_t n_vf, double delta,
+    const double *__restrict__ peps, const uint32_t *__restrict__ pm, PairCounts pc, double delta,
     long long max_iter, uint8_t *hit, double *toi, long long *n_enq_out, const HeavyEntry *__restrict__ heavy,
     const unsigned long long *__restrict__ hnodes, const int32_t *list, const unsigned int *list_count,
     unsigned int *next, int32_t *ovf_list, unsigned int *ovf_count, unsigned long long *scratch, int64_t cap,
@@ -698,6 +782,9 @@ __global__ __launch_bounds__(kHeavyBlock) void heavy_kernel(
     __shared__ long long s_cnt[kHeavyBlock / 64];
     __shared__ double s_tmin[kHeavyBlock / 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    int64_t n_vf, n_all;
+    pc.get(n_vf, n_all);
+    (void)n_all;
     unsigned long long *A = scratch + (int64_t)blockIdx.x * 6 * cap;
     unsigned long long *Bb = A + 3 * cap;
     for (;;) {
@@ -843,9 +930,11 @@ __global__ __launch_bounds__(kHeavyBlock) void heavy_kernel(
 
 __global__ void toi_init_kernel(double *out) { *out = __builtin_huge_val(); }
 
-__global__ __launch_bounds__(256) void toi_min_kernel(const double *__restrict__ toi, int64_t n, double *out)
+__global__ __launch_bounds__(256) void toi_min_kernel(const double *__restrict__ toi, PairCounts pc, double *out)
 {
     __shared__ double red[4];
+    int64_t n_vf, n;
+    pc.get(n_vf, n);
     double m = __builtin_huge_val();
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
         const double v = toi[i];
@@ -861,16 +950,61 @@ __global__ __launch_bounds__(256) void toi_min_kernel(const double *__restrict__
     }
 }
 
+// Earliest time of impact of every scene of a batch: the scene of a pair is
+// found from its vertex (VF) or first edge (EE) in the CSR offsets.
+__global__ void fill_inf_kernel(double *out, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = __builtin_huge_val();
+}
+
+__device__ __forceinline__ int64_t scene_of(const int64_t *__restrict__ off, int64_t S, int64_t i)
+{
+    int64_t lo = 0, hi = S;  // off[lo] <= i < off[hi]
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (off[mid] <= i) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void scene_min_kernel(const double *__restrict__ toi, PairCounts pc,
+                                                        const int32_t *__restrict__ vf, const int32_t *__restrict__ ee,
+                                                        const int64_t *__restrict__ v_off,
+                                                        const int64_t *__restrict__ e_off, int64_t S, double *out)
+{
+    int64_t n_vf, n;
+    pc.get(n_vf, n);
+    for (int64_t b = (int64_t)blockIdx.x * 256; b < n; b += (int64_t)gridDim.x * 256) {
+        const int64_t p = b + threadIdx.x;
+        int64_t sc = -1;
+        double t = __builtin_huge_val();
+        if (p < n) {
+            sc = p < n_vf ? scene_of(v_off, S, vf[2 * p]) : scene_of(e_off, S, ee[2 * (p - n_vf)]);
+            t = toi[p];
+        }
+        const int64_t s0 = __shfl(sc, 0);
+        if (__ballot(sc != s0) == 0ull) {
+            t = wave_min(t);
+            if ((threadIdx.x & 63) == 0 && t < __builtin_huge_val())
+                atomicMin((unsigned long long *)&out[s0], (unsigned long long)__double_as_longlong(t));
+        } else if (sc >= 0 && t < __builtin_huge_val()) {
+            atomicMin((unsigned long long *)&out[sc], (unsigned long long)__double_as_longlong(t));
+        }
+    }
+}
+
 __global__ void rerun_reset_kernel(unsigned int *c, int round)
 {
     c[2 + (round & 1)] = 0u;
     c[4] = 0u;
 }
 
-__global__ void counters_zero_kernel(unsigned int *c, int n, uint32_t *flags)
+__global__ void counters_zero_kernel(unsigned int *c, int n, uint32_t *flags, uint32_t *hist)
 {
     if ((int)threadIdx.x < n) c[threadIdx.x] = 0u;
     if (threadIdx.x == 0) *flags = 0u;
+    if (hist) hist[threadIdx.x] = 0u;
 }
 
 }  // namespace
@@ -883,37 +1017,53 @@ int pool_blocks_per_cu()
 }
 
 void launch_narrow_prep(const double *V0, const double *V1, int64_t nv, const int32_t *E, int64_t ne,
-                        const int32_t *F, int64_t nf, const int32_t *vf, int64_t n_vf, const int32_t *ee,
-                        int64_t n_ee, double delta, const NarrowBuffers &B, hipStream_t s)
+                        const int32_t *F, int64_t nf, const int32_t *vf, const int32_t *ee, PairCounts pc,
+                        double delta, const NarrowBuffers &B, hipStream_t s)
 {
-    counters_zero_kernel<<<1, 64, 0, s>>>(B.counters, 16, B.flags);
-    const int64_t n = n_vf + n_ee;
+    counters_zero_kernel<<<1, 64, 0, s>>>(B.counters, 16, B.flags, nullptr);
+    const int64_t n = pc.capacity();
     if (n == 0) return;
-    prep_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(V0, V1, nv, vf, n_vf, ee, n_ee, E, ne, F, nf, delta,
-                                                           B.ids4, B.eps, B.m, B.flags);
+    prep_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(V0, V1, nv, vf, ee, pc, E, ne, F, nf, delta, B.ids4,
+                                                           B.eps, B.m, B.flags);
 }
 
-void launch_narrow_features(const double *V0, const double *V1, int64_t n_vf, int64_t n_ee, double delta,
-                            const NarrowBuffers &B, float *feat, hipStream_t s)
+void launch_narrow_prep_sched(const double *V0, const double *V1, int64_t nv, const int32_t *E, int64_t ne,
+                              const int32_t *F, int64_t nf, const int32_t *vf, const int32_t *ee, PairCounts pc,
+                              double delta, const NarrowBuffers &B, const float *params, const float *norm,
+                              float *cost, uint32_t *hist, hipStream_t s)
 {
-    const int64_t n = n_vf + n_ee;
+    // counters, flags and the cost histogram start at zero
+    counters_zero_kernel<<<1, 256, 0, s>>>(B.counters, 16, B.flags, hist);
+    const int64_t n = pc.capacity();
     if (n == 0) return;
-    feature_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(V0, V1, B.ids4, B.eps, B.m, n_vf, n, delta, feat);
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    prep_sched_kernel<<<(unsigned)blocks, 256, 0, s>>>(V0, V1, nv, vf, ee, pc, E, ne, F, nf, delta, B.ids4, B.eps,
+                                                      B.m, B.flags, params, norm, cost, hist);
 }
 
-void launch_narrow_pool(const double *V0, const double *V1, int64_t n_vf, int64_t n_ee, double delta,
-                        long long max_iter, uint8_t *hit, double *toi, long long *n_enq, const NarrowBuffers &B,
-                        int pool_blocks, const int32_t *order, hipStream_t s)
+void launch_narrow_features(const double *V0, const double *V1, PairCounts pc, double delta, const NarrowBuffers &B,
+                            float *feat, hipStream_t s)
 {
-    const int64_t n = n_vf + n_ee;
+    const int64_t n = pc.capacity();
+    if (n == 0) return;
+    feature_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(V0, V1, B.ids4, B.eps, B.m, pc, delta, feat);
+}
+
+void launch_narrow_pool(const double *V0, const double *V1, PairCounts pc, double delta, long long max_iter,
+                        uint8_t *hit, double *toi, long long *n_enq, const NarrowBuffers &B, int pool_blocks,
+                        const int32_t *order, const uint32_t *order_n, hipStream_t s)
+{
+    const int64_t n = pc.capacity();
     if (n == 0) return;
     int64_t blocks = (n + kPoolSlots - 1) / kPoolSlots;
     if (blocks > pool_blocks) blocks = pool_blocks;
-    pool_kernel<<<(unsigned)blocks, kPoolSlots, 0, s>>>(V0, V1, B.ids4, B.eps, B.m, n_vf, n, delta, max_iter, hit,
-                                                       toi, n_enq, B.heavy, B.hnodes, B.hnode_cap, B.counters, order);
+    pool_kernel<<<(unsigned)blocks, kPoolSlots, 0, s>>>(V0, V1, B.ids4, B.eps, B.m, pc, delta, max_iter, hit, toi,
+                                                       n_enq, B.heavy, B.hnodes, B.hnode_cap, B.counters, order,
+                                                       order_n);
 }
 
-void launch_narrow_heavy(const double *V0, const double *V1, int64_t n_vf, double delta, long long max_iter,
+void launch_narrow_heavy(const double *V0, const double *V1, PairCounts pc, double delta, long long max_iter,
                          uint8_t *hit, double *toi, long long *n_enq, const NarrowBuffers &B, int nslots,
                          int64_t cap, int round, hipStream_t s)
 {
@@ -930,18 +1080,41 @@ void launch_narrow_heavy(const double *V0, const double *V1, int64_t n_vf, doubl
         next = &B.counters[4];
         rerun_reset_kernel<<<1, 1, 0, s>>>(B.counters, round);
     }
-    heavy_kernel<<<(unsigned)nslots, kHeavyBlock, 0, s>>>(V0, V1, B.ids4, B.eps, B.m, n_vf, delta, max_iter, hit,
+    heavy_kernel<<<(unsigned)nslots, kHeavyBlock, 0, s>>>(V0, V1, B.ids4, B.eps, B.m, pc, delta, max_iter, hit,
                                                           toi, n_enq, B.heavy, B.hnodes, list, count, next, ovf,
                                                           ovf_count, B.scratch, cap, B.flags);
 }
 
-void launch_toi_min(const double *toi, int64_t n, double *out, hipStream_t s)
+void launch_narrow_heavy_early(const double *V0, const double *V1, PairCounts pc, double delta, long long max_iter,
+                               uint8_t *hit, double *toi, long long *n_enq, const NarrowBuffers &B,
+                               unsigned long long *scratch, int nslots, int64_t cap, hipStream_t s)
+{
+    heavy_kernel<<<(unsigned)nslots, kHeavyBlock, 0, s>>>(V0, V1, B.ids4, B.eps, B.m, pc, delta, max_iter, hit, toi,
+                                                          n_enq, B.heavy, B.hnodes, nullptr, &B.counters[12],
+                                                          &B.counters[13], B.overflow_list[0], &B.counters[2],
+                                                          scratch, cap, B.flags);
+}
+
+void launch_toi_min(const double *toi, PairCounts pc, double *out, hipStream_t s)
 {
     toi_init_kernel<<<1, 1, 0, s>>>(out);
+    const int64_t n = pc.capacity();
     if (n == 0) return;
     int64_t blocks = (n + 255) / 256;
     if (blocks > 1024) blocks = 1024;
-    toi_min_kernel<<<(unsigned)blocks, 256, 0, s>>>(toi, n, out);
+    toi_min_kernel<<<(unsigned)blocks, 256, 0, s>>>(toi, pc, out);
+}
+
+void launch_scene_min(const double *toi, PairCounts pc, const int32_t *vf, const int32_t *ee, const int64_t *v_off,
+                      const int64_t *e_off, int64_t S, double *out, hipStream_t s)
+{
+    if (S == 0) return;
+    fill_inf_kernel<<<(unsigned)((S + 255) / 256), 256, 0, s>>>(out, S);
+    const int64_t n = pc.capacity();
+    if (n == 0) return;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 2048) blocks = 2048;
+    scene_min_kernel<<<(unsigned)blocks, 256, 0, s>>>(toi, pc, vf, ee, v_off, e_off, S, out);
 }
 
 }  // namespace ccd

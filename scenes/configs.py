@@ -118,6 +118,49 @@ def tiny_random_scene(seed, n_tris=6, extent=1.0, motion=0.6, dyadic_bits=None):
     return _scene("tiny_random", V0, V1, F, seed=seed)
 
 
+def scene_batch(seed=4, count=64, t_min=1e3, t_max=2e5):
+    """`count` scenes with log-uniform triangle counts in [t_min, t_max].
+
+    Types cycle cloth-on-sphere, two spheres, perturbed torus; scene i uses
+    seed 1000 + i and the resolution whose triangle count is nearest to its
+    target (icosphere levels only come in powers of 4).
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    targets = np.round(np.exp(rng.uniform(np.log(t_min), np.log(t_max), count))).astype(np.int64)
+    out = []
+    for i, t in enumerate(targets):
+        s = 1000 + i
+        if i % 3 == 0:
+            k = int(np.clip(np.round(np.log(max(t / 4.0, 20.0) / 20.0) / np.log(4.0)), 0, 5))
+            cloth = max(int(t) - 20 * 4 ** k, 8)
+            n = int(round(np.sqrt(cloth / 2.0))) + 1
+            out.append(cloth_on_sphere(seed=s, n=n, sphere_subdivisions=k))
+        elif i % 3 == 1:
+            k = int(np.clip(np.round(np.log(t / 40.0) / np.log(4.0)), 0, 6))
+            out.append(two_spheres(seed=s, subdivisions=k))
+        else:
+            nm = max(3, int(round(np.sqrt(t / 4.0))))
+            out.append(perturbed_torus(seed=s, n_major=2 * nm, n_minor=nm))
+        out[-1].meta["target_tris"] = int(t)
+    return out
+
+
+def concat_scenes(scenes):
+    """Concatenate scenes in CSR layout: (V0, V1, E, F, v_off, e_off, f_off), vertex ids global."""
+    v_off = np.zeros(len(scenes) + 1, np.int64)
+    e_off = np.zeros(len(scenes) + 1, np.int64)
+    f_off = np.zeros(len(scenes) + 1, np.int64)
+    for i, s in enumerate(scenes):
+        v_off[i + 1] = v_off[i] + s.nv
+        e_off[i + 1] = e_off[i] + s.ne
+        f_off[i + 1] = f_off[i] + s.nf
+    V0 = np.concatenate([s.V0 for s in scenes]) if scenes else np.zeros((0, 3))
+    V1 = np.concatenate([s.V1 for s in scenes]) if scenes else np.zeros((0, 3))
+    E = np.concatenate([s.E + v_off[i] for i, s in enumerate(scenes)]).astype(np.int32)
+    F = np.concatenate([s.F + v_off[i] for i, s in enumerate(scenes)]).astype(np.int32)
+    return V0, V1, E, F, v_off, e_off, f_off
+
+
 CONFIG_NAMES = {1: "two_spheres", 2: "cloth_on_sphere", 3: "perturbed_torus"}
 
 

@@ -7,8 +7,16 @@ def edges_of_faces(F):
     F = np.asarray(F, dtype=np.int64)
     e = np.concatenate([F[:, [0, 1]], F[:, [1, 2]], F[:, [2, 0]]], axis=0)
     e.sort(axis=1)
-    e = np.unique(e, axis=0)
-    return e.astype(np.int32)
+    return _unique_rows(e)[0].astype(np.int32)
+
+
+def _unique_rows(e):
+    """np.unique(e, axis=0, return_inverse=True) for non-negative (n, 2) int64 rows, via 1-D keys."""
+    if len(e) == 0:
+        return e.reshape(0, 2), np.zeros(0, np.int64)
+    m = int(e.max()) + 1
+    keys, inv = np.unique(e[:, 0] * m + e[:, 1], return_inverse=True)
+    return np.stack([keys // m, keys % m], 1), inv.reshape(-1)
 
 
 def icosphere(subdivisions, radius=1.0, center=(0.0, 0.0, 0.0)):
@@ -30,8 +38,7 @@ def icosphere(subdivisions, radius=1.0, center=(0.0, 0.0, 0.0)):
     for _ in range(subdivisions):
         e = np.concatenate([F[:, [0, 1]], F[:, [1, 2]], F[:, [2, 0]]], axis=0)
         e.sort(axis=1)
-        uniq, inv = np.unique(e, axis=0, return_inverse=True)
-        inv = inv.reshape(-1)
+        uniq, inv = _unique_rows(e)
         mids = V[uniq[:, 0]] + V[uniq[:, 1]]
         mids /= np.linalg.norm(mids, axis=1, keepdims=True)
         base = len(V)

@@ -178,7 +178,9 @@ def test_every_schedule_gives_identical_outputs(ctx, max_iter):
         print(f"schedules: {name} pairs={n} max_iter={max_iter}", flush=True)
         plain = narrow_with(ctx, s, vf, ee, None, max_iter)
         assert not np.any(plain[0] == 255) and not np.any(plain[3] == -7)
-        assert_identical(plain, narrow_with(ctx, s, vf, ee, ("learned", params, norm), max_iter))
+        # default early wide-stage share, every pair (up to 4096) early, and none early
+        for thr, mh in ((ccd.HEAVY_THRESHOLD, ccd.MAX_HEAVY), (-1e9, 4096), (0.0, 0)):
+            assert_identical(plain, narrow_with(ctx, s, vf, ee, ("learned", params, norm, thr, mh), max_iter))
         rng = np.random.Generator(np.random.PCG64(n))
         assert_identical(plain, narrow_with(ctx, s, vf, ee, ("order", rng.permutation(n).astype(np.int32)),
                                             max_iter))
@@ -219,6 +221,16 @@ def test_order_schedule_rejects_non_permutation(ctx, bad):
     assert e.value.status == ccd.CCD_ERR_INVALID_ARG
     # the context still works
     narrow_with(ctx, s, vf, ee, ("order", np.arange(n, dtype=np.int32)))
+
+
+def test_learned_schedule_rejects_bad_early_share(ctx):
+    s = scenes.tiny_random_scene(9, n_tris=12, extent=0.5, motion=1.0)
+    vf, ee = oracle.broad(s.V0, s.V1, s.E, s.F)
+    params, norm = random_model(6)
+    for thr, mh in ((10.0, -1), (10.0, 5000), (float("nan"), 16)):
+        with pytest.raises(ccd.CCDError) as e:
+            narrow_with(ctx, s, vf, ee, ("learned", params, norm, thr, mh))
+        assert e.value.status == ccd.CCD_ERR_INVALID_ARG
 
 
 def test_learned_schedule_rejects_missing_model(ctx):
