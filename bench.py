@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--cloth-n", type=int, default=256)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (for HBM counter scaling)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the 10M-pair torus and 64-scene batch figures reported beside the main line")
     return ap.parse_args()
 
 
@@ -86,6 +88,77 @@ def cpu_baseline(scene, gpu_pairs):
     }, flops, int(n_eval.sum())
 
 
+def extra_torus_10m(ctx, steps):
+    """Narrow phase on 10M pairs drawn from the gadget torus's candidates: learned vs plain schedule."""
+    import numpy as np
+    import torch
+    import scenes
+    from paper_2112_06300_amd import sched
+    s = scenes.perturbed_torus(seed=5, gadgets=sched.TORUS_GADGETS)
+    dev = lambda x, dt: torch.as_tensor(np.ascontiguousarray(x)).to("cuda", dt)
+    V0, V1, E, F = dev(s.V0, torch.float64), dev(s.V1, torch.float64), dev(s.E, torch.int32), dev(s.F, torch.int32)
+    cvf, cee = ctx.broad(V0, V1, E, F, vf_cap=60_000_000, ee_cap=200_000_000)
+    vf, ee = scenes.sample_pairs(cvf.cpu().numpy(), cee.cpu().numpy(), 10_000_000, seed=5)
+    del cvf, cee
+    vf, ee = dev(vf, torch.int32), dev(ee, torch.int32)
+    n = vf.shape[0] + ee.shape[0]
+    out = (torch.empty(n, dtype=torch.uint8, device="cuda"), torch.empty(n, dtype=torch.float64, device="cuda"),
+           torch.empty(1, dtype=torch.float64, device="cuda"), None)
+    try:
+        params, norm, meta = sched.load_model(sched.TORUS_MODEL_PATH)
+    except FileNotFoundError:
+        params, norm, meta = sched.load_model()
+    learned = ("learned", torch.as_tensor(params).cuda(), torch.as_tensor(norm).cuda(), ccd_mod().HEAVY_THRESHOLD,
+               ccd_mod().MAX_HEAVY)
+    res = {}
+    for name, sc in (("plain", None), ("learned", learned)):
+        ctx.narrow(V0, V1, E, F, vf, ee, DELTA, MAX_ITER, out=out, schedule=sc)
+        ms = []
+        for _ in range(steps):
+            ctx.narrow(V0, V1, E, F, vf, ee, DELTA, MAX_ITER, out=out, schedule=sc)
+            ms.append(ctx.stats()["narrow_ms"])
+        st = ctx.stats()
+        res[name] = {"narrow_ms_median": float(np.median(ms)), "pairs_per_s": n / (float(np.median(ms)) * 1e-3),
+                     "pool_ms": st["narrow_pool_ms"], "heavy_ms": st["narrow_heavy_ms"],
+                     "heavy_pairs": st["heavy_pairs"], "sched_heavy_pairs": st["sched_heavy_pairs"]}
+    return {"workload": f"10,000,000 pairs drawn (seed 5) from the candidates of the 1M-triangle perturbed torus "
+                        f"with {sched.TORUS_GADGETS} near-degenerate gadgets; narrow phase only, device events, "
+                        f"median of {steps}", "model": meta.get("train"), **res,
+            "learned_over_plain": res["learned"]["pairs_per_s"] / res["plain"]["pairs_per_s"]}
+
+
+def extra_batch64(ctx, steps):
+    """The 64-scene batch (1e3..2e5 triangles each) through one pass: captured graph vs eager launches."""
+    import numpy as np
+    import torch
+    import scenes
+    scs = scenes.scene_batch()
+    V0, V1, E, F, vo, eo, fo = scenes.concat_scenes(scs)
+    nb = int(vo[-1] + eo[-1] + fo[-1])
+    b = ccd_mod().Batch(ctx, vo, eo, fo, 3 * nb, 6 * nb)
+    dev = lambda x, dt: torch.as_tensor(np.ascontiguousarray(x)).to("cuda", dt)
+    inp = (dev(V0, torch.float64), dev(V1, torch.float64), dev(E, torch.int32), dev(F, torch.int32))
+    res = {}
+    for name, g in (("eager", False), ("graph", True)):
+        b.run(*inp, DELTA, MAX_ITER, use_graph=g)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            b.run(*inp, DELTA, MAX_ITER, use_graph=g)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1000.0 / steps
+        res[name] = {"ms_per_pass": ms, "pairs_per_s": (b.n_vf + b.n_ee) / (ms * 1e-3)}
+    out = {"workload": f"64 scenes, {int(fo[-1])} triangles, {nb} boxes, CSR layout, broad + narrow in one pass",
+           "pairs": b.n_vf + b.n_ee, **res}
+    b.close()
+    return out
+
+
+def ccd_mod():
+    import paper_2112_06300_amd as ccd
+    return ccd
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -131,6 +204,7 @@ def main():
         st_n = ctx.stats()
         return n_vf, n_ee, st_b, st_n
 
+    extras = {}
     b_keys = ("broad_ms", "box_ms", "sort_ms", "gather_ms", "sweep_ms")
     n_keys = ("narrow_ms", "narrow_prep_ms", "narrow_sched_ms", "narrow_pool_ms", "narrow_heavy_ms",
               "heavy_pairs", "sched_heavy_pairs")
@@ -165,6 +239,10 @@ def main():
     # ids for the pair filter, pair write
     broad_bytes = (48 * nv + 8 * ne + 12 * nf) + 24 * nb + 16 * nb + 28 * nb + (4 * nv + 8 * ne + 12 * nf) + 8 * pairs
     broad_gbs = broad_bytes / (stage["broad_ms"] * 1e-3) / 1e9
+
+    if not args.no_extras:
+        extras["torus_10M_pairs"] = extra_torus_10m(ctx, steps=5)
+        extras["batch_64_scenes"] = extra_batch64(ctx, steps=5)
 
     cpu = None
     flops = None
@@ -228,6 +306,7 @@ def main():
         "cpu_baseline": cpu,
         "stages_ms": stage,
         "broad_hbm": {"alg_bytes": broad_bytes, "achieved_gbs": broad_gbs, "frac": broad_gbs / HBM_PEAK_GBS},
+        "extras": extras,
         "narrow_fp64": {"alg_flops": flops, "canonical_evals": n_eval, "achieved_tflops": narrow_tflops,
                         "frac": (narrow_tflops / FP64_PEAK_TFLOPS if narrow_tflops else None),
                         "plain_achieved_tflops": plain_narrow_tflops,

@@ -237,9 +237,9 @@ ccd_status ccd_set_tuning(ccd_context *ctx, const ccd_tuning *tuning);
 ccd_status ccd_get_tuning(ccd_context *ctx, ccd_tuning *tuning);
 
 /*
- * Batches (Sec. 4.4 runs scenes of uneven size through fixed device buffers):
- * S scenes processed by one pass of the broad and narrow phases, pairs never
- * crossing scenes.  The scenes are concatenated in CSR layout: scene s owns
+ * Batches of scenes (not in the paper, whose batching, Sec. 5.4, splits one
+ * scene to fit the device memory): S scenes of uneven size processed by one
+ * pass of the broad and narrow phases, pairs never crossing scenes.  The scenes are concatenated in CSR layout: scene s owns
  * vertices [v_off[s], v_off[s+1]), edges [e_off[s], e_off[s+1]) and faces
  * [f_off[s], f_off[s+1]) of the concatenated V0, V1, E, F, whose vertex ids
  * are GLOBAL (already offset).  Offsets are HOST arrays of S + 1 values

@@ -144,8 +144,8 @@ __global__ __launch_bounds__(256) void mlp_predict_kernel(const float *__restric
     __shared__ MlpConsts C;
     mlp_load_consts(C, prm, norm);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    MlpWeights Wt;
-    mlp_load_weights(Wt, prm, lane);
+    __shared__ MlpWeights Wt;
+    mlp_load_weights(Wt, prm);
     __syncthreads();
     const int r = lane & 15, g = (lane >> 4) * 4;
     const int64_t tiles = (n + 15) / 16;

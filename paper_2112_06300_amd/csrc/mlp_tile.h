@@ -1,5 +1,6 @@
 // mlp_tile.h -- forward pass of the scheduling MLP (16 -> 64 -> 64 -> 1) for 16
-// pairs at a time on one wave, with the weights held in registers.
+// pairs at a time on one wave, with the weights as ready-made MFMA fragments
+// in LDS (one 8-byte read per operand).
 //
 // v_mfma_f32_16x16x16_bf16 lane layout (lane l, r = l % 16, g = 4 (l / 16),
 // j = 0..3): A[r][g + j], B[g + j][r], D[g + j][r].  Both layers are computed
@@ -32,11 +33,10 @@ __device__ __forceinline__ short mlp_bf16(float x)
     return (short)(u >> 16);
 }
 
-// Weight fragments of one lane: a1[ob] = block ob of W1^T, a2[ob][kb] = block
-// (ob, kb) of W2^T.
+// Weight fragments, per lane: frag[ob] = block ob of W1^T, frag[4 + 4 ob + kb]
+// = block (ob, kb) of W2^T (LDS, 10 KB).
 struct MlpWeights {
-    mlp_bf16x4 a1[4];
-    mlp_bf16x4 a2[4][4];
+    mlp_bf16x4 frag[20][64];
 };
 
 // Per-workgroup constants (LDS).
@@ -46,20 +46,23 @@ struct MlpConsts {
     float b3;
 };
 
-__device__ __forceinline__ void mlp_load_weights(MlpWeights &W, const float *__restrict__ prm, int lane)
+// Block-wide: fills W (the caller synchronizes before use).
+__device__ __forceinline__ void mlp_load_weights(MlpWeights &W, const float *__restrict__ prm)
 {
-    const int r = lane & 15, g = (lane >> 4) * 4;
+    for (int idx = threadIdx.x; idx < 20 * 64; idx += blockDim.x) {
+        const int fr = idx >> 6, lane = idx & 63;
+        const int r = lane & 15, g = (lane >> 4) * 4;
+        mlp_bf16x4 v;
+        if (fr < 4) {
 #pragma unroll
-    for (int ob = 0; ob < 4; ob++)
+            for (int j = 0; j < 4; j++) v[j] = mlp_bf16(prm[kMlpOffW1 + (g + j) * kHidden + 16 * fr + r]);
+        } else {
+            const int ob = (fr - 4) >> 2, kb = (fr - 4) & 3;
 #pragma unroll
-        for (int j = 0; j < 4; j++) W.a1[ob][j] = mlp_bf16(prm[kMlpOffW1 + (g + j) * kHidden + 16 * ob + r]);
-#pragma unroll
-    for (int ob = 0; ob < 4; ob++)
-#pragma unroll
-        for (int kb = 0; kb < 4; kb++)
-#pragma unroll
-            for (int j = 0; j < 4; j++)
-                W.a2[ob][kb][j] = mlp_bf16(prm[kMlpOffW2 + (16 * kb + g + j) * kHidden + 16 * ob + r]);
+            for (int j = 0; j < 4; j++) v[j] = mlp_bf16(prm[kMlpOffW2 + (16 * kb + g + j) * kHidden + 16 * ob + r]);
+        }
+        W.frag[fr][lane] = v;
+    }
 }
 
 // Block-wide: fills C (the caller synchronizes before use).
@@ -92,6 +95,9 @@ __device__ __forceinline__ mlp_bf16x4 mlp_input(const MlpConsts &C, const float 
 // Prediction for the tile's row r = lane % 16 (every lane of a row holds it).
 __device__ __forceinline__ float mlp_forward(const MlpWeights &W, const MlpConsts &C, mlp_bf16x4 x, int lane)
 {
+    // read the fragments from LDS here rather than keeping all 20 in registers
+    // across the caller's loop
+    asm volatile("" ::: "memory");
     const int g = (lane >> 4) * 4;
     mlp_bf16x4 h1[4];
 #pragma unroll
@@ -99,7 +105,7 @@ __device__ __forceinline__ float mlp_forward(const MlpWeights &W, const MlpConst
         mlp_f32x4 acc;
 #pragma unroll
         for (int j = 0; j < 4; j++) acc[j] = C.b1[16 * ob + g + j];
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(W.a1[ob], x, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(W.frag[ob][lane], x, acc, 0, 0, 0);
 #pragma unroll
         for (int j = 0; j < 4; j++) h1[ob][j] = mlp_bf16(fmaxf(acc[j], 0.f));
     }
@@ -110,7 +116,8 @@ __device__ __forceinline__ float mlp_forward(const MlpWeights &W, const MlpConst
 #pragma unroll
         for (int j = 0; j < 4; j++) acc[j] = C.b2[16 * ob + g + j];
 #pragma unroll
-        for (int kb = 0; kb < 4; kb++) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(W.a2[ob][kb], h1[kb], acc, 0, 0, 0);
+        for (int kb = 0; kb < 4; kb++)
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(W.frag[4 + 4 * ob + kb][lane], h1[kb], acc, 0, 0, 0);
 #pragma unroll
         for (int j = 0; j < 4; j++) s += fmaxf(acc[j], 0.f) * C.w3[16 * ob + g + j];
     }

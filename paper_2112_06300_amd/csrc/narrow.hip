@@ -303,6 +303,7 @@ __device__ __forceinline__ void pair_features(const double raw[24], bool vf, con
         Lu = fmax(Lu, lu);
         Lv = fmax(Lv, lv);
         double bmin = __builtin_huge_val(), bmax = -__builtin_huge_val();
+#pragma unroll 1
         for (int c = 0; c < 8; c++) {
             const double fv = eval_point(raw, vf, a, (double)(c & 1), (double)((c >> 1) & 1), (double)(c >> 2));
             bmin = fmin(bmin, fv);
@@ -381,8 +382,8 @@ __global__ __launch_bounds__(256) void prep_sched_kernel(
     h[threadIdx.x] = 0u;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int r = lane & 15, g = (lane >> 4) * 4;
-    MlpWeights Wt;
-    mlp_load_weights(Wt, prm, lane);
+    __shared__ MlpWeights Wt;
+    mlp_load_weights(Wt, prm);
     __syncthreads();
     int64_t n_vf, n;
     pc.get(n_vf, n);
@@ -399,7 +400,7 @@ __global__ __launch_bounds__(256) void prep_sched_kernel(
         for (int i = 0; i < kNumFeatures; i++) xs[w][lane][i] = f[i];
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-#pragma unroll
+#pragma unroll 1
         for (int t = 0; t < 4; t++) {
             const float fx[4] = {xs[w][16 * t + r][g], xs[w][16 * t + r][g + 1], xs[w][16 * t + r][g + 2],
                                  xs[w][16 * t + r][g + 3]};
@@ -443,7 +444,21 @@ struct PoolLds {
 };
 
 constexpr unsigned long long kInfBits = 0x7ff0000000000000ull;
-constexpr int kNoExpand = -1, kHandNodes = -2;
+constexpr int kNoExpand = -1, kHandNodes = -2, kCarry = -3;
+// A queue entry carried into the next round unsplit (its pair is waiting for
+// room for its children) has this bit set; numerators use bits 0..62.
+constexpr unsigned long long kCarryBit = 1ull << 63;
+
+// Queue offsets of this round's pushes: pairs that waited last round first,
+// then the others, each group in lane order.
+__device__ __forceinline__ int push_offset(bool pushing, bool first, int n, int lane, int &total)
+{
+    int t1 = 0, t2 = 0;
+    const int o1 = wave_excl_scan(pushing && first ? n : 0, lane, t1);
+    const int o2 = wave_excl_scan(pushing && !first ? n : 0, lane, t2);
+    total = t1 + t2;
+    return first ? o1 : t1 + o2;
+}
 
 __device__ __forceinline__ double node_tlo(unsigned long long nd, double tscale)
 {
@@ -500,6 +515,7 @@ __global__ __launch_bounds__(kPoolSlots) void pool_kernel(
     bool okb = false;
     // the pair this lane owns (slot = lane)
     bool active = false;
+    bool waiting = false;  // the pair's children did not fit last round
     long long p = -1;
     bool vf = false;
     int m[3] = {0, 0, 0}, l[3] = {0, 0, 0};
@@ -580,7 +596,7 @@ __global__ __launch_bounds__(kPoolSlots) void pool_kernel(
         }
         __syncthreads();
         // ---- E (owner lanes): decide, queue offsets, outputs, hand-overs, new roots
-        int outcome = 0;  // 1 finished, 2 capped, 3 hand over, 4 push the next level
+        int outcome = 0;  // 1 finished, 2 capped, 3 hand over, 4 push the next level, 5 wait
         int k = -1, push = 0, nsurv = 0;
         double tmin = __builtin_huge_val();
         if (active) {
@@ -602,10 +618,24 @@ __global__ __launch_bounds__(kPoolSlots) void pool_kernel(
             }
         }
         int total = 0;
-        int off = wave_excl_scan(outcome == 4 ? push : 0, lane, total);
+        int off = push_offset(outcome == 4, waiting, push, lane, total);
+        int coff = 0;
         if (total > kQCap) {
-            if (outcome == 4 && off + push > kQCap) outcome = 3;
-            off = wave_excl_scan(outcome == 4 ? push : 0, lane, total);
+            // Children that do not fit this round: a pair whose children could
+            // never fit goes to the wide stage; the others wait, carrying their
+            // survivors unsplit into the next round's queue (the level, t* and
+            // n_enq do not change while a pair waits).  The first pusher always
+            // fits, so some pair advances every round.
+            if (outcome == 4 && off + push > kQCap) outcome = push > kQCap ? 3 : 5;
+            off = push_offset(outcome == 4, waiting, push, lane, total);
+            int ctotal = 0;
+            coff = wave_excl_scan(outcome == 5 ? nsurv : 0, lane, ctotal);
+            if (total + ctotal > kQCap) {
+                if (outcome == 5 && total + coff + nsurv > kQCap) outcome = 3;
+                coff = wave_excl_scan(outcome == 5 ? nsurv : 0, lane, ctotal);
+            }
+            coff += total;
+            total += ctotal;
         }
         S.k[lane] = kNoExpand;
         S.pos[lane] = 0;
@@ -644,7 +674,11 @@ __global__ __launch_bounds__(kPoolSlots) void pool_kernel(
             S.k[lane] = k;
             S.off[lane] = off;
             S.lv[lane] = (uint32_t)l[0] | ((uint32_t)l[1] << 8) | ((uint32_t)l[2] << 16) | ((uint32_t)vf << 24);
+        } else if (outcome == 5) {
+            S.k[lane] = kCarry;
+            S.off[lane] = coff;
         }
+        waiting = outcome == 5;
         if (!active && pb >= 0 && !okb) {
             // a pair with a bad index or coordinate: reported as no collision (the call returns an error)
             hit[pb] = 0;
@@ -704,6 +738,10 @@ __global__ __launch_bounds__(kPoolSlots) void pool_kernel(
                     }
                 } else if (ks == kHandNodes) {
                     hnodes[S.hoff[s] + (unsigned long long)atomicAdd(&S.pos[s], 1)] = nd;
+                } else if (ks == kCarry) {
+                    const int q = S.off[s] + atomicAdd(&S.pos[s], 1);
+                    S.node[nxt][q] = nd | kCarryBit;
+                    S.slot[nxt][q] = (uint8_t)s;
                 }
             }
         }
@@ -713,7 +751,13 @@ __global__ __launch_bounds__(kPoolSlots) void pool_kernel(
         // ---- EVAL: one queued interval per lane, any slot; results folded into the slot
         for (int b0 = 0; b0 < T; b0 += kPoolSlots) {
             const int e = b0 + lane;
-            if (e < T) {
+            if (e < T && (S.node[nxt][e] & kCarryBit)) {
+                // a waiting pair's survivor: already evaluated, still to be split
+                const int s = S.slot[nxt][e];
+                S.node[nxt][e] &= ~kCarryBit;
+                S.res[e] = (uint8_t)SPLIT;
+                atomicAdd(&S.nsurv[s], 1);
+            } else if (e < T) {
                 const int s = S.slot[nxt][e];
                 const unsigned long long nd = S.node[nxt][e];
                 const uint32_t lvp = S.lv[s];

@@ -23,7 +23,10 @@ import numpy as np
 from . import MODEL_PARAMS, NUM_FEATURES, HIDDEN, Context
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-MODEL_PATH = os.path.join(HERE, "sched_model.npz")
+MODEL_PATH = os.path.join(HERE, "sched_model.npz")              # cloth on sphere
+TORUS_MODEL_PATH = os.path.join(HERE, "sched_model_torus.npz")  # perturbed torus with degenerate gadgets
+# Near-degenerate gadgets in the perturbed-torus workload: about 1 % of its candidate pairs.
+TORUS_GADGETS = 12000
 # Bumped whenever the feature definitions in the feature kernel change: a model
 # trained on other features is refused.
 FEATURE_VERSION = 1
@@ -119,21 +122,32 @@ def load_model(path=MODEL_PATH):
 
 def main():
     ap = argparse.ArgumentParser(description="train the narrow-phase cost model on the GPU")
-    ap.add_argument("--out", default=MODEL_PATH)
-    ap.add_argument("--seeds", default="12,13", help="cloth-on-sphere scene seeds to log costs from")
+    ap.add_argument("--workload", choices=["cloth", "torus"], default="cloth")
+    ap.add_argument("--out", default=None)
+    ap.add_argument("--seeds", default=None, help="scene seeds to log costs from (cloth 12,13; torus 13)")
     ap.add_argument("--cloth-n", type=int, default=256)
-    ap.add_argument("--eval-seed", type=int, default=22)
+    ap.add_argument("--eval-seed", type=int, default=None)
     ap.add_argument("--steps", type=int, default=1500)
     ap.add_argument("--batch", type=int, default=16384)
     ap.add_argument("--lr", type=float, default=3e-3)
     args = ap.parse_args()
     import torch
     import scenes
+    torus = args.workload == "torus"
+    out = args.out or (TORUS_MODEL_PATH if torus else MODEL_PATH)
+    seeds = args.seeds or ("13" if torus else "12,13")
+    eval_seed = args.eval_seed if args.eval_seed is not None else (23 if torus else 22)
+
+    def make(seed):
+        if torus:
+            return scenes.perturbed_torus(seed=seed, gadgets=TORUS_GADGETS)
+        return scenes.cloth_on_sphere(seed=seed, n=args.cloth_n)
+
     ctx = Context(0)
     t0 = time.perf_counter()
     feats, labels = [], []
-    for s in [int(x) for x in args.seeds.split(",")]:
-        f, l = cost_logs(ctx, scenes.cloth_on_sphere(seed=s, n=args.cloth_n))
+    for s in [int(x) for x in seeds.split(",")]:
+        f, l = cost_logs(ctx, make(s))
         feats.append(f)
         labels.append(l)
         print(f"seed {s}: {f.shape[0]} pairs logged", flush=True)
@@ -145,15 +159,16 @@ def main():
     t2 = time.perf_counter()
     for step, l in hist:
         print(f"step {step}: minibatch mse {l:.4f}", flush=True)
-    fe, le = cost_logs(ctx, scenes.cloth_on_sphere(seed=args.eval_seed, n=args.cloth_n))
+    fe, le = cost_logs(ctx, make(eval_seed))
     pred = ctx.mlp_predict(params, norm, fe)
     rho = spearman(pred.cpu().numpy(), le.cpu().numpy())
     mse = float(((pred - le) ** 2).mean().item())
-    meta = {"train": f"cloth_on_sphere n={args.cloth_n} seeds {args.seeds}", "pairs": int(feat.shape[0]),
+    name = f"perturbed_torus gadgets={TORUS_GADGETS}" if torus else f"cloth_on_sphere n={args.cloth_n}"
+    meta = {"train": f"{name} seeds {seeds}", "pairs": int(feat.shape[0]),
             "steps": args.steps, "batch": args.batch, "lr": args.lr, "label": "log2(1 + n_enq)",
-            "eval": f"cloth_on_sphere n={args.cloth_n} seed {args.eval_seed}", "eval_pairs": int(fe.shape[0]),
+            "eval": f"{name} seed {eval_seed}", "eval_pairs": int(fe.shape[0]),
             "eval_mse": mse, "eval_spearman": rho, "train_seconds": t2 - t1, "log_seconds": t1 - t0}
-    save_model(args.out, params.cpu().numpy(), norm.cpu().numpy(), meta)
+    save_model(out, params.cpu().numpy(), norm.cpu().numpy(), meta)
     print(json.dumps(meta), flush=True)
     ctx.close()
 

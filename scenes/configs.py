@@ -86,11 +86,14 @@ def cloth_on_sphere(seed=2, n=256, side=3.0, sphere_subdivisions=5, noise=0.3, d
     return _scene("cloth_on_sphere", V0, V1, F, seed=seed, n=n, mean_edge=ebar)
 
 
-def perturbed_torus(seed=3, n_major=1000, n_minor=500, R=1.0, r=0.4, rest_noise=0.1, noise=0.5):
+def perturbed_torus(seed=3, n_major=1000, n_minor=500, R=1.0, r=0.4, rest_noise=0.1, noise=0.5, gadgets=0):
     """Closed torus surface with Gaussian vertex perturbations.
 
     t=0 positions are the torus plus N(0, (rest_noise*e)^2), t=1 positions add
     N(0, (noise*e)^2) per coordinate (e = mean edge length of the clean torus).
+    With gadgets > 0, that many near-degenerate two-triangle gadgets
+    (`degenerate_gadgets`) are placed inside the tube, where they pair only
+    with each other.
     """
     rng = np.random.Generator(np.random.PCG64(seed))
     V, F = torus(n_major, n_minor, R, r)
@@ -98,7 +101,78 @@ def perturbed_torus(seed=3, n_major=1000, n_minor=500, R=1.0, r=0.4, rest_noise=
     ebar = float(np.linalg.norm(V[E[:, 0]] - V[E[:, 1]], axis=1).mean())
     V0 = V + rng.normal(0.0, rest_noise * ebar, size=V.shape)
     V1 = V0 + rng.normal(0.0, noise * ebar, size=V.shape)
-    return _scene("perturbed_torus", V0, V1, F, seed=seed, mean_edge=ebar)
+    if gadgets > 0:
+        G0, G1, GF = degenerate_gadgets(rng, gadgets, ebar, R=R, tube=0.6 * r)
+        V0, V1, F = merge_meshes([(V0, V1, F), (G0, G1, GF)])
+    return _scene("perturbed_torus", V0, V1, F, seed=seed, mean_edge=ebar, gadgets=int(gadgets))
+
+
+# Gadget kinds: (pair type, path, separation / height in units of the mean edge)
+GADGET_KINDS = [("ee", "parallel", 0.0), ("vf", "interior", 0.0), ("ee", "parallel", 1e-12),
+                ("vf", "edge", 0.0), ("ee", "parallel", 1e-9), ("vf", "vertex", 0.0),
+                ("vf", "interior", 1e-12), ("vf", "edge", 1e-9), ("vf", "vertex", 1e-12)]
+
+
+def degenerate_gadgets(rng, count, ebar, R=1.0, tube=0.24):
+    """`count` two-triangle gadgets with near-degenerate contacts, inside a torus tube.
+
+    Every gadget is axis-aligned with dyadic coordinates (exactly representable,
+    so zero separations are exact) and sits on its own lattice cell within
+    distance `tube` of the circle of radius R in the z = 0 plane:
+      ee: a static triangle with an edge along x, and a triangle whose edge is
+          parallel to it at separation s (0, 1e-12 e or 1e-9 e) sliding along it;
+      vf: a static triangle in the plane z = 0 and a triangle whose lowest
+          vertex moves parallel to that plane at height s, through the face's
+          interior, along one of its edges, or through one of its vertices.
+    Returns (V0, V1, F) of all gadgets.
+    """
+    q = 2.0 ** -12
+    L, w = 2.0 ** -7, 2.0 ** -8          # edge length and triangle width
+    spacing = 4.0 * L
+    # lattice points inside the tube, in a seeded random order
+    n_ring = int(2.0 * np.pi * R / spacing)
+    k = int(tube / spacing)
+    pts = []
+    for i in range(n_ring):
+        th = 2.0 * np.pi * i / n_ring
+        for a in range(-k, k + 1):
+            for b in range(-k, k + 1):
+                if (a * a + b * b) * spacing * spacing <= tube * tube:
+                    rho = R + a * spacing
+                    pts.append((rho * np.cos(th), rho * np.sin(th), b * spacing))
+    pts = np.array(pts)
+    if count > len(pts):
+        raise ValueError(f"at most {len(pts)} gadgets fit in the tube")
+    pts = pts[rng.permutation(len(pts))[:count]]
+    pts = np.round(pts / q) * q
+    V0s, V1s, Fs = [], [], []
+    for g, c in enumerate(pts):
+        kind, path, sep = GADGET_KINDS[g % len(GADGET_KINDS)]
+        s = sep * ebar
+        if kind == "ee":
+            a = [(0, 0, 0), (L, 0, 0), (0, -w, 0)]
+            b = [(-L / 2, 0, s), (L / 2, 0, s), (-L / 2, 0, s + w)]
+            a1 = a
+            b1 = [(x + L, y, z) for x, y, z in b]   # slides along the static edge
+        else:
+            a = [(0, 0, 0), (L, 0, 0), (0, L, 0)]
+            a1 = a
+            if path == "interior":
+                p0, p1 = (-L / 4, L / 4, s), (L, L / 4, s)
+            elif path == "edge":
+                p0, p1 = (-L / 4, 0, s), (L + L / 4, 0, s)
+            else:
+                p0, p1 = (-L / 4, -L / 4, s), (L / 4, L / 4, s)
+            b = [p0, (p0[0] + w, p0[1], p0[2] + w), (p0[0], p0[1] + w, p0[2] + w)]
+            d = np.subtract(p1, p0)
+            b1 = [tuple(np.add(v, d)) for v in b]
+        base = 6 * g
+        V0s.append(np.array(a + b, np.float64) + c)
+        V1s.append(np.array(a1 + b1, np.float64) + c)
+        Fs.append(np.array([[base, base + 1, base + 2], [base + 3, base + 4, base + 5]], np.int64))
+    if count == 0:
+        return np.zeros((0, 3)), np.zeros((0, 3)), np.zeros((0, 3), np.int32)
+    return np.concatenate(V0s), np.concatenate(V1s), np.concatenate(Fs).astype(np.int32)
 
 
 def tiny_random_scene(seed, n_tris=6, extent=1.0, motion=0.6, dyadic_bits=None):
@@ -159,6 +233,25 @@ def concat_scenes(scenes):
     E = np.concatenate([s.E + v_off[i] for i, s in enumerate(scenes)]).astype(np.int32)
     F = np.concatenate([s.F + v_off[i] for i, s in enumerate(scenes)]).astype(np.int32)
     return V0, V1, E, F, v_off, e_off, f_off
+
+
+def sample_pairs(vf, ee, count, seed=5):
+    """`count` candidate pairs drawn with replacement from the candidates (vf, ee) of a scene.
+
+    The candidates are put in canonical (sorted) order first, so the draw does
+    not depend on the order a broad phase emitted them in; the VF / EE mix and
+    every other property of the candidate distribution (the degenerate share
+    among them) is kept in expectation.  Returns (vf_sample, ee_sample).
+    """
+    vf = np.asarray(vf, np.int32).reshape(-1, 2)
+    ee = np.asarray(ee, np.int32).reshape(-1, 2)
+    vf = vf[np.lexsort((vf[:, 1], vf[:, 0]))]
+    ee = ee[np.lexsort((ee[:, 1], ee[:, 0]))]
+    rng = np.random.Generator(np.random.PCG64(seed))
+    pick = rng.integers(0, len(vf) + len(ee), size=count)
+    pick.sort()
+    nvf = int(np.searchsorted(pick, len(vf)))
+    return vf[pick[:nvf]], ee[pick[nvf:] - len(vf)]
 
 
 CONFIG_NAMES = {1: "two_spheres", 2: "cloth_on_sphere", 3: "perturbed_torus"}

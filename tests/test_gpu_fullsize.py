@@ -1,0 +1,182 @@
+"""The full-size workloads on the GPU, checked against the oracle where it can follow.
+
+The 1M-triangle perturbed torus (with near-degenerate gadgets inside the tube)
+and the 64-scene batch are too large for the oracle's brute-force broad phase
+and for its narrow phase on every pair, so:
+  * broad phase: for sampled vertices, faces and edges, every overlapping
+    partner found by brute force over all boxes (the oracle's boxes) must be
+    among the GPU's pairs and vice versa;
+  * narrow phase: on a uniform sample of the GPU's pairs plus a sample of the
+    gadget pairs, hit / toi / n_enq must equal the oracle's bit for bit, and the
+    reported minimum must be the minimum of the per-pair times.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import scenes
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2112_06300_amd as ccd  # noqa: E402
+
+DELTA = 1e-6
+GADGETS = 9000
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = ccd.Context(0)
+    yield c
+    c.close()
+
+
+def dev(x, dt):
+    return torch.as_tensor(np.ascontiguousarray(x)).to("cuda", dt)
+
+
+def pair_set(a):
+    a = np.asarray(a, np.int64).reshape(-1, 2)
+    return set(map(tuple, a.tolist()))
+
+
+def check_broad_sampled(s, vf, ee, rng, n_sample=200):
+    lo, hi = oracle.boxes(s.V0, s.V1, s.E, s.F)
+    nv, ne = s.nv, s.ne
+    lv, hv = lo[:nv], hi[:nv]
+    le, he = lo[nv:nv + ne], hi[nv:nv + ne]
+    lf, hf = lo[nv + ne:], hi[nv + ne:]
+    F = np.asarray(s.F, np.int64)
+    E = np.asarray(s.E, np.int64)
+    by_v, by_f, by_e = {}, {}, {}
+    for v, f in vf:
+        by_v.setdefault(v, set()).add(f)
+        by_f.setdefault(f, set()).add(v)
+    for e, g in ee:
+        by_e.setdefault(e, set()).add(g)
+        by_e.setdefault(g, set()).add(e)
+    for v in rng.choice(nv, n_sample, replace=False):
+        hit = np.nonzero(np.all((lf <= hv[v]) & (lv[v] <= hf), axis=1))[0]
+        hit = hit[~np.any(F[hit] == v, axis=1)]
+        assert set(hit.tolist()) == by_v.get(v, set()), ("vertex", v)
+    for f in rng.choice(s.nf, n_sample, replace=False):
+        hit = np.nonzero(np.all((lv <= hf[f]) & (lf[f] <= hv), axis=1))[0]
+        hit = hit[~np.isin(hit, F[f])]
+        assert set(hit.tolist()) == by_f.get(f, set()), ("face", f)
+    for e in rng.choice(ne, n_sample, replace=False):
+        hit = np.nonzero(np.all((le <= he[e]) & (le[e] <= he), axis=1))[0]
+        share = (E[hit, 0] == E[e, 0]) | (E[hit, 0] == E[e, 1]) | (E[hit, 1] == E[e, 0]) | (E[hit, 1] == E[e, 1])
+        hit = hit[~share & (hit != e)]
+        assert set(hit.tolist()) == by_e.get(e, set()), ("edge", e)
+
+
+def check_narrow_sampled(s, vf, ee, hit, toi, nenq, idx):
+    nvf = len(vf)
+    svf = vf[idx[idx < nvf]]
+    see = ee[idx[idx >= nvf] - nvf]
+    oh, ot, on_, _, _ = oracle.narrow(s.V0, s.V1, s.E, s.F, svf, see, DELTA)
+    order = np.concatenate([idx[idx < nvf], idx[idx >= nvf]])
+    assert np.array_equal(hit[order], oh)
+    assert np.array_equal(toi[order].view(np.int64), ot.view(np.int64))
+    assert np.array_equal(nenq[order], on_)
+
+
+def test_torus_with_gadgets_sampled(ctx):
+    s = scenes.perturbed_torus(gadgets=GADGETS)
+    print(f"torus: nv={s.nv} ne={s.ne} nf={s.nf} gadgets={GADGETS}", flush=True)
+    V0, V1, E, F = dev(s.V0, torch.float64), dev(s.V1, torch.float64), dev(s.E, torch.int32), dev(s.F, torch.int32)
+    gvf, gee = ctx.broad(V0, V1, E, F, vf_cap=60_000_000, ee_cap=200_000_000)
+    hit, toi, tmin, nenq = ctx.narrow(V0, V1, E, F, gvf, gee, DELTA, 10 ** 6, with_costs=True)
+    torch.cuda.synchronize()
+    vf, ee = gvf.cpu().numpy(), gee.cpu().numpy()
+    hit, toi, nenq = hit.cpu().numpy(), toi.cpu().numpy(), nenq.cpu().numpy()
+    tmin = float(tmin.cpu()[0])
+    print(f"pairs {len(vf)} + {len(ee)}, hits {int(hit.sum())}, capped {int((nenq > 10 ** 6).sum())}", flush=True)
+    # no pair is reported twice
+    assert len(pair_set(vf)) == len(vf) and len(pair_set(ee)) == len(ee)
+    rng = np.random.Generator(np.random.PCG64(31))
+    check_broad_sampled(s, vf, ee, rng)
+    # narrow: uniform sample plus gadget pairs (vertex ids past the torus)
+    torus_nv = 1000 * 500
+    n = len(vf) + len(ee)
+    gad = np.concatenate([np.nonzero(vf[:, 0] >= torus_nv)[0], len(vf) + np.nonzero(
+        np.asarray(s.E)[ee[:, 0], 0] >= torus_nv)[0]])
+    assert len(gad) > 0
+    idx = np.unique(np.concatenate([rng.choice(n, 3000, replace=False), rng.choice(gad, min(120, len(gad)),
+                                                                                   replace=False)]))
+    check_narrow_sampled(s, vf, ee, hit, toi, nenq, idx)
+    assert np.float64(tmin).view(np.int64) == np.float64(toi.min()).view(np.int64)
+    # the gadgets are near-degenerate by construction: some of their pairs hit the cap
+    assert (nenq[gad] > 10 ** 6).any()
+
+
+def test_scene_batch_64_sampled(ctx):
+    scs = scenes.scene_batch()
+    V0, V1, E, F, vo, eo, fo = scenes.concat_scenes(scs)
+    nb = int(vo[-1] + eo[-1] + fo[-1])
+    print(f"batch: {len(scs)} scenes, {int(fo[-1])} triangles, {nb} boxes", flush=True)
+    b = ccd.Batch(ctx, vo, eo, fo, 3 * nb, 6 * nb)
+    inp = (dev(V0, torch.float64), dev(V1, torch.float64), dev(E, torch.int32), dev(F, torch.int32))
+    vf, ee, hit, toi, tmin, nenq = b.run(*inp, DELTA, 10 ** 6, use_graph=True, with_costs=True)
+    torch.cuda.synchronize()
+    vf, ee = vf.cpu().numpy(), ee.cpu().numpy()
+    hit, toi, tmin, nenq = hit.cpu().numpy(), toi.cpu().numpy(), tmin.cpu().numpy(), nenq.cpu().numpy()
+    rng = np.random.Generator(np.random.PCG64(41))
+    nvf = len(vf)
+    sv = np.searchsorted(vo, vf[:, 0], side="right") - 1
+    se = np.searchsorted(eo, ee[:, 0], side="right") - 1
+    for i in rng.choice(len(scs), 8, replace=False):
+        s = scs[i]
+        print(f"scene {i}: {s.name} nf={s.nf}", flush=True)
+        mv, me = np.nonzero(sv == i)[0], np.nonzero(se == i)[0]
+        lvf = vf[mv] - np.array([vo[i], fo[i]])
+        lee = ee[me] - eo[i]
+        check_broad_sampled(s, lvf, lee, rng, n_sample=100)
+        # narrow on a sample of the scene's pairs, in the scene's own ids
+        k = min(400, len(mv) + len(me))
+        pick = rng.choice(len(mv) + len(me), k, replace=False)
+        gidx = np.concatenate([mv, nvf + me])[pick]
+        loc = np.concatenate([np.arange(len(mv)), len(mv) + np.arange(len(me))])[pick]
+        svf = lvf[loc[loc < len(mv)]]
+        see = lee[loc[loc >= len(mv)] - len(mv)]
+        oh, ot, on_, _, _ = oracle.narrow(s.V0, s.V1, s.E, s.F, svf, see, DELTA)
+        order = np.concatenate([gidx[loc < len(mv)], gidx[loc >= len(mv)]])
+        assert np.array_equal(hit[order], oh)
+        assert np.array_equal(toi[order].view(np.int64), ot.view(np.int64))
+        assert np.array_equal(nenq[order], on_)
+        # the scene's minimum is the minimum over its pairs
+        own = np.concatenate([toi[mv], toi[nvf + me]])
+        ref = own.min() if len(own) else np.inf
+        assert np.float64(tmin[i]).view(np.int64) == np.float64(ref).view(np.int64)
+    b.close()
+
+
+def test_learned_schedule_10M_pairs_identical(ctx):
+    """10M candidate pairs drawn from the perturbed torus's candidates (degenerate share kept): the learned
+    schedule's outputs equal the plain schedule's on every pair, and the oracle's on a sample."""
+    from paper_2112_06300_amd import sched
+    s = scenes.perturbed_torus(seed=5, gadgets=sched.TORUS_GADGETS)
+    V0, V1, E, F = dev(s.V0, torch.float64), dev(s.V1, torch.float64), dev(s.E, torch.int32), dev(s.F, torch.int32)
+    cvf, cee = ctx.broad(V0, V1, E, F, vf_cap=60_000_000, ee_cap=200_000_000)
+    vf, ee = scenes.sample_pairs(cvf.cpu().numpy(), cee.cpu().numpy(), 10_000_000, seed=5)
+    print(f"10M pairs: {len(vf)} VF + {len(ee)} EE", flush=True)
+    try:
+        params, norm, _ = sched.load_model(sched.TORUS_MODEL_PATH)
+    except FileNotFoundError:
+        params, norm, _ = sched.load_model()
+    dvf, dee = dev(vf, torch.int32), dev(ee, torch.int32)
+    plain = [x.cpu().numpy() for x in ctx.narrow(V0, V1, E, F, dvf, dee, DELTA, 10 ** 6, with_costs=True)]
+    learned = [x.cpu().numpy() for x in ctx.narrow(V0, V1, E, F, dvf, dee, DELTA, 10 ** 6, with_costs=True,
+                                                  schedule=("learned", params, norm))]
+    st = ctx.stats()
+    print(f"learned: {st['sched_heavy_pairs']} pairs started in the wide stage", flush=True)
+    assert np.array_equal(plain[0], learned[0])
+    assert np.array_equal(plain[1].view(np.int64), learned[1].view(np.int64))
+    assert np.array_equal(plain[2].view(np.int64), learned[2].view(np.int64))
+    assert np.array_equal(plain[3], learned[3])
+    rng = np.random.Generator(np.random.PCG64(51))
+    idx = np.unique(rng.choice(len(vf) + len(ee), 2000, replace=False))
+    check_narrow_sampled(s, vf, ee, plain[0], plain[1], plain[3], idx)
