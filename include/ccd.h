@@ -223,14 +223,18 @@ ccd_status ccd_get_stats(ccd_context *ctx, ccd_stats *out);
  *   heavy_cap_log2      log2 of each wide-stage frontier buffer in intervals
  *                       (default 13); a frontier that outgrows it is re-run
  *                       with 8x larger buffers
+ *   heavy_lds           1: wide-stage frontiers of at most 512 intervals
+ *                       stay in LDS between levels (default 0)
  * ccd_set_tuning(ctx, NULL) restores the defaults.  INVALID_ARG when a value
- * is out of range (group 1..1024, blocks 0..64, slots 1..65536, cap 8..24).
+ * is out of range (group 1..1024, blocks 0..64, slots 1..65536, cap 8..24,
+ * lds 0..1).
  */
 typedef struct {
     int32_t sweep_tile_group;
     int32_t pool_blocks_per_cu;
     int32_t heavy_slots;
     int32_t heavy_cap_log2;
+    int32_t heavy_lds;
 } ccd_tuning;
 
 ccd_status ccd_set_tuning(ccd_context *ctx, const ccd_tuning *tuning);
@@ -262,7 +266,8 @@ ccd_status ccd_get_tuning(ccd_context *ctx, ccd_tuning *tuning);
  * as ccd_broad and ccd_narrow.  Calls on one batch must not overlap.
  *
  * ccd_batch_autotune: times batch passes over candidate tunings (coordinate
- * descent over tile group, pool blocks per CU and wide-stage slots) and sets
+ * descent over tile group, pool blocks per CU, wide-stage slots and LDS
+ * frontiers) and sets
  * the best on the context.  With cache_path the choice is stored under a
  * signature of the device and the workload's size, and a later call with the
  * same signature takes it from the file without timing.  Outputs as

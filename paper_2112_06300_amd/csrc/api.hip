@@ -88,6 +88,7 @@ ccd_tuning default_tuning()
     t.pool_blocks_per_cu = 0;
     t.heavy_slots = 1024;
     t.heavy_cap_log2 = 13;
+    t.heavy_lds = 0;
     return t;
 }
 
@@ -169,7 +170,7 @@ bool valid_tuning(const ccd_tuning &t)
 {
     return t.sweep_tile_group >= 1 && t.sweep_tile_group <= 1024 && t.pool_blocks_per_cu >= 0 &&
            t.pool_blocks_per_cu <= 64 && t.heavy_slots >= 1 && t.heavy_slots <= 65536 && t.heavy_cap_log2 >= 8 &&
-           t.heavy_cap_log2 <= 24;
+           t.heavy_cap_log2 <= 24 && (t.heavy_lds == 0 || t.heavy_lds == 1);
 }
 
 }  // namespace
@@ -445,14 +446,14 @@ ccd_status narrow_impl(ccd_context *c, const double *V0, const double *V1, int64
         // pairs predicted to outgrow the pool start in the wide stage now, beside the pool
         HIP_TRY(hipStreamWaitEvent(c->side, c->ev[5], 0));
         launch_narrow_heavy_early(V0, V1, pc, delta, (long long)max_iter, hit, toi, nenq, B,
-                                  B.scratch + (size_t)nslots * 6 * cap, early_slots, cap, c->side);
+                                  B.scratch + (size_t)nslots * 6 * cap, early_slots, cap, c->tune.heavy_lds, c->side);
         HIP_TRY(hipGetLastError());
         HIP_TRY(hipEventRecord(c->ev[6], c->side));
     }
     launch_narrow_pool(V0, V1, pc, delta, (long long)max_iter, hit, toi, nenq, B, pool_blocks(c), order, order_n, s);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(c->ev[2], s));
-    launch_narrow_heavy(V0, V1, pc, delta, (long long)max_iter, hit, toi, nenq, B, nslots, cap, 0, s);
+    launch_narrow_heavy(V0, V1, pc, delta, (long long)max_iter, hit, toi, nenq, B, nslots, cap, 0, c->tune.heavy_lds, s);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(c->ev[3], s));
     if (learned && early_slots > 0) HIP_TRY(hipStreamWaitEvent(s, c->ev[6], 0));
@@ -499,7 +500,8 @@ ccd_status narrow_impl(ccd_context *c, const double *V0, const double *V1, int64
         if (st != CCD_OK) return st;
         B.scratch = (unsigned long long *)c->scratch.base;
         HIP_TRY(hipEventRecord(c->ev[0], s));
-        launch_narrow_heavy(V0, V1, pc, delta, (long long)max_iter, hit, toi, nenq, B, nslots, cap, round, s);
+        launch_narrow_heavy(V0, V1, pc, delta, (long long)max_iter, hit, toi, nenq, B, nslots, cap, round,
+                            c->tune.heavy_lds, s);
         HIP_TRY(hipGetLastError());
         launch_toi_min(toi, pc, toi_min, s);
         HIP_TRY(hipGetLastError());
@@ -691,7 +693,7 @@ void batch_enqueue(ccd_batch *b, const BatchArgs &a, hipStream_t s)
     launch_narrow_pool(a.V0, a.V1, pc, a.delta, a.max_iter, a.hit, a.toi, a.n_enq, b->N, pool_blocks(c), nullptr,
                        nullptr, s);
     launch_narrow_heavy(a.V0, a.V1, pc, a.delta, a.max_iter, a.hit, a.toi, a.n_enq, b->N, b->heavy_slots,
-                        b->heavy_cap, 0, s);
+                        b->heavy_cap, 0, c->tune.heavy_lds, s);
     launch_scene_min(a.toi, pc, a.vf, a.ee, b->off, b->off + (b->S + 1), b->S, a.toi_min, s);
 }
 
@@ -784,7 +786,7 @@ ccd_status batch_pass(ccd_batch *b, const BatchArgs &a, bool use_graph, int64_t 
             if (st != CCD_OK) return st;
             N.scratch = (unsigned long long *)big.base;
             launch_narrow_heavy(a.V0, a.V1, pc, a.delta, a.max_iter, a.hit, a.toi, a.n_enq, N, nslots, cap, round,
-                                s);
+                                c->tune.heavy_lds, s);
             HIP_TRY(hipGetLastError());
             unsigned int *hc = (unsigned int *)c->host;
             HIP_TRY(hipMemcpyAsync(hc, N.counters, 16 * 4, hipMemcpyDeviceToHost, s));
@@ -810,7 +812,7 @@ ccd_status check_batch_args(ccd_batch *b, const BatchArgs &a, const int64_t *n_v
     return CCD_OK;
 }
 
-// Autotuner cache: one line per workload signature, "signature: g p s c".
+// Autotuner cache: one line per workload signature, "signature: group blocks slots cap lds".
 bool cache_lookup(const char *path, const char *sig, ccd_tuning *t)
 {
     if (!path) return false;
@@ -822,8 +824,8 @@ bool cache_lookup(const char *path, const char *sig, ccd_tuning *t)
     while (std::fgets(line, sizeof line, f)) {
         if (std::strncmp(line, sig, n) == 0 && line[n] == ':') {
             ccd_tuning v;
-            if (std::sscanf(line + n + 1, "%d %d %d %d", &v.sweep_tile_group, &v.pool_blocks_per_cu, &v.heavy_slots,
-                            &v.heavy_cap_log2) == 4 &&
+            if (std::sscanf(line + n + 1, "%d %d %d %d %d", &v.sweep_tile_group, &v.pool_blocks_per_cu,
+                            &v.heavy_slots, &v.heavy_cap_log2, &v.heavy_lds) == 5 &&
                 valid_tuning(v)) {
                 *t = v;
                 found = true;  // the last matching line wins
@@ -839,8 +841,8 @@ void cache_store(const char *path, const char *sig, const ccd_tuning &t)
     if (!path) return;
     FILE *f = std::fopen(path, "a");
     if (!f) return;
-    std::fprintf(f, "%s: %d %d %d %d\n", sig, t.sweep_tile_group, t.pool_blocks_per_cu, t.heavy_slots,
-                 t.heavy_cap_log2);
+    std::fprintf(f, "%s: %d %d %d %d %d\n", sig, t.sweep_tile_group, t.pool_blocks_per_cu, t.heavy_slots,
+                 t.heavy_cap_log2, t.heavy_lds);
     std::fclose(f);
 }
 
@@ -990,13 +992,14 @@ ccd_status ccd_batch_autotune(ccd_batch *b, const double *V0, const double *V1, 
     if (st != CCD_OK) return st;
     const int groups[] = {1, 4, 16, 64};
     const int slots[] = {256, 512, 1024, 2048};
-    for (int param = 0; param < 3; param++) {
-        const int ncand = param == 0 ? 4 : (param == 1 ? c->pool_per_cu_max : 4);
+    for (int param = 0; param < 4; param++) {
+        const int ncand = param == 0 ? 4 : (param == 1 ? c->pool_per_cu_max : (param == 2 ? 4 : 2));
         for (int i = 0; i < ncand; i++) {
             ccd_tuning t = best;
             if (param == 0) t.sweep_tile_group = groups[i];
             else if (param == 1) t.pool_blocks_per_cu = i + 1;
-            else t.heavy_slots = slots[i];
+            else if (param == 2) t.heavy_slots = slots[i];
+            else t.heavy_lds = i;
             if (std::memcmp(&t, &best, sizeof t) == 0) continue;
             float m = 0.f;
             st = measure(t, &m);

@@ -197,7 +197,7 @@ void launch_narrow_pool(const double *V0, const double *V1, PairCounts pc, doubl
 // concurrently with the pool on another stream.
 void launch_narrow_heavy_early(const double *V0, const double *V1, PairCounts pc, double delta, long long max_iter,
                                uint8_t *hit, double *toi, long long *n_enq, const NarrowBuffers &B,
-                               unsigned long long *scratch, int nslots, int64_t cap, hipStream_t s);
+                               unsigned long long *scratch, int nslots, int64_t cap, int use_lds, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Learned schedule: MLP kNumFeatures -> 64 -> 64 -> 1 on bf16 MFMA.
@@ -233,9 +233,10 @@ void launch_check_permutation(const int32_t *order, int64_t n, uint32_t *bits, u
 // Wide stage: `nslots` workgroups, each with a frontier buffer of `cap` nodes
 // (two buffers of 3 x cap uint64).  Round 0 works on every handed-over pair;
 // round r > 0 re-runs the pairs that overflowed their buffer in round r - 1.
+// use_lds: frontiers of at most 512 intervals stay in LDS between levels.
 void launch_narrow_heavy(const double *V0, const double *V1, PairCounts pc, double delta, long long max_iter,
                          uint8_t *hit, double *toi, long long *n_enq, const NarrowBuffers &B, int nslots,
-                         int64_t cap, int round, hipStream_t s);
+                         int64_t cap, int round, int use_lds, hipStream_t s);
 
 void launch_toi_min(const double *toi, PairCounts pc, double *out, hipStream_t s);
 // out[s] = earliest toi over the pairs of scene s (CSR vertex / edge offsets

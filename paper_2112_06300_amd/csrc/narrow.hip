@@ -28,6 +28,7 @@ namespace ccd {
 namespace {
 
 constexpr int kHeavyBlock = 256;
+constexpr int kHeavyLds = 512;  // wide-stage frontier intervals kept in LDS (24 KB: no occupancy cost)
 constexpr int kPoolSlots = 64;   // pairs in flight per wave (one owner lane each)
 constexpr int kQCap = 512;       // intervals per round per wave
 constexpr int kClaim = 64;       // pairs a wave claims from the global list at once
@@ -364,26 +365,26 @@ __global__ __launch_bounds__(256) void feature_kernel(const double *__restrict__
     for (int i = 0; i < kNumFeatures; i++) feat[p * kNumFeatures + i] = f[i];
 }
 
-// The learned schedule's first pass, fused: prep of every pair, its features
-// (kept in LDS), the cost model's prediction on the matrix cores (a wave runs
-// its 64 pairs as 4 tiles of 16), and the histogram of predicted-cost bins
-// (1/4 in log2 cost, costliest first) for the ordering.  Grid-stride over
-// chunks of 256 pairs.
-__global__ __launch_bounds__(256) void prep_sched_kernel(
-    const double *__restrict__ V0, const double *__restrict__ V1, int64_t nv, const int32_t *__restrict__ vf,
-    const int32_t *__restrict__ ee, PairCounts pc, const int32_t *__restrict__ E, int64_t ne,
-    const int32_t *__restrict__ F, int64_t nf, double delta, int4 *ids4, double *peps, uint32_t *pm,
-    uint32_t *flags, const float *__restrict__ prm, const float *__restrict__ norm, float *cost, uint32_t *hist)
+// The learned schedule's pass after prep: each pair's features (kept in
+// LDS), the cost model's prediction on the matrix cores (a wave runs its 64
+// pairs as 4 tiles of 16), and the histogram of predicted-cost bins (1/4 in
+// log2 cost, costliest first) for the ordering.  Grid-stride over chunks of
+// 256 pairs.
+__global__ __launch_bounds__(256) void sched_kernel(const double *__restrict__ V0, const double *__restrict__ V1,
+                                                    const int4 *__restrict__ ids4, const double *__restrict__ peps,
+                                                    const uint32_t *__restrict__ pm, PairCounts pc, double delta,
+                                                    const float *__restrict__ prm, const float *__restrict__ norm,
+                                                    float *cost, uint32_t *hist)
 {
     __shared__ MlpConsts C;
+    __shared__ MlpWeights Wt;
     __shared__ float xs[4][64][kNumFeatures + 1];
     __shared__ uint32_t h[256];
     mlp_load_consts(C, prm, norm);
+    mlp_load_weights(Wt, prm);
     h[threadIdx.x] = 0u;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int r = lane & 15, g = (lane >> 4) * 4;
-    __shared__ MlpWeights Wt;
-    mlp_load_weights(Wt, prm);
     __syncthreads();
     int64_t n_vf, n;
     pc.get(n_vf, n);
@@ -392,10 +393,13 @@ __global__ __launch_bounds__(256) void prep_sched_kernel(
         float f[kNumFeatures];
         for (int i = 0; i < kNumFeatures; i++) f[i] = 0.f;
         if (p < n) {
-            double raw[24], eps[3];
-            uint32_t mp;
-            if (prep_pair(p, n_vf, V0, V1, nv, vf, ee, E, ne, F, nf, delta, ids4, peps, pm, flags, raw, eps, mp))
-                pair_features(raw, p < n_vf, eps, mp, delta, f);
+            const int4 id = ids4[p];
+            if (id.x >= 0) {
+                double raw[24];
+                load_raw(id, V0, V1, raw);
+                const double eps[3] = {peps[3 * p], peps[3 * p + 1], peps[3 * p + 2]};
+                pair_features(raw, p < n_vf, eps, pm[p], delta, f);
+            }
         }
         for (int i = 0; i < kNumFeatures; i++) xs[w][lane][i] = f[i];
         __builtin_amdgcn_wave_barrier();
@@ -816,8 +820,11 @@ __global__ __launch_bounds__(kHeavyBlock) void heavy_kernel(
     long long max_iter, uint8_t *hit, double *toi, long long *n_enq_out, const HeavyEntry *__restrict__ heavy,
     const unsigned long long *__restrict__ hnodes, const int32_t *list, const unsigned int *list_count,
     unsigned int *next, int32_t *ovf_list, unsigned int *ovf_count, unsigned long long *scratch, int64_t cap,
-    uint32_t *flags)
+    uint32_t *flags, int use_lds)
 {
+    // Frontier of the next level: in LDS when it surely fits (at most twice the
+    // current frontier), else in this workgroup's HBM buffers.
+    __shared__ unsigned long long s_front[2][3 * kHeavyLds];
     __shared__ int s_idx;
     __shared__ unsigned long long s_tstar;  // live t* as bits (non-negative doubles order like uint64)
     __shared__ unsigned int s_nN;
@@ -857,6 +864,8 @@ __global__ __launch_bounds__(kHeavyBlock) void heavy_kernel(
         long long nenq = h.n_enq;
         int64_t nS = h.nnodes;
         unsigned long long *cur = A, *nxt = Bb;
+        int64_t cstride = cap, nstride = cap;
+        int cur_lds = -1, nxt_lds = -1;  // LDS buffer holding the frontier, or -1 (HBM)
         int state = 0;
         double tcap = 0.0;
         double tstart = h.tstar;
@@ -884,6 +893,16 @@ __global__ __launch_bounds__(kHeavyBlock) void heavy_kernel(
             const double tsnap = __longlong_as_double((long long)s_tstar);
             const double tscale = pow2neg(l[0]), uscale = pow2neg(l[1]), vscale = pow2neg(l[2]);
             const bool finest = l[0] == kMaxLevel && l[1] == kMaxLevel && l[2] == kMaxLevel;
+            // where this level's survivors go
+            if (use_lds && 2 * nS <= kHeavyLds) {
+                nxt_lds = cur_lds == 0 ? 1 : 0;
+                nxt = s_front[nxt_lds];
+                nstride = kHeavyLds;
+            } else {
+                nxt_lds = -1;
+                nxt = cur == A ? Bb : A;
+                nstride = cap;
+            }
             if (tid == 0) s_nN = 0u;
             __syncthreads();
             long long cnt = 0;
@@ -892,7 +911,7 @@ __global__ __launch_bounds__(kHeavyBlock) void heavy_kernel(
                 const int64_t i = b0 + tid;
                 const bool has = i < nS;
                 unsigned long long pn[3] = {0ull, 0ull, 0ull};
-                if (has) { pn[0] = cur[i]; pn[1] = cur[cap + i]; pn[2] = cur[2 * cap + i]; }
+                if (has) { pn[0] = cur[i]; pn[1] = cur[cstride + i]; pn[2] = cur[2 * cstride + i]; }
 #pragma unroll
                 for (int c = 0; c < 2; c++) {
                     unsigned long long cn[3] = {pn[0], pn[1], pn[2]};
@@ -918,8 +937,8 @@ __global__ __launch_bounds__(kHeavyBlock) void heavy_kernel(
                         base = __shfl(base, leader);
                         if (surv) {
                             const int64_t pos = (int64_t)base + __popcll(mask & ((1ull << lane) - 1ull));
-                            if (pos < cap) {
-                                nxt[pos] = cn[0]; nxt[cap + pos] = cn[1]; nxt[2 * cap + pos] = cn[2];
+                            if (pos < nstride) {
+                                nxt[pos] = cn[0]; nxt[nstride + pos] = cn[1]; nxt[2 * nstride + pos] = cn[2];
                             } else {
                                 s_overflow = 1u;
                             }
@@ -952,7 +971,9 @@ __global__ __launch_bounds__(kHeavyBlock) void heavy_kernel(
             nenq += s_cnt[0];
             tcap = s_tmin[0];
             nS = (int64_t)s_nN;
-            unsigned long long *t = cur; cur = nxt; nxt = t;
+            cur = nxt;
+            cstride = nstride;
+            cur_lds = nxt_lds;
             __syncthreads();
         }
         if (tid == 0) {
@@ -1080,10 +1101,11 @@ void launch_narrow_prep_sched(const double *V0, const double *V1, int64_t nv, co
     counters_zero_kernel<<<1, 256, 0, s>>>(B.counters, 16, B.flags, hist);
     const int64_t n = pc.capacity();
     if (n == 0) return;
+    prep_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(V0, V1, nv, vf, ee, pc, E, ne, F, nf, delta, B.ids4, B.eps,
+                                                           B.m, B.flags);
     int64_t blocks = (n + 255) / 256;
-    if (blocks > 1024) blocks = 1024;
-    prep_sched_kernel<<<(unsigned)blocks, 256, 0, s>>>(V0, V1, nv, vf, ee, pc, E, ne, F, nf, delta, B.ids4, B.eps,
-                                                      B.m, B.flags, params, norm, cost, hist);
+    if (blocks > 2048) blocks = 2048;
+    sched_kernel<<<(unsigned)blocks, 256, 0, s>>>(V0, V1, B.ids4, B.eps, B.m, pc, delta, params, norm, cost, hist);
 }
 
 void launch_narrow_features(const double *V0, const double *V1, PairCounts pc, double delta, const NarrowBuffers &B,
@@ -1109,7 +1131,7 @@ void launch_narrow_pool(const double *V0, const double *V1, PairCounts pc, doubl
 
 void launch_narrow_heavy(const double *V0, const double *V1, PairCounts pc, double delta, long long max_iter,
                          uint8_t *hit, double *toi, long long *n_enq, const NarrowBuffers &B, int nslots,
-                         int64_t cap, int round, hipStream_t s)
+                         int64_t cap, int round, int use_lds, hipStream_t s)
 {
     // counters: [0] handed-over pairs, [1] work index of the first round,
     // [2] / [3] overflow counts of list 0 / 1, [4] work index of re-runs.
@@ -1126,17 +1148,17 @@ void launch_narrow_heavy(const double *V0, const double *V1, PairCounts pc, doub
     }
     heavy_kernel<<<(unsigned)nslots, kHeavyBlock, 0, s>>>(V0, V1, B.ids4, B.eps, B.m, pc, delta, max_iter, hit,
                                                           toi, n_enq, B.heavy, B.hnodes, list, count, next, ovf,
-                                                          ovf_count, B.scratch, cap, B.flags);
+                                                          ovf_count, B.scratch, cap, B.flags, use_lds);
 }
 
 void launch_narrow_heavy_early(const double *V0, const double *V1, PairCounts pc, double delta, long long max_iter,
                                uint8_t *hit, double *toi, long long *n_enq, const NarrowBuffers &B,
-                               unsigned long long *scratch, int nslots, int64_t cap, hipStream_t s)
+                               unsigned long long *scratch, int nslots, int64_t cap, int use_lds, hipStream_t s)
 {
     heavy_kernel<<<(unsigned)nslots, kHeavyBlock, 0, s>>>(V0, V1, B.ids4, B.eps, B.m, pc, delta, max_iter, hit, toi,
                                                           n_enq, B.heavy, B.hnodes, nullptr, &B.counters[12],
                                                           &B.counters[13], B.overflow_list[0], &B.counters[2],
-                                                          scratch, cap, B.flags);
+                                                          scratch, cap, B.flags, use_lds);
 }
 
 void launch_toi_min(const double *toi, PairCounts pc, double *out, hipStream_t s)

@@ -47,3 +47,39 @@ def test_null_arguments_rejected_without_device(lib):
                         None, None, None)
     assert st == ccd.CCD_ERR_INVALID_ARG
     assert lib.ccd_create(0, None) == ccd.CCD_ERR_INVALID_ARG
+
+
+def test_new_entry_points_reject_null_arguments_without_device(lib):
+    P = ctypes.c_void_p
+    out = P()
+    n = ctypes.c_int64()
+    # batches
+    offs = (ctypes.c_int64 * 2)(0, 0)
+    assert lib.ccd_batch_create(None, 1, offs, offs, offs, 0, 0, ctypes.byref(out)) == ccd.CCD_ERR_INVALID_ARG
+    assert lib.ccd_batch_run(None, None, None, None, None, 1e-6, 10, None, None, ctypes.byref(n), ctypes.byref(n),
+                             None, None, None, None, 0, None) == ccd.CCD_ERR_INVALID_ARG
+    assert lib.ccd_batch_autotune(None, None, None, None, None, 1e-6, 10, None, None, None, None, None, None, None,
+                                  None) == ccd.CCD_ERR_INVALID_ARG
+    lib.ccd_batch_destroy(None)  # no-op
+    # tuning
+    t = ccd.Tuning(16, 0, 1024, 13, 0)
+    assert lib.ccd_set_tuning(None, ctypes.byref(t)) == ccd.CCD_ERR_INVALID_ARG
+    assert lib.ccd_get_tuning(None, ctypes.byref(t)) == ccd.CCD_ERR_INVALID_ARG
+    # learned schedule pieces
+    assert lib.ccd_mlp_predict(None, None, None, None, 0, None, None) == ccd.CCD_ERR_INVALID_ARG
+    assert lib.ccd_mlp_grad(None, None, None, None, None, 0, None, None, None) == ccd.CCD_ERR_INVALID_ARG
+    assert lib.ccd_adam_step(None, None, None, None, None, 1, 1e-3, 0.9, 0.999, 1e-8, None) == \
+        ccd.CCD_ERR_INVALID_ARG
+    assert lib.ccd_features(None, None, None, 0, None, 0, None, 0, None, 0, None, 0, 1e-6, None, None) == \
+        ccd.CCD_ERR_INVALID_ARG
+    sch = ccd.Schedule(ccd.SCHED_PLAIN, None, None, None, 0.0, 0)
+    assert lib.ccd_narrow_sched(None, None, None, 0, None, 0, None, 0, None, 0, None, 0, 1e-6, 10, None, None, None,
+                                None, ctypes.byref(sch), None) == ccd.CCD_ERR_INVALID_ARG
+    assert lib.ccd_last_error()  # a message is left
+
+
+def test_model_parameter_count_matches_header():
+    text = open(HEADER).read()
+    assert f"#define CCD_MODEL_PARAMS {ccd.MODEL_PARAMS}" in text
+    assert f"#define CCD_NUM_FEATURES {ccd.NUM_FEATURES}" in text
+    assert ccd.MODEL_PARAMS == 16 * 64 + 64 + 64 * 64 + 64 + 64 + 1

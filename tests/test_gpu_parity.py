@@ -268,3 +268,23 @@ def test_end_to_end_cloth(ctx):
                                                          toi.cpu().numpy()[:len(gvf)])}
     for p, h, t in zip(ovf, oh[:len(ovf)], ot[:len(ovf)]):
         assert g[("vf",) + tuple(p)] == (h, t)
+
+
+@pytest.mark.parametrize("tuning", [{"heavy_lds": 1}, {"heavy_lds": 1, "heavy_cap_log2": 8, "heavy_slots": 16},
+                                    {"sweep_tile_group": 1, "pool_blocks_per_cu": 1}])
+def test_tunings_give_identical_results(ctx, tuning):
+    """Launch shapes (LDS frontiers, tiny wide-stage buffers that force re-runs, one pool workgroup per CU,
+    ungrouped sweep tiles) never change a result."""
+    print(f"tuning {tuning}", flush=True)
+    ctx.set_tuning(tuning)
+    try:
+        s = _degenerate_scene()
+        vf, ee = oracle.all_pairs(s.E, s.F, s.nv)
+        for max_iter in (1000, 10 ** 6):
+            oh, _, _ = check_narrow(ctx, s, vf, ee, max_iter=max_iter)
+            assert oh.any()
+        s = scenes.cloth_on_sphere(n=96, sphere_subdivisions=3, seed=21)
+        ovf, oee = check_broad(ctx, s)
+        check_narrow(ctx, s, ovf, oee)
+    finally:
+        ctx.set_tuning(None)
