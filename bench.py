@@ -140,8 +140,8 @@ def extra_torus_10m(ctx, steps):
         params, norm, meta = sched.load_model(sched.TORUS_MODEL_PATH)
     except FileNotFoundError:
         params, norm, meta = sched.load_model()
-    learned = ("learned", torch.as_tensor(params).cuda(), torch.as_tensor(norm).cuda(), ccd_mod().HEAVY_THRESHOLD,
-               ccd_mod().MAX_HEAVY)
+    learned = ("learned", torch.as_tensor(params).cuda(), torch.as_tensor(norm).cuda(),
+               ccd_mod().TORUS_HEAVY_THRESHOLD, ccd_mod().TORUS_MAX_HEAVY)
     res = {}
     for name, sc in (("plain", None), ("learned", learned)):
         ctx.narrow(V0, V1, E, F, vf, ee, DELTA, MAX_ITER, out=out, schedule=sc)

@@ -153,7 +153,8 @@ typedef struct {
     const float *norm;     /* LEARNED: device, 2 * CCD_NUM_FEATURES floats */
     const int32_t *order;  /* ORDER: device permutation of [0, n_vf + n_ee): search order */
     float heavy_threshold; /* LEARNED: predicted log2(1 + n_enq) from which a pair starts in the wide stage */
-    int32_t max_heavy;     /* LEARNED: at most this many such pairs (0: none), 0..4096 */
+    int32_t max_heavy;     /* LEARNED: at most this many such pairs (0: none); they run on up to
+                              tuning.heavy_slots workgroups */
 } ccd_schedule;
 
 /* ccd_narrow with a schedule (NULL = plain: pairs in index order).  Same
@@ -223,11 +224,15 @@ ccd_status ccd_get_stats(ccd_context *ctx, ccd_stats *out);
  *   heavy_cap_log2      log2 of each wide-stage frontier buffer in intervals
  *                       (default 13); a frontier that outgrows it is re-run
  *                       with 8x larger buffers
- *   heavy_lds           1: wide-stage frontiers of at most 512 intervals
- *                       stay in LDS between levels (default 0)
+ *   heavy_lds           1: wide-stage frontiers of at most 2 heavy_block
+ *                       intervals stay in LDS between levels (default 1)
+ *   heavy_block         threads per wide-stage pair, 64 or 256 (default 256)
+ *   pool_wait           1: a pair whose children do not fit its wave's queue
+ *                       this round waits for room, 0: it goes to the wide
+ *                       stage (default 0)
  * ccd_set_tuning(ctx, NULL) restores the defaults.  INVALID_ARG when a value
  * is out of range (group 1..1024, blocks 0..64, slots 1..65536, cap 8..24,
- * lds 0..1).
+ * lds 0..1, block 64 or 256, wait 0..1).
  */
 typedef struct {
     int32_t sweep_tile_group;
@@ -235,6 +240,8 @@ typedef struct {
     int32_t heavy_slots;
     int32_t heavy_cap_log2;
     int32_t heavy_lds;
+    int32_t heavy_block;
+    int32_t pool_wait;
 } ccd_tuning;
 
 ccd_status ccd_set_tuning(ccd_context *ctx, const ccd_tuning *tuning);
@@ -266,8 +273,8 @@ ccd_status ccd_get_tuning(ccd_context *ctx, ccd_tuning *tuning);
  * as ccd_broad and ccd_narrow.  Calls on one batch must not overlap.
  *
  * ccd_batch_autotune: times batch passes over candidate tunings (coordinate
- * descent over tile group, pool blocks per CU, wide-stage slots and LDS
- * frontiers) and sets
+ * descent over tile group, pool blocks per CU, wide-stage workgroup size,
+ * slots and LDS frontiers, and pool waiting) and sets
  * the best on the context.  With cache_path the choice is stored under a
  * signature of the device and the workload's size, and a later call with the
  * same signature takes it from the file without timing.  Outputs as

@@ -58,7 +58,8 @@ class Stats(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("sweep_tile_group", ctypes.c_int32), ("pool_blocks_per_cu", ctypes.c_int32),
-                ("heavy_slots", ctypes.c_int32), ("heavy_cap_log2", ctypes.c_int32), ("heavy_lds", ctypes.c_int32)]
+                ("heavy_slots", ctypes.c_int32), ("heavy_cap_log2", ctypes.c_int32), ("heavy_lds", ctypes.c_int32),
+                ("heavy_block", ctypes.c_int32), ("pool_wait", ctypes.c_int32)]
 
 
 class Schedule(ctypes.Structure):
@@ -67,9 +68,11 @@ class Schedule(ctypes.Structure):
 
 
 # Learned schedule defaults: predictions of log2(1 + n_enq) from which a pair starts in the wide stage, and
-# the most such pairs.
-HEAVY_THRESHOLD = 10.0
+# the most such pairs (measured best on the cloth workload; the perturbed torus prefers 10 and 20,000).
+HEAVY_THRESHOLD = 7.0
 MAX_HEAVY = 256
+TORUS_HEAVY_THRESHOLD = 10.0
+TORUS_MAX_HEAVY = 20000
 
 
 _lib = None

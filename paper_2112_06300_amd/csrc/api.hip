@@ -88,7 +88,9 @@ ccd_tuning default_tuning()
     t.pool_blocks_per_cu = 0;
     t.heavy_slots = 1024;
     t.heavy_cap_log2 = 13;
-    t.heavy_lds = 0;
+    t.heavy_lds = 1;
+    t.heavy_block = 256;
+    t.pool_wait = 0;
     return t;
 }
 
@@ -170,7 +172,8 @@ bool valid_tuning(const ccd_tuning &t)
 {
     return t.sweep_tile_group >= 1 && t.sweep_tile_group <= 1024 && t.pool_blocks_per_cu >= 0 &&
            t.pool_blocks_per_cu <= 64 && t.heavy_slots >= 1 && t.heavy_slots <= 65536 && t.heavy_cap_log2 >= 8 &&
-           t.heavy_cap_log2 <= 24 && (t.heavy_lds == 0 || t.heavy_lds == 1);
+           t.heavy_cap_log2 <= 24 && (t.heavy_lds == 0 || t.heavy_lds == 1) &&
+           (t.heavy_block == 64 || t.heavy_block == 256) && (t.pool_wait == 0 || t.pool_wait == 1);
 }
 
 }  // namespace
@@ -387,9 +390,8 @@ ccd_status narrow_impl(ccd_context *c, const double *V0, const double *V1, int64
         return fail(CCD_ERR_INVALID_ARG, "unknown schedule kind %d", kind);
     if (kind == CCD_SCHED_LEARNED && (!sched->params || !sched->norm))
         return fail(CCD_ERR_INVALID_ARG, "learned schedule without parameters or normalization");
-    if (kind == CCD_SCHED_LEARNED &&
-        (sched->max_heavy < 0 || sched->max_heavy > 4096 || !std::isfinite(sched->heavy_threshold)))
-        return fail(CCD_ERR_INVALID_ARG, "learned schedule: max_heavy outside [0, 4096] or non-finite threshold");
+    if (kind == CCD_SCHED_LEARNED && (sched->max_heavy < 0 || !std::isfinite(sched->heavy_threshold)))
+        return fail(CCD_ERR_INVALID_ARG, "learned schedule: negative max_heavy or non-finite threshold");
     if (kind == CCD_SCHED_ORDER && n > 0 && !sched->order)
         return fail(CCD_ERR_INVALID_ARG, "order schedule without an order");
     NarrowBuffers B;
@@ -420,7 +422,8 @@ ccd_status narrow_impl(ccd_context *c, const double *V0, const double *V1, int64
     int nslots = c->tune.heavy_slots;
     int64_t cap = (int64_t)1 << c->tune.heavy_cap_log2;
     const bool learned = kind == CCD_SCHED_LEARNED;
-    const int early_slots = learned ? std::max(0, std::min(sched->max_heavy, 4096)) : 0;
+    const int max_early = learned ? (int)std::min<int64_t>(sched->max_heavy, n) : 0;
+    const int early_slots = max_early > 0 ? std::min(max_early, nslots) : 0;
     st = ensure(c->scratch, (size_t)(nslots + early_slots) * 6 * cap * 8);
     if (st != CCD_OK) return st;
     B.scratch = (unsigned long long *)c->scratch.base;
@@ -433,7 +436,7 @@ ccd_status narrow_impl(ccd_context *c, const double *V0, const double *V1, int64
         launch_narrow_prep_sched(V0, V1, nv, E, ne, F, nf, vf, ee, pc, delta, B, sched->params, sched->norm, S.cost,
                                  S.bins, s);
         HIP_TRY(hipEventRecord(c->ev[4], s));
-        launch_cost_schedule(S.cost, n, sched->heavy_threshold, early_slots, S.order, B.heavy, B.counters, S.bins,
+        launch_cost_schedule(S.cost, n, sched->heavy_threshold, max_early, S.order, B.heavy, B.counters, S.bins,
                              true, s);
         order = S.order;
         order_n = S.bins + 2 * 256 + 1;
@@ -446,14 +449,17 @@ ccd_status narrow_impl(ccd_context *c, const double *V0, const double *V1, int64
         // pairs predicted to outgrow the pool start in the wide stage now, beside the pool
         HIP_TRY(hipStreamWaitEvent(c->side, c->ev[5], 0));
         launch_narrow_heavy_early(V0, V1, pc, delta, (long long)max_iter, hit, toi, nenq, B,
-                                  B.scratch + (size_t)nslots * 6 * cap, early_slots, cap, c->tune.heavy_lds, c->side);
+                                  B.scratch + (size_t)nslots * 6 * cap, early_slots, cap, c->tune.heavy_lds,
+                                  c->tune.heavy_block, c->side);
         HIP_TRY(hipGetLastError());
         HIP_TRY(hipEventRecord(c->ev[6], c->side));
     }
-    launch_narrow_pool(V0, V1, pc, delta, (long long)max_iter, hit, toi, nenq, B, pool_blocks(c), order, order_n, s);
+    launch_narrow_pool(V0, V1, pc, delta, (long long)max_iter, hit, toi, nenq, B, pool_blocks(c), order, order_n,
+                       c->tune.pool_wait, s);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(c->ev[2], s));
-    launch_narrow_heavy(V0, V1, pc, delta, (long long)max_iter, hit, toi, nenq, B, nslots, cap, 0, c->tune.heavy_lds, s);
+    launch_narrow_heavy(V0, V1, pc, delta, (long long)max_iter, hit, toi, nenq, B, nslots, cap, 0, c->tune.heavy_lds,
+                        c->tune.heavy_block, s);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(c->ev[3], s));
     if (learned && early_slots > 0) HIP_TRY(hipStreamWaitEvent(s, c->ev[6], 0));
@@ -501,7 +507,7 @@ ccd_status narrow_impl(ccd_context *c, const double *V0, const double *V1, int64
         B.scratch = (unsigned long long *)c->scratch.base;
         HIP_TRY(hipEventRecord(c->ev[0], s));
         launch_narrow_heavy(V0, V1, pc, delta, (long long)max_iter, hit, toi, nenq, B, nslots, cap, round,
-                            c->tune.heavy_lds, s);
+                            c->tune.heavy_lds, c->tune.heavy_block, s);
         HIP_TRY(hipGetLastError());
         launch_toi_min(toi, pc, toi_min, s);
         HIP_TRY(hipGetLastError());
@@ -691,9 +697,9 @@ void batch_enqueue(ccd_batch *b, const BatchArgs &a, hipStream_t s)
     const PairCounts pc{b->vf_cap, b->ee_cap, b->B.counts};
     launch_narrow_prep(a.V0, a.V1, b->nv, a.E, b->ne, a.F, b->nf, a.vf, a.ee, pc, a.delta, b->N, s);
     launch_narrow_pool(a.V0, a.V1, pc, a.delta, a.max_iter, a.hit, a.toi, a.n_enq, b->N, pool_blocks(c), nullptr,
-                       nullptr, s);
+                       nullptr, c->tune.pool_wait, s);
     launch_narrow_heavy(a.V0, a.V1, pc, a.delta, a.max_iter, a.hit, a.toi, a.n_enq, b->N, b->heavy_slots,
-                        b->heavy_cap, 0, c->tune.heavy_lds, s);
+                        b->heavy_cap, 0, c->tune.heavy_lds, c->tune.heavy_block, s);
     launch_scene_min(a.toi, pc, a.vf, a.ee, b->off, b->off + (b->S + 1), b->S, a.toi_min, s);
 }
 
@@ -786,7 +792,7 @@ ccd_status batch_pass(ccd_batch *b, const BatchArgs &a, bool use_graph, int64_t 
             if (st != CCD_OK) return st;
             N.scratch = (unsigned long long *)big.base;
             launch_narrow_heavy(a.V0, a.V1, pc, a.delta, a.max_iter, a.hit, a.toi, a.n_enq, N, nslots, cap, round,
-                                c->tune.heavy_lds, s);
+                                c->tune.heavy_lds, c->tune.heavy_block, s);
             HIP_TRY(hipGetLastError());
             unsigned int *hc = (unsigned int *)c->host;
             HIP_TRY(hipMemcpyAsync(hc, N.counters, 16 * 4, hipMemcpyDeviceToHost, s));
@@ -812,7 +818,8 @@ ccd_status check_batch_args(ccd_batch *b, const BatchArgs &a, const int64_t *n_v
     return CCD_OK;
 }
 
-// Autotuner cache: one line per workload signature, "signature: group blocks slots cap lds".
+// Autotuner cache: one line per workload signature,
+// "signature: group blocks slots cap lds block wait".
 bool cache_lookup(const char *path, const char *sig, ccd_tuning *t)
 {
     if (!path) return false;
@@ -824,8 +831,8 @@ bool cache_lookup(const char *path, const char *sig, ccd_tuning *t)
     while (std::fgets(line, sizeof line, f)) {
         if (std::strncmp(line, sig, n) == 0 && line[n] == ':') {
             ccd_tuning v;
-            if (std::sscanf(line + n + 1, "%d %d %d %d %d", &v.sweep_tile_group, &v.pool_blocks_per_cu,
-                            &v.heavy_slots, &v.heavy_cap_log2, &v.heavy_lds) == 5 &&
+            if (std::sscanf(line + n + 1, "%d %d %d %d %d %d %d", &v.sweep_tile_group, &v.pool_blocks_per_cu,
+                            &v.heavy_slots, &v.heavy_cap_log2, &v.heavy_lds, &v.heavy_block, &v.pool_wait) == 7 &&
                 valid_tuning(v)) {
                 *t = v;
                 found = true;  // the last matching line wins
@@ -841,8 +848,8 @@ void cache_store(const char *path, const char *sig, const ccd_tuning &t)
     if (!path) return;
     FILE *f = std::fopen(path, "a");
     if (!f) return;
-    std::fprintf(f, "%s: %d %d %d %d %d\n", sig, t.sweep_tile_group, t.pool_blocks_per_cu, t.heavy_slots,
-                 t.heavy_cap_log2, t.heavy_lds);
+    std::fprintf(f, "%s: %d %d %d %d %d %d %d\n", sig, t.sweep_tile_group, t.pool_blocks_per_cu, t.heavy_slots,
+                 t.heavy_cap_log2, t.heavy_lds, t.heavy_block, t.pool_wait);
     std::fclose(f);
 }
 
@@ -991,15 +998,18 @@ ccd_status ccd_batch_autotune(ccd_batch *b, const double *V0, const double *V1, 
     st = measure(best, &best_ms);
     if (st != CCD_OK) return st;
     const int groups[] = {1, 4, 16, 64};
-    const int slots[] = {256, 512, 1024, 2048};
-    for (int param = 0; param < 4; param++) {
-        const int ncand = param == 0 ? 4 : (param == 1 ? c->pool_per_cu_max : (param == 2 ? 4 : 2));
+    const int slots[] = {256, 1024, 2048, 4096};
+    const int blocks[] = {64, 256};
+    for (int param = 0; param < 6; param++) {
+        const int ncand = param == 0 ? 4 : (param == 1 ? c->pool_per_cu_max : (param == 3 ? 4 : 2));
         for (int i = 0; i < ncand; i++) {
             ccd_tuning t = best;
             if (param == 0) t.sweep_tile_group = groups[i];
             else if (param == 1) t.pool_blocks_per_cu = i + 1;
-            else if (param == 2) t.heavy_slots = slots[i];
-            else t.heavy_lds = i;
+            else if (param == 2) t.heavy_block = blocks[i];
+            else if (param == 3) t.heavy_slots = slots[i];
+            else if (param == 4) t.heavy_lds = i;
+            else t.pool_wait = i;
             if (std::memcmp(&t, &best, sizeof t) == 0) continue;
             float m = 0.f;
             st = measure(t, &m);

@@ -188,16 +188,18 @@ void launch_narrow_features(const double *V0, const double *V1, PairCounts pc, d
 // pool: the wave-pool search of every pair (hands wide / deep pairs over).
 // Pairs are taken in index order, or in `order` (a permutation) when given.
 // With order_n the pool searches order[0 .. *order_n) (the rest of the pairs
-// are the wide stage's).
+// are the wide stage's).  wait: a pair whose children do not fit this round
+// waits (1) or goes to the wide stage (0).
 void launch_narrow_pool(const double *V0, const double *V1, PairCounts pc, double delta, long long max_iter,
                         uint8_t *hit, double *toi, long long *n_enq, const NarrowBuffers &B, int pool_blocks,
-                        const int32_t *order, const uint32_t *order_n, hipStream_t s);
+                        const int32_t *order, const uint32_t *order_n, int wait, hipStream_t s);
 // Wide stage over the learned schedule's early entries heavy[0 .. counters[12])
 // (work index counters[13]), with its own frontier buffers; it may run
 // concurrently with the pool on another stream.
 void launch_narrow_heavy_early(const double *V0, const double *V1, PairCounts pc, double delta, long long max_iter,
                                uint8_t *hit, double *toi, long long *n_enq, const NarrowBuffers &B,
-                               unsigned long long *scratch, int nslots, int64_t cap, int use_lds, hipStream_t s);
+                               unsigned long long *scratch, int nslots, int64_t cap, int use_lds, int block,
+                               hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Learned schedule: MLP kNumFeatures -> 64 -> 64 -> 1 on bf16 MFMA.
@@ -233,10 +235,11 @@ void launch_check_permutation(const int32_t *order, int64_t n, uint32_t *bits, u
 // Wide stage: `nslots` workgroups, each with a frontier buffer of `cap` nodes
 // (two buffers of 3 x cap uint64).  Round 0 works on every handed-over pair;
 // round r > 0 re-runs the pairs that overflowed their buffer in round r - 1.
-// use_lds: frontiers of at most 512 intervals stay in LDS between levels.
+// block: threads per pair (64 or 256); use_lds: frontiers of at most
+// 2 block intervals stay in LDS between levels.
 void launch_narrow_heavy(const double *V0, const double *V1, PairCounts pc, double delta, long long max_iter,
                          uint8_t *hit, double *toi, long long *n_enq, const NarrowBuffers &B, int nslots,
-                         int64_t cap, int round, int use_lds, hipStream_t s);
+                         int64_t cap, int round, int use_lds, int block, hipStream_t s);
 
 void launch_toi_min(const double *toi, PairCounts pc, double *out, hipStream_t s);
 // out[s] = earliest toi over the pairs of scene s (CSR vertex / edge offsets

@@ -27,8 +27,8 @@ namespace ccd {
 
 namespace {
 
-constexpr int kHeavyBlock = 256;
-constexpr int kHeavyLds = 512;  // wide-stage frontier intervals kept in LDS (24 KB: no occupancy cost)
+// Wide stage: one workgroup of BLOCK threads (64 or 256) per pair; frontiers
+// of up to 2 BLOCK intervals may stay in LDS (6 KB or 24 KB: no occupancy cost).
 constexpr int kPoolSlots = 64;   // pairs in flight per wave (one owner lane each)
 constexpr int kQCap = 512;       // intervals per round per wave
 constexpr int kClaim = 64;       // pairs a wave claims from the global list at once
@@ -500,7 +500,7 @@ __global__ __launch_bounds__(kPoolSlots) void pool_kernel(
     const double *__restrict__ peps, const uint32_t *__restrict__ pm, PairCounts pc,
     double delta, long long max_iter, uint8_t *hit, double *toi, long long *n_enq_out, HeavyEntry *heavy,
     unsigned long long *hnodes, int64_t hnode_cap, unsigned int *counters, const int32_t *__restrict__ order,
-    const uint32_t *__restrict__ order_n)
+    const uint32_t *__restrict__ order_n, int wait)
 {
     __shared__ PoolLds S;
     int64_t n_vf, n_pairs;
@@ -630,7 +630,7 @@ __global__ __launch_bounds__(kPoolSlots) void pool_kernel(
             // survivors unsplit into the next round's queue (the level, t* and
             // n_enq do not change while a pair waits).  The first pusher always
             // fits, so some pair advances every round.
-            if (outcome == 4 && off + push > kQCap) outcome = push > kQCap ? 3 : 5;
+            if (outcome == 4 && off + push > kQCap) outcome = (push > kQCap || !wait) ? 3 : 5;
             off = push_offset(outcome == 4, waiting, push, lane, total);
             int ctotal = 0;
             coff = wave_excl_scan(outcome == 5 ? nsurv : 0, lane, ctotal);
@@ -814,7 +814,8 @@ __device__ __forceinline__ long long wave_sum_ll(long long v)
 // Wide stage: one workgroup per handed-over pair, frontier in HBM scratch.
 // `list` (optional) maps work indices to heavy slots; `list_count` holds the
 // number of work items.
-__global__ __launch_bounds__(kHeavyBlock) void heavy_kernel(
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void heavy_kernel(
     const double *__restrict__ V0, const double *__restrict__ V1, const int4 *__restrict__ ids4,
     const double *__restrict__ peps, const uint32_t *__restrict__ pm, PairCounts pc, double delta,
     long long max_iter, uint8_t *hit, double *toi, long long *n_enq_out, const HeavyEntry *__restrict__ heavy,
@@ -824,14 +825,15 @@ __global__ __launch_bounds__(kHeavyBlock) void heavy_kernel(
 {
     // Frontier of the next level: in LDS when it surely fits (at most twice the
     // current frontier), else in this workgroup's HBM buffers.
-    __shared__ unsigned long long s_front[2][3 * kHeavyLds];
+    constexpr int kLds = 2 * BLOCK;
+    __shared__ unsigned long long s_front[2][3 * kLds];
     __shared__ int s_idx;
     __shared__ unsigned long long s_tstar;  // live t* as bits (non-negative doubles order like uint64)
     __shared__ unsigned int s_nN;
     __shared__ int s_state;                 // 0 continue, 1 done, 2 capped, 3 overflow
     __shared__ unsigned int s_overflow;
-    __shared__ long long s_cnt[kHeavyBlock / 64];
-    __shared__ double s_tmin[kHeavyBlock / 64];
+    __shared__ long long s_cnt[BLOCK / 64];
+    __shared__ double s_tmin[BLOCK / 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     int64_t n_vf, n_all;
     pc.get(n_vf, n_all);
@@ -869,6 +871,10 @@ __global__ __launch_bounds__(kHeavyBlock) void heavy_kernel(
         int state = 0;
         double tcap = 0.0;
         double tstart = h.tstar;
+        // Split levels never exceed m_k, so with every m_k <= 21 an interval's
+        // three numerators pack into one word (21 bits each) and a buffer of
+        // 3 cap words holds 3 cap intervals; otherwise three separate arrays.
+        const bool packed = q.m[0] <= kLightMaxLevel && q.m[1] <= kLightMaxLevel && q.m[2] <= kLightMaxLevel;
         if (h.node_off < 0) {
             // restart from the root
             const int r = process(q, vf, 0.0, 1.0, 0.0, 1.0, 0.0, 1.0, false, delta);
@@ -876,8 +882,10 @@ __global__ __launch_bounds__(kHeavyBlock) void heavy_kernel(
             else if (r == DISCARD) state = 1;
             if (tid == 0) { cur[0] = 0ull; cur[cap] = 0ull; cur[2 * cap] = 0ull; }
             nS = 1;
+        } else if (packed) {
+            for (int64_t i = tid; i < nS; i += BLOCK) cur[i] = hnodes[h.node_off + i];
         } else {
-            for (int64_t i = tid; i < nS; i += kHeavyBlock) {
+            for (int64_t i = tid; i < nS; i += BLOCK) {
                 const unsigned long long pk = hnodes[h.node_off + i];
                 cur[i] = pk & 0x1fffffull;
                 cur[cap + i] = (pk >> 21) & 0x1fffffull;
@@ -894,10 +902,10 @@ __global__ __launch_bounds__(kHeavyBlock) void heavy_kernel(
             const double tscale = pow2neg(l[0]), uscale = pow2neg(l[1]), vscale = pow2neg(l[2]);
             const bool finest = l[0] == kMaxLevel && l[1] == kMaxLevel && l[2] == kMaxLevel;
             // where this level's survivors go
-            if (use_lds && 2 * nS <= kHeavyLds) {
+            if (use_lds && 2 * nS <= (packed ? 3 * kLds : kLds)) {
                 nxt_lds = cur_lds == 0 ? 1 : 0;
                 nxt = s_front[nxt_lds];
-                nstride = kHeavyLds;
+                nstride = kLds;
             } else {
                 nxt_lds = -1;
                 nxt = cur == A ? Bb : A;
@@ -907,11 +915,18 @@ __global__ __launch_bounds__(kHeavyBlock) void heavy_kernel(
             __syncthreads();
             long long cnt = 0;
             double tmin = __builtin_huge_val();
-            for (int64_t b0 = 0; b0 < nS; b0 += kHeavyBlock) {
+            for (int64_t b0 = 0; b0 < nS; b0 += BLOCK) {
                 const int64_t i = b0 + tid;
                 const bool has = i < nS;
                 unsigned long long pn[3] = {0ull, 0ull, 0ull};
-                if (has) { pn[0] = cur[i]; pn[1] = cur[cstride + i]; pn[2] = cur[2 * cstride + i]; }
+                if (has) {
+                    if (packed) {
+                        const unsigned long long nd = cur[i];
+                        pn[0] = nd & 0x1fffffull; pn[1] = (nd >> 21) & 0x1fffffull; pn[2] = (nd >> 42) & 0x1fffffull;
+                    } else {
+                        pn[0] = cur[i]; pn[1] = cur[cstride + i]; pn[2] = cur[2 * cstride + i];
+                    }
+                }
 #pragma unroll
                 for (int c = 0; c < 2; c++) {
                     unsigned long long cn[3] = {pn[0], pn[1], pn[2]};
@@ -937,7 +952,9 @@ __global__ __launch_bounds__(kHeavyBlock) void heavy_kernel(
                         base = __shfl(base, leader);
                         if (surv) {
                             const int64_t pos = (int64_t)base + __popcll(mask & ((1ull << lane) - 1ull));
-                            if (pos < nstride) {
+                            if (packed && pos < 3 * nstride) {
+                                nxt[pos] = cn[0] | cn[1] << 21 | cn[2] << 42;
+                            } else if (!packed && pos < nstride) {
                                 nxt[pos] = cn[0]; nxt[nstride + pos] = cn[1]; nxt[2 * nstride + pos] = cn[2];
                             } else {
                                 s_overflow = 1u;
@@ -953,7 +970,7 @@ __global__ __launch_bounds__(kHeavyBlock) void heavy_kernel(
             if (tid == 0) {
                 long long c_all = 0;
                 double tm = __builtin_huge_val();
-                for (int w = 0; w < kHeavyBlock / 64; w++) {
+                for (int w = 0; w < BLOCK / 64; w++) {
                     c_all += s_cnt[w];
                     tm = s_tmin[w] < tm ? s_tmin[w] : tm;
                 }
@@ -1118,7 +1135,7 @@ void launch_narrow_features(const double *V0, const double *V1, PairCounts pc, d
 
 void launch_narrow_pool(const double *V0, const double *V1, PairCounts pc, double delta, long long max_iter,
                         uint8_t *hit, double *toi, long long *n_enq, const NarrowBuffers &B, int pool_blocks,
-                        const int32_t *order, const uint32_t *order_n, hipStream_t s)
+                        const int32_t *order, const uint32_t *order_n, int wait, hipStream_t s)
 {
     const int64_t n = pc.capacity();
     if (n == 0) return;
@@ -1126,12 +1143,12 @@ void launch_narrow_pool(const double *V0, const double *V1, PairCounts pc, doubl
     if (blocks > pool_blocks) blocks = pool_blocks;
     pool_kernel<<<(unsigned)blocks, kPoolSlots, 0, s>>>(V0, V1, B.ids4, B.eps, B.m, pc, delta, max_iter, hit, toi,
                                                        n_enq, B.heavy, B.hnodes, B.hnode_cap, B.counters, order,
-                                                       order_n);
+                                                       order_n, wait);
 }
 
 void launch_narrow_heavy(const double *V0, const double *V1, PairCounts pc, double delta, long long max_iter,
                          uint8_t *hit, double *toi, long long *n_enq, const NarrowBuffers &B, int nslots,
-                         int64_t cap, int round, int use_lds, hipStream_t s)
+                         int64_t cap, int round, int use_lds, int block, hipStream_t s)
 {
     // counters: [0] handed-over pairs, [1] work index of the first round,
     // [2] / [3] overflow counts of list 0 / 1, [4] work index of re-runs.
@@ -1146,19 +1163,31 @@ void launch_narrow_heavy(const double *V0, const double *V1, PairCounts pc, doub
         next = &B.counters[4];
         rerun_reset_kernel<<<1, 1, 0, s>>>(B.counters, round);
     }
-    heavy_kernel<<<(unsigned)nslots, kHeavyBlock, 0, s>>>(V0, V1, B.ids4, B.eps, B.m, pc, delta, max_iter, hit,
-                                                          toi, n_enq, B.heavy, B.hnodes, list, count, next, ovf,
-                                                          ovf_count, B.scratch, cap, B.flags, use_lds);
+    if (block == 64)
+        heavy_kernel<64><<<(unsigned)nslots, 64, 0, s>>>(V0, V1, B.ids4, B.eps, B.m, pc, delta, max_iter, hit, toi,
+                                                        n_enq, B.heavy, B.hnodes, list, count, next, ovf, ovf_count,
+                                                        B.scratch, cap, B.flags, use_lds);
+    else
+        heavy_kernel<256><<<(unsigned)nslots, 256, 0, s>>>(V0, V1, B.ids4, B.eps, B.m, pc, delta, max_iter, hit, toi,
+                                                          n_enq, B.heavy, B.hnodes, list, count, next, ovf, ovf_count,
+                                                          B.scratch, cap, B.flags, use_lds);
 }
 
 void launch_narrow_heavy_early(const double *V0, const double *V1, PairCounts pc, double delta, long long max_iter,
                                uint8_t *hit, double *toi, long long *n_enq, const NarrowBuffers &B,
-                               unsigned long long *scratch, int nslots, int64_t cap, int use_lds, hipStream_t s)
+                               unsigned long long *scratch, int nslots, int64_t cap, int use_lds, int block,
+                               hipStream_t s)
 {
-    heavy_kernel<<<(unsigned)nslots, kHeavyBlock, 0, s>>>(V0, V1, B.ids4, B.eps, B.m, pc, delta, max_iter, hit, toi,
+    if (block == 64)
+        heavy_kernel<64><<<(unsigned)nslots, 64, 0, s>>>(V0, V1, B.ids4, B.eps, B.m, pc, delta, max_iter, hit, toi,
+                                                        n_enq, B.heavy, B.hnodes, nullptr, &B.counters[12],
+                                                        &B.counters[13], B.overflow_list[0], &B.counters[2], scratch,
+                                                        cap, B.flags, use_lds);
+    else
+        heavy_kernel<256><<<(unsigned)nslots, 256, 0, s>>>(V0, V1, B.ids4, B.eps, B.m, pc, delta, max_iter, hit, toi,
                                                           n_enq, B.heavy, B.hnodes, nullptr, &B.counters[12],
-                                                          &B.counters[13], B.overflow_list[0], &B.counters[2],
-                                                          scratch, cap, B.flags, use_lds);
+                                                          &B.counters[13], B.overflow_list[0], &B.counters[2], scratch,
+                                                          cap, B.flags, use_lds);
 }
 
 void launch_toi_min(const double *toi, PairCounts pc, double *out, hipStream_t s)

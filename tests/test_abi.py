@@ -62,7 +62,7 @@ def test_new_entry_points_reject_null_arguments_without_device(lib):
                                   None) == ccd.CCD_ERR_INVALID_ARG
     lib.ccd_batch_destroy(None)  # no-op
     # tuning
-    t = ccd.Tuning(16, 0, 1024, 13, 0)
+    t = ccd.Tuning(16, 0, 1024, 13, 0, 256, 1)
     assert lib.ccd_set_tuning(None, ctypes.byref(t)) == ccd.CCD_ERR_INVALID_ARG
     assert lib.ccd_get_tuning(None, ctypes.byref(t)) == ccd.CCD_ERR_INVALID_ARG
     # learned schedule pieces

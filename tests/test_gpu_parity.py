@@ -271,10 +271,13 @@ def test_end_to_end_cloth(ctx):
 
 
 @pytest.mark.parametrize("tuning", [{"heavy_lds": 1}, {"heavy_lds": 1, "heavy_cap_log2": 8, "heavy_slots": 16},
-                                    {"sweep_tile_group": 1, "pool_blocks_per_cu": 1}])
+                                    {"sweep_tile_group": 1, "pool_blocks_per_cu": 1},
+                                    {"heavy_block": 64, "heavy_slots": 4096, "heavy_lds": 1},
+                                    {"heavy_block": 64, "heavy_cap_log2": 8, "pool_wait": 1},
+                                    {"heavy_lds": 0, "pool_wait": 1, "heavy_cap_log2": 17}])
 def test_tunings_give_identical_results(ctx, tuning):
     """Launch shapes (LDS frontiers, tiny wide-stage buffers that force re-runs, one pool workgroup per CU,
-    ungrouped sweep tiles) never change a result."""
+    ungrouped sweep tiles, one-wave wide-stage workgroups, no waiting in the pool) never change a result."""
     print(f"tuning {tuning}", flush=True)
     ctx.set_tuning(tuning)
     try:
