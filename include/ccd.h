@@ -226,13 +226,15 @@ ccd_status ccd_get_stats(ccd_context *ctx, ccd_stats *out);
  *                       with 8x larger buffers
  *   heavy_lds           1: wide-stage frontiers of at most 2 heavy_block
  *                       intervals stay in LDS between levels (default 1)
- *   heavy_block         threads per wide-stage pair, 64 or 256 (default 256)
+ *   heavy_block         threads per wide-stage pair, 64, 256 or 1024, or 0
+ *                       (default): 1024 when at most 256 pairs reach the wide
+ *                       stage, else 256 (decided on the device)
  *   pool_wait           1: a pair whose children do not fit its wave's queue
  *                       this round waits for room, 0: it goes to the wide
  *                       stage (default 0)
  * ccd_set_tuning(ctx, NULL) restores the defaults.  INVALID_ARG when a value
  * is out of range (group 1..1024, blocks 0..64, slots 1..65536, cap 8..24,
- * lds 0..1, block 64 or 256, wait 0..1).
+ * lds 0..1, block 0, 64, 256 or 1024, wait 0..1).
  */
 typedef struct {
     int32_t sweep_tile_group;

@@ -89,7 +89,7 @@ ccd_tuning default_tuning()
     t.heavy_slots = 1024;
     t.heavy_cap_log2 = 13;
     t.heavy_lds = 1;
-    t.heavy_block = 256;
+    t.heavy_block = 0;
     t.pool_wait = 0;
     return t;
 }
@@ -173,7 +173,8 @@ bool valid_tuning(const ccd_tuning &t)
     return t.sweep_tile_group >= 1 && t.sweep_tile_group <= 1024 && t.pool_blocks_per_cu >= 0 &&
            t.pool_blocks_per_cu <= 64 && t.heavy_slots >= 1 && t.heavy_slots <= 65536 && t.heavy_cap_log2 >= 8 &&
            t.heavy_cap_log2 <= 24 && (t.heavy_lds == 0 || t.heavy_lds == 1) &&
-           (t.heavy_block == 64 || t.heavy_block == 256) && (t.pool_wait == 0 || t.pool_wait == 1);
+           (t.heavy_block == 0 || t.heavy_block == 64 || t.heavy_block == 256 || t.heavy_block == 1024) &&
+           (t.pool_wait == 0 || t.pool_wait == 1);
 }
 
 }  // namespace
@@ -999,9 +1000,10 @@ ccd_status ccd_batch_autotune(ccd_batch *b, const double *V0, const double *V1, 
     if (st != CCD_OK) return st;
     const int groups[] = {1, 4, 16, 64};
     const int slots[] = {256, 1024, 2048, 4096};
-    const int blocks[] = {64, 256};
+    const int blocks[] = {0, 256, 1024};
     for (int param = 0; param < 6; param++) {
-        const int ncand = param == 0 ? 4 : (param == 1 ? c->pool_per_cu_max : (param == 3 ? 4 : 2));
+        const int counts[6] = {4, c->pool_per_cu_max, 3, 4, 2, 2};
+        const int ncand = counts[param];
         for (int i = 0; i < ncand; i++) {
             ccd_tuning t = best;
             if (param == 0) t.sweep_tile_group = groups[i];

@@ -160,23 +160,28 @@ __device__ __forceinline__ int choose_axis(const double *stats, double n)
     return best;
 }
 
-// Sweep axis of every scene: one wave per scene adds the partial sums of the
-// blocks that belong to it to the straddling blocks' totals.
-__global__ __launch_bounds__(64) void axis_kernel(double *stats, const double *__restrict__ partial,
-                                                  const int32_t *__restrict__ partial_scene, int64_t nblocks,
-                                                  const int64_t *__restrict__ off, int64_t S, int64_t nv, int64_t ne,
-                                                  int64_t nf, int32_t *axis)
+// Sweep axis of every scene: one 256-thread block per scene adds the partial
+// sums of the box blocks that belong to it to the straddling blocks' totals.
+__global__ __launch_bounds__(256) void axis_kernel(double *stats, const double *__restrict__ partial,
+                                                   const int32_t *__restrict__ partial_scene, int64_t nblocks,
+                                                   const int64_t *__restrict__ off, int64_t S, int64_t nv, int64_t ne,
+                                                   int64_t nf, int32_t *axis)
 {
+    __shared__ double red[4][6];
     const int64_t s = blockIdx.x;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int64_t b = lane; b < nblocks; b += 64)
+    for (int64_t b = threadIdx.x; b < nblocks; b += 256)
         if (partial_scene[b] == (int32_t)s)
             for (int q = 0; q < 6; q++) acc[q] += partial[8 * b + q];
-    for (int q = 0; q < 6; q++) acc[q] = wave_sum(acc[q]);
-    if (lane == 0) {
+    for (int q = 0; q < 6; q++) {
+        const double t = wave_sum(acc[q]);
+        if (lane == 0) red[wave][q] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
         double t[6];
-        for (int q = 0; q < 6; q++) t[q] = stats[6 * s + q] + acc[q];
+        for (int q = 0; q < 6; q++) t[q] = stats[6 * s + q] + red[0][q] + red[1][q] + red[2][q] + red[3][q];
         int64_t n = nv + ne + nf;
         if (S > 1) {
             n = 0;
@@ -629,8 +634,8 @@ void launch_broad_boxes(const double *V0, const double *V1, int64_t nv, const in
         box_kernel<<<(unsigned)nblk, kBoxBlock, 0, s>>>(V0, V1, nv, E, ne, F, nf, B.off, B.nscenes, B.lo[0],
                                                        B.lo[1], B.lo[2], B.hi[0], B.hi[1], B.hi[2], B.bscene, B.stats,
                                                        B.partial, B.partial_scene, B.flags);
-    axis_kernel<<<(unsigned)B.nscenes, 64, 0, s>>>(B.stats, B.partial, B.partial_scene, nb > 0 ? nblk : 0, B.off,
-                                                  B.nscenes, nv, ne, nf, B.axis);
+    axis_kernel<<<(unsigned)B.nscenes, 256, 0, s>>>(B.stats, B.partial, B.partial_scene, nb > 0 ? nblk : 0, B.off,
+                                                   B.nscenes, nv, ne, nf, B.axis);
 }
 
 void launch_broad_sort(int64_t nv, int64_t ne, int64_t nf, const BroadBuffers &B, int64_t nblocks_sort,

@@ -235,7 +235,8 @@ void launch_check_permutation(const int32_t *order, int64_t n, uint32_t *bits, u
 // Wide stage: `nslots` workgroups, each with a frontier buffer of `cap` nodes
 // (two buffers of 3 x cap uint64).  Round 0 works on every handed-over pair;
 // round r > 0 re-runs the pairs that overflowed their buffer in round r - 1.
-// block: threads per pair (64 or 256); use_lds: frontiers of at most
+// block: threads per pair (64, 256 or 1024; 0 = 1024 for at most 256 entries,
+// else 256, decided on the device); use_lds: frontiers of at most
 // 2 block intervals stay in LDS between levels.
 void launch_narrow_heavy(const double *V0, const double *V1, PairCounts pc, double delta, long long max_iter,
                          uint8_t *hit, double *toi, long long *n_enq, const NarrowBuffers &B, int nslots,

@@ -27,8 +27,9 @@ namespace ccd {
 
 namespace {
 
-// Wide stage: one workgroup of BLOCK threads (64 or 256) per pair; frontiers
-// of up to 2 BLOCK intervals may stay in LDS (6 KB or 24 KB: no occupancy cost).
+// Wide stage: one workgroup of BLOCK threads (64, 256 or 1024) per pair;
+// frontiers of up to 2 BLOCK intervals may stay in LDS (6, 24 or 96 KB: no
+// occupancy cost at the kernel's register use).
 constexpr int kPoolSlots = 64;   // pairs in flight per wave (one owner lane each)
 constexpr int kQCap = 512;       // intervals per round per wave
 constexpr int kClaim = 64;       // pairs a wave claims from the global list at once
@@ -303,12 +304,30 @@ __device__ __forceinline__ void pair_features(const double raw[24], bool vf, con
         Lt = fmax(Lt, lt);
         Lu = fmax(Lu, lu);
         Lv = fmax(Lv, lv);
+        // F at the 8 corners of the root box.  At t, u, v in {0, 1} the canonical
+        // sequence reduces exactly (finite inputs): fma(0, x, y) = y and
+        // fma(+-1, x, y) = y +- x rounded once, so these are its values.
         double bmin = __builtin_huge_val(), bmax = -__builtin_huge_val();
 #pragma unroll 1
-        for (int c = 0; c < 8; c++) {
-            const double fv = eval_point(raw, vf, a, (double)(c & 1), (double)((c >> 1) & 1), (double)(c >> 2));
-            bmin = fmin(bmin, fv);
-            bmax = fmax(bmax, fv);
+        for (int tc = 0; tc < 2; tc++) {
+            double P[4];
+#pragma unroll
+            for (int k = 0; k < 4; k++) P[k] = tc ? raw[3 * k + a] + dd[k] : raw[3 * k + a];
+            double fv[4];
+            if (vf) {
+                const double g0 = P[0] - P[1], e1 = P[2] - P[1], e2 = P[3] - P[1];
+                const double g1 = g0 - e1;               // u = 1
+                fv[0] = g0; fv[1] = g1; fv[2] = g0 - e2; fv[3] = g1 - e2;
+            } else {
+                const double ea = P[1] - P[0], eb = P[3] - P[2];
+                const double A1 = ea + P[0], B1 = eb + P[2];  // u = 1, v = 1
+                fv[0] = P[0] - P[2]; fv[1] = A1 - P[2]; fv[2] = P[0] - B1; fv[3] = A1 - B1;
+            }
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                bmin = fmin(bmin, fv[j]);
+                bmax = fmax(bmax, fv[j]);
+            }
         }
         const double e = eps[a];
         gap = fmax(gap, fmax(bmin - e, -e - bmax));
@@ -370,7 +389,7 @@ __global__ __launch_bounds__(256) void feature_kernel(const double *__restrict__
 // pairs as 4 tiles of 16), and the histogram of predicted-cost bins (1/4 in
 // log2 cost, costliest first) for the ordering.  Grid-stride over chunks of
 // 256 pairs.
-__global__ __launch_bounds__(256) void sched_kernel(const double *__restrict__ V0, const double *__restrict__ V1,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void sched_kernel(const double *__restrict__ V0, const double *__restrict__ V1,
                                                     const int4 *__restrict__ ids4, const double *__restrict__ peps,
                                                     const uint32_t *__restrict__ pm, PairCounts pc, double delta,
                                                     const float *__restrict__ prm, const float *__restrict__ norm,
@@ -821,7 +840,7 @@ __global__ __launch_bounds__(BLOCK) void heavy_kernel(
     long long max_iter, uint8_t *hit, double *toi, long long *n_enq_out, const HeavyEntry *__restrict__ heavy,
     const unsigned long long *__restrict__ hnodes, const int32_t *list, const unsigned int *list_count,
     unsigned int *next, int32_t *ovf_list, unsigned int *ovf_count, unsigned long long *scratch, int64_t cap,
-    uint32_t *flags, int use_lds)
+    uint32_t *flags, int use_lds, const unsigned int *list_base, unsigned int min_count, unsigned int max_count)
 {
     // Frontier of the next level: in LDS when it surely fits (at most twice the
     // current frontier), else in this workgroup's HBM buffers.
@@ -838,6 +857,13 @@ __global__ __launch_bounds__(BLOCK) void heavy_kernel(
     int64_t n_vf, n_all;
     pc.get(n_vf, n_all);
     (void)n_all;
+    // Adaptive launches start two variants of this kernel; only the one whose
+    // range holds the number of entries left to it (those past list_base, which
+    // the early wide stage took) takes any.
+    {
+        const unsigned int c0 = *list_count - (list_base ? *list_base : 0u);
+        if (c0 < min_count || c0 > max_count) return;
+    }
     unsigned long long *A = scratch + (int64_t)blockIdx.x * 6 * cap;
     unsigned long long *Bb = A + 3 * cap;
     for (;;) {
@@ -1146,12 +1172,61 @@ void launch_narrow_pool(const double *V0, const double *V1, PairCounts pc, doubl
                                                        order_n, wait);
 }
 
+namespace {
+
+// Few wide-stage pairs: 1,024 threads each (latency: one pass per level);
+// many: 256 threads each on more workgroups (throughput).
+constexpr unsigned int kWideFew = 256;
+
+void heavy_variant(int block, int nslots, unsigned int lo, unsigned int hi, const double *V0, const double *V1,
+                   PairCounts pc, double delta, long long max_iter, uint8_t *hit, double *toi, long long *n_enq,
+                   const NarrowBuffers &B, const int32_t *list, const unsigned int *count, unsigned int *next,
+                   int32_t *ovf, unsigned int *ovf_count, unsigned long long *scratch, int64_t cap, int use_lds,
+                   const unsigned int *base, hipStream_t s)
+{
+    if (block == 1024)
+        heavy_kernel<1024><<<(unsigned)nslots, 1024, 0, s>>>(V0, V1, B.ids4, B.eps, B.m, pc, delta, max_iter, hit,
+                                                            toi, n_enq, B.heavy, B.hnodes, list, count, next, ovf,
+                                                            ovf_count, scratch, cap, B.flags, use_lds, base, lo, hi);
+    else if (block == 64)
+        heavy_kernel<64><<<(unsigned)nslots, 64, 0, s>>>(V0, V1, B.ids4, B.eps, B.m, pc, delta, max_iter, hit, toi,
+                                                        n_enq, B.heavy, B.hnodes, list, count, next, ovf, ovf_count,
+                                                        scratch, cap, B.flags, use_lds, base, lo, hi);
+    else
+        heavy_kernel<256><<<(unsigned)nslots, 256, 0, s>>>(V0, V1, B.ids4, B.eps, B.m, pc, delta, max_iter, hit, toi,
+                                                          n_enq, B.heavy, B.hnodes, list, count, next, ovf, ovf_count,
+                                                          scratch, cap, B.flags, use_lds, base, lo, hi);
+}
+
+// block 0: adaptive (both variants, each for its range of entry counts).
+void heavy_launch(int block, int nslots, const double *V0, const double *V1, PairCounts pc, double delta,
+                  long long max_iter, uint8_t *hit, double *toi, long long *n_enq, const NarrowBuffers &B,
+                  const int32_t *list, const unsigned int *count, unsigned int *next, int32_t *ovf,
+                  unsigned int *ovf_count, unsigned long long *scratch, int64_t cap, int use_lds,
+                  const unsigned int *base, hipStream_t s)
+{
+    if (block != 0) {
+        heavy_variant(block, nslots, 0u, 0xffffffffu, V0, V1, pc, delta, max_iter, hit, toi, n_enq, B, list, count,
+                      next, ovf, ovf_count, scratch, cap, use_lds, base, s);
+        return;
+    }
+    const int few = nslots < (int)kWideFew ? nslots : (int)kWideFew;
+    heavy_variant(1024, few, 0u, kWideFew, V0, V1, pc, delta, max_iter, hit, toi, n_enq, B, list, count, next, ovf,
+                  ovf_count, scratch, cap, use_lds, base, s);
+    heavy_variant(256, nslots, kWideFew + 1, 0xffffffffu, V0, V1, pc, delta, max_iter, hit, toi, n_enq, B, list,
+                  count, next, ovf, ovf_count, scratch, cap, use_lds, base, s);
+}
+
+}  // namespace
+
 void launch_narrow_heavy(const double *V0, const double *V1, PairCounts pc, double delta, long long max_iter,
                          uint8_t *hit, double *toi, long long *n_enq, const NarrowBuffers &B, int nslots,
                          int64_t cap, int round, int use_lds, int block, hipStream_t s)
 {
     // counters: [0] handed-over pairs, [1] work index of the first round,
-    // [2] / [3] overflow counts of list 0 / 1, [4] work index of re-runs.
+    // [2] / [3] overflow counts of list 0 / 1, [4] work index of re-runs,
+    // [12] entries the early wide stage took (the first round starts past them).
+    const unsigned int *base = &B.counters[12];
     const int32_t *list = nullptr;
     const unsigned int *count = &B.counters[0];
     unsigned int *next = &B.counters[1];
@@ -1161,16 +1236,13 @@ void launch_narrow_heavy(const double *V0, const double *V1, PairCounts pc, doub
         list = B.overflow_list[(round - 1) & 1];
         count = &B.counters[2 + ((round - 1) & 1)];
         next = &B.counters[4];
+        base = nullptr;
         rerun_reset_kernel<<<1, 1, 0, s>>>(B.counters, round);
+        // re-runs hold the widest frontiers: always the many-pairs variant
+        if (block == 0) block = 256;
     }
-    if (block == 64)
-        heavy_kernel<64><<<(unsigned)nslots, 64, 0, s>>>(V0, V1, B.ids4, B.eps, B.m, pc, delta, max_iter, hit, toi,
-                                                        n_enq, B.heavy, B.hnodes, list, count, next, ovf, ovf_count,
-                                                        B.scratch, cap, B.flags, use_lds);
-    else
-        heavy_kernel<256><<<(unsigned)nslots, 256, 0, s>>>(V0, V1, B.ids4, B.eps, B.m, pc, delta, max_iter, hit, toi,
-                                                          n_enq, B.heavy, B.hnodes, list, count, next, ovf, ovf_count,
-                                                          B.scratch, cap, B.flags, use_lds);
+    heavy_launch(block, nslots, V0, V1, pc, delta, max_iter, hit, toi, n_enq, B, list, count, next, ovf, ovf_count,
+                 B.scratch, cap, use_lds, base, s);
 }
 
 void launch_narrow_heavy_early(const double *V0, const double *V1, PairCounts pc, double delta, long long max_iter,
@@ -1178,16 +1250,8 @@ void launch_narrow_heavy_early(const double *V0, const double *V1, PairCounts pc
                                unsigned long long *scratch, int nslots, int64_t cap, int use_lds, int block,
                                hipStream_t s)
 {
-    if (block == 64)
-        heavy_kernel<64><<<(unsigned)nslots, 64, 0, s>>>(V0, V1, B.ids4, B.eps, B.m, pc, delta, max_iter, hit, toi,
-                                                        n_enq, B.heavy, B.hnodes, nullptr, &B.counters[12],
-                                                        &B.counters[13], B.overflow_list[0], &B.counters[2], scratch,
-                                                        cap, B.flags, use_lds);
-    else
-        heavy_kernel<256><<<(unsigned)nslots, 256, 0, s>>>(V0, V1, B.ids4, B.eps, B.m, pc, delta, max_iter, hit, toi,
-                                                          n_enq, B.heavy, B.hnodes, nullptr, &B.counters[12],
-                                                          &B.counters[13], B.overflow_list[0], &B.counters[2], scratch,
-                                                          cap, B.flags, use_lds);
+    heavy_launch(block, nslots, V0, V1, pc, delta, max_iter, hit, toi, n_enq, B, nullptr, &B.counters[12],
+                 &B.counters[13], B.overflow_list[0], &B.counters[2], scratch, cap, use_lds, nullptr, s);
 }
 
 void launch_toi_min(const double *toi, PairCounts pc, double *out, hipStream_t s)

@@ -274,7 +274,10 @@ def test_end_to_end_cloth(ctx):
                                     {"sweep_tile_group": 1, "pool_blocks_per_cu": 1},
                                     {"heavy_block": 64, "heavy_slots": 4096, "heavy_lds": 1},
                                     {"heavy_block": 64, "heavy_cap_log2": 8, "pool_wait": 1},
-                                    {"heavy_lds": 0, "pool_wait": 1, "heavy_cap_log2": 17}])
+                                    {"heavy_lds": 0, "pool_wait": 1, "heavy_cap_log2": 17},
+                                    {"heavy_block": 1024, "heavy_slots": 256},
+                                    {"heavy_block": 1024, "heavy_lds": 0, "heavy_cap_log2": 10},
+                                    {"heavy_block": 256}])
 def test_tunings_give_identical_results(ctx, tuning):
     """Launch shapes (LDS frontiers, tiny wide-stage buffers that force re-runs, one pool workgroup per CU,
     ungrouped sweep tiles, one-wave wide-stage workgroups, no waiting in the pool) never change a result."""
