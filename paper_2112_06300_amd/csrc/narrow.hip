@@ -439,14 +439,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
     if (h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
 }
 
-__device__ __forceinline__ int wave_excl_scan(int v, int lane, int &total)
+// Exclusive prefix sum over the wave and its total: shifts within each row of
+// 16 lanes (DPP row_shr 1, 2, 4, 8), then the row totals carried forward by
+// the row broadcasts of lanes 15 and 31.  All lanes must be active.
+__device__ __forceinline__ int wave_excl_scan(int v, int &total)
 {
     int x = v;
-    for (int o = 1; o < 64; o <<= 1) {
-        const int w = __shfl_up(x, o);
-        if (lane >= o) x += w;
-    }
-    total = __shfl(x, 63);
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);  // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);  // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);  // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);  // row_shr:8
+    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);  // row_bcast:15 into rows 1, 3
+    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);  // row_bcast:31 into rows 2, 3
+    total = __builtin_amdgcn_readlane(x, 63);
     return x - v;
 }
 
@@ -474,11 +479,13 @@ constexpr unsigned long long kCarryBit = 1ull << 63;
 
 // Queue offsets of this round's pushes: pairs that waited last round first,
 // then the others, each group in lane order.
-__device__ __forceinline__ int push_offset(bool pushing, bool first, int n, int lane, int &total)
+// (wait = 0: no pair ever waits, one group.)
+__device__ __forceinline__ int push_offset(bool pushing, bool first, int n, int wait, int &total)
 {
+    if (!wait) return wave_excl_scan(pushing ? n : 0, total);
     int t1 = 0, t2 = 0;
-    const int o1 = wave_excl_scan(pushing && first ? n : 0, lane, t1);
-    const int o2 = wave_excl_scan(pushing && !first ? n : 0, lane, t2);
+    const int o1 = wave_excl_scan(pushing && first ? n : 0, t1);
+    const int o2 = wave_excl_scan(pushing && !first ? n : 0, t2);
     total = t1 + t2;
     return first ? o1 : t1 + o2;
 }
@@ -556,17 +563,25 @@ __global__ __launch_bounds__(kPoolSlots) void pool_kernel(
     S.mm[lane] = 0u;
 
     for (;;) {
-        // ---- prefetch pipeline (uniform control flow)
-        if (pb < 0 && pa >= 0) {
-            // stage B: gather the points of the pair whose ids arrived last round
+        // ---- prefetch pipeline (uniform control flow).  Stage A's registers
+        // were loaded a round ago: they are taken on every path before any
+        // load of this round is issued, and the gathers go last, so that no
+        // wait in this phase covers a load just issued.
+        asm volatile("" : "+v"(ida.x), "+v"(ida.y), "+v"(ida.z), "+v"(ida.w), "+v"(epsa[0]), "+v"(epsa[1]),
+                     "+v"(epsa[2]), "+v"(ma), "+v"(pa) : : "memory");
+        const bool doB = pb < 0 && pa >= 0;
+        const int4 idb = ida;
+        if (doB) {
+            // stage B takes the pair whose ids arrived last round
             pb = pa;
             pa = -1;
-            okb = ida.x >= 0;
-            if (okb) load_raw(ida, V0, V1, raw);
+            okb = idb.x >= 0;
             epsb[0] = epsa[0]; epsb[1] = epsa[1]; epsb[2] = epsa[2];
             mb = ma;
         }
         bool need = pa < 0 && !exhausted;
+        bool got = false;
+        long long qa = 0;
         unsigned long long want = __ballot(need);
         while (want) {
             if (ch_cur >= ch_end) {
@@ -580,18 +595,23 @@ __global__ __launch_bounds__(kPoolSlots) void pool_kernel(
             const long long avail = ch_end - ch_cur;
             const long long rank = __popcll(want & lt_mask);
             if (need && rank < avail) {
-                // stage A: ids, C_eps and split levels of the claimed pair (in schedule order)
-                pa = ch_cur + rank;
-                if (order) pa = order[pa];
+                qa = ch_cur + rank;
+                got = true;
                 need = false;
-                ida = ids4[pa];
-                epsa[0] = peps[3 * pa]; epsa[1] = peps[3 * pa + 1]; epsa[2] = peps[3 * pa + 2];
-                ma = pm[pa];
             }
             const long long taken = __popcll(want) < avail ? __popcll(want) : avail;
             ch_cur += taken;
             want = __ballot(need);
         }
+        if (got) {
+            // stage A: ids, C_eps and split levels of the claimed pair (in schedule order)
+            pa = order ? (long long)order[qa] : qa;
+            ida = ids4[pa];
+            epsa[0] = peps[3 * pa]; epsa[1] = peps[3 * pa + 1]; epsa[2] = peps[3 * pa + 2];
+            ma = pm[pa];
+        }
+        // stage B: gather the points
+        if (doB && okb) load_raw(idb, V0, V1, raw);
         const int nxt = cur ^ 1;
 
         // ---- D (all lanes over last round's entries): count children that start before t*
@@ -641,7 +661,7 @@ __global__ __launch_bounds__(kPoolSlots) void pool_kernel(
             }
         }
         int total = 0;
-        int off = push_offset(outcome == 4, waiting, push, lane, total);
+        int off = push_offset(outcome == 4, waiting, push, wait, total);
         int coff = 0;
         if (total > kQCap) {
             // Children that do not fit this round: a pair whose children could
@@ -650,12 +670,12 @@ __global__ __launch_bounds__(kPoolSlots) void pool_kernel(
             // n_enq do not change while a pair waits).  The first pusher always
             // fits, so some pair advances every round.
             if (outcome == 4 && off + push > kQCap) outcome = (push > kQCap || !wait) ? 3 : 5;
-            off = push_offset(outcome == 4, waiting, push, lane, total);
+            off = push_offset(outcome == 4, waiting, push, wait, total);
             int ctotal = 0;
-            coff = wave_excl_scan(outcome == 5 ? nsurv : 0, lane, ctotal);
+            coff = wave_excl_scan(outcome == 5 ? nsurv : 0, ctotal);
             if (total + ctotal > kQCap) {
                 if (outcome == 5 && total + coff + nsurv > kQCap) outcome = 3;
-                coff = wave_excl_scan(outcome == 5 ? nsurv : 0, lane, ctotal);
+                coff = wave_excl_scan(outcome == 5 ? nsurv : 0, ctotal);
             }
             coff += total;
             total += ctotal;
@@ -710,8 +730,7 @@ __global__ __launch_bounds__(kPoolSlots) void pool_kernel(
             pb = -1;
         }
         const bool new_root = !active && pb >= 0;
-        int rtotal = 0;
-        const int roff = wave_excl_scan(new_root ? 1 : 0, lane, rtotal);
+        const int roff = __popcll(__ballot(new_root) & lt_mask);
         const bool root_fits = new_root && total + roff < kQCap;
         if (root_fits) {
             p = pb;
