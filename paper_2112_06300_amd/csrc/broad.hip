@@ -28,6 +28,12 @@ constexpr int kSortRounds = 16;
 constexpr int kSortTile = kSortThreads * kSortRounds;  // 4096 keys per block
 constexpr int kBins = 3 * 256;                        // segment x digit
 constexpr int kTile = 64;
+// A tile's candidate window is split into chunks of kSweepChunk candidates,
+// each swept by its own wave (the last chunk runs to the window's end), so
+// that long windows -- edge-edge tiles run about 3x longer than the others --
+// do not leave the end of the sweep to a few waves.
+constexpr int64_t kSweepChunk = 1024;
+constexpr int kChunksEE = 4, kChunksVF = 2;
 
 __global__ void zero_kernel(double *stats, int64_t nstats, unsigned long long *counts, uint32_t *flags)
 {
@@ -531,8 +537,8 @@ __device__ __forceinline__ void sweep_emit(int64_t j, bool ok, const SweepRecord
 template <typename K, int ROLE>
 __device__ __forceinline__ void sweep_tile(const K *__restrict__ klo, const K *__restrict__ khi,
                                            const SweepRecords &R, int64_t qbase, int64_t qend, int64_t cbeg,
-                                           int64_t cend, int32_t *__restrict__ out, int64_t out_cap,
-                                           unsigned long long *counter, int32_t (*s_out)[2])
+                                           int64_t cend, int64_t chunk, int64_t nchunks, int32_t *__restrict__ out,
+                                           int64_t out_cap, unsigned long long *counter, int32_t (*s_out)[2])
 {
     constexpr int U = SweepUnroll<K>::value;
     const int lane = threadIdx.x;
@@ -552,9 +558,13 @@ __device__ __forceinline__ void sweep_tile(const K *__restrict__ klo, const K *_
     const K kmin = uniform(wave_min_key(kl)), kmax = uniform(wave_max_key(kh));
     int64_t j = ROLE == 1 ? qbase + 1 : wave_lower_bound(klo, cbeg, cend, kmin, ROLE == 2, lane);
     j = (int64_t)uniform((unsigned long long)j);
+    // this wave's chunk of the window
+    const int64_t jw = j;
+    j = jw + chunk * kSweepChunk;
+    const int64_t jend = chunk == nchunks - 1 ? cend : (jw + (chunk + 1) * kSweepChunk < cend ? jw + (chunk + 1) * kSweepChunk : cend);
     int fill = 0;  // pairs staged in s_out (wave-uniform)
     bool done = false;
-    for (; j + U <= cend; j += U) {
+    for (; j + U <= jend; j += U) {
         K kk[U];
         float bl[U], bh[U], cl[U], ch[U];
 #pragma unroll
@@ -580,7 +590,7 @@ __device__ __forceinline__ void sweep_tile(const K *__restrict__ klo, const K *_
             if (__ballot(ok[u])) sweep_emit<K, ROLE>(j + u, ok[u], R, me, w0, w1, w2, lane, lt, fill, out, out_cap,
                                                      counter, s_out);
     }
-    for (; !done && j < cend; j++) {
+    for (; !done && j < jend; j++) {
         const K kj = klo[j];
         if (kj > kmax) break;
         bool t = (kj <= kh) & (R.lob[j] <= hb) & (lb <= R.hib[j]) & (R.loc[j] <= hc) & (lc <= R.hic[j]);
@@ -600,21 +610,27 @@ __global__ __launch_bounds__(kTile) void sweep_kernel(
     const K *__restrict__ klo, const K *__restrict__ khi, const float *__restrict__ lob,
     const float *__restrict__ hib, const float *__restrict__ loc, const float *__restrict__ hic,
     const int32_t *__restrict__ pid, const int32_t *__restrict__ vtx, int64_t nv, int64_t ne, int64_t nf,
-    int64_t tiles_v, int64_t tiles_e, int64_t ntiles, int64_t group, int32_t *__restrict__ vf, int64_t vf_cap,
-    int32_t *__restrict__ ee, int64_t ee_cap, unsigned long long *counts)
+    int64_t tiles_v, int64_t tiles_e, int64_t ntiles, int64_t tiles_grid, int64_t group, int32_t *__restrict__ vf,
+    int64_t vf_cap, int32_t *__restrict__ ee, int64_t ee_cap, unsigned long long *counts)
 {
     __shared__ int32_t s_out[kOutCap][2];
     const int64_t nb = nv + ne + nf, f0 = nv + ne;
-    const int64_t t = xcd_tile(blockIdx.x, group);
+    // block = chunk * tiles_grid + (tile slot); tiles_grid is a multiple of 8 * group
+    const int64_t chunk = (int64_t)blockIdx.x / tiles_grid;
+    const int64_t t = xcd_tile((int64_t)blockIdx.x % tiles_grid, group);
     if (t >= ntiles) return;
     const SweepRecords R{lob, hib, loc, hic, pid, vtx};
-    if (t < tiles_v)
-        sweep_tile<K, 0>(klo, khi, R, t * kTile, nv, f0, nb, vf, vf_cap, &counts[0], s_out);
-    else if (t < tiles_v + tiles_e)
-        sweep_tile<K, 1>(klo, khi, R, nv + (t - tiles_v) * kTile, f0, nv, f0, ee, ee_cap, &counts[1], s_out);
-    else
-        sweep_tile<K, 2>(klo, khi, R, f0 + (t - tiles_v - tiles_e) * kTile, nb, 0, nv, vf, vf_cap, &counts[0],
-                         s_out);
+    if (t < tiles_v) {
+        if (chunk >= kChunksVF) return;
+        sweep_tile<K, 0>(klo, khi, R, t * kTile, nv, f0, nb, chunk, kChunksVF, vf, vf_cap, &counts[0], s_out);
+    } else if (t < tiles_v + tiles_e) {
+        sweep_tile<K, 1>(klo, khi, R, nv + (t - tiles_v) * kTile, f0, nv, f0, chunk, kChunksEE, ee, ee_cap,
+                         &counts[1], s_out);
+    } else {
+        if (chunk >= kChunksVF) return;
+        sweep_tile<K, 2>(klo, khi, R, f0 + (t - tiles_v - tiles_e) * kTile, nb, 0, nv, chunk, kChunksVF, vf, vf_cap,
+                         &counts[0], s_out);
+    }
 }
 
 inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
@@ -692,15 +708,16 @@ void launch_broad_sweep(int64_t nv, int64_t ne, int64_t nf, int32_t *vf, int64_t
     const int64_t nt = tv + te + tf;
     if (nt == 0) return;
     const int64_t g = tile_group < 1 ? 1 : tile_group;
-    const int64_t grid = (nt + 8 * g - 1) / (8 * g) * (8 * g);
+    const int64_t tiles_grid = (nt + 8 * g - 1) / (8 * g) * (8 * g);
+    const int64_t grid = tiles_grid * (kChunksEE > kChunksVF ? kChunksEE : kChunksVF);
     if (B.nscenes > 1)
         sweep_kernel<unsigned long long><<<(unsigned)grid, kTile, 0, s>>>(
-            B.klo64, B.khi64, B.lob, B.hib, B.loc, B.hic, B.pid, B.vtx, nv, ne, nf, tv, te, nt, g, vf, vf_cap, ee,
-            ee_cap, B.counts);
+            B.klo64, B.khi64, B.lob, B.hib, B.loc, B.hic, B.pid, B.vtx, nv, ne, nf, tv, te, nt, tiles_grid, g, vf,
+            vf_cap, ee, ee_cap, B.counts);
     else
         sweep_kernel<uint32_t><<<(unsigned)grid, kTile, 0, s>>>(sorted_keys(B), B.khi, B.lob, B.hib, B.loc, B.hic,
-                                                               B.pid, B.vtx, nv, ne, nf, tv, te, nt, g, vf, vf_cap,
-                                                               ee, ee_cap, B.counts);
+                                                               B.pid, B.vtx, nv, ne, nf, tv, te, nt, tiles_grid, g,
+                                                               vf, vf_cap, ee, ee_cap, B.counts);
 }
 
 int64_t sort_blocks(int64_t nb) { return nb > 0 ? (nb + kSortTile - 1) / kSortTile : 1; }
