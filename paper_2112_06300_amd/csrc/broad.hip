@@ -28,12 +28,16 @@ constexpr int kSortRounds = 16;
 constexpr int kSortTile = kSortThreads * kSortRounds;  // 4096 keys per block
 constexpr int kBins = 3 * 256;                        // segment x digit
 constexpr int kTile = 64;
-// A tile's candidate window is split into chunks of kSweepChunk candidates,
-// each swept by its own wave (the last chunk runs to the window's end), so
-// that long windows -- edge-edge tiles run about 3x longer than the others --
-// do not leave the end of the sweep to a few waves.
-constexpr int64_t kSweepChunk = 1024;
-constexpr int kChunksEE = 4, kChunksVF = 2;
+// A tile's candidate window is split into chunks, each swept by its own wave
+// (the last chunk runs to the window's end), so that long windows -- edge-edge
+// tiles run about 3x longer than the others -- do not leave the end of the
+// sweep to a few waves.  Worth it while the tiles alone do not fill the GPU
+// several times over (see launch_broad_sweep).
+struct SweepChunks {
+    int64_t len;  // candidates per chunk
+    int64_t ee;   // chunks of an edge-edge tile
+    int64_t vf;   // chunks of a vertex or face tile
+};
 
 __global__ void zero_kernel(double *stats, int64_t nstats, unsigned long long *counts, uint32_t *flags)
 {
@@ -537,7 +541,8 @@ __device__ __forceinline__ void sweep_emit(int64_t j, bool ok, const SweepRecord
 template <typename K, int ROLE>
 __device__ __forceinline__ void sweep_tile(const K *__restrict__ klo, const K *__restrict__ khi,
                                            const SweepRecords &R, int64_t qbase, int64_t qend, int64_t cbeg,
-                                           int64_t cend, int64_t chunk, int64_t nchunks, int32_t *__restrict__ out,
+                                           int64_t cend, int64_t chunk, int64_t nchunks, int64_t clen,
+                                           int32_t *__restrict__ out,
                                            int64_t out_cap, unsigned long long *counter, int32_t (*s_out)[2])
 {
     constexpr int U = SweepUnroll<K>::value;
@@ -560,8 +565,8 @@ __device__ __forceinline__ void sweep_tile(const K *__restrict__ klo, const K *_
     j = (int64_t)uniform((unsigned long long)j);
     // this wave's chunk of the window
     const int64_t jw = j;
-    j = jw + chunk * kSweepChunk;
-    const int64_t jend = chunk == nchunks - 1 ? cend : (jw + (chunk + 1) * kSweepChunk < cend ? jw + (chunk + 1) * kSweepChunk : cend);
+    j = jw + chunk * clen;
+    const int64_t jend = chunk == nchunks - 1 ? cend : (jw + (chunk + 1) * clen < cend ? jw + (chunk + 1) * clen : cend);
     int fill = 0;  // pairs staged in s_out (wave-uniform)
     bool done = false;
     for (; j + U <= jend; j += U) {
@@ -610,8 +615,8 @@ __global__ __launch_bounds__(kTile) void sweep_kernel(
     const K *__restrict__ klo, const K *__restrict__ khi, const float *__restrict__ lob,
     const float *__restrict__ hib, const float *__restrict__ loc, const float *__restrict__ hic,
     const int32_t *__restrict__ pid, const int32_t *__restrict__ vtx, int64_t nv, int64_t ne, int64_t nf,
-    int64_t tiles_v, int64_t tiles_e, int64_t ntiles, int64_t tiles_grid, int64_t group, int32_t *__restrict__ vf,
-    int64_t vf_cap, int32_t *__restrict__ ee, int64_t ee_cap, unsigned long long *counts)
+    int64_t tiles_v, int64_t tiles_e, int64_t ntiles, int64_t tiles_grid, int64_t group, SweepChunks ch,
+    int32_t *__restrict__ vf, int64_t vf_cap, int32_t *__restrict__ ee, int64_t ee_cap, unsigned long long *counts)
 {
     __shared__ int32_t s_out[kOutCap][2];
     const int64_t nb = nv + ne + nf, f0 = nv + ne;
@@ -621,15 +626,16 @@ __global__ __launch_bounds__(kTile) void sweep_kernel(
     if (t >= ntiles) return;
     const SweepRecords R{lob, hib, loc, hic, pid, vtx};
     if (t < tiles_v) {
-        if (chunk >= kChunksVF) return;
-        sweep_tile<K, 0>(klo, khi, R, t * kTile, nv, f0, nb, chunk, kChunksVF, vf, vf_cap, &counts[0], s_out);
+        if (chunk >= ch.vf) return;
+        sweep_tile<K, 0>(klo, khi, R, t * kTile, nv, f0, nb, chunk, ch.vf, ch.len, vf, vf_cap, &counts[0], s_out);
     } else if (t < tiles_v + tiles_e) {
-        sweep_tile<K, 1>(klo, khi, R, nv + (t - tiles_v) * kTile, f0, nv, f0, chunk, kChunksEE, ee, ee_cap,
+        if (chunk >= ch.ee) return;
+        sweep_tile<K, 1>(klo, khi, R, nv + (t - tiles_v) * kTile, f0, nv, f0, chunk, ch.ee, ch.len, ee, ee_cap,
                          &counts[1], s_out);
     } else {
-        if (chunk >= kChunksVF) return;
-        sweep_tile<K, 2>(klo, khi, R, f0 + (t - tiles_v - tiles_e) * kTile, nb, 0, nv, chunk, kChunksVF, vf, vf_cap,
-                         &counts[0], s_out);
+        if (chunk >= ch.vf) return;
+        sweep_tile<K, 2>(klo, khi, R, f0 + (t - tiles_v - tiles_e) * kTile, nb, 0, nv, chunk, ch.vf, ch.len, vf,
+                         vf_cap, &counts[0], s_out);
     }
 }
 
@@ -709,15 +715,19 @@ void launch_broad_sweep(int64_t nv, int64_t ne, int64_t nf, int32_t *vf, int64_t
     if (nt == 0) return;
     const int64_t g = tile_group < 1 ? 1 : tile_group;
     const int64_t tiles_grid = (nt + 8 * g - 1) / (8 * g) * (8 * g);
-    const int64_t grid = tiles_grid * (kChunksEE > kChunksVF ? kChunksEE : kChunksVF);
+    // Measured (cloth on sphere, 7k tiles: 768 x 5 / 2 best; perturbed torus,
+    // 47k tiles: 2048 x 2 / 1 best): short chunks while the tiles number a few
+    // waves per SIMD, long ones beyond.
+    const SweepChunks ch = nt <= 16384 ? SweepChunks{768, 5, 2} : SweepChunks{2048, 2, 1};
+    const int64_t grid = tiles_grid * (ch.ee > ch.vf ? ch.ee : ch.vf);
     if (B.nscenes > 1)
         sweep_kernel<unsigned long long><<<(unsigned)grid, kTile, 0, s>>>(
-            B.klo64, B.khi64, B.lob, B.hib, B.loc, B.hic, B.pid, B.vtx, nv, ne, nf, tv, te, nt, tiles_grid, g, vf,
+            B.klo64, B.khi64, B.lob, B.hib, B.loc, B.hic, B.pid, B.vtx, nv, ne, nf, tv, te, nt, tiles_grid, g, ch, vf,
             vf_cap, ee, ee_cap, B.counts);
     else
         sweep_kernel<uint32_t><<<(unsigned)grid, kTile, 0, s>>>(sorted_keys(B), B.khi, B.lob, B.hib, B.loc, B.hic,
                                                                B.pid, B.vtx, nv, ne, nf, tv, te, nt, tiles_grid, g,
-                                                               vf, vf_cap, ee, ee_cap, B.counts);
+                                                               ch, vf, vf_cap, ee, ee_cap, B.counts);
 }
 
 int64_t sort_blocks(int64_t nb) { return nb > 0 ? (nb + kSortTile - 1) / kSortTile : 1; }

@@ -15,8 +15,8 @@ and a large randomly perturbed closed surface.
 from .meshes import icosphere, grid_cloth, torus, edges_of_faces, merge_meshes
 from .configs import (Scene, two_spheres, cloth_on_sphere, perturbed_torus, scene_batch, concat_scenes,
                       sample_pairs, degenerate_gadgets,
-                      tiny_random_scene, make_config, CONFIG_NAMES)
+                      tiny_random_scene, sliding_slivers, make_config, CONFIG_NAMES)
 
 __all__ = ["icosphere", "grid_cloth", "torus", "edges_of_faces", "merge_meshes",
            "Scene", "two_spheres", "cloth_on_sphere", "perturbed_torus",
-           "tiny_random_scene", "make_config", "CONFIG_NAMES"]
+           "tiny_random_scene", "sliding_slivers", "make_config", "CONFIG_NAMES"]

@@ -192,6 +192,22 @@ def tiny_random_scene(seed, n_tris=6, extent=1.0, motion=0.6, dyadic_bits=None):
     return _scene("tiny_random", V0, V1, F, seed=seed)
 
 
+def sliding_slivers(seed=3, n_tris=4000, length=20.0, size=0.01, slide=5.0):
+    """Small disconnected triangles scattered along a long bar, each sliding
+    along it by up to +-slide: boxes are long on the sweep axis and tiny on the
+    other two, so sweep windows hold hundreds to thousands of candidates while
+    few of them overlap (a stress case for long windows).
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    c = np.column_stack([rng.uniform(-length / 2, length / 2, n_tris), rng.uniform(-1.0, 1.0, (n_tris, 2))])
+    V0 = np.repeat(c, 3, axis=0) + rng.uniform(-size, size, (3 * n_tris, 3))
+    shift = np.zeros((n_tris, 3))
+    shift[:, 0] = rng.uniform(-slide, slide, n_tris)
+    V1 = V0 + np.repeat(shift, 3, axis=0)
+    F = np.arange(3 * n_tris, dtype=np.int32).reshape(n_tris, 3)
+    return _scene("sliding_slivers", V0, V1, F, seed=seed)
+
+
 def scene_batch(seed=4, count=64, t_min=1e3, t_max=2e5):
     """`count` scenes with log-uniform triangle counts in [t_min, t_max].
 

@@ -96,6 +96,14 @@ def test_broad_tiny_random(ctx, seed):
                                               dyadic_bits=(3 if seed % 2 else None)))
 
 
+def test_broad_long_windows(ctx):
+    """Sweep windows of up to ~1,000 (vertex-face) and ~3,200 (edge-edge) candidates: several chunks per tile."""
+    s = scenes.sliding_slivers()
+    vf, ee = check_broad(ctx, s)
+    assert len(vf) > 0 and len(ee) > 0
+    check_narrow(ctx, s, vf, ee)
+
+
 def test_broad_extreme_coordinates(ctx):
     rng = np.random.default_rng(5)
     s = scenes.tiny_random_scene(9, n_tris=60, extent=1.0, motion=0.5)

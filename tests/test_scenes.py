@@ -36,3 +36,15 @@ def test_concat_scenes_offsets_and_global_ids():
         assert np.array_equal(F[fo[i]:fo[i + 1]] - vo[i], s.F)
         assert np.array_equal(E[eo[i]:eo[i + 1]] - vo[i], s.E)
         assert F[fo[i]:fo[i + 1]].min() >= vo[i] and F[fo[i]:fo[i + 1]].max() < vo[i + 1]
+
+
+def test_sliding_slivers_is_seeded_and_long_on_one_axis():
+    a, b = scenes.sliding_slivers(seed=3, n_tris=50), scenes.sliding_slivers(seed=3, n_tris=50)
+    assert np.array_equal(a.V0, b.V0) and np.array_equal(a.V1, b.V1)
+    assert a.nv == 150 and a.nf == 50 and a.ne == 150
+    d = a.V1 - a.V0
+    # each triangle slides rigidly along x only
+    assert np.all(d[:, 1:] == 0.0)
+    # (up to the rounding of V0 + shift)
+    assert np.allclose(d[0::3, 0], d[1::3, 0], rtol=0, atol=1e-14) and np.allclose(d[0::3, 0], d[2::3, 0], rtol=0,
+                                                                                     atol=1e-14)
