@@ -433,9 +433,9 @@ ccd_status narrow_impl(ccd_context *c, const double *V0, const double *V1, int64
     const uint32_t *order_n = nullptr;
     HIP_TRY(hipEventRecord(c->ev[0], s));
     if (learned) {
-        // prep, features, prediction and cost histogram in one pass; then the ordering
-        launch_narrow_prep_sched(V0, V1, nv, E, ne, F, nf, vf, ee, pc, delta, B, sched->params, sched->norm, S.cost,
-                                 S.bins, s);
+        // prep and features in one pass, the prediction and cost histogram in a second; then the ordering
+        launch_narrow_prep_feat(V0, V1, nv, E, ne, F, nf, vf, ee, pc, delta, B, S.feat, S.bins, s);
+        launch_cost_predict(sched->params, sched->norm, S.feat, n, S.cost, S.bins, s);
         HIP_TRY(hipEventRecord(c->ev[4], s));
         launch_cost_schedule(S.cost, n, sched->heavy_threshold, max_early, S.order, B.heavy, B.counters, S.bins,
                              true, s);

@@ -175,13 +175,12 @@ void launch_narrow_prep(const double *V0, const double *V1, int64_t nv, const in
 // Scheduling features of every pair (after prep): n x kNumFeatures floats.
 constexpr int kNumFeatures = 16;
 constexpr int kHidden = 64;
-// The learned schedule's fused first pass: prep, features and the cost
-// model's prediction of every pair (cost[p]), and the histogram of predicted
-// cost bins (hist, 256 uint32, zeroed here).
-void launch_narrow_prep_sched(const double *V0, const double *V1, int64_t nv, const int32_t *E, int64_t ne,
-                              const int32_t *F, int64_t nf, const int32_t *vf, const int32_t *ee, PairCounts pc,
-                              double delta, const NarrowBuffers &B, const float *params, const float *norm,
-                              float *cost, uint32_t *hist, hipStream_t s);
+// The learned schedule's first pass: prep and the scheduling features of
+// every pair (feat, n x kNumFeatures floats); also zeroes the cost histogram
+// (hist, 256 uint32).
+void launch_narrow_prep_feat(const double *V0, const double *V1, int64_t nv, const int32_t *E, int64_t ne,
+                             const int32_t *F, int64_t nf, const int32_t *vf, const int32_t *ee, PairCounts pc,
+                             double delta, const NarrowBuffers &B, float *feat, uint32_t *hist, hipStream_t s);
 void launch_narrow_features(const double *V0, const double *V1, PairCounts pc, double delta, const NarrowBuffers &B,
                             float *feat, hipStream_t s);
 
@@ -210,6 +209,10 @@ constexpr int kModelParams = kNumFeatures * kHidden + kHidden + kHidden * kHidde
 
 void launch_mlp_predict(const float *params, const float *norm, const float *feat, int64_t n, float *out,
                         hipStream_t s);
+// The cost model's prediction of every pair (cost[p]) and the histogram of
+// predicted cost bins (hist, 256 uint32, accumulated).
+void launch_cost_predict(const float *params, const float *norm, const float *feat, int64_t n, float *cost,
+                         uint32_t *hist, hipStream_t s);
 // grad (kModelParams floats) and loss (1 float, sum of squared errors) are
 // accumulated; the launcher clears them first.  The loss is the mean squared
 // error over the n pairs.

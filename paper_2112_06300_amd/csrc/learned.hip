@@ -137,15 +137,21 @@ __device__ __forceinline__ void forward_tile(MlpLds &S, int w, int lane, f32x4 z
 
 // Prediction of every row of feat: one 16-row tile per wave at a time, the
 // weights in registers (mlp_tile.h).
+constexpr int kCostBins = 256;  // bins of predicted cost (1/4 in log2 cost each)
+
+// (hist: also count each prediction into its cost bin, per block in LDS.)
 __global__ __launch_bounds__(256) void mlp_predict_kernel(const float *__restrict__ prm,
                                                           const float *__restrict__ norm,
-                                                          const float *__restrict__ feat, int64_t n, float *out)
+                                                          const float *__restrict__ feat, int64_t n, float *out,
+                                                          uint32_t *hist)
 {
     __shared__ MlpConsts C;
+    __shared__ uint32_t h[kCostBins];
     mlp_load_consts(C, prm, norm);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     __shared__ MlpWeights Wt;
     mlp_load_weights(Wt, prm);
+    h[threadIdx.x] = 0u;
     __syncthreads();
     const int r = lane & 15, g = (lane >> 4) * 4;
     const int64_t tiles = (n + 15) / 16;
@@ -157,7 +163,14 @@ __global__ __launch_bounds__(256) void mlp_predict_kernel(const float *__restric
             f[0] = v.x; f[1] = v.y; f[2] = v.z; f[3] = v.w;
         }
         const float y = mlp_forward(Wt, C, mlp_input(C, f, lane), lane);
-        if (lane < 16 && row < n) out[row] = y;
+        if (lane < 16 && row < n) {
+            out[row] = y;
+            if (hist) atomicAdd(&h[sched_cost_bin(y)], 1u);
+        }
+    }
+    if (hist) {
+        __syncthreads();
+        if (h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
     }
 }
 
@@ -308,7 +321,6 @@ __global__ void adam_kernel(float *prm, const float *__restrict__ grad, float *m
 // coprime with n_light.  A pool wave claims 64 consecutive positions, so each
 // claim holds about one pair of every cost stratum and the costliest pairs are
 // claimed first.
-constexpr int kCostBins = 256;
 
 __device__ __forceinline__ int cost_bin(float c) { return sched_cost_bin(c); }
 
@@ -476,7 +488,17 @@ void launch_mlp_predict(const float *params, const float *norm, const float *fea
     const int64_t tiles = (n + 15) / 16;
     int64_t blocks = (tiles + 3) / 4;
     if (blocks > 2048) blocks = 2048;
-    mlp_predict_kernel<<<(unsigned)blocks, 256, 0, s>>>(params, norm, feat, n, out);
+    mlp_predict_kernel<<<(unsigned)blocks, 256, 0, s>>>(params, norm, feat, n, out, nullptr);
+}
+
+void launch_cost_predict(const float *params, const float *norm, const float *feat, int64_t n, float *cost,
+                         uint32_t *hist, hipStream_t s)
+{
+    if (n == 0) return;
+    const int64_t tiles = (n + 15) / 16;
+    int64_t blocks = (tiles + 3) / 4;
+    if (blocks > 1024) blocks = 1024;
+    mlp_predict_kernel<<<(unsigned)blocks, 256, 0, s>>>(params, norm, feat, n, cost, hist);
 }
 
 void launch_mlp_grad(const float *params, const float *norm, const float *feat, const float *label, int64_t n,

@@ -21,7 +21,6 @@
 //          levels above 21, continue in a workgroup of their own with the
 //          frontier in HBM scratch.
 #include "ccd_internal.h"
-#include "mlp_tile.h"
 
 namespace ccd {
 
@@ -384,59 +383,30 @@ __global__ __launch_bounds__(256) void feature_kernel(const double *__restrict__
     for (int i = 0; i < kNumFeatures; i++) feat[p * kNumFeatures + i] = f[i];
 }
 
-// The learned schedule's pass after prep: each pair's features (kept in
-// LDS), the cost model's prediction on the matrix cores (a wave runs its 64
-// pairs as 4 tiles of 16), and the histogram of predicted-cost bins (1/4 in
-// log2 cost, costliest first) for the ordering.  Grid-stride over chunks of
-// 256 pairs.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void sched_kernel(const double *__restrict__ V0, const double *__restrict__ V1,
-                                                    const int4 *__restrict__ ids4, const double *__restrict__ peps,
-                                                    const uint32_t *__restrict__ pm, PairCounts pc, double delta,
-                                                    const float *__restrict__ prm, const float *__restrict__ norm,
-                                                    float *cost, uint32_t *hist)
+// The learned schedule's first pass: prep and the 16 scheduling features of
+// every pair from the coordinates gathered once (a pair with a bad index or
+// coordinate gets zeros), as 4 float4 stores.
+__global__ __launch_bounds__(256) void prep_feat_kernel(const double *__restrict__ V0, const double *__restrict__ V1,
+                                                       int64_t nv, const int32_t *__restrict__ vf,
+                                                       const int32_t *__restrict__ ee, PairCounts pc,
+                                                       const int32_t *__restrict__ E, int64_t ne,
+                                                       const int32_t *__restrict__ F, int64_t nf, double delta,
+                                                       int4 *ids4, double *peps, uint32_t *pm, uint32_t *flags,
+                                                       float *__restrict__ feat)
 {
-    __shared__ MlpConsts C;
-    __shared__ MlpWeights Wt;
-    __shared__ float xs[4][64][kNumFeatures + 1];
-    __shared__ uint32_t h[256];
-    mlp_load_consts(C, prm, norm);
-    mlp_load_weights(Wt, prm);
-    h[threadIdx.x] = 0u;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int r = lane & 15, g = (lane >> 4) * 4;
-    __syncthreads();
     int64_t n_vf, n;
     pc.get(n_vf, n);
-    for (int64_t c0 = (int64_t)blockIdx.x * 256; c0 < n; c0 += (int64_t)gridDim.x * 256) {
-        const int64_t p = c0 + threadIdx.x;
-        float f[kNumFeatures];
-        for (int i = 0; i < kNumFeatures; i++) f[i] = 0.f;
-        if (p < n) {
-            const int4 id = ids4[p];
-            if (id.x >= 0) {
-                double raw[24];
-                load_raw(id, V0, V1, raw);
-                const double eps[3] = {peps[3 * p], peps[3 * p + 1], peps[3 * p + 2]};
-                pair_features(raw, p < n_vf, eps, pm[p], delta, f);
-            }
-        }
-        for (int i = 0; i < kNumFeatures; i++) xs[w][lane][i] = f[i];
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-#pragma unroll 1
-        for (int t = 0; t < 4; t++) {
-            const float fx[4] = {xs[w][16 * t + r][g], xs[w][16 * t + r][g + 1], xs[w][16 * t + r][g + 2],
-                                 xs[w][16 * t + r][g + 3]};
-            const float y = mlp_forward(Wt, C, mlp_input(C, fx, lane), lane);
-            const int64_t q = c0 + 64 * w + 16 * t + r;
-            const bool mine = lane < 16 && q < n;
-            if (mine) cost[q] = y;
-            if (mine) atomicAdd(&h[sched_cost_bin(y)], 1u);
-        }
-        __builtin_amdgcn_wave_barrier();
-    }
-    __syncthreads();
-    if (h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= n) return;
+    double raw[24], eps[3];
+    uint32_t mp = 0u;
+    float f[kNumFeatures];
+    for (int i = 0; i < kNumFeatures; i++) f[i] = 0.f;
+    if (prep_pair(p, n_vf, V0, V1, nv, vf, ee, E, ne, F, nf, delta, ids4, peps, pm, flags, raw, eps, mp))
+        pair_features(raw, p < n_vf, eps, mp, delta, f);
+    float4 *o = reinterpret_cast<float4 *>(feat + p * kNumFeatures);
+#pragma unroll
+    for (int q = 0; q < kNumFeatures / 4; q++) o[q] = make_float4(f[4 * q], f[4 * q + 1], f[4 * q + 2], f[4 * q + 3]);
 }
 
 // Exclusive prefix sum over the wave and its total: shifts within each row of
@@ -1154,20 +1124,16 @@ void launch_narrow_prep(const double *V0, const double *V1, int64_t nv, const in
                                                            B.eps, B.m, B.flags);
 }
 
-void launch_narrow_prep_sched(const double *V0, const double *V1, int64_t nv, const int32_t *E, int64_t ne,
-                              const int32_t *F, int64_t nf, const int32_t *vf, const int32_t *ee, PairCounts pc,
-                              double delta, const NarrowBuffers &B, const float *params, const float *norm,
-                              float *cost, uint32_t *hist, hipStream_t s)
+void launch_narrow_prep_feat(const double *V0, const double *V1, int64_t nv, const int32_t *E, int64_t ne,
+                             const int32_t *F, int64_t nf, const int32_t *vf, const int32_t *ee, PairCounts pc,
+                             double delta, const NarrowBuffers &B, float *feat, uint32_t *hist, hipStream_t s)
 {
     // counters, flags and the cost histogram start at zero
     counters_zero_kernel<<<1, 256, 0, s>>>(B.counters, 16, B.flags, hist);
     const int64_t n = pc.capacity();
     if (n == 0) return;
-    prep_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(V0, V1, nv, vf, ee, pc, E, ne, F, nf, delta, B.ids4, B.eps,
-                                                           B.m, B.flags);
-    int64_t blocks = (n + 255) / 256;
-    if (blocks > 2048) blocks = 2048;
-    sched_kernel<<<(unsigned)blocks, 256, 0, s>>>(V0, V1, B.ids4, B.eps, B.m, pc, delta, params, norm, cost, hist);
+    prep_feat_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(V0, V1, nv, vf, ee, pc, E, ne, F, nf, delta, B.ids4,
+                                                                B.eps, B.m, B.flags, feat);
 }
 
 void launch_narrow_features(const double *V0, const double *V1, PairCounts pc, double delta, const NarrowBuffers &B,
