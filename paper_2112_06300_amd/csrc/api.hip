@@ -164,6 +164,7 @@ void narrow_carve(Carver &cv, int64_t npairs, NarrowBuffers &B)
     B.overflow_list[0] = cv.take<int32_t>(m);
     B.overflow_list[1] = cv.take<int32_t>(m);
     B.flags = cv.take<uint32_t>(1);
+    B.toi_part = cv.take<double>(kToiParts);
     B.toi_min = nullptr;
     B.scratch = nullptr;
 }
@@ -357,7 +358,7 @@ ccd_status narrow_setup(ccd_context *c, const double *V0, const double *V1, int6
 struct SchedBuffers {
     float *feat, *cost;
     int32_t *order;
-    uint32_t *bits, *bins, *flag;
+    uint32_t *bits, *bins, *flag, *block_hist;
 };
 
 ccd_status sched_setup(ccd_context *c, int64_t n, SchedBuffers &S)
@@ -365,7 +366,7 @@ ccd_status sched_setup(ccd_context *c, int64_t n, SchedBuffers &S)
     const size_t m = (size_t)std::max<int64_t>(n, 1);
     const size_t words = (m + 31) / 32;
     ccd_status st = ensure(c->sched, aligned_total({m * kNumFeatures * 4, m * 4, m * 4, words * 4,
-                                                   (size_t)kSchedScratch * 4, 4}));
+                                                   (size_t)kSchedScratch * 4, 4, (size_t)256 * kCostMaxBlocks * 4}));
     if (st != CCD_OK) return st;
     Carver cv(c->sched.base);
     S.feat = cv.take<float>(m * kNumFeatures);
@@ -374,6 +375,7 @@ ccd_status sched_setup(ccd_context *c, int64_t n, SchedBuffers &S)
     S.bits = cv.take<uint32_t>(words);
     S.bins = cv.take<uint32_t>(kSchedScratch);
     S.flag = cv.take<uint32_t>(1);
+    S.block_hist = cv.take<uint32_t>((size_t)256 * kCostMaxBlocks);
     return CCD_OK;
 }
 
@@ -435,10 +437,10 @@ ccd_status narrow_impl(ccd_context *c, const double *V0, const double *V1, int64
     if (learned) {
         // prep and features in one pass, the prediction and cost histogram in a second; then the ordering
         launch_narrow_prep_feat(V0, V1, nv, E, ne, F, nf, vf, ee, pc, delta, B, S.feat, S.bins, s);
-        launch_cost_predict(sched->params, sched->norm, S.feat, n, S.cost, S.bins, s);
+        launch_cost_predict(sched->params, sched->norm, S.feat, n, S.cost, S.block_hist, s);
         HIP_TRY(hipEventRecord(c->ev[4], s));
         launch_cost_schedule(S.cost, n, sched->heavy_threshold, max_early, S.order, B.heavy, B.counters, S.bins,
-                             true, s);
+                             S.block_hist, s);
         order = S.order;
         order_n = S.bins + 2 * 256 + 1;
     } else {
@@ -464,7 +466,7 @@ ccd_status narrow_impl(ccd_context *c, const double *V0, const double *V1, int64
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(c->ev[3], s));
     if (learned && early_slots > 0) HIP_TRY(hipStreamWaitEvent(s, c->ev[6], 0));
-    launch_toi_min(toi, pc, toi_min, s);
+    launch_toi_min(toi, pc, B.toi_part, toi_min, s);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(c->ev[1], s));
     unsigned int *h = (unsigned int *)c->host;
@@ -510,7 +512,7 @@ ccd_status narrow_impl(ccd_context *c, const double *V0, const double *V1, int64
         launch_narrow_heavy(V0, V1, pc, delta, (long long)max_iter, hit, toi, nenq, B, nslots, cap, round,
                             c->tune.heavy_lds, c->tune.heavy_block, s);
         HIP_TRY(hipGetLastError());
-        launch_toi_min(toi, pc, toi_min, s);
+        launch_toi_min(toi, pc, B.toi_part, toi_min, s);
         HIP_TRY(hipGetLastError());
         HIP_TRY(hipEventRecord(c->ev[1], s));
         HIP_TRY(hipMemcpyAsync(h, B.counters, 16 * 4, hipMemcpyDeviceToHost, s));

@@ -161,8 +161,10 @@ struct NarrowBuffers {
     int32_t *overflow_list[2];     // heavy slots to re-run with larger buffers (alternating)
     unsigned long long *scratch;   // heavy frontier buffers
     uint32_t *flags;
+    double *toi_part;              // per-block minima of the time-of-impact reduction (kToiParts)
     double *toi_min;
 };
+constexpr int kToiParts = 256;
 
 // Resident 64-lane pool workgroups per CU.
 int pool_blocks_per_cu();
@@ -209,10 +211,13 @@ constexpr int kModelParams = kNumFeatures * kHidden + kHidden + kHidden * kHidde
 
 void launch_mlp_predict(const float *params, const float *norm, const float *feat, int64_t n, float *out,
                         hipStream_t s);
-// The cost model's prediction of every pair (cost[p]) and the histogram of
-// predicted cost bins (hist, 256 uint32, accumulated).
+// The cost model's prediction of every pair (cost[p]); each of its
+// cost_blocks(n) blocks also writes its counts of predicted-cost bins to
+// block_hist[bin * cost_blocks(n) + block] (256 x kCostMaxBlocks uint32).
+constexpr int64_t kCostMaxBlocks = 1024;
+int64_t cost_blocks(int64_t n);
 void launch_cost_predict(const float *params, const float *norm, const float *feat, int64_t n, float *cost,
-                         uint32_t *hist, hipStream_t s);
+                         uint32_t *block_hist, hipStream_t s);
 // grad (kModelParams floats) and loss (1 float, sum of squared errors) are
 // accumulated; the launcher clears them first.  The loss is the mean squared
 // error over the n pairs.
@@ -225,11 +230,11 @@ void launch_adam(float *params, const float *grad, float *m, float *v, int64_t s
 // entries heavy[0..H) starting from the root, and the wide stage's counters
 // [0], [1], [12] are set to H ([13] = 0); the other pairs fill order[0 ..
 // n - H), dealt by rank so that every 64 consecutive positions span the cost
-// range.  scratch: 3 x 256 + 4 uint32; scratch[2 * 256 + 1] = n - H (device).
-// hist_ready: scratch[0 .. 256) already holds the cost histogram (the fused
-// prep pass below computed it).
+// range.  block_hist: the prediction pass's per-block bin counts (turned into
+// per-block offsets here).  scratch: 3 x 256 + 4 uint32; scratch[2 * 256 + 1]
+// = n - H (device).
 void launch_cost_schedule(const float *cost, int64_t n, float threshold, int max_heavy, int32_t *order,
-                          HeavyEntry *heavy, unsigned int *counters, uint32_t *scratch, bool hist_ready,
+                          HeavyEntry *heavy, unsigned int *counters, uint32_t *scratch, uint32_t *block_hist,
                           hipStream_t s);
 constexpr int kSchedScratch = 3 * 256 + 4;
 // *flag = 0 iff order is a permutation of [0, n); bits holds ceil(n / 32) words.
@@ -245,7 +250,7 @@ void launch_narrow_heavy(const double *V0, const double *V1, PairCounts pc, doub
                          uint8_t *hit, double *toi, long long *n_enq, const NarrowBuffers &B, int nslots,
                          int64_t cap, int round, int use_lds, int block, hipStream_t s);
 
-void launch_toi_min(const double *toi, PairCounts pc, double *out, hipStream_t s);
+void launch_toi_min(const double *toi, PairCounts pc, double *part, double *out, hipStream_t s);
 // out[s] = earliest toi over the pairs of scene s (CSR vertex / edge offsets
 // on the device, S + 1 each); +inf for a scene without a hit.
 void launch_scene_min(const double *toi, PairCounts pc, const int32_t *vf, const int32_t *ee, const int64_t *v_off,

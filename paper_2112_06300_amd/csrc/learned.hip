@@ -139,7 +139,10 @@ __device__ __forceinline__ void forward_tile(MlpLds &S, int w, int lane, f32x4 z
 // weights in registers (mlp_tile.h).
 constexpr int kCostBins = 256;  // bins of predicted cost (1/4 in log2 cost each)
 
-// (hist: also count each prediction into its cost bin, per block in LDS.)
+// (hist: also count each prediction into its cost bin, per block in LDS, and
+// write the block's counts to hist[bin * gridDim.x + block].  Block b's rows
+// are the 64-row chunks b, b + G, b + 2G, ... (G = gridDim.x), which
+// cost_scatter_kernel walks again in the same grid.)
 __global__ __launch_bounds__(256) void mlp_predict_kernel(const float *__restrict__ prm,
                                                           const float *__restrict__ norm,
                                                           const float *__restrict__ feat, int64_t n, float *out,
@@ -170,7 +173,7 @@ __global__ __launch_bounds__(256) void mlp_predict_kernel(const float *__restric
     }
     if (hist) {
         __syncthreads();
-        if (h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
+        hist[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
     }
 }
 
@@ -337,21 +340,36 @@ __device__ __forceinline__ unsigned long long same_bin(int bin, bool valid)
     return m;
 }
 
-__global__ __launch_bounds__(256) void cost_hist_kernel(const float *__restrict__ cost, int64_t n, uint32_t *hist)
+__device__ __forceinline__ int wave_excl_scan_i(int v, int &total)
 {
-    __shared__ uint32_t h[kCostBins];
-    h[threadIdx.x] = 0u;
-    __syncthreads();
+    int x = v;
     const int lane = threadIdx.x & 63;
-    for (int64_t b0 = (int64_t)blockIdx.x * 256; b0 < n; b0 += (int64_t)gridDim.x * 256) {
-        const int64_t i = b0 + threadIdx.x;
-        const bool valid = i < n;
-        const int bin = valid ? cost_bin(cost[i]) : 0;
-        const unsigned long long m = same_bin(bin, valid);
-        if (valid && (__ffsll((long long)m) - 1) == lane) atomicAdd(&h[bin], (uint32_t)__popcll(m));
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o);
+        if (lane >= o) x += y;
     }
-    __syncthreads();
-    if (h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
+    total = __shfl(x, 63);
+    return x - v;
+}
+
+// Per bin (one wave each): exclusive prefix over blocks of the block counts,
+// in place, and the bin's total.
+__global__ __launch_bounds__(256) void cost_colscan_kernel(uint32_t *block_hist, int64_t G, uint32_t *tot)
+{
+    const int lane = threadIdx.x & 63;
+    const int bin = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (bin >= kCostBins) return;
+    uint32_t *row = block_hist + (int64_t)bin * G;
+    int carry = 0;
+    for (int64_t b0 = 0; b0 < G; b0 += 64) {
+        const int64_t k = b0 + lane;
+        const int x = k < G ? (int)row[k] : 0;
+        int t = 0;
+        const int ex = wave_excl_scan_i(x, t);
+        if (k < G) row[k] = (uint32_t)(carry + ex);
+        carry += t;
+    }
+    if (lane == 0) tot[bin] = (uint32_t)carry;
 }
 
 __device__ __forceinline__ uint32_t gcd_u32(uint32_t a, uint32_t b)
@@ -398,40 +416,35 @@ __global__ __launch_bounds__(256) void cost_scan_kernel(const uint32_t *hist, ui
     }
 }
 
+// Block b places the rows it predicted (64-row chunks b, b + G, ...; wave w
+// takes every 4th of them) at its own offsets within each bin: bin start +
+// the counts of the blocks before it.
 __global__ __launch_bounds__(256) void cost_scatter_kernel(const float *__restrict__ cost, int64_t n,
-                                                           uint32_t *cursor, const uint32_t *__restrict__ info,
-                                                           int32_t *order, HeavyEntry *heavy)
+                                                           const uint32_t *__restrict__ cursor,
+                                                           const uint32_t *__restrict__ block_hist,
+                                                           const uint32_t *__restrict__ info, int32_t *order,
+                                                           HeavyEntry *heavy)
 {
-    __shared__ uint32_t h[kCostBins], base[kCostBins];
-    const int lane = threadIdx.x & 63;
+    __shared__ uint32_t off[kCostBins];
+    const int64_t G = gridDim.x;
+    off[threadIdx.x] = cursor[threadIdx.x] + block_hist[(int64_t)threadIdx.x * G + blockIdx.x];
+    __syncthreads();
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const unsigned long long lt = (1ull << lane) - 1ull;
-    const int64_t chunk = ((n + gridDim.x - 1) / gridDim.x + 255) / 256 * 256;
-    const int64_t b0 = (int64_t)blockIdx.x * chunk, b1 = b0 + chunk < n ? b0 + chunk : n;
-    h[threadIdx.x] = 0u;
-    __syncthreads();
-    for (int64_t r0 = b0; r0 < b1; r0 += 256) {
-        const int64_t i = r0 + threadIdx.x;
-        const bool valid = i < b1;
-        const int bin = valid ? cost_bin(cost[i]) : 0;
-        const unsigned long long m = same_bin(bin, valid);
-        if (valid && (__ffsll((long long)m) - 1) == lane) atomicAdd(&h[bin], (uint32_t)__popcll(m));
-    }
-    __syncthreads();
-    base[threadIdx.x] = h[threadIdx.x] ? atomicAdd(&cursor[threadIdx.x], h[threadIdx.x]) : 0u;
-    h[threadIdx.x] = 0u;
-    __syncthreads();
     const uint32_t H = info[0], nl = info[1], S = info[2];
-    for (int64_t r0 = b0; r0 < b1; r0 += 256) {
-        const int64_t i = r0 + threadIdx.x;
-        const bool valid = i < b1;
+    for (int64_t k = w;; k += 4) {
+        const int64_t row0 = ((int64_t)blockIdx.x + G * k) * 64;
+        if (row0 >= n) break;
+        const int64_t i = row0 + lane;
+        const bool valid = i < n;
         const int bin = valid ? cost_bin(cost[i]) : 0;
         const unsigned long long m = same_bin(bin, valid);
         const int leader = __ffsll((long long)m) - 1;
         uint32_t first = 0u;
-        if (valid && leader == lane) first = atomicAdd(&h[bin], (uint32_t)__popcll(m));
+        if (valid && leader == lane) first = atomicAdd(&off[bin], (uint32_t)__popcll(m));
         first = __shfl(first, leader < 0 ? 0 : leader);
         if (valid) {
-            const uint32_t pos = base[bin] + first + (uint32_t)__popcll(m & lt);
+            const uint32_t pos = first + (uint32_t)__popcll(m & lt);
             if (pos < H) {
                 HeavyEntry e;
                 e.pair = (int32_t)i;
@@ -491,14 +504,19 @@ void launch_mlp_predict(const float *params, const float *norm, const float *fea
     mlp_predict_kernel<<<(unsigned)blocks, 256, 0, s>>>(params, norm, feat, n, out, nullptr);
 }
 
+// Blocks of the prediction pass and of the scatter that follows it (the same
+// grid: each block places the rows it predicted).
+int64_t cost_blocks(int64_t n)
+{
+    const int64_t chunks = (n + 63) / 64;
+    return chunks < kCostMaxBlocks ? (chunks > 0 ? chunks : 1) : kCostMaxBlocks;
+}
+
 void launch_cost_predict(const float *params, const float *norm, const float *feat, int64_t n, float *cost,
-                         uint32_t *hist, hipStream_t s)
+                         uint32_t *block_hist, hipStream_t s)
 {
     if (n == 0) return;
-    const int64_t tiles = (n + 15) / 16;
-    int64_t blocks = (tiles + 3) / 4;
-    if (blocks > 1024) blocks = 1024;
-    mlp_predict_kernel<<<(unsigned)blocks, 256, 0, s>>>(params, norm, feat, n, cost, hist);
+    mlp_predict_kernel<<<(unsigned)cost_blocks(n), 256, 0, s>>>(params, norm, feat, n, cost, block_hist);
 }
 
 void launch_mlp_grad(const float *params, const float *norm, const float *feat, const float *label, int64_t n,
@@ -522,20 +540,18 @@ void launch_adam(float *params, const float *grad, float *m, float *v, int64_t s
 }
 
 void launch_cost_schedule(const float *cost, int64_t n, float threshold, int max_heavy, int32_t *order,
-                          HeavyEntry *heavy, unsigned int *counters, uint32_t *scratch, bool hist_ready, hipStream_t s)
+                          HeavyEntry *heavy, unsigned int *counters, uint32_t *scratch, uint32_t *block_hist,
+                          hipStream_t s)
 {
-    // scratch: histogram, cursors, info
-    int64_t blocks = (n + 1023) / 1024;
-    if (blocks > 1024) blocks = 1024;
-    if (!hist_ready) {
-        zero_u32_kernel<<<1, kCostBins, 0, s>>>(scratch, kCostBins);
-        if (n > 0) cost_hist_kernel<<<(unsigned)blocks, 256, 0, s>>>(cost, n, scratch);
-    }
+    // scratch: bin totals, bin starts, info
+    const int64_t G = cost_blocks(n);
+    if (n > 0) cost_colscan_kernel<<<kCostBins / 4, 256, 0, s>>>(block_hist, G, scratch);
+    else zero_u32_kernel<<<1, kCostBins, 0, s>>>(scratch, kCostBins);
     cost_scan_kernel<<<1, kCostBins, 0, s>>>(scratch, scratch + kCostBins, scratch + 2 * kCostBins, n, threshold,
                                              max_heavy < 0 ? 0 : max_heavy, counters);
     if (n > 0)
-        cost_scatter_kernel<<<(unsigned)blocks, 256, 0, s>>>(cost, n, scratch + kCostBins, scratch + 2 * kCostBins,
-                                                            order, heavy);
+        cost_scatter_kernel<<<(unsigned)G, 256, 0, s>>>(cost, n, scratch + kCostBins, block_hist,
+                                                       scratch + 2 * kCostBins, order, heavy);
 }
 
 }  // namespace ccd

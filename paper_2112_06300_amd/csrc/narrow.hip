@@ -1025,9 +1025,9 @@ __global__ __launch_bounds__(BLOCK) void heavy_kernel(
     }
 }
 
-__global__ void toi_init_kernel(double *out) { *out = __builtin_huge_val(); }
-
-__global__ __launch_bounds__(256) void toi_min_kernel(const double *__restrict__ toi, PairCounts pc, double *out)
+// Earliest time of impact: per-block minima into part[kToiParts], then one
+// block reduces them into *out (no atomics, no initialization pass).
+__global__ __launch_bounds__(256) void toi_part_kernel(const double *__restrict__ toi, PairCounts pc, double *part)
 {
     __shared__ double red[4];
     int64_t n_vf, n;
@@ -1043,7 +1043,21 @@ __global__ __launch_bounds__(256) void toi_min_kernel(const double *__restrict__
     if (threadIdx.x == 0) {
         double r = red[0];
         for (int w = 1; w < 4; w++) r = red[w] < r ? red[w] : r;
-        atomicMin((unsigned long long *)out, (unsigned long long)__double_as_longlong(r));
+        part[blockIdx.x] = r;
+    }
+}
+
+__global__ __launch_bounds__(256) void toi_final_kernel(const double *__restrict__ part, int nparts, double *out)
+{
+    __shared__ double red[4];
+    double m = (int)threadIdx.x < nparts ? part[threadIdx.x] : __builtin_huge_val();
+    m = wave_min(m);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double r = red[0];
+        for (int w = 1; w < 4; w++) r = red[w] < r ? red[w] : r;
+        *out = r;
     }
 }
 
@@ -1239,14 +1253,13 @@ void launch_narrow_heavy_early(const double *V0, const double *V1, PairCounts pc
                  &B.counters[13], B.overflow_list[0], &B.counters[2], scratch, cap, use_lds, nullptr, s);
 }
 
-void launch_toi_min(const double *toi, PairCounts pc, double *out, hipStream_t s)
+void launch_toi_min(const double *toi, PairCounts pc, double *part, double *out, hipStream_t s)
 {
-    toi_init_kernel<<<1, 1, 0, s>>>(out);
     const int64_t n = pc.capacity();
-    if (n == 0) return;
     int64_t blocks = (n + 255) / 256;
-    if (blocks > 1024) blocks = 1024;
-    toi_min_kernel<<<(unsigned)blocks, 256, 0, s>>>(toi, pc, out);
+    if (blocks > kToiParts) blocks = kToiParts;
+    if (blocks > 0) toi_part_kernel<<<(unsigned)blocks, 256, 0, s>>>(toi, pc, part);
+    toi_final_kernel<<<1, 256, 0, s>>>(part, (int)blocks, out);
 }
 
 void launch_scene_min(const double *toi, PairCounts pc, const int32_t *vf, const int32_t *ee, const int64_t *v_off,
