@@ -699,9 +699,52 @@ __global__ __launch_bounds__(kPoolSlots) void pool_kernel(
             if (n_enq_out) n_enq_out[pb] = 0;
             pb = -1;
         }
-        const bool new_root = !active && pb >= 0;
-        const int roff = __popcll(__ballot(new_root) & lt_mask);
-        const bool root_fits = new_root && total + roff < kQCap;
+        // New roots: a free slot takes its own lane's ready pair; a free slot
+        // with none takes one from a lane whose slot is busy (after the pair
+        // list runs out, such pairs would otherwise wait for a deep search to
+        // end).  Roots are queued after the children: own first, then moved.
+        const bool own = !active && pb >= 0;
+        const bool donor = active && pb >= 0 && okb;
+        const bool taker = !active && pb < 0;
+        const unsigned long long om = __ballot(own), dm = __ballot(donor), tkm = __ballot(taker);
+        const int nown = __popcll(om);
+        int nmig = __popcll(dm) < __popcll(tkm) ? __popcll(dm) : __popcll(tkm);
+        if (nmig > kQCap - total - nown) nmig = kQCap - total - nown > 0 ? kQCap - total - nown : 0;
+        const int roff = __popcll(om & lt_mask);
+        const bool root_fits = own && total + roff < kQCap;
+        if (nmig > 0) {
+            // the rank-r taker receives the rank-r donor's pair (S.tmin: rank -> slot,
+            // S.cnt: the pair index; both are reset below)
+            const int rt = __popcll(tkm & lt_mask), rd = __popcll(dm & lt_mask);
+            const bool takes = taker && rt < nmig, gives = donor && rd < nmig;
+            if (takes) S.tmin[rt] = (unsigned long long)lane;
+            __syncthreads();
+            if (gives) {
+                const int tgt = (int)S.tmin[rd];
+#pragma unroll
+                for (int kk = 0; kk < 12; kk++) {
+                    S.x0[kk][tgt] = raw[kk];
+                    S.d[kk][tgt] = raw[12 + kk] - raw[kk];
+                }
+                S.eps[0][tgt] = epsb[0]; S.eps[1][tgt] = epsb[1]; S.eps[2][tgt] = epsb[2];
+                S.mm[tgt] = mb;
+                S.cnt[tgt] = (int)pb;
+                S.node[nxt][total + nown + rd] = 0ull;
+                S.slot[nxt][total + nown + rd] = (uint8_t)tgt;
+                pb = -1;
+            }
+            __syncthreads();
+            if (takes) {
+                p = S.cnt[lane];
+                vf = p < n_vf;
+                unpack_m(S.mm[lane], m);
+                l[0] = l[1] = l[2] = 0;
+                tstar = __builtin_huge_val();
+                nenq = 0;
+                S.lv[lane] = (uint32_t)vf << 24;
+                active = true;
+            }
+        }
         if (root_fits) {
             p = pb;
             pb = -1;
@@ -727,7 +770,7 @@ __global__ __launch_bounds__(kPoolSlots) void pool_kernel(
         S.nsurv[lane] = 0;
         S.cnt[lane] = 0;
         S.tmin[lane] = kInfBits;
-        const int T = total + __popcll(__ballot(root_fits));
+        const int T = total + __popcll(__ballot(root_fits)) + nmig;
         __syncthreads();
         // ---- F (all lanes over last round's entries): kept children, or hand-over survivors
         for (int b0 = 0; b0 < nq; b0 += kPoolSlots) {
