@@ -7,6 +7,22 @@
 
 namespace ccd {
 
+// Exclusive prefix sum over the wave and its total: shifts within each row of
+// 16 lanes (DPP row_shr 1, 2, 4, 8), then the row totals carried forward by
+// the row broadcasts of lanes 15 and 31.  All lanes must be active.
+__device__ __forceinline__ int wave_excl_scan(int v, int &total)
+{
+    int x = v;
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);  // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);  // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);  // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);  // row_shr:8
+    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);  // row_bcast:15 into rows 1, 3
+    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);  // row_bcast:31 into rows 2, 3
+    total = __builtin_amdgcn_readlane(x, 63);
+    return x - v;
+}
+
 // ---------------------------------------------------------------------------
 // Conservative float32 rounding of trajectory box bounds (Sec. 5.1): lo is the
 // largest float <= x, hi the smallest float >= x.  Round to nearest, then step

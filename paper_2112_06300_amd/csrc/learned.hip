@@ -340,36 +340,26 @@ __device__ __forceinline__ unsigned long long same_bin(int bin, bool valid)
     return m;
 }
 
-__device__ __forceinline__ int wave_excl_scan_i(int v, int &total)
+// Per bin (one block each, one thread per prediction block): exclusive prefix
+// over blocks of the block counts, in place, and the bin's total.
+__global__ __launch_bounds__(kCostMaxBlocks) void cost_colscan_kernel(uint32_t *block_hist, int64_t G, uint32_t *tot)
 {
-    int x = v;
-    const int lane = threadIdx.x & 63;
-    for (int o = 1; o < 64; o <<= 1) {
-        const int y = __shfl_up(x, o);
-        if (lane >= o) x += y;
+    __shared__ int wsum[kCostMaxBlocks / 64];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    uint32_t *row = block_hist + (int64_t)blockIdx.x * G;
+    const int x = t < G ? (int)row[t] : 0;
+    int wt = 0;
+    const int ex = wave_excl_scan(x, wt);
+    if (lane == 0) wsum[w] = wt;
+    __syncthreads();
+    int before = 0, all = 0;
+    for (int i = 0; i < kCostMaxBlocks / 64; i++) {
+        const int v = wsum[i];
+        before += i < w ? v : 0;
+        all += v;
     }
-    total = __shfl(x, 63);
-    return x - v;
-}
-
-// Per bin (one wave each): exclusive prefix over blocks of the block counts,
-// in place, and the bin's total.
-__global__ __launch_bounds__(256) void cost_colscan_kernel(uint32_t *block_hist, int64_t G, uint32_t *tot)
-{
-    const int lane = threadIdx.x & 63;
-    const int bin = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (bin >= kCostBins) return;
-    uint32_t *row = block_hist + (int64_t)bin * G;
-    int carry = 0;
-    for (int64_t b0 = 0; b0 < G; b0 += 64) {
-        const int64_t k = b0 + lane;
-        const int x = k < G ? (int)row[k] : 0;
-        int t = 0;
-        const int ex = wave_excl_scan_i(x, t);
-        if (k < G) row[k] = (uint32_t)(carry + ex);
-        carry += t;
-    }
-    if (lane == 0) tot[bin] = (uint32_t)carry;
+    if (t < G) row[t] = (uint32_t)(before + ex);
+    if (t == 0) tot[blockIdx.x] = (uint32_t)all;
 }
 
 __device__ __forceinline__ uint32_t gcd_u32(uint32_t a, uint32_t b)
@@ -545,7 +535,7 @@ void launch_cost_schedule(const float *cost, int64_t n, float threshold, int max
 {
     // scratch: bin totals, bin starts, info
     const int64_t G = cost_blocks(n);
-    if (n > 0) cost_colscan_kernel<<<kCostBins / 4, 256, 0, s>>>(block_hist, G, scratch);
+    if (n > 0) cost_colscan_kernel<<<kCostBins, kCostMaxBlocks, 0, s>>>(block_hist, G, scratch);
     else zero_u32_kernel<<<1, kCostBins, 0, s>>>(scratch, kCostBins);
     cost_scan_kernel<<<1, kCostBins, 0, s>>>(scratch, scratch + kCostBins, scratch + 2 * kCostBins, n, threshold,
                                              max_heavy < 0 ? 0 : max_heavy, counters);

@@ -271,7 +271,22 @@ __device__ __forceinline__ double eval_point(const double raw[24], bool vf, int 
 }
 
 // log2(1 + |x| / delta) in float32 (a feature, not a result)
-__device__ __forceinline__ float log_ratio(double x, double delta) { return log2f((float)(1.0 + fabs(x) / delta)); }
+// log2(1 + |x| / delta) in float32 (a feature, not a result), with 1 / delta
+// precomputed: the product differs from the quotient by at most an ulp.
+__device__ __forceinline__ float log_ratio(double x, double inv_delta)
+{
+    return log2f((float)(1.0 + fabs(x) * inv_delta));
+}
+
+// |v| for a feature: float32 square root of the float64 sum of squares when it
+// is a normal float (relative error ~1e-7, far below the features' use),
+// float64 otherwise.
+__device__ __forceinline__ double feature_norm(double sq)
+{
+    const float sf = (float)sq;
+    if (sf >= 1.17549435e-38f && sf <= 3.40282347e38f) return (double)sqrtf(sf);
+    return sqrt(sq);
+}
 
 // Scheduling features of one pair (16 floats).  They describe how hard the
 // pair's search will be -- derivative bounds, the root-level inclusion box
@@ -334,12 +349,13 @@ __device__ __forceinline__ void pair_features(const double raw[24], bool vf, con
         wmax = fmax(wmax, bmax - bmin);
         straddle += (bmin <= e && bmax >= -e) ? 1 : 0;
     }
-    f[4] = log_ratio(Lt, delta);
-    f[5] = log_ratio(Lu, delta);
-    f[6] = log_ratio(Lv, delta);
-    f[7] = (gap > 0.0 ? 1.f : -1.f) * log_ratio(gap, delta);
-    f[8] = log_ratio(wmin, delta);
-    f[9] = log_ratio(wmax, delta);
+    const double inv_delta = 1.0 / delta;
+    f[4] = log_ratio(Lt, inv_delta);
+    f[5] = log_ratio(Lu, inv_delta);
+    f[6] = log_ratio(Lv, inv_delta);
+    f[7] = (gap > 0.0 ? 1.f : -1.f) * log_ratio(gap, inv_delta);
+    f[8] = log_ratio(wmin, inv_delta);
+    f[9] = log_ratio(wmax, inv_delta);
     f[10] = (float)straddle;
     const double uc = vf ? 1.0 / 3.0 : 0.5, vc = uc;
     double F0[3], F1[3], Fm[3];
@@ -348,12 +364,13 @@ __device__ __forceinline__ void pair_features(const double raw[24], bool vf, con
         F1[a] = eval_point(raw, vf, a, 1.0, uc, vc);
         Fm[a] = eval_point(raw, vf, a, 0.5, uc, vc);
     }
-    const double n0 = sqrt(F0[0] * F0[0] + F0[1] * F0[1] + F0[2] * F0[2]);
-    const double n1 = sqrt(F1[0] * F1[0] + F1[1] * F1[1] + F1[2] * F1[2]);
-    const double nm = sqrt(Fm[0] * Fm[0] + Fm[1] * Fm[1] + Fm[2] * Fm[2]);
-    f[11] = log_ratio(n0, delta);
-    f[12] = log_ratio(n1, delta);
-    f[13] = log_ratio(nm, delta);
+    const double s0 = F0[0] * F0[0] + F0[1] * F0[1] + F0[2] * F0[2];
+    const double s1 = F1[0] * F1[0] + F1[1] * F1[1] + F1[2] * F1[2];
+    const double sm = Fm[0] * Fm[0] + Fm[1] * Fm[1] + Fm[2] * Fm[2];
+    const double n0 = feature_norm(s0), n1 = feature_norm(s1);
+    f[11] = log_ratio(n0, inv_delta);
+    f[12] = log_ratio(n1, inv_delta);
+    f[13] = log_ratio(feature_norm(sm), inv_delta);
     int flips = 0;
     for (int a = 0; a < 3; a++) flips += ((F0[a] > 0.0) != (F1[a] > 0.0)) ? 1 : 0;
     f[14] = (float)flips;
@@ -407,22 +424,6 @@ __global__ __launch_bounds__(256) void prep_feat_kernel(const double *__restrict
     float4 *o = reinterpret_cast<float4 *>(feat + p * kNumFeatures);
 #pragma unroll
     for (int q = 0; q < kNumFeatures / 4; q++) o[q] = make_float4(f[4 * q], f[4 * q + 1], f[4 * q + 2], f[4 * q + 3]);
-}
-
-// Exclusive prefix sum over the wave and its total: shifts within each row of
-// 16 lanes (DPP row_shr 1, 2, 4, 8), then the row totals carried forward by
-// the row broadcasts of lanes 15 and 31.  All lanes must be active.
-__device__ __forceinline__ int wave_excl_scan(int v, int &total)
-{
-    int x = v;
-    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);  // row_shr:1
-    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);  // row_shr:2
-    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);  // row_shr:4
-    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);  // row_shr:8
-    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);  // row_bcast:15 into rows 1, 3
-    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);  // row_bcast:31 into rows 2, 3
-    total = __builtin_amdgcn_readlane(x, 63);
-    return x - v;
 }
 
 struct PoolLds {
