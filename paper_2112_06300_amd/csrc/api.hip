@@ -359,6 +359,7 @@ struct SchedBuffers {
     float *feat, *cost;
     int32_t *order;
     uint32_t *bits, *bins, *flag, *block_hist;
+    void *packed;
 };
 
 ccd_status sched_setup(ccd_context *c, int64_t n, SchedBuffers &S)
@@ -366,7 +367,8 @@ ccd_status sched_setup(ccd_context *c, int64_t n, SchedBuffers &S)
     const size_t m = (size_t)std::max<int64_t>(n, 1);
     const size_t words = (m + 31) / 32;
     ccd_status st = ensure(c->sched, aligned_total({m * kNumFeatures * 4, m * 4, m * 4, words * 4,
-                                                   (size_t)kSchedScratch * 4, 4, (size_t)256 * kCostMaxBlocks * 4}));
+                                                   (size_t)kSchedScratch * 4, 4, (size_t)256 * kCostMaxBlocks * 4,
+                                                   (size_t)kMlpPackedBytes}));
     if (st != CCD_OK) return st;
     Carver cv(c->sched.base);
     S.feat = cv.take<float>(m * kNumFeatures);
@@ -376,6 +378,7 @@ ccd_status sched_setup(ccd_context *c, int64_t n, SchedBuffers &S)
     S.bins = cv.take<uint32_t>(kSchedScratch);
     S.flag = cv.take<uint32_t>(1);
     S.block_hist = cv.take<uint32_t>((size_t)256 * kCostMaxBlocks);
+    S.packed = cv.take<char>((size_t)kMlpPackedBytes);
     return CCD_OK;
 }
 
@@ -437,7 +440,7 @@ ccd_status narrow_impl(ccd_context *c, const double *V0, const double *V1, int64
     if (learned) {
         // prep and features in one pass, the prediction and cost histogram in a second; then the ordering
         launch_narrow_prep_feat(V0, V1, nv, E, ne, F, nf, vf, ee, pc, delta, B, S.feat, S.bins, s);
-        launch_cost_predict(sched->params, sched->norm, S.feat, n, S.cost, S.block_hist, s);
+        launch_cost_predict(sched->params, sched->norm, S.feat, n, S.cost, S.block_hist, S.packed, s);
         HIP_TRY(hipEventRecord(c->ev[4], s));
         launch_cost_schedule(S.cost, n, sched->heavy_threshold, max_early, S.order, B.heavy, B.counters, S.bins,
                              S.block_hist, s);

@@ -232,8 +232,10 @@ void launch_mlp_predict(const float *params, const float *norm, const float *fea
 // block_hist[bin * cost_blocks(n) + block] (256 x kCostMaxBlocks uint32).
 constexpr int64_t kCostMaxBlocks = 1024;
 int64_t cost_blocks(int64_t n);
+// packed: 10 KB (the network's bf16 weight fragments, written here once).
+constexpr int kMlpPackedBytes = 20 * 64 * 8;
 void launch_cost_predict(const float *params, const float *norm, const float *feat, int64_t n, float *cost,
-                         uint32_t *block_hist, hipStream_t s);
+                         uint32_t *block_hist, void *packed, hipStream_t s);
 // grad (kModelParams floats) and loss (1 float, sum of squared errors) are
 // accumulated; the launcher clears them first.  The loss is the mean squared
 // error over the n pairs.

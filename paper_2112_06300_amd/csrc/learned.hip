@@ -146,25 +146,28 @@ constexpr int kCostBins = 256;  // bins of predicted cost (1/4 in log2 cost each
 __global__ __launch_bounds__(256) void mlp_predict_kernel(const float *__restrict__ prm,
                                                           const float *__restrict__ norm,
                                                           const float *__restrict__ feat, int64_t n, float *out,
-                                                          uint32_t *hist)
+                                                          uint32_t *hist, const mlp_bf16x4 *__restrict__ packed)
 {
     __shared__ MlpConsts C;
     __shared__ uint32_t h[kCostBins];
     mlp_load_consts(C, prm, norm);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     __shared__ MlpWeights Wt;
-    mlp_load_weights(Wt, prm);
+    mlp_load_weights(Wt, prm, packed);
     h[threadIdx.x] = 0u;
     __syncthreads();
     const int r = lane & 15, g = (lane >> 4) * 4;
-    const int64_t tiles = (n + 15) / 16;
-    for (int64_t t = (int64_t)blockIdx.x * 4 + w; t < tiles; t += (int64_t)gridDim.x * 4) {
-        const int64_t row = 16 * t + r;
-        float f[4] = {0.f, 0.f, 0.f, 0.f};
-        if (row < n) {
-            const float4 v = *reinterpret_cast<const float4 *>(feat + row * F + g);
-            f[0] = v.x; f[1] = v.y; f[2] = v.z; f[3] = v.w;
-        }
+    const int64_t tiles = (n + 15) / 16, stride = (int64_t)gridDim.x * 4;
+    // the next tile's features are loaded while the current tile is evaluated
+    int64_t t = (int64_t)blockIdx.x * 4 + w;
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (t < tiles && 16 * t + r < n) v = *reinterpret_cast<const float4 *>(feat + (16 * t + r) * F + g);
+    for (; t < tiles; t += stride) {
+        const int64_t row = 16 * t + r, rown = 16 * (t + stride) + r;
+        float4 vn = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (t + stride < tiles && rown < n) vn = *reinterpret_cast<const float4 *>(feat + rown * F + g);
+        const float f[4] = {v.x, v.y, v.z, v.w};
+        v = vn;
         const float y = mlp_forward(Wt, C, mlp_input(C, f, lane), lane);
         if (lane < 16 && row < n) {
             out[row] = y;
@@ -491,7 +494,7 @@ void launch_mlp_predict(const float *params, const float *norm, const float *fea
     const int64_t tiles = (n + 15) / 16;
     int64_t blocks = (tiles + 3) / 4;
     if (blocks > 2048) blocks = 2048;
-    mlp_predict_kernel<<<(unsigned)blocks, 256, 0, s>>>(params, norm, feat, n, out, nullptr);
+    mlp_predict_kernel<<<(unsigned)blocks, 256, 0, s>>>(params, norm, feat, n, out, nullptr, nullptr);
 }
 
 // Blocks of the prediction pass and of the scatter that follows it (the same
@@ -502,11 +505,19 @@ int64_t cost_blocks(int64_t n)
     return chunks < kCostMaxBlocks ? (chunks > 0 ? chunks : 1) : kCostMaxBlocks;
 }
 
+__global__ __launch_bounds__(256) void mlp_pack_kernel(const float *__restrict__ prm, mlp_bf16x4 *packed)
+{
+    const int idx = blockIdx.x * 256 + threadIdx.x;
+    if (idx < 20 * 64) packed[idx] = mlp_fragment(prm, idx);
+}
+
 void launch_cost_predict(const float *params, const float *norm, const float *feat, int64_t n, float *cost,
-                         uint32_t *block_hist, hipStream_t s)
+                         uint32_t *block_hist, void *packed, hipStream_t s)
 {
     if (n == 0) return;
-    mlp_predict_kernel<<<(unsigned)cost_blocks(n), 256, 0, s>>>(params, norm, feat, n, cost, block_hist);
+    mlp_bf16x4 *pk = (mlp_bf16x4 *)packed;
+    mlp_pack_kernel<<<5, 256, 0, s>>>(params, pk);
+    mlp_predict_kernel<<<(unsigned)cost_blocks(n), 256, 0, s>>>(params, norm, feat, n, cost, block_hist, pk);
 }
 
 void launch_mlp_grad(const float *params, const float *norm, const float *feat, const float *label, int64_t n,

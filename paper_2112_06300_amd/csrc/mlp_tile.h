@@ -25,12 +25,15 @@ constexpr int kMlpOffB2 = kMlpOffW2 + kHidden * kHidden;
 constexpr int kMlpOffW3 = kMlpOffB2 + kHidden;
 constexpr int kMlpOffB3 = kMlpOffW3 + kHidden;
 
-// float -> bf16, round to nearest even (finite inputs)
-__device__ __forceinline__ short mlp_bf16(float x)
+// float -> bf16, round to nearest even (v_cvt_pk_bf16_f32)
+__device__ __forceinline__ short mlp_bf16(float x) { return __builtin_bit_cast(short, (__bf16)x); }
+
+// max(x, 0) for finite x: the sign bit spread into a mask (fmaxf would also
+// quiet NaNs, one more instruction per value)
+__device__ __forceinline__ float mlp_relu(float x)
 {
-    uint32_t u = __float_as_uint(x);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (short)(u >> 16);
+    const int i = __float_as_int(x);
+    return __int_as_float(i & ~(i >> 31));
 }
 
 // Weight fragments, per lane: frag[ob] = block ob of W1^T, frag[4 + 4 ob + kb]
@@ -46,23 +49,31 @@ struct MlpConsts {
     float b3;
 };
 
-// Block-wide: fills W (the caller synchronizes before use).
-__device__ __forceinline__ void mlp_load_weights(MlpWeights &W, const float *__restrict__ prm)
+// Fragment idx = 64 fr + lane of the weights (bf16 x 4).
+__device__ __forceinline__ mlp_bf16x4 mlp_fragment(const float *__restrict__ prm, int idx)
 {
-    for (int idx = threadIdx.x; idx < 20 * 64; idx += blockDim.x) {
-        const int fr = idx >> 6, lane = idx & 63;
-        const int r = lane & 15, g = (lane >> 4) * 4;
-        mlp_bf16x4 v;
-        if (fr < 4) {
+    const int fr = idx >> 6, lane = idx & 63;
+    const int r = lane & 15, g = (lane >> 4) * 4;
+    mlp_bf16x4 v;
+    if (fr < 4) {
 #pragma unroll
-            for (int j = 0; j < 4; j++) v[j] = mlp_bf16(prm[kMlpOffW1 + (g + j) * kHidden + 16 * fr + r]);
-        } else {
-            const int ob = (fr - 4) >> 2, kb = (fr - 4) & 3;
+        for (int j = 0; j < 4; j++) v[j] = mlp_bf16(prm[kMlpOffW1 + (g + j) * kHidden + 16 * fr + r]);
+    } else {
+        const int ob = (fr - 4) >> 2, kb = (fr - 4) & 3;
 #pragma unroll
-            for (int j = 0; j < 4; j++) v[j] = mlp_bf16(prm[kMlpOffW2 + (16 * kb + g + j) * kHidden + 16 * ob + r]);
-        }
-        W.frag[fr][lane] = v;
+        for (int j = 0; j < 4; j++) v[j] = mlp_bf16(prm[kMlpOffW2 + (16 * kb + g + j) * kHidden + 16 * ob + r]);
     }
+    return v;
+}
+
+// Block-wide: fills W, from the float32 parameters, or (packed != nullptr)
+// by copying fragments packed once for the call (the caller synchronizes
+// before use).
+__device__ __forceinline__ void mlp_load_weights(MlpWeights &W, const float *__restrict__ prm,
+                                                 const mlp_bf16x4 *__restrict__ packed = nullptr)
+{
+    for (int idx = threadIdx.x; idx < 20 * 64; idx += blockDim.x)
+        W.frag[idx >> 6][idx & 63] = packed ? packed[idx] : mlp_fragment(prm, idx);
 }
 
 // Block-wide: fills C (the caller synchronizes before use).
@@ -95,9 +106,6 @@ __device__ __forceinline__ mlp_bf16x4 mlp_input(const MlpConsts &C, const float 
 // Prediction for the tile's row r = lane % 16 (every lane of a row holds it).
 __device__ __forceinline__ float mlp_forward(const MlpWeights &W, const MlpConsts &C, mlp_bf16x4 x, int lane)
 {
-    // read the fragments from LDS here rather than keeping all 20 in registers
-    // across the caller's loop
-    asm volatile("" ::: "memory");
     const int g = (lane >> 4) * 4;
     mlp_bf16x4 h1[4];
 #pragma unroll
@@ -107,7 +115,7 @@ __device__ __forceinline__ float mlp_forward(const MlpWeights &W, const MlpConst
         for (int j = 0; j < 4; j++) acc[j] = C.b1[16 * ob + g + j];
         acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(W.frag[ob][lane], x, acc, 0, 0, 0);
 #pragma unroll
-        for (int j = 0; j < 4; j++) h1[ob][j] = mlp_bf16(fmaxf(acc[j], 0.f));
+        for (int j = 0; j < 4; j++) h1[ob][j] = mlp_bf16(mlp_relu(acc[j]));
     }
     float s = 0.f;
 #pragma unroll
@@ -119,7 +127,7 @@ __device__ __forceinline__ float mlp_forward(const MlpWeights &W, const MlpConst
         for (int kb = 0; kb < 4; kb++)
             acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(W.frag[4 + 4 * ob + kb][lane], h1[kb], acc, 0, 0, 0);
 #pragma unroll
-        for (int j = 0; j < 4; j++) s += fmaxf(acc[j], 0.f) * C.w3[16 * ob + g + j];
+        for (int j = 0; j < 4; j++) s += mlp_relu(acc[j]) * C.w3[16 * ob + g + j];
     }
     s += __shfl_xor(s, 16);
     s += __shfl_xor(s, 32);
