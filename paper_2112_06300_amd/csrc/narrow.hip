@@ -31,6 +31,13 @@ namespace {
 // occupancy cost at the kernel's register use).
 constexpr int kPoolSlots = 64;   // pairs in flight per wave (one owner lane each)
 constexpr int kQCap = 512;       // intervals per round per wave
+// New pairs start only while the round's queue holds fewer than this many
+// intervals: the headroom keeps the next level's children in the queue.  A
+// pair whose children overflow it goes to the wide stage, which costs far more
+// per level: on the 1M-triangle perturbed torus a full queue (512) handed
+// 543k pairs over and the narrow phase took 30 ms; 320 hands over 17k, 12 ms.
+// The cloth workload is the same within 1 % from 320 to 512.
+constexpr int kRootLimit = 320;
 constexpr int kClaim = 64;       // pairs a wave claims from the global list at once
 constexpr int DISCARD = 0, ACCEPT = 1, SPLIT = 2;
 
@@ -710,9 +717,9 @@ __global__ __launch_bounds__(kPoolSlots) void pool_kernel(
         const unsigned long long om = __ballot(own), dm = __ballot(donor), tkm = __ballot(taker);
         const int nown = __popcll(om);
         int nmig = __popcll(dm) < __popcll(tkm) ? __popcll(dm) : __popcll(tkm);
-        if (nmig > kQCap - total - nown) nmig = kQCap - total - nown > 0 ? kQCap - total - nown : 0;
+        if (nmig > kRootLimit - total - nown) nmig = kRootLimit - total - nown > 0 ? kRootLimit - total - nown : 0;
         const int roff = __popcll(om & lt_mask);
-        const bool root_fits = own && total + roff < kQCap;
+        const bool root_fits = own && total + roff < kRootLimit;
         if (nmig > 0) {
             // the rank-r taker receives the rank-r donor's pair (S.tmin: rank -> slot,
             // S.cnt: the pair index; both are reset below)
