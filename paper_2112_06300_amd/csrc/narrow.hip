@@ -29,15 +29,23 @@ namespace {
 // Wide stage: one workgroup of BLOCK threads (64, 256 or 1024) per pair;
 // frontiers of up to 2 BLOCK intervals may stay in LDS (6, 24 or 96 KB: no
 // occupancy cost at the kernel's register use).
-constexpr int kPoolSlots = 64;   // pairs in flight per wave (one owner lane each)
-constexpr int kQCap = 512;       // intervals per round per wave
+// Pool: one wave per workgroup.  Lanes 0..kSlots-1 own a pair each; all 64
+// lanes evaluate queued intervals.  The search is latency-bound, so the sizes
+// are set by occupancy: at 200 VGPRs a SIMD holds 2 waves, i.e. 8 workgroups
+// per CU, which fits 160 KB of LDS only below 20 KB per workgroup.  48 slots
+// and a queue of 352 intervals take 20,384 B; 64 slots with a 512-interval
+// queue (26,880 B, 6 workgroups per CU) measured 9 % slower on the cloth
+// workload.
+constexpr int kPoolSlots = 64;   // lanes per pool workgroup (one wave)
+constexpr int kSlots = 48;       // pairs in flight per wave (one owner lane each)
+constexpr int kQCap = 352;       // intervals per round per wave
 // New pairs start only while the round's queue holds fewer than this many
 // intervals: the headroom keeps the next level's children in the queue.  A
 // pair whose children overflow it goes to the wide stage, which costs far more
-// per level: on the 1M-triangle perturbed torus a full queue (512) handed
-// 543k pairs over and the narrow phase took 30 ms; 320 hands over 17k, 12 ms.
-// The cloth workload is the same within 1 % from 320 to 512.
-constexpr int kRootLimit = 320;
+// per level: on the 1M-triangle perturbed torus a full queue handed 543k
+// pairs over and the narrow phase took 30 ms; a limit at 5/8 of the queue
+// hands over 17k, 12 ms.
+constexpr int kRootLimit = 224;
 constexpr int kClaim = 64;       // pairs a wave claims from the global list at once
 constexpr int DISCARD = 0, ACCEPT = 1, SPLIT = 2;
 
@@ -434,9 +442,9 @@ __global__ __launch_bounds__(256) void prep_feat_kernel(const double *__restrict
 }
 
 struct PoolLds {
-    double x0[12][kPoolSlots];   // query points at t = 0 of each slot's pair
-    double d[12][kPoolSlots];    // displacements
-    double eps[3][kPoolSlots];
+    double x0[12][kSlots];   // query points at t = 0 of each slot's pair
+    double d[12][kSlots];    // displacements
+    double eps[3][kSlots];
     uint32_t lv[kPoolSlots];     // levels l_t | l_u << 8 | l_v << 16 | vertex-face << 24
     uint32_t mm[kPoolSlots];     // split levels m_t | m_u << 8 | m_v << 16
     unsigned long long node[2][kQCap];  // interval numerators, 21 bits each (t | u << 21 | v << 42)
@@ -448,6 +456,8 @@ struct PoolLds {
     unsigned long long hoff[kPoolSlots];   // first node of a hand-over in the node buffer
     int nsurv[kPoolSlots], cnt[kPoolSlots], k[kPoolSlots], off[kPoolSlots], pos[kPoolSlots];
 };
+static_assert(kSlots <= kPoolSlots && kRootLimit < kQCap, "pool sizes");
+static_assert(sizeof(PoolLds) <= 163840 / 8, "pool LDS must allow 8 workgroups per CU");
 
 constexpr unsigned long long kInfBits = 0x7ff0000000000000ull;
 constexpr int kNoExpand = -1, kHandNodes = -2, kCarry = -3;
@@ -557,7 +567,7 @@ __global__ __launch_bounds__(kPoolSlots) void pool_kernel(
             epsb[0] = epsa[0]; epsb[1] = epsa[1]; epsb[2] = epsa[2];
             mb = ma;
         }
-        bool need = pa < 0 && !exhausted;
+        bool need = pa < 0 && !exhausted && lane < kSlots;  // only owner lanes take pairs
         bool got = false;
         long long qa = 0;
         unsigned long long want = __ballot(need);
@@ -713,7 +723,7 @@ __global__ __launch_bounds__(kPoolSlots) void pool_kernel(
         // end).  Roots are queued after the children: own first, then moved.
         const bool own = !active && pb >= 0;
         const bool donor = active && pb >= 0 && okb;
-        const bool taker = !active && pb < 0;
+        const bool taker = !active && pb < 0 && lane < kSlots;
         const unsigned long long om = __ballot(own), dm = __ballot(donor), tkm = __ballot(taker);
         const int nown = __popcll(om);
         int nmig = __popcll(dm) < __popcll(tkm) ? __popcll(dm) : __popcll(tkm);
@@ -1215,7 +1225,7 @@ void launch_narrow_pool(const double *V0, const double *V1, PairCounts pc, doubl
 {
     const int64_t n = pc.capacity();
     if (n == 0) return;
-    int64_t blocks = (n + kPoolSlots - 1) / kPoolSlots;
+    int64_t blocks = (n + kSlots - 1) / kSlots;
     if (blocks > pool_blocks) blocks = pool_blocks;
     pool_kernel<<<(unsigned)blocks, kPoolSlots, 0, s>>>(V0, V1, B.ids4, B.eps, B.m, pc, delta, max_iter, hit, toi,
                                                        n_enq, B.heavy, B.hnodes, B.hnode_cap, B.counters, order,
