@@ -2,9 +2,11 @@
 
 Workload: 256 x 256 cloth (130,050 triangles) falling onto a static 10,242-vertex
 icosphere, union mesh with self and cross pairs, float64 narrow phase,
-delta = 1e-6, max_iter = 1e6.  One step = ccd_broad on device-resident
-V0/V1/E/F followed by ccd_narrow on its candidate pairs (per-pair hit/TOI and
-the global minimum).  Inputs are seeded synthetic meshes built by `scenes`.
+delta = 1e-6, max_iter = 1e6.  One step = ccd_detect on device-resident
+V0/V1/E/F: the broad phase, then the narrow phase on its candidate pairs
+(per-pair hit/TOI and the global minimum), enqueued back to back with the pair
+counts passed on the device.  Inputs are seeded synthetic meshes built by
+`scenes`.
 
 The step is timed twice: with the learned schedule (features, network and
 ordering inside the timed step) -- the reported value -- and with the plain
@@ -228,13 +230,9 @@ def main():
                ccd.MAX_HEAVY)
 
     def step(schedule):
-        n_vf, n_ee = ctx.broad_into(V0, V1, E, F, vf, ee)
-        st_b = ctx.stats()
-        n = n_vf + n_ee
-        ctx.narrow(V0, V1, E, F, vf[:n_vf], ee[:n_ee], DELTA, MAX_ITER, out=(hit[:n], toi[:n], tmin, None),
-                   schedule=schedule)
-        st_n = ctx.stats()
-        return n_vf, n_ee, st_b, st_n
+        n_vf, n_ee = ctx.detect_into(V0, V1, E, F, vf, ee, hit, toi, tmin, None, DELTA, MAX_ITER, schedule=schedule)
+        st = ctx.stats()
+        return n_vf, n_ee, st, st
 
     extras = {}
     b_keys = ("broad_ms", "box_ms", "sort_ms", "gather_ms", "sweep_ms")

@@ -167,6 +167,30 @@ ccd_status ccd_narrow_sched(ccd_context *ctx, const double *V0, const double *V1
                             uint8_t *hit, double *toi, double *toi_min, int64_t *n_enq,
                             const ccd_schedule *sched, void *stream);
 
+/* Broad phase then narrow phase in one call (Sec. 5: the candidate pairs of
+ * the sweep go straight to the root finder).  The narrow phase reads the pair
+ * counts the broad phase leaves in device memory, so both are enqueued back to
+ * back on `stream` and the host waits once, at the end.
+ *
+ *   V0 .. n_ee   as for ccd_broad: pairs into vf (vf_cap x 2) and ee
+ *                (ee_cap x 2), their counts into *n_vf and *n_ee
+ *   delta .. n_enq  as for ccd_narrow, over those pairs: hit, toi and n_enq
+ *                (optional) hold vf_cap + ee_cap entries, of which the first
+ *                *n_vf + *n_ee are written, VF pairs first
+ *   sched        NULL (plain) or a LEARNED schedule; an ORDER schedule is
+ *                rejected (its permutation needs the pair count in advance)
+ *
+ * Results are those of ccd_broad followed by ccd_narrow_sched on its pairs.
+ * Errors: those of ccd_broad (CCD_ERR_CAPACITY with the required counts in
+ * *n_vf, *n_ee: the narrow outputs are then incomplete) and of ccd_narrow.
+ * Synchronizes `stream`. */
+ccd_status ccd_detect(ccd_context *ctx, const double *V0, const double *V1, int64_t nv,
+                      const int32_t *E, int64_t ne, const int32_t *F, int64_t nf,
+                      int32_t *vf, int64_t vf_cap, int64_t *n_vf, int32_t *ee, int64_t ee_cap,
+                      int64_t *n_ee, double delta, int64_t max_iter,
+                      uint8_t *hit, double *toi, double *toi_min, int64_t *n_enq,
+                      const ccd_schedule *sched, void *stream);
+
 /* Scheduling features of every pair: feat is a DEVICE (n_vf + n_ee) x
  * CCD_NUM_FEATURES float32 array, VF pairs first (zeros for a pair with an
  * index out of range, which also makes the call fail with INVALID_ARG). */

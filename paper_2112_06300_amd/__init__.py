@@ -29,7 +29,7 @@ _STATUS_NAMES = {
 
 # Every symbol include/ccd.h declares.
 EXPORTED = ["ccd_create", "ccd_destroy", "ccd_last_error", "ccd_version", "ccd_broad", "ccd_narrow",
-            "ccd_narrow_sched", "ccd_features", "ccd_mlp_predict", "ccd_mlp_grad", "ccd_adam_step",
+            "ccd_narrow_sched", "ccd_detect", "ccd_features", "ccd_mlp_predict", "ccd_mlp_grad", "ccd_adam_step",
             "ccd_get_stats", "ccd_set_tuning", "ccd_get_tuning", "ccd_batch_create", "ccd_batch_destroy",
             "ccd_batch_run", "ccd_batch_autotune"]
 
@@ -106,6 +106,9 @@ def load_library(path=LIB_PATH):
     lib.ccd_narrow_sched.argtypes = [P, P, P, i64, P, i64, P, i64, P, i64, P, i64, ctypes.c_double, i64,
                                      P, P, P, P, ctypes.POINTER(Schedule), P]
     lib.ccd_narrow_sched.restype = ctypes.c_int
+    lib.ccd_detect.argtypes = [P, P, P, i64, P, i64, P, i64, P, i64, ctypes.POINTER(i64), P, i64, ctypes.POINTER(i64),
+                               ctypes.c_double, i64, P, P, P, P, ctypes.POINTER(Schedule), P]
+    lib.ccd_detect.restype = ctypes.c_int
     lib.ccd_features.argtypes = [P, P, P, i64, P, i64, P, i64, P, i64, P, i64, ctypes.c_double, P, P]
     lib.ccd_features.restype = ctypes.c_int
     lib.ccd_mlp_predict.argtypes = [P, P, P, P, i64, P, P]
@@ -278,6 +281,25 @@ class Context:
                                     ctypes.byref(sch), _stream(stream)))
         del keep
         return hit, toi, tmin, nenq
+
+    def detect_into(self, V0, V1, E, F, vf, ee, hit, toi, tmin, nenq=None, delta=1e-6, max_iter=10**6,
+                    schedule=None, stream=None):
+        """Broad and narrow phase in one call (one wait for the device, at the end).
+
+        Pairs go into the preallocated vf (cap, 2) and ee (cap, 2); hit, toi and nenq (optional) hold
+        vf.shape[0] + ee.shape[0] entries, of which the first n_vf + n_ee are written, VF pairs first.
+        schedule: None (plain) or ("learned", params, norm[, heavy_threshold, max_heavy]).  Returns
+        (n_vf, n_ee) or raises CCDError (CCD_ERR_CAPACITY when the pairs do not fit)."""
+        lib = load_library()
+        n_vf = ctypes.c_int64()
+        n_ee = ctypes.c_int64()
+        sch, keep = _schedule(schedule) if schedule is not None else (None, None)
+        _check(lib.ccd_detect(self._h, _ptr(V0), _ptr(V1), V0.shape[0], _ptr(E), E.shape[0], _ptr(F), F.shape[0],
+                              _ptr(vf), vf.shape[0], ctypes.byref(n_vf), _ptr(ee), ee.shape[0], ctypes.byref(n_ee),
+                              float(delta), int(max_iter), _ptr(hit), _ptr(toi), _ptr(tmin), _ptr(nenq),
+                              ctypes.byref(sch) if sch is not None else None, _stream(stream)))
+        del keep
+        return n_vf.value, n_ee.value
 
     def features(self, V0, V1, E, F, vf, ee, delta=1e-6, stream=None):
         """Scheduling features, (n_vf + n_ee) x 16 float32 on the device, VF pairs first."""

@@ -70,7 +70,7 @@ struct ccd_context {
     int device = 0;
     Pool broad, narrow, scratch, sched;
     void *host = nullptr;  // pinned host staging for counters and flags
-    hipEvent_t ev[8] = {};
+    hipEvent_t ev[12] = {};  // narrow stages 0..6, broad stages 7..11
     ccd_stats stats{};
     int cus = 256;             // compute units of the device
     int pool_per_cu_max = 4;   // resident 64-lane pool workgroups per CU
@@ -178,6 +178,70 @@ bool valid_tuning(const ccd_tuning &t)
            (t.pool_wait == 0 || t.pool_wait == 1);
 }
 
+// Broad-phase arguments checked, workspace carved, every kernel launched on s
+// (stages timed by ev[7..11]); the pair counts stay on the device (B.counts).
+ccd_status broad_enqueue(ccd_context *c, const double *V0, const double *V1, int64_t nv, const int32_t *E, int64_t ne,
+                         const int32_t *F, int64_t nf, int32_t *vf, int64_t vf_cap, const int64_t *n_vf, int32_t *ee,
+                         int64_t ee_cap, const int64_t *n_ee, BroadBuffers &B, hipStream_t s)
+{
+    if (!c || !n_vf || !n_ee) return fail(CCD_ERR_INVALID_ARG, "NULL context or count pointer");
+    if (nv < 0 || ne < 0 || nf < 0 || vf_cap < 0 || ee_cap < 0)
+        return fail(CCD_ERR_INVALID_ARG, "negative size");
+    if (nv > INT32_MAX || ne > INT32_MAX || nf > INT32_MAX || nv + ne + nf > (int64_t)UINT32_MAX)
+        return fail(CCD_ERR_INVALID_ARG, "scene too large for 32-bit ids");
+    if ((nv && (!V0 || !V1)) || (ne && !E) || (nf && !F) || (vf_cap && !vf) || (ee_cap && !ee))
+        return fail(CCD_ERR_INVALID_ARG, "NULL pointer with nonzero size");
+    HIP_TRY(hipSetDevice(c->device));
+    const int64_t nb = nv + ne + nf;
+    const int64_t nbl = sort_blocks(nb);
+    Carver measure(nullptr);
+    broad_carve(measure, nb, 1, nbl, B);
+    ccd_status st = ensure(c->broad, measure.bytes());
+    if (st != CCD_OK) return st;
+    Carver cv(c->broad.base);
+    broad_carve(cv, nb, 1, nbl, B);
+
+    HIP_TRY(hipEventRecord(c->ev[7], s));
+    launch_broad_boxes(V0, V1, nv, E, ne, F, nf, B, s);
+    HIP_TRY(hipEventRecord(c->ev[9], s));
+    launch_broad_sort(nv, ne, nf, B, nbl, s);
+    HIP_TRY(hipEventRecord(c->ev[10], s));
+    launch_broad_gather(E, F, nv, ne, nf, B, s);
+    HIP_TRY(hipEventRecord(c->ev[11], s));
+    launch_broad_sweep(nv, ne, nf, vf, vf_cap, ee, ee_cap, B, c->tune.sweep_tile_group, s);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipEventRecord(c->ev[8], s));
+    return CCD_OK;
+}
+
+// Host checks of a broad phase once its stream has reached the end: h holds
+// the device counts (h[0], h[1]), the flags (h[2]) and the sort axis (h[3]).
+ccd_status broad_finish(ccd_context *c, const unsigned long long *h, int64_t nb, int64_t vf_cap, int64_t *n_vf,
+                        int64_t ee_cap, int64_t *n_ee)
+{
+    float ms = 0.f, m_box = 0.f, m_sort = 0.f, m_gather = 0.f, m_sweep = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, c->ev[7], c->ev[8]));
+    HIP_TRY(hipEventElapsedTime(&m_box, c->ev[7], c->ev[9]));
+    HIP_TRY(hipEventElapsedTime(&m_sort, c->ev[9], c->ev[10]));
+    HIP_TRY(hipEventElapsedTime(&m_gather, c->ev[10], c->ev[11]));
+    HIP_TRY(hipEventElapsedTime(&m_sweep, c->ev[11], c->ev[8]));
+    c->stats.broad_ms = ms;
+    c->stats.box_ms = m_box;
+    c->stats.sort_ms = m_sort;
+    c->stats.gather_ms = m_gather;
+    c->stats.sweep_ms = m_sweep;
+    const uint32_t flags = (uint32_t)(h[2] & 0xffffffffu);
+    c->stats.sort_axis = nb ? (int64_t)(int32_t)(h[3] & 0xffffffffu) : 0;
+    *n_vf = (int64_t)h[0];
+    *n_ee = (int64_t)h[1];
+    if (flags & FLAG_BAD_INDEX) return fail(CCD_ERR_INVALID_ARG, "edge or face vertex id out of range");
+    if (flags & FLAG_NONFINITE) return fail(CCD_ERR_NONFINITE, "non-finite or too large (> 2^960) coordinate");
+    if (*n_vf > vf_cap || *n_ee > ee_cap)
+        return fail(CCD_ERR_CAPACITY, "output capacity too small: need %lld VF and %lld EE pairs",
+                    (long long)*n_vf, (long long)*n_ee);
+    return CCD_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -269,60 +333,17 @@ ccd_status ccd_broad(ccd_context *c, const double *V0, const double *V1, int64_t
                      const int32_t *F, int64_t nf, int32_t *vf, int64_t vf_cap, int64_t *n_vf, int32_t *ee,
                      int64_t ee_cap, int64_t *n_ee, void *stream)
 {
-    if (!c || !n_vf || !n_ee) return fail(CCD_ERR_INVALID_ARG, "NULL context or count pointer");
-    if (nv < 0 || ne < 0 || nf < 0 || vf_cap < 0 || ee_cap < 0)
-        return fail(CCD_ERR_INVALID_ARG, "negative size");
-    if (nv > INT32_MAX || ne > INT32_MAX || nf > INT32_MAX || nv + ne + nf > (int64_t)UINT32_MAX)
-        return fail(CCD_ERR_INVALID_ARG, "scene too large for 32-bit ids");
-    if ((nv && (!V0 || !V1)) || (ne && !E) || (nf && !F) || (vf_cap && !vf) || (ee_cap && !ee))
-        return fail(CCD_ERR_INVALID_ARG, "NULL pointer with nonzero size");
-    HIP_TRY(hipSetDevice(c->device));
-    hipStream_t s = (hipStream_t)stream;
-    const int64_t nb = nv + ne + nf;
-    const int64_t nbl = sort_blocks(nb);
     BroadBuffers B;
-    Carver measure(nullptr);
-    broad_carve(measure, nb, 1, nbl, B);
-    ccd_status st = ensure(c->broad, measure.bytes());
+    hipStream_t s = (hipStream_t)stream;
+    ccd_status st = broad_enqueue(c, V0, V1, nv, E, ne, F, nf, vf, vf_cap, n_vf, ee, ee_cap, n_ee, B, s);
     if (st != CCD_OK) return st;
-    Carver cv(c->broad.base);
-    broad_carve(cv, nb, 1, nbl, B);
-
-    HIP_TRY(hipEventRecord(c->ev[0], s));
-    launch_broad_boxes(V0, V1, nv, E, ne, F, nf, B, s);
-    HIP_TRY(hipEventRecord(c->ev[2], s));
-    launch_broad_sort(nv, ne, nf, B, nbl, s);
-    HIP_TRY(hipEventRecord(c->ev[3], s));
-    launch_broad_gather(E, F, nv, ne, nf, B, s);
-    HIP_TRY(hipEventRecord(c->ev[4], s));
-    launch_broad_sweep(nv, ne, nf, vf, vf_cap, ee, ee_cap, B, c->tune.sweep_tile_group, s);
-    HIP_TRY(hipGetLastError());
-    HIP_TRY(hipEventRecord(c->ev[1], s));
     unsigned long long *h = (unsigned long long *)c->host;
     HIP_TRY(hipMemcpyAsync(h, B.counts, 16, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(h + 2, B.flags, 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(h + 3, B.axis, 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    float ms = 0.f, m_box = 0.f, m_sort = 0.f, m_gather = 0.f, m_sweep = 0.f;
-    HIP_TRY(hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
-    HIP_TRY(hipEventElapsedTime(&m_box, c->ev[0], c->ev[2]));
-    HIP_TRY(hipEventElapsedTime(&m_sort, c->ev[2], c->ev[3]));
-    HIP_TRY(hipEventElapsedTime(&m_gather, c->ev[3], c->ev[4]));
-    HIP_TRY(hipEventElapsedTime(&m_sweep, c->ev[4], c->ev[1]));
-    c->stats.broad_ms = ms;
-    c->stats.box_ms = m_box;
-    c->stats.sort_ms = m_sort;
-    c->stats.gather_ms = m_gather;
-    c->stats.sweep_ms = m_sweep;
-    const uint32_t flags = (uint32_t)(h[2] & 0xffffffffu);
-    c->stats.sort_axis = nb ? (int64_t)(int32_t)(h[3] & 0xffffffffu) : 0;
-    *n_vf = (int64_t)h[0];
-    *n_ee = (int64_t)h[1];
-    if (flags & FLAG_BAD_INDEX) return fail(CCD_ERR_INVALID_ARG, "edge or face vertex id out of range");
-    if (flags & FLAG_NONFINITE) return fail(CCD_ERR_NONFINITE, "non-finite or too large (> 2^960) coordinate");
-    if (*n_vf > vf_cap || *n_ee > ee_cap)
-        return fail(CCD_ERR_CAPACITY, "output capacity too small: need %lld VF and %lld EE pairs",
-                    (long long)*n_vf, (long long)*n_ee);
+    st = broad_finish(c, h, nv + ne + nf, vf_cap, n_vf, ee_cap, n_ee);
+    if (st != CCD_OK) return st;
     g_err.clear();
     return CCD_OK;
 }
@@ -382,15 +403,8 @@ ccd_status sched_setup(ccd_context *c, int64_t n, SchedBuffers &S)
     return CCD_OK;
 }
 
-ccd_status narrow_impl(ccd_context *c, const double *V0, const double *V1, int64_t nv, const int32_t *E, int64_t ne,
-                       const int32_t *F, int64_t nf, const int32_t *vf, int64_t n_vf, const int32_t *ee,
-                       int64_t n_ee, double delta, int64_t max_iter, uint8_t *hit, double *toi, double *toi_min,
-                       int64_t *n_enq, const ccd_schedule *sched, void *stream)
+ccd_status check_schedule(const ccd_schedule *sched, int64_t n)
 {
-    if (!c || !toi_min) return fail(CCD_ERR_INVALID_ARG, "NULL context or toi_min");
-    if (max_iter < 1) return fail(CCD_ERR_INVALID_ARG, "max_iter must be >= 1");
-    const int64_t n = n_vf + n_ee;
-    if (n > 0 && (!hit || !toi)) return fail(CCD_ERR_INVALID_ARG, "NULL pointer with nonzero size");
     const int kind = sched ? sched->kind : CCD_SCHED_PLAIN;
     if (kind != CCD_SCHED_PLAIN && kind != CCD_SCHED_LEARNED && kind != CCD_SCHED_ORDER)
         return fail(CCD_ERR_INVALID_ARG, "unknown schedule kind %d", kind);
@@ -400,37 +414,42 @@ ccd_status narrow_impl(ccd_context *c, const double *V0, const double *V1, int64
         return fail(CCD_ERR_INVALID_ARG, "learned schedule: negative max_heavy or non-finite threshold");
     if (kind == CCD_SCHED_ORDER && n > 0 && !sched->order)
         return fail(CCD_ERR_INVALID_ARG, "order schedule without an order");
-    NarrowBuffers B;
-    ccd_status st = narrow_setup(c, V0, V1, nv, E, ne, F, nf, vf, n_vf, ee, n_ee, delta, B);
-    if (st != CCD_OK) return st;
-    hipStream_t s = (hipStream_t)stream;
-    B.toi_min = toi_min;
-    const PairCounts pc{n_vf, n_ee, nullptr};
-    SchedBuffers S{};
-    if (kind != CCD_SCHED_PLAIN) {
-        st = sched_setup(c, n, S);
-        if (st != CCD_OK) return st;
-    }
-    const int32_t *order = nullptr;
-    if (kind == CCD_SCHED_ORDER && n > 0) {
-        // a caller's order must be a permutation: checked before any pair is searched
-        unsigned int *h = (unsigned int *)c->host;
-        launch_check_permutation(sched->order, n, S.bits, S.flag, s);
-        HIP_TRY(hipGetLastError());
-        HIP_TRY(hipMemcpyAsync(h, S.flag, 4, hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        if (h[0]) return fail(CCD_ERR_INVALID_ARG, "order is not a permutation of [0, %lld)", (long long)n);
-        order = sched->order;
-    }
+    return CCD_OK;
+}
 
+// A narrow call between its launches and its host checks.
+struct NarrowCall {
+    NarrowBuffers B;
+    int nslots = 0;
+    int64_t cap = 0;
+    bool learned = false;
+};
+
+// Every kernel of a narrow call on stream s, stages timed by ev[0..6].  The
+// pairs are counted by pc: on the host, or on the device (pc.dev, e.g. the
+// broad phase's counts), in which case every grid is sized for pc's capacity
+// and nothing here waits for the device.  `order` is a checked permutation
+// (CCD_SCHED_ORDER) or null.
+ccd_status narrow_enqueue(ccd_context *c, const double *V0, const double *V1, int64_t nv, const int32_t *E,
+                          int64_t ne, const int32_t *F, int64_t nf, const int32_t *vf, const int32_t *ee,
+                          PairCounts pc, double delta, int64_t max_iter, uint8_t *hit, double *toi, double *toi_min,
+                          int64_t *n_enq, const ccd_schedule *sched, const int32_t *order, const SchedBuffers &S,
+                          hipStream_t s, NarrowCall &call)
+{
+    NarrowBuffers &B = call.B;
+    const int64_t n = pc.capacity();
+    B.toi_min = toi_min;
     // wide-stage frontier buffers (tuned: workgroups x nodes per buffer), and
     // the early wide stage's of the learned schedule after them
-    int nslots = c->tune.heavy_slots;
-    int64_t cap = (int64_t)1 << c->tune.heavy_cap_log2;
-    const bool learned = kind == CCD_SCHED_LEARNED;
+    call.nslots = c->tune.heavy_slots;
+    call.cap = (int64_t)1 << c->tune.heavy_cap_log2;
+    call.learned = sched && sched->kind == CCD_SCHED_LEARNED;
+    const bool learned = call.learned;
+    const int nslots = call.nslots;
+    const int64_t cap = call.cap;
     const int max_early = learned ? (int)std::min<int64_t>(sched->max_heavy, n) : 0;
     const int early_slots = max_early > 0 ? std::min(max_early, nslots) : 0;
-    st = ensure(c->scratch, (size_t)(nslots + early_slots) * 6 * cap * 8);
+    ccd_status st = ensure(c->scratch, (size_t)(nslots + early_slots) * 6 * cap * 8);
     if (st != CCD_OK) return st;
     B.scratch = (unsigned long long *)c->scratch.base;
 
@@ -440,9 +459,9 @@ ccd_status narrow_impl(ccd_context *c, const double *V0, const double *V1, int64
     if (learned) {
         // prep and features in one pass, the prediction and cost histogram in a second; then the ordering
         launch_narrow_prep_feat(V0, V1, nv, E, ne, F, nf, vf, ee, pc, delta, B, S.feat, S.bins, s);
-        launch_cost_predict(sched->params, sched->norm, S.feat, n, S.cost, S.block_hist, S.packed, s);
+        launch_cost_predict(sched->params, sched->norm, S.feat, pc, S.cost, S.block_hist, S.packed, s);
         HIP_TRY(hipEventRecord(c->ev[4], s));
-        launch_cost_schedule(S.cost, n, sched->heavy_threshold, max_early, S.order, B.heavy, B.counters, S.bins,
+        launch_cost_schedule(S.cost, pc, sched->heavy_threshold, max_early, S.order, B.heavy, B.counters, S.bins,
                              S.block_hist, s);
         order = S.order;
         order_n = S.bins + 2 * 256 + 1;
@@ -472,10 +491,18 @@ ccd_status narrow_impl(ccd_context *c, const double *V0, const double *V1, int64
     launch_toi_min(toi, pc, B.toi_part, toi_min, s);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(c->ev[1], s));
-    unsigned int *h = (unsigned int *)c->host;
-    HIP_TRY(hipMemcpyAsync(h, B.counters, 16 * 4, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(h + 16, B.flags, 4, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    return CCD_OK;
+}
+
+// Host side of a narrow call once its stream has reached the end: h holds the
+// wide stage's counters (h[0..15]) and the flags (h[16]); pc counts the pairs
+// on the host.  Pairs whose frontier outgrew its buffer are re-run here.
+ccd_status narrow_finish(ccd_context *c, const unsigned int *h, const double *V0, const double *V1, PairCounts pc,
+                         double delta, int64_t max_iter, uint8_t *hit, double *toi, double *toi_min, int64_t *n_enq,
+                         hipStream_t s, NarrowCall &call)
+{
+    NarrowBuffers &B = call.B;
+    const bool learned = call.learned;
     float ms = 0.f, ms_prep = 0.f, ms_sched = 0.f, ms_pool = 0.f, ms_heavy = 0.f;
     HIP_TRY(hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
     HIP_TRY(hipEventElapsedTime(&ms_prep, c->ev[0], c->ev[4]));
@@ -485,18 +512,22 @@ ccd_status narrow_impl(ccd_context *c, const double *V0, const double *V1, int64
     c->stats.narrow_ms = ms;
     c->stats.narrow_prep_ms = ms_prep;
     // learned: the fused prep pass counts as schedule time beyond a plain prep
-    c->stats.narrow_sched_ms = kind == CCD_SCHED_LEARNED ? ms_sched : 0.0;
+    c->stats.narrow_sched_ms = learned ? ms_sched : 0.0;
     c->stats.narrow_pool_ms = ms_pool;
     c->stats.narrow_heavy_ms = ms_heavy;
     c->stats.sched_heavy_pairs = learned ? h[12] : 0;
     c->stats.heavy_pairs = h[0] - (learned ? h[12] : 0u);
     c->stats.heavy_reruns = 0;
-    uint32_t flags = h[16];
+    const uint32_t flags = h[16];
     if (flags & FLAG_BAD_INDEX) return fail(CCD_ERR_INVALID_ARG, "pair, edge or face index out of range");
     if (flags & FLAG_NONFINITE) return fail(CCD_ERR_NONFINITE, "non-finite or too large (> 2^960) coordinate");
     // pairs whose frontier outgrew their buffer: re-run them with larger buffers
+    long long *nenq = (long long *)n_enq;
+    int64_t cap = call.cap;
+    int nslots = call.nslots;
     int round = 0;
     unsigned int overflowed = h[2];
+    unsigned int *hr = (unsigned int *)c->host;
     while (overflowed > 0) {
         round++;
         c->stats.heavy_reruns += overflowed;
@@ -508,7 +539,7 @@ ccd_status narrow_impl(ccd_context *c, const double *V0, const double *V1, int64
         if (per_slot > budget || round > 12)
             return fail(CCD_ERR_OOM, "interval frontier of %u pairs exceeds device memory", overflowed);
         nslots = (int)std::min<size_t>({(size_t)1024, budget / per_slot, (size_t)overflowed});
-        st = ensure(c->scratch, (size_t)nslots * per_slot);
+        ccd_status st = ensure(c->scratch, (size_t)nslots * per_slot);
         if (st != CCD_OK) return st;
         B.scratch = (unsigned long long *)c->scratch.base;
         HIP_TRY(hipEventRecord(c->ev[0], s));
@@ -518,13 +549,111 @@ ccd_status narrow_impl(ccd_context *c, const double *V0, const double *V1, int64
         launch_toi_min(toi, pc, B.toi_part, toi_min, s);
         HIP_TRY(hipGetLastError());
         HIP_TRY(hipEventRecord(c->ev[1], s));
-        HIP_TRY(hipMemcpyAsync(h, B.counters, 16 * 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(hr, B.counters, 16 * 4, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         HIP_TRY(hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
         c->stats.narrow_ms += ms;
         c->stats.narrow_heavy_ms += ms;
-        overflowed = h[2 + (round & 1)];
+        overflowed = hr[2 + (round & 1)];
     }
+    return CCD_OK;
+}
+
+ccd_status narrow_impl(ccd_context *c, const double *V0, const double *V1, int64_t nv, const int32_t *E, int64_t ne,
+                       const int32_t *F, int64_t nf, const int32_t *vf, int64_t n_vf, const int32_t *ee,
+                       int64_t n_ee, double delta, int64_t max_iter, uint8_t *hit, double *toi, double *toi_min,
+                       int64_t *n_enq, const ccd_schedule *sched, void *stream)
+{
+    if (!c || !toi_min) return fail(CCD_ERR_INVALID_ARG, "NULL context or toi_min");
+    if (max_iter < 1) return fail(CCD_ERR_INVALID_ARG, "max_iter must be >= 1");
+    const int64_t n = n_vf + n_ee;
+    if (n > 0 && (!hit || !toi)) return fail(CCD_ERR_INVALID_ARG, "NULL pointer with nonzero size");
+    ccd_status st = check_schedule(sched, n);
+    if (st != CCD_OK) return st;
+    NarrowCall call;
+    st = narrow_setup(c, V0, V1, nv, E, ne, F, nf, vf, n_vf, ee, n_ee, delta, call.B);
+    if (st != CCD_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    const int kind = sched ? sched->kind : CCD_SCHED_PLAIN;
+    SchedBuffers S{};
+    if (kind != CCD_SCHED_PLAIN) {
+        st = sched_setup(c, n, S);
+        if (st != CCD_OK) return st;
+    }
+    const int32_t *order = nullptr;
+    if (kind == CCD_SCHED_ORDER && n > 0) {
+        // a caller's order must be a permutation: checked before any pair is searched
+        unsigned int *h = (unsigned int *)c->host;
+        launch_check_permutation(sched->order, n, S.bits, S.flag, s);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(h, S.flag, 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (h[0]) return fail(CCD_ERR_INVALID_ARG, "order is not a permutation of [0, %lld)", (long long)n);
+        order = sched->order;
+    }
+    const PairCounts pc{n_vf, n_ee, nullptr};
+    st = narrow_enqueue(c, V0, V1, nv, E, ne, F, nf, vf, ee, pc, delta, max_iter, hit, toi, toi_min, n_enq, sched,
+                        order, S, s, call);
+    if (st != CCD_OK) return st;
+    unsigned int *h = (unsigned int *)c->host;
+    HIP_TRY(hipMemcpyAsync(h, call.B.counters, 16 * 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(h + 16, call.B.flags, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    st = narrow_finish(c, h, V0, V1, pc, delta, max_iter, hit, toi, toi_min, n_enq, s, call);
+    if (st != CCD_OK) return st;
+    g_err.clear();
+    return CCD_OK;
+}
+
+// Broad and narrow phase in one call: the narrow kernels read the pair counts
+// the broad phase leaves on the device, so the two are enqueued back to back
+// and the host waits once, at the end.
+ccd_status detect_impl(ccd_context *c, const double *V0, const double *V1, int64_t nv, const int32_t *E, int64_t ne,
+                       const int32_t *F, int64_t nf, int32_t *vf, int64_t vf_cap, int64_t *n_vf, int32_t *ee,
+                       int64_t ee_cap, int64_t *n_ee, double delta, int64_t max_iter, uint8_t *hit, double *toi,
+                       double *toi_min, int64_t *n_enq, const ccd_schedule *sched, void *stream)
+{
+    if (!c || !toi_min) return fail(CCD_ERR_INVALID_ARG, "NULL context or toi_min");
+    if (max_iter < 1) return fail(CCD_ERR_INVALID_ARG, "max_iter must be >= 1");
+    if (vf_cap < 0 || ee_cap < 0) return fail(CCD_ERR_INVALID_ARG, "negative size");
+    const int64_t cap = vf_cap + ee_cap;
+    if (cap > 0 && (!hit || !toi)) return fail(CCD_ERR_INVALID_ARG, "NULL pointer with nonzero size");
+    if (sched && sched->kind == CCD_SCHED_ORDER)
+        return fail(CCD_ERR_INVALID_ARG, "an order schedule needs the pair count before the call");
+    ccd_status st = check_schedule(sched, cap);
+    if (st != CCD_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    BroadBuffers BB;
+    st = broad_enqueue(c, V0, V1, nv, E, ne, F, nf, vf, vf_cap, n_vf, ee, ee_cap, n_ee, BB, s);
+    if (st != CCD_OK) return st;
+    NarrowCall call;
+    st = narrow_setup(c, V0, V1, nv, E, ne, F, nf, vf, vf_cap, ee, ee_cap, delta, call.B);
+    if (st != CCD_OK) return st;
+    SchedBuffers S{};
+    if (sched && sched->kind == CCD_SCHED_LEARNED) {
+        st = sched_setup(c, cap, S);
+        if (st != CCD_OK) return st;
+    }
+    const PairCounts pcd{vf_cap, ee_cap, BB.counts};
+    st = narrow_enqueue(c, V0, V1, nv, E, ne, F, nf, vf, ee, pcd, delta, max_iter, hit, toi, toi_min, n_enq, sched,
+                        nullptr, S, s, call);
+    if (st != CCD_OK) return st;
+    unsigned long long *hb = (unsigned long long *)c->host;
+    unsigned int *hn = (unsigned int *)(hb + 4);
+    HIP_TRY(hipMemcpyAsync(hb, BB.counts, 16, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(hb + 2, BB.flags, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(hb + 3, BB.axis, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(hn, call.B.counters, 16 * 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(hn + 16, call.B.flags, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    st = broad_finish(c, hb, nv + ne + nf, vf_cap, n_vf, ee_cap, n_ee);
+    if (st != CCD_OK) return st;
+    // the counters are copied before a re-run overwrites the staging area
+    unsigned int hc[17];
+    std::memcpy(hc, hn, sizeof hc);
+    const PairCounts pc{*n_vf, *n_ee, nullptr};
+    st = narrow_finish(c, hc, V0, V1, pc, delta, max_iter, hit, toi, toi_min, n_enq, s, call);
+    if (st != CCD_OK) return st;
     g_err.clear();
     return CCD_OK;
 }
@@ -561,6 +690,15 @@ ccd_status ccd_narrow_sched(ccd_context *c, const double *V0, const double *V1, 
 {
     return narrow_impl(c, V0, V1, nv, E, ne, F, nf, vf, n_vf, ee, n_ee, delta, max_iter, hit, toi, toi_min, n_enq,
                        sched, stream);
+}
+
+ccd_status ccd_detect(ccd_context *c, const double *V0, const double *V1, int64_t nv, const int32_t *E, int64_t ne,
+                      const int32_t *F, int64_t nf, int32_t *vf, int64_t vf_cap, int64_t *n_vf, int32_t *ee,
+                      int64_t ee_cap, int64_t *n_ee, double delta, int64_t max_iter, uint8_t *hit, double *toi,
+                      double *toi_min, int64_t *n_enq, const ccd_schedule *sched, void *stream)
+{
+    return detect_impl(c, V0, V1, nv, E, ne, F, nf, vf, vf_cap, n_vf, ee, ee_cap, n_ee, delta, max_iter, hit, toi,
+                       toi_min, n_enq, sched, stream);
 }
 
 ccd_status ccd_features(ccd_context *c, const double *V0, const double *V1, int64_t nv, const int32_t *E, int64_t ne,

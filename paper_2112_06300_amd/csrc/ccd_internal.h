@@ -228,13 +228,15 @@ constexpr int kModelParams = kNumFeatures * kHidden + kHidden + kHidden * kHidde
 void launch_mlp_predict(const float *params, const float *norm, const float *feat, int64_t n, float *out,
                         hipStream_t s);
 // The cost model's prediction of every pair (cost[p]); each of its
-// cost_blocks(n) blocks also writes its counts of predicted-cost bins to
-// block_hist[bin * cost_blocks(n) + block] (256 x kCostMaxBlocks uint32).
+// cost_blocks(n) blocks (n = pc.capacity(); the pairs themselves are counted
+// by pc, on the device when pc.dev is set) also writes its counts of
+// predicted-cost bins to block_hist[bin * cost_blocks(n) + block]
+// (256 x kCostMaxBlocks uint32).
 constexpr int64_t kCostMaxBlocks = 1024;
 int64_t cost_blocks(int64_t n);
 // packed: 10 KB (the network's bf16 weight fragments, written here once).
 constexpr int kMlpPackedBytes = 20 * 64 * 8;
-void launch_cost_predict(const float *params, const float *norm, const float *feat, int64_t n, float *cost,
+void launch_cost_predict(const float *params, const float *norm, const float *feat, PairCounts pc, float *cost,
                          uint32_t *block_hist, void *packed, hipStream_t s);
 // grad (kModelParams floats) and loss (1 float, sum of squared errors) are
 // accumulated; the launcher clears them first.  The loss is the mean squared
@@ -248,10 +250,10 @@ void launch_adam(float *params, const float *grad, float *m, float *v, int64_t s
 // entries heavy[0..H) starting from the root, and the wide stage's counters
 // [0], [1], [12] are set to H ([13] = 0); the other pairs fill order[0 ..
 // n - H), dealt by rank so that every 64 consecutive positions span the cost
-// range.  block_hist: the prediction pass's per-block bin counts (turned into
-// per-block offsets here).  scratch: 3 x 256 + 4 uint32; scratch[2 * 256 + 1]
-// = n - H (device).
-void launch_cost_schedule(const float *cost, int64_t n, float threshold, int max_heavy, int32_t *order,
+// range (n: the pairs pc counts).  block_hist: the prediction pass's per-block
+// bin counts (turned into per-block offsets here).  scratch: 3 x 256 + 4
+// uint32; scratch[2 * 256 + 1] = n - H (device).
+void launch_cost_schedule(const float *cost, PairCounts pc, float threshold, int max_heavy, int32_t *order,
                           HeavyEntry *heavy, unsigned int *counters, uint32_t *scratch, uint32_t *block_hist,
                           hipStream_t s);
 constexpr int kSchedScratch = 3 * 256 + 4;

@@ -145,9 +145,12 @@ constexpr int kCostBins = 256;  // bins of predicted cost (1/4 in log2 cost each
 // cost_scatter_kernel walks again in the same grid.)
 __global__ __launch_bounds__(256) void mlp_predict_kernel(const float *__restrict__ prm,
                                                           const float *__restrict__ norm,
-                                                          const float *__restrict__ feat, int64_t n, float *out,
+                                                          const float *__restrict__ feat, PairCounts pc, float *out,
                                                           uint32_t *hist, const mlp_bf16x4 *__restrict__ packed)
 {
+    int64_t n_vf, n;
+    pc.get(n_vf, n);
+    (void)n_vf;
     __shared__ MlpConsts C;
     __shared__ uint32_t h[kCostBins];
     mlp_load_consts(C, prm, norm);
@@ -374,9 +377,12 @@ __device__ __forceinline__ uint32_t gcd_u32(uint32_t a, uint32_t b)
 // Exclusive scan of the bins into cursors; H, n_light and S into info[0..2];
 // the wide stage's counters start at H (entries [0, H) are taken).
 __global__ __launch_bounds__(256) void cost_scan_kernel(const uint32_t *hist, uint32_t *cursor, uint32_t *info,
-                                                        int64_t n, float threshold, int max_heavy,
+                                                        PairCounts pc, float threshold, int max_heavy,
                                                         unsigned int *counters)
 {
+    int64_t n_vf, n;
+    pc.get(n_vf, n);
+    (void)n_vf;
     __shared__ uint32_t s[kCostBins];
     const int t = threadIdx.x;
     const uint32_t x = hist[t];
@@ -412,12 +418,15 @@ __global__ __launch_bounds__(256) void cost_scan_kernel(const uint32_t *hist, ui
 // Block b places the rows it predicted (64-row chunks b, b + G, ...; wave w
 // takes every 4th of them) at its own offsets within each bin: bin start +
 // the counts of the blocks before it.
-__global__ __launch_bounds__(256) void cost_scatter_kernel(const float *__restrict__ cost, int64_t n,
+__global__ __launch_bounds__(256) void cost_scatter_kernel(const float *__restrict__ cost, PairCounts pc,
                                                            const uint32_t *__restrict__ cursor,
                                                            const uint32_t *__restrict__ block_hist,
                                                            const uint32_t *__restrict__ info, int32_t *order,
                                                            HeavyEntry *heavy)
 {
+    int64_t n_vf, n;
+    pc.get(n_vf, n);
+    (void)n_vf;
     __shared__ uint32_t off[kCostBins];
     const int64_t G = gridDim.x;
     off[threadIdx.x] = cursor[threadIdx.x] + block_hist[(int64_t)threadIdx.x * G + blockIdx.x];
@@ -494,7 +503,8 @@ void launch_mlp_predict(const float *params, const float *norm, const float *fea
     const int64_t tiles = (n + 15) / 16;
     int64_t blocks = (tiles + 3) / 4;
     if (blocks > 2048) blocks = 2048;
-    mlp_predict_kernel<<<(unsigned)blocks, 256, 0, s>>>(params, norm, feat, n, out, nullptr, nullptr);
+    mlp_predict_kernel<<<(unsigned)blocks, 256, 0, s>>>(params, norm, feat, PairCounts{n, 0, nullptr}, out, nullptr,
+                                                        nullptr);
 }
 
 // Blocks of the prediction pass and of the scatter that follows it (the same
@@ -511,13 +521,14 @@ __global__ __launch_bounds__(256) void mlp_pack_kernel(const float *__restrict__
     if (idx < 20 * 64) packed[idx] = mlp_fragment(prm, idx);
 }
 
-void launch_cost_predict(const float *params, const float *norm, const float *feat, int64_t n, float *cost,
+void launch_cost_predict(const float *params, const float *norm, const float *feat, PairCounts pc, float *cost,
                          uint32_t *block_hist, void *packed, hipStream_t s)
 {
+    const int64_t n = pc.capacity();
     if (n == 0) return;
     mlp_bf16x4 *pk = (mlp_bf16x4 *)packed;
     mlp_pack_kernel<<<5, 256, 0, s>>>(params, pk);
-    mlp_predict_kernel<<<(unsigned)cost_blocks(n), 256, 0, s>>>(params, norm, feat, n, cost, block_hist, pk);
+    mlp_predict_kernel<<<(unsigned)cost_blocks(n), 256, 0, s>>>(params, norm, feat, pc, cost, block_hist, pk);
 }
 
 void launch_mlp_grad(const float *params, const float *norm, const float *feat, const float *label, int64_t n,
@@ -540,18 +551,19 @@ void launch_adam(float *params, const float *grad, float *m, float *v, int64_t s
                                                            c1, c2);
 }
 
-void launch_cost_schedule(const float *cost, int64_t n, float threshold, int max_heavy, int32_t *order,
+void launch_cost_schedule(const float *cost, PairCounts pc, float threshold, int max_heavy, int32_t *order,
                           HeavyEntry *heavy, unsigned int *counters, uint32_t *scratch, uint32_t *block_hist,
                           hipStream_t s)
 {
     // scratch: bin totals, bin starts, info
+    const int64_t n = pc.capacity();
     const int64_t G = cost_blocks(n);
     if (n > 0) cost_colscan_kernel<<<kCostBins, kCostMaxBlocks, 0, s>>>(block_hist, G, scratch);
     else zero_u32_kernel<<<1, kCostBins, 0, s>>>(scratch, kCostBins);
-    cost_scan_kernel<<<1, kCostBins, 0, s>>>(scratch, scratch + kCostBins, scratch + 2 * kCostBins, n, threshold,
+    cost_scan_kernel<<<1, kCostBins, 0, s>>>(scratch, scratch + kCostBins, scratch + 2 * kCostBins, pc, threshold,
                                              max_heavy < 0 ? 0 : max_heavy, counters);
     if (n > 0)
-        cost_scatter_kernel<<<(unsigned)G, 256, 0, s>>>(cost, n, scratch + kCostBins, block_hist,
+        cost_scatter_kernel<<<(unsigned)G, 256, 0, s>>>(cost, pc, scratch + kCostBins, block_hist,
                                                        scratch + 2 * kCostBins, order, heavy);
 }
 

@@ -75,6 +75,8 @@ def test_new_entry_points_reject_null_arguments_without_device(lib):
     sch = ccd.Schedule(ccd.SCHED_PLAIN, None, None, None, 0.0, 0)
     assert lib.ccd_narrow_sched(None, None, None, 0, None, 0, None, 0, None, 0, None, 0, 1e-6, 10, None, None, None,
                                 None, ctypes.byref(sch), None) == ccd.CCD_ERR_INVALID_ARG
+    assert lib.ccd_detect(None, None, None, 0, None, 0, None, 0, None, 0, ctypes.byref(n), None, 0, ctypes.byref(n),
+                          1e-6, 10, None, None, None, None, None, None) == ccd.CCD_ERR_INVALID_ARG
     assert lib.ccd_last_error()  # a message is left
 
 
