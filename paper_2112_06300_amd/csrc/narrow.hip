@@ -874,11 +874,6 @@ __device__ __forceinline__ double wave_min(double v)
     return v;
 }
 
-__device__ __forceinline__ long long wave_sum_ll(long long v)
-{
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
 
 // Wide stage: one workgroup per handed-over pair, frontier in HBM scratch.
 // `list` (optional) maps work indices to heavy slots; `list_count` holds the
@@ -895,14 +890,17 @@ __global__ __launch_bounds__(BLOCK) void heavy_kernel(
     // Frontier of the next level: in LDS when it surely fits (at most twice the
     // current frontier), else in this workgroup's HBM buffers.
     constexpr int kLds = 2 * BLOCK;
+    constexpr int kWaves = BLOCK / 64;
     __shared__ unsigned long long s_front[2][3 * kLds];
     __shared__ int s_idx;
-    __shared__ unsigned long long s_tstar;  // live t* as bits (non-negative doubles order like uint64)
-    __shared__ unsigned int s_nN;
-    __shared__ int s_state;                 // 0 continue, 1 done, 2 capped, 3 overflow
-    __shared__ unsigned int s_overflow;
-    __shared__ long long s_cnt[BLOCK / 64];
-    __shared__ double s_tmin[BLOCK / 64];
+    // Per-level reductions, three sets used in turn: set L % 3 collects level
+    // L, set (L + 1) % 3 is cleared during level L (its last readers passed
+    // the barrier that ended level L - 1), so one barrier per level suffices.
+    __shared__ unsigned int s_nN[3];          // survivors of the level (next frontier size)
+    __shared__ unsigned long long s_tl[3];    // earliest root reported at the level (bits)
+    __shared__ int s_cnt[3][kWaves];          // children kept, per wave
+    __shared__ unsigned int s_ovf[3];         // the next frontier did not fit its buffer
+    __shared__ double s_tmin[kWaves];         // earliest kept child of a capped level
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     int64_t n_vf, n_all;
     pc.get(n_vf, n_all);
@@ -946,7 +944,8 @@ __global__ __launch_bounds__(BLOCK) void heavy_kernel(
         int cur_lds = -1, nxt_lds = -1;  // LDS buffer holding the frontier, or -1 (HBM)
         int state = 0;
         double tcap = 0.0;
-        double tstart = h.tstar;
+        // t* of the pair, the same in every thread: folded in from s_tl after each level
+        double tstar = h.tstar;
         // Split levels never exceed m_k, so with every m_k <= 21 an interval's
         // three numerators pack into one word (21 bits each) and a buffer of
         // 3 cap words holds 3 cap intervals; otherwise three separate arrays.
@@ -954,7 +953,7 @@ __global__ __launch_bounds__(BLOCK) void heavy_kernel(
         if (h.node_off < 0) {
             // restart from the root
             const int r = process(q, vf, 0.0, 1.0, 0.0, 1.0, 0.0, 1.0, false, delta);
-            if (r == ACCEPT) { state = 1; tstart = 0.0; }
+            if (r == ACCEPT) { state = 1; tstar = 0.0; }
             else if (r == DISCARD) state = 1;
             if (tid == 0) { cur[0] = 0ull; cur[cap] = 0ull; cur[2 * cap] = 0ull; }
             nS = 1;
@@ -968,13 +967,14 @@ __global__ __launch_bounds__(BLOCK) void heavy_kernel(
                 cur[2 * cap + i] = (pk >> 42) & 0x1fffffull;
             }
         }
-        if (tid == 0) { s_tstar = (unsigned long long)__double_as_longlong(tstart); s_overflow = 0u; }
+        if (tid == 0) { s_ovf[0] = 0u; s_nN[0] = 0u; s_tl[0] = kInfBits; }
         __syncthreads();
-        while (state == 0) {
+        for (int lvl = 0; state == 0; lvl++) {
+            const int ps = lvl % 3, pn = (lvl + 1) % 3;
             const int k = split_dim(q.m, l);
             if (k < 0) break;  // unreachable: intervals at the finest level are always reported
             l[k]++;
-            const double tsnap = __longlong_as_double((long long)s_tstar);
+            const double tsnap = tstar;
             const double tscale = pow2neg(l[0]), uscale = pow2neg(l[1]), vscale = pow2neg(l[2]);
             const bool finest = l[0] == kMaxLevel && l[1] == kMaxLevel && l[2] == kMaxLevel;
             // where this level's survivors go
@@ -987,44 +987,48 @@ __global__ __launch_bounds__(BLOCK) void heavy_kernel(
                 nxt = cur == A ? Bb : A;
                 nstride = cap;
             }
-            if (tid == 0) s_nN = 0u;
-            __syncthreads();
-            long long cnt = 0;
-            double tmin = __builtin_huge_val();
-            for (int64_t b0 = 0; b0 < nS; b0 += BLOCK) {
+            if (tid == 0) { s_nN[pn] = 0u; s_tl[pn] = kInfBits; s_ovf[pn] = 0u; }
+            // A narrow frontier takes one child per thread (item i is child
+            // i & 1 of node i >> 1), a wide one one node and both children.
+            const bool per_child = 2 * nS <= BLOCK;
+            const int64_t items = per_child ? 2 * nS : nS;
+            const int nc = per_child ? 1 : 2;
+            int cnt = 0;
+            for (int64_t b0 = 0; b0 < items; b0 += BLOCK) {
                 const int64_t i = b0 + tid;
-                const bool has = i < nS;
+                const bool has = i < items;
+                const int64_t ni = per_child ? i >> 1 : i;
                 unsigned long long pn[3] = {0ull, 0ull, 0ull};
                 if (has) {
                     if (packed) {
-                        const unsigned long long nd = cur[i];
+                        const unsigned long long nd = cur[ni];
                         pn[0] = nd & 0x1fffffull; pn[1] = (nd >> 21) & 0x1fffffull; pn[2] = (nd >> 42) & 0x1fffffull;
                     } else {
-                        pn[0] = cur[i]; pn[1] = cur[cstride + i]; pn[2] = cur[2 * cstride + i];
+                        pn[0] = cur[ni]; pn[1] = cur[cstride + ni]; pn[2] = cur[2 * cstride + ni];
                     }
                 }
-#pragma unroll
-                for (int c = 0; c < 2; c++) {
+                for (int c = 0; c < nc; c++) {
                     unsigned long long cn[3] = {pn[0], pn[1], pn[2]};
-                    cn[k] = 2ull * pn[k] + (unsigned long long)c;
+                    cn[k] = 2ull * pn[k] + (unsigned long long)(per_child ? (int)(i & 1) : c);
                     const double t0 = (double)cn[0] * tscale;
                     const bool inF = has && t0 < tsnap;
-                    if (inF) { cnt++; tmin = t0 < tmin ? t0 : tmin; }
-                    const double live = __longlong_as_double((long long)(*(volatile unsigned long long *)&s_tstar));
+                    cnt += inF ? 1 : 0;
+                    // roots reported at this level only shorten the work, never the count
+                    const double tl = __longlong_as_double((long long)(*(volatile unsigned long long *)&s_tl[ps]));
                     int r = DISCARD;
-                    if (inF && t0 < live) {
+                    if (inF && t0 < tl) {
                         const double t1 = (double)(cn[0] + 1ull) * tscale;
                         const double u0 = (double)cn[1] * uscale, u1 = (double)(cn[1] + 1ull) * uscale;
                         const double v0 = (double)cn[2] * vscale, v1 = (double)(cn[2] + 1ull) * vscale;
                         r = process(q, vf, t0, t1, u0, u1, v0, v1, finest, delta);
                     }
-                    if (r == ACCEPT) atomicMin(&s_tstar, (unsigned long long)__double_as_longlong(t0));
+                    if (r == ACCEPT) atomicMin(&s_tl[ps], (unsigned long long)__double_as_longlong(t0));
                     const bool surv = r == SPLIT;
                     const unsigned long long mask = __ballot(surv);
                     if (mask) {
                         const int leader = __ffsll((long long)mask) - 1;
                         unsigned int base = 0u;
-                        if (lane == leader) base = atomicAdd(&s_nN, (unsigned int)__popcll(mask));
+                        if (lane == leader) base = atomicAdd(&s_nN[ps], (unsigned int)__popcll(mask));
                         base = __shfl(base, leader);
                         if (surv) {
                             const int64_t pos = (int64_t)base + __popcll(mask & ((1ull << lane) - 1ull));
@@ -1033,52 +1037,64 @@ __global__ __launch_bounds__(BLOCK) void heavy_kernel(
                             } else if (!packed && pos < nstride) {
                                 nxt[pos] = cn[0]; nxt[nstride + pos] = cn[1]; nxt[2 * nstride + pos] = cn[2];
                             } else {
-                                s_overflow = 1u;
+                                s_ovf[ps] = 1u;
                             }
                         }
                     }
                 }
             }
-            cnt = wave_sum_ll(cnt);
-            tmin = wave_min(tmin);
-            if (lane == 0) { s_cnt[wave] = cnt; s_tmin[wave] = tmin; }
+            int wcnt = 0;
+            wave_excl_scan(cnt, wcnt);
+            if (lane == 0) s_cnt[ps][wave] = wcnt;
             __syncthreads();
-            if (tid == 0) {
-                long long c_all = 0;
+            // every thread folds the level in identically
+            long long c_all = 0;
+#pragma unroll
+            for (int w = 0; w < kWaves; w++) c_all += s_cnt[ps][w];
+            const unsigned int nN = s_nN[ps];
+            const double tlev = __longlong_as_double((long long)s_tl[ps]);
+            tstar = tlev < tstar ? tlev : tstar;
+            int st = 0;
+            if (c_all == 0) st = 1;
+            else if (nenq + c_all > max_iter) st = 2;
+            else if (s_ovf[ps]) st = 3;
+            else if (nN == 0u) st = 1;
+            if (st == 2) {
+                // capped: the earliest t-lower-bound among the children kept at this level
                 double tm = __builtin_huge_val();
-                for (int w = 0; w < BLOCK / 64; w++) {
-                    c_all += s_cnt[w];
-                    tm = s_tmin[w] < tm ? s_tmin[w] : tm;
+                for (int64_t b0 = 0; b0 < 2 * nS; b0 += BLOCK) {
+                    const int64_t i = b0 + tid;
+                    if (i < 2 * nS) {
+                        const int64_t ni = i >> 1;
+                        unsigned long long c0 = packed ? (cur[ni] & 0x1fffffull) : cur[ni];
+                        if (k == 0) c0 = 2ull * c0 + (unsigned long long)(i & 1);
+                        const double t0 = (double)c0 * tscale;
+                        if (t0 < tsnap && t0 < tm) tm = t0;
+                    }
                 }
-                s_cnt[0] = c_all;
-                s_tmin[0] = tm;
-                int st = 0;
-                if (c_all == 0) st = 1;
-                else if (nenq + c_all > max_iter) st = 2;
-                else if (s_overflow) st = 3;
-                else if (s_nN == 0u) st = 1;
-                s_state = st;
+                tm = wave_min(tm);
+                if (lane == 0) s_tmin[wave] = tm;
+                __syncthreads();
+                tcap = __builtin_huge_val();
+                for (int w = 0; w < kWaves; w++) tcap = s_tmin[w] < tcap ? s_tmin[w] : tcap;
             }
-            __syncthreads();
-            state = s_state;
-            nenq += s_cnt[0];
-            tcap = s_tmin[0];
-            nS = (int64_t)s_nN;
+            state = st;
+            nenq += c_all;
+            nS = (int64_t)nN;
             cur = nxt;
             cstride = nstride;
             cur_lds = nxt_lds;
-            __syncthreads();
         }
+        __syncthreads();
         if (tid == 0) {
             if (state == 3) {
                 const unsigned o = atomicAdd(ovf_count, 1u);
                 ovf_list[o] = slot;
                 atomicOr(flags, FLAG_HEAVY_OVERFLOW);
             } else {
-                const double ts = __longlong_as_double((long long)s_tstar);
                 const bool capped = state == 2;
-                hit[p] = (uint8_t)((ts < __builtin_huge_val()) || capped);
-                toi[p] = capped ? tcap : ts;
+                hit[p] = (uint8_t)((tstar < __builtin_huge_val()) || capped);
+                toi[p] = capped ? tcap : tstar;
                 if (n_enq_out) n_enq_out[p] = nenq;
             }
         }
