@@ -990,56 +990,69 @@ __global__ __launch_bounds__(BLOCK) void heavy_kernel(
             if (tid == 0) { s_nN[pn] = 0u; s_tl[pn] = kInfBits; s_ovf[pn] = 0u; }
             // A narrow frontier takes one child per thread (item i is child
             // i & 1 of node i >> 1), a wide one one node and both children.
-            const bool per_child = 2 * nS <= BLOCK;
-            const int64_t items = per_child ? 2 * nS : nS;
-            const int nc = per_child ? 1 : 2;
             int cnt = 0;
-            for (int64_t b0 = 0; b0 < items; b0 += BLOCK) {
-                const int64_t i = b0 + tid;
-                const bool has = i < items;
-                const int64_t ni = per_child ? i >> 1 : i;
-                unsigned long long pn[3] = {0ull, 0ull, 0ull};
-                if (has) {
-                    if (packed) {
-                        const unsigned long long nd = cur[ni];
-                        pn[0] = nd & 0x1fffffull; pn[1] = (nd >> 21) & 0x1fffffull; pn[2] = (nd >> 42) & 0x1fffffull;
-                    } else {
-                        pn[0] = cur[ni]; pn[1] = cur[cstride + ni]; pn[2] = cur[2 * cstride + ni];
+            double tmin = __builtin_huge_val();  // earliest kept child (for a capped level)
+            auto child = [&](const unsigned long long cn[3], bool has) {
+                const double t0 = (double)cn[0] * tscale;
+                const bool inF = has && t0 < tsnap;
+                if (inF) { cnt++; tmin = t0 < tmin ? t0 : tmin; }
+                // roots reported at this level only shorten the work, never the count
+                const double tl = __longlong_as_double((long long)(*(volatile unsigned long long *)&s_tl[ps]));
+                int r = DISCARD;
+                if (inF && t0 < tl) {
+                    const double t1 = (double)(cn[0] + 1ull) * tscale;
+                    const double u0 = (double)cn[1] * uscale, u1 = (double)(cn[1] + 1ull) * uscale;
+                    const double v0 = (double)cn[2] * vscale, v1 = (double)(cn[2] + 1ull) * vscale;
+                    r = process(q, vf, t0, t1, u0, u1, v0, v1, finest, delta);
+                }
+                if (r == ACCEPT) atomicMin(&s_tl[ps], (unsigned long long)__double_as_longlong(t0));
+                const bool surv = r == SPLIT;
+                const unsigned long long mask = __ballot(surv);
+                if (mask) {
+                    const int leader = __ffsll((long long)mask) - 1;
+                    unsigned int base = 0u;
+                    if (lane == leader) base = atomicAdd(&s_nN[ps], (unsigned int)__popcll(mask));
+                    base = __shfl(base, leader);
+                    if (surv) {
+                        const int64_t pos = (int64_t)base + __popcll(mask & ((1ull << lane) - 1ull));
+                        if (packed && pos < 3 * nstride) {
+                            nxt[pos] = cn[0] | cn[1] << 21 | cn[2] << 42;
+                        } else if (!packed && pos < nstride) {
+                            nxt[pos] = cn[0]; nxt[nstride + pos] = cn[1]; nxt[2 * nstride + pos] = cn[2];
+                        } else {
+                            s_ovf[ps] = 1u;
+                        }
                     }
                 }
-                for (int c = 0; c < nc; c++) {
-                    unsigned long long cn[3] = {pn[0], pn[1], pn[2]};
-                    cn[k] = 2ull * pn[k] + (unsigned long long)(per_child ? (int)(i & 1) : c);
-                    const double t0 = (double)cn[0] * tscale;
-                    const bool inF = has && t0 < tsnap;
-                    cnt += inF ? 1 : 0;
-                    // roots reported at this level only shorten the work, never the count
-                    const double tl = __longlong_as_double((long long)(*(volatile unsigned long long *)&s_tl[ps]));
-                    int r = DISCARD;
-                    if (inF && t0 < tl) {
-                        const double t1 = (double)(cn[0] + 1ull) * tscale;
-                        const double u0 = (double)cn[1] * uscale, u1 = (double)(cn[1] + 1ull) * uscale;
-                        const double v0 = (double)cn[2] * vscale, v1 = (double)(cn[2] + 1ull) * vscale;
-                        r = process(q, vf, t0, t1, u0, u1, v0, v1, finest, delta);
-                    }
-                    if (r == ACCEPT) atomicMin(&s_tl[ps], (unsigned long long)__double_as_longlong(t0));
-                    const bool surv = r == SPLIT;
-                    const unsigned long long mask = __ballot(surv);
-                    if (mask) {
-                        const int leader = __ffsll((long long)mask) - 1;
-                        unsigned int base = 0u;
-                        if (lane == leader) base = atomicAdd(&s_nN[ps], (unsigned int)__popcll(mask));
-                        base = __shfl(base, leader);
-                        if (surv) {
-                            const int64_t pos = (int64_t)base + __popcll(mask & ((1ull << lane) - 1ull));
-                            if (packed && pos < 3 * nstride) {
-                                nxt[pos] = cn[0] | cn[1] << 21 | cn[2] << 42;
-                            } else if (!packed && pos < nstride) {
-                                nxt[pos] = cn[0]; nxt[nstride + pos] = cn[1]; nxt[2 * nstride + pos] = cn[2];
-                            } else {
-                                s_ovf[ps] = 1u;
-                            }
-                        }
+            };
+            auto node = [&](int64_t ni, bool has, unsigned long long pn[3]) {
+                pn[0] = pn[1] = pn[2] = 0ull;
+                if (!has) return;
+                if (packed) {
+                    const unsigned long long nd = cur[ni];
+                    pn[0] = nd & 0x1fffffull; pn[1] = (nd >> 21) & 0x1fffffull; pn[2] = (nd >> 42) & 0x1fffffull;
+                } else {
+                    pn[0] = cur[ni]; pn[1] = cur[cstride + ni]; pn[2] = cur[2 * cstride + ni];
+                }
+            };
+            if (2 * nS <= BLOCK) {
+                const int64_t i = tid;
+                const bool has = i < 2 * nS;
+                unsigned long long cn[3];
+                node(i >> 1, has, cn);
+                cn[k] = 2ull * cn[k] + (unsigned long long)(i & 1);
+                child(cn, has);
+            } else {
+                for (int64_t b0 = 0; b0 < nS; b0 += BLOCK) {
+                    const int64_t i = b0 + tid;
+                    const bool has = i < nS;
+                    unsigned long long pn[3];
+                    node(i, has, pn);
+#pragma unroll
+                    for (int c = 0; c < 2; c++) {
+                        unsigned long long cn[3] = {pn[0], pn[1], pn[2]};
+                        cn[k] = 2ull * pn[k] + (unsigned long long)c;
+                        child(cn, has);
                     }
                 }
             }
@@ -1061,18 +1074,7 @@ __global__ __launch_bounds__(BLOCK) void heavy_kernel(
             else if (nN == 0u) st = 1;
             if (st == 2) {
                 // capped: the earliest t-lower-bound among the children kept at this level
-                double tm = __builtin_huge_val();
-                for (int64_t b0 = 0; b0 < 2 * nS; b0 += BLOCK) {
-                    const int64_t i = b0 + tid;
-                    if (i < 2 * nS) {
-                        const int64_t ni = i >> 1;
-                        unsigned long long c0 = packed ? (cur[ni] & 0x1fffffull) : cur[ni];
-                        if (k == 0) c0 = 2ull * c0 + (unsigned long long)(i & 1);
-                        const double t0 = (double)c0 * tscale;
-                        if (t0 < tsnap && t0 < tm) tm = t0;
-                    }
-                }
-                tm = wave_min(tm);
+                const double tm = wave_min(tmin);
                 if (lane == 0) s_tmin[wave] = tm;
                 __syncthreads();
                 tcap = __builtin_huge_val();
