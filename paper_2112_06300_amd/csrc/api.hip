@@ -134,7 +134,6 @@ void broad_carve(Carver &cv, int64_t nb, int64_t S, int64_t nbl, BroadBuffers &B
     B.valA = cv.take<uint32_t>(n); B.valB = cv.take<uint32_t>(n);
     B.hist = cv.take<uint32_t>((size_t)768 * nbl);
     B.bin_tot = cv.take<uint32_t>(768);
-    B.bin_base = cv.take<uint32_t>(768);
     B.stats = cv.take<double>(6 * (size_t)S);
     B.partial = cv.take<double>(8 * (size_t)box_blocks(nb));
     B.partial_scene = cv.take<int32_t>((size_t)box_blocks(nb));

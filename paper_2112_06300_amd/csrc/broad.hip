@@ -252,8 +252,8 @@ __global__ __launch_bounds__(kSortThreads) void hist_kernel(const uint32_t *__re
 }
 
 // Offsets for the scatter: hist is bin-major ([bin][block]).  One wave per
-// bin turns its row into an exclusive prefix over blocks and records the
-// bin total; a second kernel scans the 768 totals into per-bin bases.
+// bin turns its row into an exclusive prefix over blocks and records the bin
+// total; the scatter blocks scan the 768 totals themselves.
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int lane)
 {
     for (int o = 1; o < 64; o <<= 1) {
@@ -280,68 +280,91 @@ __global__ __launch_bounds__(256) void bin_scan_kernel(uint32_t *hist, int64_t n
     if (lane == 0) tot[bin] = carry;
 }
 
-__global__ __launch_bounds__(1024) void bin_base_kernel(const uint32_t *tot, uint32_t *base)
-{
-    __shared__ uint32_t part[1024];
-    const int t = threadIdx.x;
-    const uint32_t x = t < kBins ? tot[t] : 0u;
-    part[t] = x;
-    __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-        const uint32_t v = t >= o ? part[t - o] : 0u;
-        __syncthreads();
-        part[t] += v;
-        __syncthreads();
-    }
-    if (t < kBins) base[t] = part[t] - x;
-}
-
-// Stable scatter: keys of the tile are ranked in their original order.  Each
-// round covers 256 consecutive keys; within a wave, lanes with the same bin
-// find each other with 10 ballots (bins < 1024); waves then take their
-// offsets in order.
+// Stable scatter of one tile (kSortThreads x ROUNDS consecutive keys, the
+// tile hist_kernel counted).  Wave w takes the contiguous run [w, w + 1) x 64
+// x ROUNDS of the tile, in order.  First each key gets its rank among the
+// earlier keys of its bin in the run: lanes of a bin find each other with 10
+// ballots (bins < 1024) and the first of them advances the wave's count of
+// the bin.  Then each bin's wave counts become offsets -- bin base (scan of
+// the bin totals) + the bin's keys in earlier tiles + in earlier waves -- and
+// every key goes to its offset + rank.  Three barriers per tile.
+template <int ROUNDS>
 __global__ __launch_bounds__(kSortThreads) void scatter_kernel(
     const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, const uint32_t *__restrict__ bscene,
     uint32_t *kout, uint32_t *vout, int64_t n, int64_t n0, int64_t n1, int shift,
-    const uint32_t *__restrict__ hist, int64_t nblocks, const uint32_t *__restrict__ bin_base, int rounds)
+    const uint32_t *__restrict__ hist, int64_t nblocks, const uint32_t *__restrict__ tot)
 {
-    __shared__ uint32_t off[kBins];
-    for (int b = threadIdx.x; b < kBins; b += kSortThreads)
-        off[b] = bin_base[b] + hist[(int64_t)b * nblocks + blockIdx.x];
+    constexpr int kW = kSortThreads / 64;
+    static_assert(kBins == 3 * kSortThreads, "three bins per thread in the base scan");
+    __shared__ uint32_t cnt[kW][kBins];  // per wave: keys of each bin so far, then the wave's offsets
+    __shared__ uint32_t base[kBins];
+    __shared__ uint32_t wsum[kW];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    for (int b = t; b < kW * kBins; b += kSortThreads) (&cnt[0][0])[b] = 0u;
+    // bin bases: exclusive scan of the 768 totals, three consecutive bins per thread
+    const uint32_t a0 = tot[3 * t], a1 = tot[3 * t + 1], a2 = tot[3 * t + 2];
+    int wt = 0;
+    const uint32_t ex = (uint32_t)wave_excl_scan((int)(a0 + a1 + a2), wt);
+    if (lane == 0) wsum[wave] = (uint32_t)wt;
     __syncthreads();
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t before = 0u;
+    for (int w = 0; w < kW; w++) before += w < wave ? wsum[w] : 0u;
+    base[3 * t] = before + ex;
+    base[3 * t + 1] = before + ex + a0;
+    base[3 * t + 2] = before + ex + a0 + a1;
+
     const unsigned long long lt = (1ull << lane) - 1ull;
-    const int64_t base = (int64_t)blockIdx.x * kSortThreads * rounds;
-    for (int r = 0; r < rounds; r++) {
-        const int64_t i = base + (int64_t)r * kSortThreads + threadIdx.x;
+    const int64_t run = (int64_t)blockIdx.x * kSortThreads * ROUNDS + (int64_t)wave * 64 * ROUNDS;
+    uint32_t key[ROUNDS], val[ROUNDS], rank[ROUNDS];
+    int bin[ROUNDS];
+#pragma unroll
+    for (int r = 0; r < ROUNDS; r++) {
+        const int64_t i = run + (int64_t)r * 64 + lane;
         const bool valid = i < n;
         uint32_t k = 0u, v = 0u;
-        int bin = 0;
+        int bn = 0;
         if (valid) {
             k = kin[i];
             v = vin[i];
-            bin = segment_of(i, n0, n1) * 256 + (int)((bscene ? bscene[v] : k) >> shift & 255u);
+            bn = segment_of(i, n0, n1) * 256 + (int)((bscene ? bscene[v] : k) >> shift & 255u);
         }
         unsigned long long match = __ballot(valid);
         for (int bit = 0; bit < 10; bit++) {
-            const bool on = (bin >> bit) & 1;
+            const bool on = (bn >> bit) & 1;
             const unsigned long long bb = __ballot(valid && on);
             match &= on ? bb : ~bb;
         }
-        const uint32_t rank = (uint32_t)__popcll(match & lt);
-        const uint32_t cnt = (uint32_t)__popcll(match);
-        uint32_t start = 0u;
-        for (int w = 0; w < kSortThreads / 64; w++) {
-            if (wave == w && valid) {
-                start = off[bin];
-                if (rank == 0u) off[bin] = start + cnt;
-            }
-            __syncthreads();
+        const uint32_t rk = (uint32_t)__popcll(match & lt);
+        // the first lane of each bin advances the wave's count (one lane per bin: no conflict)
+        uint32_t old = 0u;
+        if (valid && rk == 0u) {
+            old = cnt[wave][bn];
+            cnt[wave][bn] = old + (uint32_t)__popcll(match);
         }
-        if (valid) {
-            const uint32_t pos = start + rank;
-            kout[pos] = k;
-            vout[pos] = v;
+        const int leader = valid ? __ffsll((long long)match) - 1 : lane;
+        old = (uint32_t)__shfl((int)old, leader);
+        key[r] = k;
+        val[r] = v;
+        bin[r] = bn;
+        rank[r] = old + rk;
+    }
+    __syncthreads();
+    for (int b = t; b < kBins; b += kSortThreads) {
+        uint32_t o = base[b] + hist[(int64_t)b * nblocks + blockIdx.x];
+        for (int w = 0; w < kW; w++) {
+            const uint32_t c = cnt[w][b];
+            cnt[w][b] = o;
+            o += c;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < ROUNDS; r++) {
+        const int64_t i = run + (int64_t)r * 64 + lane;
+        if (i < n) {
+            const uint32_t pos = cnt[wave][bin[r]] + rank[r];
+            kout[pos] = key[r];
+            vout[pos] = val[r];
         }
     }
 }
@@ -677,10 +700,14 @@ void launch_broad_sort(int64_t nv, int64_t ne, int64_t nf, const BroadBuffers &B
         hist_kernel<<<(unsigned)nblocks_sort, kSortThreads, 0, s>>>(kin, vin, digits, nb, nv, nv + ne, shift, B.hist,
                                                                    nblocks_sort, sort_rounds(nb));
         bin_scan_kernel<<<kBins / 4, 256, 0, s>>>(B.hist, nblocks_sort, B.bin_tot);
-        bin_base_kernel<<<1, 1024, 0, s>>>(B.bin_tot, B.bin_base);
-        scatter_kernel<<<(unsigned)nblocks_sort, kSortThreads, 0, s>>>(kin, vin, digits, kout, vout, nb, nv, nv + ne,
-                                                                      shift, B.hist, nblocks_sort, B.bin_base,
-                                                                      sort_rounds(nb));
+        if (sort_rounds(nb) == 8)
+            scatter_kernel<8><<<(unsigned)nblocks_sort, kSortThreads, 0, s>>>(kin, vin, digits, kout, vout, nb, nv,
+                                                                             nv + ne, shift, B.hist, nblocks_sort,
+                                                                             B.bin_tot);
+        else
+            scatter_kernel<16><<<(unsigned)nblocks_sort, kSortThreads, 0, s>>>(kin, vin, digits, kout, vout, nb, nv,
+                                                                              nv + ne, shift, B.hist, nblocks_sort,
+                                                                              B.bin_tot);
         uint32_t *tk = kin, *tv = vin;
         kin = kout; vin = vout; kout = tk; vout = tv;
     }

@@ -91,7 +91,7 @@ struct BroadBuffers {
     // sort keys / payload (double-buffered)
     uint32_t *keyA, *keyB, *valA, *valB;
     uint32_t *hist;       // 768 * nblocks
-    uint32_t *bin_tot, *bin_base;  // 768 each
+    uint32_t *bin_tot;  // 768
     double *stats;        // 6 accumulators per scene: sum c_a, sum c_a^2 (boundary blocks)
     double *partial;      // per box block: the 6 sums (stride 8) when the block is one scene
     int32_t *partial_scene;  // per box block: its scene, or -1
