@@ -46,7 +46,8 @@ constexpr int kQCap = 352;       // intervals per round per wave
 // pairs over and the narrow phase took 30 ms; a limit at 5/8 of the queue
 // hands over 17k, 12 ms.
 constexpr int kRootLimit = 224;
-constexpr int kClaim = 64;       // pairs a wave claims from the global list at once
+constexpr int kClaim = 64;       // pairs a wave claims from the global list at once (one per lane)
+static_assert(kClaim <= 64, "a chunk's order entries are held one per lane");
 constexpr int DISCARD = 0, ACCEPT = 1, SPLIT = 2;
 
 struct Query {
@@ -522,8 +523,11 @@ __global__ __launch_bounds__(kPoolSlots) void pool_kernel(
     if (order_n) n_pairs = (int64_t)*order_n;
     const int lane = threadIdx.x;
     const unsigned long long lt_mask = (1ull << lane) - 1ull;
-    // wave-uniform claim state: current chunk [ch_cur, ch_end) and the next chunk, claimed ahead
-    long long ch_cur = 0, ch_end = 0, nx_base = -1;
+    // wave-uniform claim state: current chunk [ch_cur, ch_end) and the next chunk, claimed ahead.
+    // With a schedule, lane j holds entry j of each chunk's order (loaded when the chunk is
+    // claimed), so that taking a pair costs a lane shuffle, not a dependent load.
+    long long ch_cur = 0, ch_end = 0, ch_base = 0, nx_base = -1;
+    int32_t ord_cur = 0, ord_nx = 0;
     bool exhausted = false;
     // two-stage prefetch: stage A holds ids / eps / m, stage B the gathered points
     long long pa = -1, pb = -1;
@@ -543,6 +547,7 @@ __global__ __launch_bounds__(kPoolSlots) void pool_kernel(
     int nq = 0;   // its length
     if (lane == 0) nx_base = (long long)atomicAdd((unsigned long long *)&counters[8], (unsigned long long)kClaim);
     nx_base = __shfl(nx_base, 0);
+    if (order && nx_base + lane < n_pairs) ord_nx = order[nx_base + lane];
     S.tstar[lane] = kInfBits;
     S.nsurv[lane] = 0;
     S.cnt[lane] = 0;
@@ -575,15 +580,20 @@ __global__ __launch_bounds__(kPoolSlots) void pool_kernel(
             if (ch_cur >= ch_end) {
                 if (nx_base >= n_pairs) { exhausted = true; break; }
                 ch_cur = nx_base;
+                ch_base = nx_base;
                 ch_end = ch_cur + kClaim < n_pairs ? ch_cur + kClaim : n_pairs;
+                ord_cur = ord_nx;
                 unsigned long long b = 0ull;
                 if (lane == 0) b = atomicAdd((unsigned long long *)&counters[8], (unsigned long long)kClaim);
                 nx_base = (long long)__shfl(b, 0);
+                if (order && nx_base + lane < n_pairs) ord_nx = order[nx_base + lane];
             }
             const long long avail = ch_end - ch_cur;
             const long long rank = __popcll(want & lt_mask);
-            if (need && rank < avail) {
-                qa = ch_cur + rank;
+            const bool take = need && rank < avail;
+            const int oj = __shfl(ord_cur, take ? (int)(ch_cur + rank - ch_base) : lane);
+            if (take) {
+                qa = order ? (long long)oj : ch_cur + rank;
                 got = true;
                 need = false;
             }
@@ -593,7 +603,7 @@ __global__ __launch_bounds__(kPoolSlots) void pool_kernel(
         }
         if (got) {
             // stage A: ids, C_eps and split levels of the claimed pair (in schedule order)
-            pa = order ? (long long)order[qa] : qa;
+            pa = qa;
             ida = ids4[pa];
             epsa[0] = peps[3 * pa]; epsa[1] = peps[3 * pa + 1]; epsa[2] = peps[3 * pa + 2];
             ma = pm[pa];
