@@ -105,7 +105,7 @@ ccd_status ensure(Pool &p, size_t need)
 {
     if (p.bytes >= need) return CCD_OK;
     if (p.base) {
-        hipFree(p.base);
+        (void)hipFree(p.base);
         p.base = nullptr;
         p.bytes = 0;
     }
@@ -294,13 +294,13 @@ ccd_status ccd_create(int device, ccd_context **out)
 void ccd_destroy(ccd_context *c)
 {
     if (!c) return;
-    hipSetDevice(c->device);
+    (void)hipSetDevice(c->device);
     for (Pool *p : {&c->broad, &c->narrow, &c->scratch, &c->sched})
-        if (p->base) hipFree(p->base);
+        if (p->base) (void)hipFree(p->base);
     for (auto &e : c->ev)
-        if (e) hipEventDestroy(e);
-    if (c->host) hipHostFree(c->host);
-    if (c->side) hipStreamDestroy(c->side);
+        if (e) (void)hipEventDestroy(e);
+    if (c->host) (void)hipHostFree(c->host);
+    if (c->side) (void)hipStreamDestroy(c->side);
     delete c;
 }
 
@@ -806,8 +806,8 @@ struct BatchArgs {
 
 void drop_graph(ccd_batch *b)
 {
-    if (b->exec) hipGraphExecDestroy(b->exec);
-    if (b->graph) hipGraphDestroy(b->graph);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
     b->exec = nullptr;
     b->graph = nullptr;
     b->have_graph = false;
@@ -927,7 +927,7 @@ ccd_status batch_pass(ccd_batch *b, const BatchArgs &a, bool use_graph, int64_t 
             HIP_TRY(hipMemGetInfo(&free_b, &total_b));
             const size_t per_slot = (size_t)6 * cap * 8;
             if (per_slot > free_b / 2 || round > 12) {
-                if (big.base) hipFree(big.base);
+                if (big.base) (void)hipFree(big.base);
                 return fail(CCD_ERR_OOM, "interval frontier of %u pairs exceeds device memory", overflowed);
             }
             const int nslots = (int)std::min<size_t>({(size_t)1024, (free_b / 2) / per_slot, (size_t)overflowed});
@@ -942,7 +942,7 @@ ccd_status batch_pass(ccd_batch *b, const BatchArgs &a, bool use_graph, int64_t 
             HIP_TRY(hipStreamSynchronize(s));
             overflowed = hc[2 + (round & 1)];
         }
-        if (big.base) hipFree(big.base);
+        if (big.base) (void)hipFree(big.base);
         launch_scene_min(a.toi, pc, a.vf, a.ee, b->off, b->off + (b->S + 1), b->S, a.toi_min, s);
         HIP_TRY(hipGetLastError());
         HIP_TRY(hipStreamSynchronize(s));
@@ -1067,14 +1067,14 @@ ccd_status ccd_batch_create(ccd_context *c, int64_t n_scenes, const int64_t *v_o
 void ccd_batch_destroy(ccd_batch *b)
 {
     if (!b) return;
-    hipSetDevice(b->ctx->device);
-    if (b->cs) hipStreamSynchronize(b->cs);
+    (void)hipSetDevice(b->ctx->device);
+    if (b->cs) (void)hipStreamSynchronize(b->cs);
     drop_graph(b);
     for (Pool *p : {&b->mem, &b->frontier})
-        if (p->base) hipFree(p->base);
+        if (p->base) (void)hipFree(p->base);
     for (hipEvent_t e : {b->ev_in, b->ev_out, b->t0, b->t1})
-        if (e) hipEventDestroy(e);
-    if (b->cs) hipStreamDestroy(b->cs);
+        if (e) (void)hipEventDestroy(e);
+    if (b->cs) (void)hipStreamDestroy(b->cs);
     delete b;
 }
 
