@@ -602,23 +602,32 @@ __device__ __forceinline__ void sweep_tile(const K *__restrict__ klo, const K *_
             kk[u] = klo[j + u];
             bl[u] = R.lob[j + u]; bh[u] = R.hib[j + u]; cl[u] = R.loc[j + u]; ch[u] = R.hic[j + u];
         }
-        if (kk[0] > kmax) { done = true; break; }  // this and every later candidate lies beyond all windows
-        bool ok[U];
-        unsigned long long any = 0ull;
-#pragma unroll
-        for (int u = 0; u < U; u++) {
+        // The block is tested whole (one wait for its loads); candidates past
+        // every lane's upper key fail the key test, and the walk ends after
+        // the block whose last key is past them all.
+        // Only the block's union mask is kept; the rare block with an overlap
+        // repeats its tests candidate by candidate to emit the pairs.
+        // Only the block's union mask is kept; the rare block with an overlap
+        // repeats its tests candidate by candidate to emit the pairs.
+        auto test = [&](int u) {
             bool t = (kk[u] <= kh) & (bl[u] <= hb) & (lb <= bh[u]) & (cl[u] <= hc) & (lc <= ch[u]);
             if (ROLE == 0) t &= kk[u] >= kl;
             else if (ROLE == 1) t &= j + u > i;
             else t &= kk[u] > kl;
-            ok[u] = t;
-            any |= __ballot(t);
-        }
-        if (any == 0ull) continue;
+            return t;
+        };
+        unsigned long long any = 0ull;
 #pragma unroll
-        for (int u = 0; u < U; u++)
-            if (__ballot(ok[u])) sweep_emit<K, ROLE>(j + u, ok[u], R, me, w0, w1, w2, lane, lt, fill, out, out_cap,
-                                                     counter, s_out);
+        for (int u = 0; u < U; u++) any |= __ballot(test(u));
+        if (any != 0ull) {
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const bool t = test(u);
+                if (__ballot(t)) sweep_emit<K, ROLE>(j + u, t, R, me, w0, w1, w2, lane, lt, fill, out, out_cap, counter,
+                                                     s_out);
+            }
+        }
+        if (kk[U - 1] > kmax) { done = true; break; }  // every later candidate lies beyond all windows
     }
     for (; !done && j < jend; j++) {
         const K kj = klo[j];
