@@ -163,7 +163,6 @@ void narrow_carve(Carver &cv, int64_t npairs, NarrowBuffers &B)
     B.overflow_list[0] = cv.take<int32_t>(m);
     B.overflow_list[1] = cv.take<int32_t>(m);
     B.flags = cv.take<uint32_t>(1);
-    B.toi_part = cv.take<double>(kToiParts);
     B.toi_min = nullptr;
     B.scratch = nullptr;
 }
@@ -487,8 +486,6 @@ ccd_status narrow_enqueue(ccd_context *c, const double *V0, const double *V1, in
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(c->ev[3], s));
     if (learned && early_slots > 0) HIP_TRY(hipStreamWaitEvent(s, c->ev[6], 0));
-    launch_toi_min(toi, pc, B.toi_part, toi_min, s);
-    HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(c->ev[1], s));
     return CCD_OK;
 }
@@ -544,8 +541,6 @@ ccd_status narrow_finish(ccd_context *c, const unsigned int *h, const double *V0
         HIP_TRY(hipEventRecord(c->ev[0], s));
         launch_narrow_heavy(V0, V1, pc, delta, (long long)max_iter, hit, toi, nenq, B, nslots, cap, round,
                             c->tune.heavy_lds, c->tune.heavy_block, s);
-        HIP_TRY(hipGetLastError());
-        launch_toi_min(toi, pc, B.toi_part, toi_min, s);
         HIP_TRY(hipGetLastError());
         HIP_TRY(hipEventRecord(c->ev[1], s));
         HIP_TRY(hipMemcpyAsync(hr, B.counters, 16 * 4, hipMemcpyDeviceToHost, s));

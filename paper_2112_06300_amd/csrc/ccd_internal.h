@@ -177,10 +177,11 @@ struct NarrowBuffers {
     int32_t *overflow_list[2];     // heavy slots to re-run with larger buffers (alternating)
     unsigned long long *scratch;   // heavy frontier buffers
     uint32_t *flags;
-    double *toi_part;              // per-block minima of the time-of-impact reduction (kToiParts)
+    // the call's earliest time of impact (device; null in a batch, whose
+    // per-scene minima come from launch_scene_min): set to +inf by the prep
+    // launch, lowered by an atomic min wherever a pair's result is written
     double *toi_min;
 };
-constexpr int kToiParts = 256;
 
 // Resident 64-lane pool workgroups per CU.
 int pool_blocks_per_cu();
@@ -270,7 +271,6 @@ void launch_narrow_heavy(const double *V0, const double *V1, PairCounts pc, doub
                          uint8_t *hit, double *toi, long long *n_enq, const NarrowBuffers &B, int nslots,
                          int64_t cap, int round, int use_lds, int block, hipStream_t s);
 
-void launch_toi_min(const double *toi, PairCounts pc, double *part, double *out, hipStream_t s);
 // out[s] = earliest toi over the pairs of scene s (CSR vertex / edge offsets
 // on the device, S + 1 each); +inf for a scene without a hit.
 void launch_scene_min(const double *toi, PairCounts pc, const int32_t *vf, const int32_t *ee, const int64_t *v_off,

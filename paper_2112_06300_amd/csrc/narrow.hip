@@ -515,7 +515,7 @@ __global__ __launch_bounds__(kPoolSlots) void pool_kernel(
     const double *__restrict__ peps, const uint32_t *__restrict__ pm, PairCounts pc,
     double delta, long long max_iter, uint8_t *hit, double *toi, long long *n_enq_out, HeavyEntry *heavy,
     unsigned long long *hnodes, int64_t hnode_cap, unsigned int *counters, const int32_t *__restrict__ order,
-    const uint32_t *__restrict__ order_n, int wait)
+    const uint32_t *__restrict__ order_n, int wait, double *toi_min)
 {
     __shared__ PoolLds S;
     int64_t n_vf, n_pairs;
@@ -681,9 +681,13 @@ __global__ __launch_bounds__(kPoolSlots) void pool_kernel(
         S.k[lane] = kNoExpand;
         S.pos[lane] = 0;
         if (outcome == 1 || outcome == 2) {
-            hit[p] = (uint8_t)(outcome == 2 || tstar < __builtin_huge_val());
-            toi[p] = outcome == 2 ? tmin : tstar;
+            const bool h = outcome == 2 || tstar < __builtin_huge_val();
+            const double tv = outcome == 2 ? tmin : tstar;
+            hit[p] = (uint8_t)h;
+            toi[p] = tv;
             if (n_enq_out) n_enq_out[p] = nenq;
+            // the call's earliest time of impact: times are >= 0, so their bits order like the values
+            if (h && toi_min) atomicMin((unsigned long long *)toi_min, (unsigned long long)__double_as_longlong(tv));
             active = false;
         } else if (outcome == 3) {
             // survivors (levels l, still to be split), t* and count go to the wide stage
@@ -895,7 +899,8 @@ __global__ __launch_bounds__(BLOCK) void heavy_kernel(
     long long max_iter, uint8_t *hit, double *toi, long long *n_enq_out, const HeavyEntry *__restrict__ heavy,
     const unsigned long long *__restrict__ hnodes, const int32_t *list, const unsigned int *list_count,
     unsigned int *next, int32_t *ovf_list, unsigned int *ovf_count, unsigned long long *scratch, int64_t cap,
-    uint32_t *flags, int use_lds, const unsigned int *list_base, unsigned int min_count, unsigned int max_count)
+    uint32_t *flags, int use_lds, const unsigned int *list_base, unsigned int min_count, unsigned int max_count,
+    double *toi_min)
 {
     // Frontier of the next level: in LDS when it surely fits (at most twice the
     // current frontier), else in this workgroup's HBM buffers.
@@ -1105,48 +1110,16 @@ __global__ __launch_bounds__(BLOCK) void heavy_kernel(
                 atomicOr(flags, FLAG_HEAVY_OVERFLOW);
             } else {
                 const bool capped = state == 2;
-                hit[p] = (uint8_t)((tstar < __builtin_huge_val()) || capped);
-                toi[p] = capped ? tcap : tstar;
+                const bool hv = (tstar < __builtin_huge_val()) || capped;
+                const double tv = capped ? tcap : tstar;
+                hit[p] = (uint8_t)hv;
+                toi[p] = tv;
                 if (n_enq_out) n_enq_out[p] = nenq;
+                if (hv && toi_min)
+                    atomicMin((unsigned long long *)toi_min, (unsigned long long)__double_as_longlong(tv));
             }
         }
         __syncthreads();
-    }
-}
-
-// Earliest time of impact: per-block minima into part[kToiParts], then one
-// block reduces them into *out (no atomics, no initialization pass).
-__global__ __launch_bounds__(256) void toi_part_kernel(const double *__restrict__ toi, PairCounts pc, double *part)
-{
-    __shared__ double red[4];
-    int64_t n_vf, n;
-    pc.get(n_vf, n);
-    double m = __builtin_huge_val();
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-        const double v = toi[i];
-        m = v < m ? v : m;
-    }
-    m = wave_min(m);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double r = red[0];
-        for (int w = 1; w < 4; w++) r = red[w] < r ? red[w] : r;
-        part[blockIdx.x] = r;
-    }
-}
-
-__global__ __launch_bounds__(256) void toi_final_kernel(const double *__restrict__ part, int nparts, double *out)
-{
-    __shared__ double red[4];
-    double m = (int)threadIdx.x < nparts ? part[threadIdx.x] : __builtin_huge_val();
-    m = wave_min(m);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double r = red[0];
-        for (int w = 1; w < 4; w++) r = red[w] < r ? red[w] : r;
-        *out = r;
     }
 }
 
@@ -1200,10 +1173,11 @@ __global__ void rerun_reset_kernel(unsigned int *c, int round)
     c[4] = 0u;
 }
 
-__global__ void counters_zero_kernel(unsigned int *c, int n, uint32_t *flags, uint32_t *hist)
+__global__ void counters_zero_kernel(unsigned int *c, int n, uint32_t *flags, uint32_t *hist, double *toi_min)
 {
     if ((int)threadIdx.x < n) c[threadIdx.x] = 0u;
     if (threadIdx.x == 0) *flags = 0u;
+    if (threadIdx.x == 0 && toi_min) *toi_min = __builtin_huge_val();
     if (hist) hist[threadIdx.x] = 0u;
 }
 
@@ -1220,7 +1194,7 @@ void launch_narrow_prep(const double *V0, const double *V1, int64_t nv, const in
                         const int32_t *F, int64_t nf, const int32_t *vf, const int32_t *ee, PairCounts pc,
                         double delta, const NarrowBuffers &B, hipStream_t s)
 {
-    counters_zero_kernel<<<1, 64, 0, s>>>(B.counters, 16, B.flags, nullptr);
+    counters_zero_kernel<<<1, 64, 0, s>>>(B.counters, 16, B.flags, nullptr, B.toi_min);
     const int64_t n = pc.capacity();
     if (n == 0) return;
     prep_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(V0, V1, nv, vf, ee, pc, E, ne, F, nf, delta, B.ids4,
@@ -1231,8 +1205,8 @@ void launch_narrow_prep_feat(const double *V0, const double *V1, int64_t nv, con
                              const int32_t *F, int64_t nf, const int32_t *vf, const int32_t *ee, PairCounts pc,
                              double delta, const NarrowBuffers &B, float *feat, uint32_t *hist, hipStream_t s)
 {
-    // counters, flags and the cost histogram start at zero
-    counters_zero_kernel<<<1, 256, 0, s>>>(B.counters, 16, B.flags, hist);
+    // counters, flags and the cost histogram start at zero, the earliest time of impact at +inf
+    counters_zero_kernel<<<1, 256, 0, s>>>(B.counters, 16, B.flags, hist, B.toi_min);
     const int64_t n = pc.capacity();
     if (n == 0) return;
     prep_feat_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(V0, V1, nv, vf, ee, pc, E, ne, F, nf, delta, B.ids4,
@@ -1257,7 +1231,7 @@ void launch_narrow_pool(const double *V0, const double *V1, PairCounts pc, doubl
     if (blocks > pool_blocks) blocks = pool_blocks;
     pool_kernel<<<(unsigned)blocks, kPoolSlots, 0, s>>>(V0, V1, B.ids4, B.eps, B.m, pc, delta, max_iter, hit, toi,
                                                        n_enq, B.heavy, B.hnodes, B.hnode_cap, B.counters, order,
-                                                       order_n, wait);
+                                                       order_n, wait, B.toi_min);
 }
 
 namespace {
@@ -1275,15 +1249,16 @@ void heavy_variant(int block, int nslots, unsigned int lo, unsigned int hi, cons
     if (block == 1024)
         heavy_kernel<1024><<<(unsigned)nslots, 1024, 0, s>>>(V0, V1, B.ids4, B.eps, B.m, pc, delta, max_iter, hit,
                                                             toi, n_enq, B.heavy, B.hnodes, list, count, next, ovf,
-                                                            ovf_count, scratch, cap, B.flags, use_lds, base, lo, hi);
+                                                            ovf_count, scratch, cap, B.flags, use_lds, base, lo, hi,
+                                                            B.toi_min);
     else if (block == 64)
         heavy_kernel<64><<<(unsigned)nslots, 64, 0, s>>>(V0, V1, B.ids4, B.eps, B.m, pc, delta, max_iter, hit, toi,
                                                         n_enq, B.heavy, B.hnodes, list, count, next, ovf, ovf_count,
-                                                        scratch, cap, B.flags, use_lds, base, lo, hi);
+                                                        scratch, cap, B.flags, use_lds, base, lo, hi, B.toi_min);
     else
         heavy_kernel<256><<<(unsigned)nslots, 256, 0, s>>>(V0, V1, B.ids4, B.eps, B.m, pc, delta, max_iter, hit, toi,
                                                           n_enq, B.heavy, B.hnodes, list, count, next, ovf, ovf_count,
-                                                          scratch, cap, B.flags, use_lds, base, lo, hi);
+                                                          scratch, cap, B.flags, use_lds, base, lo, hi, B.toi_min);
 }
 
 // block 0: adaptive (both variants, each for its range of entry counts).
@@ -1340,15 +1315,6 @@ void launch_narrow_heavy_early(const double *V0, const double *V1, PairCounts pc
 {
     heavy_launch(block, nslots, V0, V1, pc, delta, max_iter, hit, toi, n_enq, B, nullptr, &B.counters[12],
                  &B.counters[13], B.overflow_list[0], &B.counters[2], scratch, cap, use_lds, nullptr, s);
-}
-
-void launch_toi_min(const double *toi, PairCounts pc, double *part, double *out, hipStream_t s)
-{
-    const int64_t n = pc.capacity();
-    int64_t blocks = (n + 255) / 256;
-    if (blocks > kToiParts) blocks = kToiParts;
-    if (blocks > 0) toi_part_kernel<<<(unsigned)blocks, 256, 0, s>>>(toi, pc, part);
-    toi_final_kernel<<<1, 256, 0, s>>>(part, (int)blocks, out);
 }
 
 void launch_scene_min(const double *toi, PairCounts pc, const int32_t *vf, const int32_t *ee, const int64_t *v_off,
