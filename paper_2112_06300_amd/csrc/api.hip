@@ -456,7 +456,8 @@ ccd_status narrow_enqueue(ccd_context *c, const double *V0, const double *V1, in
     HIP_TRY(hipEventRecord(c->ev[0], s));
     if (learned) {
         // prep and features in one pass, the prediction and cost histogram in a second; then the ordering
-        launch_narrow_prep_feat(V0, V1, nv, E, ne, F, nf, vf, ee, pc, delta, B, S.feat, S.bins, s);
+        launch_narrow_prep_feat(V0, V1, nv, E, ne, F, nf, vf, ee, pc, delta, B, S.feat, S.bins, sched->params,
+                                S.packed, s);
         launch_cost_predict(sched->params, sched->norm, S.feat, pc, S.cost, S.block_hist, S.packed, s);
         HIP_TRY(hipEventRecord(c->ev[4], s));
         launch_cost_schedule(S.cost, pc, sched->heavy_threshold, max_early, S.order, B.heavy, B.counters, S.bins,

@@ -199,7 +199,8 @@ constexpr int kHidden = 64;
 // (hist, 256 uint32).
 void launch_narrow_prep_feat(const double *V0, const double *V1, int64_t nv, const int32_t *E, int64_t ne,
                              const int32_t *F, int64_t nf, const int32_t *vf, const int32_t *ee, PairCounts pc,
-                             double delta, const NarrowBuffers &B, float *feat, uint32_t *hist, hipStream_t s);
+                             double delta, const NarrowBuffers &B, float *feat, uint32_t *hist,
+                             const float *params, void *packed, hipStream_t s);
 void launch_narrow_features(const double *V0, const double *V1, PairCounts pc, double delta, const NarrowBuffers &B,
                             float *feat, hipStream_t s);
 
@@ -235,7 +236,8 @@ void launch_mlp_predict(const float *params, const float *norm, const float *fea
 // (256 x kCostMaxBlocks uint32).
 constexpr int64_t kCostMaxBlocks = 1024;
 int64_t cost_blocks(int64_t n);
-// packed: 10 KB (the network's bf16 weight fragments, written here once).
+// packed: 10 KB, the network's bf16 weight fragments (written by the prep and
+// feature pass, launch_narrow_prep_feat, from the same params).
 constexpr int kMlpPackedBytes = 20 * 64 * 8;
 void launch_cost_predict(const float *params, const float *norm, const float *feat, PairCounts pc, float *cost,
                          uint32_t *block_hist, void *packed, hipStream_t s);

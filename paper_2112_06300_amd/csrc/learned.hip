@@ -515,19 +515,12 @@ int64_t cost_blocks(int64_t n)
     return chunks < kCostMaxBlocks ? (chunks > 0 ? chunks : 1) : kCostMaxBlocks;
 }
 
-__global__ __launch_bounds__(256) void mlp_pack_kernel(const float *__restrict__ prm, mlp_bf16x4 *packed)
-{
-    const int idx = blockIdx.x * 256 + threadIdx.x;
-    if (idx < 20 * 64) packed[idx] = mlp_fragment(prm, idx);
-}
-
 void launch_cost_predict(const float *params, const float *norm, const float *feat, PairCounts pc, float *cost,
                          uint32_t *block_hist, void *packed, hipStream_t s)
 {
     const int64_t n = pc.capacity();
     if (n == 0) return;
-    mlp_bf16x4 *pk = (mlp_bf16x4 *)packed;
-    mlp_pack_kernel<<<5, 256, 0, s>>>(params, pk);
+    const mlp_bf16x4 *pk = (const mlp_bf16x4 *)packed;
     mlp_predict_kernel<<<(unsigned)cost_blocks(n), 256, 0, s>>>(params, norm, feat, pc, cost, block_hist, pk);
 }
 

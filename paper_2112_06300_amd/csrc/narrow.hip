@@ -21,6 +21,7 @@
 //          levels above 21, continue in a workgroup of their own with the
 //          frontier in HBM scratch.
 #include "ccd_internal.h"
+#include "mlp_tile.h"
 
 namespace ccd {
 
@@ -425,8 +426,12 @@ __global__ __launch_bounds__(256) void prep_feat_kernel(const double *__restrict
                                                        const int32_t *__restrict__ E, int64_t ne,
                                                        const int32_t *__restrict__ F, int64_t nf, double delta,
                                                        int4 *ids4, double *peps, uint32_t *pm, uint32_t *flags,
-                                                       float *__restrict__ feat)
+                                                       float *__restrict__ feat, const float *__restrict__ prm,
+                                                       mlp_bf16x4 *packed)
 {
+    // the network's bf16 weight fragments for the prediction pass that follows
+    for (int idx = blockIdx.x * 256 + threadIdx.x; idx < 20 * 64; idx += gridDim.x * 256)
+        packed[idx] = mlp_fragment(prm, idx);
     int64_t n_vf, n;
     pc.get(n_vf, n);
     const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -1203,14 +1208,16 @@ void launch_narrow_prep(const double *V0, const double *V1, int64_t nv, const in
 
 void launch_narrow_prep_feat(const double *V0, const double *V1, int64_t nv, const int32_t *E, int64_t ne,
                              const int32_t *F, int64_t nf, const int32_t *vf, const int32_t *ee, PairCounts pc,
-                             double delta, const NarrowBuffers &B, float *feat, uint32_t *hist, hipStream_t s)
+                             double delta, const NarrowBuffers &B, float *feat, uint32_t *hist,
+                             const float *params, void *packed, hipStream_t s)
 {
     // counters, flags and the cost histogram start at zero, the earliest time of impact at +inf
     counters_zero_kernel<<<1, 256, 0, s>>>(B.counters, 16, B.flags, hist, B.toi_min);
     const int64_t n = pc.capacity();
     if (n == 0) return;
     prep_feat_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(V0, V1, nv, vf, ee, pc, E, ne, F, nf, delta, B.ids4,
-                                                                B.eps, B.m, B.flags, feat);
+                                                                B.eps, B.m, B.flags, feat, params,
+                                                                (mlp_bf16x4 *)packed);
 }
 
 void launch_narrow_features(const double *V0, const double *V1, PairCounts pc, double delta, const NarrowBuffers &B,
