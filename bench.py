@@ -226,8 +226,8 @@ def main():
     tmin = torch.empty(1, dtype=torch.float64, device="cuda")
 
     params, norm, model_meta = sched.load_model()
-    learned = ("learned", torch.as_tensor(params).cuda(), torch.as_tensor(norm).cuda(), ccd.HEAVY_THRESHOLD,
-               ccd.MAX_HEAVY)
+    learned = ccd.prepare_schedule(("learned", torch.as_tensor(params).cuda(), torch.as_tensor(norm).cuda(),
+                                    ccd.HEAVY_THRESHOLD, ccd.MAX_HEAVY))
 
     def step(schedule):
         n_vf, n_ee = ctx.detect_into(V0, V1, E, F, vf, ee, hit, toi, tmin, None, DELTA, MAX_ITER, schedule=schedule)

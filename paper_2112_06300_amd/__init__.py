@@ -440,9 +440,23 @@ def _require_f32(t, size):
         raise ValueError(f"expected a contiguous CUDA float32 tensor of {size} values")
 
 
+class PreparedSchedule:
+    """A schedule converted once (ctypes struct and the device tensors it points into), for calls in a loop."""
+
+    def __init__(self, schedule):
+        self.sch, self.keep = _schedule(schedule)
+
+
+def prepare_schedule(schedule):
+    """Convert a schedule tuple once; pass the result wherever a schedule is taken."""
+    return PreparedSchedule(schedule)
+
+
 def _schedule(schedule):
     """ctypes Schedule for ("learned", params, norm) or ("order", perm); also the tensors it points into."""
     import torch
+    if isinstance(schedule, PreparedSchedule):
+        return schedule.sch, schedule.keep
     kind = schedule[0]
     if kind == "plain":
         return Schedule(SCHED_PLAIN, None, None, None, 0.0, 0), ()

@@ -43,7 +43,7 @@ def _keyed(pairs, hit, toi, nenq):
 
 @pytest.mark.parametrize("scene,schedule", [
     ("cloth96", None), ("cloth96", "learned"), ("ragged", None), ("ragged", "learned"), ("spheres", "learned"),
-    ("tiny", None), ("tiny", "learned")])
+    ("tiny", None), ("tiny", "learned"), ("cloth96", "prepared")])
 def test_detect_matches_oracle(ctx, scene, schedule):
     if scene == "cloth96":
         s = scenes.cloth_on_sphere(n=96, sphere_subdivisions=3, seed=21)
@@ -65,6 +65,8 @@ def test_detect_matches_oracle(ctx, scene, schedule):
     tmin = torch.empty(1, dtype=torch.float64, device="cuda")
     nenq = torch.empty(n, dtype=torch.int64, device="cuda")
     sc = _learned() if schedule == "learned" else None
+    if schedule == "prepared":
+        sc = ccd.prepare_schedule(_learned())
     n_vf, n_ee = ctx.detect_into(V0, V1, E, F, vf, ee, hit, toi, tmin, nenq, DELTA, 10 ** 6, schedule=sc)
     torch.cuda.synchronize()
     assert (n_vf, n_ee) == (len(ovf), len(oee))
