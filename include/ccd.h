@@ -227,7 +227,7 @@ typedef struct {
     double narrow_ms;       /* whole ccd_narrow call, first kernel to last */
     double narrow_prep_ms;  /* per-pair ids, tolerance box and split levels */
     double narrow_sched_ms; /* learned schedule: features, network and ordering (0 when plain) */
-    double narrow_pool_ms;  /* wave-pool search (64 pairs in flight per wave) */
+    double narrow_pool_ms;  /* wave-pool search (48 pairs in flight per wave) */
     double narrow_heavy_ms; /* workgroup-per-pair search of handed-over pairs (first round) */
     int64_t sort_axis;      /* axis the last broad phase swept along */
     int64_t heavy_pairs;    /* pairs the last narrow phase passed to the wide stage */

@@ -73,7 +73,7 @@ struct ccd_context {
     hipEvent_t ev[12] = {};  // narrow stages 0..6, broad stages 7..11
     ccd_stats stats{};
     int cus = 256;             // compute units of the device
-    int pool_per_cu_max = 4;   // resident 64-lane pool workgroups per CU
+    int pool_per_cu_max = 4;   // resident one-wave pool workgroups per CU (set from the occupancy query)
     char arch[64] = "gfx950";
     ccd_tuning tune{};
     hipStream_t side = nullptr;  // second stream: the learned schedule's early wide stage

@@ -10,7 +10,7 @@
 //
 // Stages:
 //   prep:  per pair, the 4 vertex ids (checked), C_eps and the split levels.
-//   pool:  each wave keeps 64 pairs in flight (constants in LDS).  A round is
+//   pool:  each wave keeps 48 pairs in flight (constants in LDS).  A round is
 //          a bookkeeping phase -- every owner lane consumes its pair's results,
 //          counts and caps, and pushes the next level's intervals into a
 //          shared LDS queue through a wave prefix sum -- followed by a
