@@ -180,3 +180,38 @@ def test_learned_schedule_10M_pairs_identical(ctx):
     rng = np.random.Generator(np.random.PCG64(51))
     idx = np.unique(rng.choice(len(vf) + len(ee), 2000, replace=False))
     check_narrow_sampled(s, vf, ee, plain[0], plain[1], plain[3], idx)
+
+
+def test_detect_bench_workload_matches_oracle(ctx):
+    """The timed step of the benchmark -- ccd_detect with the learned schedule on the 256 x 256 cloth and
+    the 10,242-vertex sphere, with the capacities and launch shapes the benchmark uses -- against the
+    oracle's brute-force broad phase and narrow phase on every pair: identical pair sets, per-pair
+    hit / toi / n_enq bit for bit, and the minimum."""
+    from paper_2112_06300_amd import sched
+    s = scenes.cloth_on_sphere()
+    print(f"detect full size: {s.name} nv={s.nv} ne={s.ne} nf={s.nf}", flush=True)
+    V0, V1, E, F = dev(s.V0, torch.float64), dev(s.V1, torch.float64), dev(s.E, torch.int32), dev(s.F, torch.int32)
+    ovf, oee = oracle.broad(s.V0, s.V1, s.E, s.F)
+    cap_vf, cap_ee = len(ovf) + 1024, len(oee) + 1024
+    vf = torch.empty((cap_vf, 2), dtype=torch.int32, device="cuda")
+    ee = torch.empty((cap_ee, 2), dtype=torch.int32, device="cuda")
+    n = cap_vf + cap_ee
+    hit = torch.empty(n, dtype=torch.uint8, device="cuda")
+    toi = torch.empty(n, dtype=torch.float64, device="cuda")
+    tmin = torch.empty(1, dtype=torch.float64, device="cuda")
+    nenq = torch.empty(n, dtype=torch.int64, device="cuda")
+    p, nm, _ = sched.load_model()
+    sc = ccd.prepare_schedule(("learned", dev(p, torch.float32), dev(nm, torch.float32), ccd.HEAVY_THRESHOLD,
+                               ccd.MAX_HEAVY))
+    n_vf, n_ee = ctx.detect_into(V0, V1, E, F, vf, ee, hit, toi, tmin, nenq, DELTA, 10 ** 6, schedule=sc)
+    torch.cuda.synchronize()
+    assert (n_vf, n_ee) == (len(ovf), len(oee))
+    gvf, gee = vf[:n_vf].cpu().numpy(), ee[:n_ee].cpu().numpy()
+    assert pair_set(gvf) == pair_set(ovf) and pair_set(gee) == pair_set(oee)
+    oh, ot, on_, _, omin = oracle.narrow(s.V0, s.V1, s.E, s.F, gvf, gee, DELTA)
+    m = n_vf + n_ee
+    h, t, e = hit[:m].cpu().numpy(), toi[:m].cpu().numpy(), nenq[:m].cpu().numpy()
+    assert np.array_equal(h, oh), np.nonzero(h != oh)[0][:10]
+    assert np.array_equal(t.view(np.int64), ot.view(np.int64)), np.nonzero(t != ot)[0][:10]
+    assert np.array_equal(e, on_), np.nonzero(e != on_)[0][:10]
+    assert np.float64(tmin.cpu()[0]).view(np.int64) == np.float64(omin).view(np.int64)
