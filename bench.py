@@ -197,7 +197,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the narrow and broad phases of this "
-              "library run on a single MI355X; multi-GPU sharding is described in DESIGN.md but not built.",
+              "library run on a single MI355X; sharding across GPUs is designed but not built.",
               file=sys.stderr)
         sys.exit(2)
     import torch
