@@ -49,6 +49,7 @@ def _load():
                                  ctypes.POINTER(ctypes.POINTER(ctypes.c_int32)), ctypes.POINTER(i64)]
     lib.oracle_free.argtypes = [P]
     lib.oracle_query.argtypes = [ctypes.c_int, P, ctypes.c_double, i64, P, P, P, P]
+    lib.oracle_query_levels.argtypes = [ctypes.c_int, P, ctypes.c_double, i64, P, P, P, P]
     lib.oracle_eval_F.argtypes = [ctypes.c_int, P, ctypes.c_double, ctypes.c_double, ctypes.c_double, P]
     lib.oracle_eps.argtypes = [ctypes.c_int, P, P]
     lib.oracle_levels_needed.argtypes = [ctypes.c_int, P, ctypes.c_double, P]
@@ -119,6 +120,19 @@ def query(kind, q24, delta=1e-6, max_iter=10**6):
     nv = np.zeros(1, np.int64)
     lib.oracle_query(int(kind), _ptr(q), float(delta), int(max_iter), _ptr(hit), _ptr(toi), _ptr(ne), _ptr(nv))
     return bool(hit[0]), float(toi[0]), int(ne[0]), int(nv[0])
+
+
+def query_levels(kind, q24, delta=1e-6, max_iter=10**6):
+    """One query; returns (hit, toi, n_enq, levels): levels = (l_t, l_u, l_v) of the last frontier built."""
+    lib = _load()
+    q = _c(q24, np.float64).reshape(24)
+    hit = np.zeros(1, np.uint8)
+    toi = np.zeros(1, np.float64)
+    ne = np.zeros(1, np.int64)
+    lv = np.zeros(3, np.int32)
+    lib.oracle_query_levels(int(kind), _ptr(q), float(delta), int(max_iter), _ptr(hit), _ptr(toi), _ptr(ne),
+                            _ptr(lv))
+    return bool(hit[0]), float(toi[0]), int(ne[0]), tuple(int(x) for x in lv)
 
 
 def eval_F(kind, q24, t, u, v):

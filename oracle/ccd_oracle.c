@@ -404,7 +404,7 @@ typedef struct { uint64_t n[3]; } node;
  * t-lower-bound still in the frontier, which is conservative. */
 static void solve_query(const query *q, double delta, int64_t max_iter,
                         uint8_t *hit, double *toi, int64_t *n_enq_out, int64_t *n_eval_out,
-                        int64_t *n_axis_out)
+                        int64_t *n_axis_out, int32_t *levels_out)
 {
     int64_t capF = 64, nF = 1;
     node *Fr = (node *)malloc((size_t)capF * sizeof(node));
@@ -462,6 +462,8 @@ static void solve_query(const query *q, double delta, int64_t max_iter,
     if (n_enq_out) *n_enq_out = n_enq;
     if (n_eval_out) *n_eval_out = n_eval;
     if (n_axis_out) *n_axis_out = n_axis;
+    if (levels_out)
+        for (int k = 0; k < 3; k++) levels_out[k] = l[k];
     free(Fr);
     free(S);
 }
@@ -472,7 +474,18 @@ void oracle_query(int kind, const double *q24, double delta, int64_t max_iter,
 {
     query q;
     make_query(&q, kind, q24, delta);
-    solve_query(&q, delta, max_iter, hit, toi, n_enq, n_eval, NULL);
+    solve_query(&q, delta, max_iter, hit, toi, n_enq, n_eval, NULL, NULL);
+}
+
+/* The same query, also reporting the dyadic levels (t, u, v) of the last
+ * frontier the search built: how deep the subdivision went (an observation
+ * for tests; it does not change any result). */
+void oracle_query_levels(int kind, const double *q24, double delta, int64_t max_iter,
+                         uint8_t *hit, double *toi, int64_t *n_enq, int32_t levels[3])
+{
+    query q;
+    make_query(&q, kind, q24, delta);
+    solve_query(&q, delta, max_iter, hit, toi, n_enq, NULL, NULL, levels);
 }
 
 /* Internals exposed for the pins: F at one point, the tolerance box, the
@@ -551,7 +564,7 @@ static void *narrow_worker(void *arg)
             query q;
             make_query(&q, kind, q24, j->delta);
             int64_t ne_ = 0, nv_ = 0, na_ = 0;
-            solve_query(&q, j->delta, j->max_iter, &j->hit[i], &j->toi[i], &ne_, &nv_, &na_);
+            solve_query(&q, j->delta, j->max_iter, &j->hit[i], &j->toi[i], &ne_, &nv_, &na_, NULL);
             if (j->n_enq) j->n_enq[i] = ne_;
             if (j->n_eval) j->n_eval[i] = nv_;
             if (j->n_axis) j->n_axis[i] = na_;

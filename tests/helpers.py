@@ -56,3 +56,49 @@ def numpy_sweep_pairs(V0, V1, E, F, axis=0):
     vf = np.array(sorted(vf), dtype=np.int32).reshape(-1, 2)
     ee = np.array(sorted(ee), dtype=np.int32).reshape(-1, 2)
     return vf, ee
+
+
+def deep_split_query(seed, kind):
+    """A query with edges and motion of ~0.69 far from the origin (2^28..2^33).
+
+    At delta ~1e-6 its split levels m_k come out at most 21, but float64
+    rounding of coordinates that large keeps the inclusion box at least an ulp
+    of 2^33 (~2e-6) wide, so the search goes on splitting past m_k.  Returns
+    (q24, delta).  Edge-edge queries move each edge rigidly.
+    """
+    rng = np.random.default_rng(seed)
+    off = 2.0 ** int(rng.integers(28, 34))
+    delta = float(rng.choice([1e-6, 1.07e-6, 2e-6]))
+    s = 0.69
+    pts0 = rng.uniform(-s / 2, s / 2, size=(4, 3))
+    mot = rng.uniform(-s / 2, s / 2, size=(4, 3)) * rng.uniform(0, 1)
+    if kind == 1:
+        mot[0] = mot[1]
+        mot[2] = mot[3]
+    return q24(pts0 + off, pts0 + mot + off), delta
+
+
+def scene_of_queries(vf_queries, ee_queries):
+    """A scene of disconnected primitives holding the given queries, and its pairs.
+
+    Each vertex-face query (24 values: p, a, b, c at t=0 then t=1) becomes a
+    lone vertex and a triangle, each edge-edge query (a0, a1, b0, b1) two lone
+    edges.  Returns (V0, V1, E, F, vf, ee) with the pairs in query order."""
+    P0, P1, E, F, vf, ee = [], [], [], [], [], []
+    for q in vf_queries:
+        q = np.asarray(q, np.float64).reshape(2, 4, 3)
+        b = len(P0)
+        P0 += list(q[0])
+        P1 += list(q[1])
+        F.append((b + 1, b + 2, b + 3))
+        vf.append((b, len(F) - 1))
+    for q in ee_queries:
+        q = np.asarray(q, np.float64).reshape(2, 4, 3)
+        b = len(P0)
+        P0 += list(q[0])
+        P1 += list(q[1])
+        E += [(b, b + 1), (b + 2, b + 3)]
+        ee.append((len(E) - 2, len(E) - 1))
+    return (np.array(P0, np.float64).reshape(-1, 3), np.array(P1, np.float64).reshape(-1, 3),
+            np.array(E, np.int32).reshape(-1, 2), np.array(F, np.int32).reshape(-1, 3),
+            np.array(vf, np.int32).reshape(-1, 2), np.array(ee, np.int32).reshape(-1, 2))
