@@ -966,10 +966,14 @@ __global__ __launch_bounds__(BLOCK) void heavy_kernel(
         double tcap = 0.0;
         // t* of the pair, the same in every thread: folded in from s_tl after each level
         double tstar = h.tstar;
-        // Split levels never exceed m_k, so with every m_k <= 21 an interval's
-        // three numerators pack into one word (21 bits each) and a buffer of
-        // 3 cap words holds 3 cap intervals; otherwise three separate arrays.
-        const bool packed = q.m[0] <= kLightMaxLevel && q.m[1] <= kLightMaxLevel && q.m[2] <= kLightMaxLevel;
+        // While every level is at most 21, an interval's three numerators pack
+        // into one word (21 bits each) and a buffer of 3 cap words holds 3 cap
+        // intervals; from the first level that takes some l_k past 21 (the
+        // split rule goes on past m_k when the box is still wider than delta,
+        // up to level 52) the frontier is written as three separate arrays.
+        // pk_cur is the layout of the frontier being read, pk_nxt that of the
+        // one being written.
+        bool pk_cur = l[0] <= kLightMaxLevel && l[1] <= kLightMaxLevel && l[2] <= kLightMaxLevel;
         if (h.node_off < 0) {
             // restart from the root
             const int r = process(q, vf, 0.0, 1.0, 0.0, 1.0, 0.0, 1.0, false, delta);
@@ -977,7 +981,8 @@ __global__ __launch_bounds__(BLOCK) void heavy_kernel(
             else if (r == DISCARD) state = 1;
             if (tid == 0) { cur[0] = 0ull; cur[cap] = 0ull; cur[2 * cap] = 0ull; }
             nS = 1;
-        } else if (packed) {
+            pk_cur = true;
+        } else if (pk_cur) {
             for (int64_t i = tid; i < nS; i += BLOCK) cur[i] = hnodes[h.node_off + i];
         } else {
             for (int64_t i = tid; i < nS; i += BLOCK) {
@@ -994,11 +999,12 @@ __global__ __launch_bounds__(BLOCK) void heavy_kernel(
             const int k = split_dim(q.m, l);
             if (k < 0) break;  // unreachable: intervals at the finest level are always reported
             l[k]++;
+            const bool pk_nxt = pk_cur && l[k] <= kLightMaxLevel;
             const double tsnap = tstar;
             const double tscale = pow2neg(l[0]), uscale = pow2neg(l[1]), vscale = pow2neg(l[2]);
             const bool finest = l[0] == kMaxLevel && l[1] == kMaxLevel && l[2] == kMaxLevel;
             // where this level's survivors go
-            if (use_lds && 2 * nS <= (packed ? 3 * kLds : kLds)) {
+            if (use_lds && 2 * nS <= (pk_nxt ? 3 * kLds : kLds)) {
                 nxt_lds = cur_lds == 0 ? 1 : 0;
                 nxt = s_front[nxt_lds];
                 nstride = kLds;
@@ -1035,9 +1041,9 @@ __global__ __launch_bounds__(BLOCK) void heavy_kernel(
                     base = __shfl(base, leader);
                     if (surv) {
                         const int64_t pos = (int64_t)base + __popcll(mask & ((1ull << lane) - 1ull));
-                        if (packed && pos < 3 * nstride) {
+                        if (pk_nxt && pos < 3 * nstride) {
                             nxt[pos] = cn[0] | cn[1] << 21 | cn[2] << 42;
-                        } else if (!packed && pos < nstride) {
+                        } else if (!pk_nxt && pos < nstride) {
                             nxt[pos] = cn[0]; nxt[nstride + pos] = cn[1]; nxt[2 * nstride + pos] = cn[2];
                         } else {
                             s_ovf[ps] = 1u;
@@ -1048,7 +1054,7 @@ __global__ __launch_bounds__(BLOCK) void heavy_kernel(
             auto node = [&](int64_t ni, bool has, unsigned long long pn[3]) {
                 pn[0] = pn[1] = pn[2] = 0ull;
                 if (!has) return;
-                if (packed) {
+                if (pk_cur) {
                     const unsigned long long nd = cur[ni];
                     pn[0] = nd & 0x1fffffull; pn[1] = (nd >> 21) & 0x1fffffull; pn[2] = (nd >> 42) & 0x1fffffull;
                 } else {
@@ -1106,6 +1112,7 @@ __global__ __launch_bounds__(BLOCK) void heavy_kernel(
             cur = nxt;
             cstride = nstride;
             cur_lds = nxt_lds;
+            pk_cur = pk_nxt;
         }
         __syncthreads();
         if (tid == 0) {

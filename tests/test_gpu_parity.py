@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import scenes
-from helpers import q24
+from helpers import q24, deep_split_query, scene_of_queries
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -300,5 +300,27 @@ def test_tunings_give_identical_results(ctx, tuning):
         s = scenes.cloth_on_sphere(n=96, sphere_subdivisions=3, seed=21)
         ovf, oee = check_broad(ctx, s)
         check_narrow(ctx, s, ovf, oee)
+    finally:
+        ctx.set_tuning(None)
+
+
+@pytest.mark.parametrize("tuning", [None, {"heavy_lds": 0}, {"heavy_block": 64}, {"heavy_block": 1024},
+                                    {"heavy_cap_log2": 8, "heavy_slots": 16}])
+def test_narrow_levels_past_21(ctx, tuning):
+    """Pairs whose split levels m_k are at most 21 but whose search splits past level 21 (coordinates near
+    2^33 keep the inclusion box wider than delta): the wide stage must switch its frontier layout when a
+    level first exceeds 21.  Every pair compared with the oracle bit for bit."""
+    from test_oracle_pins import DEEP_SEEDS
+    if tuning:
+        ctx.set_tuning(tuning)
+    try:
+        for delta in (1.07e-6, 1e-6):
+            vq = [deep_split_query(sd, 0)[0] for sd in DEEP_SEEDS[0][delta]]
+            eq = [deep_split_query(sd, 1)[0] for sd in DEEP_SEEDS[1][delta]]
+            V0, V1, E, F, vf, ee = scene_of_queries(vq, eq)
+            s = scenes.Scene("deep_levels", V0, V1, E, F)
+            oh, _, _ = check_narrow(ctx, s, vf, ee, delta=delta)
+            assert oh.all()
+            assert ctx.stats()["heavy_pairs"] == len(vf) + len(ee)  # every pair went past the pool's 21 levels
     finally:
         ctx.set_tuning(None)
