@@ -153,6 +153,36 @@ def _stream(stream=None):
     return ctypes.c_void_p(s.cuda_stream)
 
 
+def _require(t, name, dtype, device, cols=None, rows=None, min_numel=None):
+    """Check a tensor handed to the library as a raw pointer: a contiguous CUDA tensor of `dtype` on the
+    context's device, with `cols` columns (2-D) and `rows` rows, or at least `min_numel` elements.  Raises
+    ValueError instead of letting a kernel read or write outside it."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name}: expected a torch tensor, got {type(t).__name__}")
+    if t.dtype != dtype:
+        raise ValueError(f"{name}: expected dtype {dtype}, got {t.dtype}")
+    if not t.is_cuda or t.device.index != device:
+        raise ValueError(f"{name}: expected a tensor on cuda:{device}, got {t.device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: expected a contiguous tensor")
+    if cols is not None and (t.dim() != 2 or t.shape[1] != cols):
+        raise ValueError(f"{name}: expected shape (n, {cols}), got {tuple(t.shape)}")
+    if rows is not None and t.shape[0] != rows:
+        raise ValueError(f"{name}: expected {rows} rows, got {t.shape[0]}")
+    if min_numel is not None and t.numel() < min_numel:
+        raise ValueError(f"{name}: expected at least {min_numel} elements, got {t.numel()}")
+    return t
+
+
+def _require_scene(V0, V1, E, F, device):
+    import torch
+    _require(V0, "V0", torch.float64, device, cols=3)
+    _require(V1, "V1", torch.float64, device, cols=3, rows=V0.shape[0])
+    _require(E, "E", torch.int32, device, cols=2)
+    _require(F, "F", torch.int32, device, cols=3)
+
+
 def _dev(t, dtype, cols):
     import torch
     t = torch.as_tensor(t)
@@ -237,7 +267,11 @@ class Context:
 
     def broad_into(self, V0, V1, E, F, vf, ee, stream=None):
         """Broad phase into preallocated outputs; returns (n_vf, n_ee) or raises CCDError."""
+        import torch
         lib = load_library()
+        _require_scene(V0, V1, E, F, self.device)
+        _require(vf, "vf", torch.int32, self.device, cols=2)
+        _require(ee, "ee", torch.int32, self.device, cols=2)
         n_vf = ctypes.c_int64()
         n_ee = ctypes.c_int64()
         st = lib.ccd_broad(self._h, _ptr(V0), _ptr(V1), V0.shape[0], _ptr(E), E.shape[0], _ptr(F), F.shape[0],
@@ -269,6 +303,11 @@ class Context:
             nenq = torch.empty(n, dtype=torch.int64, device=V0.device) if with_costs else None
         else:
             hit, toi, tmin, nenq = out
+            _require(hit, "hit", torch.uint8, self.device, min_numel=n)
+            _require(toi, "toi", torch.float64, self.device, min_numel=n)
+            _require(tmin, "toi_min", torch.float64, self.device, min_numel=1)
+            if nenq is not None:
+                _require(nenq, "n_enq", torch.int64, self.device, min_numel=n)
         if schedule is None:
             _check(lib.ccd_narrow(self._h, _ptr(V0), _ptr(V1), V0.shape[0], _ptr(E), E.shape[0], _ptr(F),
                                   F.shape[0], _ptr(vf), vf.shape[0], _ptr(ee), ee.shape[0], float(delta),
@@ -290,7 +329,17 @@ class Context:
         vf.shape[0] + ee.shape[0] entries, of which the first n_vf + n_ee are written, VF pairs first.
         schedule: None (plain) or ("learned", params, norm[, heavy_threshold, max_heavy]).  Returns
         (n_vf, n_ee) or raises CCDError (CCD_ERR_CAPACITY when the pairs do not fit)."""
+        import torch
         lib = load_library()
+        _require_scene(V0, V1, E, F, self.device)
+        _require(vf, "vf", torch.int32, self.device, cols=2)
+        _require(ee, "ee", torch.int32, self.device, cols=2)
+        n = vf.shape[0] + ee.shape[0]
+        _require(hit, "hit", torch.uint8, self.device, min_numel=n)
+        _require(toi, "toi", torch.float64, self.device, min_numel=n)
+        _require(tmin, "toi_min", torch.float64, self.device, min_numel=1)
+        if nenq is not None:
+            _require(nenq, "n_enq", torch.int64, self.device, min_numel=n)
         n_vf = ctypes.c_int64()
         n_ee = ctypes.c_int64()
         sch, keep = _schedule(schedule) if schedule is not None else (None, None)
@@ -373,6 +422,7 @@ class Batch:
         if any(len(o) != self.n_scenes + 1 for o in offs):
             raise ValueError("offset arrays must have the same length")
         self.vf_cap, self.ee_cap = int(vf_cap), int(ee_cap)
+        self.sizes = (int(offs[0][-1]), int(offs[1][-1]), int(offs[2][-1]))
         h = ctypes.c_void_p()
         _check(lib.ccd_batch_create(ctx.handle, self.n_scenes, offs[0].ctypes.data, offs[1].ctypes.data,
                                     offs[2].ctypes.data, self.vf_cap, self.ee_cap, ctypes.byref(h)))
@@ -385,6 +435,12 @@ class Batch:
         self.toi = torch.empty(cap, dtype=torch.float64, device=dev)
         self.n_enq = torch.empty(cap, dtype=torch.int64, device=dev)
         self.toi_min = torch.empty(self.n_scenes, dtype=torch.float64, device=dev)
+
+    def _check_inputs(self, V0, V1, E, F):
+        _require_scene(V0, V1, E, F, self.ctx.device)
+        if (V0.shape[0], E.shape[0], F.shape[0]) != self.sizes:
+            raise ValueError(f"scene sizes {(V0.shape[0], E.shape[0], F.shape[0])} differ from the batch's "
+                             f"offsets {self.sizes}")
 
     def close(self):
         if getattr(self, "_h", None):
@@ -400,6 +456,7 @@ class Batch:
     def run(self, V0, V1, E, F, delta=1e-6, max_iter=10**6, use_graph=True, with_costs=False, stream=None):
         """(vf, ee, hit, toi, toi_min, n_enq or None): views of the batch's buffers, valid until the next run."""
         lib = load_library()
+        self._check_inputs(V0, V1, E, F)
         n_vf, n_ee = ctypes.c_int64(), ctypes.c_int64()
         st = lib.ccd_batch_run(self._h, _ptr(V0), _ptr(V1), _ptr(E), _ptr(F), float(delta), int(max_iter),
                                _ptr(self.vf), _ptr(self.ee), ctypes.byref(n_vf), ctypes.byref(n_ee), _ptr(self.hit),
@@ -414,6 +471,7 @@ class Batch:
     def autotune(self, V0, V1, E, F, delta=1e-6, max_iter=10**6, cache_path=None, stream=None):
         """Time candidate tunings, set the best on the context and return it (dict)."""
         lib = load_library()
+        self._check_inputs(V0, V1, E, F)
         t = Tuning()
         _check(lib.ccd_batch_autotune(self._h, _ptr(V0), _ptr(V1), _ptr(E), _ptr(F), float(delta), int(max_iter),
                                       _ptr(self.vf), _ptr(self.ee), _ptr(self.hit), _ptr(self.toi),

@@ -135,11 +135,14 @@ __device__ __forceinline__ float mlp_forward(const MlpWeights &W, const MlpConst
 }
 
 // Bin of a predicted cost for the schedule's ordering: 256 bins of 1/4 in
-// log2 cost, costliest first.
+// log2 cost, costliest first.  The clamp is done in float before the
+// conversion (a float -> int conversion of NaN or of a value out of range is
+// undefined); NaN goes to the last bin.
 __device__ __forceinline__ int sched_cost_bin(float c)
 {
-    const int b = (int)(c * 4.f);
-    return 255 - (b < 0 ? 0 : (b > 255 ? 255 : b));
+    float x = c * 4.f;
+    x = x == x ? fminf(fmaxf(x, 0.f), 255.f) : 0.f;
+    return 255 - (int)x;
 }
 
 }  // namespace ccd

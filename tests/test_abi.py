@@ -85,3 +85,19 @@ def test_model_parameter_count_matches_header():
     assert f"#define CCD_MODEL_PARAMS {ccd.MODEL_PARAMS}" in text
     assert f"#define CCD_NUM_FEATURES {ccd.NUM_FEATURES}" in text
     assert ccd.MODEL_PARAMS == 16 * 64 + 64 + 64 * 64 + 64 + 64 + 1
+
+
+def test_binding_rejects_bad_tensors_before_any_call():
+    """Tensors passed as raw pointers are checked for dtype, device, contiguity and size first (a CPU
+    tensor, a float32 V0, a transposed view or a short output would otherwise be read or written out of
+    bounds by the kernels)."""
+    torch = pytest.importorskip("torch")
+    V = torch.zeros((4, 3), dtype=torch.float64)
+    with pytest.raises(ValueError, match="cuda"):
+        ccd._require(V, "V0", torch.float64, 0, cols=3)
+    with pytest.raises(ValueError, match="dtype"):
+        ccd._require(V.float(), "V0", torch.float64, 0, cols=3)
+    with pytest.raises(ValueError, match="dtype"):
+        ccd._require(torch.zeros((4, 2), dtype=torch.int64), "E", torch.int32, 0, cols=2)
+    with pytest.raises(ValueError):
+        ccd._require([1.0, 2.0], "V0", torch.float64, 0)

@@ -223,6 +223,21 @@ def test_order_schedule_rejects_non_permutation(ctx, bad):
     narrow_with(ctx, s, vf, ee, ("order", np.arange(n, dtype=np.int32)))
 
 
+@pytest.mark.parametrize("fill", [float("nan"), 1e30, -1e30, float("inf")])
+def test_learned_schedule_with_degenerate_predictions(ctx, fill):
+    """Parameters that make every prediction NaN, infinite or far out of range still give a permutation
+    (each pair searched exactly once) and the plain schedule's outputs."""
+    s = scenes.cloth_on_sphere(seed=7, n=32, sphere_subdivisions=2)
+    V0, V1, E, F = scene_dev(s)
+    vf, ee = ctx.broad(V0, V1, E, F)
+    vf, ee = vf.cpu().numpy(), ee.cpu().numpy()
+    params, norm = random_model(6)
+    params = np.full_like(params, fill)
+    plain = narrow_with(ctx, s, vf, ee, None)
+    for thr, mh in ((ccd.HEAVY_THRESHOLD, ccd.MAX_HEAVY), (-1e9, 4096), (0.0, 0)):
+        assert_identical(plain, narrow_with(ctx, s, vf, ee, ("learned", params, norm, thr, mh)))
+
+
 def test_learned_schedule_rejects_bad_early_share(ctx):
     s = scenes.tiny_random_scene(9, n_tris=12, extent=0.5, motion=1.0)
     vf, ee = oracle.broad(s.V0, s.V1, s.E, s.F)
