@@ -55,6 +55,11 @@ def _load():
     lib.oracle_levels_needed.argtypes = [ctypes.c_int, P, ctypes.c_double, P]
     lib.oracle_narrow.argtypes = [P, P, P, P, P, i64, P, i64, ctypes.c_double, i64, ctypes.c_int,
                                   P, P, P, P, P, P]
+    lib.oracle_narrow_ex.argtypes = [P, P, P, P, P, i64, P, i64, ctypes.c_double, i64, P, ctypes.c_int,
+                                     ctypes.c_int, P, P, P, P, P, P]
+    lib.oracle_narrow_global.argtypes = [P, P, P, P, P, i64, P, i64, ctypes.c_double, i64, P, ctypes.c_int,
+                                         P, P, P]
+    lib.oracle_initial_distance.argtypes = [P, P, P, P, i64, P, i64, P]
     _lib = lib
     return lib
 
@@ -159,11 +164,21 @@ def levels_needed(kind, q24, delta):
     return out
 
 
-def narrow_with_work(V0, V1, E, F, vf, ee, delta=1e-6, max_iter=10**6, nthreads=None):
+def _min_sep(ms, n):
+    if ms is None:
+        return None
+    ms = _c(ms, np.float64).reshape(-1)
+    if len(ms) != n or not np.all(np.isfinite(ms)) or np.any(ms < 0):
+        raise ValueError("ms must hold one finite, non-negative separation per pair")
+    return ms
+
+
+def narrow_with_work(V0, V1, E, F, vf, ee, delta=1e-6, max_iter=10**6, nthreads=None, ms=None, no_zero=False):
     """Per-pair (hit, toi, n_enq, n_eval, n_axis) and the global minimum TOI.
 
     n_axis counts the per-axis inclusion boxes the solver computed (its
-    arithmetic work)."""
+    arithmetic work).  ms: per-pair minimum separation (Sec. 7) or None;
+    no_zero: the no-zero-TOI strategy (App. B)."""
     lib = _load()
     V0, V1 = _c(V0, np.float64), _c(V1, np.float64)
     E, F = _c(E, np.int32).reshape(-1, 2), _c(F, np.int32).reshape(-1, 3)
@@ -176,16 +191,52 @@ def narrow_with_work(V0, V1, E, F, vf, ee, delta=1e-6, max_iter=10**6, nthreads=
     n_eval = np.zeros(n, np.int64)
     n_axis = np.zeros(n, np.int64)
     tmin = np.zeros(1, np.float64)
-    lib.oracle_narrow(_ptr(V0), _ptr(V1), _ptr(E), _ptr(F), _ptr(vf), len(vf), _ptr(ee), len(ee),
-                      float(delta), int(max_iter), nthreads or default_threads(),
-                      _ptr(hit), _ptr(toi), _ptr(n_enq), _ptr(n_eval), _ptr(n_axis), _ptr(tmin))
+    ms = _min_sep(ms, n)
+    lib.oracle_narrow_ex(_ptr(V0), _ptr(V1), _ptr(E), _ptr(F), _ptr(vf), len(vf), _ptr(ee), len(ee),
+                         float(delta), int(max_iter), _ptr(ms), int(bool(no_zero)), nthreads or default_threads(),
+                         _ptr(hit), _ptr(toi), _ptr(n_enq), _ptr(n_eval), _ptr(n_axis), _ptr(tmin))
     return hit, toi, n_enq, n_eval, n_axis, float(tmin[0])
 
 
-def narrow(V0, V1, E, F, vf, ee, delta=1e-6, max_iter=10**6, nthreads=None):
+def narrow(V0, V1, E, F, vf, ee, delta=1e-6, max_iter=10**6, nthreads=None, ms=None, no_zero=False):
     """Per-pair (hit uint8, toi float64, n_enq int64, n_eval int64) and the global minimum TOI."""
-    hit, toi, n_enq, n_eval, _, tmin = narrow_with_work(V0, V1, E, F, vf, ee, delta, max_iter, nthreads)
+    hit, toi, n_enq, n_eval, _, tmin = narrow_with_work(V0, V1, E, F, vf, ee, delta, max_iter, nthreads, ms,
+                                                        no_zero)
     return hit, toi, n_enq, n_eval, tmin
+
+
+def narrow_global(V0, V1, E, F, vf, ee, delta=1e-6, max_iter=10**6, order=None, ms=None, no_zero=False):
+    """Alg. 3 with one t* shared by all pairs, pairs taken one after another in `order` (default: index order).
+    Returns (t*, number of pairs whose search started)."""
+    lib = _load()
+    V0, V1 = _c(V0, np.float64), _c(V1, np.float64)
+    E, F = _c(E, np.int32).reshape(-1, 2), _c(F, np.int32).reshape(-1, 3)
+    vf = _c(vf, np.int32).reshape(-1, 2)
+    ee = _c(ee, np.int32).reshape(-1, 2)
+    n = len(vf) + len(ee)
+    if order is not None:
+        order = _c(order, np.int64).reshape(-1)
+        if len(order) != n or not np.array_equal(np.sort(order), np.arange(n)):
+            raise ValueError("order must be a permutation of the pair indices")
+    ms = _min_sep(ms, n)
+    tmin = np.zeros(1, np.float64)
+    nsr = np.zeros(1, np.int64)
+    lib.oracle_narrow_global(_ptr(V0), _ptr(V1), _ptr(E), _ptr(F), _ptr(vf), len(vf), _ptr(ee), len(ee),
+                             float(delta), int(max_iter), _ptr(ms), int(bool(no_zero)), _ptr(order), _ptr(tmin),
+                             _ptr(nsr))
+    return float(tmin[0]), int(nsr[0])
+
+
+def initial_distance(V0, E, F, vf, ee):
+    """Distance between the primitives of every pair at t = 0 (VF pairs first)."""
+    lib = _load()
+    V0 = _c(V0, np.float64)
+    E, F = _c(E, np.int32).reshape(-1, 2), _c(F, np.int32).reshape(-1, 3)
+    vf = _c(vf, np.int32).reshape(-1, 2)
+    ee = _c(ee, np.int32).reshape(-1, 2)
+    d0 = np.zeros(len(vf) + len(ee), np.float64)
+    lib.oracle_initial_distance(_ptr(V0), _ptr(E), _ptr(F), _ptr(vf), len(vf), _ptr(ee), len(ee), _ptr(d0))
+    return d0
 
 
 def all_pairs(E, F, nv):

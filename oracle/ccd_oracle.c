@@ -242,6 +242,7 @@ typedef struct {
     double x0[4][3], d[4][3]; /* start point and displacement x1 - x0 */
     double eps[3];            /* half-width of the tolerance box C_eps per axis */
     int m[3];                 /* levels after which dimension t,u,v is fine enough */
+    int no_zero;              /* App. B: an interval starting at t = 0 is always split */
 } query;
 
 /* Forward error bound of the evaluation sequence below, per axis a, with
@@ -281,6 +282,7 @@ static int levels_needed(double L, double delta)
 static void make_query(query *q, int kind, const double *q24, double delta)
 {
     q->kind = kind;
+    q->no_zero = 0;
     for (int k = 0; k < 4; k++)
         for (int a = 0; a < 3; a++) {
             q->x0[k][a] = q24[3 * k + a];
@@ -310,6 +312,17 @@ static void make_query(query *q, int kind, const double *q24, double delta)
     q->m[0] = levels_needed(Lt, delta);
     q->m[1] = levels_needed(Lu, delta);
     q->m[2] = levels_needed(Lv, delta);
+}
+
+/* Minimum separation (Sec. 7, avoiding a time of impact of zero): the
+ * tolerance box is enlarged by the separation ms on every axis, so that an
+ * interval whose F comes within ms of zero (in the max norm, which any
+ * Euclidean approach within ms also satisfies) is kept.  The sum is rounded
+ * one float up so that the enlarged box contains the exact eps + ms. */
+static void widen_eps(query *q, double ms)
+{
+    if (ms > 0.0)
+        for (int a = 0; a < 3; a++) q->eps[a] = nextafter(q->eps[a] + ms, INFINITY);
 }
 
 /* F on axis a at one corner (t, u, v), with the fixed operation sequence:
@@ -372,7 +385,10 @@ static int process_node(const query *q, const uint64_t n[3], const int l[3], dou
         if (!(bmin >= -q->eps[a] && bmax <= q->eps[a]))
             inside = 0;
     }
-    if (width < delta || inside)
+    /* App. B, no-zero-TOI strategy: an interval starting at t = 0 is split
+     * whatever its width; only the finest level stops it */
+    int at_zero = q->no_zero && n[0] == 0;
+    if ((width < delta || inside) && !at_zero)
         return NODE_ACCEPT;
     if (l[0] == ORACLE_MAX_LEVEL && l[1] == ORACLE_MAX_LEVEL && l[2] == ORACLE_MAX_LEVEL)
         return NODE_ACCEPT;
@@ -401,8 +417,14 @@ typedef struct { uint64_t n[3]; } node;
  * that the count below does not depend on processing order).  n_enq counts
  * the children kept over all levels; when it exceeds max_iter while the
  * frontier is not empty the query stops and reports a hit at the earliest
- * t-lower-bound still in the frontier, which is conservative. */
-static void solve_query(const query *q, double delta, int64_t max_iter,
+ * t-lower-bound still in the frontier, which is conservative.
+ *
+ * `bound` is a time of impact already known from other queries (+inf for a
+ * query on its own): with Alg. 3's single t* shared by all queries, the
+ * intervals that start at or after it are pruned too, and a query whose root
+ * starts there is not searched.  With the no-zero-TOI strategy (App. B) the
+ * cap is ignored while an interval starting at t = 0 is in the frontier. */
+static void solve_query(const query *q, double delta, int64_t max_iter, double bound,
                         uint8_t *hit, double *toi, int64_t *n_enq_out, int64_t *n_eval_out,
                         int64_t *n_axis_out, int32_t *levels_out)
 {
@@ -415,6 +437,7 @@ static void solve_query(const query *q, double delta, int64_t max_iter,
     double tstar = INFINITY;
     int64_t n_enq = 0, n_eval = 0, n_axis = 0;
     int capped = 0;
+    if (!(0.0 < bound)) nF = 0;
     while (nF > 0) {
         int64_t nS = 0;
         for (int64_t i = 0; i < nF; i++) {
@@ -444,11 +467,14 @@ static void solve_query(const query *q, double delta, int64_t max_iter,
                 node ch = S[i];
                 ch.n[k] = 2 * S[i].n[k] + c;
                 double tl = ldexp((double)ch.n[0], -l[0]);
-                if (tl < tstar) Fr[nF++] = ch;
+                if (tl < tstar && tl < bound) Fr[nF++] = ch;
             }
         }
         n_enq += nF;
-        if (n_enq > max_iter && nF > 0) { capped = 1; break; }
+        int zero_left = 0;
+        if (q->no_zero)
+            for (int64_t i = 0; i < nF; i++) zero_left |= Fr[i].n[0] == 0;
+        if (n_enq > max_iter && nF > 0 && !zero_left) { capped = 1; break; }
     }
     double t = tstar;
     if (capped) {
@@ -474,7 +500,7 @@ void oracle_query(int kind, const double *q24, double delta, int64_t max_iter,
 {
     query q;
     make_query(&q, kind, q24, delta);
-    solve_query(&q, delta, max_iter, hit, toi, n_enq, n_eval, NULL, NULL);
+    solve_query(&q, delta, max_iter, INFINITY, hit, toi, n_enq, n_eval, NULL, NULL);
 }
 
 /* The same query, also reporting the dyadic levels (t, u, v) of the last
@@ -485,7 +511,7 @@ void oracle_query_levels(int kind, const double *q24, double delta, int64_t max_
 {
     query q;
     make_query(&q, kind, q24, delta);
-    solve_query(&q, delta, max_iter, hit, toi, n_enq, NULL, NULL, levels);
+    solve_query(&q, delta, max_iter, INFINITY, hit, toi, n_enq, NULL, NULL, levels);
 }
 
 /* Internals exposed for the pins: F at one point, the tolerance box, the
@@ -527,12 +553,43 @@ typedef struct {
     int64_t n_vf, n_ee;
     double delta;
     int64_t max_iter;
+    const double *ms; /* per-pair minimum separation, or NULL */
+    int no_zero;
     uint8_t *hit;
     double *toi;
     int64_t *n_enq, *n_eval, *n_axis;
     int64_t next;
     pthread_mutex_t mu;
 } narrow_job;
+
+/* The 24 query doubles and the kind of pair i (VF pairs first). */
+static int pair_query(const narrow_job *j, int64_t i, double q24[24])
+{
+    int32_t ids[4];
+    int kind;
+    if (i < j->n_vf) {
+        const int32_t *pr = j->vf + 2 * i;
+        const int32_t *f = j->F + 3 * (int64_t)pr[1];
+        ids[0] = pr[0]; ids[1] = f[0]; ids[2] = f[1]; ids[3] = f[2];
+        kind = KIND_VF;
+    } else {
+        const int32_t *pr = j->ee + 2 * (i - j->n_vf);
+        const int32_t *e0 = j->E + 2 * (int64_t)pr[0], *e1 = j->E + 2 * (int64_t)pr[1];
+        ids[0] = e0[0]; ids[1] = e0[1]; ids[2] = e1[0]; ids[3] = e1[1];
+        kind = KIND_EE;
+    }
+    gather(j->V0, j->V1, ids, q24);
+    return kind;
+}
+
+static void job_query(const narrow_job *j, int64_t i, query *q)
+{
+    double q24[24];
+    int kind = pair_query(j, i, q24);
+    make_query(q, kind, q24, j->delta);
+    if (j->ms) widen_eps(q, j->ms[i]);
+    q->no_zero = j->no_zero;
+}
 
 static void *narrow_worker(void *arg)
 {
@@ -546,25 +603,10 @@ static void *narrow_worker(void *arg)
         if (b >= total) break;
         int64_t e = b + chunk < total ? b + chunk : total;
         for (int64_t i = b; i < e; i++) {
-            int32_t ids[4];
-            int kind;
-            if (i < j->n_vf) {
-                const int32_t *pr = j->vf + 2 * i;
-                const int32_t *f = j->F + 3 * (int64_t)pr[1];
-                ids[0] = pr[0]; ids[1] = f[0]; ids[2] = f[1]; ids[3] = f[2];
-                kind = KIND_VF;
-            } else {
-                const int32_t *pr = j->ee + 2 * (i - j->n_vf);
-                const int32_t *e0 = j->E + 2 * (int64_t)pr[0], *e1 = j->E + 2 * (int64_t)pr[1];
-                ids[0] = e0[0]; ids[1] = e0[1]; ids[2] = e1[0]; ids[3] = e1[1];
-                kind = KIND_EE;
-            }
-            double q24[24];
-            gather(j->V0, j->V1, ids, q24);
             query q;
-            make_query(&q, kind, q24, j->delta);
+            job_query(j, i, &q);
             int64_t ne_ = 0, nv_ = 0, na_ = 0;
-            solve_query(&q, j->delta, j->max_iter, &j->hit[i], &j->toi[i], &ne_, &nv_, &na_, NULL);
+            solve_query(&q, j->delta, j->max_iter, INFINITY, &j->hit[i], &j->toi[i], &ne_, &nv_, &na_, NULL);
             if (j->n_enq) j->n_enq[i] = ne_;
             if (j->n_eval) j->n_eval[i] = nv_;
             if (j->n_axis) j->n_axis[i] = na_;
@@ -579,16 +621,19 @@ static void *narrow_worker(void *arg)
  * n_enq / n_eval / n_axis (may be NULL) receive the per-pair count of enqueued
  * intervals, of evaluated intervals, and of per-axis inclusion boxes computed
  * (an interval discarded on its first axis computes one): the cost log of the
- * solver and the basis of its arithmetic count. */
-void oracle_narrow(const double *V0, const double *V1, const int32_t *E, const int32_t *F,
-                   const int32_t *vf, int64_t n_vf, const int32_t *ee, int64_t n_ee,
-                   double delta, int64_t max_iter, int nthreads,
-                   uint8_t *hit, double *toi, int64_t *n_enq, int64_t *n_eval, int64_t *n_axis,
-                   double *toi_min)
+ * solver and the basis of its arithmetic count.
+ * ms (may be NULL): per-pair minimum separation added to C_eps (Sec. 7);
+ * no_zero: the no-zero-TOI strategy of App. B. */
+void oracle_narrow_ex(const double *V0, const double *V1, const int32_t *E, const int32_t *F,
+                      const int32_t *vf, int64_t n_vf, const int32_t *ee, int64_t n_ee,
+                      double delta, int64_t max_iter, const double *ms, int no_zero, int nthreads,
+                      uint8_t *hit, double *toi, int64_t *n_enq, int64_t *n_eval, int64_t *n_axis,
+                      double *toi_min)
 {
     narrow_job j;
     j.V0 = V0; j.V1 = V1; j.E = E; j.F = F; j.vf = vf; j.ee = ee;
     j.n_vf = n_vf; j.n_ee = n_ee; j.delta = delta; j.max_iter = max_iter;
+    j.ms = ms; j.no_zero = no_zero;
     j.hit = hit; j.toi = toi; j.n_enq = n_enq; j.n_eval = n_eval; j.n_axis = n_axis; j.next = 0;
     pthread_mutex_init(&j.mu, NULL);
     if (nthreads < 1) nthreads = 1;
@@ -601,4 +646,145 @@ void oracle_narrow(const double *V0, const double *V1, const int32_t *E, const i
     for (int64_t i = 0; i < n_vf + n_ee; i++)
         if (toi[i] < m) m = toi[i];
     *toi_min = m;
+}
+
+void oracle_narrow(const double *V0, const double *V1, const int32_t *E, const int32_t *F,
+                   const int32_t *vf, int64_t n_vf, const int32_t *ee, int64_t n_ee,
+                   double delta, int64_t max_iter, int nthreads,
+                   uint8_t *hit, double *toi, int64_t *n_enq, int64_t *n_eval, int64_t *n_axis,
+                   double *toi_min)
+{
+    oracle_narrow_ex(V0, V1, E, F, vf, n_vf, ee, n_ee, delta, max_iter, NULL, 0, nthreads, hit, toi, n_enq,
+                     n_eval, n_axis, toi_min);
+}
+
+/* Alg. 3 as printed: one t* shared by every query.  The queries are taken one
+ * after another in `order` (a permutation of the pair indices; NULL = index
+ * order); each is searched with the t* of the queries before it as a bound
+ * (intervals starting at or after it are pruned, and so is a query's root),
+ * and its own time of impact lowers t*.  *toi_min receives the final t*.
+ * *n_searched (may be NULL) receives the number of queries whose root was
+ * searched at all. */
+void oracle_narrow_global(const double *V0, const double *V1, const int32_t *E, const int32_t *F,
+                          const int32_t *vf, int64_t n_vf, const int32_t *ee, int64_t n_ee,
+                          double delta, int64_t max_iter, const double *ms, int no_zero,
+                          const int64_t *order, double *toi_min, int64_t *n_searched)
+{
+    narrow_job j;
+    memset(&j, 0, sizeof j);
+    j.V0 = V0; j.V1 = V1; j.E = E; j.F = F; j.vf = vf; j.ee = ee;
+    j.n_vf = n_vf; j.n_ee = n_ee; j.delta = delta; j.max_iter = max_iter;
+    j.ms = ms; j.no_zero = no_zero;
+    double tstar = INFINITY;
+    int64_t searched = 0;
+    for (int64_t r = 0; r < n_vf + n_ee; r++) {
+        int64_t i = order ? order[r] : r;
+        if (!(0.0 < tstar)) break;
+        query q;
+        job_query(&j, i, &q);
+        uint8_t h = 0;
+        double t = INFINITY;
+        solve_query(&q, delta, max_iter, tstar, &h, &t, NULL, NULL, NULL, NULL);
+        searched++;
+        if (h && t < tstar) tstar = t;
+    }
+    *toi_min = tstar;
+    if (n_searched) *n_searched = searched;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Initial distance d0 between the primitives of a pair at t = 0 (Sec. 7:    */
+/* the minimum separation is chosen relative to it).  The plain definition: */
+/* the smallest Euclidean distance between the closed point and triangle,   */
+/* or between the two closed segments.                                       */
+/* ------------------------------------------------------------------------ */
+static double dot3(const double a[3], const double b[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+static void sub3(const double a[3], const double b[3], double r[3])
+{
+    for (int k = 0; k < 3; k++) r[k] = a[k] - b[k];
+}
+
+/* distance from p to the closed segment [a, b] */
+static double point_segment(const double p[3], const double a[3], const double b[3])
+{
+    double ab[3], ap[3], r[3];
+    sub3(b, a, ab);
+    sub3(p, a, ap);
+    double L = dot3(ab, ab), s = 0.0;
+    if (L > 0.0) {
+        s = dot3(ap, ab) / L;
+        if (s < 0.0) s = 0.0;
+        if (s > 1.0) s = 1.0;
+    }
+    for (int k = 0; k < 3; k++) r[k] = ap[k] - s * ab[k];
+    return sqrt(dot3(r, r));
+}
+
+/* distance from p to the closed triangle (a, b, c): the distance to its
+ * plane when the projection of p lies inside it, else the nearest edge */
+static double point_triangle(const double p[3], const double a[3], const double b[3], const double c[3])
+{
+    double e0[3], e1[3], ap[3];
+    sub3(b, a, e0);
+    sub3(c, a, e1);
+    sub3(p, a, ap);
+    double d00 = dot3(e0, e0), d01 = dot3(e0, e1), d11 = dot3(e1, e1);
+    double d20 = dot3(ap, e0), d21 = dot3(ap, e1);
+    double den = d00 * d11 - d01 * d01;
+    if (den > 0.0) {
+        double u = (d11 * d20 - d01 * d21) / den, v = (d00 * d21 - d01 * d20) / den;
+        if (u >= 0.0 && v >= 0.0 && u + v <= 1.0) {
+            double r[3];
+            for (int k = 0; k < 3; k++) r[k] = ap[k] - u * e0[k] - v * e1[k];
+            return sqrt(dot3(r, r));
+        }
+    }
+    double d = point_segment(p, a, b), x = point_segment(p, b, c), y = point_segment(p, a, c);
+    if (x < d) d = x;
+    if (y < d) d = y;
+    return d;
+}
+
+/* distance between the closed segments [a0, a1] and [b0, b1]: the interior
+ * critical point of |a(s) - b(r)| when it lies in the unit square, else the
+ * best endpoint-to-segment distance (the boundary of the square) */
+static double segment_segment(const double a0[3], const double a1[3], const double b0[3], const double b1[3])
+{
+    double da[3], db[3], w[3];
+    sub3(a1, a0, da);
+    sub3(b1, b0, db);
+    sub3(a0, b0, w);
+    double A = dot3(da, da), B = dot3(da, db), C = dot3(db, db), D = dot3(da, w), E = dot3(db, w);
+    double den = A * C - B * B;
+    double best = point_segment(a0, b0, b1), x;
+    if ((x = point_segment(a1, b0, b1)) < best) best = x;
+    if ((x = point_segment(b0, a0, a1)) < best) best = x;
+    if ((x = point_segment(b1, a0, a1)) < best) best = x;
+    if (den > 0.0) {
+        double s = (B * E - C * D) / den, r = (A * E - B * D) / den;
+        if (s >= 0.0 && s <= 1.0 && r >= 0.0 && r <= 1.0) {
+            double d[3];
+            for (int k = 0; k < 3; k++) d[k] = w[k] + s * da[k] - r * db[k];
+            x = sqrt(dot3(d, d));
+            if (x < best) best = x;
+        }
+    }
+    return best;
+}
+
+/* d0 of every pair (VF first) from the positions at t = 0. */
+void oracle_initial_distance(const double *V0, const int32_t *E, const int32_t *F,
+                             const int32_t *vf, int64_t n_vf, const int32_t *ee, int64_t n_ee, double *d0)
+{
+    for (int64_t i = 0; i < n_vf; i++) {
+        const int32_t *f = F + 3 * (int64_t)vf[2 * i + 1];
+        d0[i] = point_triangle(V0 + 3 * (int64_t)vf[2 * i], V0 + 3 * (int64_t)f[0], V0 + 3 * (int64_t)f[1],
+                               V0 + 3 * (int64_t)f[2]);
+    }
+    for (int64_t i = 0; i < n_ee; i++) {
+        const int32_t *e = E + 2 * (int64_t)ee[2 * i], *g = E + 2 * (int64_t)ee[2 * i + 1];
+        d0[n_vf + i] = segment_segment(V0 + 3 * (int64_t)e[0], V0 + 3 * (int64_t)e[1], V0 + 3 * (int64_t)g[0],
+                                       V0 + 3 * (int64_t)g[1]);
+    }
 }
