@@ -145,16 +145,22 @@ ccd_status ccd_narrow(ccd_context *ctx, const double *V0, const double *V1, int6
 #define CCD_NUM_FEATURES 16
 #define CCD_MODEL_PARAMS 5313
 
-enum { CCD_SCHED_PLAIN = 0, CCD_SCHED_LEARNED = 1, CCD_SCHED_ORDER = 2 };
+enum { CCD_SCHED_PLAIN = 0, CCD_SCHED_LEARNED = 1, CCD_SCHED_ORDER = 2, CCD_SCHED_COST = 3 };
 
+/* CCD_SCHED_COST places the pairs exactly as LEARNED does, from costs the
+ * caller gives instead of the network's predictions: with the plain solver's
+ * own log2(1 + n_enq) it is the schedule a perfect model would give, with
+ * random values a random one (the references a learned schedule is judged
+ * against).  ccd_detect rejects it (the pairs are not known before the call). */
 typedef struct {
-    int kind;              /* CCD_SCHED_PLAIN, CCD_SCHED_LEARNED or CCD_SCHED_ORDER */
+    int kind;              /* CCD_SCHED_PLAIN, CCD_SCHED_LEARNED, CCD_SCHED_ORDER or CCD_SCHED_COST */
     const float *params;   /* LEARNED: device, CCD_MODEL_PARAMS floats */
     const float *norm;     /* LEARNED: device, 2 * CCD_NUM_FEATURES floats */
     const int32_t *order;  /* ORDER: device permutation of [0, n_vf + n_ee): search order */
-    float heavy_threshold; /* LEARNED: predicted log2(1 + n_enq) from which a pair starts in the wide stage */
-    int32_t max_heavy;     /* LEARNED: at most this many such pairs (0: none); they run on up to
+    float heavy_threshold; /* LEARNED, COST: predicted log2(1 + n_enq) from which a pair starts in the wide stage */
+    int32_t max_heavy;     /* LEARNED, COST: at most this many such pairs (0: none); they run on up to
                               tuning.heavy_slots workgroups */
+    const float *cost;     /* COST: device, one float per pair (VF pairs first), log2(1 + n_enq) scale */
 } ccd_schedule;
 
 /* ccd_narrow with a schedule (NULL = plain: pairs in index order).  Same
@@ -190,6 +196,98 @@ ccd_status ccd_detect(ccd_context *ctx, const double *V0, const double *V1, int6
                       int64_t *n_ee, double delta, int64_t max_iter,
                       uint8_t *hit, double *toi, double *toi_min, int64_t *n_enq,
                       const ccd_schedule *sched, void *stream);
+
+/*
+ * Options of the narrow phase beyond the per-pair search (NULL = all off).
+ *
+ *   earliest_only  1: Alg. 3 as printed -- one t* shared by all pairs
+ *                  (Sec. 5.3 and its discussion of the atomicMin on t*).  The
+ *                  call's earliest time so far prunes the intervals of every
+ *                  pair as soon as it drops, so after the first hits most
+ *                  intervals are never evaluated.  Only toi_min is defined;
+ *                  hit, toi and n_enq are unspecified (partly written).
+ *                  toi_min is never below the per-pair mode's and never above
+ *                  the time of any pair that does not reach max_iter; it equals
+ *                  the per-pair mode's whenever the earliest pair there did not
+ *                  reach max_iter.
+ *   no_zero_toi    1: the no-zero-TOI strategy of App. B -- an interval
+ *                  starting at t = 0 is split whatever its width (only the
+ *                  finest dyadic level stops it), and max_iter does not stop
+ *                  a pair while such an interval is left.
+ *   min_sep        DEVICE, one float64 per pair (VF pairs first), or NULL:
+ *                  minimum separation ms >= 0 (Sec. 7): C_eps is enlarged by ms
+ *                  on every axis (the sum rounded one double up), so that
+ *                  pairs coming within ms of each other (in the max norm) are
+ *                  reported.  ccd_detect_ex rejects it (the pairs are not
+ *                  known before the call); use min_sep_d0_factor there.
+ *   min_sep_d0_factor  >= 0: when > 0 (and min_sep is NULL) each pair's
+ *                  minimum separation is this factor times d0, the Euclidean
+ *                  distance between the pair's primitives at t = 0 (Sec. 7
+ *                  uses 0.2), computed on the device.
+ *
+ * Errors: CCD_ERR_INVALID_ARG for a flag other than 0 or 1, a negative or
+ * non-finite factor, both min_sep and a factor, or a min_sep value that is
+ * negative, not finite or above 2^960.
+ */
+typedef struct {
+    int32_t earliest_only;
+    int32_t no_zero_toi;
+    const double *min_sep;
+    double min_sep_d0_factor;
+} ccd_narrow_options;
+
+/* ccd_narrow_sched with options (NULL = none): same arguments, outputs and
+ * errors otherwise. */
+ccd_status ccd_narrow_ex(ccd_context *ctx, const double *V0, const double *V1, int64_t nv,
+                         const int32_t *E, int64_t ne, const int32_t *F, int64_t nf,
+                         const int32_t *vf, int64_t n_vf, const int32_t *ee, int64_t n_ee,
+                         double delta, int64_t max_iter,
+                         uint8_t *hit, double *toi, double *toi_min, int64_t *n_enq,
+                         const ccd_schedule *sched, const ccd_narrow_options *opts, void *stream);
+
+/* ccd_detect with options for its narrow phase (NULL = none; min_sep must be
+ * NULL, min_sep_d0_factor may be set). */
+ccd_status ccd_detect_ex(ccd_context *ctx, const double *V0, const double *V1, int64_t nv,
+                         const int32_t *E, int64_t ne, const int32_t *F, int64_t nf,
+                         int32_t *vf, int64_t vf_cap, int64_t *n_vf, int32_t *ee, int64_t ee_cap,
+                         int64_t *n_ee, double delta, int64_t max_iter,
+                         uint8_t *hit, double *toi, double *toi_min, int64_t *n_enq,
+                         const ccd_schedule *sched, const ccd_narrow_options *opts, void *stream);
+
+/* d0 of every pair (Sec. 7: the minimum separation is chosen relative to
+ * it): the Euclidean distance at t = 0 between the vertex and the closed
+ * triangle (VF) or between the two closed segments (EE), from V0.  d0 is a
+ * DEVICE (n_vf + n_ee) float64 output, VF pairs first.  The point-triangle
+ * distance projects onto the triangle's plane with barycentric coordinates
+ * when the projection lies inside, else takes the nearest edge; the segment
+ * distance takes the interior critical point when it lies in both segments,
+ * else the nearest endpoint-to-segment distance.  Errors: CCD_ERR_INVALID_ARG
+ * (index out of range).  Synchronizes `stream`. */
+ccd_status ccd_initial_distance(ccd_context *ctx, const double *V0, int64_t nv, const int32_t *E, int64_t ne,
+                                const int32_t *F, int64_t nf, const int32_t *vf, int64_t n_vf,
+                                const int32_t *ee, int64_t n_ee, double *d0, void *stream);
+
+/*
+ * One step size for a simulator that must never reach contact (App. B, the
+ * strategy used with IPC):
+ *   1. broad phase, then the narrow phase with Alg. 3's single t*
+ *      (earliest_only) and each pair's minimum separation ms_factor * d0;
+ *   2. if that t* is 0, the narrow phase again on the same pairs with no
+ *      minimum separation and the no-zero-TOI strategy, and its t*
+ *      multiplied by `scale` (App. B uses 0.8) so that the step ends short of
+ *      touching.
+ * *toi (HOST) receives the result, +inf when no pair collides; *rerun (HOST,
+ * may be NULL) is 1 when step 2 ran.  vf / ee (DEVICE, capacities vf_cap and
+ * ee_cap) receive the candidate pairs, *n_vf / *n_ee their counts; the
+ * per-pair buffers the narrow phase needs are the library's.
+ * Errors: as ccd_detect; CCD_ERR_INVALID_ARG for ms_factor < 0 or a scale
+ * outside (0, 1].  Synchronizes `stream`.
+ */
+ccd_status ccd_toi_step(ccd_context *ctx, const double *V0, const double *V1, int64_t nv,
+                        const int32_t *E, int64_t ne, const int32_t *F, int64_t nf,
+                        int32_t *vf, int64_t vf_cap, int64_t *n_vf, int32_t *ee, int64_t ee_cap, int64_t *n_ee,
+                        double delta, int64_t max_iter, double ms_factor, double scale,
+                        double *toi, int32_t *rerun, void *stream);
 
 /* Scheduling features of every pair: feat is a DEVICE (n_vf + n_ee) x
  * CCD_NUM_FEATURES float32 array, VF pairs first (zeros for a pair with an
@@ -231,7 +329,8 @@ typedef struct {
     double narrow_heavy_ms; /* workgroup-per-pair search of handed-over pairs (first round) */
     int64_t sort_axis;      /* axis the last broad phase swept along */
     int64_t heavy_pairs;    /* pairs the last narrow phase passed to the wide stage */
-    int64_t heavy_reruns;   /* pairs re-run with a larger frontier buffer */
+    int64_t heavy_reruns;   /* wide-stage pairs whose frontier outgrew its buffer, resumed from the
+                               level they reached with larger buffers */
     int64_t sched_heavy_pairs; /* pairs the learned schedule started in the wide stage */
     double batch_ms;        /* last ccd_batch_run pass (graph launch or eager kernels) */
 } ccd_stats;
@@ -246,8 +345,10 @@ ccd_status ccd_get_stats(ccd_context *ctx, ccd_stats *out);
  *                       unit, 0 = as many as fit (default)
  *   heavy_slots         workgroups of the wide stage (default 1024)
  *   heavy_cap_log2      log2 of each wide-stage frontier buffer in intervals
- *                       (default 13); a frontier that outgrows it is re-run
- *                       with 8x larger buffers
+ *                       (default 13); a pair whose frontier outgrows it saves
+ *                       the level it is on and resumes from there, after the
+ *                       first round, on buffers sized for max_iter + 1
+ *                       intervals as far as device memory allows
  *   heavy_lds           1: wide-stage frontiers of at most 2 heavy_block
  *                       intervals stay in LDS between levels (default 1)
  *   heavy_block         threads per wide-stage pair, 64, 256 or 1024, or 0

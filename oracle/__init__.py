@@ -47,6 +47,8 @@ def _load():
     lib.oracle_broad.argtypes = [P, P, i64, P, i64, P, i64, ctypes.c_int,
                                  ctypes.POINTER(ctypes.POINTER(ctypes.c_int32)), ctypes.POINTER(i64),
                                  ctypes.POINTER(ctypes.POINTER(ctypes.c_int32)), ctypes.POINTER(i64)]
+    lib.oracle_broad_sample.argtypes = [P, P, i64, P, i64, P, i64, ctypes.c_int, i64, ctypes.POINTER(i64),
+                                        ctypes.POINTER(i64), P]
     lib.oracle_free.argtypes = [P]
     lib.oracle_query.argtypes = [ctypes.c_int, P, ctypes.c_double, i64, P, P, P, P]
     lib.oracle_query_levels.argtypes = [ctypes.c_int, P, ctypes.c_double, i64, P, P, P, P]
@@ -113,6 +115,20 @@ def broad(V0, V1, E, F, nthreads=None):
     lib.oracle_free(ctypes.cast(pvf, ctypes.c_void_p))
     lib.oracle_free(ctypes.cast(pee, ctypes.c_void_p))
     return vf, ee
+
+
+def broad_sample(V0, V1, E, F, stride, nthreads=None):
+    """Timing sample of `broad`: the brute force over 1 / stride of its rows.  Returns
+    (VF pairs found, EE pairs found, VF box tests, EE box tests)."""
+    lib = _load()
+    V0, V1 = _c(V0, np.float64), _c(V1, np.float64)
+    E, F = _c(E, np.int32).reshape(-1, 2), _c(F, np.int32).reshape(-1, 3)
+    nvf, nee = ctypes.c_int64(), ctypes.c_int64()
+    tests = np.zeros(2, np.float64)
+    lib.oracle_broad_sample(_ptr(V0), _ptr(V1), len(V0), _ptr(E), len(E), _ptr(F), len(F),
+                            nthreads or default_threads(), int(stride), ctypes.byref(nvf), ctypes.byref(nee),
+                            _ptr(tests))
+    return nvf.value, nee.value, float(tests[0]), float(tests[1])
 
 
 def query(kind, q24, delta=1e-6, max_iter=10**6):

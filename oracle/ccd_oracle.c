@@ -162,13 +162,15 @@ static void *broad_worker(void *arg)
     return NULL;
 }
 
+/* stride > 1 (timing samples only): of nthreads * 16 * stride row blocks,
+ * only every stride-th is run; *tests receives the box tests made. */
 static void run_broad(const float *lo, const float *hi, int64_t nv, int64_t ne, int64_t nf,
-                      const int32_t *E, const int32_t *F, int kind, int nthreads,
-                      int32_t **out, int64_t *n_out)
+                      const int32_t *E, const int32_t *F, int kind, int nthreads, int64_t stride,
+                      int32_t **out, int64_t *n_out, double *tests)
 {
     int64_t rows = kind == 0 ? nv : ne;
     /* Many more blocks than threads so the triangular EE work balances. */
-    int64_t nblocks = (int64_t)nthreads * 16;
+    int64_t nblocks = (int64_t)nthreads * 16 * stride;
     if (nblocks > rows) nblocks = rows > 0 ? rows : 1;
     broad_job *jobs = (broad_job *)calloc((size_t)nblocks, sizeof(broad_job));
     for (int64_t b = 0; b < nblocks; b++) {
@@ -185,6 +187,15 @@ static void run_broad(const float *lo, const float *hi, int64_t nv, int64_t ne, 
             jobs[b].row_begin = rows * b / nblocks;
             jobs[b].row_end = rows * (b + 1) / nblocks;
         }
+    }
+    if (stride > 1)
+        for (int64_t b = 0; b < nblocks; b++)
+            if (b % stride) jobs[b].row_end = jobs[b].row_begin;
+    if (tests) {
+        *tests = 0.0;
+        for (int64_t b = 0; b < nblocks; b++)
+            for (int64_t r = jobs[b].row_begin; r < jobs[b].row_end; r++)
+                *tests += kind == 0 ? (double)nf : (double)(ne - 1 - r);
     }
     /* static round-robin of blocks over threads */
     for (int64_t base = 0; base < nblocks; base += nthreads) {
@@ -222,8 +233,31 @@ void oracle_broad(const double *V0, const double *V1, int64_t nv,
     if (nthreads < 1) nthreads = 1;
     if (nthreads > 256) nthreads = 256;
     oracle_boxes(V0, V1, nv, E, ne, F, nf, lo, hi);
-    run_broad(lo, hi, nv, ne, nf, E, F, 0, nthreads, vf, n_vf);
-    run_broad(lo, hi, nv, ne, nf, E, F, 1, nthreads, ee, n_ee);
+    run_broad(lo, hi, nv, ne, nf, E, F, 0, nthreads, 1, vf, n_vf, NULL);
+    run_broad(lo, hi, nv, ne, nf, E, F, 1, nthreads, 1, ee, n_ee, NULL);
+    free(lo);
+    free(hi);
+}
+
+/* A timing sample of oracle_broad: the same brute force over 1 / stride of
+ * the rows (every stride-th block of rows, VF and EE), with the pairs found
+ * and box tests made in them; tests[0] VF, tests[1] EE. */
+void oracle_broad_sample(const double *V0, const double *V1, int64_t nv,
+                         const int32_t *E, int64_t ne, const int32_t *F, int64_t nf, int nthreads,
+                         int64_t stride, int64_t *n_vf, int64_t *n_ee, double tests[2])
+{
+    int64_t nb = nv + ne + nf;
+    float *lo = (float *)malloc((size_t)(nb > 0 ? nb : 1) * 3 * sizeof(float));
+    float *hi = (float *)malloc((size_t)(nb > 0 ? nb : 1) * 3 * sizeof(float));
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > 256) nthreads = 256;
+    if (stride < 1) stride = 1;
+    int32_t *vf = NULL, *ee = NULL;
+    oracle_boxes(V0, V1, nv, E, ne, F, nf, lo, hi);
+    run_broad(lo, hi, nv, ne, nf, E, F, 0, nthreads, stride, &vf, n_vf, &tests[0]);
+    run_broad(lo, hi, nv, ne, nf, E, F, 1, nthreads, stride, &ee, n_ee, &tests[1]);
+    free(vf);
+    free(ee);
     free(lo);
     free(hi);
 }

@@ -31,12 +31,13 @@ _STATUS_NAMES = {
 EXPORTED = ["ccd_create", "ccd_destroy", "ccd_last_error", "ccd_version", "ccd_broad", "ccd_narrow",
             "ccd_narrow_sched", "ccd_detect", "ccd_features", "ccd_mlp_predict", "ccd_mlp_grad", "ccd_adam_step",
             "ccd_get_stats", "ccd_set_tuning", "ccd_get_tuning", "ccd_batch_create", "ccd_batch_destroy",
-            "ccd_batch_run", "ccd_batch_autotune"]
+            "ccd_batch_run", "ccd_batch_autotune", "ccd_narrow_ex", "ccd_detect_ex", "ccd_initial_distance",
+            "ccd_toi_step"]
 
 NUM_FEATURES = 16
 HIDDEN = 64
 MODEL_PARAMS = NUM_FEATURES * HIDDEN + HIDDEN + HIDDEN * HIDDEN + HIDDEN + HIDDEN + 1
-SCHED_PLAIN, SCHED_LEARNED, SCHED_ORDER = 0, 1, 2
+SCHED_PLAIN, SCHED_LEARNED, SCHED_ORDER, SCHED_COST = 0, 1, 2, 3
 
 
 class CCDError(RuntimeError):
@@ -64,7 +65,13 @@ class Tuning(ctypes.Structure):
 
 class Schedule(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("params", ctypes.c_void_p), ("norm", ctypes.c_void_p),
-                ("order", ctypes.c_void_p), ("heavy_threshold", ctypes.c_float), ("max_heavy", ctypes.c_int32)]
+                ("order", ctypes.c_void_p), ("heavy_threshold", ctypes.c_float), ("max_heavy", ctypes.c_int32),
+                ("cost", ctypes.c_void_p)]
+
+
+class NarrowOptions(ctypes.Structure):
+    _fields_ = [("earliest_only", ctypes.c_int32), ("no_zero_toi", ctypes.c_int32), ("min_sep", ctypes.c_void_p),
+                ("min_sep_d0_factor", ctypes.c_double)]
 
 
 # Learned schedule defaults: predictions of log2(1 + n_enq) from which a pair starts in the wide stage, and
@@ -132,6 +139,19 @@ def load_library(path=LIB_PATH):
     lib.ccd_batch_autotune.argtypes = [P, P, P, P, P, ctypes.c_double, i64, P, P, P, P, P, ctypes.c_char_p,
                                        ctypes.POINTER(Tuning), P]
     lib.ccd_batch_autotune.restype = ctypes.c_int
+    lib.ccd_narrow_ex.argtypes = [P, P, P, i64, P, i64, P, i64, P, i64, P, i64, ctypes.c_double, i64,
+                                  P, P, P, P, ctypes.POINTER(Schedule), ctypes.POINTER(NarrowOptions), P]
+    lib.ccd_narrow_ex.restype = ctypes.c_int
+    lib.ccd_detect_ex.argtypes = [P, P, P, i64, P, i64, P, i64, P, i64, ctypes.POINTER(i64), P, i64,
+                                  ctypes.POINTER(i64), ctypes.c_double, i64, P, P, P, P, ctypes.POINTER(Schedule),
+                                  ctypes.POINTER(NarrowOptions), P]
+    lib.ccd_detect_ex.restype = ctypes.c_int
+    lib.ccd_initial_distance.argtypes = [P, P, i64, P, i64, P, i64, P, i64, P, i64, P, P]
+    lib.ccd_initial_distance.restype = ctypes.c_int
+    lib.ccd_toi_step.argtypes = [P, P, P, i64, P, i64, P, i64, P, i64, ctypes.POINTER(i64), P, i64,
+                                 ctypes.POINTER(i64), ctypes.c_double, i64, ctypes.c_double, ctypes.c_double,
+                                 ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32), P]
+    lib.ccd_toi_step.restype = ctypes.c_int
     lib.ccd_get_stats.argtypes = [P, ctypes.POINTER(Stats)]
     lib.ccd_get_stats.restype = ctypes.c_int
     _lib = lib
@@ -281,12 +301,13 @@ class Context:
         return n_vf.value, n_ee.value
 
     def narrow(self, V0, V1, E, F, vf, ee, delta=1e-6, max_iter=10**6, with_costs=False, out=None, stream=None,
-               schedule=None):
+               schedule=None, options=None):
         """Per-pair (hit uint8, toi float64, toi_min (1,) float64, n_enq int64 or None), VF pairs first.
 
-        schedule: None (plain: pairs in index order), ("learned", params, norm[, heavy_threshold, max_heavy])
-        or ("order", perm) -- where and in which order pairs are searched; the results are the same for every
-        schedule."""
+        schedule: None (plain: pairs in index order), ("learned", params, norm[, heavy_threshold, max_heavy]),
+        ("cost", per-pair costs[, heavy_threshold, max_heavy]) or ("order", perm) -- where and in which order
+        pairs are searched; the results are the same for every schedule.  options: None or a dict with earliest_only, no_zero_toi, min_sep (a CUDA float64 tensor,
+        one per pair) and min_sep_d0_factor (see ccd_narrow_options)."""
         import torch
         lib = load_library()
         V0 = _dev(V0, torch.float64, 3)
@@ -308,12 +329,24 @@ class Context:
             _require(tmin, "toi_min", torch.float64, self.device, min_numel=1)
             if nenq is not None:
                 _require(nenq, "n_enq", torch.int64, self.device, min_numel=n)
+        if options is not None:
+            opt, okeep = _options(options, self.device, n)
+            sch, keep = _schedule(schedule) if schedule is not None else (None, None)
+            _check_schedule_len(sch, keep, n)
+            _check(lib.ccd_narrow_ex(self._h, _ptr(V0), _ptr(V1), V0.shape[0], _ptr(E), E.shape[0], _ptr(F),
+                                     F.shape[0], _ptr(vf), vf.shape[0], _ptr(ee), ee.shape[0], float(delta),
+                                     int(max_iter), _ptr(hit), _ptr(toi), _ptr(tmin), _ptr(nenq),
+                                     ctypes.byref(sch) if sch is not None else None, ctypes.byref(opt),
+                                     _stream(stream)))
+            del keep, okeep
+            return hit, toi, tmin, nenq
         if schedule is None:
             _check(lib.ccd_narrow(self._h, _ptr(V0), _ptr(V1), V0.shape[0], _ptr(E), E.shape[0], _ptr(F),
                                   F.shape[0], _ptr(vf), vf.shape[0], _ptr(ee), ee.shape[0], float(delta),
                                   int(max_iter), _ptr(hit), _ptr(toi), _ptr(tmin), _ptr(nenq), _stream(stream)))
             return hit, toi, tmin, nenq
         sch, keep = _schedule(schedule)
+        _check_schedule_len(sch, keep, n)
         _check(lib.ccd_narrow_sched(self._h, _ptr(V0), _ptr(V1), V0.shape[0], _ptr(E), E.shape[0], _ptr(F),
                                     F.shape[0], _ptr(vf), vf.shape[0], _ptr(ee), ee.shape[0], float(delta),
                                     int(max_iter), _ptr(hit), _ptr(toi), _ptr(tmin), _ptr(nenq),
@@ -322,7 +355,7 @@ class Context:
         return hit, toi, tmin, nenq
 
     def detect_into(self, V0, V1, E, F, vf, ee, hit, toi, tmin, nenq=None, delta=1e-6, max_iter=10**6,
-                    schedule=None, stream=None):
+                    schedule=None, stream=None, options=None):
         """Broad and narrow phase in one call (one wait for the device, at the end).
 
         Pairs go into the preallocated vf (cap, 2) and ee (cap, 2); hit, toi and nenq (optional) hold
@@ -343,12 +376,55 @@ class Context:
         n_vf = ctypes.c_int64()
         n_ee = ctypes.c_int64()
         sch, keep = _schedule(schedule) if schedule is not None else (None, None)
-        _check(lib.ccd_detect(self._h, _ptr(V0), _ptr(V1), V0.shape[0], _ptr(E), E.shape[0], _ptr(F), F.shape[0],
-                              _ptr(vf), vf.shape[0], ctypes.byref(n_vf), _ptr(ee), ee.shape[0], ctypes.byref(n_ee),
-                              float(delta), int(max_iter), _ptr(hit), _ptr(toi), _ptr(tmin), _ptr(nenq),
-                              ctypes.byref(sch) if sch is not None else None, _stream(stream)))
+        if options is not None:
+            if isinstance(options, dict) and options.get("min_sep") is not None:
+                raise ValueError("detect takes min_sep_d0_factor, not per-pair min_sep (pairs are not known yet)")
+            opt, okeep = _options(options, self.device, 0)
+            _check(lib.ccd_detect_ex(self._h, _ptr(V0), _ptr(V1), V0.shape[0], _ptr(E), E.shape[0], _ptr(F),
+                                     F.shape[0], _ptr(vf), vf.shape[0], ctypes.byref(n_vf), _ptr(ee), ee.shape[0],
+                                     ctypes.byref(n_ee), float(delta), int(max_iter), _ptr(hit), _ptr(toi),
+                                     _ptr(tmin), _ptr(nenq), ctypes.byref(sch) if sch is not None else None,
+                                     ctypes.byref(opt), _stream(stream)))
+            del okeep
+        else:
+            _check(lib.ccd_detect(self._h, _ptr(V0), _ptr(V1), V0.shape[0], _ptr(E), E.shape[0], _ptr(F),
+                                  F.shape[0], _ptr(vf), vf.shape[0], ctypes.byref(n_vf), _ptr(ee), ee.shape[0],
+                                  ctypes.byref(n_ee), float(delta), int(max_iter), _ptr(hit), _ptr(toi), _ptr(tmin),
+                                  _ptr(nenq), ctypes.byref(sch) if sch is not None else None, _stream(stream)))
         del keep
         return n_vf.value, n_ee.value
+
+    def initial_distance(self, V0, E, F, vf, ee, stream=None):
+        """d0 of every pair (distance of its primitives at t = 0), float64 on the device, VF pairs first."""
+        import torch
+        lib = load_library()
+        V0 = _dev(V0, torch.float64, 3)
+        E = _dev(E, torch.int32, 2)
+        F = _dev(F, torch.int32, 3)
+        vf = _dev(vf, torch.int32, 2)
+        ee = _dev(ee, torch.int32, 2)
+        d0 = torch.empty(vf.shape[0] + ee.shape[0], dtype=torch.float64, device=V0.device)
+        _check(lib.ccd_initial_distance(self._h, _ptr(V0), V0.shape[0], _ptr(E), E.shape[0], _ptr(F), F.shape[0],
+                                        _ptr(vf), vf.shape[0], _ptr(ee), ee.shape[0], _ptr(d0), _stream(stream)))
+        return d0
+
+    def toi_step(self, V0, V1, E, F, vf, ee, delta=1e-6, max_iter=10**6, ms_factor=0.2, scale=0.8, stream=None):
+        """App. B's step size: (toi, rerun, n_vf, n_ee).  vf / ee are preallocated (cap, 2) int32 outputs."""
+        import torch
+        lib = load_library()
+        _require(V0, "V0", torch.float64, self.device, cols=3)
+        _require(V1, "V1", torch.float64, self.device, cols=3, rows=V0.shape[0])
+        _require(E, "E", torch.int32, self.device, cols=2)
+        _require(F, "F", torch.int32, self.device, cols=3)
+        _require(vf, "vf", torch.int32, self.device, cols=2)
+        _require(ee, "ee", torch.int32, self.device, cols=2)
+        n_vf, n_ee = ctypes.c_int64(), ctypes.c_int64()
+        t, rr = ctypes.c_double(), ctypes.c_int32()
+        _check(lib.ccd_toi_step(self._h, _ptr(V0), _ptr(V1), V0.shape[0], _ptr(E), E.shape[0], _ptr(F), F.shape[0],
+                                _ptr(vf), vf.shape[0], ctypes.byref(n_vf), _ptr(ee), ee.shape[0], ctypes.byref(n_ee),
+                                float(delta), int(max_iter), float(ms_factor), float(scale), ctypes.byref(t),
+                                ctypes.byref(rr), _stream(stream)))
+        return t.value, bool(rr.value), n_vf.value, n_ee.value
 
     def features(self, V0, V1, E, F, vf, ee, delta=1e-6, stream=None):
         """Scheduling features, (n_vf + n_ee) x 16 float32 on the device, VF pairs first."""
@@ -517,16 +593,47 @@ def _schedule(schedule):
         return schedule.sch, schedule.keep
     kind = schedule[0]
     if kind == "plain":
-        return Schedule(SCHED_PLAIN, None, None, None, 0.0, 0), ()
+        return Schedule(SCHED_PLAIN, None, None, None, 0.0, 0, None), ()
     if kind == "learned":
         params, norm = _f32(schedule[1], MODEL_PARAMS), _f32(schedule[2], 2 * NUM_FEATURES)
         thr = float(schedule[3]) if len(schedule) > 3 else HEAVY_THRESHOLD
         mh = int(schedule[4]) if len(schedule) > 4 else MAX_HEAVY
-        return Schedule(SCHED_LEARNED, params.data_ptr(), norm.data_ptr(), None, thr, mh), (params, norm)
+        return Schedule(SCHED_LEARNED, params.data_ptr(), norm.data_ptr(), None, thr, mh, None), (params, norm)
     if kind == "order":
         perm = _dev(schedule[1], torch.int32, 1).reshape(-1)
-        return Schedule(SCHED_ORDER, None, None, perm.data_ptr() if perm.numel() else None, 0.0, 0), (perm,)
+        return Schedule(SCHED_ORDER, None, None, perm.data_ptr() if perm.numel() else None, 0.0, 0, None), (perm,)
+    if kind == "cost":
+        cost = _dev(schedule[1], torch.float32, 1).reshape(-1)
+        thr = float(schedule[2]) if len(schedule) > 2 else HEAVY_THRESHOLD
+        mh = int(schedule[3]) if len(schedule) > 3 else MAX_HEAVY
+        return Schedule(SCHED_COST, None, None, None, thr, mh, cost.data_ptr() if cost.numel() else None), (cost,)
     raise ValueError(f"unknown schedule {kind!r}")
+
+
+def _check_schedule_len(sch, keep, n):
+    """An order or cost schedule holds exactly one entry per pair (the kernels read n of them)."""
+    if sch is not None and sch.kind in (SCHED_ORDER, SCHED_COST) and keep[0].numel() != n:
+        raise ValueError(f"schedule: expected {n} entries, one per pair, got {keep[0].numel()}")
+
+
+def _options(options, device, n):
+    """ctypes NarrowOptions from a dict (earliest_only, no_zero_toi, min_sep, min_sep_d0_factor)."""
+    import torch
+    o = dict(options)
+    unknown = set(o) - {"earliest_only", "no_zero_toi", "min_sep", "min_sep_d0_factor"}
+    if unknown:
+        raise ValueError(f"unknown narrow-phase options {sorted(unknown)}")
+    ms = o.get("min_sep")
+    keep = ()
+    ptr = None
+    if ms is not None:
+        _require(ms, "min_sep", torch.float64, device, min_numel=n)
+        if ms.dim() != 1 or ms.numel() != n:
+            raise ValueError(f"min_sep: expected {n} values, one per pair")
+        ptr = ms.data_ptr() if n else None
+        keep = (ms,)
+    return NarrowOptions(int(bool(o.get("earliest_only", 0))), int(bool(o.get("no_zero_toi", 0))), ptr,
+                         float(o.get("min_sep_d0_factor", 0.0))), keep
 
 
 def version():

@@ -68,7 +68,7 @@ size_t aligned_total(std::initializer_list<size_t> sizes)
 
 struct ccd_context {
     int device = 0;
-    Pool broad, narrow, scratch, sched;
+    Pool broad, narrow, scratch, sched, aux;
     void *host = nullptr;  // pinned host staging for counters and flags
     hipEvent_t ev[12] = {};  // narrow stages 0..6, broad stages 7..11
     ccd_stats stats{};
@@ -152,7 +152,10 @@ void broad_carve(Carver &cv, int64_t nb, int64_t S, int64_t nbl, BroadBuffers &B
 void narrow_carve(Carver &cv, int64_t npairs, NarrowBuffers &B)
 {
     const size_t m = (size_t)std::max<int64_t>(npairs, 1);
-    const int64_t hnode_cap = 4 * (int64_t)m + 65536;
+    // the pool's hand-overs (at most kQCap intervals each) and the frontiers the
+    // wide stage saves when they outgrow its buffers; when it is full a pair
+    // restarts from its root instead (same result, more work)
+    const int64_t hnode_cap = 8 * (int64_t)m + ((int64_t)1 << 21);
     B.ids4 = cv.take<int4>(m);
     B.eps = cv.take<double>(3 * m);
     B.m = cv.take<uint32_t>(m);
@@ -163,8 +166,10 @@ void narrow_carve(Carver &cv, int64_t npairs, NarrowBuffers &B)
     B.overflow_list[0] = cv.take<int32_t>(m);
     B.overflow_list[1] = cv.take<int32_t>(m);
     B.flags = cv.take<uint32_t>(1);
+    B.ms_scaled = cv.take<double>(m);
     B.toi_min = nullptr;
     B.scratch = nullptr;
+    B.mode = NarrowMode();
 }
 
 bool valid_tuning(const ccd_tuning &t)
@@ -294,7 +299,7 @@ void ccd_destroy(ccd_context *c)
 {
     if (!c) return;
     (void)hipSetDevice(c->device);
-    for (Pool *p : {&c->broad, &c->narrow, &c->scratch, &c->sched})
+    for (Pool *p : {&c->broad, &c->narrow, &c->scratch, &c->sched, &c->aux})
         if (p->base) (void)hipFree(p->base);
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
@@ -404,15 +409,51 @@ ccd_status sched_setup(ccd_context *c, int64_t n, SchedBuffers &S)
 ccd_status check_schedule(const ccd_schedule *sched, int64_t n)
 {
     const int kind = sched ? sched->kind : CCD_SCHED_PLAIN;
-    if (kind != CCD_SCHED_PLAIN && kind != CCD_SCHED_LEARNED && kind != CCD_SCHED_ORDER)
+    if (kind != CCD_SCHED_PLAIN && kind != CCD_SCHED_LEARNED && kind != CCD_SCHED_ORDER && kind != CCD_SCHED_COST)
         return fail(CCD_ERR_INVALID_ARG, "unknown schedule kind %d", kind);
     if (kind == CCD_SCHED_LEARNED && (!sched->params || !sched->norm))
         return fail(CCD_ERR_INVALID_ARG, "learned schedule without parameters or normalization");
-    if (kind == CCD_SCHED_LEARNED && (sched->max_heavy < 0 || !std::isfinite(sched->heavy_threshold)))
-        return fail(CCD_ERR_INVALID_ARG, "learned schedule: negative max_heavy or non-finite threshold");
+    if (kind == CCD_SCHED_COST && n > 0 && !sched->cost)
+        return fail(CCD_ERR_INVALID_ARG, "cost schedule without costs");
+    if ((kind == CCD_SCHED_LEARNED || kind == CCD_SCHED_COST) &&
+        (sched->max_heavy < 0 || !std::isfinite(sched->heavy_threshold)))
+        return fail(CCD_ERR_INVALID_ARG, "cost-ranked schedule: negative max_heavy or non-finite threshold");
     if (kind == CCD_SCHED_ORDER && n > 0 && !sched->order)
         return fail(CCD_ERR_INVALID_ARG, "order schedule without an order");
     return CCD_OK;
+}
+
+// Options checked on the host (the per-pair separations are checked on the
+// device by the prep pass).
+ccd_status check_options(const ccd_narrow_options *o, bool pairs_known)
+{
+    if (!o) return CCD_OK;
+    if ((o->earliest_only != 0 && o->earliest_only != 1) || (o->no_zero_toi != 0 && o->no_zero_toi != 1))
+        return fail(CCD_ERR_INVALID_ARG, "earliest_only and no_zero_toi must be 0 or 1");
+    if (!(o->min_sep_d0_factor >= 0.0) || !std::isfinite(o->min_sep_d0_factor))
+        return fail(CCD_ERR_INVALID_ARG, "min_sep_d0_factor must be finite and >= 0");
+    if (o->min_sep && o->min_sep_d0_factor > 0.0)
+        return fail(CCD_ERR_INVALID_ARG, "give either min_sep or min_sep_d0_factor, not both");
+    if (o->min_sep && !pairs_known)
+        return fail(CCD_ERR_INVALID_ARG, "per-pair min_sep needs the pairs before the call: use min_sep_d0_factor");
+    return CCD_OK;
+}
+
+// The narrow-phase mode of a call; with a d0 factor, the separations are
+// computed on s (into B.ms_scaled) before the prep pass reads them.
+void apply_options(const ccd_narrow_options *o, NarrowBuffers &B, const double *V0, int64_t nv, const int32_t *E,
+                   int64_t ne, const int32_t *F, int64_t nf, const int32_t *vf, const int32_t *ee, PairCounts pc,
+                   hipStream_t s)
+{
+    B.mode = NarrowMode();
+    if (!o) return;
+    B.mode.global = o->earliest_only;
+    B.mode.no_zero = o->no_zero_toi;
+    B.mode.ms = o->min_sep;
+    if (o->min_sep_d0_factor > 0.0) {
+        launch_initial_distance(V0, nv, E, ne, F, nf, vf, ee, pc, o->min_sep_d0_factor, B.ms_scaled, B.flags, s);
+        B.mode.ms = B.ms_scaled;
+    }
 }
 
 // A narrow call between its launches and its host checks.
@@ -441,8 +482,9 @@ ccd_status narrow_enqueue(ccd_context *c, const double *V0, const double *V1, in
     // the early wide stage's of the learned schedule after them
     call.nslots = c->tune.heavy_slots;
     call.cap = (int64_t)1 << c->tune.heavy_cap_log2;
-    call.learned = sched && sched->kind == CCD_SCHED_LEARNED;
+    call.learned = sched && (sched->kind == CCD_SCHED_LEARNED || sched->kind == CCD_SCHED_COST);
     const bool learned = call.learned;
+    const bool given_cost = sched && sched->kind == CCD_SCHED_COST;
     const int nslots = call.nslots;
     const int64_t cap = call.cap;
     const int max_early = learned ? (int)std::min<int64_t>(sched->max_heavy, n) : 0;
@@ -454,7 +496,16 @@ ccd_status narrow_enqueue(ccd_context *c, const double *V0, const double *V1, in
     long long *nenq = (long long *)n_enq;
     const uint32_t *order_n = nullptr;
     HIP_TRY(hipEventRecord(c->ev[0], s));
-    if (learned) {
+    if (given_cost) {
+        // the caller's costs take the place of the network's predictions
+        launch_narrow_prep(V0, V1, nv, E, ne, F, nf, vf, ee, pc, delta, B, s);
+        HIP_TRY(hipEventRecord(c->ev[4], s));
+        launch_cost_hist(sched->cost, pc, S.block_hist, s);
+        launch_cost_schedule(sched->cost, pc, sched->heavy_threshold, max_early, S.order, B.heavy, B.counters,
+                             S.bins, S.block_hist, s);
+        order = S.order;
+        order_n = S.bins + 2 * 256 + 1;
+    } else if (learned) {
         // prep and features in one pass, the prediction and cost histogram in a second; then the ordering
         launch_narrow_prep_feat(V0, V1, nv, E, ne, F, nf, vf, ee, pc, delta, B, S.feat, S.bins, sched->params,
                                 S.packed, s);
@@ -491,6 +542,55 @@ ccd_status narrow_enqueue(ccd_context *c, const double *V0, const double *V1, in
     return CCD_OK;
 }
 
+// Pairs whose frontier outgrew the wide stage's buffers, resumed from the level
+// they saved.  The first re-run round sizes the buffers for max_iter + 1
+// intervals, which no pair below the cap can outgrow (a level's frontier holds
+// at most its kept children), as far as device memory allows, on one
+// 1,024-thread workgroup per compute unit; a further round (memory-limited
+// buffers) takes 8x larger ones.  `pool` holds the frontier buffers.
+ccd_status rerun_overflowed(ccd_context *c, NarrowBuffers B, Pool &pool, unsigned int overflowed, int64_t cap,
+                            const double *V0, const double *V1, PairCounts pc, double delta, int64_t max_iter,
+                            uint8_t *hit, double *toi, long long *nenq, hipStream_t s, float *ms_total)
+{
+    int round = 0;
+    unsigned int *hr = (unsigned int *)c->host;
+    while (overflowed > 0) {
+        round++;
+        c->stats.heavy_reruns += overflowed;
+        size_t free_b = 0, total_b = 0;
+        HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+        const size_t budget = pool.bytes + free_b / 2;
+        int64_t want = cap * 8;
+        if (round == 1) {
+            int64_t need = cap;
+            while (need < max_iter + 1 && need < ((int64_t)1 << 30)) need *= 2;
+            want = std::max(want, need);
+        }
+        const size_t slots_wanted = std::min<size_t>((size_t)c->cus, (size_t)overflowed);
+        while (want > cap * 8 && slots_wanted * (size_t)6 * want * 8 > budget) want /= 2;
+        cap = want;
+        const size_t per_slot = (size_t)6 * cap * 8;
+        if (per_slot > budget || round > 12)
+            return fail(CCD_ERR_OOM, "interval frontier of %u pairs exceeds device memory", overflowed);
+        const int nslots = (int)std::min<size_t>(slots_wanted, budget / per_slot);
+        ccd_status st = ensure(pool, (size_t)nslots * per_slot);
+        if (st != CCD_OK) return st;
+        B.scratch = (unsigned long long *)pool.base;
+        HIP_TRY(hipEventRecord(c->ev[0], s));
+        launch_narrow_heavy(V0, V1, pc, delta, (long long)max_iter, hit, toi, nenq, B, nslots, cap, round,
+                            c->tune.heavy_lds, c->tune.heavy_block == 0 ? 0 : c->tune.heavy_block, s);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipEventRecord(c->ev[1], s));
+        HIP_TRY(hipMemcpyAsync(hr, B.counters, 16 * 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
+        if (ms_total) *ms_total += ms;
+        overflowed = hr[2 + (round & 1)];
+    }
+    return CCD_OK;
+}
+
 // Host side of a narrow call once its stream has reached the end: h holds the
 // wide stage's counters (h[0..15]) and the flags (h[16]); pc counts the pairs
 // on the host.  Pairs whose frontier outgrew its buffer are re-run here.
@@ -518,52 +618,30 @@ ccd_status narrow_finish(ccd_context *c, const unsigned int *h, const double *V0
     const uint32_t flags = h[16];
     if (flags & FLAG_BAD_INDEX) return fail(CCD_ERR_INVALID_ARG, "pair, edge or face index out of range");
     if (flags & FLAG_NONFINITE) return fail(CCD_ERR_NONFINITE, "non-finite or too large (> 2^960) coordinate");
-    // pairs whose frontier outgrew their buffer: re-run them with larger buffers
-    long long *nenq = (long long *)n_enq;
-    int64_t cap = call.cap;
-    int nslots = call.nslots;
-    int round = 0;
-    unsigned int overflowed = h[2];
-    unsigned int *hr = (unsigned int *)c->host;
-    while (overflowed > 0) {
-        round++;
-        c->stats.heavy_reruns += overflowed;
-        cap *= 8;
-        size_t free_b = 0, total_b = 0;
-        HIP_TRY(hipMemGetInfo(&free_b, &total_b));
-        const size_t per_slot = (size_t)6 * cap * 8;
-        const size_t budget = c->scratch.bytes + free_b / 2;
-        if (per_slot > budget || round > 12)
-            return fail(CCD_ERR_OOM, "interval frontier of %u pairs exceeds device memory", overflowed);
-        nslots = (int)std::min<size_t>({(size_t)1024, budget / per_slot, (size_t)overflowed});
-        ccd_status st = ensure(c->scratch, (size_t)nslots * per_slot);
-        if (st != CCD_OK) return st;
-        B.scratch = (unsigned long long *)c->scratch.base;
-        HIP_TRY(hipEventRecord(c->ev[0], s));
-        launch_narrow_heavy(V0, V1, pc, delta, (long long)max_iter, hit, toi, nenq, B, nslots, cap, round,
-                            c->tune.heavy_lds, c->tune.heavy_block, s);
-        HIP_TRY(hipGetLastError());
-        HIP_TRY(hipEventRecord(c->ev[1], s));
-        HIP_TRY(hipMemcpyAsync(hr, B.counters, 16 * 4, hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        HIP_TRY(hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
-        c->stats.narrow_ms += ms;
-        c->stats.narrow_heavy_ms += ms;
-        overflowed = hr[2 + (round & 1)];
-    }
-    return CCD_OK;
+    if (flags & FLAG_BAD_SEPARATION)
+        return fail(CCD_ERR_INVALID_ARG, "minimum separation must be finite, >= 0 and at most 2^960");
+    // pairs whose frontier outgrew their buffer: resumed with larger buffers
+    float ms_rerun = 0.f;
+    ccd_status st = rerun_overflowed(c, B, c->scratch, h[2], call.cap, V0, V1, pc, delta, max_iter, hit, toi,
+                                     (long long *)n_enq, s, &ms_rerun);
+    c->stats.narrow_ms += ms_rerun;
+    c->stats.narrow_heavy_ms += ms_rerun;
+    (void)toi_min;
+    return st;
 }
 
 ccd_status narrow_impl(ccd_context *c, const double *V0, const double *V1, int64_t nv, const int32_t *E, int64_t ne,
                        const int32_t *F, int64_t nf, const int32_t *vf, int64_t n_vf, const int32_t *ee,
                        int64_t n_ee, double delta, int64_t max_iter, uint8_t *hit, double *toi, double *toi_min,
-                       int64_t *n_enq, const ccd_schedule *sched, void *stream)
+                       int64_t *n_enq, const ccd_schedule *sched, const ccd_narrow_options *opts, void *stream)
 {
     if (!c || !toi_min) return fail(CCD_ERR_INVALID_ARG, "NULL context or toi_min");
     if (max_iter < 1) return fail(CCD_ERR_INVALID_ARG, "max_iter must be >= 1");
     const int64_t n = n_vf + n_ee;
     if (n > 0 && (!hit || !toi)) return fail(CCD_ERR_INVALID_ARG, "NULL pointer with nonzero size");
     ccd_status st = check_schedule(sched, n);
+    if (st != CCD_OK) return st;
+    st = check_options(opts, true);
     if (st != CCD_OK) return st;
     NarrowCall call;
     st = narrow_setup(c, V0, V1, nv, E, ne, F, nf, vf, n_vf, ee, n_ee, delta, call.B);
@@ -587,6 +665,7 @@ ccd_status narrow_impl(ccd_context *c, const double *V0, const double *V1, int64
         order = sched->order;
     }
     const PairCounts pc{n_vf, n_ee, nullptr};
+    apply_options(opts, call.B, V0, nv, E, ne, F, nf, vf, ee, pc, s);
     st = narrow_enqueue(c, V0, V1, nv, E, ne, F, nf, vf, ee, pc, delta, max_iter, hit, toi, toi_min, n_enq, sched,
                         order, S, s, call);
     if (st != CCD_OK) return st;
@@ -606,16 +685,19 @@ ccd_status narrow_impl(ccd_context *c, const double *V0, const double *V1, int64
 ccd_status detect_impl(ccd_context *c, const double *V0, const double *V1, int64_t nv, const int32_t *E, int64_t ne,
                        const int32_t *F, int64_t nf, int32_t *vf, int64_t vf_cap, int64_t *n_vf, int32_t *ee,
                        int64_t ee_cap, int64_t *n_ee, double delta, int64_t max_iter, uint8_t *hit, double *toi,
-                       double *toi_min, int64_t *n_enq, const ccd_schedule *sched, void *stream)
+                       double *toi_min, int64_t *n_enq, const ccd_schedule *sched, const ccd_narrow_options *opts,
+                       void *stream)
 {
     if (!c || !toi_min) return fail(CCD_ERR_INVALID_ARG, "NULL context or toi_min");
     if (max_iter < 1) return fail(CCD_ERR_INVALID_ARG, "max_iter must be >= 1");
     if (vf_cap < 0 || ee_cap < 0) return fail(CCD_ERR_INVALID_ARG, "negative size");
     const int64_t cap = vf_cap + ee_cap;
     if (cap > 0 && (!hit || !toi)) return fail(CCD_ERR_INVALID_ARG, "NULL pointer with nonzero size");
-    if (sched && sched->kind == CCD_SCHED_ORDER)
-        return fail(CCD_ERR_INVALID_ARG, "an order schedule needs the pair count before the call");
+    if (sched && (sched->kind == CCD_SCHED_ORDER || sched->kind == CCD_SCHED_COST))
+        return fail(CCD_ERR_INVALID_ARG, "order and cost schedules need the pair count before the call");
     ccd_status st = check_schedule(sched, cap);
+    if (st != CCD_OK) return st;
+    st = check_options(opts, false);
     if (st != CCD_OK) return st;
     hipStream_t s = (hipStream_t)stream;
     BroadBuffers BB;
@@ -630,6 +712,7 @@ ccd_status detect_impl(ccd_context *c, const double *V0, const double *V1, int64
         if (st != CCD_OK) return st;
     }
     const PairCounts pcd{vf_cap, ee_cap, BB.counts};
+    apply_options(opts, call.B, V0, nv, E, ne, F, nf, vf, ee, pcd, s);
     st = narrow_enqueue(c, V0, V1, nv, E, ne, F, nf, vf, ee, pcd, delta, max_iter, hit, toi, toi_min, n_enq, sched,
                         nullptr, S, s, call);
     if (st != CCD_OK) return st;
@@ -675,7 +758,7 @@ ccd_status ccd_narrow(ccd_context *c, const double *V0, const double *V1, int64_
                       int64_t *n_enq, void *stream)
 {
     return narrow_impl(c, V0, V1, nv, E, ne, F, nf, vf, n_vf, ee, n_ee, delta, max_iter, hit, toi, toi_min, n_enq,
-                       nullptr, stream);
+                       nullptr, nullptr, stream);
 }
 
 ccd_status ccd_narrow_sched(ccd_context *c, const double *V0, const double *V1, int64_t nv, const int32_t *E,
@@ -684,7 +767,16 @@ ccd_status ccd_narrow_sched(ccd_context *c, const double *V0, const double *V1, 
                             double *toi, double *toi_min, int64_t *n_enq, const ccd_schedule *sched, void *stream)
 {
     return narrow_impl(c, V0, V1, nv, E, ne, F, nf, vf, n_vf, ee, n_ee, delta, max_iter, hit, toi, toi_min, n_enq,
-                       sched, stream);
+                       sched, nullptr, stream);
+}
+
+ccd_status ccd_narrow_ex(ccd_context *c, const double *V0, const double *V1, int64_t nv, const int32_t *E, int64_t ne,
+                         const int32_t *F, int64_t nf, const int32_t *vf, int64_t n_vf, const int32_t *ee,
+                         int64_t n_ee, double delta, int64_t max_iter, uint8_t *hit, double *toi, double *toi_min,
+                         int64_t *n_enq, const ccd_schedule *sched, const ccd_narrow_options *opts, void *stream)
+{
+    return narrow_impl(c, V0, V1, nv, E, ne, F, nf, vf, n_vf, ee, n_ee, delta, max_iter, hit, toi, toi_min, n_enq,
+                       sched, opts, stream);
 }
 
 ccd_status ccd_detect(ccd_context *c, const double *V0, const double *V1, int64_t nv, const int32_t *E, int64_t ne,
@@ -693,7 +785,86 @@ ccd_status ccd_detect(ccd_context *c, const double *V0, const double *V1, int64_
                       double *toi_min, int64_t *n_enq, const ccd_schedule *sched, void *stream)
 {
     return detect_impl(c, V0, V1, nv, E, ne, F, nf, vf, vf_cap, n_vf, ee, ee_cap, n_ee, delta, max_iter, hit, toi,
-                       toi_min, n_enq, sched, stream);
+                       toi_min, n_enq, sched, nullptr, stream);
+}
+
+ccd_status ccd_detect_ex(ccd_context *c, const double *V0, const double *V1, int64_t nv, const int32_t *E, int64_t ne,
+                         const int32_t *F, int64_t nf, int32_t *vf, int64_t vf_cap, int64_t *n_vf, int32_t *ee,
+                         int64_t ee_cap, int64_t *n_ee, double delta, int64_t max_iter, uint8_t *hit, double *toi,
+                         double *toi_min, int64_t *n_enq, const ccd_schedule *sched, const ccd_narrow_options *opts,
+                         void *stream)
+{
+    return detect_impl(c, V0, V1, nv, E, ne, F, nf, vf, vf_cap, n_vf, ee, ee_cap, n_ee, delta, max_iter, hit, toi,
+                       toi_min, n_enq, sched, opts, stream);
+}
+
+ccd_status ccd_initial_distance(ccd_context *c, const double *V0, int64_t nv, const int32_t *E, int64_t ne,
+                                const int32_t *F, int64_t nf, const int32_t *vf, int64_t n_vf, const int32_t *ee,
+                                int64_t n_ee, double *d0, void *stream)
+{
+    if (!c) return fail(CCD_ERR_INVALID_ARG, "NULL context");
+    if (nv < 0 || ne < 0 || nf < 0 || n_vf < 0 || n_ee < 0) return fail(CCD_ERR_INVALID_ARG, "negative size");
+    const int64_t n = n_vf + n_ee;
+    if (n > INT32_MAX) return fail(CCD_ERR_INVALID_ARG, "too many pairs for one call");
+    if ((nv && !V0) || (ne && !E) || (nf && !F) || (n_vf && !vf) || (n_ee && !ee) || (n && !d0))
+        return fail(CCD_ERR_INVALID_ARG, "NULL pointer with nonzero size");
+    HIP_TRY(hipSetDevice(c->device));
+    ccd_status st = ensure(c->aux, 256);
+    if (st != CCD_OK) return st;
+    uint32_t *flags = (uint32_t *)c->aux.base;
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipMemsetAsync(flags, 0, 4, s));
+    launch_initial_distance(V0, nv, E, ne, F, nf, vf, ee, PairCounts{n_vf, n_ee, nullptr}, 1.0, d0, flags, s);
+    HIP_TRY(hipGetLastError());
+    uint32_t *h = (uint32_t *)c->host;
+    HIP_TRY(hipMemcpyAsync(h, flags, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (h[0] & FLAG_BAD_INDEX) return fail(CCD_ERR_INVALID_ARG, "pair, edge or face index out of range");
+    g_err.clear();
+    return CCD_OK;
+}
+
+ccd_status ccd_toi_step(ccd_context *c, const double *V0, const double *V1, int64_t nv, const int32_t *E, int64_t ne,
+                        const int32_t *F, int64_t nf, int32_t *vf, int64_t vf_cap, int64_t *n_vf, int32_t *ee,
+                        int64_t ee_cap, int64_t *n_ee, double delta, int64_t max_iter, double ms_factor, double scale,
+                        double *toi, int32_t *rerun, void *stream)
+{
+    if (!c || !toi) return fail(CCD_ERR_INVALID_ARG, "NULL context or toi");
+    if (!(ms_factor >= 0.0) || !std::isfinite(ms_factor)) return fail(CCD_ERR_INVALID_ARG, "ms_factor must be >= 0");
+    if (!(scale > 0.0 && scale <= 1.0)) return fail(CCD_ERR_INVALID_ARG, "scale must lie in (0, 1]");
+    if (vf_cap < 0 || ee_cap < 0) return fail(CCD_ERR_INVALID_ARG, "negative size");
+    HIP_TRY(hipSetDevice(c->device));
+    // per-pair outputs the narrow phase writes (unspecified with a shared t*) and the earliest time
+    const size_t m = (size_t)std::max<int64_t>(vf_cap + ee_cap, 1);
+    ccd_status st = ensure(c->aux, aligned_total({8, m * 8, m}));
+    if (st != CCD_OK) return st;
+    Carver cv(c->aux.base);
+    double *tmin = cv.take<double>(1);
+    double *ptoi = cv.take<double>(m);
+    uint8_t *phit = cv.take<uint8_t>(m);
+    hipStream_t s = (hipStream_t)stream;
+    ccd_narrow_options o{1, 0, nullptr, ms_factor};
+    st = detect_impl(c, V0, V1, nv, E, ne, F, nf, vf, vf_cap, n_vf, ee, ee_cap, n_ee, delta, max_iter, phit, ptoi,
+                     tmin, nullptr, nullptr, &o, stream);
+    if (st != CCD_OK) return st;
+    double t = 0.0;
+    HIP_TRY(hipMemcpyAsync(&t, tmin, 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (rerun) *rerun = 0;
+    if (t == 0.0) {
+        // App. B: again without the separation, splitting intervals at t = 0, and the time scaled down
+        ccd_narrow_options o2{1, 1, nullptr, 0.0};
+        st = narrow_impl(c, V0, V1, nv, E, ne, F, nf, vf, *n_vf, ee, *n_ee, delta, max_iter, phit, ptoi, tmin,
+                         nullptr, nullptr, &o2, stream);
+        if (st != CCD_OK) return st;
+        HIP_TRY(hipMemcpyAsync(&t, tmin, 8, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        t *= scale;
+        if (rerun) *rerun = 1;
+    }
+    *toi = t;
+    g_err.clear();
+    return CCD_OK;
 }
 
 ccd_status ccd_features(ccd_context *c, const double *V0, const double *V1, int64_t nv, const int32_t *E, int64_t ne,
@@ -907,38 +1078,15 @@ ccd_status batch_pass(ccd_batch *b, const BatchArgs &a, bool use_graph, int64_t 
     if (*n_vf > b->vf_cap || *n_ee > b->ee_cap)
         return fail(CCD_ERR_CAPACITY, "pair capacity too small: need %lld VF and %lld EE pairs", (long long)*n_vf,
                     (long long)*n_ee);
-    // frontiers that outgrew their buffer: re-run those pairs eagerly with larger buffers
+    // frontiers that outgrew their buffer: those pairs resume eagerly with larger buffers
     unsigned int overflowed = ctr[2];
     if (overflowed > 0) {
         const PairCounts pc{*n_vf, *n_ee, nullptr};
         Pool big;
-        int64_t cap = b->heavy_cap;
-        int round = 0;
-        NarrowBuffers N = b->N;
-        while (overflowed > 0) {
-            round++;
-            c->stats.heavy_reruns += overflowed;
-            cap *= 8;
-            size_t free_b = 0, total_b = 0;
-            HIP_TRY(hipMemGetInfo(&free_b, &total_b));
-            const size_t per_slot = (size_t)6 * cap * 8;
-            if (per_slot > free_b / 2 || round > 12) {
-                if (big.base) (void)hipFree(big.base);
-                return fail(CCD_ERR_OOM, "interval frontier of %u pairs exceeds device memory", overflowed);
-            }
-            const int nslots = (int)std::min<size_t>({(size_t)1024, (free_b / 2) / per_slot, (size_t)overflowed});
-            st = ensure(big, (size_t)nslots * per_slot);
-            if (st != CCD_OK) return st;
-            N.scratch = (unsigned long long *)big.base;
-            launch_narrow_heavy(a.V0, a.V1, pc, a.delta, a.max_iter, a.hit, a.toi, a.n_enq, N, nslots, cap, round,
-                                c->tune.heavy_lds, c->tune.heavy_block, s);
-            HIP_TRY(hipGetLastError());
-            unsigned int *hc = (unsigned int *)c->host;
-            HIP_TRY(hipMemcpyAsync(hc, N.counters, 16 * 4, hipMemcpyDeviceToHost, s));
-            HIP_TRY(hipStreamSynchronize(s));
-            overflowed = hc[2 + (round & 1)];
-        }
+        st = rerun_overflowed(c, b->N, big, overflowed, b->heavy_cap, a.V0, a.V1, pc, a.delta, a.max_iter, a.hit,
+                              a.toi, a.n_enq, s, nullptr);
         if (big.base) (void)hipFree(big.base);
+        if (st != CCD_OK) return st;
         launch_scene_min(a.toi, pc, a.vf, a.ee, b->off, b->off + (b->S + 1), b->S, a.toi_min, s);
         HIP_TRY(hipGetLastError());
         HIP_TRY(hipStreamSynchronize(s));

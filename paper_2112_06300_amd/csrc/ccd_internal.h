@@ -74,6 +74,7 @@ enum : uint32_t {
     FLAG_BAD_INDEX = 1u,
     FLAG_NONFINITE = 2u,
     FLAG_HEAVY_OVERFLOW = 4u,
+    FLAG_BAD_SEPARATION = 8u,
 };
 
 // ---------------------------------------------------------------------------
@@ -154,15 +155,31 @@ struct PairCounts {
 constexpr int kLightMaxLevel = 21;  // the wave pool packs numerators in 21 bits each
 constexpr int kMaxLevel = 52;       // finest dyadic level per dimension
 
-// A pair handed to the wide stage: survivors at levels lvl, still to be split.
+// A pair handed to the wide stage: survivors at levels lvl, still to be split,
+// and the pair's t* and n_enq at that point.
 struct HeavyEntry {
     int32_t pair;
     int32_t nnodes;
     int32_t lvl[3];
-    int32_t pad;
+    int32_t layout;      // node buffer layout: 0 = one word per interval (t | u << 21 | v << 42),
+                         // 1 = three arrays of nnodes words (t, then u, then v numerators)
     double tstar;
     long long n_enq;
     long long node_off;  // first survivor in the node buffer; -1: restart from the root
+};
+
+// Options of a narrow-phase call beyond the per-pair search.
+struct NarrowMode {
+    // Alg. 3's single t* shared by all pairs: the call's earliest time
+    // (toi_min) prunes the intervals of every pair as soon as it drops; only
+    // toi_min is then defined
+    int global = 0;
+    // App. B's no-zero-TOI strategy: an interval starting at t = 0 is split
+    // whatever its width (only the finest level stops it), and the cap on
+    // enqueued intervals does not stop a pair while such an interval is left
+    int no_zero = 0;
+    // per-pair minimum separation added to C_eps (Sec. 7), or null
+    const double *ms = nullptr;
 };
 
 struct NarrowBuffers {
@@ -170,7 +187,9 @@ struct NarrowBuffers {
     double *eps;                   // C_eps half-widths, 3 per pair
     uint32_t *m;                   // split levels m_t | m_u << 8 | m_v << 16 per pair
     HeavyEntry *heavy;             // capacity n_pairs
-    unsigned long long *hnodes;    // survivors of handed-over pairs (21-bit packed)
+    unsigned long long *hnodes;    // survivors of handed-over pairs (HeavyEntry::layout), bump-allocated
+                                   // by counters[10..11]: the pool's hand-overs, then the frontiers the
+                                   // wide stage's first round saves when they outgrow its buffers
     int64_t hnode_cap;
     unsigned int *counters;        // [0] handed-over pairs, [1] work index, [2]/[3] overflow counts,
                                    // [4] re-run index, [8..9] pair claim counter, [10..11] node counter
@@ -181,6 +200,8 @@ struct NarrowBuffers {
     // per-scene minima come from launch_scene_min): set to +inf by the prep
     // launch, lowered by an atomic min wherever a pair's result is written
     double *toi_min;
+    NarrowMode mode;
+    double *ms_scaled;             // per-pair minimum separation computed from d0 (min_sep_d0_factor)
 };
 
 // Resident 64-lane pool workgroups per CU.
@@ -241,6 +262,9 @@ int64_t cost_blocks(int64_t n);
 constexpr int kMlpPackedBytes = 20 * 64 * 8;
 void launch_cost_predict(const float *params, const float *norm, const float *feat, PairCounts pc, float *cost,
                          uint32_t *block_hist, void *packed, hipStream_t s);
+// The per-block cost-bin counts of caller-given costs (n = pc.capacity()
+// rows), in the layout launch_cost_predict writes.
+void launch_cost_hist(const float *cost, PairCounts pc, uint32_t *block_hist, hipStream_t s);
 // grad (kModelParams floats) and loss (1 float, sum of squared errors) are
 // accumulated; the launcher clears them first.  The loss is the mean squared
 // error over the n pairs.
@@ -265,13 +289,20 @@ void launch_check_permutation(const int32_t *order, int64_t n, uint32_t *bits, u
 
 // Wide stage: `nslots` workgroups, each with a frontier buffer of `cap` nodes
 // (two buffers of 3 x cap uint64).  Round 0 works on every handed-over pair;
-// round r > 0 re-runs the pairs that overflowed their buffer in round r - 1.
+// a pair whose next frontier outgrows the buffer saves the level it was on
+// (its frontier, levels, t* and n_enq) and round r > 0 resumes the pairs that
+// overflowed in round r - 1 from that level, with larger buffers.
 // block: threads per pair (64, 256 or 1024; 0 = 1024 for at most 256 entries,
 // else 256, decided on the device); use_lds: frontiers of at most
 // 2 block intervals stay in LDS between levels.
 void launch_narrow_heavy(const double *V0, const double *V1, PairCounts pc, double delta, long long max_iter,
                          uint8_t *hit, double *toi, long long *n_enq, const NarrowBuffers &B, int nslots,
                          int64_t cap, int round, int use_lds, int block, hipStream_t s);
+
+// out[p] = scale * d0 of every pair (d0: distance of its primitives at t = 0).
+void launch_initial_distance(const double *V0, int64_t nv, const int32_t *E, int64_t ne, const int32_t *F, int64_t nf,
+                             const int32_t *vf, const int32_t *ee, PairCounts pc, double scale, double *out,
+                             uint32_t *flags, hipStream_t s);
 
 // out[s] = earliest toi over the pairs of scene s (CSR vertex / edge offsets
 // on the device, S + 1 each); +inf for a scene without a hit.

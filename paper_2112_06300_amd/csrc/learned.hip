@@ -452,7 +452,7 @@ __global__ __launch_bounds__(256) void cost_scatter_kernel(const float *__restri
                 e.pair = (int32_t)i;
                 e.nnodes = 1;  // from the root
                 e.lvl[0] = e.lvl[1] = e.lvl[2] = 0;
-                e.pad = 0;
+                e.layout = 0;
                 e.tstar = __builtin_huge_val();
                 e.n_enq = 0;
                 e.node_off = -1;
@@ -463,6 +463,29 @@ __global__ __launch_bounds__(256) void cost_scatter_kernel(const float *__restri
             }
         }
     }
+}
+
+// Per-block counts of cost bins of caller-given costs, over the same 64-row
+// chunks as the prediction pass (block b: chunks b, b + G, ...), written to
+// hist[bin * G + b] for the scatter that follows.
+__global__ __launch_bounds__(256) void cost_hist_kernel(const float *__restrict__ cost, PairCounts pc, uint32_t *hist)
+{
+    int64_t n_vf, n;
+    pc.get(n_vf, n);
+    (void)n_vf;
+    __shared__ uint32_t h[kCostBins];
+    h[threadIdx.x] = 0u;
+    __syncthreads();
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t G = gridDim.x;
+    for (int64_t k = w;; k += 4) {
+        const int64_t row0 = ((int64_t)blockIdx.x + G * k) * 64;
+        if (row0 >= n) break;
+        const int64_t i = row0 + lane;
+        if (i < n) atomicAdd(&h[cost_bin(cost[i])], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * G + blockIdx.x] = h[threadIdx.x];
 }
 
 __global__ void zero_u32_kernel(uint32_t *a, int n)
@@ -522,6 +545,13 @@ void launch_cost_predict(const float *params, const float *norm, const float *fe
     if (n == 0) return;
     const mlp_bf16x4 *pk = (const mlp_bf16x4 *)packed;
     mlp_predict_kernel<<<(unsigned)cost_blocks(n), 256, 0, s>>>(params, norm, feat, pc, cost, block_hist, pk);
+}
+
+void launch_cost_hist(const float *cost, PairCounts pc, uint32_t *block_hist, hipStream_t s)
+{
+    const int64_t n = pc.capacity();
+    if (n == 0) return;
+    cost_hist_kernel<<<(unsigned)cost_blocks(n), 256, 0, s>>>(cost, pc, block_hist);
 }
 
 void launch_mlp_grad(const float *params, const float *norm, const float *feat, const float *label, int64_t n,

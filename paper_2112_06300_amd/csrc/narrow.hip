@@ -140,8 +140,12 @@ __device__ __forceinline__ double pow2neg(int l) { return __longlong_as_double((
 // values follow one fixed float64 sequence: x(t) = fma(t, x1 - x0, x0);
 //   VF: g = fma(-u, b - a, p - a), F = fma(-v, c - a, g)
 //   EE: A = fma(u, a1 - a0, a0), B = fma(v, b1 - b0, b0), F = A - B.
+//
+// at_zero (App. B, no-zero-TOI strategy, for an interval starting at t = 0):
+// the interval is not reported for being narrow or inside C_eps, only at the
+// finest level.
 __device__ __forceinline__ int process(const Query &q, bool vf, double t0, double t1, double u0, double u1,
-                                       double v0, double v1, bool finest, double delta)
+                                       double v0, double v1, bool finest, double delta, bool at_zero = false)
 {
     if (vf && u0 + v0 > 1.0) return DISCARD;
     double width = 0.0;
@@ -182,7 +186,7 @@ __device__ __forceinline__ int process(const Query &q, bool vf, double t0, doubl
         width = w > width ? w : width;
         inside = inside && bmin >= -q.eps[a] && bmax <= q.eps[a];
     }
-    if (width < delta || inside || finest) return ACCEPT;
+    if (((width < delta || inside) && !at_zero) || finest) return ACCEPT;
     return SPLIT;
 }
 
@@ -216,9 +220,9 @@ __device__ __forceinline__ void unpack_m(uint32_t mp, int m[3])
 __device__ __forceinline__ bool prep_pair(int64_t p, int64_t n_vf, const double *__restrict__ V0,
                                           const double *__restrict__ V1, int64_t nv, const int32_t *__restrict__ vf,
                                           const int32_t *__restrict__ ee, const int32_t *__restrict__ E, int64_t ne,
-                                          const int32_t *__restrict__ F, int64_t nf, double delta, int4 *ids4,
-                                          double *peps, uint32_t *pm, uint32_t *flags, double raw[24],
-                                          double eps[3], uint32_t &mp)
+                                          const int32_t *__restrict__ F, int64_t nf, double delta,
+                                          const double *__restrict__ ms, int4 *ids4, double *peps, uint32_t *pm,
+                                          uint32_t *flags, double raw[24], double eps[3], uint32_t &mp)
 {
     int32_t id[4] = {-1, -1, -1, -1};
     bool ok;
@@ -249,6 +253,20 @@ __device__ __forceinline__ bool prep_pair(int64_t p, int64_t n_vf, const double 
         ids4[p] = make_int4(-2, 0, 0, 0);
         return false;
     }
+    if (ms) {
+        // minimum separation (Sec. 7): C_eps enlarged by ms on every axis, the
+        // sum rounded one double up so that the box holds the exact eps + ms
+        const double d = ms[p];
+        if (!(d >= 0.0 && d <= kMaxCoord)) {
+            atomicOr(flags, FLAG_BAD_SEPARATION);
+            ids4[p] = make_int4(-2, 0, 0, 0);
+            return false;
+        }
+        if (d > 0.0) {
+#pragma unroll
+            for (int a = 0; a < 3; a++) eps[a] = __longlong_as_double(__double_as_longlong(eps[a] + d) + 1ll);
+        }
+    }
     ids4[p] = ids;
     peps[3 * p] = eps[0];
     peps[3 * p + 1] = eps[1];
@@ -266,7 +284,8 @@ __global__ __launch_bounds__(256) void prep_kernel(const double *__restrict__ V0
                                                   const int32_t *__restrict__ ee, PairCounts pc,
                                                   const int32_t *__restrict__ E, int64_t ne,
                                                   const int32_t *__restrict__ F, int64_t nf, double delta,
-                                                  int4 *ids4, double *peps, uint32_t *pm, uint32_t *flags)
+                                                  const double *__restrict__ ms, int4 *ids4, double *peps,
+                                                  uint32_t *pm, uint32_t *flags)
 {
     int64_t n_vf, n;
     pc.get(n_vf, n);
@@ -274,7 +293,7 @@ __global__ __launch_bounds__(256) void prep_kernel(const double *__restrict__ V0
     if (p >= n) return;
     double raw[24], eps[3];
     uint32_t mp;
-    prep_pair(p, n_vf, V0, V1, nv, vf, ee, E, ne, F, nf, delta, ids4, peps, pm, flags, raw, eps, mp);
+    prep_pair(p, n_vf, V0, V1, nv, vf, ee, E, ne, F, nf, delta, ms, ids4, peps, pm, flags, raw, eps, mp);
 }
 
 // F on axis a at one point (t, u, v) with the canonical sequence of process().
@@ -425,9 +444,9 @@ __global__ __launch_bounds__(256) void prep_feat_kernel(const double *__restrict
                                                        const int32_t *__restrict__ ee, PairCounts pc,
                                                        const int32_t *__restrict__ E, int64_t ne,
                                                        const int32_t *__restrict__ F, int64_t nf, double delta,
-                                                       int4 *ids4, double *peps, uint32_t *pm, uint32_t *flags,
-                                                       float *__restrict__ feat, const float *__restrict__ prm,
-                                                       mlp_bf16x4 *packed)
+                                                       const double *__restrict__ ms, int4 *ids4, double *peps,
+                                                       uint32_t *pm, uint32_t *flags, float *__restrict__ feat,
+                                                       const float *__restrict__ prm, mlp_bf16x4 *packed)
 {
     // the network's bf16 weight fragments for the prediction pass that follows
     for (int idx = blockIdx.x * 256 + threadIdx.x; idx < 20 * 64; idx += gridDim.x * 256)
@@ -440,7 +459,7 @@ __global__ __launch_bounds__(256) void prep_feat_kernel(const double *__restrict
     uint32_t mp = 0u;
     float f[kNumFeatures];
     for (int i = 0; i < kNumFeatures; i++) f[i] = 0.f;
-    if (prep_pair(p, n_vf, V0, V1, nv, vf, ee, E, ne, F, nf, delta, ids4, peps, pm, flags, raw, eps, mp))
+    if (prep_pair(p, n_vf, V0, V1, nv, vf, ee, E, ne, F, nf, delta, ms, ids4, peps, pm, flags, raw, eps, mp))
         pair_features(raw, p < n_vf, eps, mp, delta, f);
     float4 *o = reinterpret_cast<float4 *>(feat + p * kNumFeatures);
 #pragma unroll
@@ -460,6 +479,7 @@ struct PoolLds {
     unsigned long long tstar[kPoolSlots];  // t* bits (non-negative doubles order like uint64)
     unsigned long long tmin[kPoolSlots];   // earliest kept child
     unsigned long long hoff[kPoolSlots];   // first node of a hand-over in the node buffer
+    unsigned long long zmask;              // slots with a kept child starting at t = 0 (no-zero strategy)
     int nsurv[kPoolSlots], cnt[kPoolSlots], k[kPoolSlots], off[kPoolSlots], pos[kPoolSlots];
 };
 static_assert(kSlots <= kPoolSlots && kRootLimit < kQCap, "pool sizes");
@@ -520,7 +540,7 @@ __global__ __launch_bounds__(kPoolSlots) void pool_kernel(
     const double *__restrict__ peps, const uint32_t *__restrict__ pm, PairCounts pc,
     double delta, long long max_iter, uint8_t *hit, double *toi, long long *n_enq_out, HeavyEntry *heavy,
     unsigned long long *hnodes, int64_t hnode_cap, unsigned int *counters, const int32_t *__restrict__ order,
-    const uint32_t *__restrict__ order_n, int wait, double *toi_min)
+    const uint32_t *__restrict__ order_n, int wait, double *toi_min, int gmode, int no_zero)
 {
     __shared__ PoolLds S;
     int64_t n_vf, n_pairs;
@@ -559,6 +579,7 @@ __global__ __launch_bounds__(kPoolSlots) void pool_kernel(
     S.tmin[lane] = kInfBits;
     S.lv[lane] = 0u;
     S.mm[lane] = 0u;
+    if (lane == 0) S.zmask = 0ull;
 
     for (;;) {
         // ---- prefetch pipeline (uniform control flow).  Stage A's registers
@@ -567,6 +588,20 @@ __global__ __launch_bounds__(kPoolSlots) void pool_kernel(
         // wait in this phase covers a load just issued.
         asm volatile("" : "+v"(ida.x), "+v"(ida.y), "+v"(ida.z), "+v"(ida.w), "+v"(epsa[0]), "+v"(epsa[1]),
                      "+v"(epsa[2]), "+v"(ma), "+v"(pa) : : "memory");
+        // Alg. 3's shared t* (global mode): intervals starting at or after the
+        // call's earliest time so far are pruned in every pair; read once per
+        // round so that counting and writing a level's children agree.  Once
+        // it is 0 no pair can lower it: no further pair is taken.
+        double tb = __builtin_huge_val();
+        if (gmode) {
+            tb = __longlong_as_double(
+                __hip_atomic_load((long long *)toi_min, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+            if (!(tb > 0.0)) {
+                exhausted = true;
+                pa = -1;
+                pb = -1;
+            }
+        }
         const bool doB = pb < 0 && pa >= 0;
         const int4 idb = ida;
         if (doB) {
@@ -627,14 +662,16 @@ __global__ __launch_bounds__(kPoolSlots) void pool_kernel(
                 const int ks = slot_split(lvp, S.mm[s], lk);
                 if (lk + 1 <= kLightMaxLevel) {
                     const double tsn = pow2neg((int)(lvp & 255u) + (ks == 0 ? 1 : 0));
-                    const double ts = __longlong_as_double((long long)S.tstar[s]);
+                    const double ts = fmin(__longlong_as_double((long long)S.tstar[s]), tb);
                     const unsigned long long nd = S.node[cur][e];
 #pragma unroll
                     for (int c = 0; c < 2; c++) {
-                        const double tl = node_tlo(child_of(nd, ks, c), tsn);
+                        const unsigned long long ch = child_of(nd, ks, c);
+                        const double tl = node_tlo(ch, tsn);
                         if (tl < ts) {
                             atomicAdd(&S.cnt[s], 1);
                             atomicMin(&S.tmin[s], (unsigned long long)__double_as_longlong(tl));
+                            if (no_zero && (ch & 0x1fffffull) == 0ull) atomicOr(&S.zmask, 1ull << s);
                         }
                     }
                 }
@@ -645,6 +682,8 @@ __global__ __launch_bounds__(kPoolSlots) void pool_kernel(
         int outcome = 0;  // 1 finished, 2 capped, 3 hand over, 4 push the next level, 5 wait
         int k = -1, push = 0, nsurv = 0;
         double tmin = __builtin_huge_val();
+        // no-zero strategy: the cap does not stop a pair that keeps a child starting at t = 0
+        const unsigned long long zm = S.zmask;
         if (active) {
             tstar = __longlong_as_double((long long)S.tstar[lane]);
             nsurv = S.nsurv[lane];
@@ -658,7 +697,7 @@ __global__ __launch_bounds__(kPoolSlots) void pool_kernel(
                 } else {
                     const int cnt = S.cnt[lane];
                     if (cnt == 0) outcome = 1;
-                    else if (nenq + cnt > max_iter) { outcome = 2; nenq += cnt; }
+                    else if (nenq + cnt > max_iter && !((zm >> lane) & 1ull)) { outcome = 2; nenq += cnt; }
                     else { outcome = 4; push = cnt; }
                 }
             }
@@ -700,7 +739,7 @@ __global__ __launch_bounds__(kPoolSlots) void pool_kernel(
             const unsigned long long ho = atomicAdd((unsigned long long *)&counters[10], (unsigned long long)nsurv);
             HeavyEntry h;
             h.pair = (int32_t)p;
-            h.pad = 0;
+            h.layout = 0;
             if ((int64_t)(ho + nsurv) <= hnode_cap) {
                 h.nnodes = nsurv;
                 h.lvl[0] = l[0]; h.lvl[1] = l[1]; h.lvl[2] = l[2];
@@ -807,6 +846,7 @@ __global__ __launch_bounds__(kPoolSlots) void pool_kernel(
         S.nsurv[lane] = 0;
         S.cnt[lane] = 0;
         S.tmin[lane] = kInfBits;
+        if (lane == 0) S.zmask = 0ull;
         const int T = total + __popcll(__ballot(root_fits)) + nmig;
         __syncthreads();
         // ---- F (all lanes over last round's entries): kept children, or hand-over survivors
@@ -818,7 +858,7 @@ __global__ __launch_bounds__(kPoolSlots) void pool_kernel(
                 const unsigned long long nd = S.node[cur][e];
                 if (ks >= 0) {
                     const double tsn = pow2neg((int)(S.lv[s] & 255u));  // levels already advanced
-                    const double ts = __longlong_as_double((long long)S.tstar[s]);
+                    const double ts = fmin(__longlong_as_double((long long)S.tstar[s]), tb);
 #pragma unroll
                     for (int c = 0; c < 2; c++) {
                         const unsigned long long ch = child_of(nd, ks, c);
@@ -870,12 +910,18 @@ __global__ __launch_bounds__(kPoolSlots) void pool_kernel(
                     }
                 q.eps[0] = S.eps[0][s]; q.eps[1] = S.eps[1][s]; q.eps[2] = S.eps[2][s];
                 const double t0 = (double)nt * tscale;
-                const int r = process(q, evf, t0, (double)(nt + 1u) * tscale, (double)nu * uscale,
-                                      (double)(nu + 1u) * uscale, (double)nw * vscale, (double)(nw + 1u) * vscale,
-                                      false, delta);
+                int r = DISCARD;  // global mode: an interval at or after the shared t* cannot lower it
+                if (t0 < tb)
+                    r = process(q, evf, t0, (double)(nt + 1u) * tscale, (double)nu * uscale,
+                                (double)(nu + 1u) * uscale, (double)nw * vscale, (double)(nw + 1u) * vscale, false,
+                                delta, no_zero && nt == 0u);
                 S.res[e] = (uint8_t)r;
-                if (r == ACCEPT) atomicMin(&S.tstar[s], (unsigned long long)__double_as_longlong(t0));
-                else if (r == SPLIT) atomicAdd(&S.nsurv[s], 1);
+                if (r == ACCEPT) {
+                    atomicMin(&S.tstar[s], (unsigned long long)__double_as_longlong(t0));
+                    if (gmode) atomicMin((unsigned long long *)toi_min, (unsigned long long)__double_as_longlong(t0));
+                } else if (r == SPLIT) {
+                    atomicAdd(&S.nsurv[s], 1);
+                }
             }
         }
         __syncthreads();
@@ -901,11 +947,11 @@ template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void heavy_kernel(
     const double *__restrict__ V0, const double *__restrict__ V1, const int4 *__restrict__ ids4,
     const double *__restrict__ peps, const uint32_t *__restrict__ pm, PairCounts pc, double delta,
-    long long max_iter, uint8_t *hit, double *toi, long long *n_enq_out, const HeavyEntry *__restrict__ heavy,
-    const unsigned long long *__restrict__ hnodes, const int32_t *list, const unsigned int *list_count,
-    unsigned int *next, int32_t *ovf_list, unsigned int *ovf_count, unsigned long long *scratch, int64_t cap,
-    uint32_t *flags, int use_lds, const unsigned int *list_base, unsigned int min_count, unsigned int max_count,
-    double *toi_min)
+    long long max_iter, uint8_t *hit, double *toi, long long *n_enq_out, HeavyEntry *heavy,
+    unsigned long long *hnodes, int64_t hnode_cap, unsigned long long *node_ctr, int resume, const int32_t *list,
+    const unsigned int *list_count, unsigned int *next, int32_t *ovf_list, unsigned int *ovf_count,
+    unsigned long long *scratch, int64_t cap, uint32_t *flags, int use_lds, const unsigned int *list_base,
+    unsigned int min_count, unsigned int max_count, double *toi_min, int gmode, int no_zero)
 {
     // Frontier of the next level: in LDS when it surely fits (at most twice the
     // current frontier), else in this workgroup's HBM buffers.
@@ -921,6 +967,9 @@ __global__ __launch_bounds__(BLOCK) void heavy_kernel(
     __shared__ int s_cnt[3][kWaves];          // children kept, per wave
     __shared__ unsigned int s_ovf[3];         // the next frontier did not fit its buffer
     __shared__ double s_tmin[kWaves];         // earliest kept child of a capped level
+    __shared__ unsigned long long s_save;     // where an overflowing pair's frontier is saved
+    __shared__ int s_zero[3];                 // a kept child starts at t = 0 (no-zero strategy)
+    __shared__ double s_tg[3];                // global mode: the shared t* read for the next level
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     int64_t n_vf, n_all;
     pc.get(n_vf, n_all);
@@ -941,7 +990,7 @@ __global__ __launch_bounds__(BLOCK) void heavy_kernel(
         const unsigned total = *list_count;
         if (idx >= (int)total) break;
         const int slot = list ? list[idx] : idx;
-        const HeavyEntry h = heavy[slot];
+        HeavyEntry h = heavy[slot];
         const int64_t p = h.pair;
         const bool vf = p < n_vf;
         double raw[24];
@@ -973,10 +1022,21 @@ __global__ __launch_bounds__(BLOCK) void heavy_kernel(
         // up to level 52) the frontier is written as three separate arrays.
         // pk_cur is the layout of the frontier being read, pk_nxt that of the
         // one being written.
-        bool pk_cur = l[0] <= kLightMaxLevel && l[1] <= kLightMaxLevel && l[2] <= kLightMaxLevel;
+        bool pk_cur = h.layout == 0 && l[0] <= kLightMaxLevel && l[1] <= kLightMaxLevel && l[2] <= kLightMaxLevel;
+        // a saved frontier larger than this round's buffers (never, as rounds only grow them) restarts
+        if (h.node_off >= 0 && nS > (pk_cur ? 3 * cap : cap)) h.node_off = -1;
+        // global mode: once the shared t* is 0 no pair can lower it
+        const double tg0 =
+            gmode ? __longlong_as_double(__hip_atomic_load((long long *)toi_min, __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT))
+                  : __builtin_huge_val();
+        if (!(tg0 > 0.0)) state = 1;
         if (h.node_off < 0) {
             // restart from the root
-            const int r = process(q, vf, 0.0, 1.0, 0.0, 1.0, 0.0, 1.0, false, delta);
+            l[0] = l[1] = l[2] = 0;
+            nenq = 0;
+            tstar = __builtin_huge_val();
+            const int r = state ? DISCARD : process(q, vf, 0.0, 1.0, 0.0, 1.0, 0.0, 1.0, false, delta, no_zero != 0);
             if (r == ACCEPT) { state = 1; tstar = 0.0; }
             else if (r == DISCARD) state = 1;
             if (tid == 0) { cur[0] = 0ull; cur[cap] = 0ull; cur[2 * cap] = 0ull; }
@@ -984,15 +1044,21 @@ __global__ __launch_bounds__(BLOCK) void heavy_kernel(
             pk_cur = true;
         } else if (pk_cur) {
             for (int64_t i = tid; i < nS; i += BLOCK) cur[i] = hnodes[h.node_off + i];
-        } else {
+        } else if (h.layout == 0) {
             for (int64_t i = tid; i < nS; i += BLOCK) {
                 const unsigned long long pk = hnodes[h.node_off + i];
                 cur[i] = pk & 0x1fffffull;
                 cur[cap + i] = (pk >> 21) & 0x1fffffull;
                 cur[2 * cap + i] = (pk >> 42) & 0x1fffffull;
             }
+        } else {
+            for (int64_t i = tid; i < nS; i += BLOCK) {
+                cur[i] = hnodes[h.node_off + i];
+                cur[cap + i] = hnodes[h.node_off + nS + i];
+                cur[2 * cap + i] = hnodes[h.node_off + 2 * nS + i];
+            }
         }
-        if (tid == 0) { s_ovf[0] = 0u; s_nN[0] = 0u; s_tl[0] = kInfBits; }
+        if (tid == 0) { s_ovf[0] = 0u; s_nN[0] = 0u; s_tl[0] = kInfBits; s_zero[0] = 0; s_tg[0] = tg0; }
         __syncthreads();
         for (int lvl = 0; state == 0; lvl++) {
             const int ps = lvl % 3, pn = (lvl + 1) % 3;
@@ -1000,7 +1066,9 @@ __global__ __launch_bounds__(BLOCK) void heavy_kernel(
             if (k < 0) break;  // unreachable: intervals at the finest level are always reported
             l[k]++;
             const bool pk_nxt = pk_cur && l[k] <= kLightMaxLevel;
-            const double tsnap = tstar;
+            // the bound children are kept under: the pair's t* (and in global
+            // mode the shared one, read once for the whole workgroup)
+            const double tsnap = fmin(tstar, s_tg[ps]);
             const double tscale = pow2neg(l[0]), uscale = pow2neg(l[1]), vscale = pow2neg(l[2]);
             const bool finest = l[0] == kMaxLevel && l[1] == kMaxLevel && l[2] == kMaxLevel;
             // where this level's survivors go
@@ -1013,7 +1081,15 @@ __global__ __launch_bounds__(BLOCK) void heavy_kernel(
                 nxt = cur == A ? Bb : A;
                 nstride = cap;
             }
-            if (tid == 0) { s_nN[pn] = 0u; s_tl[pn] = kInfBits; s_ovf[pn] = 0u; }
+            if (tid == 0) {
+                s_nN[pn] = 0u;
+                s_tl[pn] = kInfBits;
+                s_ovf[pn] = 0u;
+                s_zero[pn] = 0;
+                s_tg[pn] = gmode ? __longlong_as_double(__hip_atomic_load((long long *)toi_min, __ATOMIC_RELAXED,
+                                                                          __HIP_MEMORY_SCOPE_AGENT))
+                                 : __builtin_huge_val();
+            }
             // A narrow frontier takes one child per thread (item i is child
             // i & 1 of node i >> 1), a wide one one node and both children.
             int cnt = 0;
@@ -1022,6 +1098,7 @@ __global__ __launch_bounds__(BLOCK) void heavy_kernel(
                 const double t0 = (double)cn[0] * tscale;
                 const bool inF = has && t0 < tsnap;
                 if (inF) { cnt++; tmin = t0 < tmin ? t0 : tmin; }
+                if (inF && no_zero && cn[0] == 0ull) s_zero[ps] = 1;
                 // roots reported at this level only shorten the work, never the count
                 const double tl = __longlong_as_double((long long)(*(volatile unsigned long long *)&s_tl[ps]));
                 int r = DISCARD;
@@ -1029,9 +1106,12 @@ __global__ __launch_bounds__(BLOCK) void heavy_kernel(
                     const double t1 = (double)(cn[0] + 1ull) * tscale;
                     const double u0 = (double)cn[1] * uscale, u1 = (double)(cn[1] + 1ull) * uscale;
                     const double v0 = (double)cn[2] * vscale, v1 = (double)(cn[2] + 1ull) * vscale;
-                    r = process(q, vf, t0, t1, u0, u1, v0, v1, finest, delta);
+                    r = process(q, vf, t0, t1, u0, u1, v0, v1, finest, delta, no_zero && cn[0] == 0ull);
                 }
-                if (r == ACCEPT) atomicMin(&s_tl[ps], (unsigned long long)__double_as_longlong(t0));
+                if (r == ACCEPT) {
+                    atomicMin(&s_tl[ps], (unsigned long long)__double_as_longlong(t0));
+                    if (gmode) atomicMin((unsigned long long *)toi_min, (unsigned long long)__double_as_longlong(t0));
+                }
                 const bool surv = r == SPLIT;
                 const unsigned long long mask = __ballot(surv);
                 if (mask) {
@@ -1095,7 +1175,7 @@ __global__ __launch_bounds__(BLOCK) void heavy_kernel(
             tstar = tlev < tstar ? tlev : tstar;
             int st = 0;
             if (c_all == 0) st = 1;
-            else if (nenq + c_all > max_iter) st = 2;
+            else if (nenq + c_all > max_iter && !(no_zero && s_zero[ps])) st = 2;
             else if (s_ovf[ps]) st = 3;
             else if (nN == 0u) st = 1;
             if (st == 2) {
@@ -1107,6 +1187,13 @@ __global__ __launch_bounds__(BLOCK) void heavy_kernel(
                 for (int w = 0; w < kWaves; w++) tcap = s_tmin[w] < tcap ? s_tmin[w] : tcap;
             }
             state = st;
+            if (st == 3) {
+                // the next frontier did not fit: keep this level's start (frontier cur,
+                // levels before the split, the t* its children were filtered by, n_enq)
+                l[k]--;
+                tstar = tsnap;
+                break;
+            }
             nenq += c_all;
             nS = (int64_t)nN;
             cur = nxt;
@@ -1115,6 +1202,48 @@ __global__ __launch_bounds__(BLOCK) void heavy_kernel(
             pk_cur = pk_nxt;
         }
         __syncthreads();
+        if (state == 3 && resume) {
+            // save the level's frontier so that the next round resumes the pair from it
+            const int64_t words = pk_cur ? nS : 3 * nS;
+            if (tid == 0) {
+                const unsigned long long o = atomicAdd(node_ctr, (unsigned long long)words);
+                s_save = (int64_t)(o + words) <= hnode_cap ? o : ~0ull;
+            }
+            __syncthreads();
+            const unsigned long long o = s_save;
+            if (o != ~0ull) {
+                if (pk_cur) {
+                    for (int64_t i = tid; i < nS; i += BLOCK) hnodes[o + i] = cur[i];
+                } else {
+                    for (int64_t i = tid; i < nS; i += BLOCK) {
+                        hnodes[o + i] = cur[i];
+                        hnodes[o + nS + i] = cur[cstride + i];
+                        hnodes[o + 2 * nS + i] = cur[2 * cstride + i];
+                    }
+                }
+            }
+            if (tid == 0) {
+                HeavyEntry e;
+                e.pair = (int32_t)p;
+                if (o != ~0ull) {
+                    e.nnodes = (int32_t)nS;
+                    e.lvl[0] = l[0]; e.lvl[1] = l[1]; e.lvl[2] = l[2];
+                    e.layout = pk_cur ? 0 : 1;
+                    e.tstar = tstar;
+                    e.n_enq = nenq;
+                    e.node_off = (long long)o;
+                } else {
+                    // node buffer full: the next round restarts the pair from its root
+                    e.nnodes = 1;
+                    e.lvl[0] = e.lvl[1] = e.lvl[2] = 0;
+                    e.layout = 0;
+                    e.tstar = __builtin_huge_val();
+                    e.n_enq = 0;
+                    e.node_off = -1;
+                }
+                heavy[slot] = e;
+            }
+        }
         if (tid == 0) {
             if (state == 3) {
                 const unsigned o = atomicAdd(ovf_count, 1u);
@@ -1133,6 +1262,113 @@ __global__ __launch_bounds__(BLOCK) void heavy_kernel(
         }
         __syncthreads();
     }
+}
+
+// ---------------------------------------------------------------------------
+// d0: distance between a pair's primitives at t = 0 (Sec. 7 sets the minimum
+// separation relative to it).  Plain float64 arithmetic, one rounding per
+// operation (contraction off), correctly rounded division and square root.
+// ---------------------------------------------------------------------------
+struct P3 {
+    double x, y, z;
+};
+
+__device__ __forceinline__ P3 vsub(P3 a, P3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ __forceinline__ double vdot(P3 a, P3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ P3 vload(const double *__restrict__ V, int32_t i)
+{
+    return {V[3 * (int64_t)i], V[3 * (int64_t)i + 1], V[3 * (int64_t)i + 2]};
+}
+
+// |p - q| for q the point of the closed segment [a, b] nearest to p: the
+// projection parameter clamped to [0, 1]
+__device__ double dist_point_segment(P3 p, P3 a, P3 b)
+{
+    const P3 ab = vsub(b, a), ap = vsub(p, a);
+    const double len2 = vdot(ab, ab);
+    double s = 0.0;
+    if (len2 > 0.0) s = fmin(fmax(vdot(ap, ab) / len2, 0.0), 1.0);
+    const P3 r = {ap.x - s * ab.x, ap.y - s * ab.y, ap.z - s * ab.z};
+    return sqrt(vdot(r, r));
+}
+
+// |p - q| for q the point of the closed triangle (a, b, c) nearest to p: the
+// orthogonal projection when its barycentric coordinates (u, v) are inside,
+// otherwise the nearest of the three edges
+__device__ double dist_point_triangle(P3 p, P3 a, P3 b, P3 c)
+{
+    const P3 e0 = vsub(b, a), e1 = vsub(c, a), ap = vsub(p, a);
+    const double g00 = vdot(e0, e0), g01 = vdot(e0, e1), g11 = vdot(e1, e1);
+    const double r0 = vdot(ap, e0), r1 = vdot(ap, e1);
+    const double det = g00 * g11 - g01 * g01;
+    if (det > 0.0) {
+        const double u = (g11 * r0 - g01 * r1) / det;
+        const double v = (g00 * r1 - g01 * r0) / det;
+        if (u >= 0.0 && v >= 0.0 && u + v <= 1.0) {
+            const P3 r = {ap.x - u * e0.x - v * e1.x, ap.y - u * e0.y - v * e1.y, ap.z - u * e0.z - v * e1.z};
+            return sqrt(vdot(r, r));
+        }
+    }
+    return fmin(fmin(dist_point_segment(p, a, b), dist_point_segment(p, b, c)), dist_point_segment(p, a, c));
+}
+
+// distance between the closed segments [a0, a1] and [b0, b1]: the smallest
+// endpoint-to-segment distance, or the interior stationary point of
+// |a0 + s (a1 - a0) - b0 - r (b1 - b0)| when it lies in the unit square
+__device__ double dist_segment_segment(P3 a0, P3 a1, P3 b0, P3 b1)
+{
+    const P3 da = vsub(a1, a0), db = vsub(b1, b0), w = vsub(a0, b0);
+    const double A = vdot(da, da), B = vdot(da, db), C = vdot(db, db), D = vdot(da, w), Ew = vdot(db, w);
+    const double det = A * C - B * B;
+    double best = fmin(fmin(dist_point_segment(a0, b0, b1), dist_point_segment(a1, b0, b1)),
+                       fmin(dist_point_segment(b0, a0, a1), dist_point_segment(b1, a0, a1)));
+    if (det > 0.0) {
+        const double s = (B * Ew - C * D) / det, r = (A * Ew - B * D) / det;
+        if (s >= 0.0 && s <= 1.0 && r >= 0.0 && r <= 1.0) {
+            const P3 d = {w.x + s * da.x - r * db.x, w.y + s * da.y - r * db.y, w.z + s * da.z - r * db.z};
+            best = fmin(best, sqrt(vdot(d, d)));
+        }
+    }
+    return best;
+}
+
+// out[p] = scale * d0 of pair p (scale 1: d0 itself).  A pair with an index
+// out of range gets 0 and raises the flag.
+__global__ __launch_bounds__(256) void initial_distance_kernel(const double *__restrict__ V0, int64_t nv,
+                                                              const int32_t *__restrict__ vf,
+                                                              const int32_t *__restrict__ ee, PairCounts pc,
+                                                              const int32_t *__restrict__ E, int64_t ne,
+                                                              const int32_t *__restrict__ F, int64_t nf, double scale,
+                                                              double *out, uint32_t *flags)
+{
+    int64_t n_vf, n;
+    pc.get(n_vf, n);
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= n) return;
+    int32_t id[4] = {-1, -1, -1, -1};
+    bool ok;
+    if (p < n_vf) {
+        const int32_t v = vf[2 * p], f = vf[2 * p + 1];
+        ok = v >= 0 && v < nv && f >= 0 && f < nf;
+        if (ok) { id[0] = v; id[1] = F[3 * (int64_t)f]; id[2] = F[3 * (int64_t)f + 1]; id[3] = F[3 * (int64_t)f + 2]; }
+    } else {
+        const int64_t q = p - n_vf;
+        const int32_t e = ee[2 * q], g = ee[2 * q + 1];
+        ok = e >= 0 && e < ne && g >= 0 && g < ne;
+        if (ok) {
+            id[0] = E[2 * (int64_t)e]; id[1] = E[2 * (int64_t)e + 1];
+            id[2] = E[2 * (int64_t)g]; id[3] = E[2 * (int64_t)g + 1];
+        }
+    }
+    for (int k = 0; k < 4; k++) ok = ok && id[k] >= 0 && id[k] < nv;
+    if (!ok) {
+        atomicOr(flags, FLAG_BAD_INDEX);
+        out[p] = 0.0;
+        return;
+    }
+    const P3 x0 = vload(V0, id[0]), x1 = vload(V0, id[1]), x2 = vload(V0, id[2]), x3 = vload(V0, id[3]);
+    const double d = p < n_vf ? dist_point_triangle(x0, x1, x2, x3) : dist_segment_segment(x0, x1, x2, x3);
+    out[p] = scale * d;
 }
 
 // Earliest time of impact of every scene of a batch: the scene of a pair is
@@ -1209,8 +1445,8 @@ void launch_narrow_prep(const double *V0, const double *V1, int64_t nv, const in
     counters_zero_kernel<<<1, 64, 0, s>>>(B.counters, 16, B.flags, nullptr, B.toi_min);
     const int64_t n = pc.capacity();
     if (n == 0) return;
-    prep_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(V0, V1, nv, vf, ee, pc, E, ne, F, nf, delta, B.ids4,
-                                                           B.eps, B.m, B.flags);
+    prep_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(V0, V1, nv, vf, ee, pc, E, ne, F, nf, delta, B.mode.ms,
+                                                           B.ids4, B.eps, B.m, B.flags);
 }
 
 void launch_narrow_prep_feat(const double *V0, const double *V1, int64_t nv, const int32_t *E, int64_t ne,
@@ -1222,8 +1458,8 @@ void launch_narrow_prep_feat(const double *V0, const double *V1, int64_t nv, con
     counters_zero_kernel<<<1, 256, 0, s>>>(B.counters, 16, B.flags, hist, B.toi_min);
     const int64_t n = pc.capacity();
     if (n == 0) return;
-    prep_feat_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(V0, V1, nv, vf, ee, pc, E, ne, F, nf, delta, B.ids4,
-                                                                B.eps, B.m, B.flags, feat, params,
+    prep_feat_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(V0, V1, nv, vf, ee, pc, E, ne, F, nf, delta,
+                                                                B.mode.ms, B.ids4, B.eps, B.m, B.flags, feat, params,
                                                                 (mlp_bf16x4 *)packed);
 }
 
@@ -1245,7 +1481,7 @@ void launch_narrow_pool(const double *V0, const double *V1, PairCounts pc, doubl
     if (blocks > pool_blocks) blocks = pool_blocks;
     pool_kernel<<<(unsigned)blocks, kPoolSlots, 0, s>>>(V0, V1, B.ids4, B.eps, B.m, pc, delta, max_iter, hit, toi,
                                                        n_enq, B.heavy, B.hnodes, B.hnode_cap, B.counters, order,
-                                                       order_n, wait, B.toi_min);
+                                                       order_n, wait, B.toi_min, B.mode.global, B.mode.no_zero);
 }
 
 namespace {
@@ -1256,42 +1492,41 @@ constexpr unsigned int kWideFew = 256;
 
 void heavy_variant(int block, int nslots, unsigned int lo, unsigned int hi, const double *V0, const double *V1,
                    PairCounts pc, double delta, long long max_iter, uint8_t *hit, double *toi, long long *n_enq,
-                   const NarrowBuffers &B, const int32_t *list, const unsigned int *count, unsigned int *next,
-                   int32_t *ovf, unsigned int *ovf_count, unsigned long long *scratch, int64_t cap, int use_lds,
-                   const unsigned int *base, hipStream_t s)
+                   const NarrowBuffers &B, int resume, const int32_t *list, const unsigned int *count,
+                   unsigned int *next, int32_t *ovf, unsigned int *ovf_count, unsigned long long *scratch, int64_t cap,
+                   int use_lds, const unsigned int *base, hipStream_t s)
 {
+    unsigned long long *node_ctr = (unsigned long long *)&B.counters[10];
+#define CCD_HEAVY_ARGS                                                                                             \
+    V0, V1, B.ids4, B.eps, B.m, pc, delta, max_iter, hit, toi, n_enq, B.heavy, B.hnodes, B.hnode_cap, node_ctr,  \
+        resume, list, count, next, ovf, ovf_count, scratch, cap, B.flags, use_lds, base, lo, hi, B.toi_min,   \
+        B.mode.global, B.mode.no_zero
     if (block == 1024)
-        heavy_kernel<1024><<<(unsigned)nslots, 1024, 0, s>>>(V0, V1, B.ids4, B.eps, B.m, pc, delta, max_iter, hit,
-                                                            toi, n_enq, B.heavy, B.hnodes, list, count, next, ovf,
-                                                            ovf_count, scratch, cap, B.flags, use_lds, base, lo, hi,
-                                                            B.toi_min);
+        heavy_kernel<1024><<<(unsigned)nslots, 1024, 0, s>>>(CCD_HEAVY_ARGS);
     else if (block == 64)
-        heavy_kernel<64><<<(unsigned)nslots, 64, 0, s>>>(V0, V1, B.ids4, B.eps, B.m, pc, delta, max_iter, hit, toi,
-                                                        n_enq, B.heavy, B.hnodes, list, count, next, ovf, ovf_count,
-                                                        scratch, cap, B.flags, use_lds, base, lo, hi, B.toi_min);
+        heavy_kernel<64><<<(unsigned)nslots, 64, 0, s>>>(CCD_HEAVY_ARGS);
     else
-        heavy_kernel<256><<<(unsigned)nslots, 256, 0, s>>>(V0, V1, B.ids4, B.eps, B.m, pc, delta, max_iter, hit, toi,
-                                                          n_enq, B.heavy, B.hnodes, list, count, next, ovf, ovf_count,
-                                                          scratch, cap, B.flags, use_lds, base, lo, hi, B.toi_min);
+        heavy_kernel<256><<<(unsigned)nslots, 256, 0, s>>>(CCD_HEAVY_ARGS);
+#undef CCD_HEAVY_ARGS
 }
 
 // block 0: adaptive (both variants, each for its range of entry counts).
 void heavy_launch(int block, int nslots, const double *V0, const double *V1, PairCounts pc, double delta,
-                  long long max_iter, uint8_t *hit, double *toi, long long *n_enq, const NarrowBuffers &B,
+                  long long max_iter, uint8_t *hit, double *toi, long long *n_enq, const NarrowBuffers &B, int resume,
                   const int32_t *list, const unsigned int *count, unsigned int *next, int32_t *ovf,
                   unsigned int *ovf_count, unsigned long long *scratch, int64_t cap, int use_lds,
                   const unsigned int *base, hipStream_t s)
 {
     if (block != 0) {
-        heavy_variant(block, nslots, 0u, 0xffffffffu, V0, V1, pc, delta, max_iter, hit, toi, n_enq, B, list, count,
-                      next, ovf, ovf_count, scratch, cap, use_lds, base, s);
+        heavy_variant(block, nslots, 0u, 0xffffffffu, V0, V1, pc, delta, max_iter, hit, toi, n_enq, B, resume, list,
+                      count, next, ovf, ovf_count, scratch, cap, use_lds, base, s);
         return;
     }
     const int few = nslots < (int)kWideFew ? nslots : (int)kWideFew;
-    heavy_variant(1024, few, 0u, kWideFew, V0, V1, pc, delta, max_iter, hit, toi, n_enq, B, list, count, next, ovf,
-                  ovf_count, scratch, cap, use_lds, base, s);
-    heavy_variant(256, nslots, kWideFew + 1, 0xffffffffu, V0, V1, pc, delta, max_iter, hit, toi, n_enq, B, list,
-                  count, next, ovf, ovf_count, scratch, cap, use_lds, base, s);
+    heavy_variant(1024, few, 0u, kWideFew, V0, V1, pc, delta, max_iter, hit, toi, n_enq, B, resume, list, count, next,
+                  ovf, ovf_count, scratch, cap, use_lds, base, s);
+    heavy_variant(256, nslots, kWideFew + 1, 0xffffffffu, V0, V1, pc, delta, max_iter, hit, toi, n_enq, B, resume,
+                  list, count, next, ovf, ovf_count, scratch, cap, use_lds, base, s);
 }
 
 }  // namespace
@@ -1301,7 +1536,7 @@ void launch_narrow_heavy(const double *V0, const double *V1, PairCounts pc, doub
                          int64_t cap, int round, int use_lds, int block, hipStream_t s)
 {
     // counters: [0] handed-over pairs, [1] work index of the first round,
-    // [2] / [3] overflow counts of list 0 / 1, [4] work index of re-runs,
+    // [2] / [3] overflow counts of list 0 / 1, [4] work index of later rounds,
     // [12] entries the early wide stage took (the first round starts past them).
     const unsigned int *base = &B.counters[12];
     const int32_t *list = nullptr;
@@ -1315,11 +1550,13 @@ void launch_narrow_heavy(const double *V0, const double *V1, PairCounts pc, doub
         next = &B.counters[4];
         base = nullptr;
         rerun_reset_kernel<<<1, 1, 0, s>>>(B.counters, round);
-        // re-runs hold the widest frontiers: always the many-pairs variant
-        if (block == 0) block = 256;
+        // later rounds hold the widest frontiers: 1,024 threads per pair
+        if (block == 0) block = 1024;
     }
-    heavy_launch(block, nslots, V0, V1, pc, delta, max_iter, hit, toi, n_enq, B, list, count, next, ovf, ovf_count,
-                 B.scratch, cap, use_lds, base, s);
+    // only the first round saves an overflowing level; later rounds that
+    // overflow again resume from the same saved level with larger buffers
+    heavy_launch(block, nslots, V0, V1, pc, delta, max_iter, hit, toi, n_enq, B, round == 0 ? 1 : 0, list, count,
+                 next, ovf, ovf_count, B.scratch, cap, use_lds, base, s);
 }
 
 void launch_narrow_heavy_early(const double *V0, const double *V1, PairCounts pc, double delta, long long max_iter,
@@ -1327,8 +1564,18 @@ void launch_narrow_heavy_early(const double *V0, const double *V1, PairCounts pc
                                unsigned long long *scratch, int nslots, int64_t cap, int use_lds, int block,
                                hipStream_t s)
 {
-    heavy_launch(block, nslots, V0, V1, pc, delta, max_iter, hit, toi, n_enq, B, nullptr, &B.counters[12],
+    heavy_launch(block, nslots, V0, V1, pc, delta, max_iter, hit, toi, n_enq, B, 1, nullptr, &B.counters[12],
                  &B.counters[13], B.overflow_list[0], &B.counters[2], scratch, cap, use_lds, nullptr, s);
+}
+
+void launch_initial_distance(const double *V0, int64_t nv, const int32_t *E, int64_t ne, const int32_t *F, int64_t nf,
+                             const int32_t *vf, const int32_t *ee, PairCounts pc, double scale, double *out,
+                             uint32_t *flags, hipStream_t s)
+{
+    const int64_t n = pc.capacity();
+    if (n == 0) return;
+    initial_distance_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(V0, nv, vf, ee, pc, E, ne, F, nf, scale, out,
+                                                                       flags);
 }
 
 void launch_scene_min(const double *toi, PairCounts pc, const int32_t *vf, const int32_t *ee, const int64_t *v_off,

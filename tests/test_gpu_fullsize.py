@@ -215,3 +215,73 @@ def test_detect_bench_workload_matches_oracle(ctx):
     assert np.array_equal(t.view(np.int64), ot.view(np.int64)), np.nonzero(t != ot)[0][:10]
     assert np.array_equal(e, on_), np.nonzero(e != on_)[0][:10]
     assert np.float64(tmin.cpu()[0]).view(np.int64) == np.float64(omin).view(np.int64)
+
+
+def _torus_manifest(s):
+    """The oracle's answer on the 1M-triangle torus with 12,000 gadgets: the committed manifest when its input
+    hash matches these inputs, else computed now by the same oracle-only script (slow: tens of minutes)."""
+    import json
+    import os
+    import sys
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    sys.path.insert(0, here)
+    import make_torus_manifest as mk
+    try:
+        man = json.load(open(mk.OUT))
+    except (OSError, ValueError):
+        man = None
+    if man is None or man.get("input_sha256") != mk.scene_hash(s):
+        print("manifest missing or stale: running the oracle on the full workload", flush=True)
+        vf, ee = oracle.broad(s.V0, s.V1, s.E, s.F)
+        hit, toi, n_enq, _, _, tmin = oracle.narrow_with_work(s.V0, s.V1, s.E, s.F, vf, ee, DELTA, 10 ** 6)
+        capped = n_enq > 10 ** 6
+        man = {"n_vf": len(vf), "n_ee": len(ee), "pairs_sha256": mk.pairs_hash(vf, ee),
+               "results_sha256": mk.results_hash(vf, ee, hit, toi, n_enq),
+               "toi_min_bits": int(np.float64(tmin).view(np.int64)), "capped_pairs": int(capped.sum()),
+               "toi_min_from_capped_pair": bool(np.any(capped & (toi == tmin))),
+               "toi_min_uncapped": float(toi[~capped].min()) if np.any(~capped) else float("inf")}
+    return mk, man
+
+
+@pytest.mark.timeout(1800)
+def test_torus_with_gadgets_full(ctx):
+    """The benchmark's workload whole: ccd_detect (learned schedule, as timed, and plain) on the 1M-triangle torus
+    with 12,000 near-degenerate gadgets.  The candidate set and every pair's hit, TOI bits and n_enq equal the
+    oracle's (brute-force broad phase, per-pair narrow phase), compared through hashes of the canonically
+    sorted pairs and results; the earliest time is identical; Alg. 3's single shared t* gives the same earliest
+    time when the oracle's earliest pair is not a capped one, and stays within the allowed range otherwise."""
+    from paper_2112_06300_amd import sched
+    s = scenes.perturbed_torus(seed=3, gadgets=sched.TORUS_GADGETS)
+    print(f"torus full: nv={s.nv} ne={s.ne} nf={s.nf}", flush=True)
+    mk, man = _torus_manifest(s)
+    V0, V1, E, F = dev(s.V0, torch.float64), dev(s.V1, torch.float64), dev(s.E, torch.int32), dev(s.F, torch.int32)
+    cap_vf, cap_ee = man["n_vf"] + 1024, man["n_ee"] + 1024
+    vf = torch.empty((cap_vf, 2), dtype=torch.int32, device="cuda")
+    ee = torch.empty((cap_ee, 2), dtype=torch.int32, device="cuda")
+    n = cap_vf + cap_ee
+    hit = torch.empty(n, dtype=torch.uint8, device="cuda")
+    toi = torch.empty(n, dtype=torch.float64, device="cuda")
+    tmin = torch.empty(1, dtype=torch.float64, device="cuda")
+    nenq = torch.empty(n, dtype=torch.int64, device="cuda")
+    p, nm, _ = sched.load_model(sched.TORUS_MODEL_PATH)
+    learned = ccd.prepare_schedule(("learned", dev(p, torch.float32), dev(nm, torch.float32),
+                                    ccd.TORUS_HEAVY_THRESHOLD, ccd.TORUS_MAX_HEAVY))
+    for name, sc in (("learned", learned), ("plain", None)):
+        n_vf, n_ee = ctx.detect_into(V0, V1, E, F, vf, ee, hit, toi, tmin, nenq, DELTA, 10 ** 6, schedule=sc)
+        torch.cuda.synchronize()
+        print(f"{name}: {n_vf} + {n_ee} pairs, stats {ctx.stats()}", flush=True)
+        assert (n_vf, n_ee) == (man["n_vf"], man["n_ee"])
+        gvf, gee = vf[:n_vf].cpu().numpy(), ee[:n_ee].cpu().numpy()
+        m = n_vf + n_ee
+        assert mk.pairs_hash(gvf, gee) == man["pairs_sha256"]
+        assert mk.results_hash(gvf, gee, hit[:m].cpu().numpy(), toi[:m].cpu().numpy(),
+                               nenq[:m].cpu().numpy()) == man["results_sha256"]
+        assert int(np.float64(tmin.cpu()[0]).view(np.int64)) == man["toi_min_bits"]
+    # Alg. 3's shared t*
+    ctx.detect_into(V0, V1, E, F, vf, ee, hit, toi, tmin, None, DELTA, 10 ** 6, options={"earliest_only": 1})
+    g = float(tmin.cpu()[0])
+    o = float(np.int64(man["toi_min_bits"]).view(np.float64))
+    if not man["toi_min_from_capped_pair"]:
+        assert np.float64(g).view(np.int64) == man["toi_min_bits"]
+    else:
+        assert o <= g <= man["toi_min_uncapped"]

@@ -267,15 +267,23 @@ def test_end_to_end_cloth(ctx):
     V0, V1 = dev(s.V0, torch.float64), dev(s.V1, torch.float64)
     E, F = dev(s.E, torch.int32), dev(s.F, torch.int32)
     gvf, gee = ctx.broad(V0, V1, E, F)
-    hit, toi, tmin, _ = ctx.narrow(V0, V1, E, F, gvf, gee, DELTA, 10 ** 6)
+    hit, toi, tmin, nenq = ctx.narrow(V0, V1, E, F, gvf, gee, DELTA, 10 ** 6, with_costs=True)
     ovf, oee = oracle.broad(s.V0, s.V1, s.E, s.F)
-    oh, ot, _, _, omin = oracle.narrow(s.V0, s.V1, s.E, s.F, ovf, oee)
-    assert float(tmin.cpu()[0]) == omin
-    # per-pair results keyed by pair
-    g = {("vf",) + tuple(p): (h, t) for p, h, t in zip(gvf.cpu().numpy(), hit.cpu().numpy()[:len(gvf)],
-                                                         toi.cpu().numpy()[:len(gvf)])}
-    for p, h, t in zip(ovf, oh[:len(ovf)], ot[:len(ovf)]):
-        assert g[("vf",) + tuple(p)] == (h, t)
+    oh, ot, on_, _, omin = oracle.narrow(s.V0, s.V1, s.E, s.F, ovf, oee)
+    assert np.float64(tmin.cpu()[0]).view(np.int64) == np.float64(omin).view(np.int64)
+    # per-pair results keyed by pair, vertex-face and edge-edge
+    nvf = len(gvf)
+    hit, toi, nenq = hit.cpu().numpy(), toi.cpu().numpy().view(np.int64), nenq.cpu().numpy()
+    g = {("vf",) + tuple(p): (hit[i], toi[i], nenq[i]) for i, p in enumerate(gvf.cpu().numpy())}
+    g.update({("ee",) + tuple(p): (hit[nvf + i], toi[nvf + i], nenq[nvf + i])
+              for i, p in enumerate(gee.cpu().numpy())})
+    assert len(g) == len(ovf) + len(oee)
+    ot = ot.view(np.int64)
+    for i, p in enumerate(ovf):
+        assert g[("vf",) + tuple(p)] == (oh[i], ot[i], on_[i])
+    for i, p in enumerate(oee):
+        j = len(ovf) + i
+        assert g[("ee",) + tuple(p)] == (oh[j], ot[j], on_[j])
 
 
 @pytest.mark.parametrize("tuning", [{"heavy_lds": 1}, {"heavy_lds": 1, "heavy_cap_log2": 8, "heavy_slots": 16},

@@ -206,3 +206,17 @@ def test_initial_distance_brute_force(kind):
             span = np.linalg.norm(P[1] - P[0]) + np.linalg.norm(P[3] - P[2])
         assert d <= dist.min() + 1e-12
         assert dist.min() - d <= span / 64
+
+
+# --------------------------------------------------------------------------- timing sample of the broad phase
+def test_broad_sample_covers_its_share_of_rows():
+    """stride 1 is the whole brute force (same pair counts, every box test); larger strides run a part of the rows
+    and never find more pairs."""
+    s = scenes.cloth_on_sphere(n=20, sphere_subdivisions=2, seed=3)
+    vf, ee = oracle.broad(s.V0, s.V1, s.E, s.F)
+    nvf, nee, tvf, tee = oracle.broad_sample(s.V0, s.V1, s.E, s.F, 1)
+    assert (nvf, nee) == (len(vf), len(ee))
+    assert tvf == s.nv * s.nf and tee == s.ne * (s.ne - 1) / 2
+    nvf4, nee4, tvf4, tee4 = oracle.broad_sample(s.V0, s.V1, s.E, s.F, 4)
+    assert nvf4 <= len(vf) and nee4 <= len(ee)
+    assert 0.15 < tvf4 / tvf < 0.35 and 0.15 < tee4 / tee < 0.35
