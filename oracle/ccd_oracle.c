@@ -197,15 +197,20 @@ static void run_broad(const float *lo, const float *hi, int64_t nv, int64_t ne, 
             for (int64_t r = jobs[b].row_begin; r < jobs[b].row_end; r++)
                 *tests += kind == 0 ? (double)nf : (double)(ne - 1 - r);
     }
-    /* static round-robin of blocks over threads */
-    for (int64_t base = 0; base < nblocks; base += nthreads) {
+    /* static round-robin of the non-empty blocks over threads */
+    int64_t *run = (int64_t *)malloc((size_t)nblocks * sizeof(int64_t));
+    int64_t nrun = 0;
+    for (int64_t b = 0; b < nblocks; b++)
+        if (jobs[b].row_end > jobs[b].row_begin) run[nrun++] = b;
+    for (int64_t base = 0; base < nrun; base += nthreads) {
         pthread_t th[256];
         int cnt = 0;
-        for (int t = 0; t < nthreads && base + t < nblocks; t++, cnt++)
-            pthread_create(&th[t], NULL, broad_worker, &jobs[base + t]);
+        for (int t = 0; t < nthreads && base + t < nrun; t++, cnt++)
+            pthread_create(&th[t], NULL, broad_worker, &jobs[run[base + t]]);
         for (int t = 0; t < cnt; t++)
             pthread_join(th[t], NULL);
     }
+    free(run);
     int64_t total = 0;
     for (int64_t b = 0; b < nblocks; b++) total += jobs[b].out.n;
     int32_t *res = (int32_t *)malloc((size_t)(total > 0 ? total : 1) * 2 * sizeof(int32_t));
