@@ -289,6 +289,30 @@ ccd_status ccd_toi_step(ccd_context *ctx, const double *V0, const double *V1, in
                         double delta, int64_t max_iter, double ms_factor, double scale,
                         double *toi, int32_t *rerun, void *stream);
 
+/*
+ * ccd_narrow for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same arguments, outputs and errors, with every workspace of the narrow
+ * phase taken from a fixed 96 MiB array that each GPU the library runs on
+ * holds until the process ends (the pool of the context is not used and
+ * nothing is allocated or freed).  Limits: at most ccd_narrow_noalloc_max_pairs
+ * pairs (about 350,000), the plain schedule and no options; wide-stage
+ * frontiers grow only within the array's 24 MiB frontier part (beyond it
+ * CCD_ERR_CAPACITY).  CCD_ERR_CAPACITY for more pairs than the limit.  Calls
+ * on one GPU share the array: calls that overlap in time on the same GPU
+ * (several threads or streams) race and must not be made.  Synchronizes
+ * `stream`.
+ */
+ccd_status ccd_narrow_noalloc(ccd_context *ctx, const double *V0, const double *V1, int64_t nv,
+                              const int32_t *E, int64_t ne, const int32_t *F, int64_t nf,
+                              const int32_t *vf, int64_t n_vf, const int32_t *ee, int64_t n_ee,
+                              double delta, int64_t max_iter,
+                              uint8_t *hit, double *toi, double *toi_min, int64_t *n_enq, void *stream);
+
+/* The most pairs ccd_narrow_noalloc takes on this context's device (0 if the
+ * fixed workspace is unavailable). */
+int64_t ccd_narrow_noalloc_max_pairs(ccd_context *ctx);
+
 /* Scheduling features of every pair: feat is a DEVICE (n_vf + n_ee) x
  * CCD_NUM_FEATURES float32 array, VF pairs first (zeros for a pair with an
  * index out of range, which also makes the call fail with INVALID_ARG). */

@@ -32,7 +32,7 @@ EXPORTED = ["ccd_create", "ccd_destroy", "ccd_last_error", "ccd_version", "ccd_b
             "ccd_narrow_sched", "ccd_detect", "ccd_features", "ccd_mlp_predict", "ccd_mlp_grad", "ccd_adam_step",
             "ccd_get_stats", "ccd_set_tuning", "ccd_get_tuning", "ccd_batch_create", "ccd_batch_destroy",
             "ccd_batch_run", "ccd_batch_autotune", "ccd_narrow_ex", "ccd_detect_ex", "ccd_initial_distance",
-            "ccd_toi_step"]
+            "ccd_toi_step", "ccd_narrow_noalloc", "ccd_narrow_noalloc_max_pairs"]
 
 NUM_FEATURES = 16
 HIDDEN = 64
@@ -152,6 +152,11 @@ def load_library(path=LIB_PATH):
                                  ctypes.POINTER(i64), ctypes.c_double, i64, ctypes.c_double, ctypes.c_double,
                                  ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32), P]
     lib.ccd_toi_step.restype = ctypes.c_int
+    lib.ccd_narrow_noalloc.argtypes = [P, P, P, i64, P, i64, P, i64, P, i64, P, i64, ctypes.c_double, i64,
+                                       P, P, P, P, P]
+    lib.ccd_narrow_noalloc.restype = ctypes.c_int
+    lib.ccd_narrow_noalloc_max_pairs.argtypes = [P]
+    lib.ccd_narrow_noalloc_max_pairs.restype = i64
     lib.ccd_get_stats.argtypes = [P, ctypes.POINTER(Stats)]
     lib.ccd_get_stats.restype = ctypes.c_int
     _lib = lib
@@ -353,6 +358,29 @@ class Context:
                                     ctypes.byref(sch), _stream(stream)))
         del keep
         return hit, toi, tmin, nenq
+
+    def narrow_noalloc(self, V0, V1, E, F, vf, ee, hit, toi, tmin, nenq=None, delta=1e-6, max_iter=10**6,
+                       stream=None):
+        """ccd_narrow into preallocated outputs without any device allocation by the library (its workspace is
+        a fixed per-GPU array): for callers that cannot allocate.  Raises CCDError (CCD_ERR_CAPACITY above
+        noalloc_max_pairs())."""
+        import torch
+        lib = load_library()
+        _require_scene(V0, V1, E, F, self.device)
+        _require(vf, "vf", torch.int32, self.device, cols=2)
+        _require(ee, "ee", torch.int32, self.device, cols=2)
+        n = vf.shape[0] + ee.shape[0]
+        _require(hit, "hit", torch.uint8, self.device, min_numel=n)
+        _require(toi, "toi", torch.float64, self.device, min_numel=n)
+        _require(tmin, "toi_min", torch.float64, self.device, min_numel=1)
+        if nenq is not None:
+            _require(nenq, "n_enq", torch.int64, self.device, min_numel=n)
+        _check(lib.ccd_narrow_noalloc(self._h, _ptr(V0), _ptr(V1), V0.shape[0], _ptr(E), E.shape[0], _ptr(F),
+                                      F.shape[0], _ptr(vf), vf.shape[0], _ptr(ee), ee.shape[0], float(delta),
+                                      int(max_iter), _ptr(hit), _ptr(toi), _ptr(tmin), _ptr(nenq), _stream(stream)))
+
+    def noalloc_max_pairs(self):
+        return int(load_library().ccd_narrow_noalloc_max_pairs(self._h))
 
     def detect_into(self, V0, V1, E, F, vf, ee, hit, toi, tmin, nenq=None, delta=1e-6, max_iter=10**6,
                     schedule=None, stream=None, options=None):

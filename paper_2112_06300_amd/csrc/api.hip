@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "ccd_internal.h"
@@ -66,6 +67,36 @@ size_t aligned_total(std::initializer_list<size_t> sizes)
 
 }  // namespace
 
+// Workspace of the allocation-free narrow phase (ccd_narrow_noalloc): one
+// array per GPU, held until the process ends.  Host code never uses its name
+// as an address: its device address comes from hipGetSymbolAddress, once per
+// device (noalloc_base).  The last kNoAllocFrontierBytes hold the wide stage's
+// frontier buffers, the rest the per-pair workspace.
+constexpr size_t kNoAllocBytes = (size_t)96 << 20;
+constexpr size_t kNoAllocFrontierBytes = (size_t)64 * 6 * 8192 * 8;  // 64 wide-stage slots of 8,192 intervals
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+
+std::mutex g_noalloc_mu;
+void *g_noalloc_ptr[256] = {};
+
+// Device address of this device's allocation-free workspace (the device must
+// be current); null if the runtime cannot give it.
+void *noalloc_base(int device)
+{
+    if (device < 0 || device >= 256) return nullptr;
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (!g_noalloc_ptr[device]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) == hipSuccess) g_noalloc_ptr[device] = p;
+        else (void)hipGetLastError();
+    }
+    return g_noalloc_ptr[device];
+}
+
+}  // namespace
+
 struct ccd_context {
     int device = 0;
     Pool broad, narrow, scratch, sched, aux;
@@ -77,6 +108,8 @@ struct ccd_context {
     char arch[64] = "gfx950";
     ccd_tuning tune{};
     hipStream_t side = nullptr;  // second stream: the learned schedule's early wide stage
+    char *noalloc = nullptr;       // this device's allocation-free workspace (device address)
+    int64_t noalloc_max_pairs = 0; // pairs its per-pair part holds
 };
 
 namespace {
@@ -275,6 +308,20 @@ ccd_status ccd_create(int device, ccd_context **out)
             if (*q == ':' || *q == ' ') { *q = 0; break; }
     }
     c->pool_per_cu_max = pool_blocks_per_cu();
+    c->noalloc = (char *)noalloc_base(device);
+    if (c->noalloc) {
+        // the most pairs whose narrow workspace fits beside the frontier buffers
+        int64_t lo = 0, hi = (int64_t)(kNoAllocBytes / 64);
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) / 2;
+            Carver m(nullptr);
+            NarrowBuffers nb;
+            narrow_carve(m, mid, nb);
+            if (m.bytes() <= kNoAllocBytes - kNoAllocFrontierBytes) lo = mid;
+            else hi = mid - 1;
+        }
+        c->noalloc_max_pairs = lo;
+    }
     if (hipHostMalloc(&c->host, 4096, hipHostMallocDefault) != hipSuccess) {
         delete c;
         return fail(CCD_ERR_OOM, "could not allocate pinned host staging");
@@ -462,6 +509,10 @@ struct NarrowCall {
     int nslots = 0;
     int64_t cap = 0;
     bool learned = false;
+    // allocation-free calls: the wide stage's frontier buffers are this fixed
+    // region (never grown); null = the context's pool
+    unsigned long long *fixed_frontier = nullptr;
+    size_t fixed_bytes = 0;
 };
 
 // Every kernel of a narrow call on stream s, stages timed by ev[0..6].  The
@@ -489,9 +540,18 @@ ccd_status narrow_enqueue(ccd_context *c, const double *V0, const double *V1, in
     const int64_t cap = call.cap;
     const int max_early = learned ? (int)std::min<int64_t>(sched->max_heavy, n) : 0;
     const int early_slots = max_early > 0 ? std::min(max_early, nslots) : 0;
-    ccd_status st = ensure(c->scratch, (size_t)(nslots + early_slots) * 6 * cap * 8);
-    if (st != CCD_OK) return st;
-    B.scratch = (unsigned long long *)c->scratch.base;
+    if (call.fixed_frontier) {
+        // as many of the tuned slots as the fixed region holds
+        call.nslots = (int)std::min<size_t>((size_t)nslots, call.fixed_bytes / ((size_t)6 * cap * 8));
+        if (call.nslots < 1 || early_slots > 0)
+            return fail(CCD_ERR_CAPACITY, "wide-stage buffers of 2^%d intervals do not fit the fixed workspace",
+                        c->tune.heavy_cap_log2);
+        B.scratch = call.fixed_frontier;
+    } else {
+        ccd_status st = ensure(c->scratch, (size_t)(nslots + early_slots) * 6 * cap * 8);
+        if (st != CCD_OK) return st;
+        B.scratch = (unsigned long long *)c->scratch.base;
+    }
 
     long long *nenq = (long long *)n_enq;
     const uint32_t *order_n = nullptr;
@@ -533,8 +593,8 @@ ccd_status narrow_enqueue(ccd_context *c, const double *V0, const double *V1, in
                        c->tune.pool_wait, s);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(c->ev[2], s));
-    launch_narrow_heavy(V0, V1, pc, delta, (long long)max_iter, hit, toi, nenq, B, nslots, cap, 0, c->tune.heavy_lds,
-                        c->tune.heavy_block, s);
+    launch_narrow_heavy(V0, V1, pc, delta, (long long)max_iter, hit, toi, nenq, B, call.nslots, cap, 0,
+                        c->tune.heavy_lds, c->tune.heavy_block, s);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(c->ev[3], s));
     if (learned && early_slots > 0) HIP_TRY(hipStreamWaitEvent(s, c->ev[6], 0));
@@ -547,19 +607,25 @@ ccd_status narrow_enqueue(ccd_context *c, const double *V0, const double *V1, in
 // intervals, which no pair below the cap can outgrow (a level's frontier holds
 // at most its kept children), as far as device memory allows, on one
 // 1,024-thread workgroup per compute unit; a further round (memory-limited
-// buffers) takes 8x larger ones.  `pool` holds the frontier buffers.
-ccd_status rerun_overflowed(ccd_context *c, NarrowBuffers B, Pool &pool, unsigned int overflowed, int64_t cap,
+// buffers) takes 8x larger ones.  `pool` holds the frontier buffers; with a
+// null pool they are the fixed region of `fixed_bytes` at `fixed` (no
+// allocation: a frontier that outgrows it is a capacity error).
+ccd_status rerun_overflowed(ccd_context *c, NarrowBuffers B, Pool *pool, unsigned int overflowed, int64_t cap,
                             const double *V0, const double *V1, PairCounts pc, double delta, int64_t max_iter,
-                            uint8_t *hit, double *toi, long long *nenq, hipStream_t s, float *ms_total)
+                            uint8_t *hit, double *toi, long long *nenq, hipStream_t s, float *ms_total,
+                            unsigned long long *fixed = nullptr, size_t fixed_bytes = 0)
 {
     int round = 0;
     unsigned int *hr = (unsigned int *)c->host;
     while (overflowed > 0) {
         round++;
         c->stats.heavy_reruns += overflowed;
-        size_t free_b = 0, total_b = 0;
-        HIP_TRY(hipMemGetInfo(&free_b, &total_b));
-        const size_t budget = pool.bytes + free_b / 2;
+        size_t budget = fixed_bytes;
+        if (pool) {
+            size_t free_b = 0, total_b = 0;
+            HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+            budget = pool->bytes + free_b / 2;
+        }
         int64_t want = cap * 8;
         if (round == 1) {
             int64_t need = cap;
@@ -568,14 +634,27 @@ ccd_status rerun_overflowed(ccd_context *c, NarrowBuffers B, Pool &pool, unsigne
         }
         const size_t slots_wanted = std::min<size_t>((size_t)c->cus, (size_t)overflowed);
         while (want > cap * 8 && slots_wanted * (size_t)6 * want * 8 > budget) want /= 2;
+        if (!pool) {
+            // a fixed region: the largest buffers it holds, as long as they grow
+            while (want > cap && (size_t)6 * want * 8 > budget) want /= 2;
+            if (want <= cap)
+                return fail(CCD_ERR_CAPACITY, "interval frontier of %u pairs exceeds the fixed workspace",
+                            overflowed);
+        }
         cap = want;
         const size_t per_slot = (size_t)6 * cap * 8;
+        if (!pool && per_slot > budget)
+            return fail(CCD_ERR_CAPACITY, "interval frontier of %u pairs exceeds the fixed workspace", overflowed);
         if (per_slot > budget || round > 12)
             return fail(CCD_ERR_OOM, "interval frontier of %u pairs exceeds device memory", overflowed);
         const int nslots = (int)std::min<size_t>(slots_wanted, budget / per_slot);
-        ccd_status st = ensure(pool, (size_t)nslots * per_slot);
-        if (st != CCD_OK) return st;
-        B.scratch = (unsigned long long *)pool.base;
+        if (pool) {
+            ccd_status st = ensure(*pool, (size_t)nslots * per_slot);
+            if (st != CCD_OK) return st;
+            B.scratch = (unsigned long long *)pool->base;
+        } else {
+            B.scratch = fixed;
+        }
         HIP_TRY(hipEventRecord(c->ev[0], s));
         launch_narrow_heavy(V0, V1, pc, delta, (long long)max_iter, hit, toi, nenq, B, nslots, cap, round,
                             c->tune.heavy_lds, c->tune.heavy_block == 0 ? 0 : c->tune.heavy_block, s);
@@ -622,8 +701,9 @@ ccd_status narrow_finish(ccd_context *c, const unsigned int *h, const double *V0
         return fail(CCD_ERR_INVALID_ARG, "minimum separation must be finite, >= 0 and at most 2^960");
     // pairs whose frontier outgrew their buffer: resumed with larger buffers
     float ms_rerun = 0.f;
-    ccd_status st = rerun_overflowed(c, B, c->scratch, h[2], call.cap, V0, V1, pc, delta, max_iter, hit, toi,
-                                     (long long *)n_enq, s, &ms_rerun);
+    ccd_status st = rerun_overflowed(c, B, call.fixed_frontier ? nullptr : &c->scratch, h[2], call.cap, V0, V1, pc,
+                                     delta, max_iter, hit, toi, (long long *)n_enq, s, &ms_rerun, call.fixed_frontier,
+                                     call.fixed_bytes);
     c->stats.narrow_ms += ms_rerun;
     c->stats.narrow_heavy_ms += ms_rerun;
     (void)toi_min;
@@ -823,6 +903,47 @@ ccd_status ccd_initial_distance(ccd_context *c, const double *V0, int64_t nv, co
     g_err.clear();
     return CCD_OK;
 }
+
+ccd_status ccd_narrow_noalloc(ccd_context *c, const double *V0, const double *V1, int64_t nv, const int32_t *E,
+                              int64_t ne, const int32_t *F, int64_t nf, const int32_t *vf, int64_t n_vf,
+                              const int32_t *ee, int64_t n_ee, double delta, int64_t max_iter, uint8_t *hit,
+                              double *toi, double *toi_min, int64_t *n_enq, void *stream)
+{
+    if (!c || !toi_min) return fail(CCD_ERR_INVALID_ARG, "NULL context or toi_min");
+    if (max_iter < 1) return fail(CCD_ERR_INVALID_ARG, "max_iter must be >= 1");
+    if (nv < 0 || ne < 0 || nf < 0 || n_vf < 0 || n_ee < 0) return fail(CCD_ERR_INVALID_ARG, "negative size");
+    if (!(delta > 0.0) || !std::isfinite(delta)) return fail(CCD_ERR_INVALID_ARG, "delta must be finite and > 0");
+    const int64_t n = n_vf + n_ee;
+    if ((n > 0 && (!hit || !toi)) || (nv && (!V0 || !V1)) || (ne && !E) || (nf && !F) || (n_vf && !vf) ||
+        (n_ee && !ee))
+        return fail(CCD_ERR_INVALID_ARG, "NULL pointer with nonzero size");
+    if (!c->noalloc) return fail(CCD_ERR_DEVICE, "the allocation-free workspace has no device address");
+    if (n > c->noalloc_max_pairs)
+        return fail(CCD_ERR_CAPACITY, "the allocation-free narrow phase takes at most %lld pairs, got %lld",
+                    (long long)c->noalloc_max_pairs, (long long)n);
+    HIP_TRY(hipSetDevice(c->device));
+    NarrowCall call;
+    Carver cv(c->noalloc);
+    narrow_carve(cv, n, call.B);
+    call.fixed_frontier = (unsigned long long *)(c->noalloc + (kNoAllocBytes - kNoAllocFrontierBytes));
+    call.fixed_bytes = kNoAllocFrontierBytes;
+    hipStream_t s = (hipStream_t)stream;
+    const PairCounts pc{n_vf, n_ee, nullptr};
+    const SchedBuffers S{};
+    ccd_status st = narrow_enqueue(c, V0, V1, nv, E, ne, F, nf, vf, ee, pc, delta, max_iter, hit, toi, toi_min, n_enq,
+                                   nullptr, nullptr, S, s, call);
+    if (st != CCD_OK) return st;
+    unsigned int *h = (unsigned int *)c->host;
+    HIP_TRY(hipMemcpyAsync(h, call.B.counters, 16 * 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(h + 16, call.B.flags, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    st = narrow_finish(c, h, V0, V1, pc, delta, max_iter, hit, toi, toi_min, n_enq, s, call);
+    if (st != CCD_OK) return st;
+    g_err.clear();
+    return CCD_OK;
+}
+
+int64_t ccd_narrow_noalloc_max_pairs(ccd_context *c) { return c ? c->noalloc_max_pairs : 0; }
 
 ccd_status ccd_toi_step(ccd_context *c, const double *V0, const double *V1, int64_t nv, const int32_t *E, int64_t ne,
                         const int32_t *F, int64_t nf, int32_t *vf, int64_t vf_cap, int64_t *n_vf, int32_t *ee,
@@ -1083,7 +1204,7 @@ ccd_status batch_pass(ccd_batch *b, const BatchArgs &a, bool use_graph, int64_t 
     if (overflowed > 0) {
         const PairCounts pc{*n_vf, *n_ee, nullptr};
         Pool big;
-        st = rerun_overflowed(c, b->N, big, overflowed, b->heavy_cap, a.V0, a.V1, pc, a.delta, a.max_iter, a.hit,
+        st = rerun_overflowed(c, b->N, &big, overflowed, b->heavy_cap, a.V0, a.V1, pc, a.delta, a.max_iter, a.hit,
                               a.toi, a.n_enq, s, nullptr);
         if (big.base) (void)hipFree(big.base);
         if (st != CCD_OK) return st;
