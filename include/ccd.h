@@ -313,6 +313,54 @@ ccd_status ccd_narrow_noalloc(ccd_context *ctx, const double *V0, const double *
  * fixed workspace is unavailable). */
 int64_t ccd_narrow_noalloc_max_pairs(ccd_context *ctx);
 
+/*
+ * Broad and narrow phase of one scene within a device-memory budget (Sec. 5.4,
+ * batching): for a scene whose candidate pairs, with their narrow-phase data,
+ * do not fit at once.
+ *
+ * The boxes are built, sorted and gathered once (they must fit: about 80 bytes
+ * per box).  What the budget leaves sizes the batches: a pair capacity S_C
+ * from the bytes each pair needs (the pair, its result and its narrow-phase
+ * workspace), and the rest holds the wide stage's frontier buffers.  The sweep
+ * runs over ranges of its query tiles (each pair is found by exactly one
+ * tile); a range whose pairs exceed S_C is split in two and swept again
+ * (broad-phase overflow splits the boxes).  Each batch's pairs then go to the
+ * narrow phase; when a frontier outgrows the buffers the budget leaves, the
+ * narrow phase runs again on each half of the pairs, which frees workspace for
+ * larger buffers (narrow-phase overflow halves the pairs), down to single
+ * pairs.  The earliest time of impact is kept over all batches.
+ *
+ *   budget_bytes  device memory the call may use beyond the caller's buffers
+ *   opts          narrow-phase options (ccd_narrow_options; min_sep must be NULL)
+ *   toi_min       HOST: earliest time of impact over all pairs (+inf if none)
+ *   out           HOST counts, and optionally every pair and result (NULL arrays
+ *                 are skipped; pairs beyond a capacity are counted, not stored)
+ *
+ * Results equal those of ccd_detect on the whole scene (the same pairs, in
+ * another order, with the same per-pair hit and TOI; with earliest_only the
+ * same toi_min guarantee).  Errors: CCD_ERR_OOM when the boxes or a single
+ * pair's frontier do not fit the budget; otherwise as ccd_detect.
+ * Synchronizes `stream`.
+ */
+typedef struct {
+    int64_t n_vf, n_ee;          /* candidate pairs found */
+    int64_t n_hits;              /* pairs with hit = 1 */
+    int64_t broad_batches;       /* tile ranges whose pairs went to the narrow phase */
+    int64_t broad_splits;        /* tile ranges split after their pairs overflowed S_C */
+    int64_t narrow_splits;       /* narrow calls re-run on halves after a frontier overflow */
+    int64_t pair_capacity;       /* S_C */
+    int32_t *vf; int64_t vf_cap; /* HOST, vf_cap x 2, or NULL */
+    int32_t *ee; int64_t ee_cap; /* HOST, ee_cap x 2, or NULL */
+    uint8_t *vf_hit, *ee_hit;    /* HOST, per stored pair, or NULL */
+    double *vf_toi, *ee_toi;     /* HOST, per stored pair, or NULL */
+} ccd_budget_result;
+
+ccd_status ccd_detect_budget(ccd_context *ctx, const double *V0, const double *V1, int64_t nv,
+                             const int32_t *E, int64_t ne, const int32_t *F, int64_t nf,
+                             int64_t budget_bytes, double delta, int64_t max_iter,
+                             const ccd_narrow_options *opts, double *toi_min, ccd_budget_result *out,
+                             void *stream);
+
 /* Scheduling features of every pair: feat is a DEVICE (n_vf + n_ee) x
  * CCD_NUM_FEATURES float32 array, VF pairs first (zeros for a pair with an
  * index out of range, which also makes the call fail with INVALID_ARG). */

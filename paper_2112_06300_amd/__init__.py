@@ -32,7 +32,7 @@ EXPORTED = ["ccd_create", "ccd_destroy", "ccd_last_error", "ccd_version", "ccd_b
             "ccd_narrow_sched", "ccd_detect", "ccd_features", "ccd_mlp_predict", "ccd_mlp_grad", "ccd_adam_step",
             "ccd_get_stats", "ccd_set_tuning", "ccd_get_tuning", "ccd_batch_create", "ccd_batch_destroy",
             "ccd_batch_run", "ccd_batch_autotune", "ccd_narrow_ex", "ccd_detect_ex", "ccd_initial_distance",
-            "ccd_toi_step", "ccd_narrow_noalloc", "ccd_narrow_noalloc_max_pairs"]
+            "ccd_toi_step", "ccd_narrow_noalloc", "ccd_narrow_noalloc_max_pairs", "ccd_detect_budget"]
 
 NUM_FEATURES = 16
 HIDDEN = 64
@@ -72,6 +72,15 @@ class Schedule(ctypes.Structure):
 class NarrowOptions(ctypes.Structure):
     _fields_ = [("earliest_only", ctypes.c_int32), ("no_zero_toi", ctypes.c_int32), ("min_sep", ctypes.c_void_p),
                 ("min_sep_d0_factor", ctypes.c_double)]
+
+
+class BudgetResult(ctypes.Structure):
+    _fields_ = [("n_vf", ctypes.c_int64), ("n_ee", ctypes.c_int64), ("n_hits", ctypes.c_int64),
+                ("broad_batches", ctypes.c_int64), ("broad_splits", ctypes.c_int64),
+                ("narrow_splits", ctypes.c_int64), ("pair_capacity", ctypes.c_int64),
+                ("vf", ctypes.c_void_p), ("vf_cap", ctypes.c_int64), ("ee", ctypes.c_void_p),
+                ("ee_cap", ctypes.c_int64), ("vf_hit", ctypes.c_void_p), ("ee_hit", ctypes.c_void_p),
+                ("vf_toi", ctypes.c_void_p), ("ee_toi", ctypes.c_void_p)]
 
 
 # Learned schedule defaults: predictions of log2(1 + n_enq) from which a pair starts in the wide stage, and
@@ -157,6 +166,10 @@ def load_library(path=LIB_PATH):
     lib.ccd_narrow_noalloc.restype = ctypes.c_int
     lib.ccd_narrow_noalloc_max_pairs.argtypes = [P]
     lib.ccd_narrow_noalloc_max_pairs.restype = i64
+    lib.ccd_detect_budget.argtypes = [P, P, P, i64, P, i64, P, i64, i64, ctypes.c_double, i64,
+                                      ctypes.POINTER(NarrowOptions), ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(BudgetResult), P]
+    lib.ccd_detect_budget.restype = ctypes.c_int
     lib.ccd_get_stats.argtypes = [P, ctypes.POINTER(Stats)]
     lib.ccd_get_stats.restype = ctypes.c_int
     _lib = lib
@@ -421,6 +434,41 @@ class Context:
                                   _ptr(nenq), ctypes.byref(sch) if sch is not None else None, _stream(stream)))
         del keep
         return n_vf.value, n_ee.value
+
+    def detect_budget(self, V0, V1, E, F, budget_bytes, delta=1e-6, max_iter=10**6, options=None, vf_cap=0,
+                      ee_cap=0, stream=None):
+        """Broad + narrow phase within a device-memory budget (ccd_detect_budget).  Returns (toi_min, info) with
+        info the counts and, when vf_cap / ee_cap > 0, host numpy arrays vf, ee, vf_hit, ee_hit, vf_toi, ee_toi
+        of the first stored pairs (batch order)."""
+        import numpy as np
+        import torch
+        lib = load_library()
+        _require_scene(V0, V1, E, F, self.device)
+        r = BudgetResult()
+        keep = {}
+        if vf_cap > 0:
+            keep["vf"] = np.zeros((vf_cap, 2), np.int32)
+            keep["vf_hit"] = np.zeros(vf_cap, np.uint8)
+            keep["vf_toi"] = np.zeros(vf_cap, np.float64)
+        if ee_cap > 0:
+            keep["ee"] = np.zeros((ee_cap, 2), np.int32)
+            keep["ee_hit"] = np.zeros(ee_cap, np.uint8)
+            keep["ee_toi"] = np.zeros(ee_cap, np.float64)
+        for k, a in keep.items():
+            setattr(r, k, a.ctypes.data)
+        r.vf_cap, r.ee_cap = int(vf_cap), int(ee_cap)
+        opt, okeep = _options(options, self.device, 0) if options is not None else (None, None)
+        t = ctypes.c_double()
+        _check(lib.ccd_detect_budget(self._h, _ptr(V0), _ptr(V1), V0.shape[0], _ptr(E), E.shape[0], _ptr(F),
+                                     F.shape[0], int(budget_bytes), float(delta), int(max_iter),
+                                     ctypes.byref(opt) if opt is not None else None, ctypes.byref(t),
+                                     ctypes.byref(r), _stream(stream)))
+        info = {k: getattr(r, k) for k in ("n_vf", "n_ee", "n_hits", "broad_batches", "broad_splits",
+                                           "narrow_splits", "pair_capacity")}
+        kv, ke = min(r.n_vf, vf_cap), min(r.n_ee, ee_cap)
+        for k, a in keep.items():
+            info[k] = a[:kv] if k.startswith("vf") else a[:ke]
+        return t.value, info
 
     def initial_distance(self, V0, E, F, vf, ee, stream=None):
         """d0 of every pair (distance of its primitives at t = 0), float64 on the device, VF pairs first."""

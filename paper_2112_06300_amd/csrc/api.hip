@@ -7,8 +7,11 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <cstddef>
 #include <mutex>
 #include <string>
+#include <utility>
+#include <vector>
 
 #include "ccd_internal.h"
 
@@ -99,7 +102,7 @@ void *noalloc_base(int device)
 
 struct ccd_context {
     int device = 0;
-    Pool broad, narrow, scratch, sched, aux;
+    Pool broad, narrow, scratch, sched, aux, budget;
     void *host = nullptr;  // pinned host staging for counters and flags
     hipEvent_t ev[12] = {};  // narrow stages 0..6, broad stages 7..11
     ccd_stats stats{};
@@ -346,7 +349,7 @@ void ccd_destroy(ccd_context *c)
 {
     if (!c) return;
     (void)hipSetDevice(c->device);
-    for (Pool *p : {&c->broad, &c->narrow, &c->scratch, &c->sched, &c->aux})
+    for (Pool *p : {&c->broad, &c->narrow, &c->scratch, &c->sched, &c->aux, &c->budget})
         if (p->base) (void)hipFree(p->base);
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
@@ -939,6 +942,217 @@ ccd_status ccd_narrow_noalloc(ccd_context *c, const double *V0, const double *V1
     HIP_TRY(hipStreamSynchronize(s));
     st = narrow_finish(c, h, V0, V1, pc, delta, max_iter, hit, toi, toi_min, n_enq, s, call);
     if (st != CCD_OK) return st;
+    g_err.clear();
+    return CCD_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// State of one ccd_detect_budget call.
+struct BudgetRun {
+    ccd_context *c;
+    const double *V0, *V1;
+    int64_t nv, ne, nf;
+    const int32_t *E, *F;
+    double delta;
+    int64_t max_iter;
+    const ccd_narrow_options *opts;
+    hipStream_t s;
+    char *narrow_base;   // first byte after the broad workspace and the batch buffers
+    char *end;           // end of the budget
+    double *tmin_dev;
+    double tmin = __builtin_huge_val();
+    int64_t narrow_splits = 0;
+};
+
+// The narrow phase on vf[0..n_vf) and ee[0..n_ee) (device), results written
+// contiguously (VF pairs first) to hit / toi.  Its workspace is carved after
+// the batch buffers and the frontier buffers take the rest of the budget; a
+// frontier that outgrows them re-runs the phase on halves of the pairs (by
+// pair type first), which leaves larger buffers to each half.
+ccd_status budget_narrow(BudgetRun &r, const int32_t *vf, int64_t n_vf, const int32_t *ee, int64_t n_ee, uint8_t *hit,
+                         double *toi)
+{
+    ccd_context *c = r.c;
+    const int64_t n = n_vf + n_ee;
+    if (n == 0) return CCD_OK;
+    NarrowCall call;
+    Carver cv(r.narrow_base);
+    narrow_carve(cv, n, call.B);
+    const size_t used = (cv.off + 255) & ~size_t(255);
+    const size_t room = (size_t)(r.end - r.narrow_base) > used ? (size_t)(r.end - r.narrow_base) - used : 0;
+    call.fixed_frontier = (unsigned long long *)(r.narrow_base + used);
+    call.fixed_bytes = room;
+    ccd_status st = CCD_ERR_CAPACITY;
+    const PairCounts pc{n_vf, n_ee, nullptr};
+    if (room >= (size_t)6 * 8 * ((size_t)1 << c->tune.heavy_cap_log2)) {
+        apply_options(r.opts, call.B, r.V0, r.nv, r.E, r.ne, r.F, r.nf, vf, ee, pc, r.s);
+        st = narrow_enqueue(c, r.V0, r.V1, r.nv, r.E, r.ne, r.F, r.nf, vf, ee, pc, r.delta, r.max_iter, hit, toi,
+                            r.tmin_dev, nullptr, nullptr, nullptr, SchedBuffers{}, r.s, call);
+        if (st == CCD_OK) {
+            unsigned int *h = (unsigned int *)c->host;
+            HIP_TRY(hipMemcpyAsync(h, call.B.counters, 16 * 4, hipMemcpyDeviceToHost, r.s));
+            HIP_TRY(hipMemcpyAsync(h + 16, call.B.flags, 4, hipMemcpyDeviceToHost, r.s));
+            HIP_TRY(hipStreamSynchronize(r.s));
+            unsigned int hc[17];
+            std::memcpy(hc, h, sizeof hc);
+            st = narrow_finish(c, hc, r.V0, r.V1, pc, r.delta, r.max_iter, hit, toi, r.tmin_dev, nullptr, r.s, call);
+        }
+    }
+    if (st == CCD_OK) {
+        double t = 0.0;
+        HIP_TRY(hipMemcpyAsync(&t, r.tmin_dev, 8, hipMemcpyDeviceToHost, r.s));
+        HIP_TRY(hipStreamSynchronize(r.s));
+        r.tmin = t < r.tmin ? t : r.tmin;
+        return CCD_OK;
+    }
+    if (st != CCD_ERR_CAPACITY) return st;
+    if (n == 1) return fail(CCD_ERR_OOM, "one pair's interval frontier does not fit the memory budget");
+    r.narrow_splits++;
+    if (n_vf > 0 && n_ee > 0) {
+        st = budget_narrow(r, vf, n_vf, nullptr, 0, hit, toi);
+        if (st != CCD_OK) return st;
+        return budget_narrow(r, nullptr, 0, ee, n_ee, hit + n_vf, toi + n_vf);
+    }
+    const int64_t h = n / 2;
+    if (n_vf > 0) {
+        st = budget_narrow(r, vf, h, nullptr, 0, hit, toi);
+        if (st != CCD_OK) return st;
+        return budget_narrow(r, vf + 2 * h, n_vf - h, nullptr, 0, hit + h, toi + h);
+    }
+    st = budget_narrow(r, nullptr, 0, ee, h, hit, toi);
+    if (st != CCD_OK) return st;
+    return budget_narrow(r, nullptr, 0, ee + 2 * h, n_ee - h, hit + h, toi + h);
+}
+
+// Bytes of the batch buffers and narrow workspace for a pair capacity S.
+size_t budget_pair_bytes(int64_t S)
+{
+    Carver m(nullptr);
+    m.take<int32_t>(2 * (size_t)S);  // vf
+    m.take<int32_t>(2 * (size_t)S);  // ee
+    m.take<uint8_t>((size_t)S);      // hit
+    m.take<double>((size_t)S);       // toi
+    m.take<double>(1);               // the batch's earliest time
+    NarrowBuffers nb;
+    narrow_carve(m, S, nb);
+    return m.bytes();
+}
+
+}  // namespace
+
+extern "C" {
+
+ccd_status ccd_detect_budget(ccd_context *c, const double *V0, const double *V1, int64_t nv, const int32_t *E,
+                             int64_t ne, const int32_t *F, int64_t nf, int64_t budget_bytes, double delta,
+                             int64_t max_iter, const ccd_narrow_options *opts, double *toi_min,
+                             ccd_budget_result *out, void *stream)
+{
+    if (!c || !toi_min || !out) return fail(CCD_ERR_INVALID_ARG, "NULL context, toi_min or out");
+    if (budget_bytes <= 0) return fail(CCD_ERR_INVALID_ARG, "budget_bytes must be > 0");
+    if (max_iter < 1) return fail(CCD_ERR_INVALID_ARG, "max_iter must be >= 1");
+    if (!(delta > 0.0) || !std::isfinite(delta)) return fail(CCD_ERR_INVALID_ARG, "delta must be finite and > 0");
+    if (nv < 0 || ne < 0 || nf < 0) return fail(CCD_ERR_INVALID_ARG, "negative size");
+    if (nv > INT32_MAX || ne > INT32_MAX || nf > INT32_MAX || nv + ne + nf > (int64_t)UINT32_MAX)
+        return fail(CCD_ERR_INVALID_ARG, "scene too large for 32-bit ids");
+    if ((nv && (!V0 || !V1)) || (ne && !E) || (nf && !F)) return fail(CCD_ERR_INVALID_ARG, "NULL pointer with nonzero size");
+    if (out->vf_cap < 0 || out->ee_cap < 0) return fail(CCD_ERR_INVALID_ARG, "negative output capacity");
+    ccd_status st = check_options(opts, false);
+    if (st != CCD_OK) return st;
+    HIP_TRY(hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t nb = nv + ne + nf;
+    const int64_t nbl = sort_blocks(nb);
+    BroadBuffers B;
+    Carver mb(nullptr);
+    broad_carve(mb, nb, 1, nbl, B);
+    const size_t broad_bytes = (mb.bytes() + 255) & ~size_t(255);
+    // the pair capacity: the batch buffers and narrow workspace of S pairs, and at
+    // least one wide-stage buffer, within the budget
+    const size_t min_front = (size_t)6 * 8 * ((size_t)1 << c->tune.heavy_cap_log2);
+    const size_t budget = (size_t)budget_bytes;
+    if (broad_bytes + budget_pair_bytes(1) + min_front > budget)
+        return fail(CCD_ERR_OOM, "the scene's %lld boxes do not fit a budget of %lld bytes", (long long)nb,
+                    (long long)budget_bytes);
+    int64_t lo = 1, hi = std::min<int64_t>((int64_t)(budget / 16), INT32_MAX / 2);
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo + 1) / 2;
+        if (broad_bytes + budget_pair_bytes(mid) + min_front <= budget) lo = mid;
+        else hi = mid - 1;
+    }
+    const int64_t S = lo;
+    st = ensure(c->budget, budget);
+    if (st != CCD_OK) return st;
+    Carver cv(c->budget.base);
+    broad_carve(cv, nb, 1, nbl, B);
+    cv.off = broad_bytes;
+    int32_t *vfb = cv.take<int32_t>(2 * (size_t)S);
+    int32_t *eeb = cv.take<int32_t>(2 * (size_t)S);
+    uint8_t *hitb = cv.take<uint8_t>((size_t)S);
+    double *toib = cv.take<double>((size_t)S);
+    BudgetRun r{c, V0, V1, nv, ne, nf, E, F, delta, max_iter, opts, s, nullptr, c->budget.base + budget, nullptr};
+    r.tmin_dev = cv.take<double>(1);
+    r.narrow_base = c->budget.base + ((cv.off + 255) & ~size_t(255));
+
+    std::memset(out, 0, offsetof(ccd_budget_result, vf));
+    out->pair_capacity = S;
+    launch_broad_boxes(V0, V1, nv, E, ne, F, nf, B, s);
+    launch_broad_sort(nv, ne, nf, B, nbl, s);
+    launch_broad_gather(E, F, nv, ne, nf, B, s);
+    HIP_TRY(hipGetLastError());
+    // query-tile ranges still to sweep (a stack: the first half of a split goes first)
+    std::vector<std::pair<int64_t, int64_t>> ranges;
+    const int64_t nt = sweep_tiles(nv, ne, nf);
+    if (nt > 0) ranges.push_back({0, nt});
+    unsigned long long *h = (unsigned long long *)c->host;
+    std::vector<uint8_t> hits;
+    while (!ranges.empty()) {
+        const auto rg = ranges.back();
+        ranges.pop_back();
+        launch_broad_counts_zero(B, s);
+        launch_broad_sweep(nv, ne, nf, vfb, S, eeb, S, B, c->tune.sweep_tile_group, s, rg.first, rg.second);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(h, B.counts, 16, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(h + 2, B.flags, 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        const uint32_t flags = (uint32_t)(h[2] & 0xffffffffu);
+        if (flags & FLAG_BAD_INDEX) return fail(CCD_ERR_INVALID_ARG, "edge or face vertex id out of range");
+        if (flags & FLAG_NONFINITE) return fail(CCD_ERR_NONFINITE, "non-finite or too large (> 2^960) coordinate");
+        const int64_t bvf = (int64_t)h[0], bee = (int64_t)h[1];
+        if (bvf + bee > S) {
+            // broad-phase overflow: the range's boxes in two batches
+            if (rg.second - rg.first == 1)
+                return fail(CCD_ERR_OOM, "the %lld pairs of one sweep tile exceed the budget's %lld",
+                            (long long)(bvf + bee), (long long)S);
+            const int64_t mid = (rg.first + rg.second) / 2;
+            ranges.push_back({mid, rg.second});
+            ranges.push_back({rg.first, mid});
+            out->broad_splits++;
+            continue;
+        }
+        out->broad_batches++;
+        st = budget_narrow(r, vfb, bvf, eeb, bee, hitb, toib);
+        if (st != CCD_OK) return st;
+        // the batch's pairs and results to the host
+        hits.resize((size_t)(bvf + bee));
+        if (bvf + bee) HIP_TRY(hipMemcpyAsync(hits.data(), hitb, (size_t)(bvf + bee), hipMemcpyDeviceToHost, s));
+        const int64_t kv = std::max<int64_t>(0, std::min<int64_t>(bvf, out->vf_cap - out->n_vf));
+        const int64_t ke = std::max<int64_t>(0, std::min<int64_t>(bee, out->ee_cap - out->n_ee));
+        if (out->vf && kv) HIP_TRY(hipMemcpyAsync(out->vf + 2 * out->n_vf, vfb, (size_t)kv * 8, hipMemcpyDeviceToHost, s));
+        if (out->ee && ke) HIP_TRY(hipMemcpyAsync(out->ee + 2 * out->n_ee, eeb, (size_t)ke * 8, hipMemcpyDeviceToHost, s));
+        if (out->vf_toi && kv) HIP_TRY(hipMemcpyAsync(out->vf_toi + out->n_vf, toib, (size_t)kv * 8, hipMemcpyDeviceToHost, s));
+        if (out->ee_toi && ke) HIP_TRY(hipMemcpyAsync(out->ee_toi + out->n_ee, toib + bvf, (size_t)ke * 8, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (out->vf_hit && kv) std::memcpy(out->vf_hit + out->n_vf, hits.data(), (size_t)kv);
+        if (out->ee_hit && ke) std::memcpy(out->ee_hit + out->n_ee, hits.data() + bvf, (size_t)ke);
+        for (uint8_t x : hits) out->n_hits += x ? 1 : 0;
+        out->n_vf += bvf;
+        out->n_ee += bee;
+    }
+    out->narrow_splits = r.narrow_splits;
+    *toi_min = r.tmin;
     g_err.clear();
     return CCD_OK;
 }

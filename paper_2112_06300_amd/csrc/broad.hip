@@ -649,15 +649,18 @@ __global__ __launch_bounds__(kTile) void sweep_kernel(
     const K *__restrict__ klo, const K *__restrict__ khi, const float *__restrict__ lob,
     const float *__restrict__ hib, const float *__restrict__ loc, const float *__restrict__ hic,
     const int32_t *__restrict__ pid, const int32_t *__restrict__ vtx, int64_t nv, int64_t ne, int64_t nf,
-    int64_t tiles_v, int64_t tiles_e, int64_t ntiles, int64_t tiles_grid, int64_t group, SweepChunks ch,
-    int32_t *__restrict__ vf, int64_t vf_cap, int32_t *__restrict__ ee, int64_t ee_cap, unsigned long long *counts)
+    int64_t tiles_v, int64_t tiles_e, int64_t tile0, int64_t tile1, int64_t tiles_grid, int64_t group,
+    SweepChunks ch, int32_t *__restrict__ vf, int64_t vf_cap, int32_t *__restrict__ ee, int64_t ee_cap,
+    unsigned long long *counts)
 {
     __shared__ int32_t s_out[kOutCap][2];
     const int64_t nb = nv + ne + nf, f0 = nv + ne;
-    // block = chunk * tiles_grid + (tile slot); tiles_grid is a multiple of 8 * group
+    // block = chunk * tiles_grid + (tile slot); tiles_grid is a multiple of 8 * group.
+    // The sweep covers the query tiles [tile0, tile1): the pairs whose earlier
+    // box in sorted order lies in them.
     const int64_t chunk = (int64_t)blockIdx.x / tiles_grid;
-    const int64_t t = xcd_tile((int64_t)blockIdx.x % tiles_grid, group);
-    if (t >= ntiles) return;
+    const int64_t t = tile0 + xcd_tile((int64_t)blockIdx.x % tiles_grid, group);
+    if (t >= tile1) return;
     const SweepRecords R{lob, hib, loc, hic, pid, vtx};
     if (t < tiles_v) {
         if (chunk >= ch.vf) return;
@@ -744,14 +747,30 @@ void launch_broad_gather(const int32_t *E, const int32_t *F, int64_t nv, int64_t
                                                    B.lob, B.hib, B.loc, B.hic, B.pid, B.vtx);
 }
 
+int64_t sweep_tiles(int64_t nv, int64_t ne, int64_t nf)
+{
+    return (nv + kTile - 1) / kTile + (ne + kTile - 1) / kTile + (nf + kTile - 1) / kTile;
+}
+
+__global__ void counts_zero_kernel(unsigned long long *counts)
+{
+    if (threadIdx.x < 2) counts[threadIdx.x] = 0ull;
+}
+
+void launch_broad_counts_zero(const BroadBuffers &B, hipStream_t s) { counts_zero_kernel<<<1, 64, 0, s>>>(B.counts); }
+
 void launch_broad_sweep(int64_t nv, int64_t ne, int64_t nf, int32_t *vf, int64_t vf_cap, int32_t *ee,
-                        int64_t ee_cap, const BroadBuffers &B, int64_t tile_group, hipStream_t s)
+                        int64_t ee_cap, const BroadBuffers &B, int64_t tile_group, hipStream_t s, int64_t tile0,
+                        int64_t tile1)
 {
     const int64_t nb = nv + ne + nf;
     if (nb == 0) return;
     const int64_t tv = (nv + kTile - 1) / kTile, te = (ne + kTile - 1) / kTile, tf = (nf + kTile - 1) / kTile;
-    const int64_t nt = tv + te + tf;
-    if (nt == 0) return;
+    const int64_t nt_all = tv + te + tf;
+    if (tile1 < 0 || tile1 > nt_all) tile1 = nt_all;
+    if (tile0 < 0) tile0 = 0;
+    const int64_t nt = tile1 - tile0;
+    if (nt <= 0) return;
     const int64_t g = tile_group < 1 ? 1 : tile_group;
     const int64_t tiles_grid = (nt + 8 * g - 1) / (8 * g) * (8 * g);
     // Measured (cloth on sphere, 7k tiles: 768 x 5 / 2 best; perturbed torus,
@@ -761,12 +780,12 @@ void launch_broad_sweep(int64_t nv, int64_t ne, int64_t nf, int32_t *vf, int64_t
     const int64_t grid = tiles_grid * (ch.ee > ch.vf ? ch.ee : ch.vf);
     if (B.nscenes > 1)
         sweep_kernel<unsigned long long><<<(unsigned)grid, kTile, 0, s>>>(
-            B.klo64, B.khi64, B.lob, B.hib, B.loc, B.hic, B.pid, B.vtx, nv, ne, nf, tv, te, nt, tiles_grid, g, ch, vf,
-            vf_cap, ee, ee_cap, B.counts);
+            B.klo64, B.khi64, B.lob, B.hib, B.loc, B.hic, B.pid, B.vtx, nv, ne, nf, tv, te, tile0, tile1, tiles_grid, g,
+            ch, vf, vf_cap, ee, ee_cap, B.counts);
     else
         sweep_kernel<uint32_t><<<(unsigned)grid, kTile, 0, s>>>(sorted_keys(B), B.khi, B.lob, B.hib, B.loc, B.hic,
-                                                               B.pid, B.vtx, nv, ne, nf, tv, te, nt, tiles_grid, g,
-                                                               ch, vf, vf_cap, ee, ee_cap, B.counts);
+                                                               B.pid, B.vtx, nv, ne, nf, tv, te, tile0, tile1,
+                                                               tiles_grid, g, ch, vf, vf_cap, ee, ee_cap, B.counts);
 }
 
 int64_t sort_blocks(int64_t nb)

@@ -119,8 +119,17 @@ void launch_broad_sort(int64_t nv, int64_t ne, int64_t nf, const BroadBuffers &B
                        hipStream_t s);
 void launch_broad_gather(const int32_t *E, const int32_t *F, int64_t nv, int64_t ne, int64_t nf,
                          const BroadBuffers &B, hipStream_t s);
+// The sweep over the query tiles [tile0, tile1) of the sorted boxes (64 boxes
+// each: vertex tiles, then edge tiles, then face tiles; tile1 < 0 = all): it
+// emits exactly the pairs whose earlier box in sorted order lies in those
+// tiles, so disjoint ranges give disjoint parts of the pair set.
 void launch_broad_sweep(int64_t nv, int64_t ne, int64_t nf, int32_t *vf, int64_t vf_cap, int32_t *ee,
-                        int64_t ee_cap, const BroadBuffers &B, int64_t tile_group, hipStream_t s);
+                        int64_t ee_cap, const BroadBuffers &B, int64_t tile_group, hipStream_t s, int64_t tile0 = 0,
+                        int64_t tile1 = -1);
+// Query tiles of a scene's sweep.
+int64_t sweep_tiles(int64_t nv, int64_t ne, int64_t nf);
+// The sweep's pair counters back to zero (before a sweep over a tile range).
+void launch_broad_counts_zero(const BroadBuffers &B, hipStream_t s);
 // Radix passes over scene ids (0 for one scene).
 int scene_passes(int64_t S);
 

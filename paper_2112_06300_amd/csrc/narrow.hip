@@ -190,6 +190,98 @@ __device__ __forceinline__ int process(const Query &q, bool vf, double t0, doubl
     return SPLIT;
 }
 
+// The inclusion boxes of both children of an interval split along dimension K
+// at its midpoint, on axis a.  T, U, V hold the corner coordinates: three
+// (low, mid, high) along K, two (low, high) otherwise.  F at a corner depends
+// on the corner alone (the fixed sequence of process()), so the corners the
+// two children share are evaluated once and each child's box is exactly the
+// one process() computes for it.  Child 0 spans indices 0..1 along K, child 1
+// indices 1..2.
+template <int K, bool VF>
+__device__ __forceinline__ void axis_pair(const Query &q, int a, const double T[3], const double U[3],
+                                          const double V[3], double &mn0, double &mx0, double &mn1, double &mx1)
+{
+    constexpr int NT = K == 0 ? 3 : 2, NU = K == 1 ? 3 : 2, NV = K == 2 ? 3 : 2;
+    // running min / max of the three slices across K (4 corners each)
+    double smn[3] = {__builtin_huge_val(), __builtin_huge_val(), __builtin_huge_val()};
+    double smx[3] = {-__builtin_huge_val(), -__builtin_huge_val(), -__builtin_huge_val()};
+#pragma unroll
+    for (int it = 0; it < NT; it++) {
+        const double t = T[it];
+        const double P0 = fma(t, q.d[0][a], q.x0[0][a]);
+        const double P1 = fma(t, q.d[1][a], q.x0[1][a]);
+        const double P2 = fma(t, q.d[2][a], q.x0[2][a]);
+        const double P3 = fma(t, q.d[3][a], q.x0[3][a]);
+        if (VF) {
+            const double pa = P0 - P1, eb = P2 - P1, ec = P3 - P1;
+#pragma unroll
+            for (int iu = 0; iu < NU; iu++) {
+                const double g = fma(-U[iu], eb, pa);
+#pragma unroll
+                for (int iv = 0; iv < NV; iv++) {
+                    const double f = fma(-V[iv], ec, g);
+                    const int sl = K == 0 ? it : (K == 1 ? iu : iv);
+                    smn[sl] = fmin(smn[sl], f);
+                    smx[sl] = fmax(smx[sl], f);
+                }
+            }
+        } else {
+            const double ea = P1 - P0, eb = P3 - P2;
+            double B[NV];
+#pragma unroll
+            for (int iv = 0; iv < NV; iv++) B[iv] = fma(V[iv], eb, P2);
+#pragma unroll
+            for (int iu = 0; iu < NU; iu++) {
+                const double A = fma(U[iu], ea, P0);
+#pragma unroll
+                for (int iv = 0; iv < NV; iv++) {
+                    const double f = A - B[iv];
+                    const int sl = K == 0 ? it : (K == 1 ? iu : iv);
+                    smn[sl] = fmin(smn[sl], f);
+                    smx[sl] = fmax(smx[sl], f);
+                }
+            }
+        }
+    }
+    mn0 = fmin(smn[0], smn[1]);
+    mx0 = fmax(smx[0], smx[1]);
+    mn1 = fmin(smn[1], smn[2]);
+    mx1 = fmax(smx[1], smx[2]);
+}
+
+// Decisions (DISCARD / ACCEPT / SPLIT) for both children of an interval split
+// along K, identical to process() on each child.  A child not needed (need
+// false) reports DISCARD without being evaluated; az: the child starts at
+// t = 0 (no-zero strategy).
+template <int K>
+__device__ __forceinline__ void process_pair(const Query &q, bool vf, const double T[3], const double U[3],
+                                             const double V[3], bool need0, bool need1, bool finest, double delta,
+                                             bool az0, bool az1, int &r0, int &r1)
+{
+    // vertex-face domain: each child's own lower u and v
+    const double cu1 = K == 1 ? U[1] : U[0], cv1 = K == 2 ? V[1] : V[0];
+    bool d0 = !need0 || (vf && U[0] + V[0] > 1.0);
+    bool d1 = !need1 || (vf && cu1 + cv1 > 1.0);
+    double w0 = 0.0, w1 = 0.0;
+    bool in0 = true, in1 = true;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        if (d0 && d1) break;
+        double mn0, mx0, mn1, mx1;
+        if (vf) axis_pair<K, true>(q, a, T, U, V, mn0, mx0, mn1, mx1);
+        else axis_pair<K, false>(q, a, T, U, V, mn0, mx0, mn1, mx1);
+        const double e = q.eps[a];
+        d0 = d0 || mn0 > e || mx0 < -e;
+        d1 = d1 || mn1 > e || mx1 < -e;
+        w0 = fmax(w0, mx0 - mn0);
+        w1 = fmax(w1, mx1 - mn1);
+        in0 = in0 && mn0 >= -e && mx0 <= e;
+        in1 = in1 && mn1 >= -e && mx1 <= e;
+    }
+    r0 = d0 ? DISCARD : ((((w0 < delta || in0) && !az0) || finest) ? ACCEPT : SPLIT);
+    r1 = d1 ? DISCARD : ((((w1 < delta || in1) && !az1) || finest) ? ACCEPT : SPLIT);
+}
+
 // Halve the dimension with the largest m_k - l_k among those below the finest
 // level; ties go to t, then u, then v.
 __device__ __forceinline__ int split_dim(const int m[3], const int l[3])
@@ -1094,20 +1186,9 @@ __global__ __launch_bounds__(BLOCK) void heavy_kernel(
             // i & 1 of node i >> 1), a wide one one node and both children.
             int cnt = 0;
             double tmin = __builtin_huge_val();  // earliest kept child (for a capped level)
-            auto child = [&](const unsigned long long cn[3], bool has) {
-                const double t0 = (double)cn[0] * tscale;
-                const bool inF = has && t0 < tsnap;
-                if (inF) { cnt++; tmin = t0 < tmin ? t0 : tmin; }
-                if (inF && no_zero && cn[0] == 0ull) s_zero[ps] = 1;
-                // roots reported at this level only shorten the work, never the count
-                const double tl = __longlong_as_double((long long)(*(volatile unsigned long long *)&s_tl[ps]));
-                int r = DISCARD;
-                if (inF && t0 < tl) {
-                    const double t1 = (double)(cn[0] + 1ull) * tscale;
-                    const double u0 = (double)cn[1] * uscale, u1 = (double)(cn[1] + 1ull) * uscale;
-                    const double v0 = (double)cn[2] * vscale, v1 = (double)(cn[2] + 1ull) * vscale;
-                    r = process(q, vf, t0, t1, u0, u1, v0, v1, finest, delta, no_zero && cn[0] == 0ull);
-                }
+            // a child's survivor (SPLIT) goes to the next frontier; an accepted
+            // one lowers the level's t* (and in global mode the shared one)
+            auto emit = [&](const unsigned long long cn[3], int r, double t0) {
                 if (r == ACCEPT) {
                     atomicMin(&s_tl[ps], (unsigned long long)__double_as_longlong(t0));
                     if (gmode) atomicMin((unsigned long long *)toi_min, (unsigned long long)__double_as_longlong(t0));
@@ -1130,6 +1211,53 @@ __global__ __launch_bounds__(BLOCK) void heavy_kernel(
                         }
                     }
                 }
+            };
+            // kept (counted) when it starts before the level's bound
+            auto keep = [&](const unsigned long long cn[3], bool has) {
+                const double t0 = (double)cn[0] * tscale;
+                const bool inF = has && t0 < tsnap;
+                if (inF) { cnt++; tmin = t0 < tmin ? t0 : tmin; }
+                if (inF && no_zero && cn[0] == 0ull) s_zero[ps] = 1;
+                return inF;
+            };
+            auto child = [&](const unsigned long long cn[3], bool has) {
+                const double t0 = (double)cn[0] * tscale;
+                const bool inF = keep(cn, has);
+                // roots reported at this level only shorten the work, never the count
+                const double tl = __longlong_as_double((long long)(*(volatile unsigned long long *)&s_tl[ps]));
+                int r = DISCARD;
+                if (inF && t0 < tl) {
+                    const double t1 = (double)(cn[0] + 1ull) * tscale;
+                    const double u0 = (double)cn[1] * uscale, u1 = (double)(cn[1] + 1ull) * uscale;
+                    const double v0 = (double)cn[2] * vscale, v1 = (double)(cn[2] + 1ull) * vscale;
+                    r = process(q, vf, t0, t1, u0, u1, v0, v1, finest, delta, no_zero && cn[0] == 0ull);
+                }
+                emit(cn, r, t0);
+            };
+            // both children of node pn, the corners they share evaluated once
+            auto children = [&](const unsigned long long pn[3], bool has) {
+                unsigned long long c0[3] = {pn[0], pn[1], pn[2]}, c1[3] = {pn[0], pn[1], pn[2]};
+                c0[k] = 2ull * pn[k];
+                c1[k] = 2ull * pn[k] + 1ull;
+                const double t00 = (double)c0[0] * tscale, t10 = (double)c1[0] * tscale;
+                const bool in0 = keep(c0, has), in1 = keep(c1, has);
+                const double tl = __longlong_as_double((long long)(*(volatile unsigned long long *)&s_tl[ps]));
+                const bool need0 = in0 && t00 < tl, need1 = in1 && t10 < tl;
+                int r0 = DISCARD, r1 = DISCARD;
+                if (need0 || need1) {
+                    // corner coordinates: low, mid, high along k (children's bounds), low, high otherwise
+                    double T[3], U[3], V[3];
+                    const unsigned long long nt = c0[0], nu = c0[1], nw = c0[2];
+                    T[0] = (double)nt * tscale; T[1] = (double)(nt + 1ull) * tscale; T[2] = (double)(nt + 2ull) * tscale;
+                    U[0] = (double)nu * uscale; U[1] = (double)(nu + 1ull) * uscale; U[2] = (double)(nu + 2ull) * uscale;
+                    V[0] = (double)nw * vscale; V[1] = (double)(nw + 1ull) * vscale; V[2] = (double)(nw + 2ull) * vscale;
+                    const bool az0 = no_zero && c0[0] == 0ull, az1 = no_zero && c1[0] == 0ull;
+                    if (k == 0) process_pair<0>(q, vf, T, U, V, need0, need1, finest, delta, az0, az1, r0, r1);
+                    else if (k == 1) process_pair<1>(q, vf, T, U, V, need0, need1, finest, delta, az0, az1, r0, r1);
+                    else process_pair<2>(q, vf, T, U, V, need0, need1, finest, delta, az0, az1, r0, r1);
+                }
+                emit(c0, r0, t00);
+                emit(c1, r1, t10);
             };
             auto node = [&](int64_t ni, bool has, unsigned long long pn[3]) {
                 pn[0] = pn[1] = pn[2] = 0ull;
@@ -1154,12 +1282,7 @@ __global__ __launch_bounds__(BLOCK) void heavy_kernel(
                     const bool has = i < nS;
                     unsigned long long pn[3];
                     node(i, has, pn);
-#pragma unroll
-                    for (int c = 0; c < 2; c++) {
-                        unsigned long long cn[3] = {pn[0], pn[1], pn[2]};
-                        cn[k] = 2ull * pn[k] + (unsigned long long)c;
-                        child(cn, has);
-                    }
+                    children(pn, has);
                 }
             }
             int wcnt = 0;

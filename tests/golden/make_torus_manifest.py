@@ -6,7 +6,8 @@ set) and the seeded scene generator.  The oracle takes tens of minutes on 8 core
 and the benchmark read this file instead, guarded by a hash of the scene's arrays (a changed generator makes
 them fall back or report no figure).  Stored:
   - the input hash and sizes, the pair counts and a hash of the canonically sorted pairs;
-  - a hash of the per-pair results (hit, TOI bits, n_enq) in canonical pair order;
+  - a hash of the per-pair results (hit, TOI bits, n_enq) in canonical pair order, and one of hit and TOI
+    bits alone;
   - the earliest time of impact (bits), the number of capped pairs and whether the earliest is a capped one;
   - the canonical work: interval evaluations and per-axis inclusion boxes by pair kind (the benchmark's
     flop count), and a histogram of evaluations per pair.
@@ -66,6 +67,16 @@ def results_hash(vf, ee, hit, toi, n_enq):
     return h.hexdigest()
 
 
+def hit_toi_hash(vf, ee, hit, toi):
+    """sha256 of hit (uint8) and TOI bits (float64) in canonical pair order (for callers without n_enq)."""
+    ov, oe = canonical_order(vf, ee)
+    perm = np.concatenate([ov, len(vf) + oe])
+    h = hashlib.sha256()
+    h.update(np.ascontiguousarray(hit[perm], np.uint8).tobytes())
+    h.update(np.ascontiguousarray(toi[perm], np.float64).tobytes())
+    return h.hexdigest()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--threads", type=int, default=oracle.default_threads())
@@ -91,6 +102,7 @@ def main():
         "n_vf": int(nvf), "n_ee": int(len(ee)),
         "pairs_sha256": pairs_hash(vf, ee),
         "results_sha256": results_hash(vf, ee, hit, toi, n_enq),
+        "hit_toi_sha256": hit_toi_hash(vf, ee, hit, toi),
         "hits": int(hit.sum()),
         "toi_min": float(tmin), "toi_min_bits": int(np.float64(tmin).view(np.int64)),
         "capped_pairs": int(capped.sum()),
