@@ -417,7 +417,8 @@ ccd_status ccd_get_stats(ccd_context *ctx, ccd_stats *out);
  *                       unit, 0 = as many as fit (default)
  *   heavy_slots         workgroups of the wide stage (default 1024)
  *   heavy_cap_log2      log2 of each wide-stage frontier buffer in intervals
- *                       (default 13); a pair whose frontier outgrows it saves
+ *                       (default 16: 3 MB per workgroup; a frontier of up to
+ *                       3 x 2^16 packed intervals); a pair whose frontier outgrows it saves
  *                       the level it is on and resumes from there, after the
  *                       first round, on buffers sized for max_iter + 1
  *                       intervals as far as device memory allows
@@ -426,12 +427,25 @@ ccd_status ccd_get_stats(ccd_context *ctx, ccd_stats *out);
  *   heavy_block         threads per wide-stage pair, 64, 256 or 1024, or 0
  *                       (default): 1024 when at most 256 pairs reach the wide
  *                       stage, else 256 (decided on the device)
+ *   resume_block        threads per pair, 256 or 1024 (default 256), and
+ *   resume_slots_per_cu workgroups per compute unit, 1..8 (default 3), of the
+ *                       rounds that resume pairs whose frontier outgrew their
+ *                       buffer
  *   pool_wait           1: a pair whose children do not fit its wave's queue
  *                       this round waits for room, 0: it goes to the wide
  *                       stage (default 0)
+ *   sweep_classes       the sweep's query boxes of each kind are grouped
+ *                       into this many classes by their extent on the sweep
+ *                       axis before they are cut into tiles of 64, so that a
+ *                       tile's walk (the union of its boxes' windows) is not
+ *                       stretched by one long box: 1 = off, 2..8 classes,
+ *                       0 (default) = 4 for a single scene of at least 2^20
+ *                       boxes, else off.  Batches of several scenes never
+ *                       group (a tile spanning two scenes would walk both).
  * ccd_set_tuning(ctx, NULL) restores the defaults.  INVALID_ARG when a value
  * is out of range (group 1..1024, blocks 0..64, slots 1..65536, cap 8..24,
- * lds 0..1, block 0, 64, 256 or 1024, wait 0..1).
+ * lds 0..1, block 0, 64, 256 or 1024, wait 0..1, resume block 256 or 1024,
+ * resume slots 1..8, classes 0..8).
  */
 typedef struct {
     int32_t sweep_tile_group;
@@ -441,6 +455,9 @@ typedef struct {
     int32_t heavy_lds;
     int32_t heavy_block;
     int32_t pool_wait;
+    int32_t resume_block;
+    int32_t resume_slots_per_cu;
+    int32_t sweep_classes;
 } ccd_tuning;
 
 ccd_status ccd_set_tuning(ccd_context *ctx, const ccd_tuning *tuning);
@@ -473,7 +490,8 @@ ccd_status ccd_get_tuning(ccd_context *ctx, ccd_tuning *tuning);
  *
  * ccd_batch_autotune: times batch passes over candidate tunings (coordinate
  * descent over tile group, pool blocks per CU, wide-stage workgroup size,
- * slots and LDS frontiers, and pool waiting) and sets
+ * slots, buffer size and LDS frontiers, pool waiting, and the resume rounds'
+ * workgroup size and count) and sets
  * the best on the context.  With cache_path the choice is stored under a
  * signature of the device and the workload's size, and a later call with the
  * same signature takes it from the file without timing.  Outputs as

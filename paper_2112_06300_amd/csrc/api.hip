@@ -123,10 +123,13 @@ ccd_tuning default_tuning()
     t.sweep_tile_group = 16;
     t.pool_blocks_per_cu = 0;
     t.heavy_slots = 1024;
-    t.heavy_cap_log2 = 13;
+    t.heavy_cap_log2 = 16;
     t.heavy_lds = 1;
     t.heavy_block = 0;
     t.pool_wait = 0;
+    t.resume_block = 256;
+    t.resume_slots_per_cu = 3;
+    t.sweep_classes = 0;
     return t;
 }
 
@@ -182,6 +185,13 @@ void broad_carve(Carver &cv, int64_t nb, int64_t S, int64_t nbl, BroadBuffers &B
     B.vtx = cv.take<int32_t>(3 * n);
     B.counts = cv.take<unsigned long long>(2);
     B.flags = cv.take<uint32_t>(1);
+    // the sweep's query order (one scene); the caller sets qclasses
+    B.qclasses = 1;
+    B.qcode = multi ? nullptr : cv.take<uint16_t>(n);
+    B.qhist = multi ? nullptr : cv.take<uint32_t>(3 * (size_t)kExtentCodes);
+    B.qthr = multi ? nullptr : cv.take<uint32_t>(3 * 8);
+    B.qcnt = multi ? nullptr : cv.take<uint32_t>((size_t)3 * 8 * class_blocks(nb));
+    B.qord = multi ? nullptr : cv.take<uint32_t>(n);
 }
 
 // Narrow-phase workspace of npairs pairs.
@@ -214,7 +224,8 @@ bool valid_tuning(const ccd_tuning &t)
            t.pool_blocks_per_cu <= 64 && t.heavy_slots >= 1 && t.heavy_slots <= 65536 && t.heavy_cap_log2 >= 8 &&
            t.heavy_cap_log2 <= 24 && (t.heavy_lds == 0 || t.heavy_lds == 1) &&
            (t.heavy_block == 0 || t.heavy_block == 64 || t.heavy_block == 256 || t.heavy_block == 1024) &&
-           (t.pool_wait == 0 || t.pool_wait == 1);
+           (t.pool_wait == 0 || t.pool_wait == 1) && (t.resume_block == 256 || t.resume_block == 1024) &&
+           t.resume_slots_per_cu >= 1 && t.resume_slots_per_cu <= 8 && t.sweep_classes >= 0 && t.sweep_classes <= 8;
 }
 
 // Broad-phase arguments checked, workspace carved, every kernel launched on s
@@ -239,6 +250,7 @@ ccd_status broad_enqueue(ccd_context *c, const double *V0, const double *V1, int
     if (st != CCD_OK) return st;
     Carver cv(c->broad.base);
     broad_carve(cv, nb, 1, nbl, B);
+    B.qclasses = sweep_class_count(c->tune.sweep_classes, nb, 1);
 
     HIP_TRY(hipEventRecord(c->ev[7], s));
     launch_broad_boxes(V0, V1, nv, E, ne, F, nf, B, s);
@@ -539,13 +551,17 @@ ccd_status narrow_enqueue(ccd_context *c, const double *V0, const double *V1, in
     call.learned = sched && (sched->kind == CCD_SCHED_LEARNED || sched->kind == CCD_SCHED_COST);
     const bool learned = call.learned;
     const bool given_cost = sched && sched->kind == CCD_SCHED_COST;
+    if (call.fixed_frontier) {
+        // as many of the tuned slots as the fixed region holds, with buffers
+        // halved (down to 8,192 intervals) until at least 64 fit
+        while (call.cap > 8192 && call.fixed_bytes / ((size_t)6 * call.cap * 8) < 64) call.cap /= 2;
+        call.nslots = (int)std::min<size_t>((size_t)call.nslots, call.fixed_bytes / ((size_t)6 * call.cap * 8));
+    }
     const int nslots = call.nslots;
     const int64_t cap = call.cap;
     const int max_early = learned ? (int)std::min<int64_t>(sched->max_heavy, n) : 0;
     const int early_slots = max_early > 0 ? std::min(max_early, nslots) : 0;
     if (call.fixed_frontier) {
-        // as many of the tuned slots as the fixed region holds
-        call.nslots = (int)std::min<size_t>((size_t)nslots, call.fixed_bytes / ((size_t)6 * cap * 8));
         if (call.nslots < 1 || early_slots > 0)
             return fail(CCD_ERR_CAPACITY, "wide-stage buffers of 2^%d intervals do not fit the fixed workspace",
                         c->tune.heavy_cap_log2);
@@ -608,9 +624,9 @@ ccd_status narrow_enqueue(ccd_context *c, const double *V0, const double *V1, in
 // Pairs whose frontier outgrew the wide stage's buffers, resumed from the level
 // they saved.  The first re-run round sizes the buffers for max_iter + 1
 // intervals, which no pair below the cap can outgrow (a level's frontier holds
-// at most its kept children), as far as device memory allows, on one
-// 1,024-thread workgroup per compute unit; a further round (memory-limited
-// buffers) takes 8x larger ones.  `pool` holds the frontier buffers; with a
+// at most its kept children), as far as device memory allows, on
+// tuning.resume_slots_per_cu workgroups of tuning.resume_block threads per
+// compute unit; a further round (memory-limited buffers) takes 8x larger ones.  `pool` holds the frontier buffers; with a
 // null pool they are the fixed region of `fixed_bytes` at `fixed` (no
 // allocation: a frontier that outgrows it is a capacity error).
 ccd_status rerun_overflowed(ccd_context *c, NarrowBuffers B, Pool *pool, unsigned int overflowed, int64_t cap,
@@ -635,7 +651,8 @@ ccd_status rerun_overflowed(ccd_context *c, NarrowBuffers B, Pool *pool, unsigne
             while (need < max_iter + 1 && need < ((int64_t)1 << 30)) need *= 2;
             want = std::max(want, need);
         }
-        const size_t slots_wanted = std::min<size_t>((size_t)c->cus, (size_t)overflowed);
+        const size_t slots_wanted =
+            std::min<size_t>((size_t)c->cus * (size_t)c->tune.resume_slots_per_cu, (size_t)overflowed);
         while (want > cap * 8 && slots_wanted * (size_t)6 * want * 8 > budget) want /= 2;
         if (!pool) {
             // a fixed region: the largest buffers it holds, as long as they grow
@@ -660,7 +677,7 @@ ccd_status rerun_overflowed(ccd_context *c, NarrowBuffers B, Pool *pool, unsigne
         }
         HIP_TRY(hipEventRecord(c->ev[0], s));
         launch_narrow_heavy(V0, V1, pc, delta, (long long)max_iter, hit, toi, nenq, B, nslots, cap, round,
-                            c->tune.heavy_lds, c->tune.heavy_block == 0 ? 0 : c->tune.heavy_block, s);
+                            c->tune.heavy_lds, c->tune.resume_block, s);
         HIP_TRY(hipGetLastError());
         HIP_TRY(hipEventRecord(c->ev[1], s));
         HIP_TRY(hipMemcpyAsync(hr, B.counters, 16 * 4, hipMemcpyDeviceToHost, s));
@@ -1087,6 +1104,7 @@ ccd_status ccd_detect_budget(ccd_context *c, const double *V0, const double *V1,
     if (st != CCD_OK) return st;
     Carver cv(c->budget.base);
     broad_carve(cv, nb, 1, nbl, B);
+    B.qclasses = sweep_class_count(c->tune.sweep_classes, nb, 1);
     cv.off = broad_bytes;
     int32_t *vfb = cv.take<int32_t>(2 * (size_t)S);
     int32_t *eeb = cv.take<int32_t>(2 * (size_t)S);
@@ -1335,6 +1353,7 @@ ccd_status batch_frontier(ccd_batch *b)
 void batch_enqueue(ccd_batch *b, const BatchArgs &a, hipStream_t s)
 {
     const ccd_context *c = b->ctx;
+    b->B.qclasses = sweep_class_count(c->tune.sweep_classes, b->nv + b->ne + b->nf, b->S);
     launch_broad_boxes(a.V0, a.V1, b->nv, a.E, b->ne, a.F, b->nf, b->B, s);
     launch_broad_sort(b->nv, b->ne, b->nf, b->B, b->nbl, s);
     launch_broad_gather(a.E, a.F, b->nv, b->ne, b->nf, b->B, s);
@@ -1441,7 +1460,7 @@ ccd_status check_batch_args(ccd_batch *b, const BatchArgs &a, const int64_t *n_v
 }
 
 // Autotuner cache: one line per workload signature,
-// "signature: group blocks slots cap lds block wait".
+// "signature: group blocks slots cap lds block wait resume_block resume_slots classes".
 bool cache_lookup(const char *path, const char *sig, ccd_tuning *t)
 {
     if (!path) return false;
@@ -1453,8 +1472,9 @@ bool cache_lookup(const char *path, const char *sig, ccd_tuning *t)
     while (std::fgets(line, sizeof line, f)) {
         if (std::strncmp(line, sig, n) == 0 && line[n] == ':') {
             ccd_tuning v;
-            if (std::sscanf(line + n + 1, "%d %d %d %d %d %d %d", &v.sweep_tile_group, &v.pool_blocks_per_cu,
-                            &v.heavy_slots, &v.heavy_cap_log2, &v.heavy_lds, &v.heavy_block, &v.pool_wait) == 7 &&
+            if (std::sscanf(line + n + 1, "%d %d %d %d %d %d %d %d %d %d", &v.sweep_tile_group,
+                            &v.pool_blocks_per_cu, &v.heavy_slots, &v.heavy_cap_log2, &v.heavy_lds, &v.heavy_block,
+                            &v.pool_wait, &v.resume_block, &v.resume_slots_per_cu, &v.sweep_classes) == 10 &&
                 valid_tuning(v)) {
                 *t = v;
                 found = true;  // the last matching line wins
@@ -1470,8 +1490,9 @@ void cache_store(const char *path, const char *sig, const ccd_tuning &t)
     if (!path) return;
     FILE *f = std::fopen(path, "a");
     if (!f) return;
-    std::fprintf(f, "%s: %d %d %d %d %d %d %d\n", sig, t.sweep_tile_group, t.pool_blocks_per_cu, t.heavy_slots,
-                 t.heavy_cap_log2, t.heavy_lds, t.heavy_block, t.pool_wait);
+    std::fprintf(f, "%s: %d %d %d %d %d %d %d %d %d %d\n", sig, t.sweep_tile_group, t.pool_blocks_per_cu,
+                 t.heavy_slots, t.heavy_cap_log2, t.heavy_lds, t.heavy_block, t.pool_wait, t.resume_block,
+                 t.resume_slots_per_cu, t.sweep_classes);
     std::fclose(f);
 }
 
@@ -1622,8 +1643,13 @@ ccd_status ccd_batch_autotune(ccd_batch *b, const double *V0, const double *V1, 
     const int groups[] = {1, 4, 16, 64};
     const int slots[] = {256, 1024, 2048, 4096};
     const int blocks[] = {0, 256, 1024};
-    for (int param = 0; param < 6; param++) {
-        const int counts[6] = {4, c->pool_per_cu_max, 3, 4, 2, 2};
+    const int caps[] = {11, 13, 15};
+    const int rblocks[] = {256, 1024};
+    const int rslots[] = {1, 2, 3};
+    const int classes[] = {0, 1, 4};
+    for (int param = 0; param < 10; param++) {
+        // query classes apply to a single scene only
+        const int counts[10] = {4, c->pool_per_cu_max, 3, 4, 2, 2, 3, 2, 3, b->S == 1 ? 3 : 0};
         const int ncand = counts[param];
         for (int i = 0; i < ncand; i++) {
             ccd_tuning t = best;
@@ -1632,7 +1658,11 @@ ccd_status ccd_batch_autotune(ccd_batch *b, const double *V0, const double *V1, 
             else if (param == 2) t.heavy_block = blocks[i];
             else if (param == 3) t.heavy_slots = slots[i];
             else if (param == 4) t.heavy_lds = i;
-            else t.pool_wait = i;
+            else if (param == 5) t.pool_wait = i;
+            else if (param == 6) t.heavy_cap_log2 = caps[i];
+            else if (param == 7) t.resume_block = rblocks[i];
+            else if (param == 8) t.resume_slots_per_cu = rslots[i];
+            else t.sweep_classes = classes[i];
             if (std::memcmp(&t, &best, sizeof t) == 0) continue;
             float m = 0.f;
             st = measure(t, &m);

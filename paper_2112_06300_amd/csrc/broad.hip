@@ -18,6 +18,8 @@
 // face-face neighbours along the axis.
 #include "ccd_internal.h"
 
+#include <algorithm>
+
 namespace ccd {
 
 namespace {
@@ -41,10 +43,12 @@ struct SweepChunks {
     int64_t vf;   // chunks of a vertex or face tile
 };
 
-__global__ void zero_kernel(double *stats, int64_t nstats, unsigned long long *counts, uint32_t *flags)
+__global__ void zero_kernel(double *stats, int64_t nstats, unsigned long long *counts, uint32_t *flags,
+                            uint32_t *qhist)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t < nstats) stats[t] = 0.0;
+    if (qhist && t < 3 * kExtentCodes) qhist[t] = 0u;
     if (t < 2) counts[t] = 0ull;
     if (t == 0) *flags = 0u;
 }
@@ -369,6 +373,15 @@ __global__ __launch_bounds__(kSortThreads) void scatter_kernel(
     }
 }
 
+// Class code of a box's extent on the sweep axis: the leading 11 bits of the
+// float (exponent and 3 mantissa bits), a monotone log scale in steps of
+// 1/8 octave.  Only the grouping of queries depends on it.
+__device__ __forceinline__ uint32_t extent_code(float lo, float hi)
+{
+    const uint32_t b = __float_as_uint(hi - lo);
+    return (b & 0x80000000u) ? 0u : b >> 20;
+}
+
 // Sweep records in sorted order.  With several scenes the keys become
 // (scene << 32 | key) composites, so that one sorted segment holds the scenes
 // one after another and no window reaches into the next scene.
@@ -378,7 +391,7 @@ __global__ void gather_kernel(const uint32_t *__restrict__ keys, const uint32_t 
                               const float *hi0, const float *hi1, const float *hi2,
                               const uint32_t *__restrict__ bscene, const int32_t *__restrict__ axis_s, uint32_t *khi,
                               unsigned long long *klo64, unsigned long long *khi64, float *lob, float *hib,
-                              float *loc, float *hic, int32_t *pid, int32_t *vtx)
+                              float *loc, float *hic, int32_t *pid, int32_t *vtx, uint16_t *qcode)
 {
     const int64_t nb = nv + ne + nf;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -395,6 +408,7 @@ __global__ void gather_kernel(const uint32_t *__restrict__ keys, const uint32_t 
     } else {
         khi[i] = kh;
     }
+    if (qcode) qcode[i] = (uint16_t)extent_code(lo[axis][g], hi[axis][g]);
     lob[i] = lo[ab][g];
     hib[i] = hi[ab][g];
     loc[i] = lo[ac][g];
@@ -416,8 +430,159 @@ __global__ void gather_kernel(const uint32_t *__restrict__ keys, const uint32_t 
     }
 }
 
-// Sweep, one wave per tile of 64 consecutive sorted query records (one query
-// per lane).  The wave walks the union of its lanes' candidate windows in
+// Query order of the sweep (one scene).  A tile's walk covers the union of
+// its 64 lanes' windows, whose length is set by the tile's longest box on the
+// sweep axis: among boxes of mixed extents most lanes would test candidates
+// far past their own windows.  So the queries of each segment are grouped into
+// C classes of extent (boundaries at the segment's extent quantiles k/C, read
+// from a histogram of the extent codes), sorted position ascending within a
+// class, and tiles are cut from that order.  A lane still enforces its own
+// window with its comparisons, so the pairs found are the same; the tiles walk
+// fewer candidates.
+constexpr int kClassRounds = 64;                     // positions per wave and round: 64
+constexpr int64_t kClassRun = 64 * kClassRounds;     // positions per class-pass block (one wave)
+constexpr int kMaxBins = 3 * 8;                      // segment x class
+
+__global__ __launch_bounds__(256) void extent_hist_kernel(const uint16_t *__restrict__ qcode, int64_t nb,
+                                                          int64_t n0, int64_t n1, uint32_t *qhist)
+{
+    __shared__ uint32_t h[3 * kExtentCodes];
+    for (int b = threadIdx.x; b < 3 * kExtentCodes; b += 256) h[b] = 0u;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kClassRun;
+    for (int r = 0; r < kClassRun / 256; r++) {
+        const int64_t i = base + (int64_t)r * 256 + threadIdx.x;
+        if (i < nb) atomicAdd(&h[segment_of(i, n0, n1) * kExtentCodes + qcode[i]], 1u);
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < 3 * kExtentCodes; b += 256)
+        if (h[b]) atomicAdd(&qhist[b], h[b]);
+}
+
+// Class thresholds: for segment s with n_s boxes, thr[8 s + k] (k = 1..C-1) is
+// the smallest code whose inclusive count reaches k n_s / C; a code x is in
+// class #{k : x > thr[k]}.  One workgroup, 8 codes per thread.
+__global__ __launch_bounds__(256) void extent_split_kernel(const uint32_t *__restrict__ qhist, int64_t nv,
+                                                           int64_t ne, int64_t nf, int C, uint32_t *qthr)
+{
+    __shared__ uint32_t wsum[4];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    constexpr int kPer = kExtentCodes / 256;
+    for (int seg = 0; seg < 3; seg++) {
+        const int64_t n = seg == 0 ? nv : (seg == 1 ? ne : nf);
+        const uint32_t *h = qhist + seg * kExtentCodes + t * kPer;
+        uint32_t mine = 0u;
+        for (int c = 0; c < kPer; c++) mine += h[c];
+        int wt = 0;
+        const uint32_t ex = (uint32_t)wave_excl_scan((int)mine, wt);
+        if (lane == 0) wsum[wave] = (uint32_t)wt;
+        __syncthreads();
+        uint64_t cum = ex;
+        for (int w = 0; w < wave; w++) cum += wsum[w];
+        if (n == 0 && t == 0)
+            for (int k = 1; k < C; k++) qthr[seg * 8 + k] = 0u;
+        for (int c = 0; c < kPer; c++) {
+            const uint64_t after = cum + h[c];
+            for (int k = 1; k < C; k++) {
+                const uint64_t target = (uint64_t)k * (uint64_t)n;
+                if (n > 0 && cum * (uint64_t)C < target && after * (uint64_t)C >= target)
+                    qthr[seg * 8 + k] = (uint32_t)(t * kPer + c);
+            }
+            cum = after;
+        }
+        __syncthreads();
+    }
+}
+
+// Bin (segment x class) of sorted position i.
+__device__ __forceinline__ int class_bin(const uint16_t *__restrict__ qcode, const uint32_t *__restrict__ qthr,
+                                         int64_t i, int64_t n0, int64_t n1, int C)
+{
+    const int seg = segment_of(i, n0, n1);
+    const uint32_t x = qcode[i];
+    int cls = 0;
+    for (int k = 1; k < C; k++) cls += x > qthr[seg * 8 + k] ? 1 : 0;
+    return seg * C + cls;
+}
+
+// Per block (one wave, kClassRun consecutive positions): its count of each
+// bin, bin-major (qcnt[bin * nblocks + block]).
+__global__ __launch_bounds__(64) void class_count_kernel(const uint16_t *__restrict__ qcode,
+                                                         const uint32_t *__restrict__ qthr, int64_t nb, int64_t n0,
+                                                         int64_t n1, int C, uint32_t *qcnt, int64_t nblocks)
+{
+    const int lane = threadIdx.x;
+    const int nbins = 3 * C;
+    uint32_t cnt[kMaxBins];
+#pragma unroll
+    for (int b = 0; b < kMaxBins; b++) cnt[b] = 0u;
+    const int64_t base = (int64_t)blockIdx.x * kClassRun;
+    for (int r = 0; r < kClassRounds; r++) {
+        const int64_t i = base + (int64_t)r * 64 + lane;
+        const int bin = i < nb ? class_bin(qcode, qthr, i, n0, n1, C) : -1;
+#pragma unroll
+        for (int b = 0; b < kMaxBins; b++)
+            if (b < nbins) cnt[b] += (uint32_t)__popcll(__ballot(bin == b));
+    }
+#pragma unroll
+    for (int b = 0; b < kMaxBins; b++)
+        if (b < nbins && lane == 0) qcnt[(int64_t)b * nblocks + blockIdx.x] = cnt[b];
+}
+
+// Exclusive prefix of the n bin-major counts in place (one workgroup).
+__global__ __launch_bounds__(1024) void class_scan_kernel(uint32_t *qcnt, int64_t n)
+{
+    __shared__ uint32_t wsum[16];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int64_t per = (n + 1023) / 1024;
+    const int64_t a = std::min<int64_t>((int64_t)t * per, n), b = std::min<int64_t>(a + per, n);
+    uint32_t mine = 0u;
+    for (int64_t k = a; k < b; k++) mine += qcnt[k];
+    int wt = 0;
+    const uint32_t ex = (uint32_t)wave_excl_scan((int)mine, wt);
+    if (lane == 0) wsum[wave] = (uint32_t)wt;
+    __syncthreads();
+    uint32_t run = ex;
+    for (int w = 0; w < wave; w++) run += wsum[w];
+    for (int64_t k = a; k < b; k++) {
+        const uint32_t x = qcnt[k];
+        qcnt[k] = run;
+        run += x;
+    }
+}
+
+// Stable scatter: every position to its bin's offset, in position order.
+__global__ __launch_bounds__(64) void class_scatter_kernel(const uint16_t *__restrict__ qcode,
+                                                           const uint32_t *__restrict__ qthr, int64_t nb, int64_t n0,
+                                                           int64_t n1, int C, const uint32_t *__restrict__ qcnt,
+                                                           int64_t nblocks, uint32_t *qord)
+{
+    const int lane = threadIdx.x;
+    const int nbins = 3 * C;
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    uint32_t off[kMaxBins];
+#pragma unroll
+    for (int b = 0; b < kMaxBins; b++) off[b] = b < nbins ? qcnt[(int64_t)b * nblocks + blockIdx.x] : 0u;
+    const int64_t base = (int64_t)blockIdx.x * kClassRun;
+    for (int r = 0; r < kClassRounds; r++) {
+        const int64_t i = base + (int64_t)r * 64 + lane;
+        const int bin = i < nb ? class_bin(qcode, qthr, i, n0, n1, C) : -1;
+        uint32_t pos = 0u;
+#pragma unroll
+        for (int b = 0; b < kMaxBins; b++) {
+            if (b < nbins) {
+                const unsigned long long m = __ballot(bin == b);
+                if (bin == b) pos = off[b] + (uint32_t)__popcll(m & lt);
+                off[b] += (uint32_t)__popcll(m);
+            }
+        }
+        if (i < nb) qord[pos] = (uint32_t)i;
+    }
+}
+
+// Sweep, one wave per tile of 64 query records (one query per lane):
+// consecutive in sorted order, or in the query order of extent classes.  The
+// wave walks the union of its lanes' candidate windows in
 // sorted order -- faces for a vertex tile, later edges for an edge tile,
 // vertices for a face tile -- reading each candidate record with wave-uniform
 // (scalar) loads.  Every lane compares its query against the candidate; the
@@ -567,14 +732,16 @@ template <typename K, int ROLE>
 __device__ __forceinline__ void sweep_tile(const K *__restrict__ klo, const K *__restrict__ khi,
                                            const SweepRecords &R, int64_t qbase, int64_t qend, int64_t cbeg,
                                            int64_t cend, int64_t chunk, int64_t nchunks, int64_t clen,
-                                           int32_t *__restrict__ out,
+                                           const uint32_t *__restrict__ qord, int32_t *__restrict__ out,
                                            int64_t out_cap, unsigned long long *counter, int32_t (*s_out)[2])
 {
     constexpr int U = SweepUnroll<K>::value;
     const int lane = threadIdx.x;
     const unsigned long long lt = (1ull << lane) - 1ull;
-    const int64_t i = qbase + lane;
-    const bool valid = i < qend;
+    // lane's query: tile slot qbase + lane of the query order (sorted order
+    // itself without qord); i is its sorted position
+    const bool valid = qbase + lane < qend;
+    const int64_t i = valid ? (qord ? (int64_t)qord[qbase + lane] : qbase + lane) : qend;
     // an invalid lane's window is empty: kh = 0 is below every key, kl = max above
     K kl = ~(K)0, kh = 0;
     float lb = 0.f, hb = 0.f, lc = 0.f, hc = 0.f;
@@ -585,58 +752,73 @@ __device__ __forceinline__ void sweep_tile(const K *__restrict__ klo, const K *_
         me = R.pid[i];
         w0 = R.vtx[3 * i]; w1 = R.vtx[3 * i + 1]; w2 = R.vtx[3 * i + 2];
     }
-    const K kmin = uniform(wave_min_key(kl)), kmax = uniform(wave_max_key(kh));
-    int64_t j = ROLE == 1 ? qbase + 1 : wave_lower_bound(klo, cbeg, cend, kmin, ROLE == 2, lane);
-    j = (int64_t)uniform((unsigned long long)j);
-    // this wave's chunk of the window
-    const int64_t jw = j;
-    j = jw + chunk * clen;
-    const int64_t jend = chunk == nchunks - 1 ? cend : (jw + (chunk + 1) * clen < cend ? jw + (chunk + 1) * clen : cend);
+    // With a query order the lanes form runs of ascending sorted position (a
+    // new run starts where a lane's position is below its left neighbour's: a
+    // class boundary inside the tile).  Each run's windows are walked on their
+    // own, so that a tile holding the end of one class and the start of the
+    // next does not walk everything between them.  Sorted order is one run.
+    const uint32_t ipos = (uint32_t)i, iprev = __shfl_up(ipos, 1);
+    const unsigned long long brk = __ballot(lane > 0 && valid && ipos < iprev);
+    const int nruns = 1 + __popcll(brk);
+    const int run = __popcll(brk & ((lt << 1) | 1ull));
     int fill = 0;  // pairs staged in s_out (wave-uniform)
-    bool done = false;
-    for (; j + U <= jend; j += U) {
-        K kk[U];
-        float bl[U], bh[U], cl[U], ch[U];
-#pragma unroll
-        for (int u = 0; u < U; u++) {
-            kk[u] = klo[j + u];
-            bl[u] = R.lob[j + u]; bh[u] = R.hib[j + u]; cl[u] = R.loc[j + u]; ch[u] = R.hic[j + u];
-        }
-        // The block is tested whole (one wait for its loads); candidates past
-        // every lane's upper key fail the key test, and the walk ends after
-        // the block whose last key is past them all.
-        // Only the block's union mask is kept; the rare block with an overlap
-        // repeats its tests candidate by candidate to emit the pairs.
-        // Only the block's union mask is kept; the rare block with an overlap
-        // repeats its tests candidate by candidate to emit the pairs.
-        auto test = [&](int u) {
-            bool t = (kk[u] <= kh) & (bl[u] <= hb) & (lb <= bh[u]) & (cl[u] <= hc) & (lc <= ch[u]);
-            if (ROLE == 0) t &= kk[u] >= kl;
-            else if (ROLE == 1) t &= j + u > i;
-            else t &= kk[u] > kl;
-            return t;
-        };
-        unsigned long long any = 0ull;
-#pragma unroll
-        for (int u = 0; u < U; u++) any |= __ballot(test(u));
-        if (any != 0ull) {
+    for (int r = 0; r < nruns; r++) {
+        // lanes of other runs get empty windows: kh = 0 is below every key, kl = max above
+        const bool act = run == r;
+        const K rkl = act ? kl : ~(K)0, rkh = act ? kh : (K)0;
+        const K kmin = uniform(wave_min_key(rkl)), kmax = uniform(wave_max_key(rkh));
+        // an edge's window starts right after it: the run's walk after its first edge
+        const int64_t ifirst = (int64_t)uniform(wave_min_key<unsigned long long>(act ? (unsigned long long)i : ~0ull));
+        int64_t j = ROLE == 1 ? ifirst + 1 : wave_lower_bound(klo, cbeg, cend, kmin, ROLE == 2, lane);
+        j = (int64_t)uniform((unsigned long long)j);
+        // this wave's chunk of the window
+        const int64_t jw = j;
+        j = jw + chunk * clen;
+        const int64_t jend =
+            chunk == nchunks - 1 ? cend : (jw + (chunk + 1) * clen < cend ? jw + (chunk + 1) * clen : cend);
+        bool done = false;
+        for (; j + U <= jend; j += U) {
+            K kk[U];
+            float bl[U], bh[U], cl[U], ch[U];
 #pragma unroll
             for (int u = 0; u < U; u++) {
-                const bool t = test(u);
-                if (__ballot(t)) sweep_emit<K, ROLE>(j + u, t, R, me, w0, w1, w2, lane, lt, fill, out, out_cap, counter,
-                                                     s_out);
+                kk[u] = klo[j + u];
+                bl[u] = R.lob[j + u]; bh[u] = R.hib[j + u]; cl[u] = R.loc[j + u]; ch[u] = R.hic[j + u];
             }
+            // The block is tested whole (one wait for its loads); candidates past
+            // every lane's upper key fail the key test, and the walk ends after
+            // the block whose last key is past them all.  Only the block's union
+            // mask is kept; the rare block with an overlap repeats its tests
+            // candidate by candidate to emit the pairs.
+            auto test = [&](int u) {
+                bool t = (kk[u] <= rkh) & (bl[u] <= hb) & (lb <= bh[u]) & (cl[u] <= hc) & (lc <= ch[u]);
+                if (ROLE == 0) t &= kk[u] >= rkl;
+                else if (ROLE == 1) t &= j + u > i;
+                else t &= kk[u] > rkl;
+                return t;
+            };
+            unsigned long long any = 0ull;
+#pragma unroll
+            for (int u = 0; u < U; u++) any |= __ballot(test(u));
+            if (any != 0ull) {
+#pragma unroll
+                for (int u = 0; u < U; u++) {
+                    const bool t = test(u);
+                    if (__ballot(t))
+                        sweep_emit<K, ROLE>(j + u, t, R, me, w0, w1, w2, lane, lt, fill, out, out_cap, counter, s_out);
+                }
+            }
+            if (kk[U - 1] > kmax) { done = true; break; }  // every later candidate lies beyond all windows
         }
-        if (kk[U - 1] > kmax) { done = true; break; }  // every later candidate lies beyond all windows
-    }
-    for (; !done && j < jend; j++) {
-        const K kj = klo[j];
-        if (kj > kmax) break;
-        bool t = (kj <= kh) & (R.lob[j] <= hb) & (lb <= R.hib[j]) & (R.loc[j] <= hc) & (lc <= R.hic[j]);
-        if (ROLE == 0) t &= kj >= kl;
-        else if (ROLE == 1) t &= j > i;
-        else t &= kj > kl;
-        if (__ballot(t)) sweep_emit<K, ROLE>(j, t, R, me, w0, w1, w2, lane, lt, fill, out, out_cap, counter, s_out);
+        for (; !done && j < jend; j++) {
+            const K kj = klo[j];
+            if (kj > kmax) break;
+            bool t = (kj <= rkh) & (R.lob[j] <= hb) & (lb <= R.hib[j]) & (R.loc[j] <= hc) & (lc <= R.hic[j]);
+            if (ROLE == 0) t &= kj >= rkl;
+            else if (ROLE == 1) t &= j > i;
+            else t &= kj > rkl;
+            if (__ballot(t)) sweep_emit<K, ROLE>(j, t, R, me, w0, w1, w2, lane, lt, fill, out, out_cap, counter, s_out);
+        }
     }
     if (fill > 0) {
         __syncthreads();
@@ -650,8 +832,8 @@ __global__ __launch_bounds__(kTile) void sweep_kernel(
     const float *__restrict__ hib, const float *__restrict__ loc, const float *__restrict__ hic,
     const int32_t *__restrict__ pid, const int32_t *__restrict__ vtx, int64_t nv, int64_t ne, int64_t nf,
     int64_t tiles_v, int64_t tiles_e, int64_t tile0, int64_t tile1, int64_t tiles_grid, int64_t group,
-    SweepChunks ch, int32_t *__restrict__ vf, int64_t vf_cap, int32_t *__restrict__ ee, int64_t ee_cap,
-    unsigned long long *counts)
+    SweepChunks ch, const uint32_t *__restrict__ qord, int32_t *__restrict__ vf, int64_t vf_cap,
+    int32_t *__restrict__ ee, int64_t ee_cap, unsigned long long *counts)
 {
     __shared__ int32_t s_out[kOutCap][2];
     const int64_t nb = nv + ne + nf, f0 = nv + ne;
@@ -664,15 +846,16 @@ __global__ __launch_bounds__(kTile) void sweep_kernel(
     const SweepRecords R{lob, hib, loc, hic, pid, vtx};
     if (t < tiles_v) {
         if (chunk >= ch.vf) return;
-        sweep_tile<K, 0>(klo, khi, R, t * kTile, nv, f0, nb, chunk, ch.vf, ch.len, vf, vf_cap, &counts[0], s_out);
+        sweep_tile<K, 0>(klo, khi, R, t * kTile, nv, f0, nb, chunk, ch.vf, ch.len, qord, vf, vf_cap, &counts[0],
+                         s_out);
     } else if (t < tiles_v + tiles_e) {
         if (chunk >= ch.ee) return;
-        sweep_tile<K, 1>(klo, khi, R, nv + (t - tiles_v) * kTile, f0, nv, f0, chunk, ch.ee, ch.len, ee, ee_cap,
-                         &counts[1], s_out);
+        sweep_tile<K, 1>(klo, khi, R, nv + (t - tiles_v) * kTile, f0, nv, f0, chunk, ch.ee, ch.len, qord, ee,
+                         ee_cap, &counts[1], s_out);
     } else {
         if (chunk >= ch.vf) return;
-        sweep_tile<K, 2>(klo, khi, R, f0 + (t - tiles_v - tiles_e) * kTile, nb, 0, nv, chunk, ch.vf, ch.len, vf,
-                         vf_cap, &counts[0], s_out);
+        sweep_tile<K, 2>(klo, khi, R, f0 + (t - tiles_v - tiles_e) * kTile, nb, 0, nv, chunk, ch.vf, ch.len, qord,
+                         vf, vf_cap, &counts[0], s_out);
     }
 }
 
@@ -687,7 +870,9 @@ void launch_broad_boxes(const double *V0, const double *V1, int64_t nv, const in
 {
     const int64_t nb = nv + ne + nf;
     const int64_t nstats = 6 * B.nscenes;
-    zero_kernel<<<grid_for(nstats > 64 ? nstats : 64, 256), 256, 0, s>>>(B.stats, nstats, B.counts, B.flags);
+    const int64_t nzero = std::max<int64_t>(std::max<int64_t>(nstats, 64), B.qhist ? 3 * kExtentCodes : 0);
+    zero_kernel<<<grid_for(nzero, 256), 256, 0, s>>>(B.stats, nstats, B.counts, B.flags,
+                                                     B.qclasses > 1 ? B.qhist : nullptr);
     const int64_t nblk = box_blocks(nb);
     if (nb > 0)
         box_kernel<<<(unsigned)nblk, kBoxBlock, 0, s>>>(V0, V1, nv, E, ne, F, nf, B.off, B.nscenes, B.lo[0],
@@ -735,6 +920,27 @@ static inline const uint32_t *sorted_vals(const BroadBuffers &B)
     return (4 + scene_passes(B.nscenes)) % 2 == 0 ? B.valA : B.valB;
 }
 
+int64_t class_blocks(int64_t nb) { return nb > 0 ? (nb + kClassRun - 1) / kClassRun : 1; }
+
+int sweep_class_count(int32_t tuned, int64_t nb, int64_t nscenes)
+{
+    if (nscenes > 1) return 1;
+    if (tuned == 0) return nb >= ((int64_t)1 << 20) ? 4 : 1;
+    return std::min<int32_t>(std::max<int32_t>(tuned, 1), 8);
+}
+
+// The query order qord (B.qclasses > 1; B.qcode written by the gather).
+static void launch_query_order(int64_t nv, int64_t ne, int64_t nf, const BroadBuffers &B, hipStream_t s)
+{
+    const int64_t nb = nv + ne + nf, nbk = class_blocks(nb);
+    const int C = B.qclasses;
+    extent_hist_kernel<<<(unsigned)nbk, 256, 0, s>>>(B.qcode, nb, nv, nv + ne, B.qhist);
+    extent_split_kernel<<<1, 256, 0, s>>>(B.qhist, nv, ne, nf, C, B.qthr);
+    class_count_kernel<<<(unsigned)nbk, 64, 0, s>>>(B.qcode, B.qthr, nb, nv, nv + ne, C, B.qcnt, nbk);
+    class_scan_kernel<<<1, 1024, 0, s>>>(B.qcnt, 3 * (int64_t)C * nbk);
+    class_scatter_kernel<<<(unsigned)nbk, 64, 0, s>>>(B.qcode, B.qthr, nb, nv, nv + ne, C, B.qcnt, nbk, B.qord);
+}
+
 void launch_broad_gather(const int32_t *E, const int32_t *F, int64_t nv, int64_t ne, int64_t nf,
                          const BroadBuffers &B, hipStream_t s)
 {
@@ -744,7 +950,9 @@ void launch_broad_gather(const int32_t *E, const int32_t *F, int64_t nv, int64_t
     gather_kernel<<<grid_for(nb, 256), 256, 0, s>>>(sorted_keys(B), sorted_vals(B), nv, ne, nf, E, F, B.lo[0],
                                                    B.lo[1], B.lo[2], B.hi[0], B.hi[1], B.hi[2], B.bscene, B.axis,
                                                    B.khi, multi ? B.klo64 : nullptr, multi ? B.khi64 : nullptr,
-                                                   B.lob, B.hib, B.loc, B.hic, B.pid, B.vtx);
+                                                   B.lob, B.hib, B.loc, B.hic, B.pid, B.vtx,
+                                                   B.qclasses > 1 ? B.qcode : nullptr);
+    if (B.qclasses > 1) launch_query_order(nv, ne, nf, B, s);
 }
 
 int64_t sweep_tiles(int64_t nv, int64_t ne, int64_t nf)
@@ -781,11 +989,12 @@ void launch_broad_sweep(int64_t nv, int64_t ne, int64_t nf, int32_t *vf, int64_t
     if (B.nscenes > 1)
         sweep_kernel<unsigned long long><<<(unsigned)grid, kTile, 0, s>>>(
             B.klo64, B.khi64, B.lob, B.hib, B.loc, B.hic, B.pid, B.vtx, nv, ne, nf, tv, te, tile0, tile1, tiles_grid, g,
-            ch, vf, vf_cap, ee, ee_cap, B.counts);
+            ch, nullptr, vf, vf_cap, ee, ee_cap, B.counts);
     else
         sweep_kernel<uint32_t><<<(unsigned)grid, kTile, 0, s>>>(sorted_keys(B), B.khi, B.lob, B.hib, B.loc, B.hic,
                                                                B.pid, B.vtx, nv, ne, nf, tv, te, tile0, tile1,
-                                                               tiles_grid, g, ch, vf, vf_cap, ee, ee_cap, B.counts);
+                                                               tiles_grid, g, ch, B.qclasses > 1 ? B.qord : nullptr,
+                                                               vf, vf_cap, ee, ee_cap, B.counts);
 }
 
 int64_t sort_blocks(int64_t nb)

@@ -105,9 +105,23 @@ struct BroadBuffers {
     int32_t *vtx;         // up to 3 vertex ids per record (stride 3)
     unsigned long long *counts;    // [0] = n_vf, [1] = n_ee
     uint32_t *flags;
+    // query order of the sweep (one scene only; null with several): the sorted
+    // positions of each segment grouped into qclasses classes of extent on the
+    // sweep axis, ascending within a class; qclasses = 1 sweeps in sorted order
+    int32_t qclasses;
+    uint16_t *qcode;      // extent code of every sorted record
+    uint32_t *qhist;      // 3 x kExtentCodes counts of the codes per segment
+    uint32_t *qthr;       // 3 x 8 class thresholds (codes)
+    uint32_t *qcnt;       // 3 x 8 x class_blocks(nb) counts, then their offsets
+    uint32_t *qord;       // the order: sorted positions, segments [V | E | F]
 };
 
+constexpr int kExtentCodes = 2048;
 int64_t sort_blocks(int64_t nb);
+int64_t class_blocks(int64_t nb);
+// Classes the sweep groups its queries into: the tuning's value, or with 0 four
+// for one scene of at least 2^20 boxes; 1 (sorted order) for several scenes.
+int sweep_class_count(int32_t tuned, int64_t nb, int64_t nscenes);
 int64_t box_blocks(int64_t nb);
 
 // Broad phase in four stages (the host records timing events between them):

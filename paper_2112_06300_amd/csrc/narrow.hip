@@ -56,7 +56,11 @@ struct Query {
     double d[4][3];   // displacement x1 - x0
     double eps[3];    // half-width of C_eps per axis
     int m[3];         // levels after which t, u, v are fine enough for delta
+    __device__ __forceinline__ double X(int k, int a) const { return x0[k][a]; }
+    __device__ __forceinline__ double D(int k, int a) const { return d[k][a]; }
+    __device__ __forceinline__ double E(int a) const { return eps[a]; }
 };
+
 
 // Smallest m >= 0 with RN(3 L) 2^-m <= delta, from exact exponent arithmetic.
 __device__ __forceinline__ int need_levels(double L, double delta)
@@ -134,6 +138,16 @@ __device__ __forceinline__ bool pair_constants(bool vf, const double raw[24], do
 // 2^-l for 0 <= l <= 52, built from the exponent bits.
 __device__ __forceinline__ double pow2neg(int l) { return __longlong_as_double((long long)(1023 - l) << 52); }
 
+// The dyadic n 2^-l for a numerator n < 2^l <= 2^52, exactly: with
+// big = 2^(52 - l), the double whose exponent is big's and whose mantissa
+// bits are n has the value big + n 2^-l, and subtracting big is exact.  Two
+// instructions where a 64-bit integer conversion and a scaling take five.
+__device__ __forceinline__ double dyadic_big(int l) { return __longlong_as_double((long long)(1075 - l) << 52); }
+__device__ __forceinline__ double dyadic(unsigned long long n, double big)
+{
+    return __longlong_as_double(__double_as_longlong(big) | (long long)n) - big;
+}
+
 // Inclusion box of F over the interval's 8 corners and the decision of
 // Alg. 3 (discard / report / split).  Inputs are finite, so min / max are
 // exact; the sign of a zero bound never changes a decision.  The corner
@@ -144,7 +158,8 @@ __device__ __forceinline__ double pow2neg(int l) { return __longlong_as_double((
 // at_zero (App. B, no-zero-TOI strategy, for an interval starting at t = 0):
 // the interval is not reported for being narrow or inside C_eps, only at the
 // finest level.
-__device__ __forceinline__ int process(const Query &q, bool vf, double t0, double t1, double u0, double u1,
+template <class Q>
+__device__ __forceinline__ int process(const Q &q, bool vf, double t0, double t1, double u0, double u1,
                                        double v0, double v1, bool finest, double delta, bool at_zero = false)
 {
     if (vf && u0 + v0 > 1.0) return DISCARD;
@@ -156,10 +171,10 @@ __device__ __forceinline__ int process(const Query &q, bool vf, double t0, doubl
 #pragma unroll
         for (int it = 0; it < 2; it++) {
             const double t = it ? t1 : t0;
-            const double P0 = fma(t, q.d[0][a], q.x0[0][a]);
-            const double P1 = fma(t, q.d[1][a], q.x0[1][a]);
-            const double P2 = fma(t, q.d[2][a], q.x0[2][a]);
-            const double P3 = fma(t, q.d[3][a], q.x0[3][a]);
+            const double P0 = fma(t, q.D(0, a), q.X(0, a));
+            const double P1 = fma(t, q.D(1, a), q.X(1, a));
+            const double P2 = fma(t, q.D(2, a), q.X(2, a));
+            const double P3 = fma(t, q.D(3, a), q.X(3, a));
             if (vf) {
                 const double pa = P0 - P1, eb = P2 - P1, ec = P3 - P1;
 #pragma unroll
@@ -181,10 +196,10 @@ __device__ __forceinline__ int process(const Query &q, bool vf, double t0, doubl
                 bmax = fmax(fmax(bmax, f00), fmax(f01, fmax(f10, f11)));
             }
         }
-        if (bmin > q.eps[a] || bmax < -q.eps[a]) return DISCARD;
+        if (bmin > q.E(a) || bmax < -q.E(a)) return DISCARD;
         const double w = bmax - bmin;
         width = w > width ? w : width;
-        inside = inside && bmin >= -q.eps[a] && bmax <= q.eps[a];
+        inside = inside && bmin >= -q.E(a) && bmax <= q.E(a);
     }
     if (((width < delta || inside) && !at_zero) || finest) return ACCEPT;
     return SPLIT;
@@ -197,21 +212,25 @@ __device__ __forceinline__ int process(const Query &q, bool vf, double t0, doubl
 // two children share are evaluated once and each child's box is exactly the
 // one process() computes for it.  Child 0 spans indices 0..1 along K, child 1
 // indices 1..2.
-template <int K, bool VF>
-__device__ __forceinline__ void axis_pair(const Query &q, int a, const double T[3], const double U[3],
+template <int K, bool VF, class Q>
+__device__ __forceinline__ void axis_pair(const Q &q, int a, const double T[3], const double U[3],
                                           const double V[3], double &mn0, double &mx0, double &mn1, double &mx1)
 {
     constexpr int NT = K == 0 ? 3 : 2, NU = K == 1 ? 3 : 2, NV = K == 2 ? 3 : 2;
-    // running min / max of the three slices across K (4 corners each)
-    double smn[3] = {__builtin_huge_val(), __builtin_huge_val(), __builtin_huge_val()};
-    double smx[3] = {-__builtin_huge_val(), -__builtin_huge_val(), -__builtin_huge_val()};
+    // running min / max of the three slices across K (4 corners each), each
+    // started at its slice's first corner
+    double smn[3], smx[3];
+    auto fold = [&](int sl, bool first, double f) {
+        smn[sl] = first ? f : fmin(smn[sl], f);
+        smx[sl] = first ? f : fmax(smx[sl], f);
+    };
 #pragma unroll
     for (int it = 0; it < NT; it++) {
         const double t = T[it];
-        const double P0 = fma(t, q.d[0][a], q.x0[0][a]);
-        const double P1 = fma(t, q.d[1][a], q.x0[1][a]);
-        const double P2 = fma(t, q.d[2][a], q.x0[2][a]);
-        const double P3 = fma(t, q.d[3][a], q.x0[3][a]);
+        const double P0 = fma(t, q.D(0, a), q.X(0, a));
+        const double P1 = fma(t, q.D(1, a), q.X(1, a));
+        const double P2 = fma(t, q.D(2, a), q.X(2, a));
+        const double P3 = fma(t, q.D(3, a), q.X(3, a));
         if (VF) {
             const double pa = P0 - P1, eb = P2 - P1, ec = P3 - P1;
 #pragma unroll
@@ -221,8 +240,8 @@ __device__ __forceinline__ void axis_pair(const Query &q, int a, const double T[
                 for (int iv = 0; iv < NV; iv++) {
                     const double f = fma(-V[iv], ec, g);
                     const int sl = K == 0 ? it : (K == 1 ? iu : iv);
-                    smn[sl] = fmin(smn[sl], f);
-                    smx[sl] = fmax(smx[sl], f);
+                    const bool first = K == 0 ? (iu == 0 && iv == 0) : (K == 1 ? (it == 0 && iv == 0) : (it == 0 && iu == 0));
+                    fold(sl, first, f);
                 }
             }
         } else {
@@ -237,8 +256,8 @@ __device__ __forceinline__ void axis_pair(const Query &q, int a, const double T[
                 for (int iv = 0; iv < NV; iv++) {
                     const double f = A - B[iv];
                     const int sl = K == 0 ? it : (K == 1 ? iu : iv);
-                    smn[sl] = fmin(smn[sl], f);
-                    smx[sl] = fmax(smx[sl], f);
+                    const bool first = K == 0 ? (iu == 0 && iv == 0) : (K == 1 ? (it == 0 && iv == 0) : (it == 0 && iu == 0));
+                    fold(sl, first, f);
                 }
             }
         }
@@ -253,8 +272,8 @@ __device__ __forceinline__ void axis_pair(const Query &q, int a, const double T[
 // along K, identical to process() on each child.  A child not needed (need
 // false) reports DISCARD without being evaluated; az: the child starts at
 // t = 0 (no-zero strategy).
-template <int K>
-__device__ __forceinline__ void process_pair(const Query &q, bool vf, const double T[3], const double U[3],
+template <int K, class Q>
+__device__ __forceinline__ void process_pair(const Q &q, bool vf, const double T[3], const double U[3],
                                              const double V[3], bool need0, bool need1, bool finest, double delta,
                                              bool az0, bool az1, int &r0, int &r1)
 {
@@ -268,13 +287,14 @@ __device__ __forceinline__ void process_pair(const Query &q, bool vf, const doub
     for (int a = 0; a < 3; a++) {
         if (d0 && d1) break;
         double mn0, mx0, mn1, mx1;
-        if (vf) axis_pair<K, true>(q, a, T, U, V, mn0, mx0, mn1, mx1);
-        else axis_pair<K, false>(q, a, T, U, V, mn0, mx0, mn1, mx1);
-        const double e = q.eps[a];
+        if (vf) axis_pair<K, true, Q>(q, a, T, U, V, mn0, mx0, mn1, mx1);
+        else axis_pair<K, false, Q>(q, a, T, U, V, mn0, mx0, mn1, mx1);
+        const double e = q.E(a);
         d0 = d0 || mn0 > e || mx0 < -e;
         d1 = d1 || mn1 > e || mx1 < -e;
-        w0 = fmax(w0, mx0 - mn0);
-        w1 = fmax(w1, mx1 - mn1);
+        // the widths are >= 0 (max >= min of finite values): the first axis's is the start
+        w0 = a == 0 ? mx0 - mn0 : fmax(w0, mx0 - mn0);
+        w1 = a == 0 ? mx1 - mn1 : fmax(w1, mx1 - mn1);
         in0 = in0 && mn0 >= -e && mx0 <= e;
         in1 = in1 && mn1 >= -e && mx1 <= e;
     }
@@ -1035,15 +1055,58 @@ __device__ __forceinline__ double wave_min(double v)
 // Wide stage: one workgroup per handed-over pair, frontier in HBM scratch.
 // `list` (optional) maps work indices to heavy slots; `list_count` holds the
 // number of work items.
+// Arguments of the wide stage, passed as one struct.  The kernel reads the
+// few that its level loop uses into registers once; every other one is read
+// where it is used through cold(), so that none of them occupies a scalar
+// register across the float64 loop (the loop's own uniform state then fits
+// the scalar register file without spills).
+struct HeavyArgs {
+    const double *V0, *V1;
+    const int4 *ids4;
+    const double *peps;
+    const uint32_t *pm;
+    PairCounts pc;
+    double delta;
+    long long max_iter;
+    uint8_t *hit;
+    double *toi;
+    long long *n_enq_out;
+    HeavyEntry *heavy;
+    unsigned long long *hnodes;
+    int64_t hnode_cap;
+    unsigned long long *node_ctr;
+    int resume;
+    const int32_t *list;
+    const unsigned int *list_count;
+    unsigned int *next;
+    int32_t *ovf_list;
+    unsigned int *ovf_count;
+    unsigned long long *scratch;
+    int64_t cap;
+    uint32_t *flags;
+    int use_lds;
+    const unsigned int *list_base;
+    unsigned int min_count, max_count;
+    double *toi_min;
+    int gmode, no_zero;
+};
+
+typedef const __attribute__((address_space(4))) HeavyArgs *KernargHeavy;
+
+// The kernel's argument block in the kernarg segment (the struct is the only
+// explicit argument, at offset 0), behind an opaque copy of the pointer so
+// that every read is a fresh scalar load at its point of use.
+__device__ __forceinline__ KernargHeavy cold()
+{
+    KernargHeavy a = (KernargHeavy)__builtin_amdgcn_kernarg_segment_ptr();
+    asm volatile("" : "+s"(a));
+    return a;
+}
+
 template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) void heavy_kernel(
-    const double *__restrict__ V0, const double *__restrict__ V1, const int4 *__restrict__ ids4,
-    const double *__restrict__ peps, const uint32_t *__restrict__ pm, PairCounts pc, double delta,
-    long long max_iter, uint8_t *hit, double *toi, long long *n_enq_out, HeavyEntry *heavy,
-    unsigned long long *hnodes, int64_t hnode_cap, unsigned long long *node_ctr, int resume, const int32_t *list,
-    const unsigned int *list_count, unsigned int *next, int32_t *ovf_list, unsigned int *ovf_count,
-    unsigned long long *scratch, int64_t cap, uint32_t *flags, int use_lds, const unsigned int *list_base,
-    unsigned int min_count, unsigned int max_count, double *toi_min, int gmode, int no_zero)
+// at least 3 waves per SIMD for the 64- and 256-thread variants (168 registers)
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(BLOCK == 1024 ? 4 : 3, 8))) void heavy_kernel(
+    const HeavyArgs args)
 {
     // Frontier of the next level: in LDS when it surely fits (at most twice the
     // current frontier), else in this workgroup's HBM buffers.
@@ -1063,30 +1126,41 @@ __global__ __launch_bounds__(BLOCK) void heavy_kernel(
     __shared__ int s_zero[3];                 // a kept child starts at t = 0 (no-zero strategy)
     __shared__ double s_tg[3];                // global mode: the shared t* read for the next level
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    int64_t n_vf, n_all;
-    pc.get(n_vf, n_all);
-    (void)n_all;
+    // loop-hot arguments
+    const double delta = args.delta;
+    const long long max_iter = args.max_iter;
+    const int gmode = args.gmode, no_zero = args.no_zero, use_lds = args.use_lds;
+    double *const toi_min = args.toi_min;
+    const int64_t cap = args.cap;
     // Adaptive launches start two variants of this kernel; only the one whose
     // range holds the number of entries left to it (those past list_base, which
     // the early wide stage took) takes any.
     {
-        const unsigned int c0 = *list_count - (list_base ? *list_base : 0u);
-        if (c0 < min_count || c0 > max_count) return;
+        const unsigned int c0 = *args.list_count - (args.list_base ? *args.list_base : 0u);
+        if (c0 < args.min_count || c0 > args.max_count) return;
     }
-    unsigned long long *A = scratch + (int64_t)blockIdx.x * 6 * cap;
+    unsigned long long *A = args.scratch + (int64_t)blockIdx.x * 6 * cap;
     unsigned long long *Bb = A + 3 * cap;
     for (;;) {
-        if (tid == 0) s_idx = (int)atomicAdd(next, 1u);
+        if (tid == 0) s_idx = (int)atomicAdd(cold()->next, 1u);
         __syncthreads();
         const int idx = s_idx;
-        const unsigned total = *list_count;
+        const unsigned total = *cold()->list_count;
         if (idx >= (int)total) break;
+        const int32_t *list = cold()->list;
         const int slot = list ? list[idx] : idx;
-        HeavyEntry h = heavy[slot];
+        HeavyEntry h = cold()->heavy[slot];
         const int64_t p = h.pair;
+        int64_t n_vf, n_all;
+        {
+            const KernargHeavy a = cold();
+            const PairCounts pc{a->pc.n_vf, a->pc.n_ee, a->pc.dev};
+            pc.get(n_vf, n_all);
+        }
+        (void)n_all;
         const bool vf = p < n_vf;
         double raw[24];
-        load_raw(ids4[p], V0, V1, raw);
+        load_raw(cold()->ids4[p], cold()->V0, cold()->V1, raw);
         Query q;
 #pragma unroll
         for (int kk = 0; kk < 4; kk++)
@@ -1095,8 +1169,11 @@ __global__ __launch_bounds__(BLOCK) void heavy_kernel(
                 q.x0[kk][a] = raw[3 * kk + a];
                 q.d[kk][a] = raw[12 + 3 * kk + a] - raw[3 * kk + a];
             }
-        q.eps[0] = peps[3 * p]; q.eps[1] = peps[3 * p + 1]; q.eps[2] = peps[3 * p + 2];
-        unpack_m(pm[p], q.m);
+        {
+            const double *peps = cold()->peps;
+            q.eps[0] = peps[3 * p]; q.eps[1] = peps[3 * p + 1]; q.eps[2] = peps[3 * p + 2];
+        }
+        unpack_m(cold()->pm[p], q.m);
         int l[3] = {h.lvl[0], h.lvl[1], h.lvl[2]};
         long long nenq = h.n_enq;
         int64_t nS = h.nnodes;
@@ -1135,8 +1212,10 @@ __global__ __launch_bounds__(BLOCK) void heavy_kernel(
             nS = 1;
             pk_cur = true;
         } else if (pk_cur) {
+            const unsigned long long *hnodes = cold()->hnodes;
             for (int64_t i = tid; i < nS; i += BLOCK) cur[i] = hnodes[h.node_off + i];
         } else if (h.layout == 0) {
+            const unsigned long long *hnodes = cold()->hnodes;
             for (int64_t i = tid; i < nS; i += BLOCK) {
                 const unsigned long long pk = hnodes[h.node_off + i];
                 cur[i] = pk & 0x1fffffull;
@@ -1144,6 +1223,7 @@ __global__ __launch_bounds__(BLOCK) void heavy_kernel(
                 cur[2 * cap + i] = (pk >> 42) & 0x1fffffull;
             }
         } else {
+            const unsigned long long *hnodes = cold()->hnodes;
             for (int64_t i = tid; i < nS; i += BLOCK) {
                 cur[i] = hnodes[h.node_off + i];
                 cur[cap + i] = hnodes[h.node_off + nS + i];
@@ -1162,6 +1242,7 @@ __global__ __launch_bounds__(BLOCK) void heavy_kernel(
             // mode the shared one, read once for the whole workgroup)
             const double tsnap = fmin(tstar, s_tg[ps]);
             const double tscale = pow2neg(l[0]), uscale = pow2neg(l[1]), vscale = pow2neg(l[2]);
+            const double tbig = dyadic_big(l[0]), ubig = dyadic_big(l[1]), vbig = dyadic_big(l[2]);
             const bool finest = l[0] == kMaxLevel && l[1] == kMaxLevel && l[2] == kMaxLevel;
             // where this level's survivors go
             if (use_lds && 2 * nS <= (pk_nxt ? 3 * kLds : kLds)) {
@@ -1213,24 +1294,23 @@ __global__ __launch_bounds__(BLOCK) void heavy_kernel(
                 }
             };
             // kept (counted) when it starts before the level's bound
-            auto keep = [&](const unsigned long long cn[3], bool has) {
-                const double t0 = (double)cn[0] * tscale;
+            // t0: the child's lower time bound; z: it starts at t = 0
+            auto keep = [&](double t0, bool z, bool has) {
                 const bool inF = has && t0 < tsnap;
                 if (inF) { cnt++; tmin = t0 < tmin ? t0 : tmin; }
-                if (inF && no_zero && cn[0] == 0ull) s_zero[ps] = 1;
+                if (inF && no_zero && z) s_zero[ps] = 1;
                 return inF;
             };
             auto child = [&](const unsigned long long cn[3], bool has) {
-                const double t0 = (double)cn[0] * tscale;
-                const bool inF = keep(cn, has);
+                const double t0 = dyadic(cn[0], tbig);
+                const bool inF = keep(t0, cn[0] == 0ull, has);
                 // roots reported at this level only shorten the work, never the count
                 const double tl = __longlong_as_double((long long)(*(volatile unsigned long long *)&s_tl[ps]));
                 int r = DISCARD;
                 if (inF && t0 < tl) {
-                    const double t1 = (double)(cn[0] + 1ull) * tscale;
-                    const double u0 = (double)cn[1] * uscale, u1 = (double)(cn[1] + 1ull) * uscale;
-                    const double v0 = (double)cn[2] * vscale, v1 = (double)(cn[2] + 1ull) * vscale;
-                    r = process(q, vf, t0, t1, u0, u1, v0, v1, finest, delta, no_zero && cn[0] == 0ull);
+                    const double u0 = dyadic(cn[1], ubig), v0 = dyadic(cn[2], vbig);
+                    r = process(q, vf, t0, t0 + tscale, u0, u0 + uscale, v0, v0 + vscale, finest, delta,
+                                no_zero && cn[0] == 0ull);
                 }
                 emit(cn, r, t0);
             };
@@ -1239,25 +1319,54 @@ __global__ __launch_bounds__(BLOCK) void heavy_kernel(
                 unsigned long long c0[3] = {pn[0], pn[1], pn[2]}, c1[3] = {pn[0], pn[1], pn[2]};
                 c0[k] = 2ull * pn[k];
                 c1[k] = 2ull * pn[k] + 1ull;
-                const double t00 = (double)c0[0] * tscale, t10 = (double)c1[0] * tscale;
-                const bool in0 = keep(c0, has), in1 = keep(c1, has);
+                // corner coordinates: low, mid, high along k (the children's bounds),
+                // low, high otherwise; n 2^-l + 2^-l is exactly (n + 1) 2^-l
+                double T[3], U[3], V[3];
+                T[0] = dyadic(c0[0], tbig); T[1] = T[0] + tscale; T[2] = T[1] + tscale;
+                U[0] = dyadic(c0[1], ubig); U[1] = U[0] + uscale; U[2] = U[1] + uscale;
+                V[0] = dyadic(c0[2], vbig); V[1] = V[0] + vscale; V[2] = V[1] + vscale;
+                const double t00 = T[0], t10 = k == 0 ? T[1] : T[0];
+                const bool in0 = keep(t00, c0[0] == 0ull, has), in1 = keep(t10, c1[0] == 0ull, has);
                 const double tl = __longlong_as_double((long long)(*(volatile unsigned long long *)&s_tl[ps]));
-                const bool need0 = in0 && t00 < tl, need1 = in1 && t10 < tl;
+                // once the next frontier has outgrown its buffer this level will be
+                // redone with larger ones (unless it ends the pair at the cap, which
+                // the count decides): its remaining children are counted, not evaluated
+                const bool ovf = *(volatile unsigned int *)&s_ovf[ps] != 0u;
+                const bool need0 = in0 && t00 < tl && !ovf, need1 = in1 && t10 < tl && !ovf;
                 int r0 = DISCARD, r1 = DISCARD;
                 if (need0 || need1) {
-                    // corner coordinates: low, mid, high along k (children's bounds), low, high otherwise
-                    double T[3], U[3], V[3];
-                    const unsigned long long nt = c0[0], nu = c0[1], nw = c0[2];
-                    T[0] = (double)nt * tscale; T[1] = (double)(nt + 1ull) * tscale; T[2] = (double)(nt + 2ull) * tscale;
-                    U[0] = (double)nu * uscale; U[1] = (double)(nu + 1ull) * uscale; U[2] = (double)(nu + 2ull) * uscale;
-                    V[0] = (double)nw * vscale; V[1] = (double)(nw + 1ull) * vscale; V[2] = (double)(nw + 2ull) * vscale;
                     const bool az0 = no_zero && c0[0] == 0ull, az1 = no_zero && c1[0] == 0ull;
                     if (k == 0) process_pair<0>(q, vf, T, U, V, need0, need1, finest, delta, az0, az1, r0, r1);
                     else if (k == 1) process_pair<1>(q, vf, T, U, V, need0, need1, finest, delta, az0, az1, r0, r1);
                     else process_pair<2>(q, vf, T, U, V, need0, need1, finest, delta, az0, az1, r0, r1);
                 }
-                emit(c0, r0, t00);
-                emit(c1, r1, t10);
+                // accepted children lower the level's t* (rare); survivors of both
+                // children take their places with one wave scan and one LDS atomic
+                if (r0 == ACCEPT || r1 == ACCEPT) {
+                    const double ta = r0 == ACCEPT ? t00 : t10;
+                    atomicMin(&s_tl[ps], (unsigned long long)__double_as_longlong(ta));
+                    if (gmode) atomicMin((unsigned long long *)toi_min, (unsigned long long)__double_as_longlong(ta));
+                }
+                const int s0 = r0 == SPLIT ? 1 : 0, s1 = r1 == SPLIT ? 1 : 0;
+                int tot = 0;
+                const int pre = wave_excl_scan(s0 + s1, tot);
+                if (tot) {
+                    unsigned int base = 0u;
+                    if (lane == 63) base = atomicAdd(&s_nN[ps], (unsigned int)tot);
+                    base = __shfl(base, 63);
+                    auto put = [&](const unsigned long long cn[3], int64_t pos) {
+                        if (pk_nxt && pos < 3 * nstride) {
+                            nxt[pos] = cn[0] | cn[1] << 21 | cn[2] << 42;
+                        } else if (!pk_nxt && pos < nstride) {
+                            nxt[pos] = cn[0]; nxt[nstride + pos] = cn[1]; nxt[2 * nstride + pos] = cn[2];
+                        } else {
+                            s_ovf[ps] = 1u;
+                        }
+                    };
+                    const int64_t pos = (int64_t)base + pre;
+                    if (s0) put(c0, pos);
+                    if (s1) put(c1, pos + s0);
+                }
             };
             auto node = [&](int64_t ni, bool has, unsigned long long pn[3]) {
                 pn[0] = pn[1] = pn[2] = 0ull;
@@ -1277,12 +1386,23 @@ __global__ __launch_bounds__(BLOCK) void heavy_kernel(
                 cn[k] = 2ull * cn[k] + (unsigned long long)(i & 1);
                 child(cn, has);
             } else {
+                // a packed frontier's next word is loaded before this node's
+                // children are evaluated (one register pair in flight)
+                bool has = tid < nS;
+                unsigned long long w = has && pk_cur ? cur[tid] : 0ull;
                 for (int64_t b0 = 0; b0 < nS; b0 += BLOCK) {
-                    const int64_t i = b0 + tid;
-                    const bool has = i < nS;
+                    const int64_t inext = b0 + BLOCK + tid;
+                    const bool hasn = inext < nS;
+                    const unsigned long long wn = hasn && pk_cur ? cur[inext] : 0ull;
                     unsigned long long pn[3];
-                    node(i, has, pn);
+                    if (pk_cur) {
+                        pn[0] = w & 0x1fffffull; pn[1] = (w >> 21) & 0x1fffffull; pn[2] = (w >> 42) & 0x1fffffull;
+                    } else {
+                        node(b0 + tid, has, pn);
+                    }
                     children(pn, has);
+                    w = wn;
+                    has = hasn;
                 }
             }
             int wcnt = 0;
@@ -1325,15 +1445,16 @@ __global__ __launch_bounds__(BLOCK) void heavy_kernel(
             pk_cur = pk_nxt;
         }
         __syncthreads();
-        if (state == 3 && resume) {
+        if (state == 3 && cold()->resume) {
             // save the level's frontier so that the next round resumes the pair from it
             const int64_t words = pk_cur ? nS : 3 * nS;
             if (tid == 0) {
-                const unsigned long long o = atomicAdd(node_ctr, (unsigned long long)words);
-                s_save = (int64_t)(o + words) <= hnode_cap ? o : ~0ull;
+                const unsigned long long o = atomicAdd(cold()->node_ctr, (unsigned long long)words);
+                s_save = (int64_t)(o + words) <= cold()->hnode_cap ? o : ~0ull;
             }
             __syncthreads();
             const unsigned long long o = s_save;
+            unsigned long long *hnodes = cold()->hnodes;
             if (o != ~0ull) {
                 if (pk_cur) {
                     for (int64_t i = tid; i < nS; i += BLOCK) hnodes[o + i] = cur[i];
@@ -1364,20 +1485,21 @@ __global__ __launch_bounds__(BLOCK) void heavy_kernel(
                     e.n_enq = 0;
                     e.node_off = -1;
                 }
-                heavy[slot] = e;
+                cold()->heavy[slot] = e;
             }
         }
         if (tid == 0) {
             if (state == 3) {
-                const unsigned o = atomicAdd(ovf_count, 1u);
-                ovf_list[o] = slot;
-                atomicOr(flags, FLAG_HEAVY_OVERFLOW);
+                const unsigned o = atomicAdd(cold()->ovf_count, 1u);
+                cold()->ovf_list[o] = slot;
+                atomicOr(cold()->flags, FLAG_HEAVY_OVERFLOW);
             } else {
                 const bool capped = state == 2;
                 const bool hv = (tstar < __builtin_huge_val()) || capped;
                 const double tv = capped ? tcap : tstar;
-                hit[p] = (uint8_t)hv;
-                toi[p] = tv;
+                cold()->hit[p] = (uint8_t)hv;
+                cold()->toi[p] = tv;
+                long long *n_enq_out = cold()->n_enq_out;
                 if (n_enq_out) n_enq_out[p] = nenq;
                 if (hv && toi_min)
                     atomicMin((unsigned long long *)toi_min, (unsigned long long)__double_as_longlong(tv));
@@ -1621,9 +1743,9 @@ void heavy_variant(int block, int nslots, unsigned int lo, unsigned int hi, cons
 {
     unsigned long long *node_ctr = (unsigned long long *)&B.counters[10];
 #define CCD_HEAVY_ARGS                                                                                             \
-    V0, V1, B.ids4, B.eps, B.m, pc, delta, max_iter, hit, toi, n_enq, B.heavy, B.hnodes, B.hnode_cap, node_ctr,  \
-        resume, list, count, next, ovf, ovf_count, scratch, cap, B.flags, use_lds, base, lo, hi, B.toi_min,   \
-        B.mode.global, B.mode.no_zero
+    HeavyArgs{V0, V1, B.ids4, B.eps, B.m, pc, delta, max_iter, hit, toi, n_enq, B.heavy, B.hnodes, B.hnode_cap,   \
+              node_ctr, resume, list, count, next, ovf, ovf_count, scratch, cap, B.flags, use_lds, base, lo, hi,   \
+              B.toi_min, B.mode.global, B.mode.no_zero}
     if (block == 1024)
         heavy_kernel<1024><<<(unsigned)nslots, 1024, 0, s>>>(CCD_HEAVY_ARGS);
     else if (block == 64)

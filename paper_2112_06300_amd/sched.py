@@ -66,8 +66,12 @@ def normalization(feat):
     return torch.cat([mean, istd]).to(torch.float32).contiguous()
 
 
-def train(ctx, feat, label, steps=1500, batch=16384, lr=3e-3, seed=0, log_every=0):
-    """Adam on the mean squared error, on the GPU; returns (params, norm, history) as device tensors."""
+def train(ctx, feat, label, steps=1500, batch=16384, lr=3e-3, seed=0, log_every=0, heavy_frac=0.0,
+          heavy_label=10.0):
+    """Adam on the mean squared error, on the GPU; returns (params, norm, history) as device tensors.
+
+    heavy_frac: the share of every minibatch drawn from the pairs whose label is at least heavy_label (the
+    few costly pairs the schedule must find among millions of cheap ones), the rest uniformly."""
     import torch
     n = feat.shape[0]
     norm = normalization(feat)
@@ -78,9 +82,13 @@ def train(ctx, feat, label, steps=1500, batch=16384, lr=3e-3, seed=0, log_every=
     loss = torch.zeros(1, dtype=torch.float32, device="cuda")
     g = torch.Generator(device="cuda")
     g.manual_seed(seed)
+    heavy = torch.nonzero(label >= heavy_label).flatten() if heavy_frac > 0 else None
+    nh = int(min(batch, n) * heavy_frac) if heavy is not None and heavy.numel() > 0 else 0
     hist = []
     for step in range(1, steps + 1):
-        idx = torch.randint(0, n, (min(batch, n),), device="cuda", generator=g)
+        idx = torch.randint(0, n, (min(batch, n) - nh,), device="cuda", generator=g)
+        if nh:
+            idx = torch.cat([idx, heavy[torch.randint(0, heavy.numel(), (nh,), device="cuda", generator=g)]])
         fb = feat.index_select(0, idx).contiguous()
         lb = label.index_select(0, idx).contiguous()
         ctx.mlp_grad(params, norm, fb, lb, grad=grad, loss=loss)
@@ -130,6 +138,10 @@ def main():
     ap.add_argument("--steps", type=int, default=1500)
     ap.add_argument("--batch", type=int, default=16384)
     ap.add_argument("--lr", type=float, default=3e-3)
+    ap.add_argument("--heavy-frac", type=float, default=0.0,
+                    help="share of each minibatch drawn from pairs with log2(1 + n_enq) >= --heavy-label")
+    ap.add_argument("--heavy-label", type=float, default=10.0)
+    ap.add_argument("--top-k", type=int, default=20000, help="report the recall of the k costliest eval pairs")
     args = ap.parse_args()
     import torch
     import scenes
@@ -154,7 +166,8 @@ def main():
     feat = torch.cat(feats).contiguous()
     label = torch.cat(labels).contiguous()
     t1 = time.perf_counter()
-    params, norm, hist = train(ctx, feat, label, steps=args.steps, batch=args.batch, lr=args.lr, log_every=100)
+    params, norm, hist = train(ctx, feat, label, steps=args.steps, batch=args.batch, lr=args.lr, log_every=100,
+                               heavy_frac=args.heavy_frac, heavy_label=args.heavy_label)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     for step, l in hist:
@@ -163,11 +176,17 @@ def main():
     pred = ctx.mlp_predict(params, norm, fe)
     rho = spearman(pred.cpu().numpy(), le.cpu().numpy())
     mse = float(((pred - le) ** 2).mean().item())
+    # how many of the k costliest pairs the network ranks among its k costliest
+    k = min(args.top_k, fe.shape[0])
+    top_true = set(torch.topk(le, k).indices.cpu().numpy().tolist())
+    top_pred = set(torch.topk(pred, k).indices.cpu().numpy().tolist())
+    recall = len(top_true & top_pred) / max(1, k)
     name = f"perturbed_torus gadgets={TORUS_GADGETS}" if torus else f"cloth_on_sphere n={args.cloth_n}"
     meta = {"train": f"{name} seeds {seeds}", "pairs": int(feat.shape[0]),
             "steps": args.steps, "batch": args.batch, "lr": args.lr, "label": "log2(1 + n_enq)",
             "eval": f"{name} seed {eval_seed}", "eval_pairs": int(fe.shape[0]),
-            "eval_mse": mse, "eval_spearman": rho, "train_seconds": t2 - t1, "log_seconds": t1 - t0}
+            "eval_mse": mse, "eval_spearman": rho, f"eval_top{k}_recall": recall, "heavy_frac": args.heavy_frac,
+            "heavy_label": args.heavy_label, "train_seconds": t2 - t1, "log_seconds": t1 - t0}
     save_model(out, params.cpu().numpy(), norm.cpu().numpy(), meta)
     print(json.dumps(meta), flush=True)
     ctx.close()

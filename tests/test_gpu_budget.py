@@ -70,10 +70,15 @@ def test_budget_cloth_splits_the_sweep(ctx):
 
 
 def test_budget_gadget_torus_splits_both(ctx):
-    """A 62,500-triangle perturbed torus with 300 near-degenerate gadgets: the capped gadget pairs' frontiers do
-    not fit beside a whole batch's narrow workspace."""
+    """A 62,500-triangle perturbed torus with 300 near-degenerate gadgets, with 8,192-interval wide-stage buffers:
+    the pair capacity leaves little room beside a batch's narrow workspace, and the capped gadget pairs' frontiers
+    do not fit it."""
     s = scenes.perturbed_torus(seed=7, n_major=250, n_minor=125, gadgets=300)
-    check(ctx, s, 96 * MB, want_narrow_split=True)
+    ctx.set_tuning({"heavy_cap_log2": 13})
+    try:
+        check(ctx, s, 96 * MB, want_narrow_split=True)
+    finally:
+        ctx.set_tuning(None)
 
 
 def test_budget_large_enough_is_one_batch(ctx):

@@ -161,6 +161,28 @@ def test_broad_rejects_bad_input(ctx):
     assert ei.value.status == ccd.CCD_ERR_NONFINITE
 
 
+@pytest.mark.parametrize("classes", [1, 2, 3, 4, 8])
+def test_broad_query_classes(ctx, classes):
+    """The sweep's queries grouped into extent classes before they are cut into tiles (tiles then walk
+    different candidate ranges): the pair set never changes.  Mixed extents (long slivers), a full-size
+    cloth, ragged tails, empty segments and one lone box."""
+    print(f"sweep_classes {classes}", flush=True)
+    ctx.set_tuning({"sweep_classes": classes})
+    try:
+        check_broad(ctx, scenes.sliding_slivers())
+        check_broad(ctx, scenes.cloth_on_sphere(n=96, sphere_subdivisions=3, seed=21))
+        check_broad(ctx, scenes.cloth_on_sphere(n=17, sphere_subdivisions=2, seed=117))
+        check_broad(ctx, scenes.tiny_random_scene(3, n_tris=67, extent=1.0, motion=0.5))
+        t = scenes.tiny_random_scene(2, n_tris=5)
+        for nv, E, F in [(0, np.zeros((0, 2), np.int32), np.zeros((0, 3), np.int32)),
+                         (1, np.zeros((0, 2), np.int32), np.zeros((0, 3), np.int32)),
+                         (t.nv, t.E, np.zeros((0, 3), np.int32)),
+                         (t.nv, np.zeros((0, 2), np.int32), t.F)]:
+            check_broad(ctx, scenes.Scene("partial", t.V0[:nv], t.V1[:nv], E, F))
+    finally:
+        ctx.set_tuning(None)
+
+
 # --------------------------------------------------------------------------- narrow
 def test_narrow_two_spheres_candidates(ctx):
     s = scenes.two_spheres()
