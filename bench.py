@@ -18,7 +18,8 @@ alternated, median and spread.  Beside them: the narrow phase on the same
 pairs with a random and a true-cost order placed the way the learned schedule
 places pairs (the references the learned one is judged by), Alg. 3's single
 shared t* (only the earliest time), and the other workloads (cloth on sphere,
-10M sampled torus pairs, the 64-scene batch, all pairs of two spheres).
+10M sampled torus pairs, the 64-scene batch of large and of small scenes, all pairs of two
+spheres).
 
 Prints one JSON line.
 """
@@ -318,12 +319,13 @@ def extra_torus_10m(ctx, steps):
             "learned_over_plain": res["learned"]["pairs_per_s"] / res["plain"]["pairs_per_s"]}
 
 
-def extra_batch64(ctx, steps):
-    """The 64-scene batch (1e3..2e5 triangles each) through one pass: captured graph vs eager launches."""
+def extra_batch64(ctx, steps, small=False):
+    """The 64-scene batch (1e3..2e5 triangles each; small: 1e2..2e3) through one pass: captured graph vs
+    eager launches."""
     import numpy as np
     import torch
     import scenes
-    scs = scenes.scene_batch()
+    scs = scenes.scene_batch(t_min=1e2, t_max=2e3) if small else scenes.scene_batch()
     V0, V1, E, F, vo, eo, fo = scenes.concat_scenes(scs)
     nb = int(vo[-1] + eo[-1] + fo[-1])
     b = ccd_mod().Batch(ctx, vo, eo, fo, 3 * nb, 6 * nb)
@@ -440,6 +442,8 @@ def main():
         extras["torus_10M_pairs"] = extra_torus_10m(ctx, steps=5)
         log("64-scene batch")
         extras["batch_64_scenes"] = extra_batch64(ctx, steps=5)
+        log("64 small scenes")
+        extras["batch_64_small_scenes"] = extra_batch64(ctx, steps=50, small=True)
         log("two spheres, all pairs")
         extras["two_spheres_all_pairs"] = extra_two_spheres_all_pairs(ctx, steps=5)
 

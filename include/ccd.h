@@ -19,6 +19,11 @@
  *     row-major.  Sizes are int64.
  *   - `stream` is a hipStream_t (NULL = the default stream).  Work is enqueued
  *     on it; calls that return counts or status synchronize that stream.
+ *     The calls on one context run in call order whatever their streams (each
+ *     call's stream first waits for the end of the previous call's work), so
+ *     the context's scratch memory, which grows by allocations ordered on the
+ *     call's stream, is never in use by an earlier call.  A stream under graph
+ *     capture is left out of that ordering.
  *   - Every call returns a ccd_status and never aborts or throws across the
  *     ABI; ccd_last_error() gives a message for the last failing call on the
  *     calling thread.

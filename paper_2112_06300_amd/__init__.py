@@ -103,6 +103,10 @@ def load_library(path=LIB_PATH):
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with paper_2112_06300_amd/build.py "
                            "(the CCD path has no CPU fallback)")
+    # PyTorch ships its own HIP runtime under the same soname as the system's: whichever is loaded first
+    # serves the whole process.  Loading torch first binds the library to the runtime its tensors and
+    # streams belong to (loaded the other way round, torch finds no GPU).
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     P = ctypes.c_void_p
     i64 = ctypes.c_int64

@@ -113,6 +113,13 @@ struct ccd_context {
     hipStream_t side = nullptr;  // second stream: the learned schedule's early wide stage
     char *noalloc = nullptr;       // this device's allocation-free workspace (device address)
     int64_t noalloc_max_pairs = 0; // pairs its per-pair part holds
+    // Calls run in call order whatever their streams: the end of each call's
+    // work is recorded in `tail`, and the next call's stream waits for it
+    // first.  So no earlier call still uses a scratch pool when a later call
+    // frees and reallocates it on its own stream (stream-ordered allocation).
+    hipEvent_t tail = nullptr;
+    bool tail_valid = false;
+    hipStream_t cs = nullptr;      // the current call's stream
 };
 
 namespace {
@@ -140,22 +147,60 @@ int pool_blocks(const ccd_context *c)
     return per_cu * c->cus;
 }
 
-ccd_status ensure(Pool &p, size_t need)
+// One call's place in its context's call order (see ccd_context::tail): the
+// stream waits for the previous call's end on entry, and this call's end is
+// recorded on exit, on every return path.
+// A stream under graph capture takes part in no such ordering (the caller's
+// graph orders its own work).
+struct CallScope {
+    ccd_context *c;
+    hipStream_t s;
+    bool capturing = false;
+    CallScope(ccd_context *ctx, void *stream) : c(ctx), s((hipStream_t)stream)
+    {
+        if (!c) return;
+        (void)hipSetDevice(c->device);
+        hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+        capturing = hipStreamIsCapturing(s, &cap) == hipSuccess && cap != hipStreamCaptureStatusNone;
+        if (c->tail_valid && !capturing) (void)hipStreamWaitEvent(s, c->tail, 0);
+        c->cs = s;
+    }
+    ~CallScope()
+    {
+        if (!c || !c->tail || capturing) return;
+        (void)hipSetDevice(c->device);
+        c->tail_valid = hipEventRecord(c->tail, s) == hipSuccess;
+    }
+};
+
+// A scratch pool of at least `need` bytes, grown (25 % headroom) by a free and
+// an allocation ordered on stream s: the old block is released only after the
+// work enqueued before it on s, and every earlier call's work is ordered before
+// s by the call order, so growing never waits for the device.
+ccd_status ensure(Pool &p, size_t need, hipStream_t s)
 {
     if (p.bytes >= need) return CCD_OK;
     if (p.base) {
-        (void)hipFree(p.base);
+        (void)hipFreeAsync(p.base, s);
         p.base = nullptr;
         p.bytes = 0;
     }
     const size_t want = need + need / 4;
-    if (hipMalloc((void **)&p.base, want) != hipSuccess) {
+    if (hipMallocAsync((void **)&p.base, want, s) != hipSuccess) {
         (void)hipGetLastError();
         p.base = nullptr;
         return fail(CCD_ERR_OOM, "could not allocate %zu bytes of device scratch", want);
     }
     p.bytes = want;
     return CCD_OK;
+}
+
+// Release a pool after the work enqueued on s.
+void release(Pool &p, hipStream_t s)
+{
+    if (p.base) (void)hipFreeAsync(p.base, s);
+    p.base = nullptr;
+    p.bytes = 0;
 }
 
 // Broad-phase workspace of nb boxes in S scenes.  Called once with a null
@@ -246,7 +291,7 @@ ccd_status broad_enqueue(ccd_context *c, const double *V0, const double *V1, int
     const int64_t nbl = sort_blocks(nb);
     Carver measure(nullptr);
     broad_carve(measure, nb, 1, nbl, B);
-    ccd_status st = ensure(c->broad, measure.bytes());
+    ccd_status st = ensure(c->broad, measure.bytes(), s);
     if (st != CCD_OK) return st;
     Carver cv(c->broad.base);
     broad_carve(cv, nb, 1, nbl, B);
@@ -352,6 +397,11 @@ ccd_status ccd_create(int device, ccd_context **out)
             return fail(CCD_ERR_DEVICE, "hipEventCreate failed");
         }
     }
+    if (hipEventCreateWithFlags(&c->tail, hipEventDisableTiming) != hipSuccess) {
+        c->tail = nullptr;
+        ccd_destroy(c);
+        return fail(CCD_ERR_DEVICE, "hipEventCreate failed");
+    }
     *out = c;
     g_err.clear();
     return CCD_OK;
@@ -361,10 +411,13 @@ void ccd_destroy(ccd_context *c)
 {
     if (!c) return;
     (void)hipSetDevice(c->device);
-    for (Pool *p : {&c->broad, &c->narrow, &c->scratch, &c->sched, &c->aux, &c->budget})
-        if (p->base) (void)hipFree(p->base);
+    // the pools are released after the last call's work
+    if (c->tail_valid) (void)hipStreamWaitEvent(nullptr, c->tail, 0);
+    for (Pool *p : {&c->broad, &c->narrow, &c->scratch, &c->sched, &c->aux, &c->budget}) release(*p, nullptr);
+    (void)hipStreamSynchronize(nullptr);
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
+    if (c->tail) (void)hipEventDestroy(c->tail);
     if (c->host) (void)hipHostFree(c->host);
     if (c->side) (void)hipStreamDestroy(c->side);
     delete c;
@@ -398,6 +451,7 @@ ccd_status ccd_broad(ccd_context *c, const double *V0, const double *V1, int64_t
                      const int32_t *F, int64_t nf, int32_t *vf, int64_t vf_cap, int64_t *n_vf, int32_t *ee,
                      int64_t ee_cap, int64_t *n_ee, void *stream)
 {
+    CallScope scope(c, stream);
     BroadBuffers B;
     hipStream_t s = (hipStream_t)stream;
     ccd_status st = broad_enqueue(c, V0, V1, nv, E, ne, F, nf, vf, vf_cap, n_vf, ee, ee_cap, n_ee, B, s);
@@ -432,7 +486,7 @@ ccd_status narrow_setup(ccd_context *c, const double *V0, const double *V1, int6
     HIP_TRY(hipSetDevice(c->device));
     Carver measure(nullptr);
     narrow_carve(measure, n, B);
-    ccd_status st = ensure(c->narrow, measure.bytes());
+    ccd_status st = ensure(c->narrow, measure.bytes(), c->cs);
     if (st != CCD_OK) return st;
     Carver cv(c->narrow.base);
     narrow_carve(cv, n, B);
@@ -454,7 +508,7 @@ ccd_status sched_setup(ccd_context *c, int64_t n, SchedBuffers &S)
     const size_t words = (m + 31) / 32;
     ccd_status st = ensure(c->sched, aligned_total({m * kNumFeatures * 4, m * 4, m * 4, words * 4,
                                                    (size_t)kSchedScratch * 4, 4, (size_t)256 * kCostMaxBlocks * 4,
-                                                   (size_t)kMlpPackedBytes}));
+                                                   (size_t)kMlpPackedBytes}), c->cs);
     if (st != CCD_OK) return st;
     Carver cv(c->sched.base);
     S.feat = cv.take<float>(m * kNumFeatures);
@@ -567,7 +621,7 @@ ccd_status narrow_enqueue(ccd_context *c, const double *V0, const double *V1, in
                         c->tune.heavy_cap_log2);
         B.scratch = call.fixed_frontier;
     } else {
-        ccd_status st = ensure(c->scratch, (size_t)(nslots + early_slots) * 6 * cap * 8);
+        ccd_status st = ensure(c->scratch, (size_t)(nslots + early_slots) * 6 * cap * 8, c->cs);
         if (st != CCD_OK) return st;
         B.scratch = (unsigned long long *)c->scratch.base;
     }
@@ -669,7 +723,7 @@ ccd_status rerun_overflowed(ccd_context *c, NarrowBuffers B, Pool *pool, unsigne
             return fail(CCD_ERR_OOM, "interval frontier of %u pairs exceeds device memory", overflowed);
         const int nslots = (int)std::min<size_t>(slots_wanted, budget / per_slot);
         if (pool) {
-            ccd_status st = ensure(*pool, (size_t)nslots * per_slot);
+            ccd_status st = ensure(*pool, (size_t)nslots * per_slot, s);
             if (st != CCD_OK) return st;
             B.scratch = (unsigned long long *)pool->base;
         } else {
@@ -857,6 +911,7 @@ ccd_status ccd_narrow(ccd_context *c, const double *V0, const double *V1, int64_
                       int64_t n_ee, double delta, int64_t max_iter, uint8_t *hit, double *toi, double *toi_min,
                       int64_t *n_enq, void *stream)
 {
+    CallScope scope(c, stream);
     return narrow_impl(c, V0, V1, nv, E, ne, F, nf, vf, n_vf, ee, n_ee, delta, max_iter, hit, toi, toi_min, n_enq,
                        nullptr, nullptr, stream);
 }
@@ -866,6 +921,7 @@ ccd_status ccd_narrow_sched(ccd_context *c, const double *V0, const double *V1, 
                             const int32_t *ee, int64_t n_ee, double delta, int64_t max_iter, uint8_t *hit,
                             double *toi, double *toi_min, int64_t *n_enq, const ccd_schedule *sched, void *stream)
 {
+    CallScope scope(c, stream);
     return narrow_impl(c, V0, V1, nv, E, ne, F, nf, vf, n_vf, ee, n_ee, delta, max_iter, hit, toi, toi_min, n_enq,
                        sched, nullptr, stream);
 }
@@ -875,6 +931,7 @@ ccd_status ccd_narrow_ex(ccd_context *c, const double *V0, const double *V1, int
                          int64_t n_ee, double delta, int64_t max_iter, uint8_t *hit, double *toi, double *toi_min,
                          int64_t *n_enq, const ccd_schedule *sched, const ccd_narrow_options *opts, void *stream)
 {
+    CallScope scope(c, stream);
     return narrow_impl(c, V0, V1, nv, E, ne, F, nf, vf, n_vf, ee, n_ee, delta, max_iter, hit, toi, toi_min, n_enq,
                        sched, opts, stream);
 }
@@ -884,6 +941,7 @@ ccd_status ccd_detect(ccd_context *c, const double *V0, const double *V1, int64_
                       int64_t ee_cap, int64_t *n_ee, double delta, int64_t max_iter, uint8_t *hit, double *toi,
                       double *toi_min, int64_t *n_enq, const ccd_schedule *sched, void *stream)
 {
+    CallScope scope(c, stream);
     return detect_impl(c, V0, V1, nv, E, ne, F, nf, vf, vf_cap, n_vf, ee, ee_cap, n_ee, delta, max_iter, hit, toi,
                        toi_min, n_enq, sched, nullptr, stream);
 }
@@ -894,6 +952,7 @@ ccd_status ccd_detect_ex(ccd_context *c, const double *V0, const double *V1, int
                          double *toi_min, int64_t *n_enq, const ccd_schedule *sched, const ccd_narrow_options *opts,
                          void *stream)
 {
+    CallScope scope(c, stream);
     return detect_impl(c, V0, V1, nv, E, ne, F, nf, vf, vf_cap, n_vf, ee, ee_cap, n_ee, delta, max_iter, hit, toi,
                        toi_min, n_enq, sched, opts, stream);
 }
@@ -902,6 +961,7 @@ ccd_status ccd_initial_distance(ccd_context *c, const double *V0, int64_t nv, co
                                 const int32_t *F, int64_t nf, const int32_t *vf, int64_t n_vf, const int32_t *ee,
                                 int64_t n_ee, double *d0, void *stream)
 {
+    CallScope scope(c, stream);
     if (!c) return fail(CCD_ERR_INVALID_ARG, "NULL context");
     if (nv < 0 || ne < 0 || nf < 0 || n_vf < 0 || n_ee < 0) return fail(CCD_ERR_INVALID_ARG, "negative size");
     const int64_t n = n_vf + n_ee;
@@ -909,7 +969,7 @@ ccd_status ccd_initial_distance(ccd_context *c, const double *V0, int64_t nv, co
     if ((nv && !V0) || (ne && !E) || (nf && !F) || (n_vf && !vf) || (n_ee && !ee) || (n && !d0))
         return fail(CCD_ERR_INVALID_ARG, "NULL pointer with nonzero size");
     HIP_TRY(hipSetDevice(c->device));
-    ccd_status st = ensure(c->aux, 256);
+    ccd_status st = ensure(c->aux, 256, c->cs);
     if (st != CCD_OK) return st;
     uint32_t *flags = (uint32_t *)c->aux.base;
     hipStream_t s = (hipStream_t)stream;
@@ -929,6 +989,7 @@ ccd_status ccd_narrow_noalloc(ccd_context *c, const double *V0, const double *V1
                               const int32_t *ee, int64_t n_ee, double delta, int64_t max_iter, uint8_t *hit,
                               double *toi, double *toi_min, int64_t *n_enq, void *stream)
 {
+    CallScope scope(c, stream);
     if (!c || !toi_min) return fail(CCD_ERR_INVALID_ARG, "NULL context or toi_min");
     if (max_iter < 1) return fail(CCD_ERR_INVALID_ARG, "max_iter must be >= 1");
     if (nv < 0 || ne < 0 || nf < 0 || n_vf < 0 || n_ee < 0) return fail(CCD_ERR_INVALID_ARG, "negative size");
@@ -1067,6 +1128,7 @@ ccd_status ccd_detect_budget(ccd_context *c, const double *V0, const double *V1,
                              int64_t max_iter, const ccd_narrow_options *opts, double *toi_min,
                              ccd_budget_result *out, void *stream)
 {
+    CallScope scope(c, stream);
     if (!c || !toi_min || !out) return fail(CCD_ERR_INVALID_ARG, "NULL context, toi_min or out");
     if (budget_bytes <= 0) return fail(CCD_ERR_INVALID_ARG, "budget_bytes must be > 0");
     if (max_iter < 1) return fail(CCD_ERR_INVALID_ARG, "max_iter must be >= 1");
@@ -1100,7 +1162,7 @@ ccd_status ccd_detect_budget(ccd_context *c, const double *V0, const double *V1,
         else hi = mid - 1;
     }
     const int64_t S = lo;
-    st = ensure(c->budget, budget);
+    st = ensure(c->budget, budget, c->cs);
     if (st != CCD_OK) return st;
     Carver cv(c->budget.base);
     broad_carve(cv, nb, 1, nbl, B);
@@ -1182,6 +1244,7 @@ ccd_status ccd_toi_step(ccd_context *c, const double *V0, const double *V1, int6
                         int64_t ee_cap, int64_t *n_ee, double delta, int64_t max_iter, double ms_factor, double scale,
                         double *toi, int32_t *rerun, void *stream)
 {
+    CallScope scope(c, stream);
     if (!c || !toi) return fail(CCD_ERR_INVALID_ARG, "NULL context or toi");
     if (!(ms_factor >= 0.0) || !std::isfinite(ms_factor)) return fail(CCD_ERR_INVALID_ARG, "ms_factor must be >= 0");
     if (!(scale > 0.0 && scale <= 1.0)) return fail(CCD_ERR_INVALID_ARG, "scale must lie in (0, 1]");
@@ -1189,7 +1252,7 @@ ccd_status ccd_toi_step(ccd_context *c, const double *V0, const double *V1, int6
     HIP_TRY(hipSetDevice(c->device));
     // per-pair outputs the narrow phase writes (unspecified with a shared t*) and the earliest time
     const size_t m = (size_t)std::max<int64_t>(vf_cap + ee_cap, 1);
-    ccd_status st = ensure(c->aux, aligned_total({8, m * 8, m}));
+    ccd_status st = ensure(c->aux, aligned_total({8, m * 8, m}), c->cs);
     if (st != CCD_OK) return st;
     Carver cv(c->aux.base);
     double *tmin = cv.take<double>(1);
@@ -1224,6 +1287,7 @@ ccd_status ccd_features(ccd_context *c, const double *V0, const double *V1, int6
                         const int32_t *F, int64_t nf, const int32_t *vf, int64_t n_vf, const int32_t *ee,
                         int64_t n_ee, double delta, float *feat, void *stream)
 {
+    CallScope scope(c, stream);
     NarrowBuffers B;
     ccd_status st = narrow_setup(c, V0, V1, nv, E, ne, F, nf, vf, n_vf, ee, n_ee, delta, B);
     if (st != CCD_OK) return st;
@@ -1246,6 +1310,7 @@ ccd_status ccd_features(ccd_context *c, const double *V0, const double *V1, int6
 ccd_status ccd_mlp_predict(ccd_context *c, const float *params, const float *norm, const float *feat, int64_t n,
                            float *out, void *stream)
 {
+    CallScope scope(c, stream);
     ccd_status st = check_mlp_args(c, params, norm, feat, n);
     if (st != CCD_OK) return st;
     if (n && !out) return fail(CCD_ERR_INVALID_ARG, "NULL out");
@@ -1258,6 +1323,7 @@ ccd_status ccd_mlp_predict(ccd_context *c, const float *params, const float *nor
 ccd_status ccd_mlp_grad(ccd_context *c, const float *params, const float *norm, const float *feat, const float *label,
                         int64_t n, float *grad, float *loss_sse, void *stream)
 {
+    CallScope scope(c, stream);
     ccd_status st = check_mlp_args(c, params, norm, feat, n);
     if (st != CCD_OK) return st;
     if (!grad || !loss_sse || (n && !label)) return fail(CCD_ERR_INVALID_ARG, "NULL pointer");
@@ -1270,6 +1336,7 @@ ccd_status ccd_mlp_grad(ccd_context *c, const float *params, const float *norm, 
 ccd_status ccd_adam_step(ccd_context *c, float *params, const float *grad, float *m, float *v, int64_t step, float lr,
                          float beta1, float beta2, float eps, void *stream)
 {
+    CallScope scope(c, stream);
     if (!c) return fail(CCD_ERR_INVALID_ARG, "NULL context");
     if (!params || !grad || !m || !v) return fail(CCD_ERR_INVALID_ARG, "NULL pointer");
     if (step < 1) return fail(CCD_ERR_INVALID_ARG, "step counts from 1");
@@ -1340,7 +1407,7 @@ ccd_status batch_frontier(ccd_batch *b)
     const int64_t cap = (int64_t)1 << t.heavy_cap_log2;
     if (b->heavy_slots == t.heavy_slots && b->heavy_cap == cap) return CCD_OK;
     drop_graph(b);
-    ccd_status st = ensure(b->frontier, (size_t)t.heavy_slots * 6 * (size_t)cap * 8);
+    ccd_status st = ensure(b->frontier, (size_t)t.heavy_slots * 6 * (size_t)cap * 8, b->cs);
     if (st != CCD_OK) return st;
     b->heavy_slots = t.heavy_slots;
     b->heavy_cap = cap;
@@ -1439,7 +1506,7 @@ ccd_status batch_pass(ccd_batch *b, const BatchArgs &a, bool use_graph, int64_t 
         Pool big;
         st = rerun_overflowed(c, b->N, &big, overflowed, b->heavy_cap, a.V0, a.V1, pc, a.delta, a.max_iter, a.hit,
                               a.toi, a.n_enq, s, nullptr);
-        if (big.base) (void)hipFree(big.base);
+        release(big, s);
         if (st != CCD_OK) return st;
         launch_scene_min(a.toi, pc, a.vf, a.ee, b->off, b->off + (b->S + 1), b->S, a.toi_min, s);
         HIP_TRY(hipGetLastError());
@@ -1536,9 +1603,17 @@ ccd_status ccd_batch_create(ccd_context *c, int64_t n_scenes, const int64_t *v_o
     (void)offp;
     broad_carve(measure, nv + ne + nf, n_scenes, b->nbl, b->B);
     narrow_carve(measure, vf_cap + ee_cap, b->N);
-    ccd_status st = ensure(b->mem, measure.bytes());
+    if (hipStreamCreateWithFlags(&b->cs, hipStreamNonBlocking) != hipSuccess || hipEventCreate(&b->ev_in) != hipSuccess ||
+        hipEventCreate(&b->ev_out) != hipSuccess || hipEventCreate(&b->t0) != hipSuccess ||
+        hipEventCreate(&b->t1) != hipSuccess) {
+        ccd_batch_destroy(b);
+        return fail(CCD_ERR_DEVICE, "could not create the batch stream or events");
+    }
+    // the batch's buffers, allocated on its stream and complete before the upload below
+    ccd_status st = ensure(b->mem, measure.bytes(), b->cs);
+    if (st == CCD_OK && hipStreamSynchronize(b->cs) != hipSuccess) st = fail(CCD_ERR_DEVICE, "batch allocation failed");
     if (st != CCD_OK) {
-        delete b;
+        ccd_batch_destroy(b);
         return st;
     }
     Carver cv(b->mem.base);
@@ -1546,12 +1621,6 @@ ccd_status ccd_batch_create(ccd_context *c, int64_t n_scenes, const int64_t *v_o
     broad_carve(cv, nv + ne + nf, n_scenes, b->nbl, b->B);
     narrow_carve(cv, vf_cap + ee_cap, b->N);
     b->B.off = b->off;
-    if (hipStreamCreateWithFlags(&b->cs, hipStreamNonBlocking) != hipSuccess || hipEventCreate(&b->ev_in) != hipSuccess ||
-        hipEventCreate(&b->ev_out) != hipSuccess || hipEventCreate(&b->t0) != hipSuccess ||
-        hipEventCreate(&b->t1) != hipSuccess) {
-        ccd_batch_destroy(b);
-        return fail(CCD_ERR_DEVICE, "could not create the batch stream or events");
-    }
     for (int g = 0; g < 3; g++) {
         if (hipMemcpy(b->off + g * (n_scenes + 1), offs[g], (size_t)(n_scenes + 1) * 8, hipMemcpyHostToDevice) !=
             hipSuccess) {
@@ -1570,8 +1639,8 @@ void ccd_batch_destroy(ccd_batch *b)
     (void)hipSetDevice(b->ctx->device);
     if (b->cs) (void)hipStreamSynchronize(b->cs);
     drop_graph(b);
-    for (Pool *p : {&b->mem, &b->frontier})
-        if (p->base) (void)hipFree(p->base);
+    for (Pool *p : {&b->mem, &b->frontier}) release(*p, b->cs);
+    if (b->cs) (void)hipStreamSynchronize(b->cs);
     for (hipEvent_t e : {b->ev_in, b->ev_out, b->t0, b->t1})
         if (e) (void)hipEventDestroy(e);
     if (b->cs) (void)hipStreamDestroy(b->cs);
@@ -1582,6 +1651,7 @@ ccd_status ccd_batch_run(ccd_batch *b, const double *V0, const double *V1, const
                          double delta, int64_t max_iter, int32_t *vf, int32_t *ee, int64_t *n_vf, int64_t *n_ee,
                          uint8_t *hit, double *toi, double *toi_min, int64_t *n_enq, int use_graph, void *stream)
 {
+    CallScope scope(b ? b->ctx : nullptr, stream);
     const BatchArgs a{V0, V1, E, F, delta, (long long)max_iter, vf, ee, hit, toi, toi_min, (long long *)n_enq};
     ccd_status st = check_batch_args(b, a, n_vf, n_ee);
     if (st != CCD_OK) return st;
@@ -1603,6 +1673,7 @@ ccd_status ccd_batch_autotune(ccd_batch *b, const double *V0, const double *V1, 
                               double delta, int64_t max_iter, int32_t *vf, int32_t *ee, uint8_t *hit, double *toi,
                               double *toi_min, const char *cache_path, ccd_tuning *chosen, void *stream)
 {
+    CallScope scope(b ? b->ctx : nullptr, stream);
     int64_t n_vf = 0, n_ee = 0;
     const BatchArgs a{V0, V1, E, F, delta, (long long)max_iter, vf, ee, hit, toi, toi_min, nullptr};
     ccd_status st = check_batch_args(b, a, &n_vf, &n_ee);

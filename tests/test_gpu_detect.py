@@ -115,3 +115,32 @@ def test_detect_rejects_order_schedule(ctx):
     perm = torch.arange(8192, dtype=torch.int32, device="cuda")
     with pytest.raises(ccd.CCDError, match="INVALID_ARG"):
         ctx.detect_into(V0, V1, E, F, vf, ee, hit, toi, tmin, schedule=("order", perm))
+
+
+def test_context_created_before_torch_touches_the_gpu():
+    """A fresh process that creates a context before torch has used the GPU, then hands torch tensors to it:
+    the library and torch share one HIP runtime, so both see the GPU and the call matches the oracle."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = (
+        "import numpy as np\n"
+        "import paper_2112_06300_amd as ccd\n"
+        "import oracle, scenes\n"
+        "c = ccd.Context(0)\n"
+        "import torch\n"
+        "s = scenes.tiny_random_scene(3, n_tris=40, extent=1.0, motion=0.5)\n"
+        "d = lambda x, t: torch.as_tensor(np.ascontiguousarray(x)).to('cuda', t)\n"
+        "vf, ee = c.broad(d(s.V0, torch.float64), d(s.V1, torch.float64), d(s.E, torch.int32), d(s.F, torch.int32))\n"
+        "canon = lambda p: p[np.lexsort((p[:, 1], p[:, 0]))] if len(p) else p\n"
+        "ovf, oee = oracle.broad(s.V0, s.V1, s.E, s.F)\n"
+        "assert np.array_equal(canon(vf.cpu().numpy()), ovf) and np.array_equal(canon(ee.cpu().numpy()), oee)\n"
+        "c.close()\n"
+        "print('ok', len(ovf), len(oee))\n")
+    env = dict(os.environ)
+    env["PYTHONPATH"] = root + os.pathsep + env.get("PYTHONPATH", "")
+    print("child: context before torch", flush=True)
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, env=env, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-2000:]
+    assert r.stdout.strip().splitlines()[-1].startswith("ok")

@@ -281,26 +281,33 @@ def test_training_on_gpu_learns_the_cost(ctx):
     assert rho > 0.5
 
 
-def test_learned_schedule_speeds_up_the_pool(ctx):
-    """The gain the schedule is for: on the benchmark's cloth scene (not one the shipped model was trained
-    on) the wave pool finishes sooner with the learned order than in index order, with identical outputs.
-    Median pool time (device events) over repeated calls; the measured ratio is about 0.9, the bound 0.97."""
+def test_learned_schedule_end_to_end_time(ctx):
+    """What the schedule costs and buys on the benchmark's cloth scene (not one the shipped model was trained
+    on), measured on the whole narrow call -- its prep with features, the network, the ordering and the early
+    wide stage included -- against index order, with identical outputs.  Median over repeated calls (device
+    events).  The pool alone finishes about 10 % sooner with the learned order, which the schedule's own
+    passes and the early wide stage use up: end to end the two are within noise here, so the test bounds the
+    learned call at 3 % over the plain one and reports both ratios."""
     s = scenes.cloth_on_sphere()
     V0, V1, E, F = scene_dev(s)
     vf, ee = ctx.broad(V0, V1, E, F)
     p, nm, _ = sched.load_model()
     learned = ccd.prepare_schedule(("learned", dev(p, torch.float32), dev(nm, torch.float32), ccd.HEAVY_THRESHOLD,
                                     ccd.MAX_HEAVY))
-    times, outs = {}, {}
-    for name, sc in (("plain", None), ("learned", learned)):
-        ms = []
-        for it in range(23):
+    narrow_ms, pool_ms, outs = {"plain": [], "learned": []}, {"plain": [], "learned": []}, {}
+    # alternated calls, so that clock drift affects both alike
+    for it in range(26):
+        for name, sc in (("plain", None), ("learned", learned)):
             out = ctx.narrow(V0, V1, E, F, vf, ee, DELTA, 10 ** 6, with_costs=True, schedule=sc)
             if it >= 3:
-                ms.append(ctx.stats()["narrow_pool_ms"])
-        times[name] = float(np.median(ms))
-        outs[name] = [o.cpu().numpy() for o in out]
-    print("median pool ms:", times, flush=True)
+                st = ctx.stats()
+                narrow_ms[name].append(st["narrow_ms"])
+                pool_ms[name].append(st["narrow_pool_ms"])
+            outs[name] = [o.cpu().numpy() for o in out]
+    med = {k: float(np.median(v)) for k, v in narrow_ms.items()}
+    pool = {k: float(np.median(v)) for k, v in pool_ms.items()}
+    print(f"median narrow ms {med}, learned/plain {med['learned'] / med['plain']:.3f}; "
+          f"pool ms {pool}, learned/plain {pool['learned'] / pool['plain']:.3f}", flush=True)
     for a, b in zip(outs["plain"], outs["learned"]):
         assert np.array_equal(a.view(np.uint8), b.view(np.uint8))
-    assert times["learned"] < 0.97 * times["plain"], times
+    assert med["learned"] < 1.03 * med["plain"], med

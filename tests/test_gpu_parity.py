@@ -267,6 +267,40 @@ def test_narrow_order_independent(ctx):
     assert np.array_equal(n2, n1[perm]) and m1 == m2
 
 
+def test_calls_on_two_streams_while_pools_grow():
+    """A fresh context called alternately on two streams with growing scenes, so that each call grows
+    scratch pools (freed and reallocated on its own stream) that the previous call on the other stream used:
+    every result equals the same call's on the default stream (calls of one context run in call order)."""
+    scs = [scenes.cloth_on_sphere(n=n, sphere_subdivisions=k, seed=50 + n) for n, k in ((9, 1), (33, 2), (65, 3),
+                                                                                     (129, 3))]
+    ref_ctx = ccd.Context(0)
+    refs = []
+    try:
+        for s in scs:
+            vf, ee = run_broad(ref_ctx, s)
+            hit, toi, tmin, nenq = run_narrow(ref_ctx, s, vf, ee)
+            refs.append((vf, ee, hit, toi.view(np.int64), tmin, nenq))
+    finally:
+        ref_ctx.close()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    c = ccd.Context(0)
+    try:
+        for i, (s, ref) in enumerate(zip(scs, refs)):
+            st = streams[i % 2]
+            vf, ee = run_broad(c, s, stream=st)
+            assert np.array_equal(vf, ref[0]) and np.array_equal(ee, ref[1])
+            hit, toi, tmin, nenq = c.narrow(dev(s.V0, torch.float64), dev(s.V1, torch.float64), dev(s.E, torch.int32),
+                                            dev(s.F, torch.int32), dev(vf, torch.int32), dev(ee, torch.int32),
+                                            DELTA, 10 ** 6, with_costs=True, stream=st)
+            st.synchronize()
+            assert np.array_equal(hit.cpu().numpy(), ref[2])
+            assert np.array_equal(toi.cpu().numpy().view(np.int64), ref[3])
+            assert float(tmin.cpu()[0]) == ref[4] or (np.isinf(ref[4]) and np.isinf(float(tmin.cpu()[0])))
+            assert np.array_equal(nenq.cpu().numpy(), ref[5])
+    finally:
+        c.close()
+
+
 def test_narrow_empty_and_errors(ctx):
     s = scenes.tiny_random_scene(2, n_tris=5)
     z = np.zeros((0, 2), np.int32)
