@@ -1108,9 +1108,12 @@ template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(BLOCK == 1024 ? 4 : 3, 8))) void heavy_kernel(
     const HeavyArgs args)
 {
-    // Frontier of the next level: in LDS when it surely fits (at most twice the
-    // current frontier), else in this workgroup's HBM buffers.
-    constexpr int kLds = 2 * BLOCK;
+    // Frontier of the next level: in LDS when the level after it surely takes
+    // one child per thread (at most BLOCK / 2 intervals: twice a frontier of at
+    // most BLOCK / 4), else in this workgroup's HBM buffers.  So the node loop
+    // of wider levels reads only HBM, and its one-node-ahead load is the only
+    // vector-memory load in flight when a node's word is waited for.
+    constexpr int kLds = BLOCK / 2;
     constexpr int kWaves = BLOCK / 64;
     __shared__ unsigned long long s_front[2][3 * kLds];
     __shared__ int s_idx;
@@ -1177,9 +1180,24 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(BLOCK == 
         int l[3] = {h.lvl[0], h.lvl[1], h.lvl[2]};
         long long nenq = h.n_enq;
         int64_t nS = h.nnodes;
-        unsigned long long *cur = A, *nxt = Bb;
+        // The frontier being read (cur) and the one being written (nxt): in LDS
+        // buffer cur_lds / nxt_lds, or (-1) in this workgroup's HBM buffer curg /
+        // nxtg.  Kept apart so that every access is a typed LDS or global one (a
+        // pointer that may be either compiles to flat accesses, whose waits also
+        // wait for the other kind).
+        unsigned long long *curg = A, *nxtg = Bb;
         int64_t cstride = cap, nstride = cap;
-        int cur_lds = -1, nxt_lds = -1;  // LDS buffer holding the frontier, or -1 (HBM)
+        int cur_lds = -1, nxt_lds = -1;
+        // (the LDS side as relaxed workgroup-scope atomics, plain ds_read / ds_write,
+        // which the compiler cannot merge with the global access into one flat one)
+        auto rd = [&](int64_t i) -> unsigned long long {
+            if (cur_lds >= 0) return __hip_atomic_load(&s_front[cur_lds][i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            return curg[i];
+        };
+        auto wr = [&](int64_t i, unsigned long long v) {
+            if (nxt_lds >= 0) __hip_atomic_store(&s_front[nxt_lds][i], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            else nxtg[i] = v;
+        };
         int state = 0;
         double tcap = 0.0;
         // t* of the pair, the same in every thread: folded in from s_tl after each level
@@ -1208,26 +1226,26 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(BLOCK == 
             const int r = state ? DISCARD : process(q, vf, 0.0, 1.0, 0.0, 1.0, 0.0, 1.0, false, delta, no_zero != 0);
             if (r == ACCEPT) { state = 1; tstar = 0.0; }
             else if (r == DISCARD) state = 1;
-            if (tid == 0) { cur[0] = 0ull; cur[cap] = 0ull; cur[2 * cap] = 0ull; }
+            if (tid == 0) { curg[0] = 0ull; curg[cap] = 0ull; curg[2 * cap] = 0ull; }
             nS = 1;
             pk_cur = true;
         } else if (pk_cur) {
             const unsigned long long *hnodes = cold()->hnodes;
-            for (int64_t i = tid; i < nS; i += BLOCK) cur[i] = hnodes[h.node_off + i];
+            for (int64_t i = tid; i < nS; i += BLOCK) curg[i] = hnodes[h.node_off + i];
         } else if (h.layout == 0) {
             const unsigned long long *hnodes = cold()->hnodes;
             for (int64_t i = tid; i < nS; i += BLOCK) {
                 const unsigned long long pk = hnodes[h.node_off + i];
-                cur[i] = pk & 0x1fffffull;
-                cur[cap + i] = (pk >> 21) & 0x1fffffull;
-                cur[2 * cap + i] = (pk >> 42) & 0x1fffffull;
+                curg[i] = pk & 0x1fffffull;
+                curg[cap + i] = (pk >> 21) & 0x1fffffull;
+                curg[2 * cap + i] = (pk >> 42) & 0x1fffffull;
             }
         } else {
             const unsigned long long *hnodes = cold()->hnodes;
             for (int64_t i = tid; i < nS; i += BLOCK) {
-                cur[i] = hnodes[h.node_off + i];
-                cur[cap + i] = hnodes[h.node_off + nS + i];
-                cur[2 * cap + i] = hnodes[h.node_off + 2 * nS + i];
+                curg[i] = hnodes[h.node_off + i];
+                curg[cap + i] = hnodes[h.node_off + nS + i];
+                curg[2 * cap + i] = hnodes[h.node_off + 2 * nS + i];
             }
         }
         if (tid == 0) { s_ovf[0] = 0u; s_nN[0] = 0u; s_tl[0] = kInfBits; s_zero[0] = 0; s_tg[0] = tg0; }
@@ -1245,13 +1263,12 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(BLOCK == 
             const double tbig = dyadic_big(l[0]), ubig = dyadic_big(l[1]), vbig = dyadic_big(l[2]);
             const bool finest = l[0] == kMaxLevel && l[1] == kMaxLevel && l[2] == kMaxLevel;
             // where this level's survivors go
-            if (use_lds && 2 * nS <= (pk_nxt ? 3 * kLds : kLds)) {
+            if (use_lds && 4 * nS <= BLOCK) {
                 nxt_lds = cur_lds == 0 ? 1 : 0;
-                nxt = s_front[nxt_lds];
                 nstride = kLds;
             } else {
                 nxt_lds = -1;
-                nxt = cur == A ? Bb : A;
+                nxtg = cur_lds < 0 && curg == A ? Bb : A;
                 nstride = cap;
             }
             if (tid == 0) {
@@ -1284,9 +1301,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(BLOCK == 
                     if (surv) {
                         const int64_t pos = (int64_t)base + __popcll(mask & ((1ull << lane) - 1ull));
                         if (pk_nxt && pos < 3 * nstride) {
-                            nxt[pos] = cn[0] | cn[1] << 21 | cn[2] << 42;
+                            wr(pos, cn[0] | cn[1] << 21 | cn[2] << 42);
                         } else if (!pk_nxt && pos < nstride) {
-                            nxt[pos] = cn[0]; nxt[nstride + pos] = cn[1]; nxt[2 * nstride + pos] = cn[2];
+                            wr(pos, cn[0]); wr(nstride + pos, cn[1]); wr(2 * nstride + pos, cn[2]);
                         } else {
                             s_ovf[ps] = 1u;
                         }
@@ -1305,7 +1322,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(BLOCK == 
                 const double t0 = dyadic(cn[0], tbig);
                 const bool inF = keep(t0, cn[0] == 0ull, has);
                 // roots reported at this level only shorten the work, never the count
-                const double tl = __longlong_as_double((long long)(*(volatile unsigned long long *)&s_tl[ps]));
+                const double tl = __longlong_as_double(
+                    (long long)__hip_atomic_load(&s_tl[ps], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
                 int r = DISCARD;
                 if (inF && t0 < tl) {
                     const double u0 = dyadic(cn[1], ubig), v0 = dyadic(cn[2], vbig);
@@ -1327,11 +1345,12 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(BLOCK == 
                 V[0] = dyadic(c0[2], vbig); V[1] = V[0] + vscale; V[2] = V[1] + vscale;
                 const double t00 = T[0], t10 = k == 0 ? T[1] : T[0];
                 const bool in0 = keep(t00, c0[0] == 0ull, has), in1 = keep(t10, c1[0] == 0ull, has);
-                const double tl = __longlong_as_double((long long)(*(volatile unsigned long long *)&s_tl[ps]));
+                const double tl = __longlong_as_double(
+                    (long long)__hip_atomic_load(&s_tl[ps], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
                 // once the next frontier has outgrown its buffer this level will be
                 // redone with larger ones (unless it ends the pair at the cap, which
                 // the count decides): its remaining children are counted, not evaluated
-                const bool ovf = *(volatile unsigned int *)&s_ovf[ps] != 0u;
+                const bool ovf = __hip_atomic_load(&s_ovf[ps], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != 0u;
                 const bool need0 = in0 && t00 < tl && !ovf, need1 = in1 && t10 < tl && !ovf;
                 int r0 = DISCARD, r1 = DISCARD;
                 if (need0 || need1) {
@@ -1356,9 +1375,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(BLOCK == 
                     base = __shfl(base, 63);
                     auto put = [&](const unsigned long long cn[3], int64_t pos) {
                         if (pk_nxt && pos < 3 * nstride) {
-                            nxt[pos] = cn[0] | cn[1] << 21 | cn[2] << 42;
+                            wr(pos, cn[0] | cn[1] << 21 | cn[2] << 42);
                         } else if (!pk_nxt && pos < nstride) {
-                            nxt[pos] = cn[0]; nxt[nstride + pos] = cn[1]; nxt[2 * nstride + pos] = cn[2];
+                            wr(pos, cn[0]); wr(nstride + pos, cn[1]); wr(2 * nstride + pos, cn[2]);
                         } else {
                             s_ovf[ps] = 1u;
                         }
@@ -1372,10 +1391,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(BLOCK == 
                 pn[0] = pn[1] = pn[2] = 0ull;
                 if (!has) return;
                 if (pk_cur) {
-                    const unsigned long long nd = cur[ni];
+                    const unsigned long long nd = rd(ni);
                     pn[0] = nd & 0x1fffffull; pn[1] = (nd >> 21) & 0x1fffffull; pn[2] = (nd >> 42) & 0x1fffffull;
                 } else {
-                    pn[0] = cur[ni]; pn[1] = cur[cstride + ni]; pn[2] = cur[2 * cstride + ni];
+                    pn[0] = rd(ni); pn[1] = rd(cstride + ni); pn[2] = rd(2 * cstride + ni);
                 }
             };
             if (2 * nS <= BLOCK) {
@@ -1386,14 +1405,17 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(BLOCK == 
                 cn[k] = 2ull * cn[k] + (unsigned long long)(i & 1);
                 child(cn, has);
             } else {
-                // a packed frontier's next word is loaded before this node's
-                // children are evaluated (one register pair in flight)
+                // A packed frontier's next word is loaded before this node's
+                // children are evaluated (one register pair in flight).  A
+                // frontier this wide is in HBM (see s_front), and the load is
+                // unconditional, clamped into the frontier, so that the compiler
+                // waits for the current word alone.
                 bool has = tid < nS;
-                unsigned long long w = has && pk_cur ? cur[tid] : 0ull;
+                unsigned long long w = curg[has ? tid : nS - 1];
                 for (int64_t b0 = 0; b0 < nS; b0 += BLOCK) {
                     const int64_t inext = b0 + BLOCK + tid;
                     const bool hasn = inext < nS;
-                    const unsigned long long wn = hasn && pk_cur ? cur[inext] : 0ull;
+                    const unsigned long long wn = curg[hasn ? inext : nS - 1];
                     unsigned long long pn[3];
                     if (pk_cur) {
                         pn[0] = w & 0x1fffffull; pn[1] = (w >> 21) & 0x1fffffull; pn[2] = (w >> 42) & 0x1fffffull;
@@ -1439,7 +1461,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(BLOCK == 
             }
             nenq += c_all;
             nS = (int64_t)nN;
-            cur = nxt;
+            curg = nxtg;
             cstride = nstride;
             cur_lds = nxt_lds;
             pk_cur = pk_nxt;
@@ -1457,12 +1479,12 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(BLOCK == 
             unsigned long long *hnodes = cold()->hnodes;
             if (o != ~0ull) {
                 if (pk_cur) {
-                    for (int64_t i = tid; i < nS; i += BLOCK) hnodes[o + i] = cur[i];
+                    for (int64_t i = tid; i < nS; i += BLOCK) hnodes[o + i] = rd(i);
                 } else {
                     for (int64_t i = tid; i < nS; i += BLOCK) {
-                        hnodes[o + i] = cur[i];
-                        hnodes[o + nS + i] = cur[cstride + i];
-                        hnodes[o + 2 * nS + i] = cur[2 * cstride + i];
+                        hnodes[o + i] = rd(i);
+                        hnodes[o + nS + i] = rd(cstride + i);
+                        hnodes[o + 2 * nS + i] = rd(2 * cstride + i);
                     }
                 }
             }
