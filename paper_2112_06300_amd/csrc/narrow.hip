@@ -154,6 +154,9 @@ __device__ __forceinline__ double dyadic(unsigned long long n, double big)
 // values follow one fixed float64 sequence: x(t) = fma(t, x1 - x0, x0);
 //   VF: g = fma(-u, b - a, p - a), F = fma(-v, c - a, g)
 //   EE: A = fma(u, a1 - a0, a0), B = fma(v, b1 - b0, b0), F = A - B.
+// Rounding is monotone, so the extremes over the corners at one t are taken
+// from the extremes of the factors (g over u; A over u and B over v): the
+// same values as corner by corner, with fewer operations.
 //
 // at_zero (App. B, no-zero-TOI strategy, for an interval starting at t = 0):
 // the interval is not reported for being narrow or inside C_eps, only at the
@@ -167,7 +170,7 @@ __device__ __forceinline__ int process(const Q &q, bool vf, double t0, double t1
     bool inside = true;
 #pragma unroll
     for (int a = 0; a < 3; a++) {
-        double bmin = __builtin_huge_val(), bmax = -__builtin_huge_val();
+        double bmin = 0.0, bmax = 0.0;
 #pragma unroll
         for (int it = 0; it < 2; it++) {
             const double t = it ? t1 : t0;
@@ -175,26 +178,26 @@ __device__ __forceinline__ int process(const Q &q, bool vf, double t0, double t1
             const double P1 = fma(t, q.D(1, a), q.X(1, a));
             const double P2 = fma(t, q.D(2, a), q.X(2, a));
             const double P3 = fma(t, q.D(3, a), q.X(3, a));
+            double lo, hi;
             if (vf) {
+                // F = fma(-v, c - a, g(u)) rises with g: its extremes over the four
+                // (u, v) corners come from the smaller and the larger g
                 const double pa = P0 - P1, eb = P2 - P1, ec = P3 - P1;
-#pragma unroll
-                for (int iu = 0; iu < 2; iu++) {
-                    const double g = fma(-(iu ? u1 : u0), eb, pa);
-#pragma unroll
-                    for (int iv = 0; iv < 2; iv++) {
-                        const double f = fma(-(iv ? v1 : v0), ec, g);
-                        bmin = fmin(bmin, f);
-                        bmax = fmax(bmax, f);
-                    }
-                }
+                const double g0 = fma(-u0, eb, pa), g1 = fma(-u1, eb, pa);
+                const double gl = fmin(g0, g1), gh = fmax(g0, g1);
+                lo = fmin(fma(-v0, ec, gl), fma(-v1, ec, gl));
+                hi = fmax(fma(-v0, ec, gh), fma(-v1, ec, gh));
             } else {
+                // F = A(u) - B(v), rounded: the extremes over the corners are the
+                // rounded differences of A's and B's extremes
                 const double ea = P1 - P0, eb = P3 - P2;
                 const double A0 = fma(u0, ea, P0), A1 = fma(u1, ea, P0);
                 const double B0 = fma(v0, eb, P2), B1 = fma(v1, eb, P2);
-                const double f00 = A0 - B0, f01 = A0 - B1, f10 = A1 - B0, f11 = A1 - B1;
-                bmin = fmin(fmin(bmin, f00), fmin(f01, fmin(f10, f11)));
-                bmax = fmax(fmax(bmax, f00), fmax(f01, fmax(f10, f11)));
+                lo = fmin(A0, A1) - fmax(B0, B1);
+                hi = fmax(A0, A1) - fmin(B0, B1);
             }
+            bmin = it ? fmin(bmin, lo) : lo;
+            bmax = it ? fmax(bmax, hi) : hi;
         }
         if (bmin > q.E(a) || bmax < -q.E(a)) return DISCARD;
         const double w = bmax - bmin;
@@ -218,12 +221,16 @@ __device__ __forceinline__ void axis_pair(const Q &q, int a, const double T[3], 
 {
     constexpr int NT = K == 0 ? 3 : 2, NU = K == 1 ? 3 : 2, NV = K == 2 ? 3 : 2;
     // running min / max of the three slices across K (4 corners each), each
-    // started at its slice's first corner
+    // started at its slice's first contribution
     double smn[3], smx[3];
-    auto fold = [&](int sl, bool first, double f) {
-        smn[sl] = first ? f : fmin(smn[sl], f);
-        smx[sl] = first ? f : fmax(smx[sl], f);
+    auto fold = [&](int sl, bool first, double lo, double hi) {
+        smn[sl] = first ? lo : fmin(smn[sl], lo);
+        smx[sl] = first ? hi : fmax(smx[sl], hi);
     };
+    // Rounding is monotone, so a slice's extremes come from extremes of the
+    // factors that vary inside it: F = A(u) - B(v) (edge-edge) gives
+    // RN(min A - max B) and RN(max A - min B); F = fma(-v, c - a, g(u))
+    // (vertex-face) rises with g.  The values are those of the corners.
 #pragma unroll
     for (int it = 0; it < NT; it++) {
         const double t = T[it];
@@ -233,32 +240,43 @@ __device__ __forceinline__ void axis_pair(const Q &q, int a, const double T[3], 
         const double P3 = fma(t, q.D(3, a), q.X(3, a));
         if (VF) {
             const double pa = P0 - P1, eb = P2 - P1, ec = P3 - P1;
+            double g[NU];
 #pragma unroll
-            for (int iu = 0; iu < NU; iu++) {
-                const double g = fma(-U[iu], eb, pa);
+            for (int iu = 0; iu < NU; iu++) g[iu] = fma(-U[iu], eb, pa);
+            if (K == 1) {
+                // slices along u: each holds one g, its corners differ in v
 #pragma unroll
-                for (int iv = 0; iv < NV; iv++) {
-                    const double f = fma(-V[iv], ec, g);
-                    const int sl = K == 0 ? it : (K == 1 ? iu : iv);
-                    const bool first = K == 0 ? (iu == 0 && iv == 0) : (K == 1 ? (it == 0 && iv == 0) : (it == 0 && iu == 0));
-                    fold(sl, first, f);
+                for (int iu = 0; iu < NU; iu++) {
+                    const double f0 = fma(-V[0], ec, g[iu]), f1 = fma(-V[1], ec, g[iu]);
+                    fold(iu, it == 0, fmin(f0, f1), fmax(f0, f1));
+                }
+            } else {
+                const double gl = fmin(g[0], g[1]), gh = fmax(g[0], g[1]);
+                if (K == 0) {
+                    fold(it, true, fmin(fma(-V[0], ec, gl), fma(-V[1], ec, gl)),
+                         fmax(fma(-V[0], ec, gh), fma(-V[1], ec, gh)));
+                } else {
+#pragma unroll
+                    for (int iv = 0; iv < NV; iv++) fold(iv, it == 0, fma(-V[iv], ec, gl), fma(-V[iv], ec, gh));
                 }
             }
         } else {
             const double ea = P1 - P0, eb = P3 - P2;
-            double B[NV];
+            double A[NU], B[NV];
+#pragma unroll
+            for (int iu = 0; iu < NU; iu++) A[iu] = fma(U[iu], ea, P0);
 #pragma unroll
             for (int iv = 0; iv < NV; iv++) B[iv] = fma(V[iv], eb, P2);
+            if (K == 0) {
+                fold(it, true, fmin(A[0], A[1]) - fmax(B[0], B[1]), fmax(A[0], A[1]) - fmin(B[0], B[1]));
+            } else if (K == 1) {
+                const double bl = fmin(B[0], B[1]), bh = fmax(B[0], B[1]);
 #pragma unroll
-            for (int iu = 0; iu < NU; iu++) {
-                const double A = fma(U[iu], ea, P0);
+                for (int iu = 0; iu < NU; iu++) fold(iu, it == 0, A[iu] - bh, A[iu] - bl);
+            } else {
+                const double al = fmin(A[0], A[1]), ah = fmax(A[0], A[1]);
 #pragma unroll
-                for (int iv = 0; iv < NV; iv++) {
-                    const double f = A - B[iv];
-                    const int sl = K == 0 ? it : (K == 1 ? iu : iv);
-                    const bool first = K == 0 ? (iu == 0 && iv == 0) : (K == 1 ? (it == 0 && iv == 0) : (it == 0 && iu == 0));
-                    fold(sl, first, f);
-                }
+                for (int iv = 0; iv < NV; iv++) fold(iv, it == 0, al - B[iv], ah - B[iv]);
             }
         }
     }
