@@ -687,6 +687,14 @@ __device__ __forceinline__ unsigned long long uniform(unsigned long long v)
     return (unsigned long long)hi << 32 | lo;
 }
 
+// A candidate's record as staged in LDS (one 32-byte slot, read by two
+// broadcast loads).
+template <typename K>
+struct alignas(16) SweepCand {
+    K key;
+    float lb, hb, lc, hc;
+};
+
 // Candidates tested per block: their records are loaded together.
 template <typename K>
 struct SweepUnroll { static constexpr int value = 8; };
@@ -733,7 +741,8 @@ __device__ __forceinline__ void sweep_tile(const K *__restrict__ klo, const K *_
                                            const SweepRecords &R, int64_t qbase, int64_t qend, int64_t cbeg,
                                            int64_t cend, int64_t chunk, int64_t nchunks, int64_t clen,
                                            const uint32_t *__restrict__ qord, int32_t *__restrict__ out,
-                                           int64_t out_cap, unsigned long long *counter, int32_t (*s_out)[2])
+                                           int64_t out_cap, unsigned long long *counter, int32_t (*s_out)[2],
+                                           SweepCand<K> *s_cand)
 {
     constexpr int U = SweepUnroll<K>::value;
     const int lane = threadIdx.x;
@@ -776,48 +785,64 @@ __device__ __forceinline__ void sweep_tile(const K *__restrict__ klo, const K *_
         j = jw + chunk * clen;
         const int64_t jend =
             chunk == nchunks - 1 ? cend : (jw + (chunk + 1) * clen < cend ? jw + (chunk + 1) * clen : cend);
-        bool done = false;
-        for (; j + U <= jend; j += U) {
-            K kk[U];
-            float bl[U], bh[U], cl[U], ch[U];
+        // Candidates in chunks of 64 staged in LDS: lane L loads candidate j + L
+        // (coalesced; past jend a sentinel whose key lies beyond every window),
+        // and the next chunk is loaded while this one is tested.  Vector loads
+        // complete in order, so the wait for a chunk leaves the next one in
+        // flight (scalar loads, which return out of order, could not do this).
+        // (the loads are unconditional, from an index clamped into the window, so
+        // that exactly one chunk is in flight when a chunk is waited for)
+        auto load = [&](int64_t jj) {
+            const int64_t js = jj < jend ? jj : jend - 1;
+            const K kv = klo[js];
+            SweepCand<K> c;
+            c.key = jj < jend ? kv : ~(K)0;
+            c.lb = R.lob[js];
+            c.hb = R.hib[js];
+            c.lc = R.loc[js];
+            c.hc = R.hic[js];
+            return c;
+        };
+        bool done = j >= jend;
+        SweepCand<K> nxt{};
+        if (!done) nxt = load(j + lane);
+        while (!done) {
+            // the wave's earlier reads of s_cand are done: LDS runs a wave's accesses in order
+            s_cand[lane] = nxt;
+            const int64_t jc = j;
+            j += kTile;
+            nxt = load(j + lane);
+#pragma unroll 1
+            for (int c0 = 0; c0 < kTile; c0 += U) {
+                SweepCand<K> cc[U];
 #pragma unroll
-            for (int u = 0; u < U; u++) {
-                kk[u] = klo[j + u];
-                bl[u] = R.lob[j + u]; bh[u] = R.hib[j + u]; cl[u] = R.loc[j + u]; ch[u] = R.hic[j + u];
-            }
-            // The block is tested whole (one wait for its loads); candidates past
-            // every lane's upper key fail the key test, and the walk ends after
-            // the block whose last key is past them all.  Only the block's union
-            // mask is kept; the rare block with an overlap repeats its tests
-            // candidate by candidate to emit the pairs.
-            auto test = [&](int u) {
-                bool t = (kk[u] <= rkh) & (bl[u] <= hb) & (lb <= bh[u]) & (cl[u] <= hc) & (lc <= ch[u]);
-                if (ROLE == 0) t &= kk[u] >= rkl;
-                else if (ROLE == 1) t &= j + u > i;
-                else t &= kk[u] > rkl;
-                return t;
-            };
-            unsigned long long any = 0ull;
-#pragma unroll
-            for (int u = 0; u < U; u++) any |= __ballot(test(u));
-            if (any != 0ull) {
+                for (int u = 0; u < U; u++) cc[u] = s_cand[c0 + u];
+                // The block is tested whole: each comparison becomes a lane mask
+                // and the masks are combined on the scalar unit.  Candidates past
+                // every lane's upper key fail the key test, and the walk ends after
+                // the block whose last key is past them all.  Only the rare block
+                // with an overlap applies the pair rules, candidate by candidate.
+                unsigned long long m[U], any = 0ull;
 #pragma unroll
                 for (int u = 0; u < U; u++) {
-                    const bool t = test(u);
-                    if (__ballot(t))
-                        sweep_emit<K, ROLE>(j + u, t, R, me, w0, w1, w2, lane, lt, fill, out, out_cap, counter, s_out);
+                    unsigned long long x = __ballot(cc[u].key <= rkh) & __ballot(cc[u].lb <= hb) &
+                                           __ballot(lb <= cc[u].hb) & __ballot(cc[u].lc <= hc) & __ballot(lc <= cc[u].hc);
+                    if (ROLE == 0) x &= __ballot(cc[u].key >= rkl);
+                    else if (ROLE == 1) x &= __ballot(jc + c0 + u > i);
+                    else x &= __ballot(cc[u].key > rkl);
+                    m[u] = x;
+                    any |= x;
                 }
+                if (any != 0ull) {
+#pragma unroll
+                    for (int u = 0; u < U; u++)
+                        if (m[u])
+                            sweep_emit<K, ROLE>(jc + c0 + u, ((m[u] >> lane) & 1ull) != 0ull, R, me, w0, w1, w2, lane, lt,
+                                                fill, out, out_cap, counter, s_out);
+                }
+                if (cc[U - 1].key > kmax) { done = true; break; }  // every later candidate lies beyond all windows
             }
-            if (kk[U - 1] > kmax) { done = true; break; }  // every later candidate lies beyond all windows
-        }
-        for (; !done && j < jend; j++) {
-            const K kj = klo[j];
-            if (kj > kmax) break;
-            bool t = (kj <= rkh) & (R.lob[j] <= hb) & (lb <= R.hib[j]) & (R.loc[j] <= hc) & (lc <= R.hic[j]);
-            if (ROLE == 0) t &= kj >= rkl;
-            else if (ROLE == 1) t &= j > i;
-            else t &= kj > rkl;
-            if (__ballot(t)) sweep_emit<K, ROLE>(j, t, R, me, w0, w1, w2, lane, lt, fill, out, out_cap, counter, s_out);
+            if (j >= jend) done = true;
         }
     }
     if (fill > 0) {
@@ -836,6 +861,7 @@ __global__ __launch_bounds__(kTile) void sweep_kernel(
     int32_t *__restrict__ ee, int64_t ee_cap, unsigned long long *counts)
 {
     __shared__ int32_t s_out[kOutCap][2];
+    __shared__ SweepCand<K> s_cand[kTile];
     const int64_t nb = nv + ne + nf, f0 = nv + ne;
     // block = chunk * tiles_grid + (tile slot); tiles_grid is a multiple of 8 * group.
     // The sweep covers the query tiles [tile0, tile1): the pairs whose earlier
@@ -847,15 +873,15 @@ __global__ __launch_bounds__(kTile) void sweep_kernel(
     if (t < tiles_v) {
         if (chunk >= ch.vf) return;
         sweep_tile<K, 0>(klo, khi, R, t * kTile, nv, f0, nb, chunk, ch.vf, ch.len, qord, vf, vf_cap, &counts[0],
-                         s_out);
+                         s_out, s_cand);
     } else if (t < tiles_v + tiles_e) {
         if (chunk >= ch.ee) return;
         sweep_tile<K, 1>(klo, khi, R, nv + (t - tiles_v) * kTile, f0, nv, f0, chunk, ch.ee, ch.len, qord, ee,
-                         ee_cap, &counts[1], s_out);
+                         ee_cap, &counts[1], s_out, s_cand);
     } else {
         if (chunk >= ch.vf) return;
         sweep_tile<K, 2>(klo, khi, R, f0 + (t - tiles_v - tiles_e) * kTile, nb, 0, nv, chunk, ch.vf, ch.len, qord,
-                         vf, vf_cap, &counts[0], s_out);
+                         vf, vf_cap, &counts[0], s_out, s_cand);
     }
 }
 
