@@ -85,11 +85,11 @@ class BudgetResult(ctypes.Structure):
 
 
 # Learned schedule defaults: predictions of log2(1 + n_enq) from which a pair starts in the wide stage, and
-# the most such pairs (measured best on the cloth workload; the perturbed torus prefers 10 and 20,000).
+# the most such pairs (measured best on the cloth workload; the perturbed torus prefers 14 and 40,000).
 HEAVY_THRESHOLD = 7.0
 MAX_HEAVY = 256
-TORUS_HEAVY_THRESHOLD = 10.0
-TORUS_MAX_HEAVY = 20000
+TORUS_HEAVY_THRESHOLD = 14.0
+TORUS_MAX_HEAVY = 40000
 
 
 _lib = None
