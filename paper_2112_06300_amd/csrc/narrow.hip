@@ -23,6 +23,8 @@
 #include "ccd_internal.h"
 #include "mlp_tile.h"
 
+#include <type_traits>
+
 namespace ccd {
 
 namespace {
@@ -1415,6 +1417,62 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(BLOCK == 
                     pn[0] = rd(ni); pn[1] = rd(cstride + ni); pn[2] = rd(2 * cstride + ni);
                 }
             };
+            // children() for a packed frontier whose level splits dimension K
+            // (fixed for the level): the children's words come from the node's
+            // word (field K doubled, plus one for the second child), with no
+            // selection by a runtime dimension
+            auto children_pk = [&](auto KC, unsigned long long w, bool has) {
+                constexpr int K = decltype(KC)::value;
+                constexpr int SH = 21 * K;
+                const unsigned long long f0 = w & 0x1fffffull, f1 = (w >> 21) & 0x1fffffull,
+                                         f2 = (w >> 42) & 0x1fffffull;
+                const unsigned long long fk = K == 0 ? f0 : (K == 1 ? f1 : f2);
+                // the first child's numerators (the second's is one more along K)
+                const unsigned long long n0 = K == 0 ? 2ull * f0 : f0, n1 = K == 1 ? 2ull * f1 : f1,
+                                         n2 = K == 2 ? 2ull * f2 : f2;
+                double T[3], U[3], V[3];
+                T[0] = dyadic(n0, tbig); T[1] = T[0] + tscale; T[2] = T[1] + tscale;
+                U[0] = dyadic(n1, ubig); U[1] = U[0] + uscale; U[2] = U[1] + uscale;
+                V[0] = dyadic(n2, vbig); V[1] = V[0] + vscale; V[2] = V[1] + vscale;
+                const double t00 = T[0], t10 = K == 0 ? T[1] : T[0];
+                const bool z0 = n0 == 0ull, z1 = K == 0 ? false : n0 == 0ull;
+                const bool in0 = keep(t00, z0, has), in1 = keep(t10, z1, has);
+                const double tl = __longlong_as_double(
+                    (long long)__hip_atomic_load(&s_tl[ps], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+                const bool ovf = __hip_atomic_load(&s_ovf[ps], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != 0u;
+                const bool need0 = in0 && t00 < tl && !ovf, need1 = in1 && t10 < tl && !ovf;
+                int r0 = DISCARD, r1 = DISCARD;
+                if (need0 || need1)
+                    process_pair<K>(q, vf, T, U, V, need0, need1, finest, delta, no_zero && z0, no_zero && z1, r0, r1);
+                if (r0 == ACCEPT || r1 == ACCEPT) {
+                    const double ta = r0 == ACCEPT ? t00 : t10;
+                    atomicMin(&s_tl[ps], (unsigned long long)__double_as_longlong(ta));
+                    if (gmode) atomicMin((unsigned long long *)toi_min, (unsigned long long)__double_as_longlong(ta));
+                }
+                const int s0 = r0 == SPLIT ? 1 : 0, s1 = r1 == SPLIT ? 1 : 0;
+                int tot = 0;
+                const int pre = wave_excl_scan(s0 + s1, tot);
+                if (tot) {
+                    unsigned int base = 0u;
+                    if (lane == 63) base = atomicAdd(&s_nN[ps], (unsigned int)tot);
+                    base = __shfl(base, 63);
+                    auto put = [&](unsigned long long plus, int64_t pos) {
+                        if (pk_nxt) {
+                            if (pos < 3 * nstride) wr(pos, w + (fk << SH) + (plus << SH));
+                            else s_ovf[ps] = 1u;
+                        } else if (pos < nstride) {
+                            wr(pos, n0 + (K == 0 ? plus : 0ull));
+                            wr(nstride + pos, n1 + (K == 1 ? plus : 0ull));
+                            wr(2 * nstride + pos, n2 + (K == 2 ? plus : 0ull));
+                        } else {
+                            s_ovf[ps] = 1u;
+                        }
+                    };
+                    const int64_t pos = (int64_t)base + pre;
+                    if (s0) put(0ull, pos);
+                    if (s1) put(1ull, pos + s0);
+                }
+            };
             if (2 * nS <= BLOCK) {
                 const int64_t i = tid;
                 const bool has = i < 2 * nS;
@@ -1428,21 +1486,31 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(BLOCK == 
                 // frontier this wide is in HBM (see s_front), and the load is
                 // unconditional, clamped into the frontier, so that the compiler
                 // waits for the current word alone.
-                bool has = tid < nS;
-                unsigned long long w = curg[has ? tid : nS - 1];
-                for (int64_t b0 = 0; b0 < nS; b0 += BLOCK) {
-                    const int64_t inext = b0 + BLOCK + tid;
-                    const bool hasn = inext < nS;
-                    const unsigned long long wn = curg[hasn ? inext : nS - 1];
-                    unsigned long long pn[3];
-                    if (pk_cur) {
-                        pn[0] = w & 0x1fffffull; pn[1] = (w >> 21) & 0x1fffffull; pn[2] = (w >> 42) & 0x1fffffull;
-                    } else {
-                        node(b0 + tid, has, pn);
+                // The loop is specialized for the level's split dimension.
+                auto run_pk = [&](auto KC) {
+                    bool has = tid < nS;
+                    unsigned long long w = curg[has ? tid : nS - 1];
+                    for (int64_t b0 = 0; b0 < nS; b0 += BLOCK) {
+                        const int64_t inext = b0 + BLOCK + tid;
+                        const bool hasn = inext < nS;
+                        const unsigned long long wn = curg[hasn ? inext : nS - 1];
+                        children_pk(KC, w, has);
+                        w = wn;
+                        has = hasn;
                     }
-                    children(pn, has);
-                    w = wn;
-                    has = hasn;
+                };
+                if (pk_cur) {
+                    if (k == 0) run_pk(std::integral_constant<int, 0>());
+                    else if (k == 1) run_pk(std::integral_constant<int, 1>());
+                    else run_pk(std::integral_constant<int, 2>());
+                } else {
+                    // levels past 21: three numerator arrays
+                    for (int64_t b0 = 0; b0 < nS; b0 += BLOCK) {
+                        const bool has = b0 + tid < nS;
+                        unsigned long long pn[3];
+                        node(b0 + tid, has, pn);
+                        children(pn, has);
+                    }
                 }
             }
             int wcnt = 0;
