@@ -160,6 +160,9 @@ __device__ __forceinline__ double dyadic(unsigned long long n, double big)
 // from the extremes of the factors (g over u; A over u and B over v): the
 // same values as corner by corner, with fewer operations.
 //
+// All three axes are evaluated before the decision (no branch per axis: the
+// decision is the same, and the work of the axes can be interleaved).
+//
 // at_zero (App. B, no-zero-TOI strategy, for an interval starting at t = 0):
 // the interval is not reported for being narrow or inside C_eps, only at the
 // finest level.
@@ -167,7 +170,7 @@ template <class Q>
 __device__ __forceinline__ int process(const Q &q, bool vf, double t0, double t1, double u0, double u1,
                                        double v0, double v1, bool finest, double delta, bool at_zero = false)
 {
-    if (vf && u0 + v0 > 1.0) return DISCARD;
+    bool disc = vf && u0 + v0 > 1.0;
     double width = 0.0;
     bool inside = true;
 #pragma unroll
@@ -201,11 +204,12 @@ __device__ __forceinline__ int process(const Q &q, bool vf, double t0, double t1
             bmin = it ? fmin(bmin, lo) : lo;
             bmax = it ? fmax(bmax, hi) : hi;
         }
-        if (bmin > q.E(a) || bmax < -q.E(a)) return DISCARD;
+        disc = disc || bmin > q.E(a) || bmax < -q.E(a);
         const double w = bmax - bmin;
         width = w > width ? w : width;
         inside = inside && bmin >= -q.E(a) && bmax <= q.E(a);
     }
+    if (disc) return DISCARD;
     if (((width < delta || inside) && !at_zero) || finest) return ACCEPT;
     return SPLIT;
 }
@@ -303,9 +307,11 @@ __device__ __forceinline__ void process_pair(const Q &q, bool vf, const double T
     bool d1 = !need1 || (vf && cu1 + cv1 > 1.0);
     double w0 = 0.0, w1 = 0.0;
     bool in0 = true, in1 = true;
+    // every axis is evaluated: a wave rarely finds both children of all its
+    // nodes outside C_eps early, and without a branch per axis the three
+    // axes' independent work can be interleaved
 #pragma unroll
     for (int a = 0; a < 3; a++) {
-        if (d0 && d1) break;
         double mn0, mx0, mn1, mx1;
         if (vf) axis_pair<K, true, Q>(q, a, T, U, V, mn0, mx0, mn1, mx1);
         else axis_pair<K, false, Q>(q, a, T, U, V, mn0, mx0, mn1, mx1);
