@@ -618,7 +618,10 @@ struct PoolLds {
     unsigned long long tmin[kPoolSlots];   // earliest kept child
     unsigned long long hoff[kPoolSlots];   // first node of a hand-over in the node buffer
     unsigned long long zmask;              // slots with a kept child starting at t = 0 (no-zero strategy)
-    int nsurv[kPoolSlots], cnt[kPoolSlots], k[kPoolSlots], off[kPoolSlots], pos[kPoolSlots];
+    unsigned long long accm;               // slots whose t* dropped during the last EVAL
+    // survivors << 16 | kept children, per slot, of the last EVAL
+    unsigned int nc[kPoolSlots];
+    int cnt[kPoolSlots], k[kPoolSlots], off[kPoolSlots], pos[kPoolSlots];
 };
 static_assert(kSlots <= kPoolSlots && kRootLimit < kQCap, "pool sizes");
 static_assert(sizeof(PoolLds) <= 163840 / 8, "pool LDS must allow 8 workgroups per CU");
@@ -665,14 +668,38 @@ __device__ __forceinline__ int slot_split(uint32_t lvp, uint32_t mp, int &lk)
     return k;
 }
 
+// Children of the split interval nd (of a slot at levels lvp, split levels
+// mp) that start before ts: their number, and whether one starts at t = 0.
+// None while the next level would pass the packed numerators' 21 bits (the
+// pair is handed over instead).
+__device__ __forceinline__ int kept_children(unsigned long long nd, uint32_t lvp, uint32_t mp, double ts, bool &z)
+{
+    int lk = 0;
+    const int ks = slot_split(lvp, mp, lk);
+    z = false;
+    if (lk + 1 > kLightMaxLevel) return 0;
+    const double tsn = pow2neg((int)(lvp & 255u) + (ks == 0 ? 1 : 0));
+    int c = 0;
+#pragma unroll
+    for (int i = 0; i < 2; i++) {
+        const unsigned long long ch = child_of(nd, ks, i);
+        if (node_tlo(ch, tsn) < ts) {
+            c++;
+            z = z || (ch & 0x1fffffull) == 0ull;
+        }
+    }
+    return c;
+}
+
 // The pool.  A round:
-//   D (all lanes, last round's queue): count the kept children of every split
-//     interval into its slot (LDS atomics);
+//   D (all lanes, last round's queue): recount the kept children of the slots
+//     whose t* dropped during the last EVAL (the others were counted there);
 //   E (owner lanes): finish, cap, hand over or expand each pair; queue offsets
 //     by wave prefix sums; free slots take their prefetched pair as a new root;
 //   F (all lanes): write the kept children (or hand-over survivors);
 //   EVAL (all lanes, this round's queue): evaluate, then fold the result into
-//     the slot (atomic min of t*, survivor count).
+//     the slot (atomic min of t*; survivors and their children kept under the
+//     t* of that moment, one packed atomic add).
 __global__ __launch_bounds__(kPoolSlots) void pool_kernel(
     const double *__restrict__ V0, const double *__restrict__ V1, const int4 *__restrict__ ids4,
     const double *__restrict__ peps, const uint32_t *__restrict__ pm, PairCounts pc,
@@ -712,12 +739,12 @@ __global__ __launch_bounds__(kPoolSlots) void pool_kernel(
     nx_base = __shfl(nx_base, 0);
     if (order && nx_base + lane < n_pairs) ord_nx = order[nx_base + lane];
     S.tstar[lane] = kInfBits;
-    S.nsurv[lane] = 0;
+    S.nc[lane] = 0u;
     S.cnt[lane] = 0;
     S.tmin[lane] = kInfBits;
     S.lv[lane] = 0u;
     S.mm[lane] = 0u;
-    if (lane == 0) S.zmask = 0ull;
+    if (lane == 0) { S.zmask = 0ull; S.accm = 0ull; }
 
     for (;;) {
         // ---- prefetch pipeline (uniform control flow).  Stage A's registers
@@ -790,27 +817,25 @@ __global__ __launch_bounds__(kPoolSlots) void pool_kernel(
         if (doB && okb) load_raw(idb, V0, V1, raw);
         const int nxt = cur ^ 1;
 
-        // ---- D (all lanes over last round's entries): count children that start before t*
-        for (int b0 = 0; b0 < nq; b0 += kPoolSlots) {
-            const int e = b0 + lane;
-            if (e < nq && S.res[e] == SPLIT) {
-                const int s = S.slot[cur][e];
-                const uint32_t lvp = S.lv[s];
-                int lk = 0;
-                const int ks = slot_split(lvp, S.mm[s], lk);
-                if (lk + 1 <= kLightMaxLevel) {
-                    const double tsn = pow2neg((int)(lvp & 255u) + (ks == 0 ? 1 : 0));
-                    const double ts = fmin(__longlong_as_double((long long)S.tstar[s]), tb);
-                    const unsigned long long nd = S.node[cur][e];
-#pragma unroll
-                    for (int c = 0; c < 2; c++) {
-                        const unsigned long long ch = child_of(nd, ks, c);
-                        const double tl = node_tlo(ch, tsn);
-                        if (tl < ts) {
-                            atomicAdd(&S.cnt[s], 1);
-                            atomicMin(&S.tmin[s], (unsigned long long)__double_as_longlong(tl));
-                            if (no_zero && (ch & 0x1fffffull) == 0ull) atomicOr(&S.zmask, 1ull << s);
-                        }
+        // ---- D (all lanes over last round's entries): children start before t*
+        // counted again for the slots whose t* dropped while EVAL counted them
+        // (in global mode, where the shared t* may have dropped too, all slots)
+        const unsigned long long redo = gmode ? ~0ull : S.accm;
+        if (redo) {
+            if ((redo >> lane) & 1ull) {
+                S.nc[lane] &= 0xffff0000u;
+                atomicAnd(&S.zmask, ~(1ull << lane));
+            }
+            for (int b0 = 0; b0 < nq; b0 += kPoolSlots) {
+                const int e = b0 + lane;
+                if (e < nq && S.res[e] == SPLIT) {
+                    const int s = S.slot[cur][e];
+                    if ((redo >> s) & 1ull) {
+                        const double ts = fmin(__longlong_as_double((long long)S.tstar[s]), tb);
+                        bool z = false;
+                        const int c = kept_children(S.node[cur][e], S.lv[s], S.mm[s], ts, z);
+                        if (c) atomicAdd(&S.nc[s], (unsigned int)c);
+                        if (no_zero && z) atomicOr(&S.zmask, 1ull << s);
                     }
                 }
             }
@@ -824,8 +849,8 @@ __global__ __launch_bounds__(kPoolSlots) void pool_kernel(
         const unsigned long long zm = S.zmask;
         if (active) {
             tstar = __longlong_as_double((long long)S.tstar[lane]);
-            nsurv = S.nsurv[lane];
-            tmin = __longlong_as_double((long long)S.tmin[lane]);
+            const unsigned int nc = S.nc[lane];
+            nsurv = (int)(nc >> 16);
             if (nsurv == 0) {
                 outcome = 1;
             } else {
@@ -833,10 +858,22 @@ __global__ __launch_bounds__(kPoolSlots) void pool_kernel(
                 if (l[k] + 1 > kLightMaxLevel) {
                     outcome = 3;
                 } else {
-                    const int cnt = S.cnt[lane];
+                    const int cnt = (int)(nc & 0xffffu);
                     if (cnt == 0) outcome = 1;
                     else if (nenq + cnt > max_iter && !((zm >> lane) & 1ull)) { outcome = 2; nenq += cnt; }
                     else { outcome = 4; push = cnt; }
+                    if (outcome == 2) {
+                        // the earliest kept child (a capped pair's reported time): a
+                        // first child starts where its parent does, a second one no
+                        // earlier, so it is the earliest kept parent's start
+                        const double ts = fmin(tstar, tb), tsc = pow2neg(l[0]);
+                        for (int e = 0; e < nq; e++) {
+                            if (S.slot[cur][e] == lane && S.res[e] == SPLIT) {
+                                const double t0 = node_tlo(S.node[cur][e], tsc);
+                                if (t0 < ts && t0 < tmin) tmin = t0;
+                            }
+                        }
+                    }
                 }
             }
         }
@@ -981,10 +1018,10 @@ __global__ __launch_bounds__(kPoolSlots) void pool_kernel(
         }
         // accumulators for the next EVAL and D
         S.tstar[lane] = (unsigned long long)__double_as_longlong(active ? tstar : __builtin_huge_val());
-        S.nsurv[lane] = 0;
+        S.nc[lane] = 0u;
         S.cnt[lane] = 0;
         S.tmin[lane] = kInfBits;
-        if (lane == 0) S.zmask = 0ull;
+        if (lane == 0) { S.zmask = 0ull; S.accm = 0ull; }
         const int T = total + __popcll(__ballot(root_fits)) + nmig;
         __syncthreads();
         // ---- F (all lanes over last round's entries): kept children, or hand-over survivors
@@ -1021,44 +1058,55 @@ __global__ __launch_bounds__(kPoolSlots) void pool_kernel(
         // ---- EVAL: one queued interval per lane, any slot; results folded into the slot
         for (int b0 = 0; b0 < T; b0 += kPoolSlots) {
             const int e = b0 + lane;
-            if (e < T && (S.node[nxt][e] & kCarryBit)) {
-                // a waiting pair's survivor: already evaluated, still to be split
+            if (e < T) {
                 const int s = S.slot[nxt][e];
-                S.node[nxt][e] &= ~kCarryBit;
-                S.res[e] = (uint8_t)SPLIT;
-                atomicAdd(&S.nsurv[s], 1);
-            } else if (e < T) {
-                const int s = S.slot[nxt][e];
-                const unsigned long long nd = S.node[nxt][e];
+                unsigned long long nd = S.node[nxt][e];
                 const uint32_t lvp = S.lv[s];
-                const bool evf = (lvp >> 24) & 1u;
-                const double tscale = pow2neg((int)(lvp & 255u));
-                const double uscale = pow2neg((int)((lvp >> 8) & 255u));
-                const double vscale = pow2neg((int)((lvp >> 16) & 255u));
-                const uint32_t nt = (uint32_t)(nd & 0x1fffffull);
-                const uint32_t nu = (uint32_t)((nd >> 21) & 0x1fffffull);
-                const uint32_t nw = (uint32_t)((nd >> 42) & 0x1fffffull);
-                Query q;
+                int r = DISCARD;
+                if (nd & kCarryBit) {
+                    // a waiting pair's survivor: already evaluated, still to be split
+                    nd &= ~kCarryBit;
+                    S.node[nxt][e] = nd;
+                    r = SPLIT;
+                } else {
+                    const bool evf = (lvp >> 24) & 1u;
+                    const double tscale = pow2neg((int)(lvp & 255u));
+                    const double uscale = pow2neg((int)((lvp >> 8) & 255u));
+                    const double vscale = pow2neg((int)((lvp >> 16) & 255u));
+                    const uint32_t nt = (uint32_t)(nd & 0x1fffffull);
+                    const uint32_t nu = (uint32_t)((nd >> 21) & 0x1fffffull);
+                    const uint32_t nw = (uint32_t)((nd >> 42) & 0x1fffffull);
+                    Query q;
 #pragma unroll
-                for (int kk = 0; kk < 4; kk++)
+                    for (int kk = 0; kk < 4; kk++)
 #pragma unroll
-                    for (int a = 0; a < 3; a++) {
-                        q.x0[kk][a] = S.x0[3 * kk + a][s];
-                        q.d[kk][a] = S.d[3 * kk + a][s];
+                        for (int a = 0; a < 3; a++) {
+                            q.x0[kk][a] = S.x0[3 * kk + a][s];
+                            q.d[kk][a] = S.d[3 * kk + a][s];
+                        }
+                    q.eps[0] = S.eps[0][s]; q.eps[1] = S.eps[1][s]; q.eps[2] = S.eps[2][s];
+                    const double t0 = (double)nt * tscale;
+                    // global mode: an interval at or after the shared t* cannot lower it
+                    if (t0 < tb)
+                        r = process(q, evf, t0, (double)(nt + 1u) * tscale, (double)nu * uscale,
+                                    (double)(nu + 1u) * uscale, (double)nw * vscale, (double)(nw + 1u) * vscale,
+                                    false, delta, no_zero && nt == 0u);
+                    if (r == ACCEPT) {
+                        atomicMin(&S.tstar[s], (unsigned long long)__double_as_longlong(t0));
+                        atomicOr(&S.accm, 1ull << s);
+                        if (gmode)
+                            atomicMin((unsigned long long *)toi_min, (unsigned long long)__double_as_longlong(t0));
                     }
-                q.eps[0] = S.eps[0][s]; q.eps[1] = S.eps[1][s]; q.eps[2] = S.eps[2][s];
-                const double t0 = (double)nt * tscale;
-                int r = DISCARD;  // global mode: an interval at or after the shared t* cannot lower it
-                if (t0 < tb)
-                    r = process(q, evf, t0, (double)(nt + 1u) * tscale, (double)nu * uscale,
-                                (double)(nu + 1u) * uscale, (double)nw * vscale, (double)(nw + 1u) * vscale, false,
-                                delta, no_zero && nt == 0u);
+                }
                 S.res[e] = (uint8_t)r;
-                if (r == ACCEPT) {
-                    atomicMin(&S.tstar[s], (unsigned long long)__double_as_longlong(t0));
-                    if (gmode) atomicMin((unsigned long long *)toi_min, (unsigned long long)__double_as_longlong(t0));
-                } else if (r == SPLIT) {
-                    atomicAdd(&S.nsurv[s], 1);
+                if (r == SPLIT) {
+                    // a survivor and its children kept under the slot's t* of this
+                    // moment (a slot whose t* drops in this EVAL is counted again in D)
+                    const double ts = fmin(__longlong_as_double((long long)S.tstar[s]), tb);
+                    bool z = false;
+                    const int c = kept_children(nd, lvp, S.mm[s], ts, z);
+                    atomicAdd(&S.nc[s], (1u << 16) | (unsigned int)c);
+                    if (no_zero && z) atomicOr(&S.zmask, 1ull << s);
                 }
             }
         }
@@ -1340,8 +1388,11 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(BLOCK == 
             // t0: the child's lower time bound; z: it starts at t = 0
             auto keep = [&](double t0, bool z, bool has) {
                 const bool inF = has && t0 < tsnap;
-                if (inF) { cnt++; tmin = t0 < tmin ? t0 : tmin; }
-                if (inF && no_zero && z) s_zero[ps] = 1;
+                cnt += inF ? 1 : 0;
+                tmin = inF && t0 < tmin ? t0 : tmin;
+                if (no_zero) {
+                    if (inF && z) s_zero[ps] = 1;
+                }
                 return inF;
             };
             auto child = [&](const unsigned long long cn[3], bool has) {
