@@ -1530,7 +1530,14 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(BLOCK == 
                     if (s1) put(1ull, pos + s0);
                 }
             };
-            if (2 * nS <= BLOCK) {
+            if (2 * nS <= BLOCK && pk_cur) {
+                // one node and both children per thread
+                const bool has = tid < nS;
+                const unsigned long long w = has ? rd(tid) : 0ull;
+                if (k == 0) children_pk(std::integral_constant<int, 0>(), w, has);
+                else if (k == 1) children_pk(std::integral_constant<int, 1>(), w, has);
+                else children_pk(std::integral_constant<int, 2>(), w, has);
+            } else if (2 * nS <= BLOCK) {
                 const int64_t i = tid;
                 const bool has = i < 2 * nS;
                 unsigned long long cn[3];
