@@ -20,7 +20,7 @@ def _declared():
 
 @pytest.fixture(scope="module")
 def lib():
-    srcs = [os.path.join(ccd.HERE, "csrc", s) for s in ccd_build.SOURCES] + [HEADER]
+    srcs = [os.path.join(ccd.HERE, "csrc", s) for s in ccd_build.SOURCES + ccd_build.HEADERS] + [HEADER]
     if not os.path.exists(ccd.LIB_PATH) or os.path.getmtime(ccd.LIB_PATH) < max(os.path.getmtime(s) for s in srcs):
         ccd_build.build()
     return ccd.load_library()
