@@ -436,9 +436,11 @@ ccd_status ccd_get_stats(ccd_context *ctx, ccd_stats *out);
  *   resume_slots_per_cu workgroups per compute unit, 1..8 (default 3), of the
  *                       rounds that resume pairs whose frontier outgrew their
  *                       buffer
- *   pool_wait           1: a pair whose children do not fit its wave's queue
- *                       this round waits for room, 0: it goes to the wide
- *                       stage (default 0)
+ *   pool_wait           what a pair whose children do not fit its wave's
+ *                       queue this round does: 0: it goes to the wide stage;
+ *                       1: it waits for room; n >= 2 (at most 352): it waits
+ *                       when it has at most n children, else goes to the
+ *                       wide stage (default 32)
  *   sweep_classes       the sweep's query boxes of each kind are grouped
  *                       into this many classes by their extent on the sweep
  *                       axis before they are cut into tiles of 64, so that a

@@ -133,7 +133,7 @@ ccd_tuning default_tuning()
     t.heavy_cap_log2 = 16;
     t.heavy_lds = 1;
     t.heavy_block = 0;
-    t.pool_wait = 0;
+    t.pool_wait = 32;
     t.resume_block = 256;
     t.resume_slots_per_cu = 3;
     t.sweep_classes = 0;
@@ -269,7 +269,7 @@ bool valid_tuning(const ccd_tuning &t)
            t.pool_blocks_per_cu <= 64 && t.heavy_slots >= 1 && t.heavy_slots <= 65536 && t.heavy_cap_log2 >= 8 &&
            t.heavy_cap_log2 <= 24 && (t.heavy_lds == 0 || t.heavy_lds == 1) &&
            (t.heavy_block == 0 || t.heavy_block == 64 || t.heavy_block == 256 || t.heavy_block == 1024) &&
-           (t.pool_wait == 0 || t.pool_wait == 1) && (t.resume_block == 256 || t.resume_block == 1024) &&
+           (t.pool_wait >= 0 && t.pool_wait <= 352) && (t.resume_block == 256 || t.resume_block == 1024) &&
            t.resume_slots_per_cu >= 1 && t.resume_slots_per_cu <= 8 && t.sweep_classes >= 0 && t.sweep_classes <= 8;
 }
 
@@ -1718,9 +1718,10 @@ ccd_status ccd_batch_autotune(ccd_batch *b, const double *V0, const double *V1, 
     const int rblocks[] = {256, 1024};
     const int rslots[] = {1, 2, 3};
     const int classes[] = {0, 1, 4};
+    const int waits[] = {0, 32, 1};
     for (int param = 0; param < 10; param++) {
         // query classes apply to a single scene only
-        const int counts[10] = {4, c->pool_per_cu_max, 3, 4, 2, 2, 3, 2, 3, b->S == 1 ? 3 : 0};
+        const int counts[10] = {4, c->pool_per_cu_max, 3, 4, 2, 3, 3, 2, 3, b->S == 1 ? 3 : 0};
         const int ncand = counts[param];
         for (int i = 0; i < ncand; i++) {
             ccd_tuning t = best;
@@ -1729,7 +1730,7 @@ ccd_status ccd_batch_autotune(ccd_batch *b, const double *V0, const double *V1, 
             else if (param == 2) t.heavy_block = blocks[i];
             else if (param == 3) t.heavy_slots = slots[i];
             else if (param == 4) t.heavy_lds = i;
-            else if (param == 5) t.pool_wait = i;
+            else if (param == 5) t.pool_wait = waits[i];
             else if (param == 6) t.heavy_cap_log2 = caps[i];
             else if (param == 7) t.resume_block = rblocks[i];
             else if (param == 8) t.resume_slots_per_cu = rslots[i];

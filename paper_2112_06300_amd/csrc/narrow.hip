@@ -640,11 +640,14 @@ __global__ __launch_bounds__(kPoolSlots) void pool_kernel(
         int coff = 0;
         if (total > kQCap) {
             // Children that do not fit this round: a pair whose children could
-            // never fit goes to the wide stage; the others wait, carrying their
-            // survivors unsplit into the next round's queue (the level, t* and
-            // n_enq do not change while a pair waits).  The first pusher always
-            // fits, so some pair advances every round.
-            if (outcome == 4 && off + push > kQCap) outcome = (push > kQCap || !wait) ? 3 : 5;
+            // never fit goes to the wide stage, and so does every pair when
+            // pairs do not wait (wait 0) or a pair with more than `wait`
+            // children (wait >= 2); the others wait, carrying their survivors
+            // unsplit into the next round's queue (the level, t* and n_enq do
+            // not change while a pair waits).  The first pusher always fits, so
+            // some pair advances every round.
+            if (outcome == 4 && off + push > kQCap)
+                outcome = (push > kQCap || !wait || (wait > 1 && push > wait)) ? 3 : 5;
             off = push_offset(outcome == 4, waiting, push, wait, total);
             int ctotal = 0;
             coff = wave_excl_scan(outcome == 5 ? nsurv : 0, ctotal);
