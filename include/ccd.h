@@ -449,10 +449,14 @@ ccd_status ccd_get_stats(ccd_context *ctx, ccd_stats *out);
  *                       0 (default) = 4 for a single scene of at least 2^20
  *                       boxes, else off.  Batches of several scenes never
  *                       group (a tile spanning two scenes would walk both).
+ *   pool_root_limit     new pairs enter a pool wave's queue of 352 intervals
+ *                       only while it holds fewer than this many (default
+ *                       192); the rest is room for the children of the pairs
+ *                       in flight.
  * ccd_set_tuning(ctx, NULL) restores the defaults.  INVALID_ARG when a value
  * is out of range (group 1..1024, blocks 0..64, slots 1..65536, cap 8..24,
- * lds 0..1, block 0, 64, 256 or 1024, wait 0..1, resume block 256 or 1024,
- * resume slots 1..8, classes 0..8).
+ * lds 0..1, block 0, 64, 256 or 1024, wait 0..352, resume block 256 or 1024,
+ * resume slots 1..8, classes 0..8, root limit 16..320).
  */
 typedef struct {
     int32_t sweep_tile_group;
@@ -465,6 +469,7 @@ typedef struct {
     int32_t resume_block;
     int32_t resume_slots_per_cu;
     int32_t sweep_classes;
+    int32_t pool_root_limit;
 } ccd_tuning;
 
 ccd_status ccd_set_tuning(ccd_context *ctx, const ccd_tuning *tuning);

@@ -61,7 +61,8 @@ class Tuning(ctypes.Structure):
     _fields_ = [("sweep_tile_group", ctypes.c_int32), ("pool_blocks_per_cu", ctypes.c_int32),
                 ("heavy_slots", ctypes.c_int32), ("heavy_cap_log2", ctypes.c_int32), ("heavy_lds", ctypes.c_int32),
                 ("heavy_block", ctypes.c_int32), ("pool_wait", ctypes.c_int32), ("resume_block", ctypes.c_int32),
-                ("resume_slots_per_cu", ctypes.c_int32), ("sweep_classes", ctypes.c_int32)]
+                ("resume_slots_per_cu", ctypes.c_int32), ("sweep_classes", ctypes.c_int32),
+                ("pool_root_limit", ctypes.c_int32)]
 
 
 class Schedule(ctypes.Structure):

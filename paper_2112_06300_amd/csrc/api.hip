@@ -137,6 +137,7 @@ ccd_tuning default_tuning()
     t.resume_block = 256;
     t.resume_slots_per_cu = 3;
     t.sweep_classes = 0;
+    t.pool_root_limit = 192;
     return t;
 }
 
@@ -270,7 +271,8 @@ bool valid_tuning(const ccd_tuning &t)
            t.heavy_cap_log2 <= 24 && (t.heavy_lds == 0 || t.heavy_lds == 1) &&
            (t.heavy_block == 0 || t.heavy_block == 64 || t.heavy_block == 256 || t.heavy_block == 1024) &&
            (t.pool_wait >= 0 && t.pool_wait <= 352) && (t.resume_block == 256 || t.resume_block == 1024) &&
-           t.resume_slots_per_cu >= 1 && t.resume_slots_per_cu <= 8 && t.sweep_classes >= 0 && t.sweep_classes <= 8;
+           t.resume_slots_per_cu >= 1 && t.resume_slots_per_cu <= 8 && t.sweep_classes >= 0 && t.sweep_classes <= 8 &&
+           t.pool_root_limit >= 16 && t.pool_root_limit <= 320;
 }
 
 // Broad-phase arguments checked, workspace carved, every kernel launched on s
@@ -663,7 +665,7 @@ ccd_status narrow_enqueue(ccd_context *c, const double *V0, const double *V1, in
         HIP_TRY(hipEventRecord(c->ev[6], c->side));
     }
     launch_narrow_pool(V0, V1, pc, delta, (long long)max_iter, hit, toi, nenq, B, pool_blocks(c), order, order_n,
-                       c->tune.pool_wait, s);
+                       c->tune.pool_wait, c->tune.pool_root_limit, s);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(c->ev[2], s));
     launch_narrow_heavy(V0, V1, pc, delta, (long long)max_iter, hit, toi, nenq, B, call.nslots, cap, 0,
@@ -1428,7 +1430,7 @@ void batch_enqueue(ccd_batch *b, const BatchArgs &a, hipStream_t s)
     const PairCounts pc{b->vf_cap, b->ee_cap, b->B.counts};
     launch_narrow_prep(a.V0, a.V1, b->nv, a.E, b->ne, a.F, b->nf, a.vf, a.ee, pc, a.delta, b->N, s);
     launch_narrow_pool(a.V0, a.V1, pc, a.delta, a.max_iter, a.hit, a.toi, a.n_enq, b->N, pool_blocks(c), nullptr,
-                       nullptr, c->tune.pool_wait, s);
+                       nullptr, c->tune.pool_wait, c->tune.pool_root_limit, s);
     launch_narrow_heavy(a.V0, a.V1, pc, a.delta, a.max_iter, a.hit, a.toi, a.n_enq, b->N, b->heavy_slots,
                         b->heavy_cap, 0, c->tune.heavy_lds, c->tune.heavy_block, s);
     launch_scene_min(a.toi, pc, a.vf, a.ee, b->off, b->off + (b->S + 1), b->S, a.toi_min, s);
@@ -1539,9 +1541,10 @@ bool cache_lookup(const char *path, const char *sig, ccd_tuning *t)
     while (std::fgets(line, sizeof line, f)) {
         if (std::strncmp(line, sig, n) == 0 && line[n] == ':') {
             ccd_tuning v;
-            if (std::sscanf(line + n + 1, "%d %d %d %d %d %d %d %d %d %d", &v.sweep_tile_group,
+            if (std::sscanf(line + n + 1, "%d %d %d %d %d %d %d %d %d %d %d", &v.sweep_tile_group,
                             &v.pool_blocks_per_cu, &v.heavy_slots, &v.heavy_cap_log2, &v.heavy_lds, &v.heavy_block,
-                            &v.pool_wait, &v.resume_block, &v.resume_slots_per_cu, &v.sweep_classes) == 10 &&
+                            &v.pool_wait, &v.resume_block, &v.resume_slots_per_cu, &v.sweep_classes,
+                            &v.pool_root_limit) == 11 &&
                 valid_tuning(v)) {
                 *t = v;
                 found = true;  // the last matching line wins
@@ -1557,9 +1560,9 @@ void cache_store(const char *path, const char *sig, const ccd_tuning &t)
     if (!path) return;
     FILE *f = std::fopen(path, "a");
     if (!f) return;
-    std::fprintf(f, "%s: %d %d %d %d %d %d %d %d %d %d\n", sig, t.sweep_tile_group, t.pool_blocks_per_cu,
+    std::fprintf(f, "%s: %d %d %d %d %d %d %d %d %d %d %d\n", sig, t.sweep_tile_group, t.pool_blocks_per_cu,
                  t.heavy_slots, t.heavy_cap_log2, t.heavy_lds, t.heavy_block, t.pool_wait, t.resume_block,
-                 t.resume_slots_per_cu, t.sweep_classes);
+                 t.resume_slots_per_cu, t.sweep_classes, t.pool_root_limit);
     std::fclose(f);
 }
 
@@ -1719,9 +1722,10 @@ ccd_status ccd_batch_autotune(ccd_batch *b, const double *V0, const double *V1, 
     const int rslots[] = {1, 2, 3};
     const int classes[] = {0, 1, 4};
     const int waits[] = {0, 32, 1};
-    for (int param = 0; param < 10; param++) {
+    const int roots[] = {192, 224, 160};
+    for (int param = 0; param < 11; param++) {
         // query classes apply to a single scene only
-        const int counts[10] = {4, c->pool_per_cu_max, 3, 4, 2, 3, 3, 2, 3, b->S == 1 ? 3 : 0};
+        const int counts[11] = {4, c->pool_per_cu_max, 3, 4, 2, 3, 3, 2, 3, b->S == 1 ? 3 : 0, 3};
         const int ncand = counts[param];
         for (int i = 0; i < ncand; i++) {
             ccd_tuning t = best;
@@ -1734,7 +1738,8 @@ ccd_status ccd_batch_autotune(ccd_batch *b, const double *V0, const double *V1, 
             else if (param == 6) t.heavy_cap_log2 = caps[i];
             else if (param == 7) t.resume_block = rblocks[i];
             else if (param == 8) t.resume_slots_per_cu = rslots[i];
-            else t.sweep_classes = classes[i];
+            else if (param == 9) t.sweep_classes = classes[i];
+            else t.pool_root_limit = roots[i];
             if (std::memcmp(&t, &best, sizeof t) == 0) continue;
             float m = 0.f;
             st = measure(t, &m);

@@ -252,10 +252,12 @@ void launch_narrow_features(const double *V0, const double *V1, PairCounts pc, d
 // Pairs are taken in index order, or in `order` (a permutation) when given.
 // With order_n the pool searches order[0 .. *order_n) (the rest of the pairs
 // are the wide stage's).  wait: a pair whose children do not fit this round
-// waits (1) or goes to the wide stage (0).
+// goes to the wide stage (0), waits (1), or waits when it has at most `wait`
+// children (>= 2).  root_limit: new pairs start only while the round's queue
+// holds fewer intervals (below 352).
 void launch_narrow_pool(const double *V0, const double *V1, PairCounts pc, double delta, long long max_iter,
                         uint8_t *hit, double *toi, long long *n_enq, const NarrowBuffers &B, int pool_blocks,
-                        const int32_t *order, const uint32_t *order_n, int wait, hipStream_t s);
+                        const int32_t *order, const uint32_t *order_n, int wait, int root_limit, hipStream_t s);
 // Wide stage over the learned schedule's early entries heavy[0 .. counters[12])
 // (work index counters[13]), with its own frontier buffers; it may run
 // concurrently with the pool on another stream.

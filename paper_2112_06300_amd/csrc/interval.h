@@ -134,6 +134,12 @@ __device__ __forceinline__ void axis_pair(const Q &q, int a, const double T[3], 
         smn[sl] = first ? lo : fmin(smn[sl], lo);
         smx[sl] = first ? hi : fmax(smx[sl], hi);
     };
+    // edge-edge split along u or v: running min / max of each child directly
+    double cmn[2], cmx[2];
+    auto cfold = [&](int c, bool first, double lo, double hi) {
+        cmn[c] = first ? lo : fmin(cmn[c], lo);
+        cmx[c] = first ? hi : fmax(cmx[c], hi);
+    };
     // Rounding is monotone, so a slice's extremes come from extremes of the
     // factors that vary inside it: F = A(u) - B(v) (edge-edge) gives
     // RN(min A - max B) and RN(max A - min B); F = fma(-v, c - a, g(u))
@@ -177,15 +183,21 @@ __device__ __forceinline__ void axis_pair(const Q &q, int a, const double T[3], 
             if (K == 0) {
                 fold(it, true, fmin(A[0], A[1]) - fmax(B[0], B[1]), fmax(A[0], A[1]) - fmin(B[0], B[1]));
             } else if (K == 1) {
+                // each child's extremes from its own extremes of A (monotone in A)
                 const double bl = fmin(B[0], B[1]), bh = fmax(B[0], B[1]);
-#pragma unroll
-                for (int iu = 0; iu < NU; iu++) fold(iu, it == 0, A[iu] - bh, A[iu] - bl);
+                cfold(0, it == 0, fmin(A[0], A[1]) - bh, fmax(A[0], A[1]) - bl);
+                cfold(1, it == 0, fmin(A[1], A[2]) - bh, fmax(A[1], A[2]) - bl);
             } else {
                 const double al = fmin(A[0], A[1]), ah = fmax(A[0], A[1]);
-#pragma unroll
-                for (int iv = 0; iv < NV; iv++) fold(iv, it == 0, al - B[iv], ah - B[iv]);
+                cfold(0, it == 0, al - fmax(B[0], B[1]), ah - fmin(B[0], B[1]));
+                cfold(1, it == 0, al - fmax(B[1], B[2]), ah - fmin(B[1], B[2]));
             }
         }
+    }
+    if (!VF && K != 0) {
+        mn0 = cmn[0]; mx0 = cmx[0];
+        mn1 = cmn[1]; mx1 = cmx[1];
+        return;
     }
     mn0 = fmin(smn[0], smn[1]);
     mx0 = fmax(smx[0], smx[1]);

@@ -39,13 +39,12 @@ namespace {
 constexpr int kPoolSlots = 64;   // lanes per pool workgroup (one wave)
 constexpr int kSlots = 48;       // pairs in flight per wave (one owner lane each)
 constexpr int kQCap = 352;       // intervals per round per wave
-// New pairs start only while the round's queue holds fewer than this many
-// intervals: the headroom keeps the next level's children in the queue.  A
-// pair whose children overflow it goes to the wide stage, which costs far more
-// per level: on the 1M-triangle perturbed torus a full queue handed 543k
-// pairs over and the narrow phase took 30 ms; a limit at 5/8 of the queue
-// hands over 17k, 12 ms.
-constexpr int kRootLimit = 224;
+// New pairs start only while the round's queue holds fewer than root_limit
+// intervals (a tuning value below kQCap): the headroom keeps the next level's
+// children in the queue.  A pair whose children overflow it waits or goes to
+// the wide stage, which costs far more per level: on the 1M-triangle
+// perturbed torus a full queue handed 543k pairs over and the narrow phase
+// took 30 ms; a limit at 5/8 of the queue hands over 17k, 12 ms.
 constexpr int kClaim = 64;       // pairs a wave claims from the global list at once (one per lane)
 static_assert(kClaim <= 64, "a chunk's order entries are held one per lane");
 
@@ -382,7 +381,7 @@ struct PoolLds {
     unsigned int nc[kPoolSlots];
     int cnt[kPoolSlots], k[kPoolSlots], off[kPoolSlots], pos[kPoolSlots];
 };
-static_assert(kSlots <= kPoolSlots && kRootLimit < kQCap, "pool sizes");
+static_assert(kSlots <= kPoolSlots, "pool sizes");
 static_assert(sizeof(PoolLds) <= 163840 / 8, "pool LDS must allow 8 workgroups per CU");
 
 constexpr int kNoExpand = -1, kHandNodes = -2, kCarry = -3;
@@ -463,7 +462,7 @@ __global__ __launch_bounds__(kPoolSlots) void pool_kernel(
     const double *__restrict__ peps, const uint32_t *__restrict__ pm, PairCounts pc,
     double delta, long long max_iter, uint8_t *hit, double *toi, long long *n_enq_out, HeavyEntry *heavy,
     unsigned long long *hnodes, int64_t hnode_cap, unsigned int *counters, const int32_t *__restrict__ order,
-    const uint32_t *__restrict__ order_n, int wait, double *toi_min, int gmode, int no_zero)
+    const uint32_t *__restrict__ order_n, int wait, int root_limit, double *toi_min, int gmode, int no_zero)
 {
     __shared__ PoolLds S;
     int64_t n_vf, n_pairs;
@@ -721,9 +720,9 @@ __global__ __launch_bounds__(kPoolSlots) void pool_kernel(
         const unsigned long long om = __ballot(own), dm = __ballot(donor), tkm = __ballot(taker);
         const int nown = __popcll(om);
         int nmig = __popcll(dm) < __popcll(tkm) ? __popcll(dm) : __popcll(tkm);
-        if (nmig > kRootLimit - total - nown) nmig = kRootLimit - total - nown > 0 ? kRootLimit - total - nown : 0;
+        if (nmig > root_limit - total - nown) nmig = root_limit - total - nown > 0 ? root_limit - total - nown : 0;
         const int roff = __popcll(om & lt_mask);
-        const bool root_fits = own && total + roff < kRootLimit;
+        const bool root_fits = own && total + roff < root_limit;
         if (nmig > 0) {
             // the rank-r taker receives the rank-r donor's pair (S.tmin: rank -> slot,
             // S.cnt: the pair index; both are reset below)
@@ -1083,7 +1082,7 @@ void launch_narrow_features(const double *V0, const double *V1, PairCounts pc, d
 
 void launch_narrow_pool(const double *V0, const double *V1, PairCounts pc, double delta, long long max_iter,
                         uint8_t *hit, double *toi, long long *n_enq, const NarrowBuffers &B, int pool_blocks,
-                        const int32_t *order, const uint32_t *order_n, int wait, hipStream_t s)
+                        const int32_t *order, const uint32_t *order_n, int wait, int root_limit, hipStream_t s)
 {
     const int64_t n = pc.capacity();
     if (n == 0) return;
@@ -1091,7 +1090,7 @@ void launch_narrow_pool(const double *V0, const double *V1, PairCounts pc, doubl
     if (blocks > pool_blocks) blocks = pool_blocks;
     pool_kernel<<<(unsigned)blocks, kPoolSlots, 0, s>>>(V0, V1, B.ids4, B.eps, B.m, pc, delta, max_iter, hit, toi,
                                                        n_enq, B.heavy, B.hnodes, B.hnode_cap, B.counters, order,
-                                                       order_n, wait, B.toi_min, B.mode.global, B.mode.no_zero);
+                                                       order_n, wait, root_limit, B.toi_min, B.mode.global, B.mode.no_zero);
 }
 
 void launch_initial_distance(const double *V0, int64_t nv, const int32_t *E, int64_t ne, const int32_t *F, int64_t nf,

@@ -350,11 +350,12 @@ def test_end_to_end_cloth(ctx):
                                     {"heavy_block": 1024, "heavy_slots": 256},
                                     {"heavy_block": 1024, "heavy_lds": 0, "heavy_cap_log2": 10},
                                     {"heavy_block": 256},
-                                    {"pool_wait": 0}, {"pool_wait": 4, "heavy_cap_log2": 8}])
+                                    {"pool_wait": 0}, {"pool_wait": 4, "heavy_cap_log2": 8},
+                                    {"pool_root_limit": 16}, {"pool_root_limit": 320, "pool_wait": 0}])
 def test_tunings_give_identical_results(ctx, tuning):
     """Launch shapes (LDS frontiers, tiny wide-stage buffers that force re-runs, one pool workgroup per CU,
     ungrouped sweep tiles, one-wave wide-stage workgroups, pool pairs that never wait, always wait or wait
-    only when they have few children) never change a result."""
+    only when they have few children, pool root admission limits from 16 to 320) never change a result."""
     print(f"tuning {tuning}", flush=True)
     ctx.set_tuning(tuning)
     try:
