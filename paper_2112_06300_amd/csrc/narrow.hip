@@ -794,12 +794,18 @@ __global__ __launch_bounds__(kPoolSlots) void pool_kernel(
                 if (ks >= 0) {
                     const double tsn = pow2neg((int)(S.lv[s] & 255u));  // levels already advanced
                     const double ts = fmin(__longlong_as_double((long long)S.tstar[s]), tb);
-#pragma unroll
-                    for (int c = 0; c < 2; c++) {
-                        const unsigned long long ch = child_of(nd, ks, c);
-                        if (node_tlo(ch, tsn) < ts) {
-                            const int q = S.off[s] + atomicAdd(&S.pos[s], 1);
-                            S.node[nxt][q] = ch;
+                    const unsigned long long c0 = child_of(nd, ks, 0), c1 = child_of(nd, ks, 1);
+                    const bool k0 = node_tlo(c0, tsn) < ts, k1 = node_tlo(c1, tsn) < ts;
+                    if (k0 || k1) {
+                        // one atomic for the entry's kept children, placed side by side
+                        int q = S.off[s] + atomicAdd(&S.pos[s], (k0 ? 1 : 0) + (k1 ? 1 : 0));
+                        if (k0) {
+                            S.node[nxt][q] = c0;
+                            S.slot[nxt][q] = (uint8_t)s;
+                            q++;
+                        }
+                        if (k1) {
+                            S.node[nxt][q] = c1;
                             S.slot[nxt][q] = (uint8_t)s;
                         }
                     }
