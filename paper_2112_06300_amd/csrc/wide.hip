@@ -372,7 +372,17 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(BLOCK == 
             // (fixed for the level): the children's words come from the node's
             // word (field K doubled, plus one for the second child), with no
             // selection by a runtime dimension
-            auto children_pk = [&](auto KC, unsigned long long w, bool has) {
+            // the level's earliest root so far and its overflow flag (read a node
+            // ahead in the node loop: an older value only lets more children be
+            // evaluated, whose results the level's end discards or re-counts alike)
+            auto read_tl = [&]() {
+                return __longlong_as_double(
+                    (long long)__hip_atomic_load(&s_tl[ps], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+            };
+            auto read_ovf = [&]() {
+                return __hip_atomic_load(&s_ovf[ps], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != 0u;
+            };
+            auto children_pk = [&](auto KC, unsigned long long w, bool has, double tl, bool ovf) {
                 constexpr int K = decltype(KC)::value;
                 constexpr int SH = 21 * K;
                 const unsigned long long f0 = w & 0x1fffffull, f1 = (w >> 21) & 0x1fffffull,
@@ -388,9 +398,6 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(BLOCK == 
                 const double t00 = T[0], t10 = K == 0 ? T[1] : T[0];
                 const bool z0 = n0 == 0ull, z1 = K == 0 ? false : n0 == 0ull;
                 const bool in0 = keep(t00, z0, has), in1 = keep(t10, z1, has);
-                const double tl = __longlong_as_double(
-                    (long long)__hip_atomic_load(&s_tl[ps], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
-                const bool ovf = __hip_atomic_load(&s_ovf[ps], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != 0u;
                 const bool need0 = in0 && t00 < tl && !ovf, need1 = in1 && t10 < tl && !ovf;
                 int r0 = DISCARD, r1 = DISCARD;
                 if (need0 || need1)
@@ -429,9 +436,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(BLOCK == 
                 // one node and both children per thread
                 const bool has = tid < nS;
                 const unsigned long long w = has ? rd(tid) : 0ull;
-                if (k == 0) children_pk(std::integral_constant<int, 0>(), w, has);
-                else if (k == 1) children_pk(std::integral_constant<int, 1>(), w, has);
-                else children_pk(std::integral_constant<int, 2>(), w, has);
+                if (k == 0) children_pk(std::integral_constant<int, 0>(), w, has, read_tl(), read_ovf());
+                else if (k == 1) children_pk(std::integral_constant<int, 1>(), w, has, read_tl(), read_ovf());
+                else children_pk(std::integral_constant<int, 2>(), w, has, read_tl(), read_ovf());
             } else if (2 * nS <= BLOCK) {
                 const int64_t i = tid;
                 const bool has = i < 2 * nS;
@@ -449,11 +456,15 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(BLOCK == 
                 auto run_pk = [&](auto KC) {
                     bool has = tid < nS;
                     unsigned long long w = curg[has ? tid : nS - 1];
+                    double tl = read_tl();
+                    bool ovf = read_ovf();
                     for (int64_t b0 = 0; b0 < nS; b0 += BLOCK) {
                         const int64_t inext = b0 + BLOCK + tid;
                         const bool hasn = inext < nS;
                         const unsigned long long wn = curg[hasn ? inext : nS - 1];
-                        children_pk(KC, w, has);
+                        children_pk(KC, w, has, tl, ovf);
+                        tl = read_tl();
+                        ovf = read_ovf();
                         w = wn;
                         has = hasn;
                     }
