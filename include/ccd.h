@@ -502,8 +502,9 @@ ccd_status ccd_get_tuning(ccd_context *ctx, ccd_tuning *tuning);
  *
  * ccd_batch_autotune: times batch passes over candidate tunings (coordinate
  * descent over tile group, pool blocks per CU, wide-stage workgroup size,
- * slots, buffer size and LDS frontiers, pool waiting, and the resume rounds'
- * workgroup size and count) and sets
+ * slots, buffer size and LDS frontiers, pool waiting (0, 32 or always), the
+ * resume rounds' workgroup size and count, the sweep's query classes (single
+ * scenes) and the pool's root admission limit (192, 224 or 160)) and sets
  * the best on the context.  With cache_path the choice is stored under a
  * signature of the device and the workload's size, and a later call with the
  * same signature takes it from the file without timing.  Outputs as
