@@ -426,9 +426,9 @@ __device__ __forceinline__ int slot_split(uint32_t lvp, uint32_t mp, int &lk)
 }
 
 // Children of the split interval nd (of a slot at levels lvp, split levels
-// mp) that start before ts: their number, and whether one starts at t = 0.
-// None while the next level would pass the packed numerators' 21 bits (the
-// pair is handed over instead).
+// mp) that start before ts: a mask (bit i: child i), and whether one starts at
+// t = 0.  None while the next level would pass the packed numerators' 21 bits
+// (the pair is handed over instead).
 __device__ __forceinline__ int kept_children(unsigned long long nd, uint32_t lvp, uint32_t mp, double ts, bool &z)
 {
     int lk = 0;
@@ -436,17 +436,21 @@ __device__ __forceinline__ int kept_children(unsigned long long nd, uint32_t lvp
     z = false;
     if (lk + 1 > kLightMaxLevel) return 0;
     const double tsn = pow2neg((int)(lvp & 255u) + (ks == 0 ? 1 : 0));
-    int c = 0;
+    int mask = 0;
 #pragma unroll
     for (int i = 0; i < 2; i++) {
         const unsigned long long ch = child_of(nd, ks, i);
         if (node_tlo(ch, tsn) < ts) {
-            c++;
+            mask |= 1 << i;
             z = z || (ch & 0x1fffffull) == 0ull;
         }
     }
-    return c;
+    return mask;
 }
+
+// A queue entry's result byte: DISCARD / ACCEPT / SPLIT in bits 0..1, and for
+// a survivor the mask of its kept children in bits 2..3.
+constexpr int kResMask = 3;
 
 // The pool.  A round:
 //   D (all lanes, last round's queue): recount the kept children of the slots
@@ -585,12 +589,14 @@ __global__ __launch_bounds__(kPoolSlots) void pool_kernel(
             }
             for (int b0 = 0; b0 < nq; b0 += kPoolSlots) {
                 const int e = b0 + lane;
-                if (e < nq && S.res[e] == SPLIT) {
+                if (e < nq && (S.res[e] & kResMask) == SPLIT) {
                     const int s = S.slot[cur][e];
                     if ((redo >> s) & 1ull) {
                         const double ts = fmin(__longlong_as_double((long long)S.tstar[s]), tb);
                         bool z = false;
-                        const int c = kept_children(S.node[cur][e], S.lv[s], S.mm[s], ts, z);
+                        const int km = kept_children(S.node[cur][e], S.lv[s], S.mm[s], ts, z);
+                        S.res[e] = (uint8_t)(SPLIT | km << 2);
+                        const int c = __popc(km);
                         if (c) atomicAdd(&S.nc[s], (unsigned int)c);
                         if (no_zero && z) atomicOr(&S.zmask, 1ull << s);
                     }
@@ -625,7 +631,7 @@ __global__ __launch_bounds__(kPoolSlots) void pool_kernel(
                         // earlier, so it is the earliest kept parent's start
                         const double ts = fmin(tstar, tb), tsc = pow2neg(l[0]);
                         for (int e = 0; e < nq; e++) {
-                            if (S.slot[cur][e] == lane && S.res[e] == SPLIT) {
+                            if (S.slot[cur][e] == lane && (S.res[e] & kResMask) == SPLIT) {
                                 const double t0 = node_tlo(S.node[cur][e], tsc);
                                 if (t0 < ts && t0 < tmin) tmin = t0;
                             }
@@ -787,15 +793,15 @@ __global__ __launch_bounds__(kPoolSlots) void pool_kernel(
         // ---- F (all lanes over last round's entries): kept children, or hand-over survivors
         for (int b0 = 0; b0 < nq; b0 += kPoolSlots) {
             const int e = b0 + lane;
-            if (e < nq && S.res[e] == SPLIT) {
+            const int res = e < nq ? S.res[e] : DISCARD;
+            if ((res & kResMask) == SPLIT) {
                 const int s = S.slot[cur][e];
                 const int ks = S.k[s];
                 const unsigned long long nd = S.node[cur][e];
                 if (ks >= 0) {
-                    const double tsn = pow2neg((int)(S.lv[s] & 255u));  // levels already advanced
-                    const double ts = fmin(__longlong_as_double((long long)S.tstar[s]), tb);
+                    // kept children as counted (under the slot's final t*)
                     const unsigned long long c0 = child_of(nd, ks, 0), c1 = child_of(nd, ks, 1);
-                    const bool k0 = node_tlo(c0, tsn) < ts, k1 = node_tlo(c1, tsn) < ts;
+                    const bool k0 = (res >> 2) & 1, k1 = (res >> 3) & 1;
                     if (k0 || k1) {
                         // one atomic for the entry's kept children, placed side by side
                         int q = S.off[s] + atomicAdd(&S.pos[s], (k0 ? 1 : 0) + (k1 ? 1 : 0));
@@ -870,7 +876,9 @@ __global__ __launch_bounds__(kPoolSlots) void pool_kernel(
                     // moment (a slot whose t* drops in this EVAL is counted again in D)
                     const double ts = fmin(__longlong_as_double((long long)S.tstar[s]), tb);
                     bool z = false;
-                    const int c = kept_children(nd, lvp, S.mm[s], ts, z);
+                    const int km = kept_children(nd, lvp, S.mm[s], ts, z);
+                    S.res[e] = (uint8_t)(SPLIT | km << 2);
+                    const int c = __popc(km);
                     atomicAdd(&S.nc[s], (1u << 16) | (unsigned int)c);
                     if (no_zero && z) atomicOr(&S.zmask, 1ull << s);
                 }
