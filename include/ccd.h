@@ -120,7 +120,9 @@ ccd_status ccd_broad(ccd_context *ctx, const double *V0, const double *V1, int64
  *
  * Results do not depend on pair order or on how the GPU schedules intervals.
  * Errors: CCD_ERR_INVALID_ARG (index out of range, delta <= 0, max_iter < 1),
- * CCD_ERR_NONFINITE, CCD_ERR_OOM.  Synchronizes `stream`.
+ * CCD_ERR_NONFINITE, CCD_ERR_OOM, CCD_ERR_CAPACITY when one level of one pair
+ * holds more than 2^29 intervals (possible only with max_iter above that).
+ * Synchronizes `stream`.
  */
 ccd_status ccd_narrow(ccd_context *ctx, const double *V0, const double *V1, int64_t nv,
                       const int32_t *E, int64_t ne, const int32_t *F, int64_t nf,

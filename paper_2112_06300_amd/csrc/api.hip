@@ -707,6 +707,10 @@ ccd_status rerun_overflowed(ccd_context *c, NarrowBuffers B, Pool *pool, unsigne
             while (need < max_iter + 1 && need < ((int64_t)1 << 30)) need *= 2;
             want = std::max(want, need);
         }
+        if (want > kMaxFrontierCap) want = kMaxFrontierCap;
+        if (want <= cap)
+            return fail(CCD_ERR_CAPACITY, "interval frontier of %u pairs exceeds 2^29 intervals in one level",
+                        overflowed);
         const size_t slots_wanted =
             std::min<size_t>((size_t)c->cus * (size_t)c->tune.resume_slots_per_cu, (size_t)overflowed);
         while (want > cap * 8 && slots_wanted * (size_t)6 * want * 8 > budget) want /= 2;

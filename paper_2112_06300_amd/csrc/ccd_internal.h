@@ -177,6 +177,9 @@ struct PairCounts {
 // ---------------------------------------------------------------------------
 constexpr int kLightMaxLevel = 21;  // the wave pool packs numerators in 21 bits each
 constexpr int kMaxLevel = 52;       // finest dyadic level per dimension
+// Largest wide-stage frontier buffer, in intervals: three of them (a packed
+// buffer's words) stay below 2^31, the node loop's 32-bit index range.
+constexpr int64_t kMaxFrontierCap = (int64_t)1 << 29;
 
 // A pair handed to the wide stage: survivors at levels lvl, still to be split,
 // and the pair's t* and n_enq at that point.

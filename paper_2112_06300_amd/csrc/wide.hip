@@ -454,14 +454,17 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(BLOCK == 
                 // waits for the current word alone.
                 // The loop is specialized for the level's split dimension.
                 auto run_pk = [&](auto KC) {
-                    bool has = tid < nS;
-                    unsigned long long w = curg[has ? tid : nS - 1];
+                    // (a frontier buffer holds fewer than 2^31 words, kMaxFrontierCap:
+                    // 32-bit indices)
+                    const uint32_t n32 = (uint32_t)nS, last = n32 - 1u;
+                    bool has = (uint32_t)tid < n32;
+                    unsigned long long w = curg[has ? (uint32_t)tid : last];
                     double tl = read_tl();
                     bool ovf = read_ovf();
-                    for (int64_t b0 = 0; b0 < nS; b0 += BLOCK) {
-                        const int64_t inext = b0 + BLOCK + tid;
-                        const bool hasn = inext < nS;
-                        const unsigned long long wn = curg[hasn ? inext : nS - 1];
+                    for (uint32_t b0 = 0; b0 < n32; b0 += BLOCK) {
+                        const uint32_t inext = b0 + BLOCK + (uint32_t)tid;
+                        const bool hasn = inext < n32;
+                        const unsigned long long wn = curg[hasn ? inext : last];
                         children_pk(KC, w, has, tl, ovf);
                         tl = read_tl();
                         ovf = read_ovf();
