@@ -59,6 +59,8 @@ def parse():
                     help="skip the figures reported beside the main line (orderings, shared t*, other workloads)")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run this many plain and learned steps of the main workload (for profilers)")
+    ap.add_argument("--profile-workload", choices=("torus", "cloth"), default="torus",
+                    help="workload of --profile-steps: the gadget torus, or the 256 x 256 cloth on a sphere")
     return ap.parse_args()
 
 
@@ -387,13 +389,21 @@ def main():
     import paper_2112_06300_amd as ccd
     from paper_2112_06300_amd import sched
 
-    log("building the torus workload")
-    scene = scenes.perturbed_torus(seed=TORUS_SEED, gadgets=TORUS_GADGETS)
-    ctx = ccd.Context(0)
-    w = Workload(ctx, scene)
-    params, norm, model_meta = sched.load_model(sched.TORUS_MODEL_PATH)
-    learned = ccd.prepare_schedule(("learned", torch.as_tensor(params).cuda(), torch.as_tensor(norm).cuda(),
-                                    ccd.TORUS_HEAVY_THRESHOLD, ccd.TORUS_MAX_HEAVY))
+    if args.profile_steps and args.profile_workload == "cloth":
+        log("building the cloth workload")
+        ctx = ccd.Context(0)
+        w = Workload(ctx, scenes.cloth_on_sphere(n=256))
+        params, norm, model_meta = sched.load_model(sched.MODEL_PATH)
+        learned = ccd.prepare_schedule(("learned", torch.as_tensor(params).cuda(), torch.as_tensor(norm).cuda(),
+                                        ccd.HEAVY_THRESHOLD, ccd.MAX_HEAVY))
+    else:
+        log("building the torus workload")
+        scene = scenes.perturbed_torus(seed=TORUS_SEED, gadgets=TORUS_GADGETS)
+        ctx = ccd.Context(0)
+        w = Workload(ctx, scene)
+        params, norm, model_meta = sched.load_model(sched.TORUS_MODEL_PATH)
+        learned = ccd.prepare_schedule(("learned", torch.as_tensor(params).cuda(), torch.as_tensor(norm).cuda(),
+                                        ccd.TORUS_HEAVY_THRESHOLD, ccd.TORUS_MAX_HEAVY))
     if args.profile_steps:
         for _ in range(args.profile_steps):
             w.step(None)
